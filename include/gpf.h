@@ -1,0 +1,254 @@
+/*
+ * gpf.h — C ABI of the MI355X (gfx950) grid potential-flow library.
+ *
+ * Method: Beckers & Eldredge, "Planar potential flow on Cartesian grids"
+ * (arXiv 2102.11910).  One solve computes, on an unbounded Cartesian grid,
+ *
+ *   w  = R_v Gamma                         regularization of point vortices
+ *                                          with the M4' kernel (Sec. 2.1,
+ *                                          eq. vortexregularization)
+ *   s* = -L^-1 w                           lattice Green's function
+ *                                          convolution (Sec. 2.1, eq. poisson)
+ *   f, s0, Gamma_j                         bound vortex sheet and constraint
+ *                                          forces from the Schur complement
+ *                                          S = -E_s L^-1 R_s (Sec. 2.2-2.4,
+ *                                          eqs. basicblock, circsystem,
+ *                                          kuttasystem, kuttasystem2/3)
+ *   s  = -L^-1 (w + R_s f + sum Gamma_j d_j)   final streamfunction
+ *   (u, v) at the vortices                 centred differences of s averaged
+ *                                          to nodes, then E_v = R_v^T (Sec. 2.1)
+ *
+ * Conventions
+ *   Grid: n x n nodes, node (i, j) at (x0 + i dx, y0 + j dx); fields are
+ *   row-major [j][i] (i fastest).  n must be a power of two, 16 <= n <= 2048.
+ *   The lattice Green's function G has the gauge G(0,0) = 0.
+ *   s is the streamfunction WITHOUT the uniform-flow part
+ *   s_inf = U_inf y - V_inf x (add it if the total psi is needed).
+ *   Every vortex stencil (plus one node for velocities) and every surface
+ *   stencil must lie inside the window: (x - x0)/dx in [2, n-3) for vortices
+ *   and new vortices, in [1, n-2) for surface points.
+ *
+ * Memory and ownership
+ *   d_* = device pointer (HIP), h_* = host pointer.  The caller owns every
+ *   input/output buffer; the library never frees them and keeps no pointer
+ *   to them after a call returns.  The library owns its handles and their
+ *   device workspaces.  Destroy bodies before their plan, plans before the
+ *   context.
+ *
+ * Asynchrony
+ *   Solves enqueue all device work on the caller's HIP stream and return;
+ *   buffers must stay valid until that stream has completed.  A plan's
+ *   workspace serves one stream at a time: concurrent solves on one plan
+ *   race.
+ *
+ * Errors
+ *   Every call returns a gpf_status.  Synchronous errors (bad arguments,
+ *   unsupported sizes, allocation failure, singular body) return at once and
+ *   set a thread-local message readable with gpf_last_error().
+ *   Data-dependent errors found on the device (a stencil leaving the window,
+ *   a singular m x m edge system) are OR-ed into the caller's device status
+ *   word as GPF_DEV_* bits; gpf_sync() turns them into a gpf_status.
+ */
+#ifndef GPF_H
+#define GPF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GPF_OK = 0,
+  GPF_E_INVALID = -1,      /* null/ill-formed argument, non-finite scalar      */
+  GPF_E_OUT_OF_GRID = -2,  /* a stencil leaves the grid window                 */
+  GPF_E_SINGULAR = -3,     /* singular Schur complement or edge system         */
+  GPF_E_NOMEM = -4,        /* device or host allocation failed                 */
+  GPF_E_DEVICE = -5,       /* HIP runtime error                                */
+  GPF_E_UNSUPPORTED = -6   /* size or mode not supported                       */
+} gpf_status;
+
+/* bits of the device status word */
+#define GPF_DEV_OUT_OF_GRID 1u
+#define GPF_DEV_SINGULAR    2u
+
+/* plan flags */
+#define GPF_FP32        0u   /* default: FP32 fields, FP64 Schur and constraints */
+#define GPF_FP64        1u   /* every field and convolution in FP64               */
+#define GPF_CONV1_FP64  2u   /* FP32 plan, but the first convolution (whose
+                                surface values feed the ill-conditioned Schur
+                                solve) in FP64, for every body               */
+#define GPF_POLICY_AUTO 4u   /* FP32 plan; first convolution in FP64 only for
+                                bodies whose measured noise amplification
+                                exceeds GPF_AMP_THRESHOLD                    */
+#define GPF_AMP_THRESHOLD 500.0
+
+typedef enum {
+  GPF_NOBODY = 0,          /* no surface: s = -L^-1 R_v Gamma                  */
+  GPF_CIRCULATION = 1,     /* prescribed bound circulation gamma_b (eq. circsystem) */
+  GPF_KUTTA_STEADY = 2,    /* Kutta condition at the body's first edge, bound
+                              circulation free (eq. kuttasystem)               */
+  GPF_KUTTA_SHED = 3       /* Kutta condition at the body's m edges, each with a
+                              new vortex, total circulation zero (eqs.
+                              kuttasystem2, kuttasystem3)                      */
+} gpf_mode;
+
+#define GPF_MAX_EDGES 8
+
+typedef struct gpf_ctx gpf_ctx;
+typedef struct gpf_plan gpf_plan;
+typedef struct gpf_body gpf_body;
+
+typedef struct {
+  int n;                   /* nodes per direction (power of two, 16..2048)      */
+  double dx;               /* cell size                                         */
+  double x0, y0;           /* position of node (0, 0)                           */
+} gpf_grid;
+
+typedef struct {
+  int nv;                              /* number of vortices (>= 0)            */
+  const double *d_xv, *d_yv, *d_gv;    /* vortex x, y, strength Gamma_q         */
+  double u_inf, v_inf;                 /* uniform flow (Sec. 2.1, s_inf)        */
+  double ub, vb, omega;                /* rigid body velocity and rotation
+                                          rate (eqs. velsurf, sfsurf)          */
+  int mode;                            /* gpf_mode                              */
+  double gamma_b;                      /* GPF_CIRCULATION: bound circulation    */
+  int m;                               /* GPF_KUTTA_SHED: number of new vortices,
+                                          equal to the body's edge count        */
+  double h_xnew[GPF_MAX_EDGES];        /* GPF_KUTTA_SHED: new vortex positions, */
+  double h_ynew[GPF_MAX_EDGES];        /*   one per edge, in edge order         */
+  double gamma_w;                      /* GPF_KUTTA_SHED: circulation of the
+                                          existing vortices; NaN = sum of d_gv  */
+} gpf_inputs;
+
+typedef struct {
+  void *d_psi;             /* n*n field s, float for FP32 plans, double for
+                              GPF_FP64 plans (required)                        */
+  double *d_u, *d_v;       /* nv velocities at the vortices, including the
+                              uniform flow (nullable)                          */
+  double *d_f;             /* ns bound sheet strength f (nullable)            */
+  double *d_ftilde;        /* ns non-singular part f / f0 (nullable)          */
+  double *d_scalars;       /* 4 + GPF_MAX_EDGES doubles (nullable):
+                              [0] circulation of the vortices sum Gamma_q,
+                              [1] total circulation of the final source,
+                              [2] s0, [3] bound circulation <1, f>,
+                              [4..] strengths of the new vortices            */
+  unsigned int *d_status;  /* device status word, OR-ed with GPF_DEV_* bits
+                              (required; the caller clears it)                */
+} gpf_outputs;
+
+/* Context bound to one HIP device. */
+gpf_status gpf_ctx_create(int device, gpf_ctx **out);
+void gpf_ctx_destroy(gpf_ctx *ctx);
+
+/* Plan for one grid: lattice Green's function table and its spectrum
+ * (Sec. 2.1, L^-1 by the lattice Green's function), twiddles and
+ * workspaces.  The spectrum of the zero-padded (2n)^2 kernel is real; it is
+ * stored as (n+1)^2 values with the scale -dx^2/(2n)^2 and a gauge shift of
+ * its mean folded in.  Blocking (host work: table quadrature and FP64 FFT). */
+gpf_status gpf_plan_create(gpf_ctx *ctx, const gpf_grid *grid, unsigned flags,
+                           gpf_plan **out);
+void gpf_plan_destroy(gpf_plan *plan);
+
+/* Body: ns surface points (host arrays, FP64), segment lengths ds
+ * (Sec. 2.2.1), and nedge edge indices (for the Kutta modes, Sec. 2.4).
+ * Builds S = -E_s L^-1 R_s exactly in FP64 from the LGF table on the
+ * device, inverts it in FP64 with partial pivoting, and forms
+ * f0 = S^-1 1 (eq. f0), Gamma0 = <1, f0> (eq. circ0) and fhat0.
+ * Returns GPF_E_SINGULAR for a singular S or Gamma0 == 0,
+ * GPF_E_OUT_OF_GRID if a surface stencil leaves the window.  Blocking. */
+gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs,
+                           const double *h_ys, const double *h_ds, int nedge,
+                           const int *h_edges, gpf_body **out);
+void gpf_body_destroy(gpf_body *body);
+
+/* Per-body constants: Gamma0, the measured noise amplification of S^-1
+ * (relative L2 change of S^-1 r per relative change of r, for the
+ * highest-frequency perturbation of the unit-freestream rhs r = -y_s), and
+ * whether the first convolution runs in FP64 for this body (0/1). */
+gpf_status gpf_body_info(const gpf_body *body, double *gamma0, double *amp,
+                         int *conv1_fp64);
+
+/* Copy the body's f0 = S^-1 1 (ns doubles) to host memory.  Blocking. */
+gpf_status gpf_body_f0(const gpf_body *body, double *h_f0);
+
+/* One full solve (Sec. 2.2-2.4): R_v, L^-1, E_s, Schur and constraint
+ * solve, R_s, L^-1, E_v.  body may be NULL only with GPF_NOBODY.
+ * Asynchronous on hip_stream (NULL = default stream). */
+gpf_status gpf_solve(gpf_plan *plan, const gpf_body *body,
+                     const gpf_inputs *in, const gpf_outputs *out,
+                     void *hip_stream);
+
+/* ---- building blocks (asynchronous on hip_stream) ---------------------- */
+
+/* w = R_v Gamma (eq. vortexregularization): d_w is n*n of the plan's field
+ * type; accumulate = 0 overwrites, 1 adds.  Out-of-window vortices are
+ * skipped and flagged in d_status. */
+gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv,
+                                   const double *d_yv, const double *d_gv,
+                                   void *d_w, int accumulate,
+                                   unsigned int *d_status, void *hip_stream);
+
+/* s = -L^-1 w by the zero-padded LGF convolution (Sec. 2.1).  d_w, d_s are
+ * n*n of the plan's field type (may alias).  gamma_src must equal
+ * dx^2 * sum(w) (the source circulation): the spectrum is gauge-shifted and
+ * the exact shift -c * gamma_src is restored in the epilogue. */
+gpf_status gpf_convolve(gpf_plan *plan, const void *d_w, void *d_s,
+                        double gamma_src, void *hip_stream);
+
+/* r = E_s s at the body's surface points (Sec. 2.2.1); d_r: ns doubles. */
+gpf_status gpf_interpolate_surface(const gpf_body *body, const void *d_s,
+                                   double *d_r, void *hip_stream);
+
+/* (u, v) = E_v of the node velocities of s, plus (u_inf, v_inf) (Sec. 2.1). */
+gpf_status gpf_vortex_velocity(gpf_plan *plan, const void *d_s, int nv,
+                               const double *d_xv, const double *d_yv,
+                               double u_inf, double v_inf, double *d_u,
+                               double *d_v, unsigned int *d_status,
+                               void *hip_stream);
+
+/* ---- kernel timing ----------------------------------------------------- */
+
+/* Kernel classes timed by HIP events recorded on the launch stream. */
+#define GPF_TK_SCATTER    0   /* vortex regularization R_v                       */
+#define GPF_TK_ROWS_FWD   1   /* convolution pass 1 (FP32)                       */
+#define GPF_TK_COLS       2   /* convolution pass 2 (FP32)                       */
+#define GPF_TK_ROWS_INV   3   /* convolution pass 3 (FP32)                       */
+#define GPF_TK_ROWS_FWD64 4   /* convolution pass 1 (FP64)                       */
+#define GPF_TK_COLS64     5   /* convolution pass 2 (FP64)                       */
+#define GPF_TK_ROWS_INV64 6   /* convolution pass 3 (FP64)                       */
+#define GPF_TK_SURFACE    7   /* E_s, Schur apply, constraints, R_s              */
+#define GPF_TK_VELOCITY   8   /* velocity interpolation E_v                      */
+#define GPF_TK_COUNT      9
+
+/* Enable (1) or disable (0) per-kernel event timing for calls on this plan
+ * from the calling thread; enabling clears the totals.  Timing adds one
+ * event pair per timed launch; it must be off during graph capture. */
+gpf_status gpf_timing_enable(gpf_plan *plan, int enable);
+
+/* Wait for the recorded events and return the number of timed launches of
+ * kernel class `kind` and their summed duration in milliseconds. */
+gpf_status gpf_timing_read(gpf_plan *plan, int kind, long long *count,
+                           double *total_ms);
+
+/* ---- host utilities ---------------------------------------------------- */
+
+/* Lattice Green's function table T[a*(nmax+1)+b] = G(a, b), 0 <= a,b <= nmax,
+ * G(0,0) = 0 (host computation, no device needed). */
+gpf_status gpf_lgf_table(int nmax, double *h_table);
+
+/* Wait for hip_stream, read the status word, clear it, and map its bits to
+ * a gpf_status (GPF_E_OUT_OF_GRID before GPF_E_SINGULAR). */
+gpf_status gpf_sync(void *hip_stream, unsigned int *d_status);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *gpf_last_error(void);
+
+/* Library version string. */
+const char *gpf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPF_H */

@@ -1,0 +1,394 @@
+// Zero-padded lattice-Green's-function convolution s = -L^-1 w on gfx950.
+//
+// The particular solution of the unbounded discrete Poisson problem
+// (Sec. 2.1, eq. poisson) is s = -dx^2 (G * w) over the infinite lattice.
+// For w supported on the n x n window this equals the circular convolution
+// of the zero-padded (2n)^2 source with the even kernel
+// K(i,j) = G(min(i,2n-i), min(j,2n-j)), whose 2-D DFT is real.
+//
+// Three passes, N = 2n:
+//   1. rows:    two real rows packed as one complex sequence, length-N FFT
+//               (upper half of the input is zero), unpacked into the two
+//               half spectra and stored k-major: X[k1][j], k1 in [0, n].
+//   2. columns: per k1, length-N FFT of X[k1][0..n) (upper half zero),
+//               times the real spectrum, inverse FFT, first n outputs kept.
+//   3. rows:    two half spectra packed as one Hermitian-pair sequence,
+//               inverse FFT, first n outputs of each row kept, minus the
+//               exact gauge term c * gamma_src.
+// The spectrum already holds -dx^2/N^2 and the gauge shift by c.
+//
+// FFT core: a group of N/16 lanes owns one sequence in LDS; every stage is a
+// Stockham radix-R step (R = 16 except a last 2/4/8 step), each lane doing
+// 16/R butterflies with its values in registers.  LDS rows are padded by one
+// element every 16 to spread the strided stores over the banks.
+#include <type_traits>
+
+#include "gpf_internal.h"
+
+namespace gpf {
+namespace {
+
+template <class T> struct CT;
+template <> struct CT<float> { using V = float2; using V2 = float4; };
+template <> struct CT<double> { using V = double2; using V2 = double4; };
+
+template <class V> __device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <class V> __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <class V> __device__ __forceinline__ V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+
+// cos / sin of 2 pi k / 16, k = 0..7
+__device__ constexpr double kC16[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                                       0.38268343236508977173, 0.0, -0.38268343236508977173,
+                                       -0.70710678118654752440, -0.92387953251128675613};
+__device__ constexpr double kS16[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                                       0.92387953251128675613, 1.0, 0.92387953251128675613,
+                                       0.70710678118654752440, 0.38268343236508977173};
+
+template <int R> __host__ __device__ constexpr int bitrev(int x) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (x & 1);
+    x >>= 1;
+  }
+  return r;
+}
+
+// In-register R-point DFT (natural order in and out), radix-2 DIT network.
+// INV selects the e^{+i} kernel (unnormalized).
+template <int R, bool INV, class V>
+__device__ __forceinline__ void dft_reg(V *v) {
+  using S = decltype(v[0].x);
+  V t[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) t[bitrev<R>(i)] = v[i];
+#pragma unroll
+  for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < R; i += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; ++k) {
+        const int idx = k * (16 / len);
+        V b = t[i + k + len / 2];
+        if (idx == 4) {  // multiply by -i (forward) or +i (inverse)
+          V r;
+          if (INV) { r.x = -b.y; r.y = b.x; } else { r.x = b.y; r.y = -b.x; }
+          b = r;
+        } else if (idx != 0) {
+          V w;
+          w.x = (S)kC16[idx];
+          w.y = INV ? (S)kS16[idx] : -(S)kS16[idx];
+          b = cmul(b, w);
+        }
+        V a = t[i + k];
+        t[i + k] = cadd(a, b);
+        t[i + k + len / 2] = csub(a, b);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = t[i];
+}
+
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+constexpr int kE = 16;  // values per lane
+
+template <int N> struct Plan {
+  static constexpr int TPS = N / kE;          // lanes per sequence
+  static constexpr int SEQ = N <= 256 ? 8 : (N == 512 ? 4 : 2);
+  static constexpr int WGT = TPS * SEQ;        // threads per workgroup
+  static constexpr int LDS_SEQ = N + N / 16;   // padded elements per sequence
+};
+
+// radix of stage `s` for a length-N transform with 16 values per lane
+template <int N> __host__ __device__ constexpr int stage_radix(int s) {
+  int rem = N, r = 16;
+  for (int i = 0; i <= s; ++i) {
+    r = rem >= 16 ? 16 : rem;
+    if (i < s) rem /= r;
+  }
+  return r;
+}
+template <int N> __host__ __device__ constexpr int num_stages() {
+  int rem = N, s = 0;
+  while (rem > 1) {
+    rem /= (rem >= 16 ? 16 : rem);
+    ++s;
+  }
+  return s;
+}
+
+// One Stockham stage on the sequence in `lds` (natural order before the
+// first stage, natural order after the last).
+template <class T, int N, int R, int NS, bool INV, bool ZERO_UPPER, bool LOWER_OUT>
+__device__ __forceinline__ void fft_stage(typename CT<T>::V *lds,
+                                          const typename CT<T>::V *tw, int lane) {
+  using V = typename CT<T>::V;
+  constexpr int TPS = N / kE;
+  constexpr int NB = kE / R;   // butterflies per lane
+  V v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int bf = lane + b * TPS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (ZERO_UPPER && r >= R / 2) {
+        v[b][r].x = (T)0;
+        v[b][r].y = (T)0;
+      } else {
+        v[b][r] = lds[pad(bf + r * (N / R))];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int bf = lane + b * TPS;
+    const int j = bf % NS;
+    if (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        V w = tw[j * r * (N / (NS * R))];
+        if (INV) w.y = -w.y;
+        v[b][r] = cmul(v[b][r], w);
+      }
+    }
+    dft_reg<R, INV>(v[b]);
+    const int base = (bf / NS) * NS * R + j;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (LOWER_OUT && r >= R / 2) continue;
+      lds[pad(base + r * NS)] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <class T, int N, int S, int NS, bool INV, bool ZIN, bool LOUT>
+__device__ __forceinline__ void fft_stages(typename CT<T>::V *lds,
+                                           const typename CT<T>::V *tw, int lane) {
+  constexpr int NST = num_stages<N>();
+  if constexpr (S < NST) {
+    constexpr int R = stage_radix<N>(S);
+    fft_stage<T, N, R, NS, INV, ZIN && S == 0, LOUT && S == NST - 1>(lds, tw, lane);
+    fft_stages<T, N, S + 1, NS * R, INV, ZIN, LOUT>(lds, tw, lane);
+  }
+}
+
+// Full length-N transform of the sequence in lds; all threads of the block
+// must call it (it synchronizes the block).
+template <class T, int N, bool INV, bool ZIN, bool LOUT>
+__device__ __forceinline__ void fft_seq(typename CT<T>::V *lds,
+                                        const typename CT<T>::V *tw, int lane) {
+  fft_stages<T, N, 0, 1, INV, ZIN, LOUT>(lds, tw, lane);
+}
+
+// logical block index: consecutive logical blocks on one XCD (blocks are
+// dispatched round-robin over the XCDs), so that blocks touching the same
+// cache lines of the k-major intermediate share an L2.
+__device__ __forceinline__ int xcd_block(int xcds) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  if (xcds <= 1 || nb % xcds) return b;
+  return (b % xcds) * (nb / xcds) + b / xcds;
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: rows, real -> half spectrum, stored k-major
+// ---------------------------------------------------------------------------
+template <class Tin, class T, int N>
+__global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const Tin *__restrict__ w,
+                                                           typename CT<T>::V *__restrict__ X,
+                                                           const typename CT<T>::V *__restrict__ tw,
+                                                           int xcds) {
+  using V = typename CT<T>::V;
+  using P = Plan<N>;
+  constexpr int n = N / 2;
+  __shared__ V lds[P::SEQ * P::LDS_SEQ];
+  const int tid = threadIdx.x;
+  const int j0 = xcd_block(xcds) * 2 * P::SEQ;
+
+  for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
+    const int q = idx / n, t = idx % n;
+    const size_t row = (size_t)(j0 + 2 * q) * n;
+    V z;
+    z.x = (T)w[row + t];
+    z.y = (T)w[row + n + t];
+    lds[q * P::LDS_SEQ + pad(t)] = z;
+  }
+  __syncthreads();
+  const int q = tid / P::TPS, lane = tid % P::TPS;
+  fft_seq<T, N, false, true, false>(lds + q * P::LDS_SEQ, tw, lane);
+
+  // unpack: A = (Z[k] + conj Z[N-k]) / 2, B = (Z[k] - conj Z[N-k]) / (2i)
+  constexpr int RW = 2 * P::SEQ;
+  for (int idx = tid; idx < (n + 1) * RW; idx += P::WGT) {
+    const int k = idx / RW, jj = idx % RW;
+    const V *L = lds + (jj >> 1) * P::LDS_SEQ;
+    const V zk = L[pad(k)];
+    const V zm = L[pad((N - k) & (N - 1))];
+    V o;
+    if ((jj & 1) == 0) {
+      o.x = (T)0.5 * (zk.x + zm.x);
+      o.y = (T)0.5 * (zk.y - zm.y);
+    } else {
+      o.x = (T)0.5 * (zk.y + zm.y);
+      o.y = (T)0.5 * (zm.x - zk.x);
+    }
+    X[(size_t)k * n + j0 + jj] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: columns, forward FFT x spectrum x inverse FFT
+// ---------------------------------------------------------------------------
+template <class T, int N>
+__global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(typename CT<T>::V *__restrict__ X,
+                                                            const T *__restrict__ spec,
+                                                            const typename CT<T>::V *__restrict__ tw) {
+  using V = typename CT<T>::V;
+  using P = Plan<N>;
+  constexpr int n = N / 2;
+  __shared__ V lds[P::SEQ * P::LDS_SEQ];
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * P::SEQ;
+
+  for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
+    const int q = idx / n, t = idx % n;
+    const int k1 = c0 + q;
+    if (k1 <= n) lds[q * P::LDS_SEQ + pad(t)] = X[(size_t)k1 * n + t];
+  }
+  __syncthreads();
+  const int q = tid / P::TPS, lane = tid % P::TPS;
+  V *L = lds + q * P::LDS_SEQ;
+  fft_seq<T, N, false, true, false>(L, tw, lane);
+  {
+    const int k1 = min(c0 + q, n);
+    const T *sp = spec + (size_t)k1 * (n + 1);
+    for (int k2 = lane; k2 < N; k2 += P::TPS) {
+      const T g = sp[k2 <= n ? k2 : N - k2];
+      V z = L[pad(k2)];
+      z.x *= g;
+      z.y *= g;
+      L[pad(k2)] = z;
+    }
+  }
+  __syncthreads();
+  fft_seq<T, N, true, false, true>(L, tw, lane);
+
+  for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
+    const int qq = idx / n, t = idx % n;
+    const int k1 = c0 + qq;
+    if (k1 <= n) X[(size_t)k1 * n + t] = lds[qq * P::LDS_SEQ + pad(t)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 3: rows, two half spectra -> two real rows, gauge epilogue
+// ---------------------------------------------------------------------------
+template <class T, int N>
+__global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const typename CT<T>::V *__restrict__ X,
+                                                           T *__restrict__ s,
+                                                           const typename CT<T>::V *__restrict__ tw,
+                                                           double c, const double *__restrict__ gamma_src,
+                                                           int xcds) {
+  using V = typename CT<T>::V;
+  using V2 = typename CT<T>::V2;
+  using P = Plan<N>;
+  constexpr int n = N / 2;
+  __shared__ V lds[P::SEQ * P::LDS_SEQ];
+  const int tid = threadIdx.x;
+  const int j0 = xcd_block(xcds) * 2 * P::SEQ;
+
+  // Z[k] = A[k] + i B[k], Z[N-k] = conj(A[k]) + i conj(B[k]); the imaginary
+  // parts of A and B at k = 0 and k = n are dropped (real rows).
+  for (int idx = tid; idx < (n + 1) * P::SEQ; idx += P::WGT) {
+    const int k = idx / P::SEQ, q = idx % P::SEQ;
+    const V2 ab = *reinterpret_cast<const V2 *>(X + (size_t)k * n + j0 + 2 * q);
+    V *L = lds + q * P::LDS_SEQ;
+    V z;
+    if (k == 0 || k == n) {
+      z.x = ab.x;
+      z.y = ab.z;
+      L[pad(k)] = z;
+    } else {
+      z.x = ab.x - ab.w;
+      z.y = ab.y + ab.z;
+      L[pad(k)] = z;
+      z.x = ab.x + ab.w;
+      z.y = ab.z - ab.y;
+      L[pad(N - k)] = z;
+    }
+  }
+  __syncthreads();
+  const int q = tid / P::TPS, lane = tid % P::TPS;
+  fft_seq<T, N, true, false, true>(lds + q * P::LDS_SEQ, tw, lane);
+
+  const T shift = (T)(c * gamma_src[0]);
+  for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
+    const int qq = idx / n, t = idx % n;
+    const V z = lds[qq * P::LDS_SEQ + pad(t)];
+    const size_t row = (size_t)(j0 + 2 * qq) * n;
+    s[row + t] = z.x - shift;
+    s[row + n + t] = z.y - shift;
+  }
+}
+
+template <class Tin, class T, int N>
+hipError_t run_conv(const Tin *w, void *xwork, T *s, const T *spec, const T *tw,
+                    double c, const double *gamma_src, int xcds, hipStream_t st) {
+  using V = typename CT<T>::V;
+  using P = Plan<N>;
+  constexpr int n = N / 2;
+  V *X = static_cast<V *>(xwork);
+  const V *twv = reinterpret_cast<const V *>(tw);
+  const int rb = n / (2 * P::SEQ);
+  const int cb = (n + 1 + P::SEQ - 1) / P::SEQ;
+  constexpr bool D = std::is_same<T, double>::value;
+  timer_begin(D ? GPF_TK_ROWS_FWD64 : GPF_TK_ROWS_FWD, st);
+  hipLaunchKernelGGL((k_rows_fwd<Tin, T, N>), dim3(rb), dim3(P::WGT), 0, st, w, X, twv, xcds);
+  timer_end(st);
+  timer_begin(D ? GPF_TK_COLS64 : GPF_TK_COLS, st);
+  hipLaunchKernelGGL((k_cols_conv<T, N>), dim3(cb), dim3(P::WGT), 0, st, X, spec, twv);
+  timer_end(st);
+  timer_begin(D ? GPF_TK_ROWS_INV64 : GPF_TK_ROWS_INV, st);
+  hipLaunchKernelGGL((k_rows_inv<T, N>), dim3(rb), dim3(P::WGT), 0, st, X, s, twv, c,
+                     gamma_src, xcds);
+  timer_end(st);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <class Tin, class T>
+hipError_t launch_convolve(int n, const Tin *w, void *xwork, T *s, const T *spec,
+                           const T *tw, double c, const double *gamma_src, int xcds,
+                           hipStream_t st) {
+  switch (n) {
+    case 16: return run_conv<Tin, T, 32>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    case 32: return run_conv<Tin, T, 64>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    case 64: return run_conv<Tin, T, 128>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    case 128: return run_conv<Tin, T, 256>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    case 256: return run_conv<Tin, T, 512>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    case 512: return run_conv<Tin, T, 1024>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    case 1024: return run_conv<Tin, T, 2048>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    case 2048: return run_conv<Tin, T, 4096>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_convolve<float, float>(int, const float *, void *, float *,
+                                                  const float *, const float *, double,
+                                                  const double *, int, hipStream_t);
+template hipError_t launch_convolve<double, double>(int, const double *, void *, double *,
+                                                    const double *, const double *, double,
+                                                    const double *, int, hipStream_t);
+template hipError_t launch_convolve<double, float>(int, const double *, void *, float *,
+                                                   const float *, const float *, double,
+                                                   const double *, int, hipStream_t);
+
+}  // namespace gpf

@@ -1,0 +1,448 @@
+// Schur complement of the immersed-surface saddle system and the constraint
+// solves (Sec. 2.2-2.4, appendix A), all in FP64.
+//
+// * S = -E_s L^-1 R_s (Sec. 2.2.2) built exactly from the LGF table:
+//     S_pq = -dS_q sum_{a in st(p)} sum_{b in st(q)} e_pa e_qb G(a - b)
+//   (dx^2 of L^-1 cancels dx^-2 of R_s).  S is indefinite, so it is
+//   inverted by Gauss-Jordan elimination with partial pivoting.
+// * Per solve, with y0 = S^-1 (s_b' - E_s s*) and y_j = S^-1 E_s L^-1 d_j:
+//   prescribed circulation (eq. circsystem, circs0):
+//       s0 = (<1, y0> - Gamma_b)/Gamma0, f = y0 - s0 f0
+//   steady Kutta at edge k (eq. kuttasystem, intermedsoln, s0):
+//       f~* = y0/f0 - c1 (c1 = fhat0.s_b'/Gamma0 from P^Gamma, using S^-1 1 = f0),
+//       s0 = f~*_k, f~ = f~* - s0
+//   Kutta at m edges with new vortices (eq. kuttasystem2/3, twovortex):
+//       sum_j (1 + fhat0.P_{k_i} f~_j) Gamma_j = -(Gamma_w + fhat0.P_{k_i} f~*),
+//       x = f~* + sum Gamma_j f~_j, s0 = mean_i x_{k_i}, f~ = x - s0
+#include "gpf_internal.h"
+
+namespace gpf {
+namespace {
+
+__device__ __forceinline__ double m4p(double r) {
+  r = fabs(r);
+  if (r <= 1.0) return 1.0 - 2.5 * r * r + 1.5 * r * r * r;
+  if (r <= 2.0) return 0.5 * (2.0 - r) * (2.0 - r) * (1.0 - r);
+  return 0.0;
+}
+
+// S[p][q], one thread per entry
+__global__ __launch_bounds__(256) void k_schur_build(int n, int ns, const int *__restrict__ st_i,
+                                                     const double *__restrict__ st_w,
+                                                     const double *__restrict__ ds,
+                                                     const double *__restrict__ lgf,
+                                                     double *__restrict__ S) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (q >= ns) return;
+  const int w = n + 1;
+  const int ip = st_i[2 * p], jp = st_i[2 * p + 1];
+  const int iq = st_i[2 * q], jq = st_i[2 * q + 1];
+  double acc = 0.0;
+  for (int b = 0; b < 4; ++b) {
+    for (int d = 0; d < 4; ++d) {
+      const int dj = abs(jp + b - jq - d);
+      const double wyy = st_w[8 * p + 4 + b] * st_w[8 * q + 4 + d];
+      double racc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int di = abs(ip + a - iq - c);
+          racc += st_w[8 * p + a] * st_w[8 * q + c] * lgf[(size_t)di * w + dj];
+        }
+      }
+      acc += wyy * racc;
+    }
+  }
+  S[(size_t)p * ns + q] = -ds[q] * acc;
+}
+
+// Gauss-Jordan step k on the augmented matrix M = [A | B] (ns x 2ns):
+// pivot search, row swap, pivot-row scaling, and column capture.
+__global__ __launch_bounds__(256) void k_gj_pivot(int ns, int k, double *__restrict__ M,
+                                                  double *__restrict__ col,
+                                                  double *__restrict__ piv_log) {
+  __shared__ double best[256];
+  __shared__ int bidx[256];
+  const int tid = threadIdx.x, ld = 2 * ns;
+  double bv = -1.0;
+  int bi = k;
+  for (int i = k + tid; i < ns; i += 256) {
+    const double a = fabs(M[(size_t)i * ld + k]);
+    if (a > bv) { bv = a; bi = i; }
+  }
+  best[tid] = bv;
+  bidx[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      if (best[tid + s] > best[tid] || (best[tid + s] == best[tid] && bidx[tid + s] < bidx[tid])) {
+        best[tid] = best[tid + s];
+        bidx[tid] = bidx[tid + s];
+      }
+    }
+    __syncthreads();
+  }
+  const int pr = bidx[0];
+  if (pr != k) {
+    for (int j = tid; j < ld; j += 256) {
+      const double t = M[(size_t)k * ld + j];
+      M[(size_t)k * ld + j] = M[(size_t)pr * ld + j];
+      M[(size_t)pr * ld + j] = t;
+    }
+  }
+  __syncthreads();
+  const double pv = M[(size_t)k * ld + k];
+  if (tid == 0) piv_log[k] = pv;
+  const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
+  __syncthreads();
+  for (int j = tid; j < ld; j += 256) M[(size_t)k * ld + j] *= inv;
+  for (int i = tid; i < ns; i += 256) col[i] = (i == k) ? 0.0 : M[(size_t)i * ld + k];
+}
+
+__global__ __launch_bounds__(256) void k_gj_eliminate(int ns, int k, double *__restrict__ M,
+                                                      const double *__restrict__ col) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  const int ld = 2 * ns;
+  if (j >= ld || i == k) return;
+  const double c = col[i];
+  if (c != 0.0) M[(size_t)i * ld + j] -= c * M[(size_t)k * ld + j];
+}
+
+__global__ void k_gj_init(int ns, const double *__restrict__ A, double *__restrict__ M) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  const int ld = 2 * ns;
+  if (j >= ld) return;
+  M[(size_t)i * ld + j] = j < ns ? A[(size_t)i * ns + j] : (j - ns == i ? 1.0 : 0.0);
+}
+
+__global__ void k_gj_extract(int ns, const double *__restrict__ M, double *__restrict__ Ainv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= ns) return;
+  Ainv[(size_t)i * ns + j] = M[(size_t)i * 2 * ns + ns + j];
+}
+
+// Y[:, c] = A X[:, c] for c < ncol; X, Y column-major (ns x ncol); one wave per row
+__global__ __launch_bounds__(256) void k_gemv(int ns, int ncol, const double *__restrict__ A,
+                                              const double *__restrict__ X,
+                                              double *__restrict__ Y) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= ns) return;
+  double acc[1 + GPF_MAX_EDGES];
+#pragma unroll
+  for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c) acc[c] = 0.0;
+  const double *a = A + (size_t)row * ns;
+  for (int q = lane; q < ns; q += 64) {
+    const double aq = a[q];
+#pragma unroll
+    for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c)
+      if (c < ncol) acc[c] += aq * X[(size_t)c * ns + q];
+  }
+#pragma unroll
+  for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c) {
+    if (c < ncol) {
+      double v = acc[c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) Y[(size_t)c * ns + row] = v;
+    }
+  }
+}
+
+// rhs[:,0] = s_b' - E_s s*;  rhs[:,1+j] = (E_s L^-1 d_j), direct LGF sums
+template <class T>
+__global__ __launch_bounds__(128) void k_surface_rhs(GridGeom g, int ns, const double *__restrict__ xs,
+                                                     const double *__restrict__ ys,
+                                                     const int *__restrict__ st_i,
+                                                     const double *__restrict__ st_w,
+                                                     const T *__restrict__ sstar,
+                                                     const double *__restrict__ lgf, SolveScalars sv,
+                                                     double *__restrict__ rhs,
+                                                     unsigned *__restrict__ status) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  const int n = g.n;
+  const int i0 = st_i[2 * p], j0 = st_i[2 * p + 1];
+  const double *ew = st_w + 8 * p;
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double r = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) r += ew[a] * (double)sstar[(size_t)(j0 + b) * n + i0 + a];
+    acc += ew[4 + b] * r;
+  }
+  const double x = xs[p], y = ys[p];
+  const double sb = (sv.ub - sv.u_inf) * y - (sv.vb - sv.v_inf) * x -
+                    0.5 * sv.omega * (x * x + y * y);
+  rhs[p] = sb - acc;
+  if (sv.mode != GPF_KUTTA_SHED) return;
+  const int w = n + 1;
+  for (int j = 0; j < sv.m; ++j) {
+    const double xi = (sv.xnew[j] - g.x0) / g.dx, eta = (sv.ynew[j] - g.y0) / g.dx;
+    if (!(xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0)) {
+      if (p == 0) atomicOr(status, GPF_DEV_OUT_OF_GRID);
+      rhs[(size_t)(1 + j) * ns + p] = 0.0;
+      continue;
+    }
+    const int vi = (int)floor(xi) - 1, vj = (int)floor(eta) - 1;
+    const double fx = xi - floor(xi), fy = eta - floor(eta);
+    double mx[4], my[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      mx[c] = m4p(fx + 1.0 - c);
+      my[c] = m4p(fy + 1.0 - c);
+    }
+    double tot = 0.0;
+    for (int b = 0; b < 4; ++b) {
+      for (int d = 0; d < 4; ++d) {
+        const int dj = abs(j0 + b - vj - d);
+        double r = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            r += ew[a] * mx[c] * lgf[(size_t)abs(i0 + a - vi - c) * w + dj];
+        tot += ew[4 + b] * my[d] * r;
+      }
+    }
+    rhs[(size_t)(1 + j) * ns + p] = tot;
+  }
+}
+
+constexpr int kCB = 256;
+
+__device__ double block_sum(double v, double *red) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  red[tid] = v;
+  __syncthreads();
+  for (int s = kCB / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kCB) void k_constraints(int ns, const double *__restrict__ Y,
+                                                     const double *__restrict__ f0,
+                                                     const double *__restrict__ ds, double gamma0,
+                                                     const double *__restrict__ xs,
+                                                     const double *__restrict__ ys, SolveScalars sv,
+                                                     double *__restrict__ sc, double *__restrict__ f,
+                                                     double *__restrict__ ft,
+                                                     unsigned *__restrict__ status) {
+  __shared__ double red[kCB];
+  __shared__ double gam[GPF_MAX_EDGES];
+  __shared__ double sh_s0;
+  const int tid = threadIdx.x;
+  const double gamma_w_dev = sc[SC_GAMMA_W];
+  const int m = sv.mode == GPF_KUTTA_SHED ? sv.m : 0;
+
+  if (sv.mode == GPF_CIRCULATION) {
+    double part = 0.0;
+    for (int p = tid; p < ns; p += kCB) part += ds[p] * Y[p];
+    const double circ = block_sum(part, red);
+    const double s0 = (circ - sv.gamma_b) / gamma0;
+    double pb = 0.0;
+    for (int p = tid; p < ns; p += kCB) {
+      const double fp = Y[p] - s0 * f0[p];
+      f[p] = fp;
+      ft[p] = fp / f0[p];
+      pb += ds[p] * fp;
+    }
+    const double gb = block_sum(pb, red);
+    if (tid == 0) {
+      sc[SC_S0] = s0;
+      sc[SC_GAMMA_B] = gb;
+      sc[SC_GAMMA_SRC2] = gamma_w_dev + gb;
+    }
+    return;
+  }
+
+  // Kutta modes: c1 = fhat0 . s_b' / Gamma0 (circulation removal of the rhs)
+  double part = 0.0;
+  for (int p = tid; p < ns; p += kCB) {
+    const double x = xs[p], y = ys[p];
+    const double sb = (sv.ub - sv.u_inf) * y - (sv.vb - sv.v_inf) * x -
+                      0.5 * sv.omega * (x * x + y * y);
+    part += ds[p] * f0[p] * sb;
+  }
+  const double c1 = block_sum(part, red) / gamma0;
+  // ft <- f~* = y0/f0 - c1
+  for (int p = tid; p < ns; p += kCB) ft[p] = Y[p] / f0[p] - c1;
+  __syncthreads();
+
+  if (sv.mode == GPF_KUTTA_STEADY) {
+    const double s0 = ft[sv.edges[0]];
+    __syncthreads();  // every thread has read f~*_k before any thread shifts it
+    double pb = 0.0;
+    for (int p = tid; p < ns; p += kCB) {
+      const double t = ft[p] - s0;
+      ft[p] = t;
+      const double fp = f0[p] * t;
+      f[p] = fp;
+      pb += ds[p] * fp;
+    }
+    const double gb = block_sum(pb, red);
+    if (tid == 0) {
+      sc[SC_S0] = s0;
+      sc[SC_GAMMA_B] = gb;
+      sc[SC_GAMMA_SRC2] = gamma_w_dev + gb;
+    }
+    return;
+  }
+
+  // shedding at m edges
+  const double gamma_w = isnan(sv.gamma_w_in) ? gamma_w_dev : sv.gamma_w_in;
+  double dstar = 0.0;
+  for (int p = tid; p < ns; p += kCB) dstar += ds[p] * f0[p] * ft[p];
+  dstar = block_sum(dstar, red);
+  double dj[GPF_MAX_EDGES];
+  for (int j = 0; j < m; ++j) {
+    double pj = 0.0;
+    for (int p = tid; p < ns; p += kCB) pj += ds[p] * Y[(size_t)(1 + j) * ns + p];
+    dj[j] = block_sum(pj, red);   // fhat0 . f~_j = sum dS f0 (y_j / f0)
+  }
+  if (tid == 0) {
+    double A[GPF_MAX_EDGES][GPF_MAX_EDGES + 1];
+    for (int i = 0; i < m; ++i) {
+      const int k = sv.edges[i];
+      for (int j = 0; j < m; ++j)
+        A[i][j] = 1.0 + dj[j] - gamma0 * Y[(size_t)(1 + j) * ns + k] / f0[k];
+      A[i][m] = -(gamma_w + dstar - gamma0 * ft[k]);
+    }
+    bool singular = false;
+    double amax = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) amax = fmax(amax, fabs(A[i][j]));
+    for (int c = 0; c < m; ++c) {
+      int pr = c;
+      for (int i = c + 1; i < m; ++i)
+        if (fabs(A[i][c]) > fabs(A[pr][c])) pr = i;
+      if (!(fabs(A[pr][c]) > 1e-13 * amax)) { singular = true; break; }
+      if (pr != c)
+        for (int j = 0; j <= m; ++j) { double t = A[c][j]; A[c][j] = A[pr][j]; A[pr][j] = t; }
+      for (int i = 0; i < m; ++i) {
+        if (i == c) continue;
+        const double fct = A[i][c] / A[c][c];
+        for (int j = c; j <= m; ++j) A[i][j] -= fct * A[c][j];
+      }
+    }
+    for (int j = 0; j < m; ++j) gam[j] = singular ? 0.0 : A[j][m] / A[j][j];
+    if (singular) atomicOr(status, GPF_DEV_SINGULAR);
+    // s0 = mean over edges of x_k, x = f~* + sum_j Gamma_j f~_j
+    double s0 = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const int k = sv.edges[i];
+      double xk = ft[k];
+      for (int j = 0; j < m; ++j) xk += gam[j] * Y[(size_t)(1 + j) * ns + k] / f0[k];
+      s0 += xk;
+    }
+    sh_s0 = s0 / m;
+  }
+  __syncthreads();
+  const double s0 = sh_s0;
+  double pb = 0.0;
+  for (int p = tid; p < ns; p += kCB) {
+    double x = ft[p];
+    for (int j = 0; j < m; ++j) x += gam[j] * Y[(size_t)(1 + j) * ns + p] / f0[p];
+    const double t = x - s0;
+    ft[p] = t;
+    const double fp = f0[p] * t;
+    f[p] = fp;
+    pb += ds[p] * fp;
+  }
+  const double gb = block_sum(pb, red);
+  if (tid == 0) {
+    double gsum = 0.0;
+    for (int j = 0; j < m; ++j) {
+      sc[SC_GAMMA_NEW + j] = gam[j];
+      gsum += gam[j];
+    }
+    sc[SC_S0] = s0;
+    sc[SC_GAMMA_B] = gb;
+    sc[SC_GAMMA_SRC2] = gamma_w_dev + gb + gsum;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_schur_build(int n, int ns, const int *st_i, const double *st_w,
+                              const double *ds, const double *lgf, double *S, hipStream_t s) {
+  hipLaunchKernelGGL(k_schur_build, dim3((ns + 255) / 256, ns), dim3(256), 0, s, n, ns, st_i, st_w,
+                     ds, lgf, S);
+  return hipGetLastError();
+}
+
+gpf_status invert_fp64(int ns, double *A, double *Ainv, hipStream_t s, double *min_pivot_rel) {
+  DevBuf M, col, piv;
+  gpf_status st;
+  if ((st = M.alloc((size_t)ns * 2 * ns * sizeof(double))) != GPF_OK) return st;
+  if ((st = col.alloc((size_t)ns * sizeof(double))) != GPF_OK) return st;
+  if ((st = piv.alloc((size_t)ns * sizeof(double))) != GPF_OK) return st;
+  const dim3 g2((2 * ns + 255) / 256, ns);
+  hipLaunchKernelGGL(k_gj_init, g2, dim3(256), 0, s, ns, A, M.as<double>());
+  for (int k = 0; k < ns; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, ns, k, M.as<double>(),
+                       col.as<double>(), piv.as<double>());
+    hipLaunchKernelGGL(k_gj_eliminate, g2, dim3(256), 0, s, ns, k, M.as<double>(),
+                       col.as<double>());
+  }
+  const dim3 g1((ns + 255) / 256, ns);
+  hipLaunchKernelGGL(k_gj_extract, g1, dim3(256), 0, s, ns, M.as<double>(), Ainv);
+  GPF_HIP(hipGetLastError());
+  std::vector<double> hp(ns), ha((size_t)ns * ns);
+  GPF_HIP(hipMemcpyAsync(hp.data(), piv.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+  GPF_HIP(hipMemcpyAsync(ha.data(), A, (size_t)ns * ns * sizeof(double), hipMemcpyDeviceToHost, s));
+  GPF_HIP(hipStreamSynchronize(s));
+  double amax = 0.0, pmin = 1e300;
+  for (double v : ha) amax = std::max(amax, std::fabs(v));
+  for (double v : hp) pmin = std::min(pmin, std::fabs(v));
+  *min_pivot_rel = amax > 0.0 ? pmin / amax : 0.0;
+  return GPF_OK;
+}
+
+hipError_t launch_gemv(int ns, int ncol, const double *A, const double *X, double *Y,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv, dim3((ns + 3) / 4), dim3(256), 0, s, ns, ncol, A, X, Y);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_surface_rhs(const GridGeom &g, int ns, const double *xs, const double *ys,
+                              const int *st_i, const double *st_w, const T *sstar,
+                              const double *lgf, const SolveScalars &sv, double *rhs,
+                              unsigned *status, hipStream_t s) {
+  hipLaunchKernelGGL((k_surface_rhs<T>), dim3((ns + 127) / 128), dim3(128), 0, s, g, ns, xs, ys,
+                     st_i, st_w, sstar, lgf, sv, rhs, status);
+  return hipGetLastError();
+}
+template hipError_t launch_surface_rhs<float>(const GridGeom &, int, const double *,
+                                              const double *, const int *, const double *,
+                                              const float *, const double *,
+                                              const SolveScalars &, double *, unsigned *,
+                                              hipStream_t);
+template hipError_t launch_surface_rhs<double>(const GridGeom &, int, const double *,
+                                               const double *, const int *, const double *,
+                                               const double *, const double *,
+                                               const SolveScalars &, double *, unsigned *,
+                                               hipStream_t);
+
+hipError_t launch_constraints(int ns, const double *y, const double *f0, const double *ds,
+                              double gamma0, const double *xs, const double *ys,
+                              const SolveScalars &sv, double *dev_scalars, double *f,
+                              double *ftilde, unsigned *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_constraints, dim3(1), dim3(kCB), 0, s, ns, y, f0, ds, gamma0, xs, ys, sv,
+                     dev_scalars, f, ftilde, status);
+  return hipGetLastError();
+}
+
+}  // namespace gpf

@@ -1,0 +1,366 @@
+// Regularization and interpolation between Lagrangian points and grid nodes.
+//
+// * R_v (Sec. 2.1, eq. vortexregularization): w += Gamma_q / dx^2 times the
+//   tensor product of M4' weights on the 4 x 4 nodes around the vortex.
+// * E_v (Sec. 2.1): the same weights applied to node velocities, which are
+//   centred differences of s (face velocities of the discrete curl averaged
+//   to nodes).
+// * R_s, E_s (Sec. 2.2.1): smoothed 3-point kernel; R_s = dx^-2 E_s^T diag(dS).
+//
+// Cell indices and fractions are computed in FP64 from FP64 positions, then
+// the weights are rounded to the field type.  Stencils that would leave the
+// window are skipped and reported in the device status word.
+#include <algorithm>
+
+#include "gpf_internal.h"
+
+namespace gpf {
+namespace {
+
+__device__ __forceinline__ double m4p(double r) {
+  r = fabs(r);
+  if (r <= 1.0) return 1.0 - 2.5 * r * r + 1.5 * r * r * r;
+  if (r <= 2.0) return 0.5 * (2.0 - r) * (2.0 - r) * (1.0 - r);
+  return 0.0;
+}
+
+// smoothed three-point kernel (Yang et al. 2009)
+__device__ __forceinline__ double yang3(double r) {
+  r = fabs(r);
+  const double s3 = 1.7320508075688772935;
+  const double pi = 3.14159265358979323846;
+  if (r <= 1.0) {
+    return 17.0 / 48.0 + s3 * pi / 108.0 + r / 4.0 - r * r / 4.0 +
+           (1.0 - 2.0 * r) / 16.0 * sqrt(fmax(-12.0 * r * r + 12.0 * r + 1.0, 0.0)) -
+           s3 / 12.0 * asin(fmin(fmax(s3 / 2.0 * (2.0 * r - 1.0), -1.0), 1.0));
+  }
+  if (r <= 2.0) {
+    return 55.0 / 48.0 - s3 * pi / 108.0 - 13.0 * r / 12.0 + r * r / 4.0 +
+           (2.0 * r - 3.0) / 48.0 * sqrt(fmax(-12.0 * r * r + 36.0 * r - 23.0, 0.0)) +
+           s3 / 36.0 * asin(fmin(fmax(s3 / 2.0 * (2.0 * r - 3.0), -1.0), 1.0));
+  }
+  return 0.0;
+}
+
+// base node (lowest stencil index) and fraction; true if [lo, hi) holds xi
+__device__ __forceinline__ bool cell(double p, double o, double dx, int lo, int hi,
+                                     int *base, double *frac) {
+  const double xi = (p - o) / dx;
+  if (!(xi >= (double)lo && xi < (double)hi)) return false;  // also rejects NaN
+  const double fl = floor(xi);
+  *base = (int)fl - 1;
+  *frac = xi - fl;
+  return true;
+}
+
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+constexpr int kScatterBlock = 256;
+
+__global__ void k_fill(unsigned *p, size_t words) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+template <class T>
+__global__ __launch_bounds__(kScatterBlock) void k_scatter_vortices(
+    GridGeom g, int nv, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ gam, T *__restrict__ w, double *__restrict__ partials,
+    double *__restrict__ gamma_out, unsigned *__restrict__ counter,
+    unsigned *__restrict__ status) {
+  __shared__ double red[kScatterBlock];
+  __shared__ bool last;
+  const int q = blockIdx.x * kScatterBlock + threadIdx.x;
+  double gq = 0.0;
+  if (q < nv) {
+    int i0, j0;
+    double fx, fy;
+    const bool okx = cell(x[q], g.x0, g.dx, 2, g.n - 3, &i0, &fx);
+    const bool oky = cell(y[q], g.y0, g.dx, 2, g.n - 3, &j0, &fy);
+    if (okx && oky) {
+      gq = gam[q];
+      const double amp = gq / (g.dx * g.dx);
+      double wx[4], wy[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        wx[a] = m4p(fx + 1.0 - a);
+        wy[a] = m4p(fy + 1.0 - a);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        T *row = w + (size_t)(j0 + b) * g.n + i0;
+        const double ab = amp * wy[b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) atomic_add(row + a, (T)(ab * wx[a]));
+      }
+    } else {
+      atomicOr(status, GPF_DEV_OUT_OF_GRID);
+    }
+  }
+  // deterministic circulation: block partials, summed in order by the
+  // last block to finish
+  red[threadIdx.x] = gq;
+  __syncthreads();
+  for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = red[0];
+    __threadfence();
+    const unsigned done = atomicAdd(counter, 1u);
+    last = (done == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kScatterBlock)
+      acc += __hip_atomic_load(partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      gamma_out[0] = red[0];
+      atomicExch(counter, 0u);
+    }
+  }
+}
+
+__global__ void k_surface_stencils(GridGeom g, int ns, const double *__restrict__ xs,
+                                   const double *__restrict__ ys, int *__restrict__ st_i,
+                                   double *__restrict__ st_w, unsigned *__restrict__ status) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  int i0, j0;
+  double fx, fy;
+  const bool okx = cell(xs[p], g.x0, g.dx, 1, g.n - 2, &i0, &fx);
+  const bool oky = cell(ys[p], g.y0, g.dx, 1, g.n - 2, &j0, &fy);
+  if (!(okx && oky)) {
+    atomicOr(status, GPF_DEV_OUT_OF_GRID);
+    i0 = j0 = 1;
+    fx = fy = 0.0;
+  }
+  st_i[2 * p] = i0;
+  st_i[2 * p + 1] = j0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    st_w[8 * p + a] = yang3(fx + 1.0 - a);
+    st_w[8 * p + 4 + a] = yang3(fy + 1.0 - a);
+  }
+}
+
+template <class T>
+__global__ void k_interp_surface(int n, int ns, const int *__restrict__ st_i,
+                                 const double *__restrict__ st_w, const T *__restrict__ f,
+                                 double *__restrict__ r) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  const int i0 = st_i[2 * p], j0 = st_i[2 * p + 1];
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double rowacc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      rowacc += st_w[8 * p + a] * (double)f[(size_t)(j0 + b) * n + i0 + a];
+    acc += st_w[8 * p + 4 + b] * rowacc;
+  }
+  r[p] = acc;
+}
+
+template <class T>
+__global__ void k_scatter_sheet(GridGeom g, int ns, const int *__restrict__ st_i,
+                                const double *__restrict__ st_w, const double *__restrict__ ds,
+                                const double *__restrict__ f, SolveScalars sv,
+                                const double *__restrict__ sc, T *__restrict__ w) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const double inv = 1.0 / (g.dx * g.dx);
+  if (p < ns) {
+    const int i0 = st_i[2 * p], j0 = st_i[2 * p + 1];
+    const double amp = ds[p] * f[p] * inv;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double ab = amp * st_w[8 * p + 4 + b];
+      T *row = w + (size_t)(j0 + b) * g.n + i0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) atomic_add(row + a, (T)(ab * st_w[8 * p + a]));
+    }
+  } else if (p < ns + sv.m && sv.mode == GPF_KUTTA_SHED) {
+    const int j = p - ns;
+    int i0, j0;
+    double fx, fy;
+    if (cell(sv.xnew[j], g.x0, g.dx, 2, g.n - 3, &i0, &fx) &&
+        cell(sv.ynew[j], g.y0, g.dx, 2, g.n - 3, &j0, &fy)) {
+      const double amp = sc[SC_GAMMA_NEW + j] * inv;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double ab = amp * m4p(fy + 1.0 - b);
+        T *row = w + (size_t)(j0 + b) * g.n + i0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) atomic_add(row + a, (T)(ab * m4p(fx + 1.0 - a)));
+      }
+    }
+  }
+}
+
+// velocity at the vortices: u = (s[j+1] - s[j-1]) / 2dx, v = -(s[i+1] - s[i-1]) / 2dx
+// at the 4 x 4 stencil nodes, interpolated with M4' weights, plus the
+// uniform flow.
+template <class T>
+__global__ __launch_bounds__(256) void k_vortex_velocity(GridGeom g, int nv,
+                                                         const double *__restrict__ x,
+                                                         const double *__restrict__ y,
+                                                         const T *__restrict__ s, double uinf,
+                                                         double vinf, double *__restrict__ u,
+                                                         double *__restrict__ v,
+                                                         unsigned *__restrict__ status) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nv) return;
+  int i0, j0;
+  double fx, fy;
+  if (!(cell(x[q], g.x0, g.dx, 2, g.n - 3, &i0, &fx) &&
+        cell(y[q], g.y0, g.dx, 2, g.n - 3, &j0, &fy))) {
+    atomicOr(status, GPF_DEV_OUT_OF_GRID);
+    u[q] = NAN;
+    v[q] = NAN;
+    return;
+  }
+  double wx[4], wy[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    wx[a] = m4p(fx + 1.0 - a);
+    wy[a] = m4p(fy + 1.0 - a);
+  }
+  // rows j0-1 .. j0+4, columns i0-1 .. i0+4 of s
+  double uacc = 0.0, vacc = 0.0;
+  const size_t n = g.n;
+  const T *base = s + (size_t)(j0 - 1) * n + (i0 - 1);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double ur = 0.0, vr = 0.0;
+    const T *rm = base + (size_t)b * n;       // row j0+b-1
+    const T *rc = rm + n;                      // row j0+b
+    const T *rp = rc + n;                      // row j0+b+1
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ur += wx[a] * ((double)rp[a + 1] - (double)rm[a + 1]);
+      vr += wx[a] * ((double)rc[a + 2] - (double)rc[a]);
+    }
+    uacc += wy[b] * ur;
+    vacc += wy[b] * vr;
+  }
+  const double h = 0.5 / g.dx;
+  u[q] = uacc * h + uinf;
+  v[q] = -vacc * h + vinf;
+}
+
+__global__ void k_copy_doubles(const double *__restrict__ src, double *__restrict__ dst,
+                               int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+}  // namespace
+
+int scatter_vortex_blocks(int nv) { return nv > 0 ? (nv + kScatterBlock - 1) / kScatterBlock : 1; }
+
+hipError_t launch_fill(void *p, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  int blocks = (int)std::min<size_t>((words + 255) / 256, 4096);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, static_cast<unsigned *>(p), words);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_scatter_vortices(const GridGeom &g, int nv, const double *x,
+                                   const double *y, const double *gam, T *w,
+                                   double *partials, double *gamma_out, unsigned *counter,
+                                   unsigned *status, hipStream_t s) {
+  timer_begin(GPF_TK_SCATTER, s);
+  hipLaunchKernelGGL((k_scatter_vortices<T>), dim3(scatter_vortex_blocks(nv)),
+                     dim3(kScatterBlock), 0, s, g, nv, x, y, gam, w, partials, gamma_out,
+                     counter, status);
+  timer_end(s);
+  return hipGetLastError();
+}
+template hipError_t launch_scatter_vortices<float>(const GridGeom &, int, const double *,
+                                                   const double *, const double *, float *,
+                                                   double *, double *, unsigned *, unsigned *,
+                                                   hipStream_t);
+template hipError_t launch_scatter_vortices<double>(const GridGeom &, int, const double *,
+                                                    const double *, const double *, double *,
+                                                    double *, double *, unsigned *,
+                                                    unsigned *, hipStream_t);
+
+hipError_t launch_surface_stencils(const GridGeom &g, int ns, const double *xs,
+                                   const double *ys, int *st_i, double *st_w,
+                                   unsigned *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_surface_stencils, dim3((ns + 127) / 128), dim3(128), 0, s, g, ns, xs,
+                     ys, st_i, st_w, status);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_interp_surface(int n, int ns, const int *st_i, const double *st_w,
+                                 const T *field, double *r, hipStream_t s) {
+  hipLaunchKernelGGL((k_interp_surface<T>), dim3((ns + 127) / 128), dim3(128), 0, s, n, ns,
+                     st_i, st_w, field, r);
+  return hipGetLastError();
+}
+template hipError_t launch_interp_surface<float>(int, int, const int *, const double *,
+                                                 const float *, double *, hipStream_t);
+template hipError_t launch_interp_surface<double>(int, int, const int *, const double *,
+                                                  const double *, double *, hipStream_t);
+
+template <class T>
+hipError_t launch_scatter_sheet(const GridGeom &g, int ns, const int *st_i,
+                                const double *st_w, const double *ds, const double *f,
+                                const SolveScalars &sv, const double *dev_scalars, T *w,
+                                hipStream_t s) {
+  const int total = ns + (sv.mode == GPF_KUTTA_SHED ? sv.m : 0);
+  hipLaunchKernelGGL((k_scatter_sheet<T>), dim3((total + 127) / 128), dim3(128), 0, s, g, ns,
+                     st_i, st_w, ds, f, sv, dev_scalars, w);
+  return hipGetLastError();
+}
+template hipError_t launch_scatter_sheet<float>(const GridGeom &, int, const int *,
+                                                const double *, const double *, const double *,
+                                                const SolveScalars &, const double *, float *,
+                                                hipStream_t);
+template hipError_t launch_scatter_sheet<double>(const GridGeom &, int, const int *,
+                                                 const double *, const double *,
+                                                 const double *, const SolveScalars &,
+                                                 const double *, double *, hipStream_t);
+
+template <class T>
+hipError_t launch_vortex_velocity(const GridGeom &g, int nv, const double *x, const double *y,
+                                  const T *s, double uinf, double vinf, double *u, double *v,
+                                  unsigned *status, hipStream_t st) {
+  if (nv <= 0) return hipSuccess;
+  timer_begin(GPF_TK_VELOCITY, st);
+  hipLaunchKernelGGL((k_vortex_velocity<T>), dim3((nv + 255) / 256), dim3(256), 0, st, g, nv, x,
+                     y, s, uinf, vinf, u, v, status);
+  timer_end(st);
+  return hipGetLastError();
+}
+template hipError_t launch_vortex_velocity<float>(const GridGeom &, int, const double *,
+                                                  const double *, const float *, double, double,
+                                                  double *, double *, unsigned *, hipStream_t);
+template hipError_t launch_vortex_velocity<double>(const GridGeom &, int, const double *,
+                                                   const double *, const double *, double,
+                                                   double, double *, double *, unsigned *,
+                                                   hipStream_t);
+
+hipError_t launch_copy_doubles(const double *src, double *dst, int count, hipStream_t s) {
+  const int blocks = std::max(1, std::min((count + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_copy_doubles, dim3(blocks), dim3(256), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+}  // namespace gpf

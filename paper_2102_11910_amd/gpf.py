@@ -1,0 +1,365 @@
+"""ctypes binding of libgpf.so (include/gpf.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  torch tensors supply device memory and streams.  Importing this
+module loads the in-tree library and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpf.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gpf.h")
+
+GPF_OK = 0
+GPF_E_INVALID = -1
+GPF_E_OUT_OF_GRID = -2
+GPF_E_SINGULAR = -3
+GPF_E_NOMEM = -4
+GPF_E_DEVICE = -5
+GPF_E_UNSUPPORTED = -6
+STATUS_NAMES = {0: "GPF_OK", -1: "GPF_E_INVALID", -2: "GPF_E_OUT_OF_GRID", -3: "GPF_E_SINGULAR",
+                -4: "GPF_E_NOMEM", -5: "GPF_E_DEVICE", -6: "GPF_E_UNSUPPORTED"}
+
+GPF_DEV_OUT_OF_GRID = 1
+GPF_DEV_SINGULAR = 2
+
+GPF_FP32 = 0
+GPF_FP64 = 1
+GPF_CONV1_FP64 = 2
+GPF_POLICY_AUTO = 4
+
+TK_NAMES = ["scatter", "rows_fwd", "cols", "rows_inv", "rows_fwd64", "cols64", "rows_inv64",
+            "surface", "velocity"]
+
+GPF_NOBODY, GPF_CIRCULATION, GPF_KUTTA_STEADY, GPF_KUTTA_SHED = 0, 1, 2, 3
+MODES = {"none": GPF_NOBODY, "circulation": GPF_CIRCULATION, "kutta": GPF_KUTTA_STEADY,
+         "shed": GPF_KUTTA_SHED}
+GPF_MAX_EDGES = 8
+N_SCALARS = 4 + GPF_MAX_EDGES
+
+
+class GpfError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class gpf_grid(C.Structure):
+    _fields_ = [("n", C.c_int), ("dx", C.c_double), ("x0", C.c_double), ("y0", C.c_double)]
+
+
+class gpf_inputs(C.Structure):
+    _fields_ = [("nv", C.c_int), ("d_xv", C.c_void_p), ("d_yv", C.c_void_p), ("d_gv", C.c_void_p),
+                ("u_inf", C.c_double), ("v_inf", C.c_double),
+                ("ub", C.c_double), ("vb", C.c_double), ("omega", C.c_double),
+                ("mode", C.c_int), ("gamma_b", C.c_double), ("m", C.c_int),
+                ("h_xnew", C.c_double * GPF_MAX_EDGES), ("h_ynew", C.c_double * GPF_MAX_EDGES),
+                ("gamma_w", C.c_double)]
+
+
+class gpf_outputs(C.Structure):
+    _fields_ = [("d_psi", C.c_void_p), ("d_u", C.c_void_p), ("d_v", C.c_void_p),
+                ("d_f", C.c_void_p), ("d_ftilde", C.c_void_p), ("d_scalars", C.c_void_p),
+                ("d_status", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch's HIP runtime must be the one the library binds to: both carry
+    # the soname libamdhip64.so.7, but torch loads its copy by file name, so
+    # loading the library first would put two HIP runtimes in the process.
+    import torch  # noqa: F401
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    PP = C.POINTER(C.c_void_p)
+    D = C.c_double
+    I = C.c_int
+    DP = C.POINTER(C.c_double)
+    sig = {
+        "gpf_ctx_create": (I, [I, PP]),
+        "gpf_ctx_destroy": (None, [P]),
+        "gpf_plan_create": (I, [P, C.POINTER(gpf_grid), C.c_uint, PP]),
+        "gpf_plan_destroy": (None, [P]),
+        "gpf_body_create": (I, [P, I, DP, DP, DP, I, C.POINTER(C.c_int), PP]),
+        "gpf_body_destroy": (None, [P]),
+        "gpf_body_info": (I, [P, DP, DP, C.POINTER(C.c_int)]),
+        "gpf_body_f0": (I, [P, DP]),
+        "gpf_solve": (I, [P, P, C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
+        "gpf_regularize_vortices": (I, [P, I, P, P, P, P, I, P, P]),
+        "gpf_convolve": (I, [P, P, P, D, P]),
+        "gpf_interpolate_surface": (I, [P, P, P, P]),
+        "gpf_vortex_velocity": (I, [P, P, I, P, P, D, D, P, P, P, P]),
+        "gpf_lgf_table": (I, [I, DP]),
+        "gpf_timing_enable": (I, [P, I]),
+        "gpf_timing_read": (I, [P, I, C.POINTER(C.c_longlong), DP]),
+        "gpf_sync": (I, [P, P]),
+        "gpf_last_error": (C.c_char_p, []),
+        "gpf_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def declared_symbols() -> list[str]:
+    """Names of the functions declared in include/gpf.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpf_[a-z0-9_]+)\s*\(", text)))
+
+
+def check(st: int, where: str) -> None:
+    if st != GPF_OK:
+        raise GpfError(st, where, lib.gpf_last_error().decode())
+
+
+def _dp(arr):
+    import numpy as np
+    a = np.ascontiguousarray(arr, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def lgf_table(nmax: int):
+    """Host lattice Green's function table from the library (no GPU needed)."""
+    import numpy as np
+    t = np.zeros((nmax + 1) * (nmax + 1))
+    check(lib.gpf_lgf_table(nmax, t.ctypes.data_as(C.POINTER(C.c_double))), "gpf_lgf_table")
+    return t.reshape(nmax + 1, nmax + 1)
+
+
+# ---------------------------------------------------------------------------
+# object wrappers (torch supplies device memory and streams)
+# ---------------------------------------------------------------------------
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        check(lib.gpf_ctx_create(device, C.byref(h)), "gpf_ctx_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib.gpf_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    def __init__(self, ctx: Context, n: int, dx: float, x0: float | None = None,
+                 y0: float | None = None, flags: int = GPF_FP32):
+        if x0 is None:
+            x0 = -(n - 1) * dx / 2.0
+        if y0 is None:
+            y0 = -(n - 1) * dx / 2.0
+        self.ctx = ctx
+        self.n, self.dx, self.x0, self.y0, self.flags = n, dx, x0, y0, flags
+        self.fp64 = bool(flags & GPF_FP64)
+        g = gpf_grid(n, dx, x0, y0)
+        h = C.c_void_p()
+        check(lib.gpf_plan_create(ctx.h, C.byref(g), flags, C.byref(h)), "gpf_plan_create")
+        self.h = h
+
+    @property
+    def field_dtype(self):
+        import torch
+        return torch.float64 if self.fp64 else torch.float32
+
+    def close(self):
+        if self.h:
+            lib.gpf_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Body:
+    def __init__(self, plan: Plan, xs, ys, ds, edges=()):
+        self.plan = plan
+        ax, px = _dp(xs)
+        ay, py = _dp(ys)
+        ad, pd = _dp(ds)
+        self.ns = len(ax)
+        self.edges = tuple(int(e) for e in edges)
+        ed = (C.c_int * max(1, len(self.edges)))(*self.edges)
+        h = C.c_void_p()
+        check(lib.gpf_body_create(plan.h, self.ns, px, py, pd, len(self.edges), ed, C.byref(h)),
+              "gpf_body_create")
+        self.h = h
+
+    def info(self):
+        g0, amp, c1 = C.c_double(), C.c_double(), C.c_int()
+        check(lib.gpf_body_info(self.h, C.byref(g0), C.byref(amp), C.byref(c1)), "gpf_body_info")
+        return {"gamma0": g0.value, "amp": amp.value, "conv1_fp64": bool(c1.value)}
+
+    def f0(self):
+        import numpy as np
+        out = np.zeros(self.ns)
+        check(lib.gpf_body_f0(self.h, out.ctypes.data_as(C.POINTER(C.c_double))), "gpf_body_f0")
+        return out
+
+    def close(self):
+        if self.h:
+            lib.gpf_body_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_inputs(X, Y, G, u_inf=0.0, v_inf=0.0, ub=0.0, vb=0.0, omega=0.0, mode="none",
+                gamma_b=0.0, znew=(), gamma_w=None) -> gpf_inputs:
+    """Fill gpf_inputs; X, Y, G are float64 device tensors."""
+    inp = gpf_inputs()
+    inp.nv = int(X.numel()) if X is not None else 0
+    inp.d_xv = X.data_ptr() if inp.nv else None
+    inp.d_yv = Y.data_ptr() if inp.nv else None
+    inp.d_gv = G.data_ptr() if inp.nv else None
+    inp.u_inf, inp.v_inf, inp.ub, inp.vb, inp.omega = u_inf, v_inf, ub, vb, omega
+    inp.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    inp.gamma_b = gamma_b
+    inp.m = len(znew)
+    for j, z in enumerate(znew):
+        inp.h_xnew[j] = z[0]
+        inp.h_ynew[j] = z[1]
+    inp.gamma_w = math.nan if gamma_w is None else gamma_w
+    return inp
+
+
+def make_outputs(psi, u=None, v=None, f=None, ftilde=None, scalars=None, status=None) -> gpf_outputs:
+    out = gpf_outputs()
+    out.d_psi = psi.data_ptr()
+    out.d_u = None if u is None else u.data_ptr()
+    out.d_v = None if v is None else v.data_ptr()
+    out.d_f = None if f is None else f.data_ptr()
+    out.d_ftilde = None if ftilde is None else ftilde.data_ptr()
+    out.d_scalars = None if scalars is None else scalars.data_ptr()
+    out.d_status = status.data_ptr()
+    return out
+
+
+def gpf_solve(plan: Plan, body: Body | None, inp: gpf_inputs, out: gpf_outputs, stream=None):
+    check(lib.gpf_solve(plan.h, None if body is None else body.h, C.byref(inp), C.byref(out),
+                        _stream_ptr(stream)), "gpf_solve")
+
+
+def timing_enable(plan: Plan, enable: bool = True):
+    check(lib.gpf_timing_enable(plan.h, int(bool(enable))), "gpf_timing_enable")
+
+
+def timing_read(plan: Plan) -> dict:
+    """{kernel class: (launch count, total ms)}; waits for the events."""
+    out = {}
+    for k, name in enumerate(TK_NAMES):
+        cnt, ms = C.c_longlong(), C.c_double()
+        check(lib.gpf_timing_read(plan.h, k, C.byref(cnt), C.byref(ms)), "gpf_timing_read")
+        out[name] = (cnt.value, ms.value)
+    return out
+
+
+def gpf_sync(status, stream=None):
+    check(lib.gpf_sync(_stream_ptr(stream), C.c_void_p(status.data_ptr())), "gpf_sync")
+
+
+def gpf_regularize_vortices(plan: Plan, X, Y, G, w, accumulate=False, status=None, stream=None):
+    nv = int(X.numel())
+    check(lib.gpf_regularize_vortices(plan.h, nv, _ptr(X) if nv else None, _ptr(Y) if nv else None,
+                                      _ptr(G) if nv else None, _ptr(w), int(bool(accumulate)),
+                                      _ptr(status), _stream_ptr(stream)), "gpf_regularize_vortices")
+
+
+def gpf_convolve(plan: Plan, w, s, gamma_src: float, stream=None):
+    check(lib.gpf_convolve(plan.h, _ptr(w), _ptr(s), float(gamma_src), _stream_ptr(stream)),
+          "gpf_convolve")
+
+
+def gpf_interpolate_surface(body: Body, s, r, stream=None):
+    check(lib.gpf_interpolate_surface(body.h, _ptr(s), _ptr(r), _stream_ptr(stream)),
+          "gpf_interpolate_surface")
+
+
+def gpf_vortex_velocity(plan: Plan, s, X, Y, u_inf, v_inf, u, v, status=None, stream=None):
+    nv = int(X.numel())
+    check(lib.gpf_vortex_velocity(plan.h, _ptr(s), nv, _ptr(X), _ptr(Y), float(u_inf),
+                                  float(v_inf), _ptr(u), _ptr(v), _ptr(status),
+                                  _stream_ptr(stream)), "gpf_vortex_velocity")
+
+
+class Solver:
+    """One plan (and optional body) with preallocated torch outputs.
+
+    solve() runs gpf_solve and returns the output tensors (device).
+    """
+
+    def __init__(self, ctx: Context, n: int, dx: float, surface=None, flags: int = GPF_FP32,
+                 edges=None):
+        import torch
+        self.plan = Plan(ctx, n, dx, flags=flags)
+        self.body = None
+        dev = torch.device("cuda", ctx.device)
+        self.dev = dev
+        if surface is not None:
+            self.body = Body(self.plan, surface.xs, surface.ys, surface.ds,
+                             surface.edges if edges is None else edges)
+        ns = self.body.ns if self.body else 1
+        self.psi = torch.empty((n, n), dtype=self.plan.field_dtype, device=dev)
+        self.f = torch.zeros(ns, dtype=torch.float64, device=dev)
+        self.ftilde = torch.zeros(ns, dtype=torch.float64, device=dev)
+        self.scalars = torch.zeros(N_SCALARS, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.u = self.v = None
+
+    def upload(self, case):
+        import torch
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(self.dev)
+        return t(case.X), t(case.Y), t(case.G)
+
+    def inputs_for(self, case, X, Y, G):
+        return make_inputs(X, Y, G, case.u_inf, case.v_inf, case.ub, case.vb, case.omega,
+                           case.mode, case.gamma_b, case.znew, case.gamma_w)
+
+    def solve(self, inp: gpf_inputs, X, stream=None, velocities=True):
+        import torch
+        nv = int(X.numel()) if X is not None else 0
+        if velocities and (self.u is None or self.u.numel() != nv):
+            self.u = torch.empty(nv, dtype=torch.float64, device=self.dev)
+            self.v = torch.empty(nv, dtype=torch.float64, device=self.dev)
+        out = make_outputs(self.psi, self.u if velocities else None, self.v if velocities else None,
+                           self.f if self.body else None, self.ftilde if self.body else None,
+                           self.scalars, self.status)
+        gpf_solve(self.plan, self.body, inp, out, stream)
+        return out
