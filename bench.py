@@ -1,12 +1,15 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the grid potential-flow solve on one MI355X.
 
-Workload (one step = one full solve): flat plate of chord 1 at 20 deg,
-Ns = 256 surface points, Kutta condition at both edges with one new vortex
-per edge; 512 x 512 grid, dx = 0.005; 1e4 vortices from a Gaussian blob
-behind the trailing edge.  The solve is R_v -> L^-1 -> E_s -> Schur and edge
-constraints -> R_s -> L^-1 -> E_v.  The plan (LGF table, spectrum) and the
-body (S^-1, f0) are resident; inputs are in HBM before the timed region.
+Workload: flat plate of chord 1 at 20 deg, Ns = 256 surface points, Kutta
+condition at both edges with one new vortex per edge; 512 x 512 grid,
+dx = 0.005; 1e4 vortices from a Gaussian blob behind the trailing edge.
+One full solve is R_v -> L^-1 -> E_s -> Schur and edge constraints -> R_s
+-> L^-1 -> E_v.  A step solves a batch of such problems (different vortex
+seeds around the same plate) in shared launches; the plain path (one solve
+per step, one launch per stage) is timed beside it.  The plan (LGF table,
+spectrum) and the body (S^-1, f0) are resident; inputs are in HBM before
+the timed region.
 
 Prints one JSON line: grid points solved per second (n^2 per full solve),
 per-step latency p50/p99, the roofline of the dominant kernel from HIP
@@ -82,11 +85,33 @@ def cpu_baseline(case, budget_s: float = 12.0) -> dict:
                       f"thread; plan and body set up beforehand), {el:.1f} s"}
 
 
+def timed(run_step, K, plan, gpf, torch, np, with_events=True):
+    """K steps between synchronizations; per-step events and kernel events."""
+    stream = torch.cuda.current_stream()
+    if with_events:
+        gpf.timing_enable(plan, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(K):
+        run_step()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = gpf.timing_read(plan) if with_events else {}
+    if with_events:
+        gpf.timing_enable(plan, False)
+    lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(K)])
+    return wall, lat, kt
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=32, help="problems per batched step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
@@ -102,70 +127,78 @@ def main() -> int:
     from paper_2102_11910_amd import gpf
     from paper_2102_11910_amd import workloads as wl
 
-    case = wl.config2()
+    B = args.batch
+    cases = [wl.config2(seed=2 + i) for i in range(B)]
+    case = cases[0]
     n = case.n
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    log(f"[bench] setup: {case.name}, nv={case.nv}, ns={case.surface.ns}")
+    log(f"[bench] setup: {case.name}, nv={case.nv}, ns={case.surface.ns}, batch={B}")
     ctx = gpf.Context(0)
     t0 = time.perf_counter()
     solver = gpf.Solver(ctx, n, case.dx, case.surface, flags=gpf.GPF_POLICY_AUTO)
-    info = solver.body.info()
+    plan, body = solver.plan, solver.body
+    info = body.info()
     log(f"[bench] plan+body {time.perf_counter() - t0:.2f} s, body {info}")
-    X, Y, G = solver.upload(case)
-    inp = solver.inputs_for(case, X, Y, G)
-    stream = torch.cuda.current_stream()
+    dev = solver.dev
+    # one set of inputs/outputs per problem of the batch
+    ins, outs, keep = [], [], []
+    for c in cases:
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
+        psi = torch.empty((n, n), dtype=torch.float32, device=dev)
+        u = torch.empty(c.nv, dtype=torch.float64, device=dev)
+        v = torch.empty_like(u)
+        f = torch.empty(body.ns, dtype=torch.float64, device=dev)
+        ft = torch.empty_like(f)
+        sc = torch.zeros(gpf.N_SCALARS, dtype=torch.float64, device=dev)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, znew=c.znew))
+        outs.append(gpf.make_outputs(psi, u, v, f, ft, sc, st))
+        keep.append((X, Y, G, psi, u, v, f, ft, sc, st))
+    batch = gpf.Batch(ctx, B)
+    plans, bodies = [plan] * B, [body] * B
+
+    def step_batched():
+        batch.solve(plans, bodies, ins, outs)
+
+    def step_plain():
+        gpf.gpf_solve(plan, body, ins[0], outs[0])
 
     for _ in range(args.warmup):
-        solver.solve(inp, X)
-    gpf.gpf_sync(solver.status)
+        step_batched()
+        step_plain()
+    for k in keep:
+        gpf.gpf_sync(k[-1])
     torch.cuda.synchronize()
 
-    # timed region: K full solves, kernel classes bracketed by HIP events on
-    # the launch stream, one event per step boundary for latency
     K = args.steps
-    gpf.timing_enable(solver.plan, True)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for k in range(K):
-        solver.solve(inp, X)
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpf.gpf_sync(solver.status)
-    kt = gpf.timing_read(solver.plan)
-    gpf.timing_enable(solver.plan, False)
-    lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(K)])
+    # batched: K steps of B problems, kernel events on the launch stream
+    wall_b, lat_b, kt = timed(step_batched, K, plan, gpf, torch, np)
+    wall_b_noev, _, _ = timed(step_batched, K, plan, gpf, torch, np, with_events=False)
+    # plain: one problem per step, each stage its own launch
+    Kp = 4 * K
+    wall_p, lat_p, _ = timed(step_plain, Kp, plan, gpf, torch, np, with_events=False)
+    for k in keep:
+        gpf.gpf_sync(k[-1])
 
-    # same region without the kernel events (their cost is reported)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for k in range(K):
-        solver.solve(inp, X)
-    torch.cuda.synchronize()
-    wall_noev = time.perf_counter() - t1
-
-    ms_per_step = 1e3 * wall / K
-    value = n * n * K / wall
+    value = B * n * n * K / wall_b_noev
+    value_plain = n * n * Kp / wall_p
     m = len(case.znew)
-    w_fp64 = info["conv1_fp64"]
-    kb = kernel_bytes(n, case.nv, case.surface.ns, m, w_fp64)
+    nv_mean = int(np.mean([c.nv for c in cases]))
+    kb1 = kernel_bytes(n, nv_mean, case.surface.ns, m, info["conv1_fp64"])
     per_kernel = {}
     for name, (cnt, ms) in kt.items():
         if cnt:
             avg_ms = ms / cnt
             per_kernel[name] = {"launches": cnt, "avg_us": 1e3 * avg_ms,
-                                "share": ms / (1e3 * wall),
-                                "GBps": kb[name] / (avg_ms * 1e-3) / 1e9}
+                                "GBps": B * kb1[name] / (avg_ms * 1e-3) / 1e9}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"] * per_kernel[k]["launches"])
     d = per_kernel[dom]
     achieved = d["GBps"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": kb[dom], "avg_us": round(d["avg_us"], 3)}
-    log("[bench] kernels: " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
-                                          for k, v in per_kernel.items()}))
+                "traffic": None, "bytes_per_launch": B * kb1[dom], "avg_us": round(d["avg_us"], 3)}
+    log("[bench] kernels (batched): " + json.dumps(
+        {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_kernel.items()}))
 
     res = {
         "metric": METRIC,
@@ -174,19 +207,27 @@ def main() -> int:
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * wall_b_noev / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "flat plate c=1 at 20 deg, Ns=256, Kutta at both edges with "
-                               "new vortices; 512^2 grid dx=0.005; 1e4 vortices (Gaussian blob)",
-                   "n": n, "nv": case.nv, "ns": case.surface.ns, "path": "plain",
+                               "new vortices; 512^2 grid dx=0.005; 1e4 vortices (Gaussian blob); "
+                               f"a step solves {B} such problems (different vortex seeds) in "
+                               "shared launches",
+                   "n": n, "nv": case.nv, "ns": case.surface.ns, "batch": B, "path": "batched",
                    "precision": "FP32 fields; FP64 first convolution (noise amplification "
                                 f"{info['amp']:.3g} > 500), FP64 Schur/constraints"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "value_without_kernel_events": n * n * K / wall_noev,
+        "latency_ms": {"p50": float(np.percentile(lat_b, 50)),
+                       "p99": float(np.percentile(lat_b, 99)),
+                       "per": f"batch of {B} solves"},
+        "plain": {"value": value_plain, "ms_per_solve": 1e3 * wall_p / Kp,
+                  "latency_ms": {"p50": float(np.percentile(lat_p, 50)),
+                                 "p99": float(np.percentile(lat_p, 99))}},
+        "speedup_vs_plain": value / value_plain,
+        "value_with_kernel_events": B * n * n * K / wall_b,
         "roofline": roofline,
         "kernels": {k: {"avg_us": round(v["avg_us"], 3), "GBps": round(v["GBps"], 1),
                         "launches": v["launches"]} for k, v in per_kernel.items()},

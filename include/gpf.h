@@ -98,6 +98,7 @@ typedef enum {
 typedef struct gpf_ctx gpf_ctx;
 typedef struct gpf_plan gpf_plan;
 typedef struct gpf_body gpf_body;
+typedef struct gpf_batch gpf_batch;
 
 typedef struct {
   int n;                   /* nodes per direction (power of two, 16..2048)      */
@@ -178,6 +179,26 @@ gpf_status gpf_body_f0(const gpf_body *body, double *h_f0);
 gpf_status gpf_solve(gpf_plan *plan, const gpf_body *body,
                      const gpf_inputs *in, const gpf_outputs *out,
                      void *hip_stream);
+
+/* ---- batches of independent problems ------------------------------------ */
+
+/* Workspaces for up to max_problems problems solved together. */
+gpf_status gpf_batch_create(gpf_ctx *ctx, int max_problems, gpf_batch **out);
+void gpf_batch_destroy(gpf_batch *batch);
+
+/* Solve nprob independent problems (each as in gpf_solve; bodies may be
+ * NULL or hold NULL for GPF_NOBODY problems).  Problems are grouped by grid
+ * size and precision; each group runs as one launch sequence whose kernels
+ * cover all of its problems (one grid dimension indexes the problem), so
+ * that small problems share launches instead of paying one launch each.
+ * Problem i uses workspace i of the batch; plans and bodies may repeat.
+ * Every problem needs its own output buffers and status word (a status word
+ * may be shared).  Asynchronous on hip_stream; the batch serves one stream
+ * at a time.  Results equal those of solving each problem alone up to the
+ * order of floating-point atomic additions. */
+gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
+                             const gpf_body *const *bodies, const gpf_inputs *inputs,
+                             const gpf_outputs *outputs, void *hip_stream);
 
 /* ---- building blocks (asynchronous on hip_stream) ---------------------- */
 

@@ -1,14 +1,15 @@
-// Host runtime behind the C ABI (include/gpf.h): contexts, plans, bodies and
-// the per-solve launch sequence.
+// Host runtime behind the C ABI (include/gpf.h): contexts, plans, bodies,
+// batches, and the launch sequence of a solve.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
-#include <string>
-#include <type_traits>
-#include <vector>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
+#include <type_traits>
+#include <vector>
 
 #include "gpf_internal.h"
 
@@ -42,14 +43,16 @@ gpf_status DevBuf::alloc(size_t nbytes) {
   return GPF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
 static thread_local KernelTimer *g_timer = nullptr;
 
 void timer_install(KernelTimer *t) { g_timer = t; }
 
 void timer_begin(int kind, hipStream_t s) {
   KernelTimer *t = g_timer;
-  if (!t) return;
-  if (t->pool.size() < 2) return;  // out of events: stop recording
+  if (!t || t->pool.size() < 2) return;  // no timer, or out of events
   hipEvent_t a = t->pool.back();
   t->pool.pop_back();
   if (hipEventRecord(a, s) != hipSuccess) {
@@ -109,6 +112,56 @@ gpf_status KernelTimer::flush() {
   return GPF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// descriptor ring
+// ---------------------------------------------------------------------------
+DescRing::~DescRing() {
+  for (auto e : ev) (void)hipEventDestroy(e);
+  if (host) (void)hipHostFree(host);
+}
+
+gpf_status DescRing::init(int nslots, size_t bytes_per_slot) {
+  slots = nslots;
+  slot_bytes = (bytes_per_slot + 255) / 256 * 256;
+  GPF_HIP(hipHostMalloc(reinterpret_cast<void **>(&host), slots * slot_bytes, hipHostMallocDefault));
+  GPF_TRY(dev.alloc(slots * slot_bytes));
+  ev.resize(slots);
+  for (auto &e : ev) GPF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  busy.assign(slots, 0);
+  pinned.assign(slots, 0);
+  return GPF_OK;
+}
+
+gpf_status DescRing::push(const void *src, size_t nbytes, hipStream_t s, void **dptr) {
+  if (nbytes > slot_bytes) return fail(GPF_E_INVALID, "descriptor block larger than a ring slot");
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  GPF_HIP(hipStreamIsCapturing(s, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  int slot = -1;
+  for (int tries = 0; tries < slots; ++tries) {
+    const int k = (next + tries) % slots;
+    if (!pinned[k]) {
+      slot = k;
+      break;
+    }
+  }
+  if (slot < 0) return fail(GPF_E_NOMEM, "all descriptor slots are held by captured graphs");
+  next = (slot + 1) % slots;
+  if (busy[slot] && !capturing) GPF_HIP(hipEventSynchronize(ev[slot]));
+  char *h = host + (size_t)slot * slot_bytes;
+  char *d = dev.as<char>() + (size_t)slot * slot_bytes;
+  std::memcpy(h, src, nbytes);
+  GPF_HIP(hipMemcpyAsync(d, h, nbytes, hipMemcpyHostToDevice, s));
+  if (capturing) {
+    pinned[slot] = 1;  // the graph replays this copy: keep the slot forever
+  } else {
+    GPF_HIP(hipEventRecord(ev[slot], s));
+    busy[slot] = 1;
+  }
+  *dptr = d;
+  return GPF_OK;
+}
+
 namespace {
 
 // cache of host LGF tables and unscaled spectra, keyed by n
@@ -150,11 +203,7 @@ std::pair<double, std::shared_ptr<std::vector<double>>> get_spectrum(int n) {
 }
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
-
-GridGeom geom(const gpf_plan *p) {
-  return GridGeom{p->grid.n, p->grid.dx, p->grid.x0, p->grid.y0};
-}
-
+bool is_finite(double v) { return std::isfinite(v); }
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
 int xcd_count(int device) {
@@ -173,8 +222,7 @@ gpf_status upload_spectrum(gpf_plan *p, DevBuf &spec, DevBuf &tw) {
   const double scale = -p->grid.dx * p->grid.dx / (double(N) * double(N));
   std::vector<T> hs((size_t)(n + 1) * (n + 1));
   for (size_t i = 0; i < hs.size(); ++i) hs[i] = (T)((*sp.second)[i] * scale);
-  gpf_status st;
-  if ((st = spec.alloc(hs.size() * sizeof(T))) != GPF_OK) return st;
+  GPF_TRY(spec.alloc(hs.size() * sizeof(T)));
   GPF_HIP(hipMemcpy(spec.p, hs.data(), hs.size() * sizeof(T), hipMemcpyHostToDevice));
   std::vector<T> ht(2 * (size_t)N);
   const double pi = 3.14159265358979323846;
@@ -182,88 +230,124 @@ gpf_status upload_spectrum(gpf_plan *p, DevBuf &spec, DevBuf &tw) {
     ht[2 * k] = (T)std::cos(-2.0 * pi * k / N);
     ht[2 * k + 1] = (T)std::sin(-2.0 * pi * k / N);
   }
-  if ((st = tw.alloc(ht.size() * sizeof(T))) != GPF_OK) return st;
+  GPF_TRY(tw.alloc(ht.size() * sizeof(T)));
   GPF_HIP(hipMemcpy(tw.p, ht.data(), ht.size() * sizeof(T), hipMemcpyHostToDevice));
   return GPF_OK;
 }
 
-bool is_finite(double v) { return std::isfinite(v); }
+constexpr int kMaxVortices = 1 << 22;
+constexpr int kPlanRingSlots = 64;
+constexpr size_t kProblemDescBytes = sizeof(ProbDesc) + 2 * sizeof(ConvDesc);
 
 }  // namespace
 }  // namespace gpf
 
 using namespace gpf;
 
-gpf_status gpf_plan::ensure_fp64_conv() {
-  const int n = grid.n;
-  gpf_status st;
-  if (!spec64.p && (st = upload_spectrum<double>(this, spec64, tw64)) != GPF_OK) return st;
-  if ((st = w64.alloc((size_t)n * n * sizeof(double))) != GPF_OK) return st;
-  if ((st = x64.alloc((size_t)(n + 1) * n * 2 * sizeof(double))) != GPF_OK) return st;
-  if ((st = s64.alloc((size_t)n * n * sizeof(double))) != GPF_OK) return st;
+gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns) {
+  const size_t cells = (size_t)nn * nn, half = (size_t)(nn + 1) * nn;
+  // source fields start zeroed; the last reader of a source leaves it zero
+  auto zeroed = [&](DevBuf &b, size_t bytes) -> gpf_status {
+    if (b.bytes >= bytes) return GPF_OK;
+    GPF_TRY(b.alloc(bytes));
+    GPF_HIP(hipMemset(b.p, 0, b.bytes));
+    return GPF_OK;
+  };
+  if (need32) {
+    GPF_TRY(zeroed(w32, cells * 4));
+    GPF_TRY(x32.alloc(half * 8));
+  }
+  if (need64) {
+    GPF_TRY(zeroed(w64, cells * 8));
+    GPF_TRY(x64.alloc(half * 16));
+    GPF_TRY(s64.alloc(cells * 8));
+  }
+  GPF_TRY(zeroed(aux, AUX_BYTES));
+  GPF_TRY(part.alloc(sizeof(double) * (size_t)scatter_blocks(kMaxVortices)));
+  if (nns > 0) {
+    const size_t cols = 1 + GPF_MAX_EDGES;
+    GPF_TRY(rhs.alloc(cols * nns * sizeof(double)));
+    GPF_TRY(y.alloc(cols * nns * sizeof(double)));
+    GPF_TRY(f.alloc(nns * sizeof(double)));
+    GPF_TRY(ft.alloc(nns * sizeof(double)));
+    ns = std::max(ns, nns);
+  }
+  n = std::max(n, nn);
   return GPF_OK;
 }
 
-gpf_status gpf_plan::ensure_schur_ws(int ns) {
-  if (ns <= ns_cap) return GPF_OK;
-  gpf_status st;
-  const size_t cols = 1 + GPF_MAX_EDGES;
-  if ((st = rhs.alloc(cols * ns * sizeof(double))) != GPF_OK) return st;
-  if ((st = y.alloc(cols * ns * sizeof(double))) != GPF_OK) return st;
-  if ((st = fbuf.alloc(ns * sizeof(double))) != GPF_OK) return st;
-  if ((st = fwork.alloc(ns * sizeof(double))) != GPF_OK) return st;
-  ns_cap = ns;
-  return GPF_OK;
+gpf_batch::~gpf_batch() {
+  for (auto *w : ws) delete w;
 }
 
+gpf_status gpf_plan::ensure_fp64() {
+  if (!spec64.p) GPF_TRY(upload_spectrum<double>(this, spec64, tw64));
+  return ws.ensure(grid.n, false, true, 0);
+}
+
+// ---------------------------------------------------------------------------
+// launch sequence of one group (same n and precision; 1..nb problems)
+// ---------------------------------------------------------------------------
 namespace gpf {
 namespace {
 
-template <class TP>
-gpf_status solve_impl(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
-                      const gpf_outputs *out, hipStream_t s, bool conv1_fp64) {
-  const GridGeom g = geom(plan);
-  const int n = g.n;
-  const int x = plan->ctx->xcds;
-  unsigned *status = out->d_status;
-  double *sc = plan->sc.as<double>();
-  unsigned *counter = reinterpret_cast<unsigned *>(plan->sc.as<char>() + SC_COUNTER_OFFSET_BYTES);
-  TP *psi = static_cast<TP *>(out->d_psi);
-  // the source field of both convolutions: FP64 when the first one runs in FP64
-  const bool w_fp64 = conv1_fp64 || std::is_same<TP, double>::value;
-  void *w = w_fp64 ? plan->w64.p : plan->w32.p;
-  const size_t wbytes = (size_t)n * n * (w_fp64 ? 8 : 4);
-  GPF_HIP(launch_fill(w, wbytes, s));
-  if (w_fp64)
-    GPF_HIP(launch_scatter_vortices<double>(g, in->nv, in->d_xv, in->d_yv, in->d_gv, (double *)w,
-                                            plan->part.as<double>(), sc + SC_GAMMA_W, counter,
-                                            status, s));
-  else
-    GPF_HIP(launch_scatter_vortices<float>(g, in->nv, in->d_xv, in->d_yv, in->d_gv, (float *)w,
-                                           plan->part.as<double>(), sc + SC_GAMMA_W, counter,
-                                           status, s));
-  const TP *spec = std::is_same<TP, double>::value ? (const TP *)plan->spec64.p : (const TP *)plan->spec32.p;
-  const TP *tw = std::is_same<TP, double>::value ? (const TP *)plan->tw64.p : (const TP *)plan->tw32.p;
-  void *xw = std::is_same<TP, double>::value ? plan->x64.p : plan->x32.p;
+struct GroupCfg {
+  int n = 0;
+  bool body = false;
+  bool fp64_plan = false;  // all fields FP64
+  bool conv1_fp64 = false; // FP32 plan with an FP64 first convolution
+};
 
-  if (in->mode == GPF_NOBODY) {
-    if (w_fp64 && std::is_same<TP, float>::value)
-      GPF_HIP((launch_convolve<double, float>(n, (const double *)w, xw, (float *)psi,
-                                              (const float *)spec, (const float *)tw,
-                                              plan->gauge_c, sc + SC_GAMMA_W, x, s)));
-    else
-      GPF_HIP((launch_convolve<TP, TP>(n, (const TP *)w, xw, psi, spec, tw, plan->gauge_c,
-                                       sc + SC_GAMMA_W, x, s)));
-    if (out->d_u && out->d_v)
-      GPF_HIP(launch_vortex_velocity<TP>(g, in->nv, in->d_xv, in->d_yv, psi, in->u_inf,
-                                         in->v_inf, out->d_u, out->d_v, status, s));
-    if (out->d_scalars) GPF_HIP(launch_copy_doubles(sc, out->d_scalars, SC_COUNT, s));
-    return GPF_OK;
-  }
+struct ProblemRef {
+  gpf_plan *plan;
+  const gpf_body *body;
+  const gpf_inputs *in;
+  const gpf_outputs *out;
+  gpf_workspace *ws;
+};
 
-  // first convolution: s* (only its surface values are used)
-  const int ns = body->ns;
-  SolveScalars sv{};
+GroupCfg config_of(const ProblemRef &r) {
+  GroupCfg c;
+  c.n = r.plan->grid.n;
+  c.body = r.in->mode != GPF_NOBODY;
+  c.fp64_plan = r.plan->fp64;
+  c.conv1_fp64 = !c.fp64_plan && c.body && r.body->conv1_fp64;
+  return c;
+}
+
+bool same_cfg(const GroupCfg &a, const GroupCfg &b) {
+  return a.n == b.n && a.body == b.body && a.fp64_plan == b.fp64_plan &&
+         a.conv1_fp64 == b.conv1_fp64;
+}
+
+// fill the descriptors of one problem
+void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &c1, ConvDesc &c2) {
+  const gpf_plan *p = r.plan;
+  const gpf_inputs *in = r.in;
+  const gpf_outputs *out = r.out;
+  gpf_workspace *ws = r.ws;
+  const bool w64 = cfg.fp64_plan || cfg.conv1_fp64;
+  std::memset(&pd, 0, sizeof(pd));
+  std::memset(&c1, 0, sizeof(c1));
+  std::memset(&c2, 0, sizeof(c2));
+  pd.n = p->grid.n;
+  pd.dx = p->grid.dx;
+  pd.x0 = p->grid.x0;
+  pd.y0 = p->grid.y0;
+  pd.lgf = p->lgf.as<double>();
+  pd.nv = in->nv;
+  pd.xv = in->d_xv;
+  pd.yv = in->d_yv;
+  pd.gv = in->d_gv;
+  pd.w = w64 ? ws->w64.p : ws->w32.p;
+  pd.aux = ws->aux.as<double>();
+  pd.partials = ws->part.as<double>();
+  pd.status = out->d_status;
+  pd.psi = out->d_psi;
+  pd.u = (out->d_u && out->d_v) ? out->d_u : nullptr;
+  pd.v = out->d_v;
+  pd.sc_out = out->d_scalars;
+  SolveScalars &sv = pd.sv;
   sv.u_inf = in->u_inf;
   sv.v_inf = in->v_inf;
   sv.ub = in->ub;
@@ -273,61 +357,145 @@ gpf_status solve_impl(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in
   sv.gamma_w_in = in->gamma_w;
   sv.mode = in->mode;
   sv.m = in->mode == GPF_KUTTA_SHED ? in->m : 0;
-  for (int e = 0; e < body->nedge; ++e) sv.edges[e] = body->edges[e];
   for (int j = 0; j < sv.m; ++j) {
     sv.xnew[j] = in->h_xnew[j];
     sv.ynew[j] = in->h_ynew[j];
   }
-  double *rhs = plan->rhs.as<double>();
-  const auto surface_rhs_timed = [&](auto *sfield) -> gpf_status {
-    timer_begin(GPF_TK_SURFACE, s);
-    GPF_HIP(launch_surface_rhs(g, ns, body->xs.as<double>(), body->ys.as<double>(),
-                               body->st_i.as<int>(), body->st_w.as<double>(), sfield,
-                               plan->lgf.as<double>(), sv, rhs, status, s));
-    return GPF_OK;
-  };
-  if (conv1_fp64) {
-    double *sstar = plan->s64.as<double>();
-    GPF_HIP((launch_convolve<double, double>(n, (const double *)w, plan->x64.p, sstar,
-                                             plan->spec64.as<double>(), plan->tw64.as<double>(),
-                                             plan->gauge_c, sc + SC_GAMMA_W, x, s)));
-    gpf_status st = surface_rhs_timed(sstar);
-    if (st != GPF_OK) return st;
-  } else {
-    // s* goes into the caller's psi buffer, overwritten by the final field
-    GPF_HIP((launch_convolve<TP, TP>(n, (const TP *)w, xw, psi, spec, tw, plan->gauge_c,
-                                     sc + SC_GAMMA_W, x, s)));
-    gpf_status st = surface_rhs_timed(psi);
-    if (st != GPF_OK) return st;
+  const void *spec2 = cfg.fp64_plan ? p->spec64.p : p->spec32.p;
+  const void *tw2 = cfg.fp64_plan ? p->tw64.p : p->tw32.p;
+  void *x2 = cfg.fp64_plan ? ws->x64.p : ws->x32.p;
+  c1.in = pd.w;
+  c1.c = p->gauge_c;
+  c1.gamma = pd.aux + SC_GAMMA_W;
+  if (!cfg.body) {
+    // one convolution; it is the last reader of the source
+    c1.X = x2;
+    c1.out = out->d_psi;
+    c1.spec = spec2;
+    c1.tw = tw2;
+    c1.zero_in = 1;
+    pd.s1 = out->d_psi;
+    c2 = c1;
+    return;
   }
-  GPF_HIP(launch_gemv(ns, 1 + sv.m, body->sinv.as<double>(), rhs, plan->y.as<double>(), s));
-  double *ft = out->d_ftilde ? out->d_ftilde : plan->fwork.as<double>();
-  GPF_HIP(launch_constraints(ns, plan->y.as<double>(), body->f0.as<double>(), body->ds.as<double>(),
-                             body->gamma0, body->xs.as<double>(), body->ys.as<double>(), sv, sc,
-                             plan->fbuf.as<double>(), ft, status, s));
-  if (w_fp64)
-    GPF_HIP(launch_scatter_sheet<double>(g, ns, body->st_i.as<int>(), body->st_w.as<double>(),
-                                         body->ds.as<double>(), plan->fbuf.as<double>(), sv, sc,
-                                         (double *)w, s));
-  else
-    GPF_HIP(launch_scatter_sheet<float>(g, ns, body->st_i.as<int>(), body->st_w.as<double>(),
-                                        body->ds.as<double>(), plan->fbuf.as<double>(), sv, sc,
-                                        (float *)w, s));
-  timer_end(s);
-  // final convolution of all vorticity
-  if (w_fp64 && std::is_same<TP, float>::value)
-    GPF_HIP((launch_convolve<double, float>(n, (const double *)w, xw, (float *)psi,
-                                            (const float *)spec, (const float *)tw, plan->gauge_c,
-                                            sc + SC_GAMMA_SRC2, x, s)));
-  else
-    GPF_HIP((launch_convolve<TP, TP>(n, (const TP *)w, xw, psi, spec, tw, plan->gauge_c,
-                                     sc + SC_GAMMA_SRC2, x, s)));
-  if (out->d_u && out->d_v)
-    GPF_HIP(launch_vortex_velocity<TP>(g, in->nv, in->d_xv, in->d_yv, psi, in->u_inf, in->v_inf,
-                                       out->d_u, out->d_v, status, s));
-  if (out->d_f) GPF_HIP(launch_copy_doubles(plan->fbuf.as<double>(), out->d_f, ns, s));
-  if (out->d_scalars) GPF_HIP(launch_copy_doubles(sc, out->d_scalars, SC_COUNT, s));
+  const gpf_body *b = r.body;
+  for (int e = 0; e < b->nedge; ++e) sv.edges[e] = b->edges[e];
+  pd.ns = b->ns;
+  pd.xs = b->xs.as<double>();
+  pd.ys = b->ys.as<double>();
+  pd.ds = b->ds.as<double>();
+  pd.sinv = b->sinv.as<double>();
+  pd.f0 = b->f0.as<double>();
+  pd.st_i = b->st_i.as<int>();
+  pd.st_w = b->st_w.as<double>();
+  pd.gamma0 = b->gamma0;
+  pd.rhs = ws->rhs.as<double>();
+  pd.y = ws->y.as<double>();
+  pd.f = ws->f.as<double>();
+  pd.ft = ws->ft.as<double>();
+  pd.f_out = out->d_f;
+  pd.ft_out = out->d_ftilde;
+  // first convolution: only its surface values are used
+  c1.X = cfg.conv1_fp64 ? ws->x64.p : x2;
+  c1.out = cfg.conv1_fp64 ? ws->s64.p : out->d_psi;
+  c1.spec = cfg.conv1_fp64 ? p->spec64.p : spec2;
+  c1.tw = cfg.conv1_fp64 ? p->tw64.p : tw2;
+  c1.zero_in = 0;
+  pd.s1 = c1.out;
+  // final convolution of all vorticity; it leaves the source zeroed
+  c2.in = pd.w;
+  c2.X = x2;
+  c2.out = out->d_psi;
+  c2.spec = spec2;
+  c2.tw = tw2;
+  c2.gamma = pd.aux + SC_GAMMA_SRC2;
+  c2.c = p->gauge_c;
+  c2.zero_in = 1;
+}
+
+template <class TW, class T1, class T2>
+gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const ConvDesc *c1,
+                        const ConvDesc *c2, int nv_max, int ns_max, int m_max, int xcds,
+                        hipStream_t s) {
+  GPF_HIP(launch_scatter_vortices<TW>(pd, nb, nv_max, s));
+  GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, s)));
+  if (cfg.body) {
+    GPF_HIP(launch_surface_rhs<T1>(pd, nb, ns_max, m_max, s));
+    GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, s));
+    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, s)));
+  }
+  GPF_HIP(launch_vortex_velocity<T2>(pd, nb, nv_max, s));
   return GPF_OK;
+}
+
+// Run problems that share one configuration as one launch sequence.
+gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, DescRing &ring,
+                     int xcds, hipStream_t s) {
+  const int nb = (int)probs.size();
+  std::vector<char> blk(nb * kProblemDescBytes);
+  ProbDesc *pd = reinterpret_cast<ProbDesc *>(blk.data());
+  ConvDesc *c1 = reinterpret_cast<ConvDesc *>(blk.data() + nb * sizeof(ProbDesc));
+  ConvDesc *c2 = c1 + nb;
+  int nv_max = 0, ns_max = 0, m_max = 0;
+  for (int i = 0; i < nb; ++i) {
+    describe(probs[i], cfg, pd[i], c1[i], c2[i]);
+    nv_max = std::max(nv_max, pd[i].nv);
+    ns_max = std::max(ns_max, pd[i].ns);
+    m_max = std::max(m_max, pd[i].sv.m);
+  }
+  void *dev = nullptr;
+  GPF_TRY(ring.push(blk.data(), blk.size(), s, &dev));
+  const ProbDesc *dpd = static_cast<const ProbDesc *>(dev);
+  const ConvDesc *dc1 =
+      reinterpret_cast<const ConvDesc *>(static_cast<char *>(dev) + nb * sizeof(ProbDesc));
+  const ConvDesc *dc2 = dc1 + nb;
+  if (cfg.fp64_plan)
+    return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, xcds, s);
+  if (cfg.conv1_fp64)
+    return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, xcds, s);
+  return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, xcds, s);
+}
+
+gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
+                    const gpf_outputs *out) {
+  if (!plan || !in || !out) return fail(GPF_E_INVALID, "solve: null argument");
+  if (!out->d_psi || !out->d_status) return fail(GPF_E_INVALID, "solve: d_psi and d_status are required");
+  if (in->nv < 0 || in->nv > kMaxVortices) return fail(GPF_E_UNSUPPORTED, "solve: nv must be in [0, 2^22]");
+  if (in->nv > 0 && (!in->d_xv || !in->d_yv || !in->d_gv))
+    return fail(GPF_E_INVALID, "solve: null vortex arrays");
+  if (!is_finite(in->u_inf) || !is_finite(in->v_inf) || !is_finite(in->ub) || !is_finite(in->vb) ||
+      !is_finite(in->omega))
+    return fail(GPF_E_INVALID, "solve: non-finite freestream or body motion");
+  if (in->mode < GPF_NOBODY || in->mode > GPF_KUTTA_SHED) return fail(GPF_E_INVALID, "solve: unknown mode");
+  if (in->mode != GPF_NOBODY) {
+    if (!body) return fail(GPF_E_INVALID, "solve: this mode needs a body");
+    if (body->plan != plan) return fail(GPF_E_INVALID, "solve: body belongs to another plan");
+  }
+  if (in->mode == GPF_CIRCULATION && !is_finite(in->gamma_b))
+    return fail(GPF_E_INVALID, "solve: non-finite gamma_b");
+  if (in->mode == GPF_KUTTA_STEADY && body->nedge < 1)
+    return fail(GPF_E_INVALID, "solve: steady Kutta needs a body with an edge");
+  if (in->mode == GPF_KUTTA_SHED) {
+    if (in->m < 1 || in->m != body->nedge)
+      return fail(GPF_E_INVALID, "solve: shedding needs one new vortex per body edge");
+    for (int j = 0; j < in->m; ++j)
+      if (!is_finite(in->h_xnew[j]) || !is_finite(in->h_ynew[j]))
+        return fail(GPF_E_INVALID, "solve: non-finite new vortex position");
+    if (!std::isnan(in->gamma_w) && !is_finite(in->gamma_w))
+      return fail(GPF_E_INVALID, "solve: gamma_w must be finite or NaN");
+  }
+  return GPF_OK;
+}
+
+ProbDesc single_problem(const gpf_plan *plan) {
+  ProbDesc pd;
+  std::memset(&pd, 0, sizeof(pd));
+  pd.n = plan->grid.n;
+  pd.dx = plan->grid.dx;
+  pd.x0 = plan->grid.x0;
+  pd.y0 = plan->grid.y0;
+  pd.status = plan->status_scratch.as<unsigned>();
+  return pd;
 }
 
 }  // namespace
@@ -336,7 +504,7 @@ gpf_status solve_impl(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in
 extern "C" {
 
 const char *gpf_last_error(void) { return g_last_error.c_str(); }
-const char *gpf_version(void) { return "gpf 0.1 (gfx950)"; }
+const char *gpf_version(void) { return "gpf 0.2 (gfx950)"; }
 
 gpf_status gpf_lgf_table(int nmax, double *h_table) {
   if (nmax < 0 || nmax > 8192 || !h_table) return fail(GPF_E_INVALID, "gpf_lgf_table: bad arguments");
@@ -351,10 +519,10 @@ gpf_status gpf_ctx_create(int device, gpf_ctx **out) {
   GPF_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(GPF_E_INVALID, "gpf_ctx_create: bad device");
   GPF_HIP(hipSetDevice(device));
-  auto *c = new gpf_ctx;
-  c->device = device;
   hipDeviceProp_t prop;
   GPF_HIP(hipGetDeviceProperties(&prop, device));
+  auto *c = new gpf_ctx;
+  c->device = device;
   c->num_cu = prop.multiProcessorCount;
   c->xcds = xcd_count(device);
   *out = c;
@@ -379,26 +547,17 @@ gpf_status gpf_plan_create(gpf_ctx *ctx, const gpf_grid *grid, unsigned flags, g
   p->grid = *grid;
   p->flags = flags;
   p->fp64 = (flags & GPF_FP64) != 0;
-  gpf_status st;
   auto tab = get_table(n);
-  p->host_lgf = *tab;
-  if ((st = p->lgf.alloc(tab->size() * sizeof(double))) != GPF_OK) return st;
+  GPF_TRY(p->lgf.alloc(tab->size() * sizeof(double)));
   GPF_HIP(hipMemcpy(p->lgf.p, tab->data(), tab->size() * sizeof(double), hipMemcpyHostToDevice));
-  if (p->fp64) {
-    if ((st = p->ensure_fp64_conv()) != GPF_OK) return st;
-  } else {
-    if ((st = upload_spectrum<float>(p.get(), p->spec32, p->tw32)) != GPF_OK) return st;
-    if ((st = p->w32.alloc((size_t)n * n * sizeof(float))) != GPF_OK) return st;
-    if ((st = p->x32.alloc((size_t)(n + 1) * n * 2 * sizeof(float))) != GPF_OK) return st;
-    if (flags & GPF_CONV1_FP64)
-      if ((st = p->ensure_fp64_conv()) != GPF_OK) return st;
+  if (p->fp64 || (flags & GPF_CONV1_FP64)) GPF_TRY(p->ensure_fp64());
+  if (!p->fp64) {
+    GPF_TRY(upload_spectrum<float>(p.get(), p->spec32, p->tw32));
+    GPF_TRY(p->ws.ensure(n, true, false, 0));
   }
-  if ((st = p->sc.alloc(512)) != GPF_OK) return st;
-  GPF_HIP(hipMemset(p->sc.p, 0, 512));
-  if ((st = p->part.alloc(sizeof(double) * (size_t)scatter_vortex_blocks(1 << 22))) != GPF_OK)
-    return st;
-  if ((st = p->status_scratch.alloc(256)) != GPF_OK) return st;
+  GPF_TRY(p->status_scratch.alloc(256));
   GPF_HIP(hipMemset(p->status_scratch.p, 0, 256));
+  GPF_TRY(p->ring.init(kPlanRingSlots, kProblemDescBytes));
   GPF_HIP(hipDeviceSynchronize());
   *out = p.release();
   return GPF_OK;
@@ -429,29 +588,29 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   b->ns = ns;
   b->nedge = nedge;
   for (int e = 0; e < nedge; ++e) b->edges[e] = h_edges[e];
-  b->hx.assign(h_xs, h_xs + ns);
-  b->hy.assign(h_ys, h_ys + ns);
-  b->hds.assign(h_ds, h_ds + ns);
-  gpf_status st;
   const size_t vb = ns * sizeof(double);
-  if ((st = b->xs.alloc(vb)) || (st = b->ys.alloc(vb)) || (st = b->ds.alloc(vb)) ||
-      (st = b->st_i.alloc(2 * ns * sizeof(int))) || (st = b->st_w.alloc(8 * vb)) ||
-      (st = b->sinv.alloc((size_t)ns * vb)) || (st = b->f0.alloc(vb)) || (st = b->fhat0.alloc(vb)))
-    return st;
-  if ((st = plan->ensure_schur_ws(ns)) != GPF_OK) return st;
+  GPF_TRY(b->xs.alloc(vb));
+  GPF_TRY(b->ys.alloc(vb));
+  GPF_TRY(b->ds.alloc(vb));
+  GPF_TRY(b->st_i.alloc(2 * ns * sizeof(int)));
+  GPF_TRY(b->st_w.alloc(8 * vb));
+  GPF_TRY(b->sinv.alloc((size_t)ns * vb));
+  GPF_TRY(b->f0.alloc(vb));
+  GPF_TRY(b->fhat0.alloc(vb));
+  GPF_TRY(plan->ws.ensure(g.n, !plan->fp64, plan->fp64, ns));
   GPF_HIP(hipMemcpy(b->xs.p, h_xs, vb, hipMemcpyHostToDevice));
   GPF_HIP(hipMemcpy(b->ys.p, h_ys, vb, hipMemcpyHostToDevice));
   GPF_HIP(hipMemcpy(b->ds.p, h_ds, vb, hipMemcpyHostToDevice));
   hipStream_t s = nullptr;
   unsigned *status = plan->status_scratch.as<unsigned>();
-  GPF_HIP(launch_surface_stencils(geom(plan), ns, b->xs.as<double>(), b->ys.as<double>(),
+  GPF_HIP(launch_surface_stencils(g.n, g.dx, g.x0, g.y0, ns, b->xs.as<double>(), b->ys.as<double>(),
                                   b->st_i.as<int>(), b->st_w.as<double>(), status, s));
   DevBuf S;
-  if ((st = S.alloc((size_t)ns * vb)) != GPF_OK) return st;
+  GPF_TRY(S.alloc((size_t)ns * vb));
   GPF_HIP(launch_schur_build(g.n, ns, b->st_i.as<int>(), b->st_w.as<double>(), b->ds.as<double>(),
                              plan->lgf.as<double>(), S.as<double>(), s));
   double min_piv = 0.0;
-  if ((st = invert_fp64(ns, S.as<double>(), b->sinv.as<double>(), s, &min_piv)) != GPF_OK) return st;
+  GPF_TRY(invert_fp64(ns, S.as<double>(), b->sinv.as<double>(), s, &min_piv));
   if (!(min_piv > 1e-14)) return fail(GPF_E_SINGULAR, "gpf_body_create: Schur complement is singular");
   // f0 = S^-1 1; amplification probe: r = -y_s and the alternating vector
   std::vector<double> X(3 * (size_t)ns);
@@ -464,7 +623,8 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   if (rmax == 0.0) rmax = 1.0;
   for (int p = 0; p < ns; ++p) X[2 * ns + p] = (p & 1) ? -rmax : rmax;
   DevBuf dX, dY;
-  if ((st = dX.alloc(3 * vb)) || (st = dY.alloc(3 * vb))) return st;
+  GPF_TRY(dX.alloc(3 * vb));
+  GPF_TRY(dY.alloc(3 * vb));
   GPF_HIP(hipMemcpy(dX.p, X.data(), 3 * vb, hipMemcpyHostToDevice));
   GPF_HIP(launch_gemv(ns, 3, b->sinv.as<double>(), dX.as<double>(), dY.as<double>(), s));
   std::vector<double> Y(3 * (size_t)ns);
@@ -489,11 +649,9 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   if (!(std::fabs(g0) > 0.0) || !is_finite(g0)) return fail(GPF_E_SINGULAR, "gpf_body_create: Gamma0 is zero");
   b->gamma0 = g0;
   b->amp = (nr > 0.0 && npert > 0.0) ? std::sqrt(nf / nr) / std::sqrt(npert / nrhs) : INFINITY;
-  const bool fp32_plan = !plan->fp64;
-  b->conv1_fp64 = fp32_plan && ((plan->flags & GPF_CONV1_FP64) ||
-                                ((plan->flags & GPF_POLICY_AUTO) && b->amp > GPF_AMP_THRESHOLD));
-  if (b->conv1_fp64)
-    if ((st = plan->ensure_fp64_conv()) != GPF_OK) return st;
+  b->conv1_fp64 = !plan->fp64 && ((plan->flags & GPF_CONV1_FP64) ||
+                                  ((plan->flags & GPF_POLICY_AUTO) && b->amp > GPF_AMP_THRESHOLD));
+  if (b->conv1_fp64) GPF_TRY(plan->ensure_fp64());
   GPF_HIP(hipMemcpy(b->f0.p, Y.data(), vb, hipMemcpyHostToDevice));
   GPF_HIP(hipMemcpy(b->fhat0.p, fh.data(), vb, hipMemcpyHostToDevice));
   GPF_HIP(hipDeviceSynchronize());
@@ -526,22 +684,26 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
                                    unsigned int *d_status, void *hip_stream) {
   if (!plan || !d_w || nv < 0 || (nv > 0 && (!d_xv || !d_yv || !d_gv)))
     return fail(GPF_E_INVALID, "gpf_regularize_vortices: bad arguments");
-  if (nv > (1 << 22)) return fail(GPF_E_UNSUPPORTED, "gpf_regularize_vortices: nv above 2^22");
+  if (nv > kMaxVortices) return fail(GPF_E_UNSUPPORTED, "gpf_regularize_vortices: nv above 2^22");
   hipStream_t s = as_stream(hip_stream);
+  TimerScope scope(plan->timing ? &plan->timer : nullptr);
   const int n = plan->grid.n;
-  const size_t bytes = (size_t)n * n * (plan->fp64 ? 8 : 4);
-  if (!accumulate) GPF_HIP(launch_fill(d_w, bytes, s));
-  unsigned *status = d_status ? d_status : plan->status_scratch.as<unsigned>();
-  double *sc = plan->sc.as<double>();
-  unsigned *counter = reinterpret_cast<unsigned *>(plan->sc.as<char>() + SC_COUNTER_OFFSET_BYTES);
+  if (!accumulate) GPF_HIP(launch_fill(d_w, (size_t)n * n * (plan->fp64 ? 8 : 4), s));
+  ProbDesc pd = single_problem(plan);
+  pd.nv = nv;
+  pd.xv = d_xv;
+  pd.yv = d_yv;
+  pd.gv = d_gv;
+  pd.w = d_w;
+  pd.aux = plan->ws.aux.as<double>();
+  pd.partials = plan->ws.part.as<double>();
+  if (d_status) pd.status = d_status;
+  void *dev = nullptr;
+  GPF_TRY(plan->ring.push(&pd, sizeof(pd), s, &dev));
   if (plan->fp64)
-    GPF_HIP(launch_scatter_vortices<double>(geom(plan), nv, d_xv, d_yv, d_gv, (double *)d_w,
-                                            plan->part.as<double>(), sc + SC_GAMMA_W, counter,
-                                            status, s));
+    GPF_HIP(launch_scatter_vortices<double>(static_cast<ProbDesc *>(dev), 1, nv, s));
   else
-    GPF_HIP(launch_scatter_vortices<float>(geom(plan), nv, d_xv, d_yv, d_gv, (float *)d_w,
-                                           plan->part.as<double>(), sc + SC_GAMMA_W, counter,
-                                           status, s));
+    GPF_HIP(launch_scatter_vortices<float>(static_cast<ProbDesc *>(dev), 1, nv, s));
   return GPF_OK;
 }
 
@@ -551,21 +713,25 @@ gpf_status gpf_convolve(gpf_plan *plan, const void *d_w, void *d_s, double gamma
     return fail(GPF_E_INVALID, "gpf_convolve: bad arguments");
   hipStream_t s = as_stream(hip_stream);
   TimerScope scope(plan->timing ? &plan->timer : nullptr);
-  // the gauge term is read from device memory by the last pass
-  double *slot = plan->sc.as<double>() + SC_COUNT;  // scratch slot after the named ones
-  GPF_HIP(hipMemcpyAsync(slot, &gamma_src, sizeof(double), hipMemcpyHostToDevice, s));
+  ConvDesc cd;
+  std::memset(&cd, 0, sizeof(cd));
+  cd.in = const_cast<void *>(d_w);
+  cd.X = plan->fp64 ? plan->ws.x64.p : plan->ws.x32.p;
+  cd.out = d_s;
+  cd.spec = plan->fp64 ? plan->spec64.p : plan->spec32.p;
+  cd.tw = plan->fp64 ? plan->tw64.p : plan->tw32.p;
+  cd.gamma = nullptr;
+  cd.gamma_val = gamma_src;
+  cd.c = plan->gauge_c;
+  cd.zero_in = 0;
+  void *dev = nullptr;
+  GPF_TRY(plan->ring.push(&cd, sizeof(cd), s, &dev));
   const int n = plan->grid.n;
   const int x = plan->ctx->xcds;
   if (plan->fp64)
-    GPF_HIP((launch_convolve<double, double>(n, (const double *)d_w, plan->x64.p, (double *)d_s,
-                                             plan->spec64.as<double>(), plan->tw64.as<double>(),
-                                             plan->gauge_c, slot, x, s)));
+    GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, x, s)));
   else
-    GPF_HIP((launch_convolve<float, float>(n, (const float *)d_w, plan->x32.p, (float *)d_s,
-                                           plan->spec32.as<float>(), plan->tw32.as<float>(),
-                                           plan->gauge_c, slot, x, s)));
-  // the host value must stay alive until the copy has been issued
-  GPF_HIP(hipStreamSynchronize(s));
+    GPF_HIP((launch_convolve<float, float>(n, static_cast<ConvDesc *>(dev), 1, x, s)));
   return GPF_OK;
 }
 
@@ -589,58 +755,103 @@ gpf_status gpf_vortex_velocity(gpf_plan *plan, const void *d_s, int nv, const do
   if (!plan || !d_s || nv < 0 || (nv > 0 && (!d_xv || !d_yv || !d_u || !d_v)) ||
       !is_finite(u_inf) || !is_finite(v_inf))
     return fail(GPF_E_INVALID, "gpf_vortex_velocity: bad arguments");
+  if (nv > kMaxVortices) return fail(GPF_E_UNSUPPORTED, "gpf_vortex_velocity: nv above 2^22");
   hipStream_t s = as_stream(hip_stream);
-  unsigned *status = d_status ? d_status : plan->status_scratch.as<unsigned>();
+  TimerScope scope(plan->timing ? &plan->timer : nullptr);
+  ProbDesc pd = single_problem(plan);
+  pd.nv = nv;
+  pd.xv = d_xv;
+  pd.yv = d_yv;
+  pd.psi = d_s;
+  pd.u = d_u;
+  pd.v = d_v;
+  pd.sv.u_inf = u_inf;
+  pd.sv.v_inf = v_inf;
+  if (d_status) pd.status = d_status;
+  void *dev = nullptr;
+  GPF_TRY(plan->ring.push(&pd, sizeof(pd), s, &dev));
   if (plan->fp64)
-    GPF_HIP(launch_vortex_velocity<double>(geom(plan), nv, d_xv, d_yv, (const double *)d_s, u_inf,
-                                           v_inf, d_u, d_v, status, s));
+    GPF_HIP(launch_vortex_velocity<double>(static_cast<ProbDesc *>(dev), 1, nv, s));
   else
-    GPF_HIP(launch_vortex_velocity<float>(geom(plan), nv, d_xv, d_yv, (const float *)d_s, u_inf,
-                                          v_inf, d_u, d_v, status, s));
+    GPF_HIP(launch_vortex_velocity<float>(static_cast<ProbDesc *>(dev), 1, nv, s));
   return GPF_OK;
 }
 
 // ---------------------------------------------------------------------------
-// full solve
+// solves
 // ---------------------------------------------------------------------------
-
 
 gpf_status gpf_solve(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
                      const gpf_outputs *out, void *hip_stream) {
-  if (!plan || !in || !out) return fail(GPF_E_INVALID, "gpf_solve: null argument");
-  if (!out->d_psi || !out->d_status) return fail(GPF_E_INVALID, "gpf_solve: d_psi and d_status are required");
-  if (in->nv < 0 || in->nv > (1 << 22)) return fail(GPF_E_UNSUPPORTED, "gpf_solve: nv must be in [0, 2^22]");
-  if (in->nv > 0 && (!in->d_xv || !in->d_yv || !in->d_gv))
-    return fail(GPF_E_INVALID, "gpf_solve: null vortex arrays");
-  if (!is_finite(in->u_inf) || !is_finite(in->v_inf) || !is_finite(in->ub) || !is_finite(in->vb) ||
-      !is_finite(in->omega))
-    return fail(GPF_E_INVALID, "gpf_solve: non-finite freestream or body motion");
-  if (in->mode < GPF_NOBODY || in->mode > GPF_KUTTA_SHED)
-    return fail(GPF_E_INVALID, "gpf_solve: unknown mode");
-  if (in->mode != GPF_NOBODY) {
-    if (!body) return fail(GPF_E_INVALID, "gpf_solve: this mode needs a body");
-    if (body->plan != plan) return fail(GPF_E_INVALID, "gpf_solve: body belongs to another plan");
-  }
-  if (in->mode == GPF_CIRCULATION && !is_finite(in->gamma_b))
-    return fail(GPF_E_INVALID, "gpf_solve: non-finite gamma_b");
-  if (in->mode == GPF_KUTTA_STEADY && body->nedge < 1)
-    return fail(GPF_E_INVALID, "gpf_solve: steady Kutta needs a body with an edge");
-  if (in->mode == GPF_KUTTA_SHED) {
-    if (in->m < 1 || in->m != body->nedge)
-      return fail(GPF_E_INVALID, "gpf_solve: shedding needs one new vortex per body edge");
-    for (int j = 0; j < in->m; ++j)
-      if (!is_finite(in->h_xnew[j]) || !is_finite(in->h_ynew[j]))
-        return fail(GPF_E_INVALID, "gpf_solve: non-finite new vortex position");
-    if (!std::isnan(in->gamma_w) && !is_finite(in->gamma_w))
-      return fail(GPF_E_INVALID, "gpf_solve: gamma_w must be finite or NaN");
-  }
+  GPF_TRY(validate(plan, body, in, out));
   hipError_t e = hipSetDevice(plan->ctx->device);
   if (e != hipSuccess) return fail(GPF_E_DEVICE, hipGetErrorString(e));
   hipStream_t s = as_stream(hip_stream);
   TimerScope scope(plan->timing ? &plan->timer : nullptr);
-  const bool conv1_fp64 = body && body->conv1_fp64 && in->mode != GPF_NOBODY;
-  if (plan->fp64) return solve_impl<double>(plan, body, in, out, s, false);
-  return solve_impl<float>(plan, body, in, out, s, conv1_fp64);
+  ProblemRef r{plan, in->mode == GPF_NOBODY ? nullptr : body, in, out, &plan->ws};
+  const GroupCfg cfg = config_of(r);
+  std::vector<ProblemRef> one{r};
+  return run_group(cfg, one, plan->ring, plan->ctx->xcds, s);
+}
+
+gpf_status gpf_batch_create(gpf_ctx *ctx, int max_problems, gpf_batch **out) {
+  if (!ctx || !out || max_problems < 1 || max_problems > 4096)
+    return fail(GPF_E_INVALID, "gpf_batch_create: bad arguments");
+  *out = nullptr;
+  GPF_HIP(hipSetDevice(ctx->device));
+  std::unique_ptr<gpf_batch> b(new gpf_batch);
+  b->ctx = ctx;
+  b->max_problems = max_problems;
+  b->ws.resize(max_problems, nullptr);
+  for (auto &w : b->ws) w = new gpf_workspace;
+  GPF_TRY(b->ring.init(16, (size_t)max_problems * kProblemDescBytes));
+  *out = b.release();
+  return GPF_OK;
+}
+
+void gpf_batch_destroy(gpf_batch *batch) { delete batch; }
+
+gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
+                             const gpf_body *const *bodies, const gpf_inputs *inputs,
+                             const gpf_outputs *outputs, void *hip_stream) {
+  if (!batch || nprob < 0 || (nprob > 0 && (!plans || !inputs || !outputs)))
+    return fail(GPF_E_INVALID, "gpf_solve_batched: bad arguments");
+  if (nprob > batch->max_problems)
+    return fail(GPF_E_INVALID, "gpf_solve_batched: more problems than the batch holds");
+  GPF_HIP(hipSetDevice(batch->ctx->device));
+  std::vector<ProblemRef> refs;
+  for (int i = 0; i < nprob; ++i) {
+    const gpf_body *b = bodies ? bodies[i] : nullptr;
+    GPF_TRY(validate(plans[i], b, &inputs[i], &outputs[i]));
+    if (plans[i]->ctx->device != batch->ctx->device)
+      return fail(GPF_E_INVALID, "gpf_solve_batched: plan on another device");
+    for (int k = 0; k < i; ++k)
+      if (outputs[k].d_psi == outputs[i].d_psi)
+        return fail(GPF_E_INVALID, "gpf_solve_batched: two problems share an output field");
+    ProblemRef r{plans[i], inputs[i].mode == GPF_NOBODY ? nullptr : b, &inputs[i], &outputs[i],
+                 batch->ws[i]};
+    const GroupCfg cfg = config_of(r);
+    const bool w64 = cfg.fp64_plan || cfg.conv1_fp64;
+    GPF_TRY(r.ws->ensure(cfg.n, !cfg.fp64_plan, w64, r.body ? r.body->ns : 0));
+    refs.push_back(r);
+  }
+  if (nprob == 0) return GPF_OK;
+  hipStream_t s = as_stream(hip_stream);
+  TimerScope scope(plans[0]->timing ? &plans[0]->timer : nullptr);
+  // group by configuration, keeping the first-seen order of the groups
+  std::vector<char> done(nprob, 0);
+  for (int i = 0; i < nprob; ++i) {
+    if (done[i]) continue;
+    const GroupCfg cfg = config_of(refs[i]);
+    std::vector<ProblemRef> grp;
+    for (int k = i; k < nprob; ++k)
+      if (!done[k] && same_cfg(cfg, config_of(refs[k]))) {
+        grp.push_back(refs[k]);
+        done[k] = 1;
+      }
+    GPF_TRY(run_group(cfg, grp, batch->ring, batch->ctx->xcds, s));
+  }
+  return GPF_OK;
 }
 
 gpf_status gpf_timing_enable(gpf_plan *plan, int enable) {
@@ -653,8 +864,7 @@ gpf_status gpf_timing_enable(gpf_plan *plan, int enable) {
 gpf_status gpf_timing_read(gpf_plan *plan, int kind, long long *count, double *total_ms) {
   if (!plan || kind < 0 || kind >= GPF_TK_COUNT || !count || !total_ms)
     return fail(GPF_E_INVALID, "gpf_timing_read: bad arguments");
-  gpf_status st = plan->timer.flush();
-  if (st != GPF_OK) return st;
+  GPF_TRY(plan->timer.flush());
   *count = plan->timer.count[kind];
   *total_ms = plan->timer.total_ms[kind];
   return GPF_OK;

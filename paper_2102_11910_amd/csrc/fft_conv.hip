@@ -201,14 +201,16 @@ __device__ __forceinline__ int xcd_block(int xcds) {
 // pass 1: rows, real -> half spectrum, stored k-major
 // ---------------------------------------------------------------------------
 template <class Tin, class T, int N>
-__global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const Tin *__restrict__ w,
-                                                           typename CT<T>::V *__restrict__ X,
-                                                           const typename CT<T>::V *__restrict__ tw,
+__global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const ConvDesc *__restrict__ cd,
                                                            int xcds) {
   using V = typename CT<T>::V;
   using P = Plan<N>;
   constexpr int n = N / 2;
   __shared__ V lds[P::SEQ * P::LDS_SEQ];
+  const ConvDesc &C = cd[blockIdx.y];
+  Tin *__restrict__ w = static_cast<Tin *>(C.in);
+  V *__restrict__ X = static_cast<V *>(C.X);
+  const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
   const int j0 = xcd_block(xcds) * 2 * P::SEQ;
 
@@ -221,6 +223,11 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const Tin *__restrict
     lds[q * P::LDS_SEQ + pad(t)] = z;
   }
   __syncthreads();
+  if (C.zero_in) {
+    // this pass is the last reader of the source (all of its rows are in
+    // LDS now): leave it zero for the next accumulation
+    for (int idx = tid; idx < 2 * P::SEQ * n; idx += P::WGT) w[(size_t)j0 * n + idx] = (Tin)0;
+  }
   const int q = tid / P::TPS, lane = tid % P::TPS;
   fft_seq<T, N, false, true, false>(lds + q * P::LDS_SEQ, tw, lane);
 
@@ -247,13 +254,15 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const Tin *__restrict
 // pass 2: columns, forward FFT x spectrum x inverse FFT
 // ---------------------------------------------------------------------------
 template <class T, int N>
-__global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(typename CT<T>::V *__restrict__ X,
-                                                            const T *__restrict__ spec,
-                                                            const typename CT<T>::V *__restrict__ tw) {
+__global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__restrict__ cd) {
   using V = typename CT<T>::V;
   using P = Plan<N>;
   constexpr int n = N / 2;
   __shared__ V lds[P::SEQ * P::LDS_SEQ];
+  const ConvDesc &C = cd[blockIdx.y];
+  V *__restrict__ X = static_cast<V *>(C.X);
+  const T *__restrict__ spec = static_cast<const T *>(C.spec);
+  const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * P::SEQ;
 
@@ -291,16 +300,17 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(typename CT<T>::V *_
 // pass 3: rows, two half spectra -> two real rows, gauge epilogue
 // ---------------------------------------------------------------------------
 template <class T, int N>
-__global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const typename CT<T>::V *__restrict__ X,
-                                                           T *__restrict__ s,
-                                                           const typename CT<T>::V *__restrict__ tw,
-                                                           double c, const double *__restrict__ gamma_src,
+__global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const ConvDesc *__restrict__ cd,
                                                            int xcds) {
   using V = typename CT<T>::V;
   using V2 = typename CT<T>::V2;
   using P = Plan<N>;
   constexpr int n = N / 2;
   __shared__ V lds[P::SEQ * P::LDS_SEQ];
+  const ConvDesc &C = cd[blockIdx.y];
+  const V *__restrict__ X = static_cast<const V *>(C.X);
+  T *__restrict__ s = static_cast<T *>(C.out);
+  const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
   const int j0 = xcd_block(xcds) * 2 * P::SEQ;
 
@@ -328,7 +338,7 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const typename CT<T>:
   const int q = tid / P::TPS, lane = tid % P::TPS;
   fft_seq<T, N, true, false, true>(lds + q * P::LDS_SEQ, tw, lane);
 
-  const T shift = (T)(c * gamma_src[0]);
+  const T shift = (T)(C.c * (C.gamma ? C.gamma[0] : C.gamma_val));
   for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
     const int qq = idx / n, t = idx % n;
     const V z = lds[qq * P::LDS_SEQ + pad(t)];
@@ -339,25 +349,20 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const typename CT<T>:
 }
 
 template <class Tin, class T, int N>
-hipError_t run_conv(const Tin *w, void *xwork, T *s, const T *spec, const T *tw,
-                    double c, const double *gamma_src, int xcds, hipStream_t st) {
-  using V = typename CT<T>::V;
+hipError_t run_conv(const ConvDesc *d, int nb, int xcds, hipStream_t st) {
   using P = Plan<N>;
   constexpr int n = N / 2;
-  V *X = static_cast<V *>(xwork);
-  const V *twv = reinterpret_cast<const V *>(tw);
   const int rb = n / (2 * P::SEQ);
   const int cb = (n + 1 + P::SEQ - 1) / P::SEQ;
   constexpr bool D = std::is_same<T, double>::value;
   timer_begin(D ? GPF_TK_ROWS_FWD64 : GPF_TK_ROWS_FWD, st);
-  hipLaunchKernelGGL((k_rows_fwd<Tin, T, N>), dim3(rb), dim3(P::WGT), 0, st, w, X, twv, xcds);
+  hipLaunchKernelGGL((k_rows_fwd<Tin, T, N>), dim3(rb, nb), dim3(P::WGT), 0, st, d, xcds);
   timer_end(st);
   timer_begin(D ? GPF_TK_COLS64 : GPF_TK_COLS, st);
-  hipLaunchKernelGGL((k_cols_conv<T, N>), dim3(cb), dim3(P::WGT), 0, st, X, spec, twv);
+  hipLaunchKernelGGL((k_cols_conv<T, N>), dim3(cb, nb), dim3(P::WGT), 0, st, d);
   timer_end(st);
   timer_begin(D ? GPF_TK_ROWS_INV64 : GPF_TK_ROWS_INV, st);
-  hipLaunchKernelGGL((k_rows_inv<T, N>), dim3(rb), dim3(P::WGT), 0, st, X, s, twv, c,
-                     gamma_src, xcds);
+  hipLaunchKernelGGL((k_rows_inv<T, N>), dim3(rb, nb), dim3(P::WGT), 0, st, d, xcds);
   timer_end(st);
   return hipGetLastError();
 }
@@ -365,30 +370,22 @@ hipError_t run_conv(const Tin *w, void *xwork, T *s, const T *spec, const T *tw,
 }  // namespace
 
 template <class Tin, class T>
-hipError_t launch_convolve(int n, const Tin *w, void *xwork, T *s, const T *spec,
-                           const T *tw, double c, const double *gamma_src, int xcds,
-                           hipStream_t st) {
+hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, hipStream_t st) {
   switch (n) {
-    case 16: return run_conv<Tin, T, 32>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
-    case 32: return run_conv<Tin, T, 64>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
-    case 64: return run_conv<Tin, T, 128>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
-    case 128: return run_conv<Tin, T, 256>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
-    case 256: return run_conv<Tin, T, 512>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
-    case 512: return run_conv<Tin, T, 1024>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
-    case 1024: return run_conv<Tin, T, 2048>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
-    case 2048: return run_conv<Tin, T, 4096>(w, xwork, s, spec, tw, c, gamma_src, xcds, st);
+    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, st);
+    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, st);
+    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, st);
+    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, st);
+    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, st);
+    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, st);
+    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, st);
+    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_convolve<float, float>(int, const float *, void *, float *,
-                                                  const float *, const float *, double,
-                                                  const double *, int, hipStream_t);
-template hipError_t launch_convolve<double, double>(int, const double *, void *, double *,
-                                                    const double *, const double *, double,
-                                                    const double *, int, hipStream_t);
-template hipError_t launch_convolve<double, float>(int, const double *, void *, float *,
-                                                   const float *, const float *, double,
-                                                   const double *, int, hipStream_t);
+template hipError_t launch_convolve<float, float>(int, const ConvDesc *, int, int, hipStream_t);
+template hipError_t launch_convolve<double, double>(int, const ConvDesc *, int, int, hipStream_t);
+template hipError_t launch_convolve<double, float>(int, const ConvDesc *, int, int, hipStream_t);
 
 }  // namespace gpf

@@ -1,4 +1,8 @@
 // Internal declarations of the gpf library (host runtime + HIP kernels).
+//
+// Every solve kernel works on a batch of independent problems: blockIdx.y
+// selects a problem, whose pointers and scalars come from a descriptor in
+// device memory.  A plain solve is a batch of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,6 +29,12 @@ gpf_status fail(gpf_status st, const std::string &msg);
                                            hipGetErrorString(e_));           \
   } while (0)
 
+#define GPF_TRY(call)                \
+  do {                               \
+    gpf_status s_ = (call);          \
+    if (s_ != GPF_OK) return s_;     \
+  } while (0)
+
 // ---------------------------------------------------------------------------
 // host numerics (lgf_host.cpp)
 // ---------------------------------------------------------------------------
@@ -36,8 +46,19 @@ void lgf_table_host(int nmax, double *table);
 double lgf_spectrum_host(int n, const double *table, double *spec);
 
 // ---------------------------------------------------------------------------
-// device objects
+// device memory and timing
 // ---------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf();
+  gpf_status alloc(size_t nbytes);  // keeps the buffer if it is large enough
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
 // Per-kernel event timing (opt-in).  Launchers bracket their kernels with
 // timer_begin/timer_end; the marks go to the timer installed for the
 // current thread by the API entry point (none: no-op).
@@ -64,20 +85,141 @@ struct TimerScope {
   ~TimerScope() { timer_install(nullptr); }
 };
 
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  ~DevBuf();
-  gpf_status alloc(size_t nbytes);
-  template <class T> T *as() const { return static_cast<T *>(p); }
+// Ring of descriptor slots: host staging in pinned memory, copied to device
+// memory on the caller's stream.  A slot is reused only after the event
+// recorded behind its copy has completed; slots taken while the stream is
+// being captured into a graph are never reused.
+struct DescRing {
+  int slots = 0;
+  size_t slot_bytes = 0;
+  char *host = nullptr;
+  DevBuf dev;
+  std::vector<hipEvent_t> ev;
+  std::vector<char> busy, pinned;
+  int next = 0;
+  DescRing() = default;
+  DescRing(const DescRing &) = delete;
+  DescRing &operator=(const DescRing &) = delete;
+  ~DescRing();
+  gpf_status init(int nslots, size_t bytes_per_slot);
+  gpf_status push(const void *src, size_t bytes, hipStream_t s, void **dptr);
 };
+
+// ---------------------------------------------------------------------------
+// descriptors
+// ---------------------------------------------------------------------------
+// scalar slots (doubles) of a problem's aux block
+enum ScalarSlot {
+  SC_GAMMA_W = 0,     // circulation of the vortices (sum Gamma_q)
+  SC_GAMMA_SRC2 = 1,  // source circulation of the final convolution
+  SC_S0 = 2,
+  SC_GAMMA_B = 3,
+  SC_GAMMA_NEW = 4,   // .. 4 + GPF_MAX_EDGES
+  SC_COUNT = 4 + GPF_MAX_EDGES,
+  SC_USER = SC_COUNT,  // gamma_src of a building-block convolution
+  AUX_DOUBLES = 32,    // counters follow the doubles
+  AUX_BYTES = AUX_DOUBLES * 8 + 64
+};
+
+struct SolveScalars {
+  double u_inf, v_inf, ub, vb, omega;
+  double gamma_b, gamma_w_in;   // gamma_w_in NaN -> use the device sum
+  int mode, m;
+  int edges[GPF_MAX_EDGES];
+  double xnew[GPF_MAX_EDGES], ynew[GPF_MAX_EDGES];
+};
+
+// one convolution of one problem: out = conv(in) - c * gamma[0]
+struct ConvDesc {
+  void *in;            // n*n source (zeroed after it is read when zero_in)
+  void *X;             // (n+1)*n complex intermediate
+  void *out;           // n*n result
+  const void *spec;    // (n+1)^2 scaled spectrum
+  const void *tw;      // 2n twiddles
+  const double *gamma; // source circulation (device); null: use gamma_val
+  double gamma_val;
+  double c;            // gauge shift of the spectrum
+  int zero_in;
+};
+
+struct ProbDesc {
+  // grid
+  int n;
+  double dx, x0, y0;
+  const double *lgf;            // (n+1)^2 LGF table
+  // vortices
+  int nv;
+  const double *xv, *yv, *gv;
+  // fields
+  void *w;                      // source field (zero on entry)
+  const void *s1;               // result of the first convolution
+  // per-problem aux: scalars, partial sums, counters
+  double *aux;
+  double *partials;
+  unsigned *status;
+  // body
+  int ns;
+  const double *xs, *ys, *ds, *sinv, *f0;
+  const int *st_i;
+  const double *st_w;
+  double gamma0;
+  double *rhs, *y, *f, *ft;     // Schur workspaces: ns x (1+m)
+  // outputs (nullable)
+  const void *psi;              // final field (velocities read it)
+  double *u, *v, *f_out, *ft_out, *sc_out;
+  SolveScalars sv;
+};
+
+__host__ __device__ inline unsigned *aux_counter(double *aux, int k) {
+  return reinterpret_cast<unsigned *>(aux + AUX_DOUBLES) + k;
+}
+
+// ---------------------------------------------------------------------------
+// kernel launchers (asynchronous on `s`; `nb` problems, same n)
+// ---------------------------------------------------------------------------
+int scatter_blocks(int nv_max);
+template <class T>
+hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
+template <class Tin, class T>
+hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, hipStream_t s);
+template <class T>
+hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
+template <class T>
+hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
+template <class T>
+hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
+
+// single-problem helpers used at setup and by the building blocks
+hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
+                                   const double *xs, const double *ys, int *st_i,
+                                   double *st_w, unsigned *status, hipStream_t s);
+template <class T>
+hipError_t launch_interp_surface(int n, int ns, const int *st_i, const double *st_w,
+                                 const T *field, double *r, hipStream_t s);
+hipError_t launch_schur_build(int n, int ns, const int *st_i, const double *st_w,
+                              const double *ds, const double *lgf, double *S, hipStream_t s);
+gpf_status invert_fp64(int ns, double *A, double *Ainv, hipStream_t s, double *min_pivot_rel);
+hipError_t launch_gemv(int ns, int ncol, const double *A, const double *X, double *Y,
+                       hipStream_t s);
 
 }  // namespace gpf
 
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
 struct gpf_ctx {
   int device = 0;
   int num_cu = 0;
   int xcds = 8;
+};
+
+// Workspace of one problem slot: source fields, intermediates, first
+// convolution output, aux block and Schur vectors.
+struct gpf_workspace {
+  int n = 0, ns = 0;
+  gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y, f, ft;
+  gpf_status ensure(int n, bool need32, bool need64, int ns);
 };
 
 struct gpf_plan {
@@ -86,26 +228,15 @@ struct gpf_plan {
   unsigned flags = 0;
   bool fp64 = false;          // field type double
   double gauge_c = 0.0;       // spectrum shift restored as -c * gamma_src
-  // resident constants
-  gpf::DevBuf lgf;            // (n+1)^2 double LGF table (Schur build, new vortices)
+  gpf::DevBuf lgf;            // (n+1)^2 double LGF table
   gpf::DevBuf spec32, spec64; // (n+1)^2 scaled, centred spectrum
   gpf::DevBuf tw32, tw64;     // 2n twiddles exp(-2 pi i k / 2n)
-  // workspaces
-  gpf::DevBuf w32, w64;       // n*n source fields
-  gpf::DevBuf x32, x64;       // (n+1)*n complex intermediate, k-major
-  gpf::DevBuf s64;            // n*n FP64 field (first convolution in FP64)
-  gpf::DevBuf sc;             // device scalars (double) and counters
-  gpf::DevBuf part;           // block partial sums (double)
-  gpf::DevBuf rhs, y;         // ns x (1+m) Schur right-hand sides and results
-  gpf::DevBuf fbuf;           // ns sheet strength scratch
-  gpf::DevBuf fwork;          // ns ftilde scratch
-  gpf::DevBuf status_scratch; // used when building blocks get no status word
-  int ns_cap = 0;
-  std::vector<double> host_lgf;  // host copy of the table
+  gpf::DevBuf status_scratch; // status word for building blocks given none
+  gpf_workspace ws;           // workspace of plain solves
+  gpf::DescRing ring;         // descriptors of plain solves
   gpf::KernelTimer timer;
   bool timing = false;
-  gpf_status ensure_fp64_conv();
-  gpf_status ensure_schur_ws(int ns);
+  gpf_status ensure_fp64();
 };
 
 struct gpf_body {
@@ -116,101 +247,16 @@ struct gpf_body {
   double gamma0 = 0.0;
   double amp = 0.0;
   bool conv1_fp64 = false;
-  std::vector<double> hx, hy, hds;
   gpf::DevBuf xs, ys, ds;     // surface geometry (double)
-  gpf::DevBuf st_i, st_w;     // stencils: int2 base per point, 8 doubles weights
+  gpf::DevBuf st_i, st_w;     // stencils: base (i0, j0) per point, 8 weights
   gpf::DevBuf sinv;           // ns x ns S^-1, row-major, FP64
   gpf::DevBuf f0, fhat0;      // ns each
 };
 
-namespace gpf {
-
-// ---------------------------------------------------------------------------
-// kernel launchers (all asynchronous on `stream`)
-// ---------------------------------------------------------------------------
-struct GridGeom {
-  int n;
-  double dx, x0, y0;
+struct gpf_batch {
+  gpf_ctx *ctx = nullptr;
+  int max_problems = 0;
+  std::vector<gpf_workspace *> ws;
+  gpf::DescRing ring;
+  ~gpf_batch();
 };
-
-// fields
-hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
-template <class T>
-hipError_t launch_scatter_vortices(const GridGeom &g, int nv, const double *x,
-                                   const double *y, const double *gam, T *w,
-                                   double *partials, double *gamma_out,
-                                   unsigned *counter, unsigned *status,
-                                   hipStream_t s);
-int scatter_vortex_blocks(int nv);
-
-// convolution: s = conv(w) - c * (*gamma_src); Tin = type of w, T = compute/out type
-template <class Tin, class T>
-hipError_t launch_convolve(int n, const Tin *w, void *xwork, T *s, const T *spec,
-                           const T *tw, double c, const double *gamma_src,
-                           int xcds, hipStream_t st);
-
-// surface stencils and gathers
-hipError_t launch_surface_stencils(const GridGeom &g, int ns, const double *xs,
-                                   const double *ys, int *st_i, double *st_w,
-                                   unsigned *status, hipStream_t s);
-template <class T>
-hipError_t launch_interp_surface(int n, int ns, const int *st_i,
-                                 const double *st_w, const T *field, double *r,
-                                 hipStream_t s);
-
-// Schur complement build and inversion (FP64)
-hipError_t launch_schur_build(int n, int ns, const int *st_i, const double *st_w,
-                              const double *ds, const double *lgf, double *S,
-                              hipStream_t s);
-gpf_status invert_fp64(int ns, double *A, double *Ainv, hipStream_t s, double *min_pivot_rel);
-hipError_t launch_gemv(int ns, int ncol, const double *A, const double *X,
-                       double *Y, hipStream_t s);
-
-// per-solve surface right-hand sides: rhs[:,0] = s_b' - E_s s*,
-// rhs[:,1+j] = E_s L^-1 d_j (direct LGF sums)
-struct SolveScalars {
-  double u_inf, v_inf, ub, vb, omega;
-  double gamma_b, gamma_w_in;   // gamma_w_in NaN -> use device sum
-  int mode, m;
-  int edges[GPF_MAX_EDGES];
-  double xnew[GPF_MAX_EDGES], ynew[GPF_MAX_EDGES];
-};
-template <class T>
-hipError_t launch_surface_rhs(const GridGeom &g, int ns, const double *xs,
-                              const double *ys, const int *st_i,
-                              const double *st_w, const T *sstar,
-                              const double *lgf, const SolveScalars &sv,
-                              double *rhs, unsigned *status, hipStream_t s);
-// constraint solve (one workgroup): writes f (ns), ftilde, scalars
-hipError_t launch_constraints(int ns, const double *y, const double *f0,
-                              const double *ds, double gamma0,
-                              const double *xs, const double *ys,
-                              const SolveScalars &sv, double *dev_scalars,
-                              double *f, double *ftilde, unsigned *status,
-                              hipStream_t s);
-// w += R_s f + sum_j Gamma_j d_j
-template <class T>
-hipError_t launch_scatter_sheet(const GridGeom &g, int ns, const int *st_i,
-                                const double *st_w, const double *ds,
-                                const double *f, const SolveScalars &sv,
-                                const double *dev_scalars, T *w, hipStream_t s);
-template <class T>
-hipError_t launch_vortex_velocity(const GridGeom &g, int nv, const double *x,
-                                  const double *y, const T *s, double uinf,
-                                  double vinf, double *u, double *v,
-                                  unsigned *status, hipStream_t st);
-hipError_t launch_copy_doubles(const double *dev_scalars, double *out, int count,
-                               hipStream_t s);
-
-// device scalar slots (doubles) inside plan->sc
-enum ScalarSlot {
-  SC_GAMMA_W = 0,     // circulation of the vortices (sum Gamma_q)
-  SC_GAMMA_SRC2 = 1,  // source circulation of the final convolution
-  SC_S0 = 2,
-  SC_GAMMA_B = 3,
-  SC_GAMMA_NEW = 4,   // .. 4 + GPF_MAX_EDGES
-  SC_COUNT = 4 + GPF_MAX_EDGES,
-  SC_COUNTER_OFFSET_BYTES = 256  // unsigned counter lives after the doubles
-};
-
-}  // namespace gpf

@@ -154,65 +154,72 @@ __global__ __launch_bounds__(256) void k_gemv(int ns, int ncol, const double *__
   }
 }
 
-// rhs[:,0] = s_b' - E_s s*;  rhs[:,1+j] = (E_s L^-1 d_j), direct LGF sums
+// rhs[:,0] = s_b' - E_s s*;  rhs[:,1+j] = (E_s L^-1 d_j) by direct LGF sums.
+// Blocks [0, nbe) give one thread per surface point for the first column;
+// the remaining blocks give 16 lanes per (point, new vortex) pair, one lane
+// per node of the surface stencil, each summing the 16 nodes of the vortex
+// stencil.
+constexpr int kRB = 256;
+
 template <class T>
-__global__ __launch_bounds__(128) void k_surface_rhs(GridGeom g, int ns, const double *__restrict__ xs,
-                                                     const double *__restrict__ ys,
-                                                     const int *__restrict__ st_i,
-                                                     const double *__restrict__ st_w,
-                                                     const T *__restrict__ sstar,
-                                                     const double *__restrict__ lgf, SolveScalars sv,
-                                                     double *__restrict__ rhs,
-                                                     unsigned *__restrict__ status) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ns) return;
-  const int n = g.n;
-  const int i0 = st_i[2 * p], j0 = st_i[2 * p + 1];
-  const double *ew = st_w + 8 * p;
-  double acc = 0.0;
+__global__ __launch_bounds__(kRB) void k_surface_rhs(const ProbDesc *__restrict__ d, int nbe) {
+  const ProbDesc &P = d[blockIdx.y];
+  const int ns = P.ns, n = P.n;
+  const SolveScalars &sv = P.sv;
+  if ((int)blockIdx.x < nbe) {
+    const int p = blockIdx.x * kRB + threadIdx.x;
+    if (p >= ns) return;
+    const int i0 = P.st_i[2 * p], j0 = P.st_i[2 * p + 1];
+    const double *ew = P.st_w + 8 * p;
+    const T *s1 = static_cast<const T *>(P.s1);
+    double acc = 0.0;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    double r = 0.0;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) r += ew[a] * (double)sstar[(size_t)(j0 + b) * n + i0 + a];
-    acc += ew[4 + b] * r;
-  }
-  const double x = xs[p], y = ys[p];
-  const double sb = (sv.ub - sv.u_inf) * y - (sv.vb - sv.v_inf) * x -
-                    0.5 * sv.omega * (x * x + y * y);
-  rhs[p] = sb - acc;
-  if (sv.mode != GPF_KUTTA_SHED) return;
-  const int w = n + 1;
-  for (int j = 0; j < sv.m; ++j) {
-    const double xi = (sv.xnew[j] - g.x0) / g.dx, eta = (sv.ynew[j] - g.y0) / g.dx;
-    if (!(xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0)) {
-      if (p == 0) atomicOr(status, GPF_DEV_OUT_OF_GRID);
-      rhs[(size_t)(1 + j) * ns + p] = 0.0;
-      continue;
-    }
-    const int vi = (int)floor(xi) - 1, vj = (int)floor(eta) - 1;
-    const double fx = xi - floor(xi), fy = eta - floor(eta);
-    double mx[4], my[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      mx[c] = m4p(fx + 1.0 - c);
-      my[c] = m4p(fy + 1.0 - c);
-    }
-    double tot = 0.0;
     for (int b = 0; b < 4; ++b) {
-      for (int d = 0; d < 4; ++d) {
-        const int dj = abs(j0 + b - vj - d);
-        double r = 0.0;
+      double r = 0.0;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            r += ew[a] * mx[c] * lgf[(size_t)abs(i0 + a - vi - c) * w + dj];
-        tot += ew[4 + b] * my[d] * r;
-      }
+      for (int a = 0; a < 4; ++a) r += ew[a] * (double)s1[(size_t)(j0 + b) * n + i0 + a];
+      acc += ew[4 + b] * r;
     }
-    rhs[(size_t)(1 + j) * ns + p] = tot;
+    const double x = P.xs[p], y = P.ys[p];
+    const double sb = (sv.ub - sv.u_inf) * y - (sv.vb - sv.v_inf) * x -
+                      0.5 * sv.omega * (x * x + y * y);
+    P.rhs[p] = sb - acc;
+    return;
   }
+  if (sv.mode != GPF_KUTTA_SHED) return;
+  const int m = sv.m;
+  const int pj = ((int)blockIdx.x - nbe) * (kRB / 16) + (int)threadIdx.x / 16;
+  const int lane = threadIdx.x & 15;
+  const bool active = pj < ns * m;
+  double val = 0.0;
+  int p = 0, j = 0;
+  if (active) {
+    p = pj % ns;
+    j = pj / ns;
+    const double xi = (sv.xnew[j] - P.x0) / P.dx, eta = (sv.ynew[j] - P.y0) / P.dx;
+    if (xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0) {
+      const int vi = (int)floor(xi) - 1, vj = (int)floor(eta) - 1;
+      const double fx = xi - floor(xi), fy = eta - floor(eta);
+      const int a = lane & 3, b = lane >> 2;
+      const int ia = P.st_i[2 * p] + a, jb = P.st_i[2 * p + 1] + b;
+      const int w = n + 1;
+      double r = 0.0;
+#pragma unroll
+      for (int dd = 0; dd < 4; ++dd) {
+        const int dj = abs(jb - vj - dd);
+        double rr = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rr += m4p(fx + 1.0 - c) * P.lgf[(size_t)abs(ia - vi - c) * w + dj];
+        r += m4p(fy + 1.0 - dd) * rr;
+      }
+      val = P.st_w[8 * p + a] * P.st_w[8 * p + 4 + b] * r;
+    } else if (lane == 0 && p == 0) {
+      atomicOr(P.status, GPF_DEV_OUT_OF_GRID);
+    }
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) val += __shfl_xor(val, off);
+  if (active && lane == 0) P.rhs[(size_t)(1 + j) * ns + p] = val;
 }
 
 constexpr int kCB = 256;
@@ -231,18 +238,19 @@ __device__ double block_sum(double v, double *red) {
   return r;
 }
 
-__global__ __launch_bounds__(kCB) void k_constraints(int ns, const double *__restrict__ Y,
-                                                     const double *__restrict__ f0,
-                                                     const double *__restrict__ ds, double gamma0,
-                                                     const double *__restrict__ xs,
-                                                     const double *__restrict__ ys, SolveScalars sv,
-                                                     double *__restrict__ sc, double *__restrict__ f,
-                                                     double *__restrict__ ft,
-                                                     unsigned *__restrict__ status) {
-  __shared__ double red[kCB];
-  __shared__ double gam[GPF_MAX_EDGES];
-  __shared__ double sh_s0;
+// Constraint solve of one problem by one workgroup: reads Y = S^-1 rhs,
+// writes f, f~ and the scalar slots.
+__device__ void constraints_block(const ProbDesc &P, double *red, double *gam, double *sh_s0) {
   const int tid = threadIdx.x;
+  const int ns = P.ns;
+  const SolveScalars &sv = P.sv;
+  const double *__restrict__ Y = P.y;
+  const double *__restrict__ f0 = P.f0;
+  const double *__restrict__ ds = P.ds;
+  double *__restrict__ f = P.f;
+  double *__restrict__ ft = P.ft;
+  double *sc = P.aux;
+  const double gamma0 = P.gamma0;
   const double gamma_w_dev = sc[SC_GAMMA_W];
   const int m = sv.mode == GPF_KUTTA_SHED ? sv.m : 0;
 
@@ -270,7 +278,7 @@ __global__ __launch_bounds__(kCB) void k_constraints(int ns, const double *__res
   // Kutta modes: c1 = fhat0 . s_b' / Gamma0 (circulation removal of the rhs)
   double part = 0.0;
   for (int p = tid; p < ns; p += kCB) {
-    const double x = xs[p], y = ys[p];
+    const double x = P.xs[p], y = P.ys[p];
     const double sb = (sv.ub - sv.u_inf) * y - (sv.vb - sv.v_inf) * x -
                       0.5 * sv.omega * (x * x + y * y);
     part += ds[p] * f0[p] * sb;
@@ -337,7 +345,7 @@ __global__ __launch_bounds__(kCB) void k_constraints(int ns, const double *__res
       }
     }
     for (int j = 0; j < m; ++j) gam[j] = singular ? 0.0 : A[j][m] / A[j][j];
-    if (singular) atomicOr(status, GPF_DEV_SINGULAR);
+    if (singular) atomicOr(P.status, GPF_DEV_SINGULAR);
     // s0 = mean over edges of x_k, x = f~* + sum_j Gamma_j f~_j
     double s0 = 0.0;
     for (int i = 0; i < m; ++i) {
@@ -346,10 +354,10 @@ __global__ __launch_bounds__(kCB) void k_constraints(int ns, const double *__res
       for (int j = 0; j < m; ++j) xk += gam[j] * Y[(size_t)(1 + j) * ns + k] / f0[k];
       s0 += xk;
     }
-    sh_s0 = s0 / m;
+    *sh_s0 = s0 / m;
   }
   __syncthreads();
-  const double s0 = sh_s0;
+  const double s0 = *sh_s0;
   double pb = 0.0;
   for (int p = tid; p < ns; p += kCB) {
     double x = ft[p];
@@ -371,6 +379,97 @@ __global__ __launch_bounds__(kCB) void k_constraints(int ns, const double *__res
     sc[SC_GAMMA_B] = gb;
     sc[SC_GAMMA_SRC2] = gamma_w_dev + gb + gsum;
   }
+}
+
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// Y = S^-1 [rhs columns] (one wave per row); the last workgroup of each
+// problem then solves the constraints, scatters R_s f and the new vortices
+// into the source field and copies the outputs.
+template <class T>
+__global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict__ d) {
+  __shared__ double red[kCB];
+  __shared__ double gam[GPF_MAX_EDGES];
+  __shared__ double sh_s0;
+  __shared__ bool last;
+  const ProbDesc &P = d[blockIdx.y];
+  const int ns = P.ns;
+  const int ncol = 1 + (P.sv.mode == GPF_KUTTA_SHED ? P.sv.m : 0);
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row < ns) {
+    double acc[1 + GPF_MAX_EDGES];
+#pragma unroll
+    for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c) acc[c] = 0.0;
+    const double *a = P.sinv + (size_t)row * ns;
+    for (int q = lane; q < ns; q += 64) {
+      const double aq = a[q];
+#pragma unroll
+      for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c)
+        if (c < ncol) acc[c] += aq * P.rhs[(size_t)c * ns + q];
+    }
+#pragma unroll
+    for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c) {
+      if (c < ncol) {
+        double v = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) P.y[(size_t)c * ns + row] = v;
+      }
+    }
+  }
+  __syncthreads();
+  unsigned *counter = aux_counter(P.aux, 1);
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned done = atomicAdd(counter, 1u);
+    last = (done == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  constraints_block(P, red, gam, &sh_s0);
+  __syncthreads();
+  // R_s f and the new vortices into the source field
+  T *w = static_cast<T *>(P.w);
+  const int n = P.n;
+  const double inv = 1.0 / (P.dx * P.dx);
+  for (int p = threadIdx.x; p < ns; p += kCB) {
+    const int i0 = P.st_i[2 * p], j0 = P.st_i[2 * p + 1];
+    const double amp = P.ds[p] * P.f[p] * inv;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double ab = amp * P.st_w[8 * p + 4 + b];
+      T *r = w + (size_t)(j0 + b) * n + i0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) atomic_add(r + a, (T)(ab * P.st_w[8 * p + a]));
+    }
+  }
+  if (P.sv.mode == GPF_KUTTA_SHED && (int)threadIdx.x < P.sv.m) {
+    const int j = threadIdx.x;
+    const double xi = (P.sv.xnew[j] - P.x0) / P.dx, eta = (P.sv.ynew[j] - P.y0) / P.dx;
+    if (xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0) {
+      const int i0 = (int)floor(xi) - 1, j0 = (int)floor(eta) - 1;
+      const double fx = xi - floor(xi), fy = eta - floor(eta);
+      const double amp = gam[j] * inv;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double ab = amp * m4p(fy + 1.0 - b);
+        T *r = w + (size_t)(j0 + b) * n + i0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) atomic_add(r + a, (T)(ab * m4p(fx + 1.0 - a)));
+      }
+    }
+  }
+  // outputs
+  for (int p = threadIdx.x; p < ns; p += kCB) {
+    if (P.f_out) P.f_out[p] = P.f[p];
+    if (P.ft_out) P.ft_out[p] = P.ft[p];
+  }
+  __syncthreads();
+  if (P.sc_out && (int)threadIdx.x < SC_COUNT) P.sc_out[threadIdx.x] = P.aux[threadIdx.x];
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
 }
 
 }  // namespace
@@ -417,32 +516,23 @@ hipError_t launch_gemv(int ns, int ncol, const double *A, const double *X, doubl
 }
 
 template <class T>
-hipError_t launch_surface_rhs(const GridGeom &g, int ns, const double *xs, const double *ys,
-                              const int *st_i, const double *st_w, const T *sstar,
-                              const double *lgf, const SolveScalars &sv, double *rhs,
-                              unsigned *status, hipStream_t s) {
-  hipLaunchKernelGGL((k_surface_rhs<T>), dim3((ns + 127) / 128), dim3(128), 0, s, g, ns, xs, ys,
-                     st_i, st_w, sstar, lgf, sv, rhs, status);
+hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s) {
+  const int nbe = (ns_max + kRB - 1) / kRB;
+  const int nbl = (ns_max * m_max + kRB / 16 - 1) / (kRB / 16);
+  timer_begin(GPF_TK_SURFACE, s);
+  hipLaunchKernelGGL((k_surface_rhs<T>), dim3(nbe + nbl, nb), dim3(kRB), 0, s, d, nbe);
   return hipGetLastError();
 }
-template hipError_t launch_surface_rhs<float>(const GridGeom &, int, const double *,
-                                              const double *, const int *, const double *,
-                                              const float *, const double *,
-                                              const SolveScalars &, double *, unsigned *,
-                                              hipStream_t);
-template hipError_t launch_surface_rhs<double>(const GridGeom &, int, const double *,
-                                               const double *, const int *, const double *,
-                                               const double *, const double *,
-                                               const SolveScalars &, double *, unsigned *,
-                                               hipStream_t);
+template hipError_t launch_surface_rhs<float>(const ProbDesc *, int, int, int, hipStream_t);
+template hipError_t launch_surface_rhs<double>(const ProbDesc *, int, int, int, hipStream_t);
 
-hipError_t launch_constraints(int ns, const double *y, const double *f0, const double *ds,
-                              double gamma0, const double *xs, const double *ys,
-                              const SolveScalars &sv, double *dev_scalars, double *f,
-                              double *ftilde, unsigned *status, hipStream_t s) {
-  hipLaunchKernelGGL(k_constraints, dim3(1), dim3(kCB), 0, s, ns, y, f0, ds, gamma0, xs, ys, sv,
-                     dev_scalars, f, ftilde, status);
+template <class T>
+hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, hipStream_t s) {
+  hipLaunchKernelGGL((k_schur_apply<T>), dim3((ns_max + 3) / 4, nb), dim3(kCB), 0, s, d);
+  timer_end(s);
   return hipGetLastError();
 }
+template hipError_t launch_schur_apply<float>(const ProbDesc *, int, int, hipStream_t);
+template hipError_t launch_schur_apply<double>(const ProbDesc *, int, int, hipStream_t);
 
 }  // namespace gpf

@@ -65,23 +65,22 @@ __global__ void k_fill(unsigned *p, size_t words) {
 }
 
 template <class T>
-__global__ __launch_bounds__(kScatterBlock) void k_scatter_vortices(
-    GridGeom g, int nv, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ gam, T *__restrict__ w, double *__restrict__ partials,
-    double *__restrict__ gamma_out, unsigned *__restrict__ counter,
-    unsigned *__restrict__ status) {
+__global__ __launch_bounds__(kScatterBlock) void k_scatter_vortices(const ProbDesc *__restrict__ d) {
   __shared__ double red[kScatterBlock];
   __shared__ bool last;
+  const ProbDesc &P = d[blockIdx.y];
+  T *__restrict__ w = static_cast<T *>(P.w);
+  const int n = P.n;
   const int q = blockIdx.x * kScatterBlock + threadIdx.x;
   double gq = 0.0;
-  if (q < nv) {
+  if (q < P.nv) {
     int i0, j0;
     double fx, fy;
-    const bool okx = cell(x[q], g.x0, g.dx, 2, g.n - 3, &i0, &fx);
-    const bool oky = cell(y[q], g.y0, g.dx, 2, g.n - 3, &j0, &fy);
+    const bool okx = cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx);
+    const bool oky = cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy);
     if (okx && oky) {
-      gq = gam[q];
-      const double amp = gq / (g.dx * g.dx);
+      gq = P.gv[q];
+      const double amp = gq / (P.dx * P.dx);
       double wx[4], wy[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
@@ -90,25 +89,26 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_vortices(
       }
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        T *row = w + (size_t)(j0 + b) * g.n + i0;
+        T *row = w + (size_t)(j0 + b) * n + i0;
         const double ab = amp * wy[b];
 #pragma unroll
         for (int a = 0; a < 4; ++a) atomic_add(row + a, (T)(ab * wx[a]));
       }
     } else {
-      atomicOr(status, GPF_DEV_OUT_OF_GRID);
+      atomicOr(P.status, GPF_DEV_OUT_OF_GRID);
     }
   }
-  // deterministic circulation: block partials, summed in order by the
-  // last block to finish
+  // deterministic circulation: block partials, summed in order by the last
+  // block of this problem to finish
   red[threadIdx.x] = gq;
   __syncthreads();
   for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
+  unsigned *counter = aux_counter(P.aux, 0);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = red[0];
+    P.partials[blockIdx.x] = red[0];
     __threadfence();
     const unsigned done = atomicAdd(counter, 1u);
     last = (done == gridDim.x - 1);
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_vortices(
     __threadfence();
     double acc = 0.0;
     for (int b = threadIdx.x; b < (int)gridDim.x; b += kScatterBlock)
-      acc += __hip_atomic_load(partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      acc += __hip_atomic_load(P.partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
@@ -126,21 +126,23 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_vortices(
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      gamma_out[0] = red[0];
+      P.aux[SC_GAMMA_W] = red[0];
+      if (P.sc_out) P.sc_out[SC_GAMMA_W] = red[0];
       atomicExch(counter, 0u);
     }
   }
 }
 
-__global__ void k_surface_stencils(GridGeom g, int ns, const double *__restrict__ xs,
-                                   const double *__restrict__ ys, int *__restrict__ st_i,
-                                   double *__restrict__ st_w, unsigned *__restrict__ status) {
+__global__ void k_surface_stencils(int n, double dx, double x0, double y0, int ns,
+                                   const double *__restrict__ xs, const double *__restrict__ ys,
+                                   int *__restrict__ st_i, double *__restrict__ st_w,
+                                   unsigned *__restrict__ status) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ns) return;
   int i0, j0;
   double fx, fy;
-  const bool okx = cell(xs[p], g.x0, g.dx, 1, g.n - 2, &i0, &fx);
-  const bool oky = cell(ys[p], g.y0, g.dx, 1, g.n - 2, &j0, &fy);
+  const bool okx = cell(xs[p], x0, dx, 1, n - 2, &i0, &fx);
+  const bool oky = cell(ys[p], y0, dx, 1, n - 2, &j0, &fy);
   if (!(okx && oky)) {
     atomicOr(status, GPF_DEV_OUT_OF_GRID);
     i0 = j0 = 1;
@@ -174,61 +176,22 @@ __global__ void k_interp_surface(int n, int ns, const int *__restrict__ st_i,
   r[p] = acc;
 }
 
-template <class T>
-__global__ void k_scatter_sheet(GridGeom g, int ns, const int *__restrict__ st_i,
-                                const double *__restrict__ st_w, const double *__restrict__ ds,
-                                const double *__restrict__ f, SolveScalars sv,
-                                const double *__restrict__ sc, T *__restrict__ w) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const double inv = 1.0 / (g.dx * g.dx);
-  if (p < ns) {
-    const int i0 = st_i[2 * p], j0 = st_i[2 * p + 1];
-    const double amp = ds[p] * f[p] * inv;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const double ab = amp * st_w[8 * p + 4 + b];
-      T *row = w + (size_t)(j0 + b) * g.n + i0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) atomic_add(row + a, (T)(ab * st_w[8 * p + a]));
-    }
-  } else if (p < ns + sv.m && sv.mode == GPF_KUTTA_SHED) {
-    const int j = p - ns;
-    int i0, j0;
-    double fx, fy;
-    if (cell(sv.xnew[j], g.x0, g.dx, 2, g.n - 3, &i0, &fx) &&
-        cell(sv.ynew[j], g.y0, g.dx, 2, g.n - 3, &j0, &fy)) {
-      const double amp = sc[SC_GAMMA_NEW + j] * inv;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const double ab = amp * m4p(fy + 1.0 - b);
-        T *row = w + (size_t)(j0 + b) * g.n + i0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) atomic_add(row + a, (T)(ab * m4p(fx + 1.0 - a)));
-      }
-    }
-  }
-}
-
 // velocity at the vortices: u = (s[j+1] - s[j-1]) / 2dx, v = -(s[i+1] - s[i-1]) / 2dx
 // at the 4 x 4 stencil nodes, interpolated with M4' weights, plus the
 // uniform flow.
 template <class T>
-__global__ __launch_bounds__(256) void k_vortex_velocity(GridGeom g, int nv,
-                                                         const double *__restrict__ x,
-                                                         const double *__restrict__ y,
-                                                         const T *__restrict__ s, double uinf,
-                                                         double vinf, double *__restrict__ u,
-                                                         double *__restrict__ v,
-                                                         unsigned *__restrict__ status) {
+__global__ __launch_bounds__(256) void k_vortex_velocity(const ProbDesc *__restrict__ d) {
+  const ProbDesc &P = d[blockIdx.y];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nv) return;
+  if (q >= P.nv || P.u == nullptr) return;
+  const int n = P.n;
   int i0, j0;
   double fx, fy;
-  if (!(cell(x[q], g.x0, g.dx, 2, g.n - 3, &i0, &fx) &&
-        cell(y[q], g.y0, g.dx, 2, g.n - 3, &j0, &fy))) {
-    atomicOr(status, GPF_DEV_OUT_OF_GRID);
-    u[q] = NAN;
-    v[q] = NAN;
+  if (!(cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx) &&
+        cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy))) {
+    atomicOr(P.status, GPF_DEV_OUT_OF_GRID);
+    P.u[q] = NAN;
+    P.v[q] = NAN;
     return;
   }
   double wx[4], wy[4];
@@ -239,8 +202,7 @@ __global__ __launch_bounds__(256) void k_vortex_velocity(GridGeom g, int nv,
   }
   // rows j0-1 .. j0+4, columns i0-1 .. i0+4 of s
   double uacc = 0.0, vacc = 0.0;
-  const size_t n = g.n;
-  const T *base = s + (size_t)(j0 - 1) * n + (i0 - 1);
+  const T *base = static_cast<const T *>(P.psi) + (size_t)(j0 - 1) * n + (i0 - 1);
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     double ur = 0.0, vr = 0.0;
@@ -255,20 +217,14 @@ __global__ __launch_bounds__(256) void k_vortex_velocity(GridGeom g, int nv,
     uacc += wy[b] * ur;
     vacc += wy[b] * vr;
   }
-  const double h = 0.5 / g.dx;
-  u[q] = uacc * h + uinf;
-  v[q] = -vacc * h + vinf;
-}
-
-__global__ void k_copy_doubles(const double *__restrict__ src, double *__restrict__ dst,
-                               int count) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
-    dst[i] = src[i];
+  const double h = 0.5 / P.dx;
+  P.u[q] = uacc * h + P.sv.u_inf;
+  P.v[q] = -vacc * h + P.sv.v_inf;
 }
 
 }  // namespace
 
-int scatter_vortex_blocks(int nv) { return nv > 0 ? (nv + kScatterBlock - 1) / kScatterBlock : 1; }
+int scatter_blocks(int nv_max) { return nv_max > 0 ? (nv_max + kScatterBlock - 1) / kScatterBlock : 1; }
 
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
@@ -279,31 +235,21 @@ hipError_t launch_fill(void *p, size_t bytes, hipStream_t s) {
 }
 
 template <class T>
-hipError_t launch_scatter_vortices(const GridGeom &g, int nv, const double *x,
-                                   const double *y, const double *gam, T *w,
-                                   double *partials, double *gamma_out, unsigned *counter,
-                                   unsigned *status, hipStream_t s) {
+hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int nv_max, hipStream_t s) {
   timer_begin(GPF_TK_SCATTER, s);
-  hipLaunchKernelGGL((k_scatter_vortices<T>), dim3(scatter_vortex_blocks(nv)),
-                     dim3(kScatterBlock), 0, s, g, nv, x, y, gam, w, partials, gamma_out,
-                     counter, status);
+  hipLaunchKernelGGL((k_scatter_vortices<T>), dim3(scatter_blocks(nv_max), nb), dim3(kScatterBlock),
+                     0, s, d);
   timer_end(s);
   return hipGetLastError();
 }
-template hipError_t launch_scatter_vortices<float>(const GridGeom &, int, const double *,
-                                                   const double *, const double *, float *,
-                                                   double *, double *, unsigned *, unsigned *,
-                                                   hipStream_t);
-template hipError_t launch_scatter_vortices<double>(const GridGeom &, int, const double *,
-                                                    const double *, const double *, double *,
-                                                    double *, double *, unsigned *,
-                                                    unsigned *, hipStream_t);
+template hipError_t launch_scatter_vortices<float>(const ProbDesc *, int, int, hipStream_t);
+template hipError_t launch_scatter_vortices<double>(const ProbDesc *, int, int, hipStream_t);
 
-hipError_t launch_surface_stencils(const GridGeom &g, int ns, const double *xs,
-                                   const double *ys, int *st_i, double *st_w,
+hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
+                                   const double *xs, const double *ys, int *st_i, double *st_w,
                                    unsigned *status, hipStream_t s) {
-  hipLaunchKernelGGL(k_surface_stencils, dim3((ns + 127) / 128), dim3(128), 0, s, g, ns, xs,
-                     ys, st_i, st_w, status);
+  hipLaunchKernelGGL(k_surface_stencils, dim3((ns + 127) / 128), dim3(128), 0, s, n, dx, x0, y0,
+                     ns, xs, ys, st_i, st_w, status);
   return hipGetLastError();
 }
 
@@ -320,47 +266,14 @@ template hipError_t launch_interp_surface<double>(int, int, const int *, const d
                                                   const double *, double *, hipStream_t);
 
 template <class T>
-hipError_t launch_scatter_sheet(const GridGeom &g, int ns, const int *st_i,
-                                const double *st_w, const double *ds, const double *f,
-                                const SolveScalars &sv, const double *dev_scalars, T *w,
-                                hipStream_t s) {
-  const int total = ns + (sv.mode == GPF_KUTTA_SHED ? sv.m : 0);
-  hipLaunchKernelGGL((k_scatter_sheet<T>), dim3((total + 127) / 128), dim3(128), 0, s, g, ns,
-                     st_i, st_w, ds, f, sv, dev_scalars, w);
+hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s) {
+  if (nv_max <= 0) return hipSuccess;
+  timer_begin(GPF_TK_VELOCITY, s);
+  hipLaunchKernelGGL((k_vortex_velocity<T>), dim3((nv_max + 255) / 256, nb), dim3(256), 0, s, d);
+  timer_end(s);
   return hipGetLastError();
 }
-template hipError_t launch_scatter_sheet<float>(const GridGeom &, int, const int *,
-                                                const double *, const double *, const double *,
-                                                const SolveScalars &, const double *, float *,
-                                                hipStream_t);
-template hipError_t launch_scatter_sheet<double>(const GridGeom &, int, const int *,
-                                                 const double *, const double *,
-                                                 const double *, const SolveScalars &,
-                                                 const double *, double *, hipStream_t);
-
-template <class T>
-hipError_t launch_vortex_velocity(const GridGeom &g, int nv, const double *x, const double *y,
-                                  const T *s, double uinf, double vinf, double *u, double *v,
-                                  unsigned *status, hipStream_t st) {
-  if (nv <= 0) return hipSuccess;
-  timer_begin(GPF_TK_VELOCITY, st);
-  hipLaunchKernelGGL((k_vortex_velocity<T>), dim3((nv + 255) / 256), dim3(256), 0, st, g, nv, x,
-                     y, s, uinf, vinf, u, v, status);
-  timer_end(st);
-  return hipGetLastError();
-}
-template hipError_t launch_vortex_velocity<float>(const GridGeom &, int, const double *,
-                                                  const double *, const float *, double, double,
-                                                  double *, double *, unsigned *, hipStream_t);
-template hipError_t launch_vortex_velocity<double>(const GridGeom &, int, const double *,
-                                                   const double *, const double *, double,
-                                                   double, double *, double *, unsigned *,
-                                                   hipStream_t);
-
-hipError_t launch_copy_doubles(const double *src, double *dst, int count, hipStream_t s) {
-  const int blocks = std::max(1, std::min((count + 255) / 256, 1024));
-  hipLaunchKernelGGL(k_copy_doubles, dim3(blocks), dim3(256), 0, s, src, dst, count);
-  return hipGetLastError();
-}
+template hipError_t launch_vortex_velocity<float>(const ProbDesc *, int, int, hipStream_t);
+template hipError_t launch_vortex_velocity<double>(const ProbDesc *, int, int, hipStream_t);
 
 }  // namespace gpf

@@ -98,6 +98,10 @@ def _load():
         "gpf_lgf_table": (I, [I, DP]),
         "gpf_timing_enable": (I, [P, I]),
         "gpf_timing_read": (I, [P, I, C.POINTER(C.c_longlong), DP]),
+        "gpf_batch_create": (I, [P, I, PP]),
+        "gpf_batch_destroy": (None, [P]),
+        "gpf_solve_batched": (I, [P, I, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
         "gpf_sync": (I, [P, P]),
         "gpf_last_error": (C.c_char_p, []),
         "gpf_version": (C.c_char_p, []),
@@ -319,6 +323,37 @@ def gpf_vortex_velocity(plan: Plan, s, X, Y, u_inf, v_inf, u, v, status=None, st
                                   _stream_ptr(stream)), "gpf_vortex_velocity")
 
 
+class Batch:
+    """Workspaces for up to max_problems problems solved in shared launches."""
+
+    def __init__(self, ctx: Context, max_problems: int):
+        h = C.c_void_p()
+        check(lib.gpf_batch_create(ctx.h, max_problems, C.byref(h)), "gpf_batch_create")
+        self.h = h
+        self.ctx = ctx
+        self.max_problems = max_problems
+
+    def solve(self, plans, bodies, inputs, outputs, stream=None):
+        k = len(plans)
+        pa = (C.c_void_p * k)(*[p.h.value for p in plans])
+        ba = (C.c_void_p * k)(*[(b.h.value if b is not None else None) for b in bodies])
+        ia = (gpf_inputs * k)(*inputs)
+        oa = (gpf_outputs * k)(*outputs)
+        check(lib.gpf_solve_batched(self.h, k, pa, ba, ia, oa, _stream_ptr(stream)),
+              "gpf_solve_batched")
+
+    def close(self):
+        if self.h:
+            lib.gpf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One plan (and optional body) with preallocated torch outputs.
 
@@ -352,14 +387,18 @@ class Solver:
         return make_inputs(X, Y, G, case.u_inf, case.v_inf, case.ub, case.vb, case.omega,
                            case.mode, case.gamma_b, case.znew, case.gamma_w)
 
-    def solve(self, inp: gpf_inputs, X, stream=None, velocities=True):
+    def outputs(self, nv: int, velocities=True) -> gpf_outputs:
         import torch
-        nv = int(X.numel()) if X is not None else 0
         if velocities and (self.u is None or self.u.numel() != nv):
             self.u = torch.empty(nv, dtype=torch.float64, device=self.dev)
             self.v = torch.empty(nv, dtype=torch.float64, device=self.dev)
-        out = make_outputs(self.psi, self.u if velocities else None, self.v if velocities else None,
-                           self.f if self.body else None, self.ftilde if self.body else None,
-                           self.scalars, self.status)
+        return make_outputs(self.psi, self.u if velocities else None,
+                            self.v if velocities else None,
+                            self.f if self.body else None, self.ftilde if self.body else None,
+                            self.scalars, self.status)
+
+    def solve(self, inp: gpf_inputs, X, stream=None, velocities=True):
+        nv = int(X.numel()) if X is not None else 0
+        out = self.outputs(nv, velocities)
         gpf_solve(self.plan, self.body, inp, out, stream)
         return out
