@@ -85,6 +85,40 @@ def cpu_baseline(case, budget_s: float = 12.0) -> dict:
                       f"thread; plan and body set up beforehand), {el:.1f} s"}
 
 
+def conv_roofline(gpf, torch, np, ctx, log, sizes=(1024, 2048), reps=20):
+    """The LGF convolution alone (three passes, FP32) on large grids: achieved
+    algorithmic GB/s (44 n^2 bytes per convolution) from HIP events."""
+    out = {}
+    for n in sizes:
+        plan = gpf.Plan(ctx, n, 2.56 / n)
+        g = torch.Generator(device="cpu").manual_seed(n)
+        w = torch.randn((n, n), generator=g, dtype=torch.float32).to("cuda")
+        s = torch.empty_like(w)
+        gam = float(w.double().sum()) * (2.56 / n) ** 2
+        for _ in range(3):
+            gpf.gpf_convolve(plan, w, s, gam)
+        torch.cuda.synchronize()
+        gpf.timing_enable(plan, True)
+        for _ in range(reps):
+            gpf.gpf_convolve(plan, w, s, gam)
+        kt = gpf.timing_read(plan)
+        gpf.timing_enable(plan, False)
+        kb = kernel_bytes(n, 0, 0, 0, False)
+        passes, tot_us = {}, 0.0
+        for name in ("rows_fwd", "cols", "rows_inv"):
+            cnt, ms = kt[name]
+            us = 1e3 * ms / cnt
+            tot_us += us
+            passes[name] = {"avg_us": round(us, 3), "GBps": round(kb[name] / (us * 1e-6) / 1e9, 1)}
+        conv_bytes = kb["rows_fwd"] + kb["cols"] + kb["rows_inv"]
+        gbps = conv_bytes / (tot_us * 1e-6) / 1e9
+        out[str(n)] = {"us": round(tot_us, 2), "bytes": conv_bytes, "GBps": round(gbps, 1),
+                       "frac_of_8TBps": round(gbps / HBM_PEAK_GBS, 4), "passes": passes}
+        log(f"[bench] convolution {n}^2: {tot_us:.1f} us, {gbps:.0f} GB/s {passes}")
+        del plan
+    return out
+
+
 def timed(run_step, K, plan, gpf, torch, np, with_events=True):
     """K steps between synchronizations; per-step events and kernel events."""
     stream = torch.cuda.current_stream()
@@ -232,6 +266,7 @@ def main() -> int:
         "kernels": {k: {"avg_us": round(v["avg_us"], 3), "GBps": round(v["GBps"], 1),
                         "launches": v["launches"]} for k, v in per_kernel.items()},
     }
+    res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         res["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)

@@ -276,6 +276,26 @@ gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns) {
   return GPF_OK;
 }
 
+gpf_status gpf_workspace::ensure_vortices(int nvv) {
+  if (n > 0) {
+    const size_t tiles = (size_t)bin_tiles(n) + 1;
+    if (bin_cnt.bytes < tiles * sizeof(int)) {
+      GPF_TRY(bin_cnt.alloc(tiles * sizeof(int)));
+      GPF_HIP(hipMemset(bin_cnt.p, 0, bin_cnt.bytes));  // counts start (and end) at zero
+    }
+    GPF_TRY(bin_start.alloc(tiles * sizeof(int)));
+    GPF_TRY(cell_start.alloc(((size_t)n * n + 1) * sizeof(int)));
+  }
+  if (nvv > nv || !rank.p) {
+    const size_t cap = std::max<size_t>(1024, (size_t)nvv);
+    GPF_TRY(rank.alloc(cap * sizeof(int)));
+    GPF_TRY(order.alloc(cap * sizeof(int)));
+    GPF_TRY(sorted.alloc(3 * cap * sizeof(double)));
+    nv = (int)cap;
+  }
+  return GPF_OK;
+}
+
 gpf_batch::~gpf_batch() {
   for (auto *w : ws) delete w;
 }
@@ -330,6 +350,8 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   std::memset(&pd, 0, sizeof(pd));
   std::memset(&c1, 0, sizeof(c1));
   std::memset(&c2, 0, sizeof(c2));
+  c1.row_lo = c2.row_lo = 0;
+  c1.row_hi = c2.row_hi = p->grid.n - 1;
   pd.n = p->grid.n;
   pd.dx = p->grid.dx;
   pd.x0 = p->grid.x0;
@@ -342,6 +364,12 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.w = w64 ? ws->w64.p : ws->w32.p;
   pd.aux = ws->aux.as<double>();
   pd.partials = ws->part.as<double>();
+  pd.bin_cnt = ws->bin_cnt.as<int>();
+  pd.bin_start = ws->bin_start.as<int>();
+  pd.rank = ws->rank.as<int>();
+  pd.order = ws->order.as<int>();
+  pd.cell_start = ws->cell_start.as<int>();
+  pd.sorted = ws->sorted.as<double>();
   pd.status = out->d_status;
   pd.psi = out->d_psi;
   pd.u = (out->d_u && out->d_v) ? out->d_u : nullptr;
@@ -368,12 +396,12 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   c1.c = p->gauge_c;
   c1.gamma = pd.aux + SC_GAMMA_W;
   if (!cfg.body) {
-    // one convolution; it is the last reader of the source
+    // one convolution
     c1.X = x2;
     c1.out = out->d_psi;
     c1.spec = spec2;
     c1.tw = tw2;
-    c1.zero_in = 1;
+    c1.zero_in = 1;   // the only reader of the source: leave it zero
     pd.s1 = out->d_psi;
     c2 = c1;
     return;
@@ -401,8 +429,10 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   c1.spec = cfg.conv1_fp64 ? p->spec64.p : spec2;
   c1.tw = cfg.conv1_fp64 ? p->tw64.p : tw2;
   c1.zero_in = 0;
+  c1.row_lo = b->row_lo;   // only the surface stencils read this field
+  c1.row_hi = b->row_hi;
   pd.s1 = c1.out;
-  // final convolution of all vorticity; it leaves the source zeroed
+  // final convolution of all vorticity
   c2.in = pd.w;
   c2.X = x2;
   c2.out = out->d_psi;
@@ -410,14 +440,14 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   c2.tw = tw2;
   c2.gamma = pd.aux + SC_GAMMA_SRC2;
   c2.c = p->gauge_c;
-  c2.zero_in = 1;
+  c2.zero_in = 1;   // the last reader of the source: leave it zero
 }
 
 template <class TW, class T1, class T2>
 gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const ConvDesc *c1,
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, int xcds,
                         hipStream_t s) {
-  GPF_HIP(launch_scatter_vortices<TW>(pd, nb, nv_max, s));
+  GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
   GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, s)));
   if (cfg.body) {
     GPF_HIP(launch_surface_rhs<T1>(pd, nb, ns_max, m_max, s));
@@ -587,6 +617,13 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   b->plan = plan;
   b->ns = ns;
   b->nedge = nedge;
+  b->row_lo = g.n;
+  b->row_hi = -1;
+  for (int p = 0; p < ns; ++p) {
+    const int j0 = (int)std::floor((h_ys[p] - g.y0) / g.dx) - 1;  // lowest stencil row
+    b->row_lo = std::min(b->row_lo, j0);
+    b->row_hi = std::max(b->row_hi, j0 + 3);
+  }
   for (int e = 0; e < nedge; ++e) b->edges[e] = h_edges[e];
   const size_t vb = ns * sizeof(double);
   GPF_TRY(b->xs.alloc(vb));
@@ -688,6 +725,7 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   hipStream_t s = as_stream(hip_stream);
   TimerScope scope(plan->timing ? &plan->timer : nullptr);
   const int n = plan->grid.n;
+  GPF_TRY(plan->ws.ensure_vortices(nv));
   if (!accumulate) GPF_HIP(launch_fill(d_w, (size_t)n * n * (plan->fp64 ? 8 : 4), s));
   ProbDesc pd = single_problem(plan);
   pd.nv = nv;
@@ -697,13 +735,19 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   pd.w = d_w;
   pd.aux = plan->ws.aux.as<double>();
   pd.partials = plan->ws.part.as<double>();
+  pd.bin_cnt = plan->ws.bin_cnt.as<int>();
+  pd.bin_start = plan->ws.bin_start.as<int>();
+  pd.rank = plan->ws.rank.as<int>();
+  pd.order = plan->ws.order.as<int>();
+  pd.cell_start = plan->ws.cell_start.as<int>();
+  pd.sorted = plan->ws.sorted.as<double>();
   if (d_status) pd.status = d_status;
   void *dev = nullptr;
   GPF_TRY(plan->ring.push(&pd, sizeof(pd), s, &dev));
   if (plan->fp64)
-    GPF_HIP(launch_scatter_vortices<double>(static_cast<ProbDesc *>(dev), 1, nv, s));
+    GPF_HIP(launch_scatter_vortices<double>(static_cast<ProbDesc *>(dev), 1, n, nv, s));
   else
-    GPF_HIP(launch_scatter_vortices<float>(static_cast<ProbDesc *>(dev), 1, nv, s));
+    GPF_HIP(launch_scatter_vortices<float>(static_cast<ProbDesc *>(dev), 1, n, nv, s));
   return GPF_OK;
 }
 
@@ -724,6 +768,8 @@ gpf_status gpf_convolve(gpf_plan *plan, const void *d_w, void *d_s, double gamma
   cd.gamma_val = gamma_src;
   cd.c = plan->gauge_c;
   cd.zero_in = 0;
+  cd.row_lo = 0;
+  cd.row_hi = plan->grid.n - 1;
   void *dev = nullptr;
   GPF_TRY(plan->ring.push(&cd, sizeof(cd), s, &dev));
   const int n = plan->grid.n;
@@ -788,6 +834,7 @@ gpf_status gpf_solve(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
   if (e != hipSuccess) return fail(GPF_E_DEVICE, hipGetErrorString(e));
   hipStream_t s = as_stream(hip_stream);
   TimerScope scope(plan->timing ? &plan->timer : nullptr);
+  GPF_TRY(plan->ws.ensure_vortices(in->nv));
   ProblemRef r{plan, in->mode == GPF_NOBODY ? nullptr : body, in, out, &plan->ws};
   const GroupCfg cfg = config_of(r);
   std::vector<ProblemRef> one{r};
@@ -833,6 +880,7 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
     const GroupCfg cfg = config_of(r);
     const bool w64 = cfg.fp64_plan || cfg.conv1_fp64;
     GPF_TRY(r.ws->ensure(cfg.n, !cfg.fp64_plan, w64, r.body ? r.body->ns : 0));
+    GPF_TRY(r.ws->ensure_vortices(inputs[i].nv));
     refs.push_back(r);
   }
   if (nprob == 0) return GPF_OK;

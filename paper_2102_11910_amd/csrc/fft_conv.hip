@@ -123,29 +123,48 @@ template <int N> __host__ __device__ constexpr int num_stages() {
   return s;
 }
 
-// One Stockham stage on the sequence in `lds` (natural order before the
-// first stage, natural order after the last).
-template <class T, int N, int R, int NS, bool INV, bool ZERO_UPPER, bool LOWER_OUT>
-__device__ __forceinline__ void fft_stage(typename CT<T>::V *lds,
+// One Stockham stage.  Lane `lane` of the group owning a sequence handles
+// butterflies bf = lane + b * TPS (b < 16/R), each reading elements
+// bf + r * N/R and writing base + r * NS.  With IN_REGS the stage reads its
+// 16 values from x[] instead of LDS, where x[k] holds element lane + k * TPS
+// (the stage-0 layout, radix 16).  With OUT_REGS the results stay in x[],
+// again as x[k] = element lane + k * TPS: in the last stage the butterfly
+// b, output r lands at lane + TPS * (b + r * 16/R).
+template <class T, int N, int R, int NS, bool INV, bool ZERO_UPPER, bool LOWER_OUT, bool IN_REGS,
+          bool OUT_REGS>
+__device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
                                           const typename CT<T>::V *tw, int lane) {
   using V = typename CT<T>::V;
   constexpr int TPS = N / kE;
   constexpr int NB = kE / R;   // butterflies per lane
+  static_assert(!IN_REGS || R == kE, "register input needs a radix-16 first stage");
   V v[NB][R];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int bf = lane + b * TPS;
+  if (IN_REGS) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (ZERO_UPPER && r >= R / 2) {
-        v[b][r].x = (T)0;
-        v[b][r].y = (T)0;
+        v[0][r].x = (T)0;
+        v[0][r].y = (T)0;
       } else {
-        v[b][r] = lds[pad(bf + r * (N / R))];
+        v[0][r] = x[r];
       }
     }
+  } else {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int bf = lane + b * TPS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (ZERO_UPPER && r >= R / 2) {
+          v[b][r].x = (T)0;
+          v[b][r].y = (T)0;
+        } else {
+          v[b][r] = lds[pad(bf + r * (N / R))];
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int bf = lane + b * TPS;
@@ -159,33 +178,40 @@ __device__ __forceinline__ void fft_stage(typename CT<T>::V *lds,
       }
     }
     dft_reg<R, INV>(v[b]);
-    const int base = (bf / NS) * NS * R + j;
+    if (OUT_REGS) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (LOWER_OUT && r >= R / 2) continue;
-      lds[pad(base + r * NS)] = v[b][r];
+      for (int r = 0; r < R; ++r) x[b + r * NB] = v[b][r];
+    } else {
+      const int base = (bf / NS) * NS * R + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (LOWER_OUT && r >= R / 2) continue;
+        lds[pad(base + r * NS)] = v[b][r];
+      }
     }
   }
-  __syncthreads();
+  if (!OUT_REGS) __syncthreads();
 }
 
-template <class T, int N, int S, int NS, bool INV, bool ZIN, bool LOUT>
-__device__ __forceinline__ void fft_stages(typename CT<T>::V *lds,
+template <class T, int N, int S, int NS, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS>
+__device__ __forceinline__ void fft_stages(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
                                            const typename CT<T>::V *tw, int lane) {
   constexpr int NST = num_stages<N>();
   if constexpr (S < NST) {
     constexpr int R = stage_radix<N>(S);
-    fft_stage<T, N, R, NS, INV, ZIN && S == 0, LOUT && S == NST - 1>(lds, tw, lane);
-    fft_stages<T, N, S + 1, NS * R, INV, ZIN, LOUT>(lds, tw, lane);
+    fft_stage<T, N, R, NS, INV, ZIN && S == 0, LOUT && S == NST - 1, IN_REGS && S == 0,
+              OUT_REGS && S == NST - 1>(x, lds, tw, lane);
+    fft_stages<T, N, S + 1, NS * R, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, tw, lane);
   }
 }
 
-// Full length-N transform of the sequence in lds; all threads of the block
-// must call it (it synchronizes the block).
-template <class T, int N, bool INV, bool ZIN, bool LOUT>
-__device__ __forceinline__ void fft_seq(typename CT<T>::V *lds,
+// Length-N transform of one sequence; all threads of the block must call it
+// (it synchronizes the block).  IN_REGS / OUT_REGS: input / output in x[]
+// (x[k] = element lane + k * N/16), otherwise in natural order in lds.
+template <class T, int N, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS>
+__device__ __forceinline__ void fft_seq(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
                                         const typename CT<T>::V *tw, int lane) {
-  fft_stages<T, N, 0, 1, INV, ZIN, LOUT>(lds, tw, lane);
+  fft_stages<T, N, 0, 1, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, tw, lane);
 }
 
 // logical block index: consecutive logical blocks on one XCD (blocks are
@@ -214,22 +240,22 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const ConvDesc *__res
   const int tid = threadIdx.x;
   const int j0 = xcd_block(xcds) * 2 * P::SEQ;
 
-  for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
-    const int q = idx / n, t = idx % n;
+  const int q = tid / P::TPS, lane = tid % P::TPS;
+  V x[kE];
+  {
+    // elements lane + k * TPS of the packed row pair; k >= 8 is the zero half
     const size_t row = (size_t)(j0 + 2 * q) * n;
-    V z;
-    z.x = (T)w[row + t];
-    z.y = (T)w[row + n + t];
-    lds[q * P::LDS_SEQ + pad(t)] = z;
+#pragma unroll
+    for (int k = 0; k < kE / 2; ++k) {
+      x[k].x = (T)w[row + lane + k * P::TPS];
+      x[k].y = (T)w[row + n + lane + k * P::TPS];
+    }
   }
-  __syncthreads();
   if (C.zero_in) {
-    // this pass is the last reader of the source (all of its rows are in
-    // LDS now): leave it zero for the next accumulation
+    __syncthreads();
     for (int idx = tid; idx < 2 * P::SEQ * n; idx += P::WGT) w[(size_t)j0 * n + idx] = (Tin)0;
   }
-  const int q = tid / P::TPS, lane = tid % P::TPS;
-  fft_seq<T, N, false, true, false>(lds + q * P::LDS_SEQ, tw, lane);
+  fft_seq<T, N, false, true, false, true, false>(x, lds + q * P::LDS_SEQ, tw, lane);
 
   // unpack: A = (Z[k] + conj Z[N-k]) / 2, B = (Z[k] - conj Z[N-k]) / (2i)
   constexpr int RW = 2 * P::SEQ;
@@ -266,33 +292,28 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * P::SEQ;
 
-  for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
-    const int q = idx / n, t = idx % n;
-    const int k1 = c0 + q;
-    if (k1 <= n) lds[q * P::LDS_SEQ + pad(t)] = X[(size_t)k1 * n + t];
-  }
-  __syncthreads();
   const int q = tid / P::TPS, lane = tid % P::TPS;
+  const int k1 = min(c0 + q, n);   // blocks past the last column redo it and store nothing
+  V *col = X + (size_t)k1 * n;
+  V x[kE];
+#pragma unroll
+  for (int k = 0; k < kE / 2; ++k) x[k] = col[lane + k * P::TPS];
   V *L = lds + q * P::LDS_SEQ;
-  fft_seq<T, N, false, true, false>(L, tw, lane);
+  fft_seq<T, N, false, true, false, true, true>(x, L, tw, lane);
   {
-    const int k1 = min(c0 + q, n);
     const T *sp = spec + (size_t)k1 * (n + 1);
-    for (int k2 = lane; k2 < N; k2 += P::TPS) {
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int k2 = lane + k * P::TPS;
       const T g = sp[k2 <= n ? k2 : N - k2];
-      V z = L[pad(k2)];
-      z.x *= g;
-      z.y *= g;
-      L[pad(k2)] = z;
+      x[k].x *= g;
+      x[k].y *= g;
     }
   }
-  __syncthreads();
-  fft_seq<T, N, true, false, true>(L, tw, lane);
-
-  for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
-    const int qq = idx / n, t = idx % n;
-    const int k1 = c0 + qq;
-    if (k1 <= n) X[(size_t)k1 * n + t] = lds[qq * P::LDS_SEQ + pad(t)];
+  fft_seq<T, N, true, false, true, true, true>(x, L, tw, lane);
+  if (c0 + q <= n) {
+#pragma unroll
+    for (int k = 0; k < kE / 2; ++k) col[lane + k * P::TPS] = x[k];
   }
 }
 
@@ -313,6 +334,7 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const ConvDesc *__res
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
   const int j0 = xcd_block(xcds) * 2 * P::SEQ;
+  if (j0 + 2 * P::SEQ <= C.row_lo || j0 > C.row_hi) return;  // rows nobody reads
 
   // Z[k] = A[k] + i B[k], Z[N-k] = conj(A[k]) + i conj(B[k]); the imaginary
   // parts of A and B at k = 0 and k = n are dropped (real rows).
@@ -336,15 +358,14 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const ConvDesc *__res
   }
   __syncthreads();
   const int q = tid / P::TPS, lane = tid % P::TPS;
-  fft_seq<T, N, true, false, true>(lds + q * P::LDS_SEQ, tw, lane);
-
+  V x[kE];
+  fft_seq<T, N, true, false, true, false, true>(x, lds + q * P::LDS_SEQ, tw, lane);
   const T shift = (T)(C.c * (C.gamma ? C.gamma[0] : C.gamma_val));
-  for (int idx = tid; idx < P::SEQ * n; idx += P::WGT) {
-    const int qq = idx / n, t = idx % n;
-    const V z = lds[qq * P::LDS_SEQ + pad(t)];
-    const size_t row = (size_t)(j0 + 2 * qq) * n;
-    s[row + t] = z.x - shift;
-    s[row + n + t] = z.y - shift;
+  const size_t row = (size_t)(j0 + 2 * q) * n;
+#pragma unroll
+  for (int k = 0; k < kE / 2; ++k) {
+    s[row + lane + k * P::TPS] = x[k].x - shift;
+    s[row + n + lane + k * P::TPS] = x[k].y - shift;
   }
 }
 

@@ -140,6 +140,7 @@ struct ConvDesc {
   double gamma_val;
   double c;            // gauge shift of the spectrum
   int zero_in;
+  int row_lo, row_hi;  // rows of `out` that are needed (inclusive)
 };
 
 struct ProbDesc {
@@ -157,6 +158,11 @@ struct ProbDesc {
   double *aux;
   double *partials;
   unsigned *status;
+  // vortex binning by tiles of cells: counts, starts, ranks, order; then
+  // by cell within each tile: cell starts (tile-major cell order) and the
+  // vortex data (xi, eta, Gamma/dx^2) in that order
+  int *bin_cnt, *bin_start, *rank, *order, *cell_start;
+  double *sorted;
   // body
   int ns;
   const double *xs, *ys, *ds, *sinv, *f0;
@@ -178,8 +184,12 @@ __host__ __device__ inline unsigned *aux_counter(double *aux, int k) {
 // kernel launchers (asynchronous on `s`; `nb` problems, same n)
 // ---------------------------------------------------------------------------
 int scatter_blocks(int nv_max);
+int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n < 32)
+// R_v: bin the vortices by tile, then one workgroup per tile accumulates
+// its vortices in LDS and adds the window to the source field (which must
+// hold zeros, or the values to add to)
 template <class T>
-hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
+hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s);
 template <class Tin, class T>
 hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, hipStream_t s);
 template <class T>
@@ -217,9 +227,11 @@ struct gpf_ctx {
 // Workspace of one problem slot: source fields, intermediates, first
 // convolution output, aux block and Schur vectors.
 struct gpf_workspace {
-  int n = 0, ns = 0;
+  int n = 0, ns = 0, nv = 0;
   gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y, f, ft;
+  gpf::DevBuf bin_cnt, bin_start, rank, order, cell_start, sorted;
   gpf_status ensure(int n, bool need32, bool need64, int ns);
+  gpf_status ensure_vortices(int nv);
 };
 
 struct gpf_plan {
@@ -247,6 +259,7 @@ struct gpf_body {
   double gamma0 = 0.0;
   double amp = 0.0;
   bool conv1_fp64 = false;
+  int row_lo = 0, row_hi = 0; // grid rows read by the surface stencils
   gpf::DevBuf xs, ys, ds;     // surface geometry (double)
   gpf::DevBuf st_i, st_w;     // stencils: base (i0, j0) per point, 8 weights
   gpf::DevBuf sinv;           // ns x ns S^-1, row-major, FP64

@@ -224,29 +224,37 @@ __global__ __launch_bounds__(kRB) void k_surface_rhs(const ProbDesc *__restrict_
 
 constexpr int kCB = 256;
 
+// sum over the workgroup (kCB = 4 waves): wave shuffles, then the four
+// wave totals through LDS; every thread gets the result
 __device__ double block_sum(double v, double *red) {
-  const int tid = threadIdx.x;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();  // red[] may still be read by the previous call
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
   __syncthreads();
-  red[tid] = v;
-  __syncthreads();
-  for (int s = kCB / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
+  return red[0] + red[1] + red[2] + red[3];
 }
 
 // Constraint solve of one problem by one workgroup: reads Y = S^-1 rhs,
 // writes f, f~ and the scalar slots.
-__device__ void constraints_block(const ProbDesc &P, double *red, double *gam, double *sh_s0) {
+struct ConstraintScratch {
+  double red[kCB];
+  double gam[GPF_MAX_EDGES];
+  double dj[GPF_MAX_EDGES];
+  double A[GPF_MAX_EDGES][GPF_MAX_EDGES + 1];
+  double s0;
+};
+
+__device__ void constraints_block(const ProbDesc &P, const double *__restrict__ Y,
+                                  const double *__restrict__ f0, const double *__restrict__ ds,
+                                  ConstraintScratch &cs) {
+  double *red = cs.red;
+  double *gam = cs.gam;
+  double *dj = cs.dj;
   const int tid = threadIdx.x;
   const int ns = P.ns;
   const SolveScalars &sv = P.sv;
-  const double *__restrict__ Y = P.y;
-  const double *__restrict__ f0 = P.f0;
-  const double *__restrict__ ds = P.ds;
   double *__restrict__ f = P.f;
   double *__restrict__ ft = P.ft;
   double *sc = P.aux;
@@ -313,14 +321,14 @@ __device__ void constraints_block(const ProbDesc &P, double *red, double *gam, d
   double dstar = 0.0;
   for (int p = tid; p < ns; p += kCB) dstar += ds[p] * f0[p] * ft[p];
   dstar = block_sum(dstar, red);
-  double dj[GPF_MAX_EDGES];
   for (int j = 0; j < m; ++j) {
     double pj = 0.0;
     for (int p = tid; p < ns; p += kCB) pj += ds[p] * Y[(size_t)(1 + j) * ns + p];
-    dj[j] = block_sum(pj, red);   // fhat0 . f~_j = sum dS f0 (y_j / f0)
+    const double v = block_sum(pj, red);   // fhat0 . f~_j = sum dS f0 (y_j / f0)
+    if (tid == 0) dj[j] = v;
   }
   if (tid == 0) {
-    double A[GPF_MAX_EDGES][GPF_MAX_EDGES + 1];
+    auto &A = cs.A;
     for (int i = 0; i < m; ++i) {
       const int k = sv.edges[i];
       for (int j = 0; j < m; ++j)
@@ -354,10 +362,10 @@ __device__ void constraints_block(const ProbDesc &P, double *red, double *gam, d
       for (int j = 0; j < m; ++j) xk += gam[j] * Y[(size_t)(1 + j) * ns + k] / f0[k];
       s0 += xk;
     }
-    *sh_s0 = s0 / m;
+    cs.s0 = s0 / m;
   }
   __syncthreads();
-  const double s0 = *sh_s0;
+  const double s0 = cs.s0;
   double pb = 0.0;
   for (int p = tid; p < ns; p += kCB) {
     double x = ft[p];
@@ -387,12 +395,14 @@ __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAd
 // Y = S^-1 [rhs columns] (one wave per row); the last workgroup of each
 // problem then solves the constraints, scatters R_s f and the new vortices
 // into the source field and copies the outputs.
+constexpr int kStageDoubles = 3072;
+
 template <class T>
 __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict__ d) {
-  __shared__ double red[kCB];
-  __shared__ double gam[GPF_MAX_EDGES];
-  __shared__ double sh_s0;
+  __shared__ double stage[kStageDoubles];
+  __shared__ ConstraintScratch cs;
   __shared__ bool last;
+  double *gam = cs.gam;
   const ProbDesc &P = d[blockIdx.y];
   const int ns = P.ns;
   const int ncol = 1 + (P.sv.mode == GPF_KUTTA_SHED ? P.sv.m : 0);
@@ -429,7 +439,22 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   __syncthreads();
   if (!last) return;
   __threadfence();
-  constraints_block(P, red, gam, &sh_s0);
+  // the constraint phases read Y, f0 and dS several times: stage them in
+  // LDS once when they fit (Y was just written by other workgroups)
+  const double *Y = P.y, *f0 = P.f0, *ds = P.ds;
+  if ((size_t)ns * (ncol + 2) <= kStageDoubles) {
+    double *Ys = stage, *f0s = stage + (size_t)ncol * ns, *dss = f0s + ns;
+    for (int k = threadIdx.x; k < ncol * ns; k += kCB) Ys[k] = P.y[k];
+    for (int k = threadIdx.x; k < ns; k += kCB) {
+      f0s[k] = P.f0[k];
+      dss[k] = P.ds[k];
+    }
+    __syncthreads();
+    Y = Ys;
+    f0 = f0s;
+    ds = dss;
+  }
+  constraints_block(P, Y, f0, ds, cs);
   __syncthreads();
   // R_s f and the new vortices into the source field
   T *w = static_cast<T *>(P.w);

@@ -64,42 +64,66 @@ __global__ void k_fill(unsigned *p, size_t words) {
     p[i] = 0u;
 }
 
-template <class T>
-__global__ __launch_bounds__(kScatterBlock) void k_scatter_vortices(const ProbDesc *__restrict__ d) {
+// ---------------------------------------------------------------------------
+// R_v by tiles.  A vortex belongs to the tile of its base cell floor(xi);
+// its 4 x 4 stencil covers nodes floor(xi)-1 .. floor(xi)+2, so the nodes
+// owned by a tile receive contributions only from vortices of the tile and
+// of its 8 neighbours.  No atomic additions of weights: each tile's nodes
+// are summed by one workgroup and stored.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int tile_cells(int n) { return n <= 16 ? n : (n <= 1024 ? 16 : 32); }
+constexpr int kMaxTiles = 4096;
+
+// 1. count vortices per tile.  A block first histograms its own vortices in
+//    LDS, then adds each non-empty bin to the global count once; a vortex's
+//    rank in its tile = the block's offset for the tile + its rank in the
+//    block.  The last block of each problem sums the circulation in order
+//    and turns the counts into tile starts (clearing the counts).
+__global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__restrict__ d) {
   __shared__ double red[kScatterBlock];
+  __shared__ int hist[kMaxTiles];
+  __shared__ int part[kScatterBlock];
   __shared__ bool last;
   const ProbDesc &P = d[blockIdx.y];
-  T *__restrict__ w = static_cast<T *>(P.w);
-  const int n = P.n;
+  const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
+  for (int t = threadIdx.x; t < ntiles; t += kScatterBlock) hist[t] = 0;
+  __syncthreads();
   const int q = blockIdx.x * kScatterBlock + threadIdx.x;
   double gq = 0.0;
+  int tile = -1, lrank = 0;
   if (q < P.nv) {
     int i0, j0;
     double fx, fy;
-    const bool okx = cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx);
-    const bool oky = cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy);
-    if (okx && oky) {
+    if (cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx) &&
+        cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy)) {
       gq = P.gv[q];
-      const double amp = gq / (P.dx * P.dx);
-      double wx[4], wy[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        wx[a] = m4p(fx + 1.0 - a);
-        wy[a] = m4p(fy + 1.0 - a);
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        T *row = w + (size_t)(j0 + b) * n + i0;
-        const double ab = amp * wy[b];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) atomic_add(row + a, (T)(ab * wx[a]));
-      }
+      tile = ((j0 + 1) / ts) * tps + (i0 + 1) / ts;
+      lrank = atomicAdd(hist + tile, 1);
     } else {
       atomicOr(P.status, GPF_DEV_OUT_OF_GRID);
     }
   }
-  // deterministic circulation: block partials, summed in order by the last
-  // block of this problem to finish
+  __syncthreads();
+  {
+    // add the non-empty bins to the global counts; the atomics of one
+    // thread are independent, so issue them all before using the results
+    constexpr int kPer = kMaxTiles / kScatterBlock;
+    int ret[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int t = threadIdx.x + k * kScatterBlock;
+      const int c = t < ntiles ? hist[t] : 0;
+      ret[k] = c ? atomicAdd(P.bin_cnt + t, c) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int t = threadIdx.x + k * kScatterBlock;
+      if (t < ntiles) hist[t] = ret[k];
+    }
+  }
+  __syncthreads();
+  if (q < P.nv) P.rank[q] = tile >= 0 ? hist[tile] + lrank : -1;
   red[threadIdx.x] = gq;
   __syncthreads();
   for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
@@ -114,22 +138,117 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_vortices(const ProbDe
     last = (done == gridDim.x - 1);
   }
   __syncthreads();
-  if (last) {
-    __threadfence();
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kScatterBlock)
-      acc += __hip_atomic_load(P.partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    red[threadIdx.x] = acc;
+  if (!last) return;
+  __threadfence();
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += kScatterBlock)
+    acc += __hip_atomic_load(P.partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
-    for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    P.aux[SC_GAMMA_W] = red[0];
+    if (P.sc_out) P.sc_out[SC_GAMMA_W] = red[0];
+  }
+  // exclusive scan of the tile counts: each thread sums a contiguous run
+  // (its loads issued together), the run totals are scanned in LDS, then
+  // each run is written out
+  constexpr int kPer = kMaxTiles / kScatterBlock;
+  const int per = (ntiles + kScatterBlock - 1) / kScatterBlock;
+  const int lo = threadIdx.x * per, hi = min(lo + per, ntiles);
+  int cnts[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    cnts[k] = lo + k < hi
+                  ? __hip_atomic_load(P.bin_cnt + lo + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  : 0;
+  int run = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) run += cnts[k];
+  part[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < kScatterBlock; off <<= 1) {  // inclusive Hillis-Steele
+    const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int pos = part[threadIdx.x] - run;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (lo + k < hi) {
+      P.bin_start[lo + k] = pos;
+      P.bin_cnt[lo + k] = 0;
+      pos += cnts[k];
     }
-    if (threadIdx.x == 0) {
-      P.aux[SC_GAMMA_W] = red[0];
-      if (P.sc_out) P.sc_out[SC_GAMMA_W] = red[0];
-      atomicExch(counter, 0u);
+  }
+  if (threadIdx.x == kScatterBlock - 1) {
+    P.bin_start[ntiles] = part[kScatterBlock - 1];
+    atomicExch(counter, 0u);
+  }
+}
+
+// 2. place each vortex index at its tile's start + rank
+__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d) {
+  const ProbDesc &P = d[blockIdx.y];
+  const int q = blockIdx.x * kScatterBlock + threadIdx.x;
+  if (q >= P.nv) return;
+  const int r = P.rank[q];
+  if (r < 0) return;
+  const int n = P.n, ts = tile_cells(n), tps = n / ts;
+  int i0, j0;
+  double fx, fy;
+  cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx);
+  cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy);
+  const int t = ((j0 + 1) / ts) * tps + (i0 + 1) / ts;
+  P.order[P.bin_start[t] + r] = q;
+}
+
+// 3. one workgroup per tile: the tile's vortices add their 4 x 4 stencils
+//    into an LDS window of (ts+3)^2 nodes (nodes X0-1 .. X0+ts+1), which is
+//    then added to the field; only window nodes that received weight take a
+//    global atomic, and each node sits in at most four windows.
+constexpr int kTileBlock = 256;
+
+template <class T>
+__global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__restrict__ d) {
+  __shared__ T win[35 * 35];
+  const ProbDesc &P = d[blockIdx.y];
+  const int n = P.n, ts = tile_cells(n), tps = n / ts;
+  const int t = blockIdx.x;
+  const int b0 = P.bin_start[t], b1 = P.bin_start[t + 1];
+  if (b0 == b1) return;
+  const int X0 = (t % tps) * ts - 1, Y0 = (t / tps) * ts - 1;   // window origin
+  const int bw = ts + 3, nwin = bw * bw;
+  for (int k = threadIdx.x; k < nwin; k += kTileBlock) win[k] = (T)0;
+  __syncthreads();
+  const double inv = 1.0 / (P.dx * P.dx);
+  for (int k = b0 + threadIdx.x; k < b1; k += kTileBlock) {
+    const int q = P.order[k];
+    int i0, j0;
+    double fx, fy;
+    cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx);
+    cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy);
+    const double amp = P.gv[q] * inv;
+    double wx[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) wx[a] = m4p(fx + 1.0 - a);
+    T *row = win + (j0 - Y0) * bw + (i0 - X0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double ab = amp * m4p(fy + 1.0 - b);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) atomicAdd(row + b * bw + a, (T)(ab * wx[a]));
     }
+  }
+  __syncthreads();
+  T *w = static_cast<T *>(P.w);
+  for (int k = threadIdx.x; k < nwin; k += kTileBlock) {
+    const T v = win[k];
+    if (v != (T)0) atomic_add(w + (size_t)(Y0 + k / bw) * n + X0 + k % bw, v);
   }
 }
 
@@ -234,16 +353,23 @@ hipError_t launch_fill(void *p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+int bin_tiles(int n) {
+  const int ts = tile_cells(n);
+  return (n / ts) * (n / ts);
+}
+
 template <class T>
-hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int nv_max, hipStream_t s) {
+hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s) {
   timer_begin(GPF_TK_SCATTER, s);
-  hipLaunchKernelGGL((k_scatter_vortices<T>), dim3(scatter_blocks(nv_max), nb), dim3(kScatterBlock),
-                     0, s, d);
+  const int vb = scatter_blocks(nv_max);
+  hipLaunchKernelGGL(k_bin_count, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
+  hipLaunchKernelGGL(k_bin_place, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
+  hipLaunchKernelGGL((k_tile_scatter<T>), dim3(bin_tiles(n), nb), dim3(kTileBlock), 0, s, d);
   timer_end(s);
   return hipGetLastError();
 }
-template hipError_t launch_scatter_vortices<float>(const ProbDesc *, int, int, hipStream_t);
-template hipError_t launch_scatter_vortices<double>(const ProbDesc *, int, int, hipStream_t);
+template hipError_t launch_scatter_vortices<float>(const ProbDesc *, int, int, int, hipStream_t);
+template hipError_t launch_scatter_vortices<double>(const ProbDesc *, int, int, int, hipStream_t);
 
 hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
                                    const double *xs, const double *ys, int *st_i, double *st_w,
