@@ -52,6 +52,100 @@ def kernel_bytes(n: int, nv: int, ns: int, m: int, w_fp64: bool) -> dict:
     }
 
 
+# kernel class -> (source file, kernel-name prefixes in a profiler trace)
+KERNEL_SOURCES = {
+    "scatter": ("transfer.hip", ("k_bin_count", "k_bin_place", "k_tile_scatter")),
+    "rows_fwd": ("fft_conv.hip", ("k_rows_fwd<double, float",)),
+    "cols": ("fft_conv.hip", ("k_cols_conv<float",)),
+    "rows_inv": ("fft_conv.hip", ("k_rows_inv<float",)),
+    "rows_fwd64": ("fft_conv.hip", ("k_rows_fwd<double, double",)),
+    "cols64": ("fft_conv.hip", ("k_cols_conv<double",)),
+    "rows_inv64": ("fft_conv.hip", ("k_rows_inv<double",)),
+    "surface": ("schur.hip", ("k_surface_rhs", "k_schur_apply")),
+    "velocity": ("transfer.hip", ("k_vortex_velocity",)),
+}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "plate512_batch32_hbm_traffic.md")
+COPY_BYTES = 1 << 28   # calibration copy: 256 MiB read + 256 MiB written
+
+
+def source_hash(fname: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in (fname, "gpf_internal.h"):
+        with open(os.path.join(ROOT, "paper_2102_11910_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_rows(d: str):
+    import csv
+    import glob
+    fs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not fs:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    with open(fs[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, command: str) -> None:
+    """Writes the HBM-traffic summary from two rocprofv3 --pmc runs of
+    `bench.py --pmc-workload` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
+    Bytes are scaled by what each counter reads for the calibration copy."""
+    def per_kernel(rows, counter):
+        acc = {}
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"]
+            acc.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0)
+        return ({k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()},
+                {k: max(v) for k, v in acc.items()})
+
+    fetch, cnt, fetch_max = per_kernel(_pmc_rows(fetch_dir), "FETCH_SIZE")
+    write, _, write_max = per_kernel(_pmc_rows(write_dir), "WRITE_SIZE")
+    # the calibration copy is the largest dispatch of a copy kernel
+    copy = [k for k in fetch if "copy" in k.lower()]
+    copy_k = max(copy, key=lambda k: fetch_max[k])
+    ff, fw = fetch_max[copy_k] / COPY_BYTES, write_max.get(copy_k, COPY_BYTES) / COPY_BYTES
+    lines = ["# HBM traffic per launch, 512^2 plate workload, batch of 32 problems", "",
+             "Two rocprofv3 counter runs of the batched step (FETCH_SIZE, then WRITE_SIZE),",
+             "each scaled by the reading of the same counter for a 256 MiB device copy.", "",
+             f"command_fetch: {command.format(counter='FETCH_SIZE', out=fetch_dir)}",
+             f"command_write: {command.format(counter='WRITE_SIZE', out=write_dir)}",
+             f"copy_kernel: {copy_k}",
+             f"copy_factor_fetch: {ff:.4f}", f"copy_factor_write: {fw:.4f}", ""]
+    for cls, (src, prefixes) in KERNEL_SOURCES.items():
+        ks = [k for k in fetch if any(p in k for p in prefixes)]
+        if not ks:
+            continue
+        fb = sum(fetch[k] for k in ks) / ff
+        wb = sum(write.get(k, 0.0) for k in ks) / fw
+        lines.append(f"class {cls}: fetch_bytes={fb:.0f} write_bytes={wb:.0f} "
+                     f"source={src}@{source_hash(src)} kernels={len(ks)}")
+    lines += ["", "| kernel | dispatches | FETCH (MB, raw) | WRITE (MB, raw) |", "|---|---|---|---|"]
+    for k in sorted(fetch, key=lambda k: -fetch[k]):
+        lines.append(f"| {k[:90]} | {cnt[k]} | {fetch[k] / 1e6:.2f} | {write.get(k, 0) / 1e6:.2f} |")
+    with open(TRAFFIC_SUMMARY, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote", TRAFFIC_SUMMARY)
+
+
+def measured_traffic(cls: str):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary, or None when it is absent or the kernel source changed since."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    src, _ = KERNEL_SOURCES[cls]
+    with open(TRAFFIC_SUMMARY) as fh:
+        for line in fh:
+            if line.startswith(f"class {cls}:"):
+                kv = dict(t.split("=", 1) for t in line.split(":", 1)[1].split())
+                if kv["source"] != f"{src}@{source_hash(src)}":
+                    return None
+                return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
 def cpu_baseline(case, budget_s: float = 12.0) -> dict:
     """The FP64 oracle, single-threaded, on a bounded sample of full solves."""
     import numpy as np
@@ -119,6 +213,37 @@ def conv_roofline(gpf, torch, np, ctx, log, sizes=(1024, 2048), reps=20):
     return out
 
 
+def rk2_leg(gpf, torch, np, ctx, log, wl, steps=40):
+    """Explicit-midpoint advection of the 1024^2 ellipse workload (1e5 vortices):
+    ms per step with the step captured as one graph vs launched eagerly."""
+    case = wl.config3()
+    dt = case.extra.get("dt", 0.5 * case.dx)
+    plan = gpf.Plan(ctx, case.n, case.dx, flags=gpf.GPF_POLICY_AUTO)
+    body = gpf.Body(plan, case.surface.xs, case.surface.ys, case.surface.ds)
+    dev = torch.device("cuda", 0)
+    out = {"workload": f"{case.name}, nv={case.nv}, dt={dt}"}
+    for use_graph in (True, False):
+        X = torch.as_tensor(case.X, dtype=torch.float64).to(dev)
+        Y = torch.as_tensor(case.Y, dtype=torch.float64).to(dev)
+        G = torch.as_tensor(case.G, dtype=torch.float64).to(dev)
+        inp = gpf.make_inputs(X, Y, G, case.u_inf, case.v_inf, case.ub, case.vb, case.omega,
+                              case.mode, case.gamma_b)
+        rk = gpf.Rk2(plan, body, inp, X, Y, dt, use_graph=use_graph)
+        rk.run(3)
+        rk.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rk.run(steps)
+        rk.sync()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        out["graph_ms_per_step" if use_graph else "eager_ms_per_step"] = ms
+        log(f"[bench] rk2 {'graph' if use_graph else 'eager'}: {ms:.3f} ms/step")
+        rk.close()
+    out["steps"] = steps
+    return out
+
+
 def timed(run_step, K, plan, gpf, torch, np, with_events=True):
     """K steps between synchronizations; per-step events and kernel events."""
     stream = torch.cuda.current_stream()
@@ -148,7 +273,16 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=32, help="problems per batched step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="only a few batched steps and a 256 MiB copy, for counter runs")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the HBM-traffic summary from two counter runs")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc,
+                      command="rocprofv3 --pmc {counter} --output-format csv -d {out} -o pmc "
+                              "-- python3 bench.py --pmc-workload")
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -197,6 +331,18 @@ def main() -> int:
     def step_plain():
         gpf.gpf_solve(plan, body, ins[0], outs[0])
 
+    if args.pmc_workload:
+        for _ in range(3):
+            step_batched()
+        torch.cuda.synchronize()
+        a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] pmc workload done")
+        return 0
+
     for _ in range(args.warmup):
         step_batched()
         step_plain()
@@ -230,7 +376,8 @@ def main() -> int:
     achieved = d["GBps"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": B * kb1[dom], "avg_us": round(d["avg_us"], 3)}
+                "traffic": measured_traffic(dom), "bytes_per_launch": B * kb1[dom],
+                "avg_us": round(d["avg_us"], 3)}
     log("[bench] kernels (batched): " + json.dumps(
         {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_kernel.items()}))
 
@@ -267,6 +414,7 @@ def main() -> int:
                         "launches": v["launches"]} for k, v in per_kernel.items()},
     }
     res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
+    res["rk2"] = rk2_leg(gpf, torch, np, ctx, log, wl)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         res["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)

@@ -99,6 +99,7 @@ typedef struct gpf_ctx gpf_ctx;
 typedef struct gpf_plan gpf_plan;
 typedef struct gpf_body gpf_body;
 typedef struct gpf_batch gpf_batch;
+typedef struct gpf_rk2 gpf_rk2;
 
 typedef struct {
   int n;                   /* nodes per direction (power of two, 16..2048)      */
@@ -199,6 +200,36 @@ void gpf_batch_destroy(gpf_batch *batch);
 gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
                              const gpf_body *const *bodies, const gpf_inputs *inputs,
                              const gpf_outputs *outputs, void *hip_stream);
+
+/* ---- time stepping ------------------------------------------------------ */
+
+/* Vortex advection by the explicit midpoint rule (the paper advances the
+ * vortices with forward Euler or RK4, Sec. 2.4 and 2.6; the midpoint rule
+ * uses the same velocity evaluation):
+ *     u1 = u(x);  x* = x + dt/2 u1;  u2 = u(x*);  x <- x + dt u2,
+ * where every velocity evaluation is a full solve as in gpf_solve with the
+ * settings of `in` (mode, uniform flow, body motion, gamma_b; the shedding
+ * mode is not supported: new vortices need a release rule).  d_x, d_y (nv
+ * doubles, device) are the vortex positions, updated in place by each step;
+ * in->d_gv holds the strengths; in->d_xv, in->d_yv are ignored.  With
+ * use_graph = 1 one step is captured once into a HIP graph (two solves and
+ * two position updates) and every step replays it; the captured descriptors
+ * stay reserved until gpf_rk2_destroy.  The object owns the field, velocity,
+ * sheet and status buffers of the last stage (gpf_rk2_fields). */
+gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
+                          double *d_x, double *d_y, double dt, int use_graph,
+                          gpf_rk2 **out);
+
+/* Enqueue nsteps steps on hip_stream (asynchronous). */
+gpf_status gpf_rk2_run(gpf_rk2 *rk, int nsteps, void *hip_stream);
+
+/* Device buffers of the last stage: field s (n*n, plan field type),
+ * velocities u, v at the midpoint positions, sheet strength f (ns, NULL
+ * without a body), scalar block (as in gpf_outputs) and status word. */
+gpf_status gpf_rk2_fields(const gpf_rk2 *rk, const void **d_psi, const double **d_u,
+                          const double **d_v, const double **d_f,
+                          const double **d_scalars, unsigned int **d_status);
+void gpf_rk2_destroy(gpf_rk2 *rk);
 
 /* ---- building blocks (asynchronous on hip_stream) ---------------------- */
 

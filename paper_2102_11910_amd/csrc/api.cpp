@@ -267,9 +267,6 @@ gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns) {
   if (nns > 0) {
     const size_t cols = 1 + GPF_MAX_EDGES;
     GPF_TRY(rhs.alloc(cols * nns * sizeof(double)));
-    GPF_TRY(y.alloc(cols * nns * sizeof(double)));
-    GPF_TRY(f.alloc(nns * sizeof(double)));
-    GPF_TRY(ft.alloc(nns * sizeof(double)));
     ns = std::max(ns, nns);
   }
   n = std::max(n, nn);
@@ -284,13 +281,11 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
       GPF_HIP(hipMemset(bin_cnt.p, 0, bin_cnt.bytes));  // counts start (and end) at zero
     }
     GPF_TRY(bin_start.alloc(tiles * sizeof(int)));
-    GPF_TRY(cell_start.alloc(((size_t)n * n + 1) * sizeof(int)));
   }
   if (nvv > nv || !rank.p) {
     const size_t cap = std::max<size_t>(1024, (size_t)nvv);
     GPF_TRY(rank.alloc(cap * sizeof(int)));
     GPF_TRY(order.alloc(cap * sizeof(int)));
-    GPF_TRY(sorted.alloc(3 * cap * sizeof(double)));
     nv = (int)cap;
   }
   return GPF_OK;
@@ -368,8 +363,6 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.bin_start = ws->bin_start.as<int>();
   pd.rank = ws->rank.as<int>();
   pd.order = ws->order.as<int>();
-  pd.cell_start = ws->cell_start.as<int>();
-  pd.sorted = ws->sorted.as<double>();
   pd.status = out->d_status;
   pd.psi = out->d_psi;
   pd.u = (out->d_u && out->d_v) ? out->d_u : nullptr;
@@ -414,13 +407,14 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.ds = b->ds.as<double>();
   pd.sinv = b->sinv.as<double>();
   pd.f0 = b->f0.as<double>();
+  pd.ghat = b->ghat.as<double>();
+  pd.mom_x = b->mom_x;
+  pd.mom_y = b->mom_y;
+  pd.mom_r2 = b->mom_r2;
   pd.st_i = b->st_i.as<int>();
   pd.st_w = b->st_w.as<double>();
   pd.gamma0 = b->gamma0;
   pd.rhs = ws->rhs.as<double>();
-  pd.y = ws->y.as<double>();
-  pd.f = ws->f.as<double>();
-  pd.ft = ws->ft.as<double>();
   pd.f_out = out->d_f;
   pd.ft_out = out->d_ftilde;
   // first convolution: only its surface values are used
@@ -633,7 +627,7 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   GPF_TRY(b->st_w.alloc(8 * vb));
   GPF_TRY(b->sinv.alloc((size_t)ns * vb));
   GPF_TRY(b->f0.alloc(vb));
-  GPF_TRY(b->fhat0.alloc(vb));
+  GPF_TRY(b->ghat.alloc(vb));
   GPF_TRY(plan->ws.ensure(g.n, !plan->fp64, plan->fp64, ns));
   GPF_HIP(hipMemcpy(b->xs.p, h_xs, vb, hipMemcpyHostToDevice));
   GPF_HIP(hipMemcpy(b->ys.p, h_ys, vb, hipMemcpyHostToDevice));
@@ -671,10 +665,13 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   GPF_HIP(hipMemset(status, 0, sizeof(unsigned)));
   if (hstatus & GPF_DEV_OUT_OF_GRID) return fail(GPF_E_OUT_OF_GRID, "gpf_body_create: stencil outside grid");
   double g0 = 0.0, nr = 0.0, nf = 0.0, nrhs = 0.0, npert = 0.0;
-  std::vector<double> fh(ns);
+  double mx = 0.0, my = 0.0, mr2 = 0.0;
   for (int p = 0; p < ns; ++p) {
-    g0 += h_ds[p] * Y[p];
-    fh[p] = h_ds[p] * Y[p];
+    const double fh = h_ds[p] * Y[p];
+    g0 += fh;
+    mx += fh * h_xs[p];
+    my += fh * h_ys[p];
+    mr2 += fh * (h_xs[p] * h_xs[p] + h_ys[p] * h_ys[p]);
     nr += Y[ns + p] * Y[ns + p];
     nf += Y[2 * ns + p] * Y[2 * ns + p];
     nrhs += X[ns + p] * X[ns + p];
@@ -685,12 +682,15 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
       return fail(GPF_E_SINGULAR, "gpf_body_create: f0 has a zero or non-finite entry");
   if (!(std::fabs(g0) > 0.0) || !is_finite(g0)) return fail(GPF_E_SINGULAR, "gpf_body_create: Gamma0 is zero");
   b->gamma0 = g0;
+  b->mom_x = mx;
+  b->mom_y = my;
+  b->mom_r2 = mr2;
   b->amp = (nr > 0.0 && npert > 0.0) ? std::sqrt(nf / nr) / std::sqrt(npert / nrhs) : INFINITY;
   b->conv1_fp64 = !plan->fp64 && ((plan->flags & GPF_CONV1_FP64) ||
                                   ((plan->flags & GPF_POLICY_AUTO) && b->amp > GPF_AMP_THRESHOLD));
   if (b->conv1_fp64) GPF_TRY(plan->ensure_fp64());
   GPF_HIP(hipMemcpy(b->f0.p, Y.data(), vb, hipMemcpyHostToDevice));
-  GPF_HIP(hipMemcpy(b->fhat0.p, fh.data(), vb, hipMemcpyHostToDevice));
+  GPF_HIP(launch_gemv_t(ns, b->sinv.as<double>(), b->ds.as<double>(), b->ghat.as<double>(), s));
   GPF_HIP(hipDeviceSynchronize());
   *out = b.release();
   return GPF_OK;
@@ -739,8 +739,6 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   pd.bin_start = plan->ws.bin_start.as<int>();
   pd.rank = plan->ws.rank.as<int>();
   pd.order = plan->ws.order.as<int>();
-  pd.cell_start = plan->ws.cell_start.as<int>();
-  pd.sorted = plan->ws.sorted.as<double>();
   if (d_status) pd.status = d_status;
   void *dev = nullptr;
   GPF_TRY(plan->ring.push(&pd, sizeof(pd), s, &dev));
@@ -901,6 +899,143 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
   }
   return GPF_OK;
 }
+
+// ---------------------------------------------------------------------------
+// explicit-midpoint time stepping
+// ---------------------------------------------------------------------------
+
+gpf_rk2::~gpf_rk2() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cap) (void)hipStreamDestroy(cap);
+}
+
+namespace gpf {
+namespace {
+
+// one step: two solves and two position updates, enqueued on s
+gpf_status rk2_enqueue(gpf_rk2 *rk, hipStream_t s) {
+  gpf_plan *plan = rk->plan;
+  ProblemRef r1{plan, rk->body, &rk->in1, &rk->out1, &plan->ws};
+  ProblemRef r2{plan, rk->body, &rk->in2, &rk->out2, &plan->ws};
+  const GroupCfg cfg = config_of(r1);
+  std::vector<ProblemRef> one{r1};
+  GPF_TRY(run_group(cfg, one, plan->ring, plan->ctx->xcds, s));
+  GPF_HIP(launch_axpy2(rk->nv, rk->x, rk->y, rk->u1.as<double>(), rk->v1.as<double>(),
+                       0.5 * rk->dt, rk->xm.as<double>(), rk->ym.as<double>(), s));
+  one[0] = r2;
+  GPF_TRY(run_group(cfg, one, plan->ring, plan->ctx->xcds, s));
+  GPF_HIP(launch_axpy2(rk->nv, rk->x, rk->y, rk->u2.as<double>(), rk->v2.as<double>(), rk->dt,
+                       rk->x, rk->y, s));
+  return GPF_OK;
+}
+
+}  // namespace
+}  // namespace gpf
+
+gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in, double *d_x,
+                          double *d_y, double dt, int use_graph, gpf_rk2 **out) {
+  if (!plan || !in || !out || (in->nv > 0 && (!d_x || !d_y)) || !is_finite(dt))
+    return fail(GPF_E_INVALID, "gpf_rk2_create: bad arguments");
+  *out = nullptr;
+  if (in->mode == GPF_KUTTA_SHED)
+    return fail(GPF_E_UNSUPPORTED, "gpf_rk2_create: the shedding mode needs a vortex release rule");
+  GPF_HIP(hipSetDevice(plan->ctx->device));
+  std::unique_ptr<gpf_rk2> rk(new gpf_rk2);
+  rk->plan = plan;
+  rk->body = in->mode == GPF_NOBODY ? nullptr : body;
+  rk->x = d_x;
+  rk->y = d_y;
+  rk->dt = dt;
+  rk->nv = in->nv;
+  rk->use_graph = use_graph != 0;
+  const int n = plan->grid.n;
+  const size_t vb = std::max(1, in->nv) * sizeof(double);
+  const int ns = rk->body ? rk->body->ns : 1;
+  GPF_TRY(rk->xm.alloc(vb));
+  GPF_TRY(rk->ym.alloc(vb));
+  GPF_TRY(rk->u1.alloc(vb));
+  GPF_TRY(rk->v1.alloc(vb));
+  GPF_TRY(rk->u2.alloc(vb));
+  GPF_TRY(rk->v2.alloc(vb));
+  GPF_TRY(rk->psi.alloc((size_t)n * n * (plan->fp64 ? 8 : 4)));
+  GPF_TRY(rk->f.alloc(ns * sizeof(double)));
+  GPF_TRY(rk->ft.alloc(ns * sizeof(double)));
+  GPF_TRY(rk->sc.alloc(SC_COUNT * sizeof(double)));
+  GPF_TRY(rk->status.alloc(sizeof(unsigned)));
+  GPF_HIP(hipMemset(rk->status.p, 0, sizeof(unsigned)));
+  rk->in1 = *in;
+  rk->in1.d_xv = d_x;
+  rk->in1.d_yv = d_y;
+  rk->in2 = rk->in1;
+  rk->in2.d_xv = rk->xm.as<double>();
+  rk->in2.d_yv = rk->ym.as<double>();
+  gpf_outputs o{};
+  o.d_psi = rk->psi.p;
+  o.d_f = rk->body ? rk->f.as<double>() : nullptr;
+  o.d_ftilde = rk->body ? rk->ft.as<double>() : nullptr;
+  o.d_scalars = rk->sc.as<double>();
+  o.d_status = rk->status.as<unsigned>();
+  rk->out1 = o;
+  rk->out1.d_u = rk->u1.as<double>();
+  rk->out1.d_v = rk->v1.as<double>();
+  rk->out2 = o;
+  rk->out2.d_u = rk->u2.as<double>();
+  rk->out2.d_v = rk->v2.as<double>();
+  GPF_TRY(validate(plan, rk->body, &rk->in1, &rk->out1));
+  GPF_TRY(plan->ws.ensure_vortices(in->nv));
+  if (rk->use_graph) {
+    GPF_HIP(hipStreamCreateWithFlags(&rk->cap, hipStreamNonBlocking));
+    // capture one step; descriptors pushed while capturing stay reserved
+    GPF_HIP(hipStreamBeginCapture(rk->cap, hipStreamCaptureModeThreadLocal));
+    gpf_status st;
+    {
+      TimerScope none(nullptr);
+      st = rk2_enqueue(rk.get(), rk->cap);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(rk->cap, &g);
+    if (st != GPF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    GPF_HIP(e);
+    rk->graph = g;
+    GPF_HIP(hipGraphInstantiate(&rk->exec, rk->graph, nullptr, nullptr, 0));
+  }
+  *out = rk.release();
+  return GPF_OK;
+}
+
+gpf_status gpf_rk2_run(gpf_rk2 *rk, int nsteps, void *hip_stream) {
+  if (!rk || nsteps < 0) return fail(GPF_E_INVALID, "gpf_rk2_run: bad arguments");
+  hipStream_t s = as_stream(hip_stream);
+  GPF_HIP(hipSetDevice(rk->plan->ctx->device));
+  for (int k = 0; k < nsteps; ++k) {
+    if (rk->use_graph) {
+      GPF_HIP(hipGraphLaunch(rk->exec, s));
+    } else {
+      TimerScope scope(rk->plan->timing ? &rk->plan->timer : nullptr);
+      GPF_TRY(rk2_enqueue(rk, s));
+    }
+  }
+  return GPF_OK;
+}
+
+gpf_status gpf_rk2_fields(const gpf_rk2 *rk, const void **d_psi, const double **d_u,
+                          const double **d_v, const double **d_f, const double **d_scalars,
+                          unsigned int **d_status) {
+  if (!rk) return fail(GPF_E_INVALID, "gpf_rk2_fields: null object");
+  if (d_psi) *d_psi = rk->psi.p;
+  if (d_u) *d_u = rk->u2.as<double>();
+  if (d_v) *d_v = rk->v2.as<double>();
+  if (d_f) *d_f = rk->body ? rk->f.as<double>() : nullptr;
+  if (d_scalars) *d_scalars = rk->sc.as<double>();
+  if (d_status) *d_status = rk->status.as<unsigned>();
+  return GPF_OK;
+}
+
+void gpf_rk2_destroy(gpf_rk2 *rk) { delete rk; }
 
 gpf_status gpf_timing_enable(gpf_plan *plan, int enable) {
   if (!plan) return fail(GPF_E_INVALID, "gpf_timing_enable: null plan");

@@ -158,18 +158,17 @@ struct ProbDesc {
   double *aux;
   double *partials;
   unsigned *status;
-  // vortex binning by tiles of cells: counts, starts, ranks, order; then
-  // by cell within each tile: cell starts (tile-major cell order) and the
-  // vortex data (xi, eta, Gamma/dx^2) in that order
-  int *bin_cnt, *bin_start, *rank, *order, *cell_start;
-  double *sorted;
+  // vortex binning by tiles of cells: counts, starts, ranks, order
+  int *bin_cnt, *bin_start, *rank, *order;
   // body
   int ns;
   const double *xs, *ys, *ds, *sinv, *f0;
+  const double *ghat;           // S^-T dS: circulation of S^-1 r is ghat . r
   const int *st_i;
   const double *st_w;
   double gamma0;
-  double *rhs, *y, *f, *ft;     // Schur workspaces: ns x (1+m)
+  double mom_x, mom_y, mom_r2;  // sums of fhat0 x, fhat0 y, fhat0 (x^2 + y^2)
+  double *rhs;                  // Schur right-hand sides: ns x (1+m)
   // outputs (nullable)
   const void *psi;              // final field (velocities read it)
   double *u, *v, *f_out, *ft_out, *sc_out;
@@ -199,6 +198,10 @@ hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, hipStream_t
 template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
 
+// xo = x + a u, yo = y + a v (in place allowed)
+hipError_t launch_axpy2(int nv, const double *x, const double *y, const double *u,
+                        const double *v, double a, double *xo, double *yo, hipStream_t s);
+
 // single-problem helpers used at setup and by the building blocks
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
@@ -212,6 +215,7 @@ hipError_t launch_schur_build(int n, int ns, const int *st_i, const double *st_w
 gpf_status invert_fp64(int ns, double *A, double *Ainv, hipStream_t s, double *min_pivot_rel);
 hipError_t launch_gemv(int ns, int ncol, const double *A, const double *X, double *Y,
                        hipStream_t s);
+hipError_t launch_gemv_t(int ns, const double *A, const double *x, double *y, hipStream_t s);
 
 }  // namespace gpf
 
@@ -228,8 +232,8 @@ struct gpf_ctx {
 // convolution output, aux block and Schur vectors.
 struct gpf_workspace {
   int n = 0, ns = 0, nv = 0;
-  gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y, f, ft;
-  gpf::DevBuf bin_cnt, bin_start, rank, order, cell_start, sorted;
+  gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs;
+  gpf::DevBuf bin_cnt, bin_start, rank, order;
   gpf_status ensure(int n, bool need32, bool need64, int ns);
   gpf_status ensure_vortices(int nv);
 };
@@ -263,7 +267,9 @@ struct gpf_body {
   gpf::DevBuf xs, ys, ds;     // surface geometry (double)
   gpf::DevBuf st_i, st_w;     // stencils: base (i0, j0) per point, 8 weights
   gpf::DevBuf sinv;           // ns x ns S^-1, row-major, FP64
-  gpf::DevBuf f0, fhat0;      // ns each
+  gpf::DevBuf f0;             // S^-1 1
+  gpf::DevBuf ghat;           // S^-T dS
+  double mom_x = 0.0, mom_y = 0.0, mom_r2 = 0.0;  // moments of fhat0 = dS f0
 };
 
 struct gpf_batch {
@@ -272,4 +278,20 @@ struct gpf_batch {
   std::vector<gpf_workspace *> ws;
   gpf::DescRing ring;
   ~gpf_batch();
+};
+
+struct gpf_rk2 {
+  gpf_plan *plan = nullptr;
+  const gpf_body *body = nullptr;
+  gpf_inputs in1{}, in2{};
+  gpf_outputs out1{}, out2{};
+  double *x = nullptr, *y = nullptr;
+  double dt = 0.0;
+  int nv = 0;
+  bool use_graph = false;
+  gpf::DevBuf xm, ym, u1, v1, u2, v2, psi, f, ft, sc, status;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~gpf_rk2();
 };

@@ -154,6 +154,17 @@ __global__ __launch_bounds__(256) void k_gemv(int ns, int ncol, const double *__
   }
 }
 
+// y = A^T x, one thread per column of A (row-major, ns x ns)
+__global__ __launch_bounds__(256) void k_gemv_t(int ns, const double *__restrict__ A,
+                                                const double *__restrict__ x,
+                                                double *__restrict__ y) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ns) return;
+  double acc = 0.0;
+  for (int p = 0; p < ns; ++p) acc += x[p] * A[(size_t)p * ns + q];
+  y[q] = acc;
+}
+
 // rhs[:,0] = s_b' - E_s s*;  rhs[:,1+j] = (E_s L^-1 d_j) by direct LGF sums.
 // Blocks [0, nbe) give one thread per surface point for the first column;
 // the remaining blocks give 16 lanes per (point, new vortex) pair, one lane
@@ -222,279 +233,265 @@ __global__ __launch_bounds__(kRB) void k_surface_rhs(const ProbDesc *__restrict_
   if (active && lane == 0) P.rhs[(size_t)(1 + j) * ns + p] = val;
 }
 
-constexpr int kCB = 256;
-
-// sum over the workgroup (kCB = 4 waves): wave shuffles, then the four
-// wave totals through LDS; every thread gets the result
-__device__ double block_sum(double v, double *red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  const int wave = threadIdx.x >> 6;
-  __syncthreads();  // red[] may still be read by the previous call
-  if ((threadIdx.x & 63) == 0) red[wave] = v;
-  __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
-}
-
-// Constraint solve of one problem by one workgroup: reads Y = S^-1 rhs,
-// writes f, f~ and the scalar slots.
-struct ConstraintScratch {
-  double red[kCB];
-  double gam[GPF_MAX_EDGES];
-  double dj[GPF_MAX_EDGES];
-  double A[GPF_MAX_EDGES][GPF_MAX_EDGES + 1];
-  double s0;
-};
-
-__device__ void constraints_block(const ProbDesc &P, const double *__restrict__ Y,
-                                  const double *__restrict__ f0, const double *__restrict__ ds,
-                                  ConstraintScratch &cs) {
-  double *red = cs.red;
-  double *gam = cs.gam;
-  double *dj = cs.dj;
-  const int tid = threadIdx.x;
-  const int ns = P.ns;
-  const SolveScalars &sv = P.sv;
-  double *__restrict__ f = P.f;
-  double *__restrict__ ft = P.ft;
-  double *sc = P.aux;
-  const double gamma0 = P.gamma0;
-  const double gamma_w_dev = sc[SC_GAMMA_W];
-  const int m = sv.mode == GPF_KUTTA_SHED ? sv.m : 0;
-
-  if (sv.mode == GPF_CIRCULATION) {
-    double part = 0.0;
-    for (int p = tid; p < ns; p += kCB) part += ds[p] * Y[p];
-    const double circ = block_sum(part, red);
-    const double s0 = (circ - sv.gamma_b) / gamma0;
-    double pb = 0.0;
-    for (int p = tid; p < ns; p += kCB) {
-      const double fp = Y[p] - s0 * f0[p];
-      f[p] = fp;
-      ft[p] = fp / f0[p];
-      pb += ds[p] * fp;
-    }
-    const double gb = block_sum(pb, red);
-    if (tid == 0) {
-      sc[SC_S0] = s0;
-      sc[SC_GAMMA_B] = gb;
-      sc[SC_GAMMA_SRC2] = gamma_w_dev + gb;
-    }
-    return;
-  }
-
-  // Kutta modes: c1 = fhat0 . s_b' / Gamma0 (circulation removal of the rhs)
-  double part = 0.0;
-  for (int p = tid; p < ns; p += kCB) {
-    const double x = P.xs[p], y = P.ys[p];
-    const double sb = (sv.ub - sv.u_inf) * y - (sv.vb - sv.v_inf) * x -
-                      0.5 * sv.omega * (x * x + y * y);
-    part += ds[p] * f0[p] * sb;
-  }
-  const double c1 = block_sum(part, red) / gamma0;
-  // ft <- f~* = y0/f0 - c1
-  for (int p = tid; p < ns; p += kCB) ft[p] = Y[p] / f0[p] - c1;
-  __syncthreads();
-
-  if (sv.mode == GPF_KUTTA_STEADY) {
-    const double s0 = ft[sv.edges[0]];
-    __syncthreads();  // every thread has read f~*_k before any thread shifts it
-    double pb = 0.0;
-    for (int p = tid; p < ns; p += kCB) {
-      const double t = ft[p] - s0;
-      ft[p] = t;
-      const double fp = f0[p] * t;
-      f[p] = fp;
-      pb += ds[p] * fp;
-    }
-    const double gb = block_sum(pb, red);
-    if (tid == 0) {
-      sc[SC_S0] = s0;
-      sc[SC_GAMMA_B] = gb;
-      sc[SC_GAMMA_SRC2] = gamma_w_dev + gb;
-    }
-    return;
-  }
-
-  // shedding at m edges
-  const double gamma_w = isnan(sv.gamma_w_in) ? gamma_w_dev : sv.gamma_w_in;
-  double dstar = 0.0;
-  for (int p = tid; p < ns; p += kCB) dstar += ds[p] * f0[p] * ft[p];
-  dstar = block_sum(dstar, red);
-  for (int j = 0; j < m; ++j) {
-    double pj = 0.0;
-    for (int p = tid; p < ns; p += kCB) pj += ds[p] * Y[(size_t)(1 + j) * ns + p];
-    const double v = block_sum(pj, red);   // fhat0 . f~_j = sum dS f0 (y_j / f0)
-    if (tid == 0) dj[j] = v;
-  }
-  if (tid == 0) {
-    auto &A = cs.A;
-    for (int i = 0; i < m; ++i) {
-      const int k = sv.edges[i];
-      for (int j = 0; j < m; ++j)
-        A[i][j] = 1.0 + dj[j] - gamma0 * Y[(size_t)(1 + j) * ns + k] / f0[k];
-      A[i][m] = -(gamma_w + dstar - gamma0 * ft[k]);
-    }
-    bool singular = false;
-    double amax = 0.0;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) amax = fmax(amax, fabs(A[i][j]));
-    for (int c = 0; c < m; ++c) {
-      int pr = c;
-      for (int i = c + 1; i < m; ++i)
-        if (fabs(A[i][c]) > fabs(A[pr][c])) pr = i;
-      if (!(fabs(A[pr][c]) > 1e-13 * amax)) { singular = true; break; }
-      if (pr != c)
-        for (int j = 0; j <= m; ++j) { double t = A[c][j]; A[c][j] = A[pr][j]; A[pr][j] = t; }
-      for (int i = 0; i < m; ++i) {
-        if (i == c) continue;
-        const double fct = A[i][c] / A[c][c];
-        for (int j = c; j <= m; ++j) A[i][j] -= fct * A[c][j];
-      }
-    }
-    for (int j = 0; j < m; ++j) gam[j] = singular ? 0.0 : A[j][m] / A[j][j];
-    if (singular) atomicOr(P.status, GPF_DEV_SINGULAR);
-    // s0 = mean over edges of x_k, x = f~* + sum_j Gamma_j f~_j
-    double s0 = 0.0;
-    for (int i = 0; i < m; ++i) {
-      const int k = sv.edges[i];
-      double xk = ft[k];
-      for (int j = 0; j < m; ++j) xk += gam[j] * Y[(size_t)(1 + j) * ns + k] / f0[k];
-      s0 += xk;
-    }
-    cs.s0 = s0 / m;
-  }
-  __syncthreads();
-  const double s0 = cs.s0;
-  double pb = 0.0;
-  for (int p = tid; p < ns; p += kCB) {
-    double x = ft[p];
-    for (int j = 0; j < m; ++j) x += gam[j] * Y[(size_t)(1 + j) * ns + p] / f0[p];
-    const double t = x - s0;
-    ft[p] = t;
-    const double fp = f0[p] * t;
-    f[p] = fp;
-    pb += ds[p] * fp;
-  }
-  const double gb = block_sum(pb, red);
-  if (tid == 0) {
-    double gsum = 0.0;
-    for (int j = 0; j < m; ++j) {
-      sc[SC_GAMMA_NEW + j] = gam[j];
-      gsum += gam[j];
-    }
-    sc[SC_S0] = s0;
-    sc[SC_GAMMA_B] = gb;
-    sc[SC_GAMMA_SRC2] = gamma_w_dev + gb + gsum;
-  }
-}
-
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-// Y = S^-1 [rhs columns] (one wave per row); the last workgroup of each
-// problem then solves the constraints, scatters R_s f and the new vortices
-// into the source field and copies the outputs.
-constexpr int kStageDoubles = 3072;
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Surface solve of one batch in one launch.  Every scalar the constraint
+// modes need is a dot product with the rhs columns: the circulations
+// sum_p dS_p y_c[p] = ghat . rhs_c (ghat = S^-T dS, a body constant) and the
+// values y_c[k] at the edge points (rows k of S^-1).  Each workgroup forms
+// them itself, solves the small constraint system, then finishes its own
+// rows of f and f~: outputs and R_s f into the source field.  Workgroup 0
+// writes the scalars and adds the new vortices.  No workgroup waits for
+// another.
+constexpr int kCB = 256;                       // 4 waves
+constexpr int kRowsPerWave = 4;
+constexpr int kCRows = 4 * kRowsPerWave;       // surface rows per workgroup
+constexpr int kMaxCol = 1 + GPF_MAX_EDGES;
+constexpr int kRStage = 6144;                  // rhs doubles staged in LDS
 
 template <class T>
 __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict__ d) {
-  __shared__ double stage[kStageDoubles];
-  __shared__ ConstraintScratch cs;
-  __shared__ bool last;
-  double *gam = cs.gam;
+  __shared__ double rs[kRStage];
+  __shared__ double red[4][kMaxCol];             // per-wave parts of ghat . rhs_c
+  __shared__ double ye[GPF_MAX_EDGES][kMaxCol];  // y_c / f0 at the edge points
+  __shared__ double yr[kCRows][kMaxCol];         // y_c at this workgroup's rows
+  __shared__ double scal[3 + GPF_MAX_EDGES];     // c1, s0, Gamma_b, Gamma_j
+  __shared__ double circ[kMaxCol];               // ghat . rhs_c
+  __shared__ double A[GPF_MAX_EDGES][GPF_MAX_EDGES + 1];
   const ProbDesc &P = d[blockIdx.y];
   const int ns = P.ns;
-  const int ncol = 1 + (P.sv.mode == GPF_KUTTA_SHED ? P.sv.m : 0);
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row < ns) {
-    double acc[1 + GPF_MAX_EDGES];
+  const int row0 = blockIdx.x * kCRows;
+  if (row0 >= ns) return;
+  const SolveScalars &sv = P.sv;
+  const int mode = sv.mode;
+  const int m = mode == GPF_KUTTA_SHED ? sv.m : 0;
+  const int ncol = 1 + m;
+  const int ne = mode == GPF_KUTTA_SHED ? m : (mode == GPF_KUTTA_STEADY ? 1 : 0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  // Loads below are unconditional, with indices clamped into range, so
+  // that each wave keeps many of them in flight; sums of clamped terms
+  // are discarded.
+  const double gw_dev = P.aux[SC_GAMMA_W];
+  const double *R = P.rhs;
+  if (ncol * ns <= kRStage) {
+#pragma unroll 4
+    for (int k = tid; k < ncol * ns; k += kCB) rs[k] = P.rhs[k];
+    __syncthreads();
+    R = rs;
+  }
+  size_t coff[kMaxCol];   // column offsets, clamped to the last column
 #pragma unroll
-    for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c) acc[c] = 0.0;
-    const double *a = P.sinv + (size_t)row * ns;
+  for (int c = 0; c < kMaxCol; ++c) coff[c] = (size_t)min(c, ncol - 1) * ns;
+  // ghat . rhs_c, all columns in one sweep
+  {
+    double acc[kMaxCol];
+#pragma unroll
+    for (int c = 0; c < kMaxCol; ++c) acc[c] = 0.0;
+#pragma unroll 2
+    for (int q = tid; q < ns; q += kCB) {
+      const double g = P.ghat[q];
+#pragma unroll
+      for (int c = 0; c < kMaxCol; ++c) acc[c] += g * R[coff[c] + q];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCol; ++c) {
+      if (c < ncol) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) red[wave][c] = v;
+      }
+    }
+  }
+  // rows of S^-1 at the edge points, one wave each
+  for (int e = wave; e < ne; e += 4) {
+    const int k = sv.edges[e];
+    const double inv_f0 = 1.0 / P.f0[k];
+    const double *a = P.sinv + (size_t)k * ns;
+    double acc[kMaxCol];
+#pragma unroll
+    for (int c = 0; c < kMaxCol; ++c) acc[c] = 0.0;
+#pragma unroll 4
     for (int q = lane; q < ns; q += 64) {
       const double aq = a[q];
 #pragma unroll
-      for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c)
-        if (c < ncol) acc[c] += aq * P.rhs[(size_t)c * ns + q];
+      for (int c = 0; c < kMaxCol; ++c) acc[c] += aq * R[coff[c] + q];
     }
 #pragma unroll
-    for (int c = 0; c < 1 + GPF_MAX_EDGES; ++c) {
+    for (int c = 0; c < kMaxCol; ++c) {
       if (c < ncol) {
-        double v = acc[c];
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) ye[e][c] = v * inv_f0;
+      }
+    }
+  }
+  // this workgroup's rows: kRowsPerWave per wave, interleaved over q
+  {
+    const int r0 = row0 + wave * kRowsPerWave;
+    const int nr = min(kRowsPerWave, ns - r0);
+    double acc[kRowsPerWave][kMaxCol];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) P.y[(size_t)c * ns + row] = v;
+    for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+      for (int c = 0; c < kMaxCol; ++c) acc[r][c] = 0.0;
+    if (nr > 0) {
+      const double *arow[kRowsPerWave];
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) arow[r] = P.sinv + (size_t)min(r0 + r, ns - 1) * ns;
+#pragma unroll 2
+      for (int q = lane; q < ns; q += 64) {
+        double aq[kRowsPerWave], rq[kMaxCol];
+#pragma unroll
+        for (int r = 0; r < kRowsPerWave; ++r) aq[r] = arow[r][q];
+#pragma unroll
+        for (int c = 0; c < kMaxCol; ++c) rq[c] = R[coff[c] + q];
+#pragma unroll
+        for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+          for (int c = 0; c < kMaxCol; ++c) acc[r][c] += aq[r] * rq[c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) {
+      if (r < nr) {
+#pragma unroll
+        for (int c = 0; c < kMaxCol; ++c) {
+          if (c < ncol) {
+            const double v = wave_sum(acc[r][c]);
+            if (lane == 0) yr[wave * kRowsPerWave + r][c] = v;
+          }
+        }
       }
     }
   }
   __syncthreads();
-  unsigned *counter = aux_counter(P.aux, 1);
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned done = atomicAdd(counter, 1u);
-    last = (done == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // the constraint phases read Y, f0 and dS several times: stage them in
-  // LDS once when they fit (Y was just written by other workgroups)
-  const double *Y = P.y, *f0 = P.f0, *ds = P.ds;
-  if ((size_t)ns * (ncol + 2) <= kStageDoubles) {
-    double *Ys = stage, *f0s = stage + (size_t)ncol * ns, *dss = f0s + ns;
-    for (int k = threadIdx.x; k < ncol * ns; k += kCB) Ys[k] = P.y[k];
-    for (int k = threadIdx.x; k < ns; k += kCB) {
-      f0s[k] = P.f0[k];
-      dss[k] = P.ds[k];
+
+  // constraint scalars (one thread; every workgroup gets the same values)
+  if (tid == 0) {
+    for (int c = 0; c < ncol; ++c) circ[c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+    const double g0 = P.gamma0;
+    double c1 = 0.0, s0 = 0.0, gb = 0.0, gsum = 0.0;
+    double *gam = scal + 3;
+    for (int j = 0; j < GPF_MAX_EDGES; ++j) gam[j] = 0.0;
+    if (mode == GPF_CIRCULATION) {
+      s0 = (circ[0] - sv.gamma_b) / g0;
+      gb = circ[0] - s0 * g0;
+    } else {
+      // c1 = fhat0 . s_b' / Gamma0 through the body moments of fhat0
+      c1 = ((sv.ub - sv.u_inf) * P.mom_y - (sv.vb - sv.v_inf) * P.mom_x -
+            0.5 * sv.omega * P.mom_r2) / g0;
+      if (mode == GPF_KUTTA_STEADY) {
+        s0 = ye[0][0] - c1;
+        gb = circ[0] - (c1 + s0) * g0;
+      } else {
+        const double gamma_w = isnan(sv.gamma_w_in) ? gw_dev : sv.gamma_w_in;
+        const double dstar = circ[0] - c1 * g0;   // fhat0 . f~*
+        double amax = 0.0;
+        for (int i = 0; i < m; ++i) {
+          for (int j = 0; j < m; ++j) {
+            A[i][j] = 1.0 + circ[1 + j] - g0 * ye[i][1 + j];
+            amax = fmax(amax, fabs(A[i][j]));
+          }
+          A[i][m] = -(gamma_w + dstar - g0 * (ye[i][0] - c1));
+        }
+        bool singular = false;
+        for (int c = 0; c < m; ++c) {
+          int pr = c;
+          for (int i = c + 1; i < m; ++i)
+            if (fabs(A[i][c]) > fabs(A[pr][c])) pr = i;
+          if (!(fabs(A[pr][c]) > 1e-13 * amax)) { singular = true; break; }
+          if (pr != c)
+            for (int j = 0; j <= m; ++j) { const double t = A[c][j]; A[c][j] = A[pr][j]; A[pr][j] = t; }
+          for (int i = 0; i < m; ++i) {
+            if (i == c) continue;
+            const double fct = A[i][c] / A[c][c];
+            for (int j = c; j <= m; ++j) A[i][j] -= fct * A[c][j];
+          }
+        }
+        for (int j = 0; j < m; ++j) gam[j] = singular ? 0.0 : A[j][m] / A[j][j];
+        if (singular && blockIdx.x == 0) atomicOr(P.status, GPF_DEV_SINGULAR);
+        // s0: mean over the edges of x_k = f~*_k + sum_j Gamma_j f~_j,k
+        for (int i = 0; i < m; ++i) {
+          double xk = ye[i][0] - c1;
+          for (int j = 0; j < m; ++j) xk += gam[j] * ye[i][1 + j];
+          s0 += xk;
+        }
+        s0 /= m;
+        double gj = 0.0;
+        for (int j = 0; j < m; ++j) {
+          gj += gam[j] * circ[1 + j];
+          gsum += gam[j];
+        }
+        gb = dstar + gj - s0 * g0;
+      }
     }
-    __syncthreads();
-    Y = Ys;
-    f0 = f0s;
-    ds = dss;
+    scal[0] = c1;
+    scal[1] = s0;
+    scal[2] = gb;
+    if (blockIdx.x == 0) {
+      P.aux[SC_GAMMA_SRC2] = gw_dev + gb + gsum;
+      P.aux[SC_S0] = s0;
+      P.aux[SC_GAMMA_B] = gb;
+      for (int j = 0; j < GPF_MAX_EDGES; ++j) P.aux[SC_GAMMA_NEW + j] = gam[j];
+      if (P.sc_out) {
+        P.sc_out[SC_GAMMA_W] = gw_dev;
+        P.sc_out[SC_GAMMA_SRC2] = gw_dev + gb + gsum;
+        P.sc_out[SC_S0] = s0;
+        P.sc_out[SC_GAMMA_B] = gb;
+        for (int j = 0; j < GPF_MAX_EDGES; ++j) P.sc_out[SC_GAMMA_NEW + j] = gam[j];
+      }
+    }
   }
-  constraints_block(P, Y, f0, ds, cs);
   __syncthreads();
-  // R_s f and the new vortices into the source field
-  T *w = static_cast<T *>(P.w);
+
+  // f, f~ of the rows; 16 lanes per row add R_s f at its 16 stencil nodes
+  const double c1 = scal[0], s0 = scal[1];
   const int n = P.n;
-  const double inv = 1.0 / (P.dx * P.dx);
-  for (int p = threadIdx.x; p < ns; p += kCB) {
-    const int i0 = P.st_i[2 * p], j0 = P.st_i[2 * p + 1];
-    const double amp = P.ds[p] * P.f[p] * inv;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const double ab = amp * P.st_w[8 * p + 4 + b];
-      T *r = w + (size_t)(j0 + b) * n + i0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) atomic_add(r + a, (T)(ab * P.st_w[8 * p + a]));
+  T *w = static_cast<T *>(P.w);
+  const double inv_dx2 = 1.0 / (P.dx * P.dx);
+  {
+    const int lr = tid >> 4, node = tid & 15;
+    const int p = row0 + lr;
+    if (p < ns) {
+      const double f0p = P.f0[p];
+      double ft, f;
+      if (mode == GPF_CIRCULATION) {
+        f = yr[lr][0] - s0 * f0p;
+        ft = f / f0p;
+      } else {
+        double x = yr[lr][0] / f0p - c1;
+        for (int j = 0; j < m; ++j) x += scal[3 + j] * yr[lr][1 + j] / f0p;
+        ft = x - s0;
+        f = f0p * ft;
+      }
+      if (node == 0) {
+        if (P.f_out) P.f_out[p] = f;
+        if (P.ft_out) P.ft_out[p] = ft;
+      }
+      const int a = node & 3, b = node >> 2;
+      const int i0 = P.st_i[2 * p], j0 = P.st_i[2 * p + 1];
+      const double amp = P.ds[p] * f * inv_dx2;
+      atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
+                 (T)(amp * P.st_w[8 * p + a] * P.st_w[8 * p + 4 + b]));
     }
   }
-  if (P.sv.mode == GPF_KUTTA_SHED && (int)threadIdx.x < P.sv.m) {
-    const int j = threadIdx.x;
-    const double xi = (P.sv.xnew[j] - P.x0) / P.dx, eta = (P.sv.ynew[j] - P.y0) / P.dx;
+  if (blockIdx.x == 0 && mode == GPF_KUTTA_SHED && tid < 16 * m) {
+    const int j = tid >> 4, node = tid & 15;
+    const double xi = (sv.xnew[j] - P.x0) / P.dx, eta = (sv.ynew[j] - P.y0) / P.dx;
     if (xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0) {
       const int i0 = (int)floor(xi) - 1, j0 = (int)floor(eta) - 1;
       const double fx = xi - floor(xi), fy = eta - floor(eta);
-      const double amp = gam[j] * inv;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const double ab = amp * m4p(fy + 1.0 - b);
-        T *r = w + (size_t)(j0 + b) * n + i0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) atomic_add(r + a, (T)(ab * m4p(fx + 1.0 - a)));
-      }
+      const int a = node & 3, b = node >> 2;
+      atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
+                 (T)(scal[3 + j] * inv_dx2 * m4p(fy + 1.0 - b) * m4p(fx + 1.0 - a)));
     }
   }
-  // outputs
-  for (int p = threadIdx.x; p < ns; p += kCB) {
-    if (P.f_out) P.f_out[p] = P.f[p];
-    if (P.ft_out) P.ft_out[p] = P.ft[p];
-  }
-  __syncthreads();
-  if (P.sc_out && (int)threadIdx.x < SC_COUNT) P.sc_out[threadIdx.x] = P.aux[threadIdx.x];
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
 }
 
 }  // namespace
@@ -540,6 +537,11 @@ hipError_t launch_gemv(int ns, int ncol, const double *A, const double *X, doubl
   return hipGetLastError();
 }
 
+hipError_t launch_gemv_t(int ns, const double *A, const double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_t, dim3((ns + 255) / 256), dim3(256), 0, s, ns, A, x, y);
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s) {
   const int nbe = (ns_max + kRB - 1) / kRB;
@@ -553,7 +555,7 @@ template hipError_t launch_surface_rhs<double>(const ProbDesc *, int, int, int, 
 
 template <class T>
 hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, hipStream_t s) {
-  hipLaunchKernelGGL((k_schur_apply<T>), dim3((ns_max + 3) / 4, nb), dim3(kCB), 0, s, d);
+  hipLaunchKernelGGL((k_schur_apply<T>), dim3((ns_max + kCRows - 1) / kCRows, nb), dim3(kCB), 0, s, d);
   timer_end(s);
   return hipGetLastError();
 }

@@ -341,7 +341,23 @@ __global__ __launch_bounds__(256) void k_vortex_velocity(const ProbDesc *__restr
   P.v[q] = -vacc * h + P.sv.v_inf;
 }
 
+__global__ void k_axpy2(int nv, const double *__restrict__ x, const double *__restrict__ y,
+                        const double *__restrict__ u, const double *__restrict__ v, double a,
+                        double *xo, double *yo) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nv) return;
+  xo[q] = x[q] + a * u[q];
+  yo[q] = y[q] + a * v[q];
+}
+
 }  // namespace
+
+hipError_t launch_axpy2(int nv, const double *x, const double *y, const double *u,
+                        const double *v, double a, double *xo, double *yo, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy2, dim3((nv + 255) / 256), dim3(256), 0, s, nv, x, y, u, v, a, xo, yo);
+  return hipGetLastError();
+}
 
 int scatter_blocks(int nv_max) { return nv_max > 0 ? (nv_max + kScatterBlock - 1) / kScatterBlock : 1; }
 

@@ -102,6 +102,10 @@ def _load():
         "gpf_batch_destroy": (None, [P]),
         "gpf_solve_batched": (I, [P, I, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                   C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
+        "gpf_rk2_create": (I, [P, P, C.POINTER(gpf_inputs), P, P, D, I, PP]),
+        "gpf_rk2_run": (I, [P, I, P]),
+        "gpf_rk2_fields": (I, [P, PP, PP, PP, PP, PP, PP]),
+        "gpf_rk2_destroy": (None, [P]),
         "gpf_sync": (I, [P, P]),
         "gpf_last_error": (C.c_char_p, []),
         "gpf_version": (C.c_char_p, []),
@@ -345,6 +349,41 @@ class Batch:
     def close(self):
         if self.h:
             lib.gpf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Rk2:
+    """Explicit-midpoint vortex advection; X, Y (float64 device tensors) are
+    updated in place by run()."""
+
+    def __init__(self, plan: Plan, body, inp: gpf_inputs, X, Y, dt: float, use_graph=True):
+        h = C.c_void_p()
+        check(lib.gpf_rk2_create(plan.h, None if body is None else body.h, C.byref(inp),
+                                 _ptr(X), _ptr(Y), float(dt), int(bool(use_graph)), C.byref(h)),
+              "gpf_rk2_create")
+        self.h = h
+        self.plan, self.body, self.inp, self.X, self.Y = plan, body, inp, X, Y
+
+    def run(self, nsteps: int, stream=None):
+        check(lib.gpf_rk2_run(self.h, int(nsteps), _stream_ptr(stream)), "gpf_rk2_run")
+
+    def status_ptr(self) -> int:
+        ptrs = [C.c_void_p() for _ in range(6)]
+        check(lib.gpf_rk2_fields(self.h, *[C.byref(p) for p in ptrs]), "gpf_rk2_fields")
+        return ptrs[5].value
+
+    def sync(self, stream=None):
+        check(lib.gpf_sync(_stream_ptr(stream), C.c_void_p(self.status_ptr())), "gpf_sync")
+
+    def close(self):
+        if self.h:
+            lib.gpf_rk2_destroy(self.h)
             self.h = None
 
     def __del__(self):

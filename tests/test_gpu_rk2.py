@@ -1,0 +1,101 @@
+"""Explicit-midpoint time stepping on the GPU: one step against the oracle's
+midpoint step (the 1024^2 ellipse workload and a small case), and captured
+graph replays against eager steps.  Multi-step trajectories are compared
+only between the two GPU paths (the dynamics is chaotic: parity over many
+steps is unpinned)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2102_11910_amd import gpf  # noqa: E402
+from paper_2102_11910_amd import workloads as wl  # noqa: E402
+from oracle.solve import rk2_step  # noqa: E402
+from tests.conftest import rell2  # noqa: E402
+from tests.oracle_adapter import body_of, problem_of  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpf.Context(0)
+
+
+def make(ctx, case, flags=gpf.GPF_POLICY_AUTO):
+    plan = gpf.Plan(ctx, case.n, case.dx, flags=flags)
+    body = gpf.Body(plan, case.surface.xs, case.surface.ys, case.surface.ds) if case.surface else None
+    X = torch.as_tensor(case.X, dtype=torch.float64).to(DEV)
+    Y = torch.as_tensor(case.Y, dtype=torch.float64).to(DEV)
+    G = torch.as_tensor(case.G, dtype=torch.float64).to(DEV)
+    inp = gpf.make_inputs(X, Y, G, case.u_inf, case.v_inf, case.ub, case.vb, case.omega,
+                          case.mode, case.gamma_b)
+    return plan, body, X, Y, G, inp
+
+
+@pytest.mark.parametrize("which", ["small", "config3"])
+def test_rk2_step_matches_oracle(ctx, which):
+    case = wl.random_case(41, 128, 2.0 / 128, 300) if which == "small" else wl.config3()
+    dt = case.extra.get("dt", 0.5 * case.dx)
+    say(f"[rk2] {case.name}: nv={case.nv}, dt={dt}")
+    plan, body, X, Y, G, inp = make(ctx, case)
+    rk = gpf.Rk2(plan, body, inp, X, Y, dt, use_graph=True)
+    rk.run(1)
+    rk.sync()
+    torch.cuda.synchronize()
+    Xn, Yn = X.cpu().numpy(), Y.cpu().numpy()
+    xr, yr, _, _ = rk2_step(problem_of(case), body_of(case), dt)
+    dref = np.r_[xr - case.X, yr - case.Y]
+    dgot = np.r_[Xn - case.X, Yn - case.Y]
+    err = rell2(dgot, dref)
+    say(f"   displacement relL2 = {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_rk2_graph_equals_eager(ctx):
+    # The vortex scatter adds through atomics, so its summation order (and
+    # the last bits of the field) can change between any two runs; an FP64
+    # plan keeps that far below what a replay mistake would show.
+    # dt keeps the 15 steps' drift (about 1.5 cells) inside the 4-cell margin
+    # the random cloud leaves at the grid edge
+    case = wl.random_case(42, 128, 2.0 / 128, 500, surface="ellipse")
+    dt = 0.08 * case.dx
+    plan, body, X1, Y1, G, inp = make(ctx, case, flags=gpf.GPF_FP64)
+    X2, Y2 = X1.clone(), Y1.clone()
+    rk_g = gpf.Rk2(plan, body, inp, X1, Y1, dt, use_graph=True)
+    rk_e = gpf.Rk2(plan, body, inp, X2, Y2, dt, use_graph=False)
+    for rep in range(3):
+        rk_g.run(5)
+        rk_g.sync()
+        rk_e.run(5)
+        rk_e.sync()
+        torch.cuda.synchronize()
+        d = float(torch.max(torch.abs(X1 - X2)).item() + torch.max(torch.abs(Y1 - Y2)).item())
+        say(f"[rk2 graph vs eager] after {5 * (rep + 1)} steps: max |dx| = {d:.2e}")
+        assert d <= 1e-9
+    moved = float(torch.max(torch.abs(X1.cpu() - torch.as_tensor(case.X))).item())
+    assert moved > 1e-3
+
+
+def test_rk2_rejects_shedding(ctx):
+    case = wl.random_case(43, 64, 2.0 / 64, 20, surface="plate", mode="shed")
+    plan = gpf.Plan(ctx, case.n, case.dx)
+    body = gpf.Body(plan, case.surface.xs, case.surface.ys, case.surface.ds, case.surface.edges)
+    X = torch.as_tensor(case.X, dtype=torch.float64).to(DEV)
+    Y = torch.as_tensor(case.Y, dtype=torch.float64).to(DEV)
+    G = torch.as_tensor(case.G, dtype=torch.float64).to(DEV)
+    inp = gpf.make_inputs(X, Y, G, mode="shed", znew=case.znew)
+    with pytest.raises(gpf.GpfError) as e:
+        gpf.Rk2(plan, body, inp, X, Y, 1e-3)
+    assert e.value.status == gpf.GPF_E_UNSUPPORTED
