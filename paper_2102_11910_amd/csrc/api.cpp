@@ -281,11 +281,12 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
       GPF_HIP(hipMemset(bin_cnt.p, 0, bin_cnt.bytes));  // counts start (and end) at zero
     }
     GPF_TRY(bin_start.alloc(tiles * sizeof(int)));
+    GPF_TRY(tile_list.alloc(tiles * sizeof(int)));
   }
   if (nvv > nv || !rank.p) {
     const size_t cap = std::max<size_t>(1024, (size_t)nvv);
     GPF_TRY(rank.alloc(cap * sizeof(int)));
-    GPF_TRY(order.alloc(cap * sizeof(int)));
+    GPF_TRY(sorted.alloc(3 * cap * sizeof(double)));
     nv = (int)cap;
   }
   return GPF_OK;
@@ -361,8 +362,9 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.partials = ws->part.as<double>();
   pd.bin_cnt = ws->bin_cnt.as<int>();
   pd.bin_start = ws->bin_start.as<int>();
+  pd.tile_list = ws->tile_list.as<int>();
   pd.rank = ws->rank.as<int>();
-  pd.order = ws->order.as<int>();
+  pd.sorted = ws->sorted.as<double>();
   pd.status = out->d_status;
   pd.psi = out->d_psi;
   pd.u = (out->d_u && out->d_v) ? out->d_u : nullptr;
@@ -737,8 +739,9 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   pd.partials = plan->ws.part.as<double>();
   pd.bin_cnt = plan->ws.bin_cnt.as<int>();
   pd.bin_start = plan->ws.bin_start.as<int>();
+  pd.tile_list = plan->ws.tile_list.as<int>();
   pd.rank = plan->ws.rank.as<int>();
-  pd.order = plan->ws.order.as<int>();
+  pd.sorted = plan->ws.sorted.as<double>();
   if (d_status) pd.status = d_status;
   void *dev = nullptr;
   GPF_TRY(plan->ring.push(&pd, sizeof(pd), s, &dev));

@@ -152,14 +152,17 @@ struct ProbDesc {
   int nv;
   const double *xv, *yv, *gv;
   // fields
-  void *w;                      // source field (zero on entry)
+  void *w;                      // source field (zero on entry, or the values R_v adds to)
   const void *s1;               // result of the first convolution
   // per-problem aux: scalars, partial sums, counters
   double *aux;
   double *partials;
   unsigned *status;
-  // vortex binning by tiles of cells: counts, starts, ranks, order
-  int *bin_cnt, *bin_start, *rank, *order;
+  // vortex binning by tiles of cells: counts (zero between solves), tile
+  // starts, rank of each vortex in its tile, tile-sorted (xi, eta, Gamma/dx^2)
+  int *bin_cnt, *bin_start, *rank;
+  int *tile_list;               // [0] = number of non-empty tiles, then their indices
+  double *sorted;
   // body
   int ns;
   const double *xs, *ys, *ds, *sinv, *f0;
@@ -184,9 +187,9 @@ __host__ __device__ inline unsigned *aux_counter(double *aux, int k) {
 // ---------------------------------------------------------------------------
 int scatter_blocks(int nv_max);
 int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n < 32)
-// R_v: bin the vortices by tile, then one workgroup per tile accumulates
-// its vortices in LDS and adds the window to the source field (which must
-// hold zeros, or the values to add to)
+// R_v: bin and sort the vortices by tile, then one workgroup per tile sums
+// its vortices in an LDS window and adds the window to the source field
+// (which must hold zeros, or the values to add to)
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s);
 template <class Tin, class T>
@@ -203,7 +206,7 @@ hipError_t launch_axpy2(int nv, const double *x, const double *y, const double *
                         const double *v, double a, double *xo, double *yo, hipStream_t s);
 
 // single-problem helpers used at setup and by the building blocks
-hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);   // zero bytes (a multiple of 4)
 hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
                                    const double *xs, const double *ys, int *st_i,
                                    double *st_w, unsigned *status, hipStream_t s);
@@ -233,7 +236,7 @@ struct gpf_ctx {
 struct gpf_workspace {
   int n = 0, ns = 0, nv = 0;
   gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs;
-  gpf::DevBuf bin_cnt, bin_start, rank, order;
+  gpf::DevBuf bin_cnt, bin_start, tile_list, rank, sorted;
   gpf_status ensure(int n, bool need32, bool need64, int ns);
   gpf_status ensure_vortices(int nv);
 };

@@ -65,25 +65,24 @@ __global__ void k_fill(unsigned *p, size_t words) {
 }
 
 // ---------------------------------------------------------------------------
-// R_v by tiles.  A vortex belongs to the tile of its base cell floor(xi);
-// its 4 x 4 stencil covers nodes floor(xi)-1 .. floor(xi)+2, so the nodes
-// owned by a tile receive contributions only from vortices of the tile and
-// of its 8 neighbours.  No atomic additions of weights: each tile's nodes
-// are summed by one workgroup and stored.
+// R_v by tiles of ts x ts cells: the vortices are counted and sorted by the
+// tile of their base cell floor(xi), then each tile's vortices are summed in
+// an LDS window by one workgroup.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int tile_cells(int n) { return n <= 16 ? n : (n <= 1024 ? 16 : 32); }
 constexpr int kMaxTiles = 4096;
 
-// 1. count vortices per tile.  A block first histograms its own vortices in
-//    LDS, then adds each non-empty bin to the global count once; a vortex's
-//    rank in its tile = the block's offset for the tile + its rank in the
-//    block.  The last block of each problem sums the circulation in order
-//    and turns the counts into tile starts (clearing the counts).
+__device__ __forceinline__ int vortex_tile(int i0, int j0, int ts, int tps) {
+  return ((j0 + 1) / ts) * tps + (i0 + 1) / ts;
+}
+
+// 1. count vortices per tile.  A workgroup histograms its vortices in LDS,
+//    then adds each non-empty bin to the global count once; a vortex's rank
+//    in its tile = the workgroup's offset for the tile + its rank within the
+//    workgroup.  Each workgroup also stores its partial circulation.
 __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__restrict__ d) {
-  __shared__ double red[kScatterBlock];
   __shared__ int hist[kMaxTiles];
-  __shared__ int part[kScatterBlock];
-  __shared__ bool last;
+  __shared__ double red[kScatterBlock / 64];
   const ProbDesc &P = d[blockIdx.y];
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
   for (int t = threadIdx.x; t < ntiles; t += kScatterBlock) hist[t] = 0;
@@ -97,7 +96,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
     if (cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx) &&
         cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy)) {
       gq = P.gv[q];
-      tile = ((j0 + 1) / ts) * tps + (i0 + 1) / ts;
+      tile = vortex_tile(i0, j0, ts, tps);
       lrank = atomicAdd(hist + tile, 1);
     } else {
       atomicOr(P.status, GPF_DEV_OUT_OF_GRID);
@@ -105,8 +104,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
   }
   __syncthreads();
   {
-    // add the non-empty bins to the global counts; the atomics of one
-    // thread are independent, so issue them all before using the results
+    // the atomics of one thread are independent: issue them all before
+    // using the results
     constexpr int kPer = kMaxTiles / kScatterBlock;
     int ret[kPer];
 #pragma unroll
@@ -124,93 +123,123 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
   }
   __syncthreads();
   if (q < P.nv) P.rank[q] = tile >= 0 ? hist[tile] + lrank : -1;
-  red[threadIdx.x] = gq;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) gq += __shfl_xor(gq, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gq;
   __syncthreads();
-  for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  unsigned *counter = aux_counter(P.aux, 0);
   if (threadIdx.x == 0) {
-    P.partials[blockIdx.x] = red[0];
-    __threadfence();
-    const unsigned done = atomicAdd(counter, 1u);
-    last = (done == gridDim.x - 1);
+    double s = 0.0;
+    for (int w = 0; w < kScatterBlock / 64; ++w) s += red[w];
+    P.partials[blockIdx.x] = s;
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kScatterBlock)
-    acc += __hip_atomic_load(P.partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kScatterBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    P.aux[SC_GAMMA_W] = red[0];
-    if (P.sc_out) P.sc_out[SC_GAMMA_W] = red[0];
-  }
-  // exclusive scan of the tile counts: each thread sums a contiguous run
-  // (its loads issued together), the run totals are scanned in LDS, then
-  // each run is written out
+}
+
+// 2. every workgroup scans the tile counts into tile starts (workgroup 0
+//    also stores them and the circulation, summed over the partials in
+//    order), then writes each of its vortices to slot start + rank of the
+//    tile-sorted list as (xi, eta, Gamma / dx^2).
+__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d) {
+  __shared__ int start[kMaxTiles + 1];
+  __shared__ int wsum[kScatterBlock / 64];
+  __shared__ double gsum[kScatterBlock / 64];
+  const ProbDesc &P = d[blockIdx.y];
+  const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int kPer = kMaxTiles / kScatterBlock;
   const int per = (ntiles + kScatterBlock - 1) / kScatterBlock;
-  const int lo = threadIdx.x * per, hi = min(lo + per, ntiles);
+  const int lo = tid * per;
   int cnts[kPer];
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    cnts[k] = lo + k < hi
-                  ? __hip_atomic_load(P.bin_cnt + lo + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                  : 0;
+  for (int k = 0; k < kPer; ++k) cnts[k] = (k < per && lo + k < ntiles) ? P.bin_cnt[lo + k] : 0;
   int run = 0;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) run += cnts[k];
-  part[threadIdx.x] = run;
-  __syncthreads();
-  for (int off = 1; off < kScatterBlock; off <<= 1) {  // inclusive Hillis-Steele
-    const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  int incl = run;   // inclusive scan of the run totals: waves, then across waves
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
   }
-  int pos = part[threadIdx.x] - run;
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int pos = incl - run, total = 0;
+#pragma unroll
+  for (int w = 0; w < kScatterBlock / 64; ++w) {
+    if (w < wave) pos += wsum[w];
+    total += wsum[w];
+  }
+  const bool store = blockIdx.x == 0;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    if (lo + k < hi) {
-      P.bin_start[lo + k] = pos;
-      P.bin_cnt[lo + k] = 0;
+    if (k < per && lo + k < ntiles) {
+      start[lo + k] = pos;
+      if (store) P.bin_start[lo + k] = pos;
       pos += cnts[k];
     }
   }
-  if (threadIdx.x == kScatterBlock - 1) {
-    P.bin_start[ntiles] = part[kScatterBlock - 1];
-    atomicExch(counter, 0u);
+  if (tid == 0) {
+    start[ntiles] = total;
+    if (store) P.bin_start[ntiles] = total;
   }
-}
-
-// 2. place each vortex index at its tile's start + rank
-__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d) {
-  const ProbDesc &P = d[blockIdx.y];
-  const int q = blockIdx.x * kScatterBlock + threadIdx.x;
+  if (store) {
+    // list of the non-empty tiles, in tile order: tile_list[0] = count
+    int ne = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) ne += cnts[k] != 0;
+    int inc = ne;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(inc, off);
+      if (lane >= off) inc += v;
+    }
+    __syncthreads();   // wsum is reused
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int at = inc - ne, tot_ne = 0;
+#pragma unroll
+    for (int w = 0; w < kScatterBlock / 64; ++w) {
+      if (w < wave) at += wsum[w];
+      tot_ne += wsum[w];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (cnts[k] != 0) P.tile_list[1 + at++] = lo + k;
+    if (tid == 0) P.tile_list[0] = tot_ne;
+  }
+  if (store) {
+    // circulation: the partials summed in a fixed order (strided per
+    // thread, then waves), so every solve gives the same bits
+    double g = 0.0;
+    for (int b = tid; b < (int)gridDim.x; b += kScatterBlock) g += P.partials[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off);
+    if (lane == 0) gsum[wave] = g;
+  }
+  __syncthreads();
+  if (store && tid == 0) {
+    double g = 0.0;
+    for (int w = 0; w < kScatterBlock / 64; ++w) g += gsum[w];
+    P.aux[SC_GAMMA_W] = g;
+    if (P.sc_out) P.sc_out[SC_GAMMA_W] = g;
+  }
+  const int q = blockIdx.x * kScatterBlock + tid;
   if (q >= P.nv) return;
   const int r = P.rank[q];
   if (r < 0) return;
-  const int n = P.n, ts = tile_cells(n), tps = n / ts;
-  int i0, j0;
-  double fx, fy;
-  cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx);
-  cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy);
-  const int t = ((j0 + 1) / ts) * tps + (i0 + 1) / ts;
-  P.order[P.bin_start[t] + r] = q;
+  const double xi = (P.xv[q] - P.x0) / P.dx, eta = (P.yv[q] - P.y0) / P.dx;
+  const int t = vortex_tile((int)floor(xi) - 1, (int)floor(eta) - 1, ts, tps);
+  double *o = P.sorted + 3 * (size_t)(start[t] + r);
+  o[0] = xi;
+  o[1] = eta;
+  o[2] = P.gv[q] / (P.dx * P.dx);
 }
 
-// 3. one workgroup per tile: the tile's vortices add their 4 x 4 stencils
-//    into an LDS window of (ts+3)^2 nodes (nodes X0-1 .. X0+ts+1), which is
-//    then added to the field; only window nodes that received weight take a
-//    global atomic, and each node sits in at most four windows.
+// 3. workgroups take the non-empty tiles in turn: the tile's vortices add their 4 x 4
+//    stencils into an LDS window of (ts+3)^2 nodes (nodes X0-1 .. X0+ts+1),
+//    which is then added to the field (zero, or the values to add to); only
+//    window nodes that received weight take a global atomic, and each node
+//    lies in at most four windows.  The tile's count is cleared for the next
+//    solve.
 constexpr int kTileBlock = 256;
 
 template <class T>
@@ -218,37 +247,54 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
   __shared__ T win[35 * 35];
   const ProbDesc &P = d[blockIdx.y];
   const int n = P.n, ts = tile_cells(n), tps = n / ts;
-  const int t = blockIdx.x;
-  const int b0 = P.bin_start[t], b1 = P.bin_start[t + 1];
-  if (b0 == b1) return;
-  const int X0 = (t % tps) * ts - 1, Y0 = (t / tps) * ts - 1;   // window origin
+  const int tid = threadIdx.x;
   const int bw = ts + 3, nwin = bw * bw;
-  for (int k = threadIdx.x; k < nwin; k += kTileBlock) win[k] = (T)0;
-  __syncthreads();
-  const double inv = 1.0 / (P.dx * P.dx);
-  for (int k = b0 + threadIdx.x; k < b1; k += kTileBlock) {
-    const int q = P.order[k];
-    int i0, j0;
-    double fx, fy;
-    cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx);
-    cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy);
-    const double amp = P.gv[q] * inv;
-    double wx[4];
+  const int cnt = P.tile_list[0];
+  for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int t = P.tile_list[1 + i];
+    const int b0 = P.bin_start[t], b1 = P.bin_start[t + 1];
+    if (tid == 0) P.bin_cnt[t] = 0;
+    const int X0 = (t % tps) * ts - 1, Y0 = (t / tps) * ts - 1;   // window origin
+    for (int k = tid; k < nwin; k += kTileBlock) win[k] = (T)0;
+    __syncthreads();
+    // records are taken kBatch at a time per thread, their loads issued
+    // before any is used (dense tiles hold hundreds of vortices)
+    constexpr int kBatch = 4;
+    for (int k0 = b0; k0 < b1; k0 += kBatch * kTileBlock) {
+      double rec[kBatch][3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) wx[a] = m4p(fx + 1.0 - a);
-    T *row = win + (j0 - Y0) * bw + (i0 - X0);
+      for (int j = 0; j < kBatch; ++j) {
+        const int k = min(k0 + j * kTileBlock + tid, b1 - 1);
+        const double *r = P.sorted + 3 * (size_t)k;
+        rec[j][0] = r[0];
+        rec[j][1] = r[1];
+        rec[j][2] = k0 + j * kTileBlock + tid < b1 ? r[2] : 0.0;   // clamped duplicates add zero
+      }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const double ab = amp * m4p(fy + 1.0 - b);
+      for (int j = 0; j < kBatch; ++j) {
+        if (k0 + j * kTileBlock + tid >= b1) continue;
+        const double xi = rec[j][0], eta = rec[j][1], amp = rec[j][2];
+        const double flx = floor(xi), fly = floor(eta);
+        const double fx = xi - flx, fy = eta - fly;
+        double wx[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) atomicAdd(row + b * bw + a, (T)(ab * wx[a]));
+        for (int a = 0; a < 4; ++a) wx[a] = m4p(fx + 1.0 - a);
+        T *row = win + ((int)fly - 1 - Y0) * bw + ((int)flx - 1 - X0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double ab = amp * m4p(fy + 1.0 - b);
+#pragma unroll
+          for (int a = 0; a < 4; ++a) atomicAdd(row + b * bw + a, (T)(ab * wx[a]));
+        }
+      }
     }
-  }
-  __syncthreads();
-  T *w = static_cast<T *>(P.w);
-  for (int k = threadIdx.x; k < nwin; k += kTileBlock) {
-    const T v = win[k];
-    if (v != (T)0) atomic_add(w + (size_t)(Y0 + k / bw) * n + X0 + k % bw, v);
+    __syncthreads();
+    T *w = static_cast<T *>(P.w);
+    for (int k = tid; k < nwin; k += kTileBlock) {
+      const T v = win[k];
+      if (v != (T)0) atomic_add(w + (size_t)(Y0 + k / bw) * n + X0 + k % bw, v);
+    }
+    __syncthreads();   // the window is cleared for the next tile
   }
 }
 
@@ -380,7 +426,9 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   const int vb = scatter_blocks(nv_max);
   hipLaunchKernelGGL(k_bin_count, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
   hipLaunchKernelGGL(k_bin_place, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
-  hipLaunchKernelGGL((k_tile_scatter<T>), dim3(bin_tiles(n), nb), dim3(kTileBlock), 0, s, d);
+  // about one workgroup per 64 vortices, looping over the non-empty tiles
+  const int tb = std::max(1, std::min(bin_tiles(n), (nv_max + 63) / 64));
+  hipLaunchKernelGGL((k_tile_scatter<T>), dim3(tb, nb), dim3(kTileBlock), 0, s, d);
   timer_end(s);
   return hipGetLastError();
 }
