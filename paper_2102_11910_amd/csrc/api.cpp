@@ -444,11 +444,11 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, int xcds,
                         hipStream_t s) {
   GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
-  GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, s)));
+  GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body, s)));
   if (cfg.body) {
     GPF_HIP(launch_surface_rhs<T1>(pd, nb, ns_max, m_max, s));
     GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, s));
-    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, s)));
+    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, false, s)));
   }
   GPF_HIP(launch_vortex_velocity<T2>(pd, nb, nv_max, s));
   return GPF_OK;
@@ -776,9 +776,9 @@ gpf_status gpf_convolve(gpf_plan *plan, const void *d_w, void *d_s, double gamma
   const int n = plan->grid.n;
   const int x = plan->ctx->xcds;
   if (plan->fp64)
-    GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, x, s)));
+    GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, x, false, s)));
   else
-    GPF_HIP((launch_convolve<float, float>(n, static_cast<ConvDesc *>(dev), 1, x, s)));
+    GPF_HIP((launch_convolve<float, float>(n, static_cast<ConvDesc *>(dev), 1, x, false, s)));
   return GPF_OK;
 }
 

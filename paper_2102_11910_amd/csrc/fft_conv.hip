@@ -21,6 +21,7 @@
 // Stockham radix-R step (R = 16 except a last 2/4/8 step), each lane doing
 // 16/R butterflies with its values in registers.  LDS rows are padded by one
 // element every 16 to spread the strided stores over the banks.
+#include <algorithm>
 #include <type_traits>
 
 #include "gpf_internal.h"
@@ -105,6 +106,23 @@ template <int N> struct Plan {
   static constexpr int LDS_SEQ = N + N / 16;   // padded elements per sequence
 };
 
+// Row passes: a workgroup holds 2 SEQ rows, so each k-major row of the
+// intermediate is touched in runs of 2 SEQ elements; the wide SEQ gives
+// 128-byte runs within about 72 KB of LDS (two workgroups per CU).
+// The wide shape suits launches with many row blocks (batches); single
+// problems and row-pruned passes keep the narrow shape for more workgroups.
+template <class T, int N, bool WIDE> struct RowPlan {
+  static constexpr int TPS = N / kE;
+  static constexpr int LDS_SEQ = N + N / 16;
+  static constexpr int ELEM = 2 * (int)sizeof(T);
+  static constexpr int fit(int s) {
+    while (s > 1 && s * LDS_SEQ * ELEM > 72 * 1024) s /= 2;
+    return s;
+  }
+  static constexpr int SEQ = WIDE ? fit(64 / ELEM) : Plan<N>::SEQ;
+  static constexpr int WGT = TPS * SEQ;
+};
+
 // radix of stage `s` for a length-N transform with 16 values per lane
 template <int N> __host__ __device__ constexpr int stage_radix(int s) {
   int rem = N, r = 16;
@@ -122,6 +140,57 @@ template <int N> __host__ __device__ constexpr int num_stages() {
   }
   return s;
 }
+// stride NS of stage s (product of the earlier radices)
+template <int N> __host__ __device__ constexpr int stage_ns(int s) {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= stage_radix<N>(i);
+  return ns;
+}
+// base twiddles a lane keeps for stages before s (stage 0 needs none): the
+// R-1 factors of its first butterfly.  Only a last stage has more than one
+// butterfly per lane, and there butterfly b sits at j + b N/16, so its
+// factors are the base ones times 16th roots of unity.
+template <int N> __host__ __device__ constexpr int tw_before(int s) {
+  int c = 0;
+  for (int i = 1; i < s; ++i) c += stage_radix<N>(i) - 1;
+  return c;
+}
+template <int N> __host__ __device__ constexpr int tw_regs() {
+  return tw_before<N>(num_stages<N>()) > 0 ? tw_before<N>(num_stages<N>()) : 1;
+}
+
+// Twiddles in registers where the kernel's occupancy is bounded by LDS
+// anyway (larger transforms read them from the global table per stage).
+template <class T, int N> __host__ __device__ constexpr bool tw_in_regs() { return N <= 1024; }
+
+// Every twiddle factor a lane uses, loaded once at kernel start (the loads
+// overlap the data loads instead of waiting behind each stage's barrier);
+// inverse transforms use their conjugates.
+template <class T, int N, int S>
+__device__ __forceinline__ void load_twiddles(typename CT<T>::V (&wr)[tw_regs<N>()],
+                                              const typename CT<T>::V *tw, int lane) {
+  if constexpr (S < num_stages<N>()) {
+    if constexpr (S >= 1) {
+      constexpr int R = stage_radix<N>(S), NS = stage_ns<N>(S), OFF = tw_before<N>(S);
+      const int j = lane % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) wr[OFF + r - 1] = tw[j * r * (N / (NS * R))];
+    }
+    load_twiddles<T, N, S + 1>(wr, tw, lane);
+  }
+}
+
+// w * exp(-+2 pi i k / 16); k is a constant once the callers' loops unroll
+template <bool INV, class V> __device__ __forceinline__ V rot16(V w, int k) {
+  using S = decltype(w.x);
+  k &= 15;
+  if (k == 0) return w;
+  V c;
+  c.x = (S)(k < 8 ? kC16[k] : -kC16[k - 8]);
+  const S sn = (S)(k < 8 ? kS16[k] : -kS16[k - 8]);
+  c.y = INV ? sn : -sn;
+  return cmul(w, c);
+}
 
 // One Stockham stage.  Lane `lane` of the group owning a sequence handles
 // butterflies bf = lane + b * TPS (b < 16/R), each reading elements
@@ -130,14 +199,18 @@ template <int N> __host__ __device__ constexpr int num_stages() {
 // (the stage-0 layout, radix 16).  With OUT_REGS the results stay in x[],
 // again as x[k] = element lane + k * TPS: in the last stage the butterfly
 // b, output r lands at lane + TPS * (b + r * 16/R).
-template <class T, int N, int R, int NS, bool INV, bool ZERO_UPPER, bool LOWER_OUT, bool IN_REGS,
+template <class T, int N, int S, bool INV, bool ZERO_UPPER, bool LOWER_OUT, bool IN_REGS,
           bool OUT_REGS>
 __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
+                                          const typename CT<T>::V (&wr)[tw_regs<N>()],
                                           const typename CT<T>::V *tw, int lane) {
   using V = typename CT<T>::V;
   constexpr int TPS = N / kE;
+  constexpr int R = stage_radix<N>(S), NS = stage_ns<N>(S);
   constexpr int NB = kE / R;   // butterflies per lane
   static_assert(!IN_REGS || R == kE, "register input needs a radix-16 first stage");
+  static_assert(NB == 1 || (S == num_stages<N>() - 1 && NS * R == N),
+                "several butterflies per lane only in a last stage");
   V v[NB][R];
   if (IN_REGS) {
 #pragma unroll
@@ -172,8 +245,15 @@ __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename C
     if (NS > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        V w = tw[j * r * (N / (NS * R))];
-        if (INV) w.y = -w.y;
+        V w;
+        if constexpr (tw_in_regs<T, N>()) {
+          w = wr[tw_before<N>(S) + r - 1];
+          if (INV) w.y = -w.y;
+          if (NB > 1) w = rot16<INV>(w, b * r);   // butterfly b sits at j + b N/16
+        } else {
+          w = tw[j * r * (N / (NS * R))];
+          if (INV) w.y = -w.y;
+        }
         v[b][r] = cmul(v[b][r], w);
       }
     }
@@ -193,15 +273,15 @@ __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename C
   if (!OUT_REGS) __syncthreads();
 }
 
-template <class T, int N, int S, int NS, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS>
+template <class T, int N, int S, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS>
 __device__ __forceinline__ void fft_stages(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
+                                           const typename CT<T>::V (&wr)[tw_regs<N>()],
                                            const typename CT<T>::V *tw, int lane) {
   constexpr int NST = num_stages<N>();
   if constexpr (S < NST) {
-    constexpr int R = stage_radix<N>(S);
-    fft_stage<T, N, R, NS, INV, ZIN && S == 0, LOUT && S == NST - 1, IN_REGS && S == 0,
-              OUT_REGS && S == NST - 1>(x, lds, tw, lane);
-    fft_stages<T, N, S + 1, NS * R, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, tw, lane);
+    fft_stage<T, N, S, INV, ZIN && S == 0, LOUT && S == NST - 1, IN_REGS && S == 0,
+              OUT_REGS && S == NST - 1>(x, lds, wr, tw, lane);
+    fft_stages<T, N, S + 1, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, wr, tw, lane);
   }
 }
 
@@ -210,8 +290,9 @@ __device__ __forceinline__ void fft_stages(typename CT<T>::V (&x)[kE], typename 
 // (x[k] = element lane + k * N/16), otherwise in natural order in lds.
 template <class T, int N, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS>
 __device__ __forceinline__ void fft_seq(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
+                                        const typename CT<T>::V (&wr)[tw_regs<N>()],
                                         const typename CT<T>::V *tw, int lane) {
-  fft_stages<T, N, 0, 1, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, tw, lane);
+  fft_stages<T, N, 0, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, wr, tw, lane);
 }
 
 // logical block index: consecutive logical blocks on one XCD (blocks are
@@ -226,11 +307,11 @@ __device__ __forceinline__ int xcd_block(int xcds) {
 // ---------------------------------------------------------------------------
 // pass 1: rows, real -> half spectrum, stored k-major
 // ---------------------------------------------------------------------------
-template <class Tin, class T, int N>
-__global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const ConvDesc *__restrict__ cd,
-                                                           int xcds) {
+template <class Tin, class T, int N, bool WIDE>
+__global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_fwd(const ConvDesc *__restrict__ cd,
+                                                                 int xcds) {
   using V = typename CT<T>::V;
-  using P = Plan<N>;
+  using P = RowPlan<T, N, WIDE>;
   constexpr int n = N / 2;
   __shared__ V lds[P::SEQ * P::LDS_SEQ];
   const ConvDesc &C = cd[blockIdx.y];
@@ -242,6 +323,8 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const ConvDesc *__res
 
   const int q = tid / P::TPS, lane = tid % P::TPS;
   V x[kE];
+  V wr[tw_regs<N>()];
+  if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, lane);
   {
     // elements lane + k * TPS of the packed row pair; k >= 8 is the zero half
     const size_t row = (size_t)(j0 + 2 * q) * n;
@@ -255,7 +338,7 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_fwd(const ConvDesc *__res
     __syncthreads();
     for (int idx = tid; idx < 2 * P::SEQ * n; idx += P::WGT) w[(size_t)j0 * n + idx] = (Tin)0;
   }
-  fft_seq<T, N, false, true, false, true, false>(x, lds + q * P::LDS_SEQ, tw, lane);
+  fft_seq<T, N, false, true, false, true, false>(x, lds + q * P::LDS_SEQ, wr, tw, lane);
 
   // unpack: A = (Z[k] + conj Z[N-k]) / 2, B = (Z[k] - conj Z[N-k]) / (2i)
   constexpr int RW = 2 * P::SEQ;
@@ -291,26 +374,33 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * P::SEQ;
-
   const int q = tid / P::TPS, lane = tid % P::TPS;
   const int k1 = min(c0 + q, n);   // blocks past the last column redo it and store nothing
   V *col = X + (size_t)k1 * n;
   V x[kE];
 #pragma unroll
   for (int k = 0; k < kE / 2; ++k) x[k] = col[lane + k * P::TPS];
-  V *L = lds + q * P::LDS_SEQ;
-  fft_seq<T, N, false, true, false, true, true>(x, L, tw, lane);
+  // the spectrum row (and, when kept in registers, the twiddles) are loaded
+  // up front, beside the column
+  T g[kE];
   {
     const T *sp = spec + (size_t)k1 * (n + 1);
 #pragma unroll
     for (int k = 0; k < kE; ++k) {
       const int k2 = lane + k * P::TPS;
-      const T g = sp[k2 <= n ? k2 : N - k2];
-      x[k].x *= g;
-      x[k].y *= g;
+      g[k] = sp[k2 <= n ? k2 : N - k2];
     }
   }
-  fft_seq<T, N, true, false, true, true, true>(x, L, tw, lane);
+  V wr[tw_regs<N>()];
+  if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, lane);
+  V *L = lds + q * P::LDS_SEQ;
+  fft_seq<T, N, false, true, false, true, true>(x, L, wr, tw, lane);
+#pragma unroll
+  for (int k = 0; k < kE; ++k) {
+    x[k].x *= g[k];
+    x[k].y *= g[k];
+  }
+  fft_seq<T, N, true, false, true, true, true>(x, L, wr, tw, lane);
   if (c0 + q <= n) {
 #pragma unroll
     for (int k = 0; k < kE / 2; ++k) col[lane + k * P::TPS] = x[k];
@@ -320,12 +410,12 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
 // ---------------------------------------------------------------------------
 // pass 3: rows, two half spectra -> two real rows, gauge epilogue
 // ---------------------------------------------------------------------------
-template <class T, int N>
-__global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const ConvDesc *__restrict__ cd,
-                                                           int xcds) {
+template <class T, int N, bool WIDE>
+__global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const ConvDesc *__restrict__ cd,
+                                                                 int xcds) {
   using V = typename CT<T>::V;
   using V2 = typename CT<T>::V2;
-  using P = Plan<N>;
+  using P = RowPlan<T, N, WIDE>;
   constexpr int n = N / 2;
   __shared__ V lds[P::SEQ * P::LDS_SEQ];
   const ConvDesc &C = cd[blockIdx.y];
@@ -335,6 +425,8 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const ConvDesc *__res
   const int tid = threadIdx.x;
   const int j0 = xcd_block(xcds) * 2 * P::SEQ;
   if (j0 + 2 * P::SEQ <= C.row_lo || j0 > C.row_hi) return;  // rows nobody reads
+  V wr[tw_regs<N>()];
+  if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, tid % P::TPS);
 
   // Z[k] = A[k] + i B[k], Z[N-k] = conj(A[k]) + i conj(B[k]); the imaginary
   // parts of A and B at k = 0 and k = n are dropped (real rows).
@@ -359,7 +451,7 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const ConvDesc *__res
   __syncthreads();
   const int q = tid / P::TPS, lane = tid % P::TPS;
   V x[kE];
-  fft_seq<T, N, true, false, true, false, true>(x, lds + q * P::LDS_SEQ, tw, lane);
+  fft_seq<T, N, true, false, true, false, true>(x, lds + q * P::LDS_SEQ, wr, tw, lane);
   const T shift = (T)(C.c * (C.gamma ? C.gamma[0] : C.gamma_val));
   const size_t row = (size_t)(j0 + 2 * q) * n;
 #pragma unroll
@@ -369,21 +461,52 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_rows_inv(const ConvDesc *__res
   }
 }
 
+int num_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+  }
+  return cus;
+}
+
+template <class Tin, class T, int N, bool WIDE>
+void launch_rows_fwd(const ConvDesc *d, int nb, int xcds, hipStream_t st) {
+  using RP = RowPlan<T, N, WIDE>;
+  hipLaunchKernelGGL((k_rows_fwd<Tin, T, N, WIDE>), dim3(N / 2 / (2 * RP::SEQ), nb), dim3(RP::WGT),
+                     0, st, d, xcds);
+}
+template <class T, int N, bool WIDE>
+void launch_rows_inv(const ConvDesc *d, int nb, int xcds, hipStream_t st) {
+  using RP = RowPlan<T, N, WIDE>;
+  hipLaunchKernelGGL((k_rows_inv<T, N, WIDE>), dim3(N / 2 / (2 * RP::SEQ), nb), dim3(RP::WGT), 0,
+                     st, d, xcds);
+}
+
 template <class Tin, class T, int N>
-hipError_t run_conv(const ConvDesc *d, int nb, int xcds, hipStream_t st) {
+hipError_t run_conv(const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_t st) {
   using P = Plan<N>;
   constexpr int n = N / 2;
-  const int rb = n / (2 * P::SEQ);
-  const int cb = (n + 1 + P::SEQ - 1) / P::SEQ;
+  // wide row blocks when they still give two or more workgroups per CU
+  const bool wide = (n / (2 * RowPlan<T, N, true>::SEQ)) * nb >= 2 * num_cus();
   constexpr bool D = std::is_same<T, double>::value;
   timer_begin(D ? GPF_TK_ROWS_FWD64 : GPF_TK_ROWS_FWD, st);
-  hipLaunchKernelGGL((k_rows_fwd<Tin, T, N>), dim3(rb, nb), dim3(P::WGT), 0, st, d, xcds);
+  if (wide)
+    launch_rows_fwd<Tin, T, N, true>(d, nb, xcds, st);
+  else
+    launch_rows_fwd<Tin, T, N, false>(d, nb, xcds, st);
   timer_end(st);
   timer_begin(D ? GPF_TK_COLS64 : GPF_TK_COLS, st);
-  hipLaunchKernelGGL((k_cols_conv<T, N>), dim3(cb, nb), dim3(P::WGT), 0, st, d);
+  hipLaunchKernelGGL((k_cols_conv<T, N>), dim3((n + 1 + P::SEQ - 1) / P::SEQ, nb), dim3(P::WGT), 0,
+                     st, d);
   timer_end(st);
   timer_begin(D ? GPF_TK_ROWS_INV64 : GPF_TK_ROWS_INV, st);
-  hipLaunchKernelGGL((k_rows_inv<T, N>), dim3(rb, nb), dim3(P::WGT), 0, st, d, xcds);
+  if (wide && !pruned)
+    launch_rows_inv<T, N, true>(d, nb, xcds, st);
+  else
+    launch_rows_inv<T, N, false>(d, nb, xcds, st);
   timer_end(st);
   return hipGetLastError();
 }
@@ -391,22 +514,22 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, hipStream_t st) {
 }  // namespace
 
 template <class Tin, class T>
-hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, hipStream_t st) {
+hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_t st) {
   switch (n) {
-    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, st);
-    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, st);
-    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, st);
-    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, st);
-    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, st);
-    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, st);
-    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, st);
-    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, st);
+    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, pruned, st);
+    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, pruned, st);
+    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, pruned, st);
+    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, pruned, st);
+    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, pruned, st);
+    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, pruned, st);
+    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, pruned, st);
+    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, pruned, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_convolve<float, float>(int, const ConvDesc *, int, int, hipStream_t);
-template hipError_t launch_convolve<double, double>(int, const ConvDesc *, int, int, hipStream_t);
-template hipError_t launch_convolve<double, float>(int, const ConvDesc *, int, int, hipStream_t);
+template hipError_t launch_convolve<float, float>(int, const ConvDesc *, int, int, bool, hipStream_t);
+template hipError_t launch_convolve<double, double>(int, const ConvDesc *, int, int, bool, hipStream_t);
+template hipError_t launch_convolve<double, float>(int, const ConvDesc *, int, int, bool, hipStream_t);
 
 }  // namespace gpf

@@ -192,8 +192,9 @@ int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n 
 // (which must hold zeros, or the values to add to)
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s);
+// pruned: the descriptors restrict the output rows (narrow inverse rows)
 template <class Tin, class T>
-hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, hipStream_t s);
+hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_t s);
 template <class T>
 hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
 template <class T>
