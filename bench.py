@@ -244,6 +244,54 @@ def rk2_leg(gpf, torch, np, ctx, log, wl, steps=40):
     return out
 
 
+def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
+    """64 independent problems of uneven size (n 128..1024, 1e3..1e5 vortices,
+    ellipses): grid points per second batched vs solved one after another."""
+    cases = wl.config4()
+    dev = torch.device("cuda", 0)
+    plans = {}
+    for c in cases:
+        if c.n not in plans:
+            plans[c.n] = gpf.Plan(ctx, c.n, c.dx, flags=gpf.GPF_POLICY_AUTO)
+    bodies, ins, outs, keep = [], [], [], []
+    for c in cases:
+        sf = c.surface
+        bodies.append(gpf.Body(plans[c.n], sf.xs, sf.ys, sf.ds))
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
+        keep.append((X, Y, G))
+        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, gamma_b=c.gamma_b))
+        outs.append(gpf.Outputs(c.n, c.nv, sf.ns))
+    batch = gpf.Batch(ctx, len(cases))
+    pl = [plans[c.n] for c in cases]
+    gp = float(sum(c.n * c.n for c in cases))
+
+    def batched():
+        batch.solve(pl, bodies, ins, [o.struct for o in outs])
+
+    def plain():
+        for p, b, i, o in zip(pl, bodies, ins, outs):
+            gpf.gpf_solve(p, b, i, o.struct)
+
+    res = {"workload": f"{len(cases)} ellipse problems, n in {sorted(plans)}, "
+                       f"nv {min(c.nv for c in cases)}..{max(c.nv for c in cases)}",
+           "grid_points_per_batch": gp}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        res[name] = {"ms_per_batch": 1e3 * el, "grid_points_per_s": gp / el}
+        log(f"[bench] C4 {name}: {1e3 * el:.3f} ms per 64 problems, {gp / el:.3g} GP/s")
+    for o in outs:
+        gpf.gpf_sync(o.status)
+    res["speedup"] = res["batched"]["grid_points_per_s"] / res["plain"]["grid_points_per_s"]
+    return res
+
+
 def timed(run_step, K, plan, gpf, torch, np, with_events=True):
     """K steps between synchronizations; per-step events and kernel events."""
     stream = torch.cuda.current_stream()
@@ -415,6 +463,7 @@ def main() -> int:
     }
     res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
     res["rk2"] = rk2_leg(gpf, torch, np, ctx, log, wl)
+    res["c4"] = c4_leg(gpf, torch, np, ctx, log, wl)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         res["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)

@@ -280,6 +280,24 @@ def make_outputs(psi, u=None, v=None, f=None, ftilde=None, scalars=None, status=
     return out
 
 
+class Outputs:
+    """Device tensors for one solve's outputs (field of the plan's type, FP64
+    velocities, surface strengths and scalars) and their gpf_outputs."""
+
+    def __init__(self, n: int, nv: int, ns: int = 0, fp64: bool = False, device=None):
+        import torch
+        dev = device or torch.device("cuda", 0)
+        self.psi = torch.empty((n, n), dtype=torch.float64 if fp64 else torch.float32, device=dev)
+        self.u = torch.empty(max(nv, 1), dtype=torch.float64, device=dev)
+        self.v = torch.empty_like(self.u)
+        self.f = torch.empty(max(ns, 1), dtype=torch.float64, device=dev) if ns else None
+        self.ft = torch.empty_like(self.f) if ns else None
+        self.scalars = torch.zeros(N_SCALARS, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.struct = make_outputs(self.psi, self.u if nv else None, self.v if nv else None,
+                                   self.f, self.ft, self.scalars, self.status)
+
+
 def gpf_solve(plan: Plan, body: Body | None, inp: gpf_inputs, out: gpf_outputs, stream=None):
     check(lib.gpf_solve(plan.h, None if body is None else body.h, C.byref(inp), C.byref(out),
                         _stream_ptr(stream)), "gpf_solve")

@@ -168,3 +168,54 @@ def test_graph_capture_replays_solve(ctx):
     ref = snapshot(s)
     assert rell2(moved["s"], ref["s"]) <= 1e-6
     assert rell2(moved["s"], eager["s"]) > 1e-4
+
+
+def test_uneven_batch_of_64_matches_alone(ctx):
+    """The 64-problem batch of uneven sizes (n from 128 to 1024, 1e3-1e5
+    vortices, ellipses of random aspect and rotation): one launch sequence
+    per configuration, every problem equal to its own plain solve, and the
+    two smallest problems against the oracle."""
+    cases = wl.config4()
+    dev = torch.device("cuda", 0)
+    plans = {}
+    for c in cases:
+        if c.n not in plans:
+            plans[c.n] = gpf.Plan(ctx, c.n, c.dx, flags=gpf.GPF_POLICY_AUTO)
+    bodies, ins, keep = [], [], []
+    for c in cases:
+        sf = c.surface
+        bodies.append(gpf.Body(plans[c.n], sf.xs, sf.ys, sf.ds))
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
+        keep.append((X, Y, G))
+        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, gamma_b=c.gamma_b))
+    say(f"[C4] {len(cases)} problems, n: {sorted(set(c.n for c in cases))}, "
+        f"FP64 first convolution: {sum(b.info()['conv1_fp64'] for b in bodies)}")
+    alone = []
+    for c, b, inp in zip(cases, bodies, ins):
+        o = gpf.Outputs(c.n, c.nv, c.surface.ns)
+        gpf.gpf_solve(plans[c.n], b, inp, o.struct)
+        gpf.gpf_sync(o.status)
+        alone.append(o)
+    outs = [gpf.Outputs(c.n, c.nv, c.surface.ns) for c in cases]
+    batch = gpf.Batch(ctx, len(cases))
+    batch.solve([plans[c.n] for c in cases], bodies, ins, [o.struct for o in outs])
+    for o in outs:
+        gpf.gpf_sync(o.status)
+    torch.cuda.synchronize()
+    worst = {"s": 0.0, "f": 0.0, "u": 0.0}
+    for c, a, o in zip(cases, alone, outs):
+        es = rell2(o.psi.double().cpu().numpy(), a.psi.double().cpu().numpy())
+        ef = rell2(o.f.cpu().numpy(), a.f.cpu().numpy())
+        eu = rell2(np.r_[o.u.cpu().numpy(), o.v.cpu().numpy()], np.r_[a.u.cpu().numpy(), a.v.cpu().numpy()])
+        worst = {"s": max(worst["s"], es), "f": max(worst["f"], ef), "u": max(worst["u"], eu)}
+    say(f"   batch vs alone, worst relL2: {worst}")
+    assert worst["s"] <= 1e-5 and worst["u"] <= 1e-5 and worst["f"] <= 1e-4
+    # the two smallest problems against the oracle
+    small = sorted(range(len(cases)), key=lambda i: (cases[i].n, cases[i].nv))[:2]
+    for i in small:
+        c, o = cases[i], outs[i]
+        ref = oracle_solve(problem_of(c), body_of(c))
+        es = rell2(o.psi.double().cpu().numpy(), ref.s)
+        ef = rell2(o.f.cpu().numpy(), ref.f)
+        say(f"   {c.name} nv={c.nv} ns={c.surface.ns}: oracle relL2 s {es:.2e} f {ef:.2e}")
+        assert es <= 1e-5 and ef <= 1e-4
