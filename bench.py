@@ -292,6 +292,77 @@ def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
     return res
 
 
+def c5_leg(gpf, torch, np, ctx, log, wl, npool=16, copies=6, nsat=480, nopen=960):
+    """Serving: requests (n 256..2048, up to 1e6 vortices, cylinders with a
+    prescribed circulation and plates with Kutta at both edges) through
+    gpf_server with 32 slots and a 64 GiB budget.  A pool of distinct
+    requests is cycled (each pool entry has `copies` output sets, so requests
+    in flight never share outputs).  Closed loop: saturated throughput mu.
+    Open loop: Poisson arrivals at 0.5 mu and 0.8 mu, latency from submission
+    to observed completion (server clock), p50/p99."""
+    rng = np.random.default_rng(5)
+    pool = [wl.config5_request(rng) for _ in range(npool)]
+    dev = torch.device("cuda", 0)
+    srv = gpf.Server(ctx, 64 << 30, max_slots=32, flags=gpf.GPF_POLICY_AUTO)
+    bodies, plans, ins, keep, outs = {}, [], [], [], []
+    for c in pool:
+        plan = srv.plan(c.n, c.dx)
+        sf = c.surface
+        key = (c.n, sf.kind, sf.ns, round(float(sf.xs[0]), 9), round(float(sf.ys[0]), 9))
+        if key not in bodies:
+            edges = tuple(c.edges) if c.mode == "shed" else ()
+            bodies[key] = gpf.Body(plan, sf.xs, sf.ys, sf.ds, edges)
+        plans.append((plan, bodies[key]))
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
+        keep.append((X, Y, G))
+        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, gamma_b=c.gamma_b,
+                                   znew=c.znew))
+        outs.append([gpf.Outputs(c.n, c.nv, sf.ns) for _ in range(copies)])
+    window = npool * copies
+
+    def run(count, arrivals=None):
+        ids, lats = [], []
+        t0 = time.perf_counter()
+        for i in range(count):
+            if i >= window:
+                lats.append(srv.wait(ids[i - window]))
+            if arrivals is not None:
+                while time.perf_counter() - t0 < arrivals[i]:
+                    pass
+            k = i % npool
+            plan, body = plans[k]
+            ids.append(srv.submit(plan, body, ins[k], outs[k][(i // npool) % copies].struct))
+        for r in ids[max(0, count - window):]:
+            lats.append(srv.wait(r))
+        return time.perf_counter() - t0, np.array(lats)
+
+    run(2 * window)                       # warm-up: plans, workspaces, first launches
+    gp_req = np.mean([c.n * c.n for c in pool])
+    el, _ = run(nsat)
+    mu = nsat / el
+    res = {"workload": f"{npool} distinct requests cycled: n {sorted(set(c.n for c in pool))}, "
+                       f"nv {min(c.nv for c in pool)}..{max(c.nv for c in pool)}, "
+                       f"{sum(c.mode == 'shed' for c in pool)} plates with Kutta x2, "
+                       f"{sum(c.mode == 'circulation' for c in pool)} cylinders",
+           "slots": 32, "saturated_requests_per_s": mu, "saturated_grid_points_per_s": mu * gp_req}
+    log(f"[bench] C5 saturated: {mu:.0f} requests/s, {mu * gp_req:.3g} GP/s")
+    for frac in (0.5, 0.8):
+        lam = frac * mu
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=nopen))
+        el, lats = run(nopen, arr)
+        res[f"load_{frac}"] = {"offered_per_s": lam, "achieved_per_s": nopen / el,
+                               "p50_ms": 1e3 * float(np.percentile(lats, 50)),
+                               "p99_ms": 1e3 * float(np.percentile(lats, 99))}
+        log(f"[bench] C5 at {frac} mu: p50 {res[f'load_{frac}']['p50_ms']:.3f} ms, "
+            f"p99 {res[f'load_{frac}']['p99_ms']:.3f} ms")
+    for o in outs:
+        for x in o:
+            gpf.gpf_sync(x.status)
+    del bodies
+    srv.close()
+    return res
+
+
 def timed(run_step, K, plan, gpf, torch, np, with_events=True):
     """K steps between synchronizations; per-step events and kernel events."""
     stream = torch.cuda.current_stream()
@@ -464,6 +535,7 @@ def main() -> int:
     res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
     res["rk2"] = rk2_leg(gpf, torch, np, ctx, log, wl)
     res["c4"] = c4_leg(gpf, torch, np, ctx, log, wl)
+    res["c5"] = c5_leg(gpf, torch, np, ctx, log, wl)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         res["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)

@@ -65,7 +65,8 @@ typedef enum {
   GPF_E_SINGULAR = -3,     /* singular Schur complement or edge system         */
   GPF_E_NOMEM = -4,        /* device or host allocation failed                 */
   GPF_E_DEVICE = -5,       /* HIP runtime error                                */
-  GPF_E_UNSUPPORTED = -6   /* size or mode not supported                       */
+  GPF_E_UNSUPPORTED = -6,  /* size or mode not supported                       */
+  GPF_E_BUSY = -7          /* serving queue full: retry later                  */
 } gpf_status;
 
 /* bits of the device status word */
@@ -200,6 +201,54 @@ void gpf_batch_destroy(gpf_batch *batch);
 gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
                              const gpf_body *const *bodies, const gpf_inputs *inputs,
                              const gpf_outputs *outputs, void *hip_stream);
+
+/* ---- serving ----------------------------------------------------------- */
+
+/* A request server for independent solves (many callers, mixed grid sizes).
+ * The server owns one resident plan per grid (gpf_server_plan), a HIP
+ * stream, two sets of max_slots problem workspaces and a worker thread.
+ * The worker takes queued requests in arrival order, up to max_slots at a
+ * time, and solves them as one batch (gpf_solve_batched) while the previous
+ * batch may still run on the device; completion is observed with an event
+ * per batch.  Admission: a request is refused with GPF_E_NOMEM when the
+ * server's resident plans plus both workspace sets at the largest grid seen
+ * would exceed hbm_budget_bytes (bodies belong to the caller and are not
+ * counted), and with GPF_E_BUSY when 64 * max_slots requests are already
+ * waiting.  plan_flags (GPF_FP32, GPF_POLICY_AUTO, ...) apply to every
+ * server plan.  max_slots in [1, 256]. */
+typedef struct gpf_server gpf_server;
+gpf_status gpf_server_create(gpf_ctx *ctx, size_t hbm_budget_bytes, int max_slots,
+                             unsigned plan_flags, gpf_server **out);
+
+/* The server's resident plan for *grid (created on first use; owned by the
+ * server, valid until gpf_server_destroy).  Bodies for requests on this
+ * grid are created on it with gpf_body_create. */
+gpf_status gpf_server_plan(gpf_server *srv, const gpf_grid *grid, gpf_plan **out);
+
+/* Queue one solve (as gpf_solve) on the server plan of *grid; body may be
+ * NULL for GPF_NOBODY and must otherwise have been created on that plan.
+ * The inputs and outputs structs are copied; the device buffers they name
+ * must stay valid and untouched until the request is done, and no two
+ * requests in flight may share an output field.  Data-dependent errors go to
+ * the request's d_status as with gpf_solve.  *request_id identifies the
+ * request for gpf_server_poll / gpf_server_wait. */
+gpf_status gpf_server_submit(gpf_server *srv, const gpf_grid *grid, const gpf_body *body,
+                             const gpf_inputs *in, const gpf_outputs *out,
+                             unsigned long long *request_id);
+
+/* *done = 1 once the request's outputs are complete; then *latency_s is the
+ * time from submission to the observed completion (host clock) and the
+ * return value is the request's launch status (GPF_OK or the error that
+ * prevented it).  An unknown or already collected id gives GPF_E_INVALID.
+ * A done request is forgotten after it has been reported. */
+gpf_status gpf_server_poll(gpf_server *srv, unsigned long long request_id, int *done,
+                           double *latency_s);
+
+/* Block until the request is done; as gpf_server_poll otherwise. */
+gpf_status gpf_server_wait(gpf_server *srv, unsigned long long request_id, double *latency_s);
+
+/* Finish every queued request, then free the server and its plans. */
+void gpf_server_destroy(gpf_server *srv);
 
 /* ---- time stepping ------------------------------------------------------ */
 

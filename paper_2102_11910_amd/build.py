@@ -10,14 +10,14 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpf.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.cpp", "lgf_host.cpp", "fft_conv.hip", "transfer.hip", "schur.hip"]
+SOURCES = ["api.cpp", "server.cpp", "lgf_host.cpp", "fft_conv.hip", "transfer.hip", "schur.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay disabled in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I" + os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument",
+    "-I" + os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument", "-pthread",
 ]
 
 
@@ -35,7 +35,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")

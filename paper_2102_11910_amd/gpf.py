@@ -22,8 +22,9 @@ GPF_E_SINGULAR = -3
 GPF_E_NOMEM = -4
 GPF_E_DEVICE = -5
 GPF_E_UNSUPPORTED = -6
+GPF_E_BUSY = -7
 STATUS_NAMES = {0: "GPF_OK", -1: "GPF_E_INVALID", -2: "GPF_E_OUT_OF_GRID", -3: "GPF_E_SINGULAR",
-                -4: "GPF_E_NOMEM", -5: "GPF_E_DEVICE", -6: "GPF_E_UNSUPPORTED"}
+                -4: "GPF_E_NOMEM", -5: "GPF_E_DEVICE", -6: "GPF_E_UNSUPPORTED", -7: "GPF_E_BUSY"}
 
 GPF_DEV_OUT_OF_GRID = 1
 GPF_DEV_SINGULAR = 2
@@ -106,6 +107,13 @@ def _load():
         "gpf_rk2_run": (I, [P, I, P]),
         "gpf_rk2_fields": (I, [P, PP, PP, PP, PP, PP, PP]),
         "gpf_rk2_destroy": (None, [P]),
+        "gpf_server_create": (I, [P, C.c_size_t, I, C.c_uint, PP]),
+        "gpf_server_plan": (I, [P, C.POINTER(gpf_grid), PP]),
+        "gpf_server_submit": (I, [P, C.POINTER(gpf_grid), P, C.POINTER(gpf_inputs),
+                                  C.POINTER(gpf_outputs), C.POINTER(C.c_ulonglong)]),
+        "gpf_server_poll": (I, [P, C.c_ulonglong, C.POINTER(C.c_int), DP]),
+        "gpf_server_wait": (I, [P, C.c_ulonglong, DP]),
+        "gpf_server_destroy": (None, [P]),
         "gpf_sync": (I, [P, P]),
         "gpf_last_error": (C.c_char_p, []),
         "gpf_version": (C.c_char_p, []),
@@ -182,7 +190,7 @@ class Context:
 
 class Plan:
     def __init__(self, ctx: Context, n: int, dx: float, x0: float | None = None,
-                 y0: float | None = None, flags: int = GPF_FP32):
+                 y0: float | None = None, flags: int = GPF_FP32, _handle=None):
         if x0 is None:
             x0 = -(n - 1) * dx / 2.0
         if y0 is None:
@@ -190,9 +198,13 @@ class Plan:
         self.ctx = ctx
         self.n, self.dx, self.x0, self.y0, self.flags = n, dx, x0, y0, flags
         self.fp64 = bool(flags & GPF_FP64)
-        g = gpf_grid(n, dx, x0, y0)
+        self.grid = gpf_grid(n, dx, x0, y0)
+        self.owned = _handle is None
+        if _handle is not None:     # a plan owned by a server
+            self.h = _handle
+            return
         h = C.c_void_p()
-        check(lib.gpf_plan_create(ctx.h, C.byref(g), flags, C.byref(h)), "gpf_plan_create")
+        check(lib.gpf_plan_create(ctx.h, C.byref(self.grid), flags, C.byref(h)), "gpf_plan_create")
         self.h = h
 
     @property
@@ -201,9 +213,9 @@ class Plan:
         return torch.float64 if self.fp64 else torch.float32
 
     def close(self):
-        if self.h:
+        if self.h and self.owned:
             lib.gpf_plan_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -367,6 +379,59 @@ class Batch:
     def close(self):
         if self.h:
             lib.gpf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server (gpf_server_*): resident plans per grid, batches of up
+    to max_slots queued requests solved by a worker thread."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int, flags: int = GPF_POLICY_AUTO):
+        h = C.c_void_p()
+        check(lib.gpf_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), flags, C.byref(h)),
+              "gpf_server_create")
+        self.h, self.ctx, self.flags = h, ctx, flags
+        self._plans = {}
+
+    def plan(self, n: int, dx: float, x0: float | None = None, y0: float | None = None) -> Plan:
+        x0 = -(n - 1) * dx / 2.0 if x0 is None else x0
+        y0 = -(n - 1) * dx / 2.0 if y0 is None else y0
+        key = (n, dx, x0, y0)
+        if key not in self._plans:
+            g = gpf_grid(n, dx, x0, y0)
+            h = C.c_void_p()
+            check(lib.gpf_server_plan(self.h, C.byref(g), C.byref(h)), "gpf_server_plan")
+            self._plans[key] = Plan(self.ctx, n, dx, x0, y0, self.flags, _handle=h)
+        return self._plans[key]
+
+    def submit(self, plan: Plan, body, inp: gpf_inputs, out: gpf_outputs) -> int:
+        rid = C.c_ulonglong()
+        check(lib.gpf_server_submit(self.h, C.byref(plan.grid), None if body is None else body.h,
+                                    C.byref(inp), C.byref(out), C.byref(rid)), "gpf_server_submit")
+        return rid.value
+
+    def poll(self, rid: int):
+        """(done, latency_s or None)"""
+        done, lat = C.c_int(), C.c_double()
+        check(lib.gpf_server_poll(self.h, rid, C.byref(done), C.byref(lat)), "gpf_server_poll")
+        return bool(done.value), (lat.value if done.value else None)
+
+    def wait(self, rid: int) -> float:
+        lat = C.c_double()
+        check(lib.gpf_server_wait(self.h, rid, C.byref(lat)), "gpf_server_wait")
+        return lat.value
+
+    def close(self):
+        if self.h:
+            for p in self._plans.values():
+                p.h = None
+            lib.gpf_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

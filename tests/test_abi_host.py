@@ -36,6 +36,13 @@ def test_null_arguments_rejected_without_device():
     assert gpf.lib.gpf_plan_create(None, None, 0, None) == gpf.GPF_E_INVALID
     assert gpf.lib.gpf_body_info(None, None, None, None) == gpf.GPF_E_INVALID
     assert gpf.lib.gpf_sync(None, None) == gpf.GPF_E_INVALID
+    assert gpf.lib.gpf_server_create(None, 1 << 30, 4, 0, None) == gpf.GPF_E_INVALID
+    assert gpf.lib.gpf_server_plan(None, None, None) == gpf.GPF_E_INVALID
+    assert gpf.lib.gpf_server_submit(None, None, None, None, None, None) == gpf.GPF_E_INVALID
+    done = gpf.C.c_int()
+    assert gpf.lib.gpf_server_poll(None, 1, gpf.C.byref(done), None) == gpf.GPF_E_INVALID
+    assert gpf.lib.gpf_server_wait(None, 1, None) == gpf.GPF_E_INVALID
+    gpf.lib.gpf_server_destroy(None)
 
 
 def test_no_device_reports_device_error():
