@@ -23,7 +23,7 @@
  *   row-major [j][i] (i fastest).  n must be a power of two, 16 <= n <= 2048.
  *   The lattice Green's function G has the gauge G(0,0) = 0.
  *   s is the streamfunction WITHOUT the uniform-flow part
- *   s_inf = U_inf y - V_inf x (add it if the total psi is needed).
+ *   s_inf = U_inf y - V_inf x, unless the plan has GPF_PSI_TOTAL.
  *   Every vortex stencil (plus one node for velocities) and every surface
  *   stencil must lie inside the window: (x - x0)/dx in [2, n-3) for vortices
  *   and new vortices, in [1, n-2) for surface points.
@@ -83,6 +83,13 @@ typedef enum {
                                 bodies whose measured noise amplification
                                 exceeds GPF_AMP_THRESHOLD                    */
 #define GPF_AMP_THRESHOLD 500.0
+#define GPF_PSI_TOTAL   8u   /* store the total streamfunction psi = s + s_inf
+                                (s_inf = U_inf y - V_inf x, Sec. 2.1) instead
+                                of s; velocities are then differenced from
+                                psi and U_inf is not added again.  With FP32
+                                fields psi is rounded at the magnitude of
+                                U_inf y, which costs velocity accuracy
+                                (about ulp(|psi|)/dx); off by default       */
 
 typedef enum {
   GPF_NOBODY = 0,          /* no surface: s = -L^-1 R_v Gamma                  */

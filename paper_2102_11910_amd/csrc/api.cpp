@@ -390,8 +390,20 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   c1.in = pd.w;
   c1.c = p->gauge_c;
   c1.gamma = pd.aux + SC_GAMMA_W;
+  // the final convolution adds s_inf when the plan stores the total psi
+  const bool total = (p->flags & GPF_PSI_TOTAL) != 0;
+  pd.psi_total = total ? 1 : 0;
+  auto set_inf = [&](ConvDesc &cd) {
+    cd.add_inf = total ? 1 : 0;
+    cd.inf_u = in->u_inf;
+    cd.inf_v = in->v_inf;
+    cd.ox = p->grid.x0;
+    cd.oy = p->grid.y0;
+    cd.h = p->grid.dx;
+  };
   if (!cfg.body) {
     // one convolution
+    set_inf(c1);
     c1.X = x2;
     c1.out = out->d_psi;
     c1.spec = spec2;
@@ -437,6 +449,7 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   c2.gamma = pd.aux + SC_GAMMA_SRC2;
   c2.c = p->gauge_c;
   c2.zero_in = 1;   // the last reader of the source: leave it zero
+  set_inf(c2);
 }
 
 template <class TW, class T1, class T2>
@@ -565,7 +578,7 @@ gpf_status gpf_plan_create(gpf_ctx *ctx, const gpf_grid *grid, unsigned flags, g
     return fail(GPF_E_UNSUPPORTED, "gpf_plan_create: n must be a power of two in [16, 2048]");
   if (!(grid->dx > 0.0) || !is_finite(grid->dx) || !is_finite(grid->x0) || !is_finite(grid->y0))
     return fail(GPF_E_INVALID, "gpf_plan_create: dx must be positive and x0, y0 finite");
-  if (flags & ~(GPF_FP64 | GPF_CONV1_FP64 | GPF_POLICY_AUTO))
+  if (flags & ~(GPF_FP64 | GPF_CONV1_FP64 | GPF_POLICY_AUTO | GPF_PSI_TOTAL))
     return fail(GPF_E_INVALID, "gpf_plan_create: unknown flag");
   GPF_HIP(hipSetDevice(ctx->device));
   std::unique_ptr<gpf_plan> p(new gpf_plan);

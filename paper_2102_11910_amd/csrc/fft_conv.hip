@@ -453,7 +453,21 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const C
   V x[kE];
   fft_seq<T, N, true, false, true, false, true>(x, lds + q * P::LDS_SEQ, wr, tw, lane);
   const T shift = (T)(C.c * (C.gamma ? C.gamma[0] : C.gamma_val));
-  const size_t row = (size_t)(j0 + 2 * q) * n;
+  const int j = j0 + 2 * q;
+  const size_t row = (size_t)j * n;
+  if (C.add_inf) {
+    // total psi: + U_inf y - V_inf x, added in FP64 before the one rounding
+    const double ya = C.inf_u * (C.oy + j * C.h), yb = C.inf_u * (C.oy + (j + 1) * C.h);
+    const double sh = C.c * (C.gamma ? C.gamma[0] : C.gamma_val);
+#pragma unroll
+    for (int k = 0; k < kE / 2; ++k) {
+      const int i = lane + k * P::TPS;
+      const double xi = C.inf_v * (C.ox + i * C.h);
+      s[row + i] = (T)((double)x[k].x - sh + (ya - xi));
+      s[row + n + i] = (T)((double)x[k].y - sh + (yb - xi));
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < kE / 2; ++k) {
     s[row + lane + k * P::TPS] = x[k].x - shift;

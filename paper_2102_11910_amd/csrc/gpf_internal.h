@@ -141,6 +141,8 @@ struct ConvDesc {
   double c;            // gauge shift of the spectrum
   int zero_in;
   int row_lo, row_hi;  // rows of `out` that are needed (inclusive)
+  int add_inf;         // add s_inf = inf_u (oy + j h) - inf_v (ox + i h) to the output
+  double inf_u, inf_v, ox, oy, h;
 };
 
 struct ProbDesc {
@@ -175,6 +177,7 @@ struct ProbDesc {
   // outputs (nullable)
   const void *psi;              // final field (velocities read it)
   double *u, *v, *f_out, *ft_out, *sc_out;
+  int psi_total;                // psi holds s + s_inf: velocities add no U_inf
   SolveScalars sv;
 };
 

@@ -383,8 +383,9 @@ __global__ __launch_bounds__(256) void k_vortex_velocity(const ProbDesc *__restr
     vacc += wy[b] * vr;
   }
   const double h = 0.5 / P.dx;
-  P.u[q] = uacc * h + P.sv.u_inf;
-  P.v[q] = -vacc * h + P.sv.v_inf;
+  const double ui = P.psi_total ? 0.0 : P.sv.u_inf, vi = P.psi_total ? 0.0 : P.sv.v_inf;
+  P.u[q] = uacc * h + ui;
+  P.v[q] = -vacc * h + vi;
 }
 
 __global__ void k_axpy2(int nv, const double *__restrict__ x, const double *__restrict__ y,

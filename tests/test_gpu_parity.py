@@ -236,6 +236,25 @@ def test_config2_full_parity(ctx, flags):
 # edge cases and error paths
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("mode,surface", [("circulation", "cylinder"), ("none", None)])
+def test_total_streamfunction_flag(ctx, mode, surface):
+    """GPF_PSI_TOTAL stores psi = s + U_inf y - V_inf x (Sec. 2.1) and
+    differences it for the velocities: equal to the oracle's s plus the
+    uniform-flow field, velocities within the FP32 rounding of psi."""
+    case = wl.random_case(61, 128, 2.0 / 128, 300, surface=surface, mode=mode)
+    got = run_solve(ctx, case, gpf.GPF_FP32 | gpf.GPF_PSI_TOTAL)
+    ref = oracle_solve(problem_of(case), body_of(case))
+    g = grid_of(case)
+    xs = g.x0 + g.dx * np.arange(case.n)
+    ys = g.y0 + g.dx * np.arange(case.n)
+    sinf = case.u_inf * ys[:, None] - case.v_inf * xs[None, :]
+    es = rell2(got["s"], ref.s + sinf)
+    eu = rell2(np.r_[got["u"], got["v"]], np.r_[ref.u, ref.v])
+    say(f"[psi total] {mode}: psi {es:.2e}, uv {eu:.2e}")
+    assert es <= 1e-6
+    assert eu <= 1e-4
+
+
 def test_empty_vortex_set(ctx):
     case = wl.random_case(5, 64, 2.0 / 64, 0, surface="cylinder")
     case.X = case.Y = case.G = np.zeros(0)
