@@ -210,7 +210,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__r
     // circulation: the partials summed in a fixed order (strided per
     // thread, then waves), so every solve gives the same bits
     double g = 0.0;
-    for (int b = tid; b < (int)gridDim.x; b += kScatterBlock) g += P.partials[b];
+    const int nvb = (P.nv + kScatterBlock - 1) / kScatterBlock;   // workgroups of bin_count
+    for (int b = tid; b < nvb; b += kScatterBlock) g += P.partials[b];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off);
     if (lane == 0) gsum[wave] = g;
@@ -222,16 +223,18 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__r
     P.aux[SC_GAMMA_W] = g;
     if (P.sc_out) P.sc_out[SC_GAMMA_W] = g;
   }
-  const int q = blockIdx.x * kScatterBlock + tid;
-  if (q >= P.nv) return;
-  const int r = P.rank[q];
-  if (r < 0) return;
-  const double xi = (P.xv[q] - P.x0) / P.dx, eta = (P.yv[q] - P.y0) / P.dx;
-  const int t = vortex_tile((int)floor(xi) - 1, (int)floor(eta) - 1, ts, tps);
-  double *o = P.sorted + 3 * (size_t)(start[t] + r);
-  o[0] = xi;
-  o[1] = eta;
-  o[2] = P.gv[q] / (P.dx * P.dx);
+  // several vortices per thread when there are many (every workgroup
+  // repeats the scan above)
+  for (int q = blockIdx.x * kScatterBlock + tid; q < P.nv; q += gridDim.x * kScatterBlock) {
+    const int r = P.rank[q];
+    if (r < 0) continue;
+    const double xi = (P.xv[q] - P.x0) / P.dx, eta = (P.yv[q] - P.y0) / P.dx;
+    const int t = vortex_tile((int)floor(xi) - 1, (int)floor(eta) - 1, ts, tps);
+    double *o = P.sorted + 3 * (size_t)(start[t] + r);
+    o[0] = xi;
+    o[1] = eta;
+    o[2] = P.gv[q] / (P.dx * P.dx);
+  }
 }
 
 // 3. workgroups take the non-empty tiles in turn: the tile's vortices add their 4 x 4
@@ -426,7 +429,8 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   timer_begin(GPF_TK_SCATTER, s);
   const int vb = scatter_blocks(nv_max);
   hipLaunchKernelGGL(k_bin_count, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
-  hipLaunchKernelGGL(k_bin_place, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
+  const int pb = std::max(std::min(vb, 64), (vb + 7) / 8);
+  hipLaunchKernelGGL(k_bin_place, dim3(pb, nb), dim3(kScatterBlock), 0, s, d);
   // about one workgroup per 64 vortices, looping over the non-empty tiles
   const int tb = std::max(1, std::min(bin_tiles(n), (nv_max + 63) / 64));
   hipLaunchKernelGGL((k_tile_scatter<T>), dim3(tb, nb), dim3(kTileBlock), 0, s, d);
