@@ -30,13 +30,16 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "grid points solved/sec (R -> L^-1 -> E) at FP32 vs plain; p50/p99 latency"
 
 
-def kernel_bytes(n: int, nv: int, ns: int, m: int, w_fp64: bool) -> dict:
+def kernel_bytes(n: int, nv: int, ns: int, m: int, w_fp64: bool, keep: float = 1.0) -> dict:
     """Algorithmic HBM bytes per launch of each kernel class.
 
     Convolution passes move their input and output once: pass 1 reads the
     n x n source and writes the n x (n+1) half spectrum; pass 2 reads and
     writes it and reads the (n+1)^2 real spectrum; pass 3 reads it and
-    writes the n x n field.  FP32 complex = 8 B, FP64 complex = 16 B.
+    writes the n x n field.  FP32 complex = 8 B, FP64 complex = 16 B.  The
+    first (FP64) convolution feeds only the surface stencils: its column
+    pass writes, and its last pass reads and writes, the fraction `keep` of
+    the rows.
     """
     win = 8 if w_fp64 else 4
     return {
@@ -45,11 +48,23 @@ def kernel_bytes(n: int, nv: int, ns: int, m: int, w_fp64: bool) -> dict:
         "cols": 16 * n * (n + 1) + 4 * (n + 1) ** 2,
         "rows_inv": 8 * n * (n + 1) + 4 * n * n,
         "rows_fwd64": 8 * n * n + 16 * n * (n + 1),
-        "cols64": 32 * n * (n + 1) + 8 * (n + 1) ** 2,
-        "rows_inv64": 16 * n * (n + 1) + 8 * n * n,
+        "cols64": 16 * n * (n + 1) * (1 + keep) + 8 * (n + 1) ** 2,
+        "rows_inv64": keep * (16 * n * (n + 1) + 8 * n * n),
         "surface": 8 * ns * ns + 8 * ns * (4 + 3 * (1 + m)),
         "velocity": 24 * nv + 16 * nv,
     }
+
+
+def kept_rows(case) -> float:
+    """Fraction of grid rows the first convolution keeps: the rows of the
+    surface stencils (base row floor(eta) - 1 to + 3), widened to whole
+    16-row groups."""
+    import numpy as np
+    eta = (np.asarray(case.surface.ys, np.float64) - case.x0) / case.dx
+    lo = int(np.floor(eta).min()) - 1
+    hi = int(np.floor(eta).max()) + 2
+    lo, hi = lo & ~15, min(case.n - 1, hi | 15)
+    return (hi - lo + 1) / case.n
 
 
 # kernel class -> (source file, kernel-name prefixes in a profiler trace)
@@ -483,7 +498,8 @@ def main() -> int:
     value_plain = n * n * Kp / wall_p
     m = len(case.znew)
     nv_mean = int(np.mean([c.nv for c in cases]))
-    kb1 = kernel_bytes(n, nv_mean, case.surface.ns, m, info["conv1_fp64"])
+    keep = kept_rows(case)
+    kb1 = kernel_bytes(n, nv_mean, case.surface.ns, m, info["conv1_fp64"], keep)
     per_kernel = {}
     for name, (cnt, ms) in kt.items():
         if cnt:
@@ -495,7 +511,7 @@ def main() -> int:
     achieved = d["GBps"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom), "bytes_per_launch": B * kb1[dom],
+                "traffic": measured_traffic(dom), "bytes_per_launch": int(B * kb1[dom]),
                 "avg_us": round(d["avg_us"], 3)}
     log("[bench] kernels (batched): " + json.dumps(
         {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_kernel.items()}))

@@ -402,8 +402,16 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
   }
   fft_seq<T, N, true, false, true, true, true>(x, L, wr, tw, lane);
   if (c0 + q <= n) {
+    // only the rows the last pass reads: all, unless the first convolution
+    // feeds the surface stencils alone.  The last pass transforms rows in
+    // pairs inside 16-row-aligned workgroups, and an unwritten (stale) partner
+    // row would add its rounding noise, so whole 16-row groups are kept.
+    const int lo = C.row_lo & ~15, hi = C.row_hi | 15;
 #pragma unroll
-    for (int k = 0; k < kE / 2; ++k) col[lane + k * P::TPS] = x[k];
+    for (int k = 0; k < kE / 2; ++k) {
+      const int j = lane + k * P::TPS;
+      if (j >= lo && j <= hi) col[j] = x[k];
+    }
   }
 }
 
