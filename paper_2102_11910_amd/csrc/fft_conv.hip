@@ -437,10 +437,21 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const C
   if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, tid % P::TPS);
 
   // Z[k] = A[k] + i B[k], Z[N-k] = conj(A[k]) + i conj(B[k]); the imaginary
-  // parts of A and B at k = 0 and k = n are dropped (real rows).
-  for (int idx = tid; idx < (n + 1) * P::SEQ; idx += P::WGT) {
+  // parts of A and B at k = 0 and k = n are dropped (real rows).  Every
+  // load of a thread is issued before any is unpacked.
+  constexpr int ITEMS = (n + 1) * P::SEQ, ITER = (ITEMS + P::WGT - 1) / P::WGT;
+  V2 abv[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int idx = min(tid + it * P::WGT, ITEMS - 1);
+    abv[it] = *reinterpret_cast<const V2 *>(X + (size_t)(idx / P::SEQ) * n + j0 + 2 * (idx % P::SEQ));
+  }
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int idx = tid + it * P::WGT;
+    if (idx >= ITEMS) break;
     const int k = idx / P::SEQ, q = idx % P::SEQ;
-    const V2 ab = *reinterpret_cast<const V2 *>(X + (size_t)k * n + j0 + 2 * q);
+    const V2 ab = abv[it];
     V *L = lds + q * P::LDS_SEQ;
     V z;
     if (k == 0 || k == n) {
