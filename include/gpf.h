@@ -39,7 +39,7 @@
  *   Solves enqueue all device work on the caller's HIP stream and return;
  *   buffers must stay valid until that stream has completed.  A plan's
  *   workspace serves one stream at a time: concurrent solves on one plan
- *   race.
+ *   race, unless the plan has GPF_PLAN_MULTISTREAM.
  *
  * Errors
  *   Every call returns a gpf_status.  Synchronous errors (bad arguments,
@@ -83,6 +83,11 @@ typedef enum {
                                 bodies whose measured noise amplification
                                 exceeds GPF_AMP_THRESHOLD                    */
 #define GPF_AMP_THRESHOLD 500.0
+#define GPF_PLAN_MULTISTREAM 16u /* gpf_solve keeps one workspace (and
+                                descriptor ring) per HIP stream, so solves on
+                                different streams may share the plan; the
+                                building blocks, time stepping and kernel
+                                timing still serve one stream at a time    */
 #define GPF_PSI_TOTAL   8u   /* store the total streamfunction psi = s + s_inf
                                 (s_inf = U_inf y - V_inf x, Sec. 2.1) instead
                                 of s; velocities are then differenced from

@@ -578,7 +578,7 @@ gpf_status gpf_plan_create(gpf_ctx *ctx, const gpf_grid *grid, unsigned flags, g
     return fail(GPF_E_UNSUPPORTED, "gpf_plan_create: n must be a power of two in [16, 2048]");
   if (!(grid->dx > 0.0) || !is_finite(grid->dx) || !is_finite(grid->x0) || !is_finite(grid->y0))
     return fail(GPF_E_INVALID, "gpf_plan_create: dx must be positive and x0, y0 finite");
-  if (flags & ~(GPF_FP64 | GPF_CONV1_FP64 | GPF_POLICY_AUTO | GPF_PSI_TOTAL))
+  if (flags & ~(GPF_FP64 | GPF_CONV1_FP64 | GPF_POLICY_AUTO | GPF_PSI_TOTAL | GPF_PLAN_MULTISTREAM))
     return fail(GPF_E_INVALID, "gpf_plan_create: unknown flag");
   GPF_HIP(hipSetDevice(ctx->device));
   std::unique_ptr<gpf_plan> p(new gpf_plan);
@@ -841,18 +841,43 @@ gpf_status gpf_vortex_velocity(gpf_plan *plan, const void *d_s, int nv, const do
 // solves
 // ---------------------------------------------------------------------------
 
+gpf_status gpf_plan::slot_for(hipStream_t s, gpf_stream_slot **out) {
+  std::lock_guard<std::mutex> lk(slots_mu);
+  for (auto &sl : slots)
+    if (sl->stream == s) {
+      *out = sl.get();
+      return GPF_OK;
+    }
+  std::unique_ptr<gpf_stream_slot> sl(new gpf_stream_slot);
+  sl->stream = s;
+  GPF_TRY(sl->ring.init(kPlanRingSlots, kProblemDescBytes));
+  *out = sl.get();
+  slots.push_back(std::move(sl));
+  return GPF_OK;
+}
+
 gpf_status gpf_solve(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
                      const gpf_outputs *out, void *hip_stream) {
   GPF_TRY(validate(plan, body, in, out));
   hipError_t e = hipSetDevice(plan->ctx->device);
   if (e != hipSuccess) return fail(GPF_E_DEVICE, hipGetErrorString(e));
   hipStream_t s = as_stream(hip_stream);
-  TimerScope scope(plan->timing ? &plan->timer : nullptr);
-  GPF_TRY(plan->ws.ensure_vortices(in->nv));
-  ProblemRef r{plan, in->mode == GPF_NOBODY ? nullptr : body, in, out, &plan->ws};
+  gpf_workspace *ws = &plan->ws;
+  DescRing *ring = &plan->ring;
+  if (plan->flags & GPF_PLAN_MULTISTREAM) {
+    gpf_stream_slot *sl = nullptr;
+    GPF_TRY(plan->slot_for(s, &sl));
+    ws = &sl->ws;
+    ring = &sl->ring;
+  }
+  ProblemRef r{plan, in->mode == GPF_NOBODY ? nullptr : body, in, out, ws};
   const GroupCfg cfg = config_of(r);
+  GPF_TRY(ws->ensure(cfg.n, !cfg.fp64_plan, cfg.fp64_plan || cfg.conv1_fp64,
+                     r.body ? r.body->ns : 0));
+  GPF_TRY(ws->ensure_vortices(in->nv));
+  TimerScope scope(plan->timing && ws == &plan->ws ? &plan->timer : nullptr);
   std::vector<ProblemRef> one{r};
-  return run_group(cfg, one, plan->ring, plan->ctx->xcds, s);
+  return run_group(cfg, one, *ring, plan->ctx->xcds, s);
 }
 
 gpf_status gpf_batch_create(gpf_ctx *ctx, int max_problems, gpf_batch **out) {

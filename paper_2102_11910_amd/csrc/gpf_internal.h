@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -245,6 +247,13 @@ struct gpf_workspace {
   gpf_status ensure_vortices(int nv);
 };
 
+// workspace and descriptor ring of one stream (GPF_PLAN_MULTISTREAM)
+struct gpf_stream_slot {
+  hipStream_t stream = nullptr;
+  gpf_workspace ws;
+  gpf::DescRing ring;
+};
+
 struct gpf_plan {
   gpf_ctx *ctx = nullptr;
   gpf_grid grid{};
@@ -259,7 +268,10 @@ struct gpf_plan {
   gpf::DescRing ring;         // descriptors of plain solves
   gpf::KernelTimer timer;
   bool timing = false;
+  std::mutex slots_mu;
+  std::vector<std::unique_ptr<gpf_stream_slot>> slots;   // GPF_PLAN_MULTISTREAM
   gpf_status ensure_fp64();
+  gpf_status slot_for(hipStream_t s, gpf_stream_slot **out);
 };
 
 struct gpf_body {

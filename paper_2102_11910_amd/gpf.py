@@ -34,6 +34,7 @@ GPF_FP64 = 1
 GPF_CONV1_FP64 = 2
 GPF_POLICY_AUTO = 4
 GPF_PSI_TOTAL = 8
+GPF_PLAN_MULTISTREAM = 16
 
 TK_NAMES = ["scatter", "rows_fwd", "cols", "rows_inv", "rows_fwd64", "cols64", "rows_inv64",
             "surface", "velocity"]

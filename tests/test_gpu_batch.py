@@ -219,3 +219,37 @@ def test_uneven_batch_of_64_matches_alone(ctx):
         ef = rell2(o.f.cpu().numpy(), ref.f)
         say(f"   {c.name} nv={c.nv} ns={c.surface.ns}: oracle relL2 s {es:.2e} f {ef:.2e}")
         assert es <= 1e-5 and ef <= 1e-4
+
+
+def test_plan_shared_by_two_streams(ctx):
+    """GPF_PLAN_MULTISTREAM: solves on two streams share one plan, each with
+    its own workspace, and equal sequential solves on a plain plan."""
+    cases = [wl.random_case(71, 128, 2.0 / 128, 400, surface="cylinder"),
+             wl.random_case(72, 128, 2.0 / 128, 300, surface="ellipse")]
+    dev = torch.device("cuda", 0)
+    shared = gpf.Plan(ctx, 128, 2.0 / 128, flags=gpf.GPF_POLICY_AUTO | gpf.GPF_PLAN_MULTISTREAM)
+    alone = gpf.Plan(ctx, 128, 2.0 / 128, flags=gpf.GPF_POLICY_AUTO)
+    runs = []
+    for c in cases:
+        sf = c.surface
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
+        inp = gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, c.ub, c.vb, c.omega, c.mode, c.gamma_b)
+        runs.append(dict(inp=inp, keep=(X, Y, G),
+                         b_shared=gpf.Body(shared, sf.xs, sf.ys, sf.ds),
+                         b_alone=gpf.Body(alone, sf.xs, sf.ys, sf.ds),
+                         o=gpf.Outputs(c.n, c.nv, sf.ns), ref=gpf.Outputs(c.n, c.nv, sf.ns)))
+    for r in runs:
+        gpf.gpf_solve(alone, r["b_alone"], r["inp"], r["ref"].struct)
+        gpf.gpf_sync(r["ref"].status)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        for r, st in zip(runs, streams):
+            gpf.gpf_solve(shared, r["b_shared"], r["inp"], r["o"].struct, stream=st)
+        for st in streams:
+            st.synchronize()
+        for i, r in enumerate(runs):
+            es = rell2(r["o"].psi.double().cpu().numpy(), r["ref"].psi.double().cpu().numpy())
+            ef = rell2(r["o"].f.cpu().numpy(), r["ref"].f.cpu().numpy())
+            say(f"[two streams rep {rep}] problem {i}: s {es:.1e} f {ef:.1e}")
+            assert es <= 1e-5 and ef <= 1e-4
