@@ -118,9 +118,8 @@ enum ScalarSlot {
   SC_GAMMA_B = 3,
   SC_GAMMA_NEW = 4,   // .. 4 + GPF_MAX_EDGES
   SC_COUNT = 4 + GPF_MAX_EDGES,
-  SC_USER = SC_COUNT,  // gamma_src of a building-block convolution
-  AUX_DOUBLES = 32,    // counters follow the doubles
-  AUX_BYTES = AUX_DOUBLES * 8 + 64
+  AUX_DOUBLES = 32,
+  AUX_BYTES = AUX_DOUBLES * 8
 };
 
 struct SolveScalars {
@@ -158,7 +157,7 @@ struct ProbDesc {
   // fields
   void *w;                      // source field (zero on entry, or the values R_v adds to)
   const void *s1;               // result of the first convolution
-  // per-problem aux: scalars, partial sums, counters
+  // per-problem aux: scalars and partial sums
   double *aux;
   double *partials;
   unsigned *status;
@@ -182,10 +181,6 @@ struct ProbDesc {
   int psi_total;                // psi holds s + s_inf: velocities add no U_inf
   SolveScalars sv;
 };
-
-__host__ __device__ inline unsigned *aux_counter(double *aux, int k) {
-  return reinterpret_cast<unsigned *>(aux + AUX_DOUBLES) + k;
-}
 
 // ---------------------------------------------------------------------------
 // kernel launchers (asynchronous on `s`; `nb` problems, same n)

@@ -255,6 +255,18 @@ def test_total_streamfunction_flag(ctx, mode, surface):
     assert eu <= 1e-4
 
 
+@pytest.mark.parametrize("flags", [gpf.GPF_FP64, gpf.GPF_POLICY_AUTO])
+def test_shedding_at_one_edge(ctx, flags):
+    """Kutta condition with one new vortex at the trailing edge only (the
+    m-edge system with m = 1, Sec. 2.4.2)."""
+    case = wl.random_case(81, 128, 2.0 / 128, 250, surface="plate", mode="shed")
+    case.edges = (case.surface.edges[1],)
+    case.znew = (case.znew[1],)
+    got = run_solve(ctx, case, flags)
+    ref = oracle_solve(problem_of(case), body_of(case))
+    compare(case, got, ref, flags == gpf.GPF_FP64, f"shed at one edge, flags={flags}")
+
+
 def test_empty_vortex_set(ctx):
     case = wl.random_case(5, 64, 2.0 / 64, 0, surface="cylinder")
     case.X = case.Y = case.G = np.zeros(0)
