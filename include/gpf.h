@@ -200,6 +200,14 @@ gpf_status gpf_solve(gpf_plan *plan, const gpf_body *body,
 gpf_status gpf_batch_create(gpf_ctx *ctx, int max_problems, gpf_batch **out);
 void gpf_batch_destroy(gpf_batch *batch);
 
+/* Split each configuration group of a batch over `lanes` (1..4) internal
+ * streams: the caller's stream is forked to them with an event before the
+ * solve and joined after it, so that the latency-bound kernels of one part
+ * overlap the bandwidth-bound passes of another.  Results are unchanged;
+ * lanes = 1 (the default) runs everything on the caller's stream.  The
+ * fork and join are events, so a captured graph records them. */
+gpf_status gpf_batch_set_lanes(gpf_batch *batch, int lanes);
+
 /* Solve nprob independent problems (each as in gpf_solve; bodies may be
  * NULL or hold NULL for GPF_NOBODY problems).  Problems are grouped by grid
  * size and precision; each group runs as one launch sequence whose kernels

@@ -293,6 +293,11 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
 }
 
 gpf_batch::~gpf_batch() {
+  for (int l = 0; l < kMaxLanes; ++l) {
+    if (lane_stream[l]) (void)hipStreamDestroy(lane_stream[l]);
+    if (join_ev[l]) (void)hipEventDestroy(join_ev[l]);
+  }
+  if (fork_ev) (void)hipEventDestroy(fork_ev);
   for (auto *w : ws) delete w;
 }
 
@@ -897,6 +902,21 @@ gpf_status gpf_batch_create(gpf_ctx *ctx, int max_problems, gpf_batch **out) {
 
 void gpf_batch_destroy(gpf_batch *batch) { delete batch; }
 
+gpf_status gpf_batch_set_lanes(gpf_batch *batch, int lanes) {
+  if (!batch || lanes < 1 || lanes > gpf_batch::kMaxLanes)
+    return fail(GPF_E_INVALID, "gpf_batch_set_lanes: lanes must be in [1, 4]");
+  GPF_HIP(hipSetDevice(batch->ctx->device));
+  if (lanes > 1 && !batch->fork_ev)
+    GPF_HIP(hipEventCreateWithFlags(&batch->fork_ev, hipEventDisableTiming));
+  for (int l = 0; l < lanes && lanes > 1; ++l) {
+    if (!batch->lane_stream[l])
+      GPF_HIP(hipStreamCreateWithFlags(&batch->lane_stream[l], hipStreamNonBlocking));
+    if (!batch->join_ev[l]) GPF_HIP(hipEventCreateWithFlags(&batch->join_ev[l], hipEventDisableTiming));
+  }
+  batch->lanes = lanes;
+  return GPF_OK;
+}
+
 gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
                              const gpf_body *const *bodies, const gpf_inputs *inputs,
                              const gpf_outputs *outputs, void *hip_stream) {
@@ -925,7 +945,13 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
   if (nprob == 0) return GPF_OK;
   hipStream_t s = as_stream(hip_stream);
   TimerScope scope(plans[0]->timing ? &plans[0]->timer : nullptr);
-  // group by configuration, keeping the first-seen order of the groups
+  const int lanes = std::min(batch->lanes, nprob);
+  if (lanes > 1) {
+    GPF_HIP(hipEventRecord(batch->fork_ev, s));
+    for (int l = 0; l < lanes; ++l) GPF_HIP(hipStreamWaitEvent(batch->lane_stream[l], batch->fork_ev, 0));
+  }
+  // group by configuration, keeping the first-seen order of the groups;
+  // with lanes, the members of each group are dealt out over the lanes
   std::vector<char> done(nprob, 0);
   for (int i = 0; i < nprob; ++i) {
     if (done[i]) continue;
@@ -936,7 +962,23 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
         grp.push_back(refs[k]);
         done[k] = 1;
       }
-    GPF_TRY(run_group(cfg, grp, batch->ring, batch->ctx->xcds, s));
+    if (lanes == 1) {
+      GPF_TRY(run_group(cfg, grp, batch->ring, batch->ctx->xcds, s));
+      continue;
+    }
+    const int per = ((int)grp.size() + lanes - 1) / lanes;
+    for (int l = 0; l < lanes; ++l) {
+      const int a = l * per, b = std::min((int)grp.size(), a + per);
+      if (a >= b) break;
+      std::vector<ProblemRef> part(grp.begin() + a, grp.begin() + b);
+      GPF_TRY(run_group(cfg, part, batch->ring, batch->ctx->xcds, batch->lane_stream[l]));
+    }
+  }
+  if (lanes > 1) {
+    for (int l = 0; l < lanes; ++l) {
+      GPF_HIP(hipEventRecord(batch->join_ev[l], batch->lane_stream[l]));
+      GPF_HIP(hipStreamWaitEvent(s, batch->join_ev[l], 0));
+    }
   }
   return GPF_OK;
 }

@@ -287,10 +287,16 @@ struct gpf_body {
 };
 
 struct gpf_batch {
+  static constexpr int kMaxLanes = 4;
   gpf_ctx *ctx = nullptr;
   int max_problems = 0;
   std::vector<gpf_workspace *> ws;
   gpf::DescRing ring;
+  // lanes > 1: the batch is split over that many internal streams, forked
+  // from and joined to the caller's stream with events
+  int lanes = 1;
+  hipStream_t lane_stream[kMaxLanes] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
   ~gpf_batch();
 };
 

@@ -103,6 +103,7 @@ def _load():
         "gpf_timing_read": (I, [P, I, C.POINTER(C.c_longlong), DP]),
         "gpf_batch_create": (I, [P, I, PP]),
         "gpf_batch_destroy": (None, [P]),
+        "gpf_batch_set_lanes": (I, [P, I]),
         "gpf_solve_batched": (I, [P, I, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                   C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
         "gpf_rk2_create": (I, [P, P, C.POINTER(gpf_inputs), P, P, D, I, PP]),
@@ -362,12 +363,15 @@ def gpf_vortex_velocity(plan: Plan, s, X, Y, u_inf, v_inf, u, v, status=None, st
 class Batch:
     """Workspaces for up to max_problems problems solved in shared launches."""
 
-    def __init__(self, ctx: Context, max_problems: int):
+    def __init__(self, ctx: Context, max_problems: int, lanes: int = 1):
         h = C.c_void_p()
         check(lib.gpf_batch_create(ctx.h, max_problems, C.byref(h)), "gpf_batch_create")
         self.h = h
         self.ctx = ctx
         self.max_problems = max_problems
+        if lanes != 1:
+            check(lib.gpf_batch_set_lanes(h, int(lanes)), "gpf_batch_set_lanes")
+        self.lanes = lanes
 
     def solve(self, plans, bodies, inputs, outputs, stream=None):
         k = len(plans)

@@ -253,3 +253,30 @@ def test_plan_shared_by_two_streams(ctx):
             ef = rell2(r["o"].f.cpu().numpy(), r["ref"].f.cpu().numpy())
             say(f"[two streams rep {rep}] problem {i}: s {es:.1e} f {ef:.1e}")
             assert es <= 1e-5 and ef <= 1e-4
+
+
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_batch_lanes_equal_one_lane(ctx, lanes):
+    """A batch split over internal streams (gpf_batch_set_lanes) gives the
+    results of the single-stream batch."""
+    cases = mixed_cases() + [wl.config1(seed=21), wl.random_case(36, 64, 2.0 / 64, 77, surface="cylinder")]
+    solvers = [solver_for(ctx, c) for c in cases]
+    uploads = [s.upload(c) for s, c in zip(solvers, cases)]
+    inputs = [s.inputs_for(c, *u) for s, c, u in zip(solvers, cases, uploads)]
+    res = {}
+    for ln in (1, lanes):
+        batch = gpf.Batch(ctx, len(cases), lanes=ln)
+        for rep in range(2):
+            for s in solvers:
+                s.psi.fill_(float("nan"))
+            outs = [s.outputs(int(u[0].numel())) for s, u in zip(solvers, uploads)]
+            batch.solve([s.plan for s in solvers], [s.body for s in solvers], inputs, outs)
+            for s in solvers:
+                gpf.gpf_sync(s.status)
+        res[ln] = [snapshot(s) for s in solvers]
+    worst = 0.0
+    for a, b in zip(res[1], res[lanes]):
+        for k in a:
+            worst = max(worst, rell2(b[k], a[k]) if np.any(a[k]) else float(np.max(np.abs(b[k]))))
+    say(f"[lanes {lanes}] worst relL2 against one lane: {worst:.2e}")
+    assert worst <= 1e-5
