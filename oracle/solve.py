@@ -26,6 +26,14 @@ Modes
       sum_j (1 + fhat0 . P_{k_i} f~_j) Gamma_j = -(Gamma_w + fhat0 . P_{k_i} f~*)
                                                           (eq. twovortex, any m)
       x = f~* + sum_j Gamma_j f~_j,  s0 = mean_i x_{k_i},  f~ = x - s0 1
+      With edge bounds (Sec. 2.5, generalized edge condition; bounds on the
+      non-singular sheet f~ at each edge, Kutta = both bounds zero): edge i
+      is active when f~*_{k_i} lies outside [fmin_i, fmax_i], with target the
+      violated bound t_i; inactive edges shed nothing (Gamma_i = 0).  The
+      active rows read (eq. twovortex-gen)
+      sum_j (1 + fhat0 . P_{k_i} f~_j) Gamma_j = -(Gamma_w + fhat0 . P_{k_i} f~* + Gamma0 t_i)
+      and s0 = mean over active i of (x_{k_i} - t_i); with no active edge,
+      Kelvin's theorem alone gives s0 = (fhat0 . f~* + Gamma_w)/Gamma0.
 * ``none``         no body: s = s*.
 
 E_s s* here equals -E_s L^-1 w of the paper's formulas.
@@ -60,6 +68,7 @@ class Problem:
     edges: tuple = ()             # kutta: (k,), shed: (k_1..k_m)
     znew: tuple = ()              # shed: new vortex positions [(x, y), ...]
     gamma_w: float | None = None  # shed: circulation of existing vorticity
+    fbounds: tuple = ()           # shed: ((fmin, fmax), ...) per edge; () = Kutta (0, 0)
 
 
 @dataclass
@@ -138,15 +147,35 @@ def solve(p: Problem, body: Body | None = None, table=None) -> Result:
         ft_star = body.solve_tilde(body.remove_circulation(sb) - Es_star)
         ft_j = np.stack([body.solve_tilde(surface_response_to_vortex(grid, body, z, table))
                          for z in p.znew], axis=1)                     # Ns x m
-        A = np.empty((m, m))
-        rhs = np.empty(m)
+        bounds = list(p.fbounds) if p.fbounds else [(0.0, 0.0)] * m
+        assert len(bounds) == m
+        # active edges and their targets (the violated bound)
+        active, target = [], []
         for i, k in enumerate(edges):
-            # fhat0 . P_k x = fhat0 . x - Gamma0 x_k
-            A[i, :] = 1.0 + body.fhat0 @ ft_j - body.gamma0 * ft_j[k, :]
-            rhs[i] = -(gamma_w + body.fhat0 @ ft_star - body.gamma0 * ft_star[k])
-        gamma_new = np.linalg.solve(A, rhs)
-        x = ft_star + ft_j @ gamma_new
-        s0 = float(np.mean(x[edges]))
+            lo, hi = bounds[i]
+            if ft_star[k] < lo:
+                active.append(i)
+                target.append(lo)
+            elif ft_star[k] > hi:
+                active.append(i)
+                target.append(hi)
+        gamma_new = np.zeros(m)
+        if active:
+            na = len(active)
+            A = np.empty((na, na))
+            rhs = np.empty(na)
+            for r, (i, t) in enumerate(zip(active, target)):
+                k = edges[i]
+                # fhat0 . P_k x = fhat0 . x - Gamma0 x_k
+                A[r, :] = 1.0 + body.fhat0 @ ft_j[:, active] - body.gamma0 * ft_j[k, active]
+                rhs[r] = -(gamma_w + body.fhat0 @ ft_star - body.gamma0 * ft_star[k]
+                           + body.gamma0 * t)
+            gamma_new[active] = np.linalg.solve(A, rhs)
+            x = ft_star + ft_j @ gamma_new
+            s0 = float(np.mean([x[edges[i]] - t for i, t in zip(active, target)]))
+        else:
+            x = ft_star
+            s0 = float((body.fhat0 @ ft_star + gamma_w) / body.gamma0)
         ftilde = x - s0
         f = body.f0 * ftilde
         for gj, z in zip(gamma_new, p.znew):

@@ -159,6 +159,7 @@ class Case:
     edges: tuple = ()
     znew: tuple = ()
     gamma_w: float | None = None
+    fbounds: tuple = ()        # shed: ((fmin, fmax), ...) per edge on f~; () = Kutta
     extra: dict = field(default_factory=dict)
 
     @property

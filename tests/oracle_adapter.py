@@ -17,7 +17,8 @@ def problem_of(case, X=None, Y=None):
                    G=np.asarray(case.G, np.float64),
                    u_inf=case.u_inf, v_inf=case.v_inf, ub=case.ub, vb=case.vb,
                    omega=case.omega, mode=case.mode, gamma_b=case.gamma_b,
-                   edges=tuple(case.edges), znew=tuple(case.znew), gamma_w=case.gamma_w)
+                   edges=tuple(case.edges), znew=tuple(case.znew), gamma_w=case.gamma_w,
+                   fbounds=tuple(case.fbounds))
 
 
 def body_of(case, table=None):

@@ -5,6 +5,10 @@
   kuttasystem2/3) on tiny grids;
 * the constraint rows hold: no-penetration up to a uniform value (eq. nopen),
   prescribed circulation (eq. circdef), Kutta (eq. kutta), Kelvin;
+* generalized edge conditions (Sec. 2.5, eq. twovortex-gen): equality bounds
+  against the dense system with target rows, the single-edge closed form,
+  the active-set choice, and its reductions to Kutta and to a prescribed
+  circulation;
 * S f0 = 1, S~ 1 = 1 (eq. Son1), P^Gamma removes circulation (eq. circrem);
 * continuum closed forms within discretization error: cylinder in uniform
   flow (Fig. 4), uniform f0 on a circle (Fig. 5), vortex near a cylinder
@@ -78,8 +82,19 @@ def brute_force(case):
     elif case.mode == "kutta":
         A[ns, case.edges[0]] = 1.0           # f~_k = 0  <=>  f_k = 0
     else:
+        # edge rows: f~_k = t (f_k = f0_k t) at an edge held at a bound,
+        # Gamma_i = 0 at an edge left free.  Bounds here are either an
+        # equality (always held) or unbounded (never held), so the active set
+        # is known without the oracle's intermediate sheet.
+        bounds = case.fbounds or [(0.0, 0.0)] * m
         for i, k in enumerate(case.edges):
-            A[ns + i, k] = 1.0
+            lo, hi = bounds[i]
+            if lo == hi:
+                A[ns + i, k] = 1.0
+                b[ns + i] = body.f0[k] * lo
+            else:
+                assert lo < -1e20 and hi > 1e20
+                A[ns + i, ns + 1 + i] = 1.0
         A[ns + m, :ns] = sf.ds                # Kelvin: <1,f> + sum Gamma_j + Gamma_w = 0
         A[ns + m, ns + 1:] = 1.0
         b[ns + m] = -np.sum(case.G)
@@ -258,3 +273,89 @@ def test_shed_one_edge_matches_closed_form():
     g1 = (-p.G.sum() - body.fhat0 @ PK(ft_star)) / (1.0 + body.fhat0 @ PK(ft1))
     assert abs(res.gamma_new[0] - g1) <= 1e-12 * abs(g1)
     assert abs(res.s0 - (ft_star + g1 * ft1)[k]) <= 1e-12 * max(1, abs(res.s0))
+
+
+FREE = (-1e30, 1e30)
+
+
+@pytest.mark.parametrize("bounds", [((0.3, 0.3), (-0.2, -0.2)), ((0.25, 0.25), FREE),
+                                    (FREE, (-0.4, -0.4)), (FREE, FREE)])
+def test_edge_bounds_equal_brute_force(bounds):
+    """Targets on f~ at the edges, and free edges, against one dense solve."""
+    case = wl.random_case(11, 24, 0.1, 6, surface="plate", mode="shed")
+    case.fbounds = bounds
+    res = solve(problem_of(case), body_of(case))
+    f, s0, gam = brute_force(case)
+    assert np.max(np.abs(res.f - f)) <= 1e-10 * np.max(np.abs(f))
+    assert abs(res.s0 - s0) <= 1e-10 * max(1.0, abs(s0))
+    assert np.max(np.abs(res.gamma_new - gam)) <= 1e-10 * max(1.0, np.max(np.abs(gam)))
+    for i, (lo, hi) in enumerate(bounds):
+        if lo == hi:
+            assert abs(res.ftilde[case.edges[i]] - lo) <= 1e-12
+        else:
+            assert res.gamma_new[i] == 0.0
+
+
+def _intermediate(case):
+    """f~* and the unit responses f~_j from the pieces of the solve."""
+    from oracle.operators import inv_laplacian_fft
+    from oracle.solve import surface_response_to_vortex
+    p = problem_of(case)
+    body = body_of(case)
+    grid = p.grid
+    w = regularize_vortices(grid, p.X, p.Y, p.G)
+    Es_star = interpolate_surface(grid, body.xs, body.ys, inv_laplacian_fft(w, grid.dx))
+    ft_star = body.solve_tilde(body.remove_circulation(surface_rhs(p, body)) - Es_star)
+    ft_j = [body.solve_tilde(surface_response_to_vortex(grid, body, z)) for z in case.znew]
+    return p, body, ft_star, ft_j
+
+
+def test_edge_bounds_active_set_and_closed_form():
+    """The bound that f~* violates is the one held; an edge whose f~* lies
+    inside its range sheds nothing; the single active edge obeys the closed
+    form Gamma = -(Gamma_w + fhat0 P_k f~* + Gamma0 t)/(1 + fhat0 P_k f~_1)."""
+    case = wl.random_case(14, 64, 0.04, 30, surface="plate", mode="shed")
+    p, body, ft_star, ft_j = _intermediate(case)
+    k1, k2 = case.edges
+    for side in ("below", "above"):
+        if side == "below":      # f~*_k1 < fmin: held at fmin
+            b1 = (ft_star[k1] + 0.3, ft_star[k1] + 0.9)
+            t = b1[0]
+        else:                    # f~*_k1 > fmax: held at fmax
+            b1 = (ft_star[k1] - 0.9, ft_star[k1] - 0.3)
+            t = b1[1]
+        b2 = (ft_star[k2] - 0.5, ft_star[k2] + 0.5)     # inside: free
+        case.fbounds = (b1, b2)
+        res = solve(problem_of(case), body)
+        assert res.gamma_new[1] == 0.0
+        PK = lambda x: x - x[k1]
+        g1 = -(p.G.sum() + body.fhat0 @ PK(ft_star) + body.gamma0 * t) / \
+            (1.0 + body.fhat0 @ PK(ft_j[0]))
+        assert abs(res.gamma_new[0] - g1) <= 1e-12 * abs(g1)
+        assert abs(res.ftilde[k1] - t) <= 1e-12
+        kel = np.dot(body.ds, res.f) + res.gamma_new.sum() + p.G.sum()
+        assert abs(kel) <= 1e-12
+
+
+def test_edge_bounds_reduce_to_kutta_and_to_circulation():
+    """Zero bounds are the Kutta condition (the same result as no bounds);
+    bounds wide enough to hold f~* shed nothing, leaving the body with the
+    circulation -Gamma_w (Kelvin), as the prescribed-circulation mode gives."""
+    case = wl.random_case(15, 64, 0.04, 30, surface="plate", mode="shed")
+    body = body_of(case)
+    ref = solve(problem_of(case), body)
+    case.fbounds = ((0.0, 0.0), (0.0, 0.0))
+    kut = solve(problem_of(case), body)
+    assert np.array_equal(kut.f, ref.f) and kut.s0 == ref.s0
+    assert np.array_equal(kut.gamma_new, ref.gamma_new)
+
+    case.fbounds = (FREE, FREE)
+    free = solve(problem_of(case), body)
+    assert np.all(free.gamma_new == 0.0)
+    circ_case = wl.random_case(15, 64, 0.04, 30, surface="plate", mode="circulation")
+    circ_case.gamma_b = -float(np.sum(case.G))
+    circ = solve(problem_of(circ_case), body)
+    assert np.array_equal(circ_case.X, case.X)
+    scale = np.max(np.abs(circ.f))
+    assert np.max(np.abs(free.f - circ.f)) <= 1e-10 * scale
+    assert np.max(np.abs(free.s - circ.s)) <= 1e-10 * np.max(np.abs(circ.s))
