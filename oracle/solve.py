@@ -28,9 +28,14 @@ Modes
       x = f~* + sum_j Gamma_j f~_j,  s0 = mean_i x_{k_i},  f~ = x - s0 1
       With edge bounds (Sec. 2.5, generalized edge condition; bounds on the
       non-singular sheet f~ at each edge, Kutta = both bounds zero): edge i
-      is active when f~*_{k_i} lies outside [fmin_i, fmax_i], with target the
-      violated bound t_i; inactive edges shed nothing (Gamma_i = 0).  The
-      active rows read (eq. twovortex-gen)
+      is active when the intermediate sheet lies outside [fmin_i, fmax_i] at
+      k_i, with target the violated bound t_i; inactive edges shed nothing
+      (Gamma_i = 0).  The intermediate sheet tested is the Kelvin-consistent
+      one, f~*_K = f~* - (fhat0 . f~* + Gamma_w)/Gamma0, i.e. the sheet the
+      body would carry if nothing were shed: f~* alone moves with the
+      Green's function gauge and with the constant removed from s_b, while
+      f~*_K does not, and with it a shed strength goes to zero as f~*_K
+      reaches its bound.  The active rows read (eq. twovortex-gen)
       sum_j (1 + fhat0 . P_{k_i} f~_j) Gamma_j = -(Gamma_w + fhat0 . P_{k_i} f~* + Gamma0 t_i)
       and s0 = mean over active i of (x_{k_i} - t_i); with no active edge,
       Kelvin's theorem alone gives s0 = (fhat0 . f~* + Gamma_w)/Gamma0.
@@ -149,14 +154,16 @@ def solve(p: Problem, body: Body | None = None, table=None) -> Result:
                          for z in p.znew], axis=1)                     # Ns x m
         bounds = list(p.fbounds) if p.fbounds else [(0.0, 0.0)] * m
         assert len(bounds) == m
-        # active edges and their targets (the violated bound)
+        # active edges and their targets (the violated bound), tested on
+        # the Kelvin-consistent intermediate sheet
+        ft_kel = ft_star - (body.fhat0 @ ft_star + gamma_w) / body.gamma0
         active, target = [], []
         for i, k in enumerate(edges):
             lo, hi = bounds[i]
-            if ft_star[k] < lo:
+            if ft_kel[k] < lo:
                 active.append(i)
                 target.append(lo)
-            elif ft_star[k] > hi:
+            elif ft_kel[k] > hi:
                 active.append(i)
                 target.append(hi)
         gamma_new = np.zeros(m)

@@ -26,3 +26,22 @@ def body_of(case, table=None):
         return None
     s = case.surface
     return body_setup(grid_of(case), s.xs, s.ys, s.ds, table)
+
+
+def intermediate_sheet(case, body=None):
+    """The oracle's intermediate sheet f~* of a shedding case, its
+    Kelvin-consistent shift f~*_K (the sheet with nothing shed, which the
+    generalized edge conditions of Sec. 2.5 inspect), and the unit-vortex
+    responses f~_j."""
+    from oracle.operators import interpolate_surface, inv_laplacian_fft, regularize_vortices
+    from oracle.solve import surface_response_to_vortex, surface_rhs
+    p = problem_of(case)
+    body = body or body_of(case)
+    grid = p.grid
+    w = regularize_vortices(grid, p.X, p.Y, p.G)
+    Es_star = interpolate_surface(grid, body.xs, body.ys, inv_laplacian_fft(w, grid.dx))
+    ft_star = body.solve_tilde(body.remove_circulation(surface_rhs(p, body)) - Es_star)
+    ft_j = [body.solve_tilde(surface_response_to_vortex(grid, body, z)) for z in case.znew]
+    gamma_w = float(np.sum(p.G)) if p.gamma_w is None else p.gamma_w
+    ft_kel = ft_star - (body.fhat0 @ ft_star + gamma_w) / body.gamma0
+    return ft_star, ft_kel, ft_j

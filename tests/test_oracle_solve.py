@@ -297,23 +297,17 @@ def test_edge_bounds_equal_brute_force(bounds):
 
 
 def _intermediate(case):
-    """f~* and the unit responses f~_j from the pieces of the solve."""
-    from oracle.operators import inv_laplacian_fft
-    from oracle.solve import surface_response_to_vortex
-    p = problem_of(case)
+    from tests.oracle_adapter import intermediate_sheet
     body = body_of(case)
-    grid = p.grid
-    w = regularize_vortices(grid, p.X, p.Y, p.G)
-    Es_star = interpolate_surface(grid, body.xs, body.ys, inv_laplacian_fft(w, grid.dx))
-    ft_star = body.solve_tilde(body.remove_circulation(surface_rhs(p, body)) - Es_star)
-    ft_j = [body.solve_tilde(surface_response_to_vortex(grid, body, z)) for z in case.znew]
-    return p, body, ft_star, ft_j
+    _, ft_kel, ft_j = intermediate_sheet(case, body)
+    return problem_of(case), body, ft_kel, ft_j
 
 
 def test_edge_bounds_active_set_and_closed_form():
-    """The bound that f~* violates is the one held; an edge whose f~* lies
-    inside its range sheds nothing; the single active edge obeys the closed
-    form Gamma = -(Gamma_w + fhat0 P_k f~* + Gamma0 t)/(1 + fhat0 P_k f~_1)."""
+    """The bound that the intermediate sheet violates is the one held; an
+    edge inside its range sheds nothing; the single active edge obeys the
+    closed form Gamma = -(Gamma_w + fhat0 P_k f~* + Gamma0 t)/(1 + fhat0 P_k f~_1)
+    (P_k removes uniform shifts, so f~* and f~*_K give the same value)."""
     case = wl.random_case(14, 64, 0.04, 30, surface="plate", mode="shed")
     p, body, ft_star, ft_j = _intermediate(case)
     k1, k2 = case.edges
@@ -359,3 +353,24 @@ def test_edge_bounds_reduce_to_kutta_and_to_circulation():
     scale = np.max(np.abs(circ.f))
     assert np.max(np.abs(free.f - circ.f)) <= 1e-10 * scale
     assert np.max(np.abs(free.s - circ.s)) <= 1e-10 * np.max(np.abs(circ.s))
+
+
+def test_edge_bounds_shed_strength_is_continuous():
+    """Tested on the Kelvin-consistent intermediate sheet f~*_K, the shed
+    strength is affine in the distance of the bound below f~*_K at the edge
+    and reaches zero with it: no jump where an edge turns active.  With both
+    edges inside their ranges the sheet is f~*_K itself."""
+    case = wl.random_case(16, 64, 0.04, 30, surface="plate", mode="shed")
+    p, body, ft_kel, _ = _intermediate(case)
+    k1, k2 = case.edges
+    ratios = []
+    for eps in (1e-2, 1e-4, 1e-6):
+        case.fbounds = ((-1e30, ft_kel[k1] - eps), FREE)
+        res = solve(problem_of(case), body)
+        assert res.gamma_new[1] == 0.0 and res.gamma_new[0] != 0.0
+        ratios.append(res.gamma_new[0] / eps)
+    assert max(abs(r / ratios[0] - 1.0) for r in ratios) <= 1e-6
+    case.fbounds = ((ft_kel[k1] - 1e-3, ft_kel[k1] + 1e-3), (ft_kel[k2] - 1e-3, 1e30))
+    res = solve(problem_of(case), body)
+    assert np.all(res.gamma_new == 0.0)
+    assert np.max(np.abs(res.ftilde - ft_kel)) <= 1e-12 * np.max(np.abs(ft_kel))
