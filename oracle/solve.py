@@ -41,6 +41,9 @@ Modes
       Kelvin's theorem alone gives s0 = (fhat0 . f~* + Gamma_w)/Gamma0.
 * ``none``         no body: s = s*.
 
+Time stepping: ``rk2_step`` (explicit midpoint, fixed modes) and
+``shed_step`` (forward Euler with one new vortex per edge, Sec. 2.4.1).
+
 E_s s* here equals -E_s L^-1 w of the paper's formulas.
 """
 from __future__ import annotations
@@ -212,3 +215,46 @@ def rk2_step(p: Problem, body: Body | None, dt: float, table=None):
     pm = Problem(**{**p.__dict__, "X": Xm, "Y": Ym})
     r2 = solve(pm, body, table)
     return p.X + dt * r2.u, p.Y + dt * r2.v, r1, r2
+
+
+@dataclass
+class ShedState:
+    """Vortices of a shedding run and, per edge, the index of the last vortex
+    it released with nonzero strength (-1 before the first)."""
+    X: np.ndarray
+    Y: np.ndarray
+    G: np.ndarray
+    last: list
+
+
+def shed_step(p: Problem, body: Body, st: ShedState, dt: float, first, table=None):
+    """One forward Euler step of vortex shedding (Sec. 2.4.1; Sec. 2.5 with
+    edge bounds).
+
+    New vortex j goes one third of the way from edge point k_j to the
+    current position of the last vortex that edge released, or to the edge
+    point plus first[j] before its first release.  The new vortices join the
+    set with strength zero, so the solve (shedding mode of p, its bounds
+    included, Gamma_w the sum of the strengths) also gives the velocity at
+    them; they then take the strengths Gamma_j, and every vortex moves by
+    x <- x + dt u(x).  An edge that shed zero keeps its last release.
+    Returns the new state and the solve's result.
+    """
+    edges = list(p.edges)
+    znew = []
+    for j, k in enumerate(edges):
+        ex, ey = body.xs[k], body.ys[k]
+        l = st.last[j]
+        if l >= 0:
+            znew.append((ex + (st.X[l] - ex) / 3.0, ey + (st.Y[l] - ey) / 3.0))
+        else:
+            znew.append((ex + first[j][0], ey + first[j][1]))
+    nv = len(st.X)
+    X = np.concatenate([st.X, [z[0] for z in znew]])
+    Y = np.concatenate([st.Y, [z[1] for z in znew]])
+    G = np.concatenate([st.G, np.zeros(len(edges))])
+    q = Problem(**{**p.__dict__, "X": X, "Y": Y, "G": G, "znew": tuple(znew), "gamma_w": None})
+    res = solve(q, body, table)
+    G[nv:] = res.gamma_new
+    last = [nv + j if res.gamma_new[j] != 0.0 else st.last[j] for j in range(len(edges))]
+    return ShedState(X + dt * res.u, Y + dt * res.v, G, last), res
