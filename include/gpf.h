@@ -103,7 +103,9 @@ typedef enum {
                               circulation free (eq. kuttasystem)               */
   GPF_KUTTA_SHED = 3       /* Kutta condition at the body's m edges, each with a
                               new vortex, total circulation zero (eqs.
-                              kuttasystem2, kuttasystem3)                      */
+                              kuttasystem2, kuttasystem3); with the edge
+                              bounds fmin/fmax, the generalized edge
+                              conditions (eq. twovortex-gen)                   */
 } gpf_mode;
 
 #define GPF_MAX_EDGES 8
@@ -113,6 +115,7 @@ typedef struct gpf_plan gpf_plan;
 typedef struct gpf_body gpf_body;
 typedef struct gpf_batch gpf_batch;
 typedef struct gpf_rk2 gpf_rk2;
+typedef struct gpf_shed gpf_shed;
 
 typedef struct {
   int n;                   /* nodes per direction (power of two, 16..2048)      */
@@ -134,6 +137,22 @@ typedef struct {
   double h_ynew[GPF_MAX_EDGES];        /*   one per edge, in edge order         */
   double gamma_w;                      /* GPF_KUTTA_SHED: circulation of the
                                           existing vortices; NaN = sum of d_gv  */
+  double fmin[GPF_MAX_EDGES];          /* GPF_KUTTA_SHED: generalized edge      */
+  double fmax[GPF_MAX_EDGES];          /*   conditions (Sec. 2.5): bounds on the
+                                          non-singular sheet f~ at each edge, in
+                                          edge order.  An edge where the sheet
+                                          the body would carry with nothing shed
+                                          (Kelvin-consistent intermediate, f~* -
+                                          (fhat0.f~* + Gamma_w)/Gamma0) lies in
+                                          [fmin, fmax] sheds nothing (its new
+                                          vortex gets strength 0); otherwise
+                                          f~_k is held at the bound it violates.  fmin = fmax = 0 (a zeroed
+                                          struct) is the Kutta condition; +-inf
+                                          leaves an edge free.  For a flat plate
+                                          of chord c, bounds on the suction
+                                          parameter map as f~ = -2 pi c sigma /
+                                          Gamma0.  fmin > fmax or NaN:
+                                          GPF_E_INVALID.                        */
 } gpf_inputs;
 
 typedef struct {
@@ -299,6 +318,44 @@ gpf_status gpf_rk2_fields(const gpf_rk2 *rk, const void **d_psi, const double **
                           const double **d_v, const double **d_f,
                           const double **d_scalars, unsigned int **d_status);
 void gpf_rk2_destroy(gpf_rk2 *rk);
+
+/* Vortex shedding with forward Euler steps (Sec. 2.4.1: new vortices go one
+ * third of the way from the edge to the last vortex released there, and the
+ * vortices move with forward Euler; Sec. 2.5 for edge bounds).  Each step:
+ *   1. places one new vortex per body edge k_j, at e + (z_last - e)/3, e the
+ *      edge point and z_last the current position of the last vortex edge j
+ *      released with nonzero strength, or at e + (h_first[2j], h_first[2j+1])
+ *      before edge j has released one;
+ *   2. appends the new vortices with strength zero (so the velocity is
+ *      evaluated at them too) and solves in the shedding mode of `in`, edge
+ *      bounds included, which gives their strengths Gamma_j (zero at an edge
+ *      inside its bounds);
+ *   3. stores Gamma_j and advances every vortex: x <- x + dt u(x).
+ * in->mode must be GPF_KUTTA_SHED with in->m equal to the body's edge
+ * count; in->h_xnew/h_ynew and in->gamma_w are ignored (Gamma_w is the sum
+ * of the strengths).  The body stays in place: ub, vb, omega must be zero
+ * (GPF_E_UNSUPPORTED otherwise; a translating body is the same flow as a
+ * body at rest in the opposite uniform flow).  d_x, d_y, d_g are device arrays of `capacity`
+ * doubles owned by the caller: the first in->nv hold the initial vortices
+ * (in->d_xv/d_yv/d_gv are ignored), every step appends m vortices and
+ * moves them all in place.  `out` names caller-owned buffers as for
+ * gpf_solve, overwritten by every step: d_u and d_v (capacity doubles; the
+ * velocities before the position update), d_scalars and d_status are
+ * required, d_f and d_ftilde optional.  h_first holds 2m doubles (host).
+ * gpf_shed_run returns GPF_E_INVALID, enqueueing nothing, when the steps
+ * would exceed the capacity.  A vortex that leaves the window sets
+ * GPF_DEV_OUT_OF_GRID in the status word, and the results from then on
+ * are not valid. */
+gpf_status gpf_shed_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
+                           const gpf_outputs *out, double *d_x, double *d_y, double *d_g,
+                           int capacity, double dt, const double *h_first, gpf_shed **sh);
+
+/* Enqueue nsteps steps on hip_stream (asynchronous). */
+gpf_status gpf_shed_run(gpf_shed *sh, int nsteps, void *hip_stream);
+
+/* Number of vortices after the enqueued steps (-1 for a NULL object). */
+int gpf_shed_count(const gpf_shed *sh);
+void gpf_shed_destroy(gpf_shed *sh);
 
 /* ---- building blocks (asynchronous on hip_stream) ---------------------- */
 

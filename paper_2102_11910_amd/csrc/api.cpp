@@ -325,6 +325,7 @@ struct ProblemRef {
   const gpf_inputs *in;
   const gpf_outputs *out;
   gpf_workspace *ws;
+  int znew_from = -1;   // >= 0: the new vortices are vortices znew_from.. of in
 };
 
 GroupCfg config_of(const ProblemRef &r) {
@@ -385,9 +386,12 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   sv.gamma_w_in = in->gamma_w;
   sv.mode = in->mode;
   sv.m = in->mode == GPF_KUTTA_SHED ? in->m : 0;
+  sv.znew_from = r.znew_from;
   for (int j = 0; j < sv.m; ++j) {
     sv.xnew[j] = in->h_xnew[j];
     sv.ynew[j] = in->h_ynew[j];
+    sv.fmin[j] = in->fmin[j];
+    sv.fmax[j] = in->fmax[j];
   }
   const void *spec2 = cfg.fp64_plan ? p->spec64.p : p->spec32.p;
   const void *tw2 = cfg.fp64_plan ? p->tw64.p : p->tw32.p;
@@ -522,9 +526,13 @@ gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs
   if (in->mode == GPF_KUTTA_SHED) {
     if (in->m < 1 || in->m != body->nedge)
       return fail(GPF_E_INVALID, "solve: shedding needs one new vortex per body edge");
-    for (int j = 0; j < in->m; ++j)
+    for (int j = 0; j < in->m; ++j) {
       if (!is_finite(in->h_xnew[j]) || !is_finite(in->h_ynew[j]))
         return fail(GPF_E_INVALID, "solve: non-finite new vortex position");
+      // NaN fails the comparison; infinite bounds leave the edge free
+      if (!(in->fmin[j] <= in->fmax[j]))
+        return fail(GPF_E_INVALID, "solve: edge bounds need fmin <= fmax");
+    }
     if (!std::isnan(in->gamma_w) && !is_finite(in->gamma_w))
       return fail(GPF_E_INVALID, "solve: gamma_w must be finite or NaN");
   }
@@ -1119,6 +1127,114 @@ gpf_status gpf_rk2_fields(const gpf_rk2 *rk, const void **d_psi, const double **
 }
 
 void gpf_rk2_destroy(gpf_rk2 *rk) { delete rk; }
+
+// ---------------------------------------------------------------------------
+// shedding with forward Euler steps
+// ---------------------------------------------------------------------------
+
+namespace gpf {
+namespace {
+
+// one step: place the new vortices, solve, store strengths and move
+gpf_status shed_enqueue(gpf_shed *sh, const ShedGeom &geom, hipStream_t s) {
+  gpf_plan *plan = sh->plan;
+  const int nv = sh->nv + sh->m;
+  double *x = sh->x, *y = sh->y, *g = sh->g;
+  int *last = sh->last.as<int>();
+  GPF_HIP(launch_shed_place(geom, sh->nv, last, x, y, g, s));
+  sh->in.nv = nv;
+  ProblemRef r{plan, sh->body, &sh->in, &sh->out, &plan->ws, sh->nv};
+  const GroupCfg cfg = config_of(r);
+  std::vector<ProblemRef> one{r};
+  GPF_TRY(run_group(cfg, one, plan->ring, plan->ctx->xcds, s));
+  GPF_HIP(launch_shed_advance(sh->m, nv, sh->out.d_scalars, last, x, y, g, sh->out.d_u,
+                              sh->out.d_v, sh->dt, s));
+  sh->nv = nv;
+  return GPF_OK;
+}
+
+}  // namespace
+}  // namespace gpf
+
+gpf_status gpf_shed_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
+                           const gpf_outputs *out, double *d_x, double *d_y, double *d_g,
+                           int capacity, double dt, const double *h_first, gpf_shed **psh) {
+  if (!plan || !body || !in || !out || !psh || !h_first || !is_finite(dt) || in->nv < 0 ||
+      !d_x || !d_y || !d_g)
+    return fail(GPF_E_INVALID, "gpf_shed_create: bad arguments");
+  *psh = nullptr;
+  if (!out->d_u || !out->d_v || !out->d_scalars)
+    return fail(GPF_E_INVALID, "gpf_shed_create: d_u, d_v and d_scalars are required");
+  if (in->mode != GPF_KUTTA_SHED)
+    return fail(GPF_E_INVALID, "gpf_shed_create: needs the shedding mode");
+  if (in->ub != 0.0 || in->vb != 0.0 || in->omega != 0.0)
+    return fail(GPF_E_UNSUPPORTED,
+                "gpf_shed_create: the body stays in place; give a translation as the uniform flow");
+  const int m = body->nedge;
+  if (m < 1 || in->m != m) return fail(GPF_E_INVALID, "gpf_shed_create: one new vortex per body edge");
+  if (capacity < in->nv + m) return fail(GPF_E_INVALID, "gpf_shed_create: capacity below nv + m");
+  for (int j = 0; j < 2 * m; ++j)
+    if (!is_finite(h_first[j])) return fail(GPF_E_INVALID, "gpf_shed_create: non-finite h_first");
+  GPF_HIP(hipSetDevice(plan->ctx->device));
+  std::unique_ptr<gpf_shed> sh(new gpf_shed);
+  sh->plan = plan;
+  sh->body = body;
+  sh->nv = in->nv;
+  sh->capacity = capacity;
+  sh->m = m;
+  sh->dt = dt;
+  for (int j = 0; j < 2 * m; ++j) sh->first[j] = h_first[j];
+  for (int j = 0; j < m; ++j) {
+    const size_t k = (size_t)body->edges[j];
+    GPF_HIP(hipMemcpy(&sh->edge_xy[2 * j], body->xs.as<double>() + k, sizeof(double),
+                      hipMemcpyDeviceToHost));
+    GPF_HIP(hipMemcpy(&sh->edge_xy[2 * j + 1], body->ys.as<double>() + k, sizeof(double),
+                      hipMemcpyDeviceToHost));
+  }
+  GPF_TRY(sh->last.alloc(GPF_MAX_EDGES * sizeof(int)));
+  GPF_HIP(hipMemset(sh->last.p, 0xff, GPF_MAX_EDGES * sizeof(int)));   // -1: nothing released
+  sh->x = d_x;
+  sh->y = d_y;
+  sh->g = d_g;
+  sh->in = *in;
+  sh->in.d_xv = d_x;
+  sh->in.d_yv = d_y;
+  sh->in.d_gv = d_g;
+  sh->in.nv = in->nv + m;
+  sh->in.gamma_w = std::nan("");
+  for (int j = 0; j < GPF_MAX_EDGES; ++j) sh->in.h_xnew[j] = sh->in.h_ynew[j] = 0.0;
+  sh->out = *out;
+  GPF_TRY(validate(plan, body, &sh->in, &sh->out));
+  ProblemRef r{plan, body, &sh->in, &sh->out, &plan->ws, in->nv};
+  const GroupCfg cfg = config_of(r);
+  GPF_TRY(plan->ws.ensure(cfg.n, !cfg.fp64_plan, cfg.fp64_plan || cfg.conv1_fp64, body->ns));
+  GPF_TRY(plan->ws.ensure_vortices(capacity));
+  *psh = sh.release();
+  return GPF_OK;
+}
+
+gpf_status gpf_shed_run(gpf_shed *sh, int nsteps, void *hip_stream) {
+  if (!sh || nsteps < 0) return fail(GPF_E_INVALID, "gpf_shed_run: bad arguments");
+  if ((long long)sh->nv + (long long)nsteps * sh->m > sh->capacity)
+    return fail(GPF_E_INVALID, "gpf_shed_run: the steps would exceed the vortex capacity");
+  hipStream_t s = as_stream(hip_stream);
+  GPF_HIP(hipSetDevice(sh->plan->ctx->device));
+  ShedGeom geom{};
+  geom.m = sh->m;
+  for (int j = 0; j < sh->m; ++j) {
+    geom.ex[j] = sh->edge_xy[2 * j];
+    geom.ey[j] = sh->edge_xy[2 * j + 1];
+    geom.fx[j] = sh->first[2 * j];
+    geom.fy[j] = sh->first[2 * j + 1];
+  }
+  TimerScope scope(sh->plan->timing ? &sh->plan->timer : nullptr);
+  for (int k = 0; k < nsteps; ++k) GPF_TRY(shed_enqueue(sh, geom, s));
+  return GPF_OK;
+}
+
+int gpf_shed_count(const gpf_shed *sh) { return sh ? sh->nv : -1; }
+
+void gpf_shed_destroy(gpf_shed *sh) { delete sh; }
 
 gpf_status gpf_timing_enable(gpf_plan *plan, int enable) {
   if (!plan) return fail(GPF_E_INVALID, "gpf_timing_enable: null plan");

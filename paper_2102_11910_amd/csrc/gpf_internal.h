@@ -128,6 +128,9 @@ struct SolveScalars {
   int mode, m;
   int edges[GPF_MAX_EDGES];
   double xnew[GPF_MAX_EDGES], ynew[GPF_MAX_EDGES];
+  double fmin[GPF_MAX_EDGES], fmax[GPF_MAX_EDGES];   // edge bounds on f~
+  int znew_from;   // >= 0: new vortex j sits at vortex znew_from + j (device
+                   // arrays) instead of (xnew[j], ynew[j])
 };
 
 // one convolution of one problem: out = conv(in) - c * gamma[0]
@@ -203,6 +206,17 @@ template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
 
 // xo = x + a u, yo = y + a v (in place allowed)
+// shedding steps (nv counts the new vortices; nv >= m >= 1)
+struct ShedGeom {
+  int m;
+  double ex[GPF_MAX_EDGES], ey[GPF_MAX_EDGES];   // edge points
+  double fx[GPF_MAX_EDGES], fy[GPF_MAX_EDGES];   // offsets of the first release
+};
+hipError_t launch_shed_place(const ShedGeom &sg, int nv, const int *last, double *x, double *y,
+                             double *g, hipStream_t s);
+hipError_t launch_shed_advance(int m, int nv, const double *sc, int *last, double *x, double *y,
+                               double *g, const double *u, const double *v, double dt,
+                               hipStream_t s);
 hipError_t launch_axpy2(int nv, const double *x, const double *y, const double *u,
                         const double *v, double a, double *xo, double *yo, hipStream_t s);
 
@@ -298,6 +312,19 @@ struct gpf_batch {
   hipStream_t lane_stream[kMaxLanes] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
   ~gpf_batch();
+};
+
+struct gpf_shed {
+  gpf_plan *plan = nullptr;
+  const gpf_body *body = nullptr;
+  gpf_inputs in{};
+  gpf_outputs out{};
+  int nv = 0, capacity = 0, m = 0;
+  double dt = 0.0;
+  double first[2 * GPF_MAX_EDGES] = {};     // offsets of each edge's first release
+  double edge_xy[2 * GPF_MAX_EDGES] = {};   // edge points
+  double *x = nullptr, *y = nullptr, *g = nullptr;   // caller's vortex arrays
+  gpf::DevBuf last;   // per edge: index of its last nonzero release, or -1
 };
 
 struct gpf_rk2 {

@@ -207,7 +207,9 @@ __global__ __launch_bounds__(kRB) void k_surface_rhs(const ProbDesc *__restrict_
   if (active) {
     p = pj % ns;
     j = pj / ns;
-    const double xi = (sv.xnew[j] - P.x0) / P.dx, eta = (sv.ynew[j] - P.y0) / P.dx;
+    const double zx = sv.znew_from >= 0 ? P.xv[sv.znew_from + j] : sv.xnew[j];
+    const double zy = sv.znew_from >= 0 ? P.yv[sv.znew_from + j] : sv.ynew[j];
+    const double xi = (zx - P.x0) / P.dx, eta = (zy - P.y0) / P.dx;
     if (xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0) {
       const int vi = (int)floor(xi) - 1, vj = (int)floor(eta) - 1;
       const double fx = xi - floor(xi), fy = eta - floor(eta);
@@ -392,37 +394,62 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
       } else {
         const double gamma_w = isnan(sv.gamma_w_in) ? gw_dev : sv.gamma_w_in;
         const double dstar = circ[0] - c1 * g0;   // fhat0 . f~*
-        double amax = 0.0;
+        // Generalized edge conditions (Sec. 2.5): edge i takes part when the
+        // intermediate sheet lies outside [fmin_i, fmax_i] at k_i, with the
+        // violated bound as its target; the others shed nothing.  Kutta is
+        // fmin = fmax = 0.  The sheet tested is the one the body carries if
+        // nothing is shed, f~* - s0 with Kelvin's s0 = (fhat0 . f~* +
+        // Gamma_w)/Gamma0: independent of the Green's function gauge, and
+        // the shed strength vanishes as it reaches a bound.
+        const double s0_keep = (dstar + gamma_w) / g0;
+        int act[GPF_MAX_EDGES];
+        double tgt[GPF_MAX_EDGES];
+        int na = 0;
         for (int i = 0; i < m; ++i) {
-          for (int j = 0; j < m; ++j) {
-            A[i][j] = 1.0 + circ[1 + j] - g0 * ye[i][1 + j];
-            amax = fmax(amax, fabs(A[i][j]));
+          const double fs = ye[i][0] - c1 - s0_keep;
+          if (fs < sv.fmin[i]) { act[na] = i; tgt[na++] = sv.fmin[i]; }
+          else if (fs > sv.fmax[i]) { act[na] = i; tgt[na++] = sv.fmax[i]; }
+        }
+        // rows of eq. twovortex-gen over the active edges:
+        // sum_j (1 + fhat0 . P_k f~_j) Gamma_j = -(Gamma_w + fhat0 . P_k f~* + Gamma0 t)
+        double amax = 0.0;
+        for (int r = 0; r < na; ++r) {
+          const int i = act[r];
+          for (int c = 0; c < na; ++c) {
+            const int j = act[c];
+            A[r][c] = 1.0 + circ[1 + j] - g0 * ye[i][1 + j];
+            amax = fmax(amax, fabs(A[r][c]));
           }
-          A[i][m] = -(gamma_w + dstar - g0 * (ye[i][0] - c1));
+          A[r][na] = -(gamma_w + dstar - g0 * (ye[i][0] - c1) + g0 * tgt[r]);
         }
         bool singular = false;
-        for (int c = 0; c < m; ++c) {
+        for (int c = 0; c < na; ++c) {
           int pr = c;
-          for (int i = c + 1; i < m; ++i)
+          for (int i = c + 1; i < na; ++i)
             if (fabs(A[i][c]) > fabs(A[pr][c])) pr = i;
           if (!(fabs(A[pr][c]) > 1e-13 * amax)) { singular = true; break; }
           if (pr != c)
-            for (int j = 0; j <= m; ++j) { const double t = A[c][j]; A[c][j] = A[pr][j]; A[pr][j] = t; }
-          for (int i = 0; i < m; ++i) {
+            for (int j = 0; j <= na; ++j) { const double t = A[c][j]; A[c][j] = A[pr][j]; A[pr][j] = t; }
+          for (int i = 0; i < na; ++i) {
             if (i == c) continue;
             const double fct = A[i][c] / A[c][c];
-            for (int j = c; j <= m; ++j) A[i][j] -= fct * A[c][j];
+            for (int j = c; j <= na; ++j) A[i][j] -= fct * A[c][j];
           }
         }
-        for (int j = 0; j < m; ++j) gam[j] = singular ? 0.0 : A[j][m] / A[j][j];
+        for (int r = 0; r < na; ++r) gam[act[r]] = singular ? 0.0 : A[r][na] / A[r][r];
         if (singular && blockIdx.x == 0) atomicOr(P.status, GPF_DEV_SINGULAR);
-        // s0: mean over the edges of x_k = f~*_k + sum_j Gamma_j f~_j,k
-        for (int i = 0; i < m; ++i) {
-          double xk = ye[i][0] - c1;
-          for (int j = 0; j < m; ++j) xk += gam[j] * ye[i][1 + j];
-          s0 += xk;
+        if (na > 0) {
+          // s0: mean over the active edges of x_k - t, x = f~* + sum_j Gamma_j f~_j
+          for (int r = 0; r < na; ++r) {
+            const int i = act[r];
+            double xk = ye[i][0] - c1;
+            for (int j = 0; j < m; ++j) xk += gam[j] * ye[i][1 + j];
+            s0 += xk - tgt[r];
+          }
+          s0 /= na;
+        } else {
+          s0 = s0_keep;   // nothing shed: Kelvin's theorem alone fixes s0
         }
-        s0 /= m;
         double gj = 0.0;
         for (int j = 0; j < m; ++j) {
           gj += gam[j] * circ[1 + j];
@@ -483,7 +510,9 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   }
   if (blockIdx.x == 0 && mode == GPF_KUTTA_SHED && tid < 16 * m) {
     const int j = tid >> 4, node = tid & 15;
-    const double xi = (sv.xnew[j] - P.x0) / P.dx, eta = (sv.ynew[j] - P.y0) / P.dx;
+    const double zx = sv.znew_from >= 0 ? P.xv[sv.znew_from + j] : sv.xnew[j];
+    const double zy = sv.znew_from >= 0 ? P.yv[sv.znew_from + j] : sv.ynew[j];
+    const double xi = (zx - P.x0) / P.dx, eta = (zy - P.y0) / P.dx;
     if (xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0) {
       const int i0 = (int)floor(xi) - 1, j0 = (int)floor(eta) - 1;
       const double fx = xi - floor(xi), fy = eta - floor(eta);

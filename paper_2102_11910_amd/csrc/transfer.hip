@@ -400,7 +400,61 @@ __global__ void k_axpy2(int nv, const double *__restrict__ x, const double *__re
   yo[q] = y[q] + a * v[q];
 }
 
+// Shedding step, before the solve: new vortex j goes one third of the way
+// from edge point e_j to the last vortex that edge released (Sec. 2.4.1),
+// or to e_j + first_j before the first release; appended with strength 0.
+__global__ void k_shed_place(ShedGeom sg, int nv, const int *__restrict__ last, double *x,
+                             double *y, double *g) {
+  const int j = threadIdx.x;
+  if (j >= sg.m) return;
+  const int l = last[j];
+  double zx, zy;
+  if (l >= 0) {
+    zx = sg.ex[j] + (x[l] - sg.ex[j]) / 3.0;
+    zy = sg.ey[j] + (y[l] - sg.ey[j]) / 3.0;
+  } else {
+    zx = sg.ex[j] + sg.fx[j];
+    zy = sg.ey[j] + sg.fy[j];
+  }
+  x[nv + j] = zx;
+  y[nv + j] = zy;
+  g[nv + j] = 0.0;
+}
+
+// Shedding step, after the solve: the new vortices (the last m of nv) take
+// their strengths from the scalar block; an edge that shed a nonzero
+// strength records its new vortex as its last release; every vortex moves
+// by forward Euler.
+__global__ void k_shed_advance(int m, int nv, const double *__restrict__ sc, int *last,
+                               double *x, double *y, double *g, const double *__restrict__ u,
+                               const double *__restrict__ v, double dt) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) {
+    const double gj = sc[SC_GAMMA_NEW + q];
+    g[nv - m + q] = gj;
+    if (gj != 0.0) last[q] = nv - m + q;
+  }
+  if (q < nv) {
+    x[q] += dt * u[q];
+    y[q] += dt * v[q];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_shed_place(const ShedGeom &sg, int nv, const int *last, double *x, double *y,
+                             double *g, hipStream_t s) {
+  hipLaunchKernelGGL(k_shed_place, dim3(1), dim3(64), 0, s, sg, nv, last, x, y, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_shed_advance(int m, int nv, const double *sc, int *last, double *x, double *y,
+                               double *g, const double *u, const double *v, double dt,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_shed_advance, dim3((nv + 255) / 256), dim3(256), 0, s, m, nv, sc, last, x,
+                     y, g, u, v, dt);
+  return hipGetLastError();
+}
 
 hipError_t launch_axpy2(int nv, const double *x, const double *y, const double *u,
                         const double *v, double a, double *xo, double *yo, hipStream_t s) {

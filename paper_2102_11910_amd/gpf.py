@@ -62,7 +62,8 @@ class gpf_inputs(C.Structure):
                 ("ub", C.c_double), ("vb", C.c_double), ("omega", C.c_double),
                 ("mode", C.c_int), ("gamma_b", C.c_double), ("m", C.c_int),
                 ("h_xnew", C.c_double * GPF_MAX_EDGES), ("h_ynew", C.c_double * GPF_MAX_EDGES),
-                ("gamma_w", C.c_double)]
+                ("gamma_w", C.c_double),
+                ("fmin", C.c_double * GPF_MAX_EDGES), ("fmax", C.c_double * GPF_MAX_EDGES)]
 
 
 class gpf_outputs(C.Structure):
@@ -110,6 +111,11 @@ def _load():
         "gpf_rk2_run": (I, [P, I, P]),
         "gpf_rk2_fields": (I, [P, PP, PP, PP, PP, PP, PP]),
         "gpf_rk2_destroy": (None, [P]),
+        "gpf_shed_create": (I, [P, P, C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P, P, P, I,
+                                D, DP, PP]),
+        "gpf_shed_run": (I, [P, I, P]),
+        "gpf_shed_count": (I, [P]),
+        "gpf_shed_destroy": (None, [P]),
         "gpf_server_create": (I, [P, C.c_size_t, I, C.c_uint, PP]),
         "gpf_server_plan": (I, [P, C.POINTER(gpf_grid), PP]),
         "gpf_server_submit": (I, [P, C.POINTER(gpf_grid), P, C.POINTER(gpf_inputs),
@@ -265,8 +271,9 @@ class Body:
 
 
 def make_inputs(X, Y, G, u_inf=0.0, v_inf=0.0, ub=0.0, vb=0.0, omega=0.0, mode="none",
-                gamma_b=0.0, znew=(), gamma_w=None) -> gpf_inputs:
-    """Fill gpf_inputs; X, Y, G are float64 device tensors."""
+                gamma_b=0.0, znew=(), gamma_w=None, fbounds=()) -> gpf_inputs:
+    """Fill gpf_inputs; X, Y, G are float64 device tensors.  fbounds:
+    ((fmin, fmax), ...) per edge for the shedding mode; () is Kutta."""
     inp = gpf_inputs()
     inp.nv = int(X.numel()) if X is not None else 0
     inp.d_xv = X.data_ptr() if inp.nv else None
@@ -280,6 +287,9 @@ def make_inputs(X, Y, G, u_inf=0.0, v_inf=0.0, ub=0.0, vb=0.0, omega=0.0, mode="
         inp.h_xnew[j] = z[0]
         inp.h_ynew[j] = z[1]
     inp.gamma_w = math.nan if gamma_w is None else gamma_w
+    for j, (lo, hi) in enumerate(fbounds):
+        inp.fmin[j] = lo
+        inp.fmax[j] = hi
     return inp
 
 
@@ -482,6 +492,44 @@ class Rk2:
             pass
 
 
+class Shed:
+    """Vortex shedding with forward Euler steps.  X, Y, G are float64 device
+    tensors of `capacity` entries whose first inp.nv hold the initial
+    vortices; run() appends one vortex per edge each step and moves them all
+    in place.  out: gpf_outputs with u, v of `capacity` entries, scalars and
+    status.  first: ((dx, dy), ...) offset of each edge's first release."""
+
+    def __init__(self, plan: Plan, body: Body, inp: gpf_inputs, out: gpf_outputs, X, Y, G,
+                 dt: float, first):
+        assert X.numel() == Y.numel() == G.numel()
+        h = C.c_void_p()
+        arr = (C.c_double * (2 * len(first)))(*[float(c) for z in first for c in z])
+        check(lib.gpf_shed_create(plan.h, body.h, C.byref(inp), C.byref(out), _ptr(X), _ptr(Y),
+                                  _ptr(G), int(X.numel()), float(dt), arr, C.byref(h)),
+              "gpf_shed_create")
+        self.h = h
+        self.plan, self.body, self.inp, self.out, self.X, self.Y, self.G = \
+            plan, body, inp, out, X, Y, G
+
+    def run(self, nsteps: int, stream=None):
+        check(lib.gpf_shed_run(self.h, int(nsteps), _stream_ptr(stream)), "gpf_shed_run")
+
+    @property
+    def nv(self) -> int:
+        return lib.gpf_shed_count(self.h)
+
+    def close(self):
+        if self.h:
+            lib.gpf_shed_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One plan (and optional body) with preallocated torch outputs.
 
@@ -513,7 +561,8 @@ class Solver:
 
     def inputs_for(self, case, X, Y, G):
         return make_inputs(X, Y, G, case.u_inf, case.v_inf, case.ub, case.vb, case.omega,
-                           case.mode, case.gamma_b, case.znew, case.gamma_w)
+                           case.mode, case.gamma_b, case.znew, case.gamma_w,
+                           getattr(case, "fbounds", ()))
 
     def outputs(self, nv: int, velocities=True) -> gpf_outputs:
         import torch

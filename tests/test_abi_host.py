@@ -51,3 +51,33 @@ def test_no_device_reports_device_error():
         pytest.skip("a GPU is present")
     h = C.c_void_p()
     assert gpf.lib.gpf_ctx_create(0, C.byref(h)) == gpf.GPF_E_DEVICE
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the header's sizes and offsets
+    (compiled with the host C compiler from include/gpf.h)."""
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    inc = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include")
+    structs = [gpf.gpf_grid, gpf.gpf_inputs, gpf.gpf_outputs]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gpf.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                  text=True).stdout.splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == C.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, f"{name}.{f}"
