@@ -35,6 +35,8 @@ class Surface:
     ds: np.ndarray
     edges: tuple = ()          # indices of sharp edges (plates: LE, TE)
     params: dict = field(default_factory=dict)
+    nx: np.ndarray | None = None   # unit normals into the fluid (None: zero-thickness body)
+    ny: np.ndarray | None = None
 
     @property
     def ns(self) -> int:
@@ -48,7 +50,8 @@ def cylinder(radius: float, ns: int, center=(0.0, 0.0)) -> Surface:
     ys = center[1] + radius * np.sin(th)
     ds = np.full(ns, 2.0 * np.pi * radius / ns)
     return Surface("cylinder", f32(xs), f32(ys), f32(ds), (),
-                   {"radius": radius, "center": center, "theta": th})
+                   {"radius": radius, "center": center, "theta": th},
+                   np.cos(th), np.sin(th))
 
 
 def flat_plate(chord: float, alpha_deg: float, ns: int, center=(0.0, 0.0)) -> Surface:
@@ -81,8 +84,12 @@ def ellipse(a: float, b: float, ns: int, rotation: float = 0.0, center=(0.0, 0.0
     xs = center[0] + c * x - s * y
     ys = center[1] + s * x + c * y
     ds = np.full(ns, perim / ns)
+    nxl, nyl = b * np.cos(tp), a * np.sin(tp)          # outward normal before rotation
+    nl = np.hypot(nxl, nyl)
+    nxl, nyl = nxl / nl, nyl / nl
     return Surface("ellipse", f32(xs), f32(ys), f32(ds), (),
-                   {"a": a, "b": b, "rotation": rotation, "center": center})
+                   {"a": a, "b": b, "rotation": rotation, "center": center},
+                   c * nxl - s * nyl, s * nxl + c * nyl)
 
 
 # ----------------------------------------------------------------------------
