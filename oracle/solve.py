@@ -238,7 +238,8 @@ def shed_step(p: Problem, body: Body, st: ShedState, dt: float, first, table=Non
     included, Gamma_w the sum of the strengths) also gives the velocity at
     them; they then take the strengths Gamma_j, and every vortex moves by
     x <- x + dt u(x).  An edge that shed zero keeps its last release.
-    Returns the new state and the solve's result.
+    Returns the new state, the solve's result and the problem it solved
+    (vortices before the move, new ones included with strength zero).
     """
     edges = list(p.edges)
     znew = []
@@ -257,4 +258,4 @@ def shed_step(p: Problem, body: Body, st: ShedState, dt: float, first, table=Non
     res = solve(q, body, table)
     G[nv:] = res.gamma_new
     last = [nv + j if res.gamma_new[j] != 0.0 else st.last[j] for j in range(len(edges))]
-    return ShedState(X + dt * res.u, Y + dt * res.v, G, last), res
+    return ShedState(X + dt * res.u, Y + dt * res.v, G, last), res, q
