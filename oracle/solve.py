@@ -256,6 +256,7 @@ def shed_step(p: Problem, body: Body, st: ShedState, dt: float, first, table=Non
     G = np.concatenate([st.G, np.zeros(len(edges))])
     q = Problem(**{**p.__dict__, "X": X, "Y": Y, "G": G, "znew": tuple(znew), "gamma_w": None})
     res = solve(q, body, table)
-    G[nv:] = res.gamma_new
+    G1 = G.copy()          # q keeps the new vortices at strength zero
+    G1[nv:] = res.gamma_new
     last = [nv + j if res.gamma_new[j] != 0.0 else st.last[j] for j in range(len(edges))]
-    return ShedState(X + dt * res.u, Y + dt * res.v, G, last), res, q
+    return ShedState(X + dt * res.u, Y + dt * res.v, G1, last), res, q
