@@ -259,6 +259,46 @@ def rk2_leg(gpf, torch, np, ctx, log, wl, steps=40):
     return out
 
 
+def shed_leg(gpf, torch, np, ctx, log, wl, steps=200):
+    """Forward Euler shedding on the 512^2 plate (1e4 vortices, a new vortex
+    at each edge per step, Kutta at both): ms per step with the state
+    resident on the device."""
+    case = wl.config2()
+    dt = 0.002
+    plan = gpf.Plan(ctx, case.n, case.dx, flags=gpf.GPF_POLICY_AUTO)
+    sf = case.surface
+    body = gpf.Body(plan, sf.xs, sf.ys, sf.ds, case.edges)
+    dev = torch.device("cuda", 0)
+    warm = 5
+    cap = case.nv + 2 * (warm + steps)
+    pad = lambda a: torch.as_tensor(np.r_[np.asarray(a, np.float64), np.zeros(cap - case.nv)],
+                                    dtype=torch.float64).to(dev)
+    X, Y, G = pad(case.X), pad(case.Y), pad(case.G)
+    u = torch.zeros(cap, dtype=torch.float64, device=dev)
+    v = torch.zeros(cap, dtype=torch.float64, device=dev)
+    psi = torch.empty((case.n, case.n), dtype=plan.field_dtype, device=dev)
+    sc = torch.zeros(gpf.N_SCALARS, dtype=torch.float64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    inp = gpf.make_inputs(X, Y, G, case.u_inf, case.v_inf, 0.0, 0.0, 0.0, "shed", 0.0, case.znew)
+    inp.nv = case.nv
+    out = gpf.make_outputs(psi, u, v, None, None, sc, status)
+    first = [(z[0] - sf.xs[k], z[1] - sf.ys[k]) for z, k in zip(case.znew, case.edges)]
+    sh = gpf.Shed(plan, body, inp, out, X, Y, G, dt, first)
+    sh.run(warm)
+    sh.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sh.run(steps)
+    sh.sync()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    log(f"[bench] shedding: {ms:.3f} ms/step, {sh.nv} vortices at the end")
+    res = {"workload": f"{case.name}, nv={case.nv}+2/step, dt={dt}", "ms_per_step": ms,
+           "steps": steps, "nv_end": sh.nv}
+    sh.close()
+    return res
+
+
 def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
     """64 independent problems of uneven size (n 128..1024, 1e3..1e5 vortices,
     ellipses): grid points per second batched vs solved one after another."""
@@ -550,6 +590,7 @@ def main() -> int:
     }
     res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
     res["rk2"] = rk2_leg(gpf, torch, np, ctx, log, wl)
+    res["shed"] = shed_leg(gpf, torch, np, ctx, log, wl)
     res["c4"] = c4_leg(gpf, torch, np, ctx, log, wl)
     res["c5"] = c5_leg(gpf, torch, np, ctx, log, wl)
     if not args.no_cpu_baseline:

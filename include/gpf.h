@@ -169,6 +169,16 @@ typedef struct {
                               [4..] strengths of the new vortices            */
   unsigned int *d_status;  /* device status word, OR-ed with GPF_DEV_* bits
                               (required; the caller clears it)                */
+  double *d_impulse;       /* 3 doubles (nullable): linear impulse P_x, P_y
+                              and angular impulse Pi_O about the origin of
+                              the fluid (eqs. linimpxd, linimpyd, angimpd):
+                              every vortex (new ones included) and the body's
+                              sheet plus its motion term, the surface
+                              velocity taken relative to the fluid at
+                              infinity.  Force and moment on a single body
+                              are -rho d(P, Pi_O)/dt (eq. FMimp).  With a
+                              body it needs d_f.  With zero total
+                              circulation it does not depend on the origin. */
 } gpf_outputs;
 
 /* Context bound to one HIP device. */
@@ -205,6 +215,28 @@ gpf_status gpf_body_info(const gpf_body *body, double *gamma0, double *amp,
 
 /* Copy the body's f0 = S^-1 1 (ns doubles) to host memory.  Blocking. */
 gpf_status gpf_body_f0(const gpf_body *body, double *h_f0);
+
+/* Unit surface normals pointing into the fluid (ns doubles each, host),
+ * used by the impulse's body-motion term and the body's area and centroid
+ * (appendix on discrete surfaces).  A body without normals (the default) is
+ * taken as having zero thickness, like a plate, whose two faces cancel in
+ * those terms.  Non-finite values: GPF_E_INVALID.  Blocking. */
+gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double *h_ny);
+
+/* Enclosed area V = (<x_s, n_x> + <y_s, n_y>)/2 and centroid
+ * X_c = <x_s^2 + y_s^2, n_x>/(2V), Y_c likewise with n_y (eq. centroid).
+ * Without normals: area 0 and the arc-length centroid of the points. */
+gpf_status gpf_body_geometry(const gpf_body *body, double *area, double *xc, double *yc);
+
+/* Added-mass tensor (Sec. 2.6.3), 3x3 row-major into h_m: rows are unit
+ * x translation, unit y translation and unit rotation about the origin,
+ * columns the force x, force y and moment about the centroid coefficients:
+ * rho (P_x, P_y, Pi_O - (X_c P_y - Y_c P_x)) of the sheet
+ * f = S^-1 P^Gamma s_b of that motion (no Kutta condition) with its motion
+ * term.  The rotation row and column follow the paper's formula, which
+ * keeps the rigid surface velocity in the motion term (a circle gives
+ * -pi a^4 rho there).  Blocking. */
+gpf_status gpf_body_added_mass(const gpf_body *body, double rho, double *h_m);
 
 /* One full solve (Sec. 2.2-2.4): R_v, L^-1, E_s, Schur and constraint
  * solve, R_s, L^-1, E_v.  body may be NULL only with GPF_NOBODY.
@@ -341,7 +373,10 @@ void gpf_rk2_destroy(gpf_rk2 *rk);
  * moves them all in place.  `out` names caller-owned buffers as for
  * gpf_solve, overwritten by every step: d_u and d_v (capacity doubles; the
  * velocities before the position update), d_scalars and d_status are
- * required, d_f and d_ftilde optional.  h_first holds 2m doubles (host).
+ * required, d_f and d_ftilde optional.  d_impulse, if set, is a history:
+ * step k since creation writes its impulse (after the solve, new vortices
+ * included, before the positions move) to d_impulse[3k..3k+2], so it must
+ * hold 3 (capacity - in->nv) / m doubles; it needs d_f.  h_first holds 2m doubles (host).
  * gpf_shed_run returns GPF_E_INVALID, enqueueing nothing, when the steps
  * would exceed the capacity.  A vortex that leaves the window sets
  * GPF_DEV_OUT_OF_GRID in the status word, and the results from then on

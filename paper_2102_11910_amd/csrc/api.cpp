@@ -235,7 +235,6 @@ gpf_status upload_spectrum(gpf_plan *p, DevBuf &spec, DevBuf &tw) {
   return GPF_OK;
 }
 
-constexpr int kMaxVortices = 1 << 22;
 constexpr int kPlanRingSlots = 64;
 constexpr size_t kProblemDescBytes = sizeof(ProbDesc) + 2 * sizeof(ConvDesc);
 
@@ -263,7 +262,7 @@ gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns) {
     GPF_TRY(s64.alloc(cells * 8));
   }
   GPF_TRY(zeroed(aux, AUX_BYTES));
-  GPF_TRY(part.alloc(sizeof(double) * (size_t)scatter_blocks(kMaxVortices)));
+  GPF_TRY(part.alloc(sizeof(double) * 4 * (size_t)kPartStride));
   if (nns > 0) {
     const size_t cols = 1 + GPF_MAX_EDGES;
     GPF_TRY(rhs.alloc(cols * nns * sizeof(double)));
@@ -376,6 +375,7 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.u = (out->d_u && out->d_v) ? out->d_u : nullptr;
   pd.v = out->d_v;
   pd.sc_out = out->d_scalars;
+  pd.imp_out = out->d_impulse;
   SolveScalars &sv = pd.sv;
   sv.u_inf = in->u_inf;
   sv.v_inf = in->v_inf;
@@ -440,6 +440,8 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.rhs = ws->rhs.as<double>();
   pd.f_out = out->d_f;
   pd.ft_out = out->d_ftilde;
+  pd.nx = b->nx.as<double>();
+  pd.ny = b->ny.as<double>();
   // first convolution: only its surface values are used
   c1.X = cfg.conv1_fp64 ? ws->x64.p : x2;
   c1.out = cfg.conv1_fp64 ? ws->s64.p : out->d_psi;
@@ -463,8 +465,8 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
 
 template <class TW, class T1, class T2>
 gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const ConvDesc *c1,
-                        const ConvDesc *c2, int nv_max, int ns_max, int m_max, int xcds,
-                        hipStream_t s) {
+                        const ConvDesc *c2, int nv_max, int ns_max, int m_max, bool impulse,
+                        int xcds, hipStream_t s) {
   GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
   GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body, s)));
   if (cfg.body) {
@@ -473,6 +475,7 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
     GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, false, s)));
   }
   GPF_HIP(launch_vortex_velocity<T2>(pd, nb, nv_max, s));
+  if (impulse) GPF_HIP(launch_impulse(pd, nb, s));
   return GPF_OK;
 }
 
@@ -485,11 +488,13 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   ConvDesc *c1 = reinterpret_cast<ConvDesc *>(blk.data() + nb * sizeof(ProbDesc));
   ConvDesc *c2 = c1 + nb;
   int nv_max = 0, ns_max = 0, m_max = 0;
+  bool impulse = false;
   for (int i = 0; i < nb; ++i) {
     describe(probs[i], cfg, pd[i], c1[i], c2[i]);
     nv_max = std::max(nv_max, pd[i].nv);
     ns_max = std::max(ns_max, pd[i].ns);
     m_max = std::max(m_max, pd[i].sv.m);
+    impulse = impulse || pd[i].imp_out != nullptr;
   }
   void *dev = nullptr;
   GPF_TRY(ring.push(blk.data(), blk.size(), s, &dev));
@@ -498,16 +503,21 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
       reinterpret_cast<const ConvDesc *>(static_cast<char *>(dev) + nb * sizeof(ProbDesc));
   const ConvDesc *dc2 = dc1 + nb;
   if (cfg.fp64_plan)
-    return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, xcds, s);
+    return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
+                                                   xcds, s);
   if (cfg.conv1_fp64)
-    return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, xcds, s);
-  return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, xcds, s);
+    return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
+                                                   xcds, s);
+  return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
+                                                   xcds, s);
 }
 
 gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
                     const gpf_outputs *out) {
   if (!plan || !in || !out) return fail(GPF_E_INVALID, "solve: null argument");
   if (!out->d_psi || !out->d_status) return fail(GPF_E_INVALID, "solve: d_psi and d_status are required");
+  if (out->d_impulse && in->mode != GPF_NOBODY && !out->d_f)
+    return fail(GPF_E_INVALID, "solve: the impulse with a body needs d_f");
   if (in->nv < 0 || in->nv > kMaxVortices) return fail(GPF_E_UNSUPPORTED, "solve: nv must be in [0, 2^22]");
   if (in->nv > 0 && (!in->d_xv || !in->d_yv || !in->d_gv))
     return fail(GPF_E_INVALID, "solve: null vortex arrays");
@@ -656,6 +666,24 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   GPF_TRY(b->sinv.alloc((size_t)ns * vb));
   GPF_TRY(b->f0.alloc(vb));
   GPF_TRY(b->ghat.alloc(vb));
+  GPF_TRY(b->nx.alloc(vb));
+  GPF_TRY(b->ny.alloc(vb));
+  GPF_HIP(hipMemset(b->nx.p, 0, vb));
+  GPF_HIP(hipMemset(b->ny.p, 0, vb));
+  b->hxs.assign(h_xs, h_xs + ns);
+  b->hys.assign(h_ys, h_ys + ns);
+  b->hds.assign(h_ds, h_ds + ns);
+  {
+    // no normals yet: zero area, arc-length centroid
+    double L = 0.0, sx = 0.0, sy = 0.0;
+    for (int p = 0; p < ns; ++p) {
+      L += h_ds[p];
+      sx += h_ds[p] * h_xs[p];
+      sy += h_ds[p] * h_ys[p];
+    }
+    b->xc = sx / L;
+    b->yc = sy / L;
+  }
   GPF_TRY(plan->ws.ensure(g.n, !plan->fp64, plan->fp64, ns));
   GPF_HIP(hipMemcpy(b->xs.p, h_xs, vb, hipMemcpyHostToDevice));
   GPF_HIP(hipMemcpy(b->ys.p, h_ys, vb, hipMemcpyHostToDevice));
@@ -718,6 +746,7 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
                                   ((plan->flags & GPF_POLICY_AUTO) && b->amp > GPF_AMP_THRESHOLD));
   if (b->conv1_fp64) GPF_TRY(plan->ensure_fp64());
   GPF_HIP(hipMemcpy(b->f0.p, Y.data(), vb, hipMemcpyHostToDevice));
+  b->hf0.assign(Y.begin(), Y.begin() + ns);
   GPF_HIP(launch_gemv_t(ns, b->sinv.as<double>(), b->ds.as<double>(), b->ghat.as<double>(), s));
   GPF_HIP(hipDeviceSynchronize());
   *out = b.release();
@@ -737,6 +766,103 @@ gpf_status gpf_body_info(const gpf_body *body, double *gamma0, double *amp, int 
 gpf_status gpf_body_f0(const gpf_body *body, double *h_f0) {
   if (!body || !h_f0) return fail(GPF_E_INVALID, "gpf_body_f0: null argument");
   GPF_HIP(hipMemcpy(h_f0, body->f0.p, body->ns * sizeof(double), hipMemcpyDeviceToHost));
+  return GPF_OK;
+}
+
+gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double *h_ny) {
+  if (!body || !h_nx || !h_ny) return fail(GPF_E_INVALID, "gpf_body_set_normals: null argument");
+  const int ns = body->ns;
+  for (int p = 0; p < ns; ++p)
+    if (!is_finite(h_nx[p]) || !is_finite(h_ny[p]))
+      return fail(GPF_E_INVALID, "gpf_body_set_normals: non-finite normal");
+  GPF_HIP(hipSetDevice(body->plan->ctx->device));
+  GPF_HIP(hipMemcpy(body->nx.p, h_nx, ns * sizeof(double), hipMemcpyHostToDevice));
+  GPF_HIP(hipMemcpy(body->ny.p, h_ny, ns * sizeof(double), hipMemcpyHostToDevice));
+  // area and centroid (eq. centroid); the area as the mean of its two forms
+  double vx = 0.0, vy = 0.0, cx = 0.0, cy = 0.0;
+  for (int p = 0; p < ns; ++p) {
+    const double x = body->hxs[p], y = body->hys[p], w = body->hds[p];
+    const double r2 = x * x + y * y;
+    vx += w * x * h_nx[p];
+    vy += w * y * h_ny[p];
+    cx += w * r2 * h_nx[p];
+    cy += w * r2 * h_ny[p];
+  }
+  const double V = 0.5 * (vx + vy);
+  body->has_normals = true;
+  body->area = V;
+  if (V != 0.0) {
+    body->xc = cx / (2.0 * V);
+    body->yc = cy / (2.0 * V);
+  }
+  return GPF_OK;
+}
+
+gpf_status gpf_body_geometry(const gpf_body *body, double *area, double *xc, double *yc) {
+  if (!body) return fail(GPF_E_INVALID, "gpf_body_geometry: null body");
+  if (area) *area = body->area;
+  if (xc) *xc = body->xc;
+  if (yc) *yc = body->yc;
+  return GPF_OK;
+}
+
+gpf_status gpf_body_added_mass(const gpf_body *body, double rho, double *h_m) {
+  if (!body || !h_m || !is_finite(rho)) return fail(GPF_E_INVALID, "gpf_body_added_mass: bad arguments");
+  const int ns = body->ns;
+  GPF_HIP(hipSetDevice(body->plan->ctx->device));
+  // surface streamfunctions of the unit motions, circulation removed:
+  // P^Gamma s = s - 1 (fhat0 . s)/Gamma0
+  std::vector<double> X(3 * (size_t)ns);
+  for (int p = 0; p < ns; ++p) {
+    const double x = body->hxs[p], y = body->hys[p];
+    X[p] = y;
+    X[ns + p] = -x;
+    X[2 * ns + p] = -0.5 * (x * x + y * y);
+  }
+  for (int c = 0; c < 3; ++c) {
+    double fs = 0.0;
+    for (int p = 0; p < ns; ++p) fs += body->hds[p] * body->hf0[p] * X[c * ns + p];
+    const double sh = fs / body->gamma0;
+    for (int p = 0; p < ns; ++p) X[c * ns + p] -= sh;
+  }
+  const size_t vb = ns * sizeof(double);
+  DevBuf dX, dF, dImp, dDesc;
+  GPF_TRY(dX.alloc(3 * vb));
+  GPF_TRY(dF.alloc(3 * vb));
+  GPF_TRY(dImp.alloc(9 * sizeof(double)));
+  GPF_TRY(dDesc.alloc(3 * sizeof(ProbDesc)));
+  hipStream_t s = nullptr;
+  GPF_HIP(hipMemcpy(dX.p, X.data(), 3 * vb, hipMemcpyHostToDevice));
+  GPF_HIP(launch_gemv(ns, 3, body->sinv.as<double>(), dX.as<double>(), dF.as<double>(), s));
+  // the impulse of each sheet with its motion (no vortices)
+  ProbDesc pd[3];
+  const double motion[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};  // ub, vb, omega
+  for (int c = 0; c < 3; ++c) {
+    std::memset(&pd[c], 0, sizeof(ProbDesc));
+    pd[c].ns = ns;
+    pd[c].xs = body->xs.as<double>();
+    pd[c].ys = body->ys.as<double>();
+    pd[c].ds = body->ds.as<double>();
+    pd[c].nx = body->nx.as<double>();
+    pd[c].ny = body->ny.as<double>();
+    pd[c].f_out = dF.as<double>() + (size_t)c * ns;
+    pd[c].imp_out = dImp.as<double>() + 3 * c;
+    pd[c].sv.mode = GPF_NOBODY;
+    pd[c].sv.ub = motion[c][0];
+    pd[c].sv.vb = motion[c][1];
+    pd[c].sv.omega = motion[c][2];
+    pd[c].sv.znew_from = -1;
+  }
+  GPF_HIP(hipMemcpy(dDesc.p, pd, sizeof(pd), hipMemcpyHostToDevice));
+  GPF_HIP(launch_impulse(static_cast<const ProbDesc *>(dDesc.p), 3, s));
+  double imp[9];
+  GPF_HIP(hipMemcpy(imp, dImp.p, sizeof(imp), hipMemcpyDeviceToHost));
+  for (int c = 0; c < 3; ++c) {
+    const double px = imp[3 * c], py = imp[3 * c + 1], pi = imp[3 * c + 2];
+    h_m[3 * c] = rho * px;
+    h_m[3 * c + 1] = rho * py;
+    h_m[3 * c + 2] = rho * (pi - (body->xc * py - body->yc * px));
+  }
   return GPF_OK;
 }
 
@@ -1143,13 +1269,16 @@ gpf_status shed_enqueue(gpf_shed *sh, const ShedGeom &geom, hipStream_t s) {
   int *last = sh->last.as<int>();
   GPF_HIP(launch_shed_place(geom, sh->nv, last, x, y, g, s));
   sh->in.nv = nv;
-  ProblemRef r{plan, sh->body, &sh->in, &sh->out, &plan->ws, sh->nv};
+  gpf_outputs o = sh->out;   // the impulse, if asked for, goes to this step's row
+  if (o.d_impulse) o.d_impulse += 3 * (size_t)sh->steps;
+  ProblemRef r{plan, sh->body, &sh->in, &o, &plan->ws, sh->nv};
   const GroupCfg cfg = config_of(r);
   std::vector<ProblemRef> one{r};
   GPF_TRY(run_group(cfg, one, plan->ring, plan->ctx->xcds, s));
   GPF_HIP(launch_shed_advance(sh->m, nv, sh->out.d_scalars, last, x, y, g, sh->out.d_u,
                               sh->out.d_v, sh->dt, s));
   sh->nv = nv;
+  ++sh->steps;
   return GPF_OK;
 }
 

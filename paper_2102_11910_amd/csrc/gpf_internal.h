@@ -181,6 +181,8 @@ struct ProbDesc {
   // outputs (nullable)
   const void *psi;              // final field (velocities read it)
   double *u, *v, *f_out, *ft_out, *sc_out;
+  double *imp_out;              // impulse (P_x, P_y, Pi_O), or null
+  const double *nx, *ny;        // body normals into the fluid (zeros: thin body)
   int psi_total;                // psi holds s + s_inf: velocities add no U_inf
   SolveScalars sv;
 };
@@ -189,6 +191,10 @@ struct ProbDesc {
 // kernel launchers (asynchronous on `s`; `nb` problems, same n)
 // ---------------------------------------------------------------------------
 int scatter_blocks(int nv_max);
+// binning partials per workgroup of vortices, four planes of kPartStride:
+// sum Gamma, sum Gamma x, sum Gamma y, sum Gamma (x^2 + y^2)
+constexpr int kMaxVortices = 1 << 22;
+constexpr int kPartStride = kMaxVortices / 256;
 int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n < 32)
 // R_v: bin and sort the vortices by tile, then one workgroup per tile sums
 // its vortices in an LDS window and adds the window to the source field
@@ -234,6 +240,8 @@ gpf_status invert_fp64(int ns, double *A, double *Ainv, hipStream_t s, double *m
 hipError_t launch_gemv(int ns, int ncol, const double *A, const double *X, double *Y,
                        hipStream_t s);
 hipError_t launch_gemv_t(int ns, const double *A, const double *x, double *y, hipStream_t s);
+// impulse of each problem whose imp_out is set (after the surface solve)
+hipError_t launch_impulse(const ProbDesc *d, int nb, hipStream_t s);
 
 }  // namespace gpf
 
@@ -297,6 +305,10 @@ struct gpf_body {
   gpf::DevBuf sinv;           // ns x ns S^-1, row-major, FP64
   gpf::DevBuf f0;             // S^-1 1
   gpf::DevBuf ghat;           // S^-T dS
+  gpf::DevBuf nx, ny;         // unit normals into the fluid (zeros until set)
+  bool has_normals = false;
+  double area = 0.0, xc = 0.0, yc = 0.0;   // enclosed area and centroid
+  std::vector<double> hxs, hys, hds, hf0;  // host copies of the geometry and f0
   double mom_x = 0.0, mom_y = 0.0, mom_r2 = 0.0;  // moments of fhat0 = dS f0
 };
 
@@ -320,6 +332,7 @@ struct gpf_shed {
   gpf_inputs in{};
   gpf_outputs out{};
   int nv = 0, capacity = 0, m = 0;
+  int steps = 0;   // steps enqueued so far
   double dt = 0.0;
   double first[2 * GPF_MAX_EDGES] = {};     // offsets of each edge's first release
   double edge_xy[2 * GPF_MAX_EDGES] = {};   // edge points

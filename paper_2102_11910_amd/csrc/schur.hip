@@ -165,6 +165,70 @@ __global__ __launch_bounds__(256) void k_gemv_t(int ns, const double *__restrict
   y[q] = acc;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Impulse about the origin (eqs. linimpxd, linimpyd, angimpd), one
+// workgroup per problem that asks for it.  The node inner products of the
+// regularized vortices equal the point sums (the M4' weights reproduce x, y
+// and x^2 + y^2), so the fluid part comes from the moments that binning
+// already summed per workgroup; new vortices add their strengths at their
+// positions; the body adds dS (f + n_x v_y - n_y v_x), with the surface
+// velocity relative to the fluid at infinity.
+__global__ __launch_bounds__(256) void k_impulse(const ProbDesc *__restrict__ d) {
+  const ProbDesc &P = d[blockIdx.y];
+  if (!P.imp_out) return;
+  __shared__ double red[3][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SolveScalars &sv = P.sv;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;   // sums of (y, x, x^2 + y^2) times strength
+  const int nvb = (P.nv + 255) / 256;
+  for (int b = tid; b < nvb; b += 256) {
+    a0 += P.partials[2 * (size_t)kPartStride + b];
+    a1 += P.partials[1 * (size_t)kPartStride + b];
+    a2 += P.partials[3 * (size_t)kPartStride + b];
+  }
+  if (sv.mode == GPF_KUTTA_SHED && tid < sv.m) {
+    const double g = P.aux[SC_GAMMA_NEW + tid];
+    const double x = sv.znew_from >= 0 ? P.xv[sv.znew_from + tid] : sv.xnew[tid];
+    const double y = sv.znew_from >= 0 ? P.yv[sv.znew_from + tid] : sv.ynew[tid];
+    a0 += g * y;
+    a1 += g * x;
+    a2 += g * (x * x + y * y);
+  }
+  if (P.ns > 0 && P.f_out) {
+    const double ux = sv.ub - sv.u_inf, uy = sv.vb - sv.v_inf, om = sv.omega;
+    for (int p = tid; p < P.ns; p += 256) {
+      const double x = P.xs[p], y = P.ys[p];
+      const double vx = ux - om * y, vy = uy + om * x;
+      const double q = P.ds[p] * (P.f_out[p] + P.nx[p] * vy - P.ny[p] * vx);
+      a0 += y * q;
+      a1 += x * q;
+      a2 += (x * x + y * y) * q;
+    }
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    red[0][wave] = a0;
+    red[1][wave] = a1;
+    red[2][wave] = a2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double s0 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double s1 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const double s2 = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    P.imp_out[0] = s0;
+    P.imp_out[1] = -s1;
+    P.imp_out[2] = -0.5 * s2;
+  }
+}
+
 // rhs[:,0] = s_b' - E_s s*;  rhs[:,1+j] = (E_s L^-1 d_j) by direct LGF sums.
 // Blocks [0, nbe) give one thread per surface point for the first column;
 // the remaining blocks give 16 lanes per (point, new vortex) pair, one lane
@@ -238,11 +302,6 @@ __global__ __launch_bounds__(kRB) void k_surface_rhs(const ProbDesc *__restrict_
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
 
 // Surface solve of one batch in one launch.  Every scalar the constraint
 // modes need is a dot product with the rhs columns: the circulations
@@ -563,6 +622,11 @@ gpf_status invert_fp64(int ns, double *A, double *Ainv, hipStream_t s, double *m
 hipError_t launch_gemv(int ns, int ncol, const double *A, const double *X, double *Y,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_gemv, dim3((ns + 3) / 4), dim3(256), 0, s, ns, ncol, A, X, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_impulse(const ProbDesc *d, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_impulse, dim3(1, nb), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 

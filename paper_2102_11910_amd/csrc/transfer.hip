@@ -57,6 +57,7 @@ __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 constexpr int kScatterBlock = 256;
+static_assert(kPartStride * kScatterBlock == kMaxVortices, "one partial per bin_count workgroup");
 
 __global__ void k_fill(unsigned *p, size_t words) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
@@ -82,20 +83,22 @@ __device__ __forceinline__ int vortex_tile(int i0, int j0, int ts, int tps) {
 //    workgroup.  Each workgroup also stores its partial circulation.
 __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__restrict__ d) {
   __shared__ int hist[kMaxTiles];
-  __shared__ double red[kScatterBlock / 64];
+  __shared__ double red[4][kScatterBlock / 64];
   const ProbDesc &P = d[blockIdx.y];
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
   for (int t = threadIdx.x; t < ntiles; t += kScatterBlock) hist[t] = 0;
   __syncthreads();
   const int q = blockIdx.x * kScatterBlock + threadIdx.x;
-  double gq = 0.0;
+  double gq = 0.0, xq = 0.0, yq = 0.0;
   int tile = -1, lrank = 0;
   if (q < P.nv) {
     int i0, j0;
     double fx, fy;
-    if (cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx) &&
-        cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy)) {
+    const double x = P.xv[q], y = P.yv[q];
+    if (cell(x, P.x0, P.dx, 2, n - 3, &i0, &fx) && cell(y, P.y0, P.dx, 2, n - 3, &j0, &fy)) {
       gq = P.gv[q];
+      xq = x;
+      yq = y;
       tile = vortex_tile(i0, j0, ts, tps);
       lrank = atomicAdd(hist + tile, 1);
     } else {
@@ -123,14 +126,23 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
   }
   __syncthreads();
   if (q < P.nv) P.rank[q] = tile >= 0 ? hist[tile] + lrank : -1;
+  // circulation and its first and second moments (the impulse of the
+  // vortices: the M4' weights reproduce x, y and x^2 + y^2 exactly)
+  double mom[4] = {gq, gq * xq, gq * yq, gq * (xq * xq + yq * yq)};
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) gq += __shfl_xor(gq, off);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gq;
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mom[c] += __shfl_xor(mom[c], off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][threadIdx.x >> 6] = mom[c];
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 4) {
     double s = 0.0;
-    for (int w = 0; w < kScatterBlock / 64; ++w) s += red[w];
-    P.partials[blockIdx.x] = s;
+    for (int w = 0; w < kScatterBlock / 64; ++w) s += red[threadIdx.x][w];
+    P.partials[(size_t)threadIdx.x * kPartStride + blockIdx.x] = s;
   }
 }
 

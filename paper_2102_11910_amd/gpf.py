@@ -69,7 +69,7 @@ class gpf_inputs(C.Structure):
 class gpf_outputs(C.Structure):
     _fields_ = [("d_psi", C.c_void_p), ("d_u", C.c_void_p), ("d_v", C.c_void_p),
                 ("d_f", C.c_void_p), ("d_ftilde", C.c_void_p), ("d_scalars", C.c_void_p),
-                ("d_status", C.c_void_p)]
+                ("d_status", C.c_void_p), ("d_impulse", C.c_void_p)]
 
 
 def _load():
@@ -94,6 +94,9 @@ def _load():
         "gpf_body_destroy": (None, [P]),
         "gpf_body_info": (I, [P, DP, DP, C.POINTER(C.c_int)]),
         "gpf_body_f0": (I, [P, DP]),
+        "gpf_body_set_normals": (I, [P, DP, DP]),
+        "gpf_body_geometry": (I, [P, DP, DP, DP]),
+        "gpf_body_added_mass": (I, [P, D, DP]),
         "gpf_solve": (I, [P, P, C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
         "gpf_regularize_vortices": (I, [P, I, P, P, P, P, I, P, P]),
         "gpf_convolve": (I, [P, P, P, D, P]),
@@ -258,6 +261,26 @@ class Body:
         check(lib.gpf_body_f0(self.h, out.ctypes.data_as(C.POINTER(C.c_double))), "gpf_body_f0")
         return out
 
+    def set_normals(self, nx, ny):
+        ax, px = _dp(nx)
+        ay, py = _dp(ny)
+        assert len(ax) == len(ay) == self.ns
+        check(lib.gpf_body_set_normals(self.h, px, py), "gpf_body_set_normals")
+
+    def geometry(self):
+        """(area, x_c, y_c)."""
+        v = [C.c_double() for _ in range(3)]
+        check(lib.gpf_body_geometry(self.h, *[C.byref(a) for a in v]), "gpf_body_geometry")
+        return tuple(a.value for a in v)
+
+    def added_mass(self, rho: float = 1.0):
+        """3x3 added-mass tensor (rows: x, y, rotation; columns: F_x, F_y, M)."""
+        import numpy as np
+        out = np.zeros(9)
+        check(lib.gpf_body_added_mass(self.h, float(rho), out.ctypes.data_as(C.POINTER(C.c_double))),
+              "gpf_body_added_mass")
+        return out.reshape(3, 3)
+
     def close(self):
         if self.h:
             lib.gpf_body_destroy(self.h)
@@ -293,7 +316,8 @@ def make_inputs(X, Y, G, u_inf=0.0, v_inf=0.0, ub=0.0, vb=0.0, omega=0.0, mode="
     return inp
 
 
-def make_outputs(psi, u=None, v=None, f=None, ftilde=None, scalars=None, status=None) -> gpf_outputs:
+def make_outputs(psi, u=None, v=None, f=None, ftilde=None, scalars=None, status=None,
+                 impulse=None) -> gpf_outputs:
     out = gpf_outputs()
     out.d_psi = psi.data_ptr()
     out.d_u = None if u is None else u.data_ptr()
@@ -302,6 +326,7 @@ def make_outputs(psi, u=None, v=None, f=None, ftilde=None, scalars=None, status=
     out.d_ftilde = None if ftilde is None else ftilde.data_ptr()
     out.d_scalars = None if scalars is None else scalars.data_ptr()
     out.d_status = status.data_ptr()
+    out.d_impulse = None if impulse is None else impulse.data_ptr()
     return out
 
 

@@ -50,7 +50,7 @@ def loop_case(seed, nv, keep=0.6):
 class Run:
     """A GPU shedding run and the matching oracle objects."""
 
-    def __init__(self, ctx, case, flags, dt, capacity):
+    def __init__(self, ctx, case, flags, dt, capacity, impulse_rows=0):
         self.case, self.dt = case, dt
         self.plan = gpf.Plan(ctx, case.n, case.dx, flags=flags)
         sf = case.surface
@@ -70,7 +70,10 @@ class Run:
         inp = gpf.make_inputs(self.X, self.Y, self.G, case.u_inf, case.v_inf, case.ub, case.vb,
                               case.omega, case.mode, 0.0, case.znew, None, case.fbounds)
         inp.nv = nv
-        out = gpf.make_outputs(self.psi, self.u, self.v, self.f, self.ft, self.sc, self.status)
+        self.imp = (torch.zeros(3 * impulse_rows, dtype=torch.float64, device=DEV)
+                    if impulse_rows else None)
+        out = gpf.make_outputs(self.psi, self.u, self.v, self.f, self.ft, self.sc, self.status,
+                               self.imp)
         self.shed = gpf.Shed(self.plan, self.body, inp, out, self.X, self.Y, self.G, dt, self.first)
         self.p = problem_of(case)
         self.obody = body_of(case)
@@ -101,7 +104,7 @@ def _per_step(run, steps, tol_x, tol_g, label):
     last = [-1] * m
     for k in range(steps):
         X0, Y0, G0 = run.state()
-        ost, res = shed_step(run.p, run.obody, ShedState(X0, Y0, G0, list(last)), run.dt,
+        ost, res, _ = shed_step(run.p, run.obody, ShedState(X0, Y0, G0, list(last)), run.dt,
                              run.first)
         run.step()
         got = run.state()
@@ -139,7 +142,7 @@ def test_shedding_trajectory_fp64(ctx):
     st = ShedState(np.asarray(case.X, np.float64), np.asarray(case.Y, np.float64),
                    np.asarray(case.G, np.float64), [-1, -1])
     for _ in range(6):
-        st, res = shed_step(run.p, run.obody, st, run.dt, run.first)
+        st, res, _ = shed_step(run.p, run.obody, st, run.dt, run.first)
     ex = np.max(np.abs(np.r_[X - st.X, Y - st.Y]))
     eg = np.max(np.abs(G - st.G)) / np.max(np.abs(st.G))
     say(f"   trajectory: x {ex:.2e}, G {eg:.2e}")
@@ -186,3 +189,27 @@ def test_shed_create_rejects_bad_arguments(ctx):
     with pytest.raises(gpf.GpfError) as e:
         Run(ctx, case, gpf.GPF_FP64, dt=0.01, capacity=case.nv + 8)
     assert e.value.status == gpf.GPF_E_INVALID
+
+
+def test_shedding_impulse_history(ctx):
+    """Each step writes its impulse to its own row; each row matches the
+    oracle's impulse of that step's solve from the same state."""
+    from oracle.impulse import solution_impulse
+    say("[shed] impulse history")
+    case = loop_case(135, 300)
+    steps = 4
+    run = Run(ctx, case, gpf.GPF_FP64, dt=0.005, capacity=case.nv + 2 * steps,
+              impulse_rows=steps)
+    last = [-1, -1]
+    for k in range(steps):
+        X0, Y0, G0 = run.state()
+        ost, res, q = shed_step(run.p, run.obody, ShedState(X0, Y0, G0, list(last)), run.dt,
+                                run.first)
+        run.step()
+        run.state()
+        got = run.imp[3 * k:3 * k + 3].cpu().numpy()
+        ref = solution_impulse(q, run.obody, res)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        say(f"   step {k}: impulse {got} err {err:.2e}")
+        assert err <= 1e-9
+        last = ost.last
