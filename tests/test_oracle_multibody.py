@@ -1,0 +1,173 @@
+"""Pins of the oracle's several-body solve (Sec. 2.7, eq. kuttasystem4).
+
+* one body: the bordered elimination gives the single-body solves of every
+  mode (a separate formulation: the paper's closed forms with P_k and S~);
+* two bodies: one dense solve of the bordered system assembled from its
+  rows (no-penetration with a uniform value per body, then per body its
+  circulation, steady-Kutta or Kelvin row and per new vortex its edge row)
+  on a tiny grid equals the elimination;
+* mirror symmetry: two cylinders mirror images of each other, with mirrored
+  vortices of opposite strength and a uniform flow along the mirror line,
+  carry opposite sheets and uniform values at mirrored points (the
+  streamfunction is odd under the reflection);
+* Kelvin per body and the edge rows hold.
+"""
+import numpy as np
+import pytest
+
+from oracle.body import body_setup
+from oracle.multibody import BodySpec, MultiProblem, solve_multi
+from oracle.operators import Grid, regularize_vortices, surface_matrix, unit_vortex
+from oracle.solve import Problem, solve, surface_rhs
+from paper_2102_11910_amd import workloads as wl
+from tests.oracle_adapter import body_of, problem_of
+from tests.test_oracle_solve import dense_inverse_laplacian
+
+FREE = (-1e30, 1e30)
+
+
+def _single_as_multi(case):
+    p = problem_of(case)
+    spec = BodySpec(mode=case.mode, gamma_b=case.gamma_b, ub=case.ub, vb=case.vb,
+                    omega=case.omega, edges=tuple(case.edges), znew=tuple(case.znew),
+                    gamma_w=float(np.sum(p.G)), fbounds=tuple(case.fbounds))
+    return MultiProblem(p.grid, p.X, p.Y, p.G, [spec], p.u_inf, p.v_inf)
+
+
+@pytest.mark.parametrize("surface,mode,fb", [("cylinder", "circulation", ()),
+                                             ("plate", "kutta", ()),
+                                             ("plate", "shed", ()),
+                                             ("plate", "shed", ((0.2, 0.2), FREE))])
+def test_one_body_equals_single_body_solve(surface, mode, fb):
+    case = wl.random_case(61, 64, 0.04, 40, surface=surface, mode=mode)
+    case.fbounds = fb
+    p, body = problem_of(case), body_of(case)
+    ref = solve(p, body)
+    got = solve_multi(_single_as_multi(case), body, np.zeros(case.surface.ns, int))
+    sc = np.max(np.abs(ref.f))
+    assert np.max(np.abs(got.f - ref.f)) <= 1e-10 * sc
+    assert np.max(np.abs(got.s - ref.s)) <= 1e-10 * np.max(np.abs(ref.s))
+    assert np.max(np.abs(np.r_[got.u - ref.u, got.v - ref.v])) <= 1e-10 * np.max(np.abs(ref.u))
+    if mode == "shed":
+        assert np.max(np.abs(got.gamma_new - ref.gamma_new)) <= 1e-10 * max(1, np.max(np.abs(ref.gamma_new)))
+    # s0: the same up to the circulation projection of s_b' in the single-body form
+    c1 = 0.0 if mode == "circulation" else np.dot(body.fhat0, surface_rhs(p, body)) / body.gamma0
+    assert abs(got.s0[0] - (ref.s0 + c1)) <= 1e-10 * max(1.0, abs(ref.s0))
+
+
+def _two_bodies(n=28, dx=0.1):
+    """A small cylinder and a short plate side by side on a tiny grid."""
+    grid = Grid.centered(n, dx)
+    cyl = wl.cylinder(0.35, 14, center=(-0.55, 0.1))
+    pl = wl.flat_plate(0.7, 20.0, 6, center=(0.6, -0.1))
+    xs = np.r_[cyl.xs, pl.xs]
+    ys = np.r_[cyl.ys, pl.ys]
+    ds = np.r_[cyl.ds, pl.ds]
+    part = np.r_[np.zeros(cyl.ns, int), np.ones(pl.ns, int)]
+    le, te = cyl.ns + pl.edges[0], cyl.ns + pl.edges[1]
+    rng = np.random.default_rng(7)
+    X = np.array([-0.2, 0.1, 1.0]) + 0.01 * rng.normal(size=3)
+    Y = np.array([0.8, -0.9, 0.6])
+    G = np.array([0.3, -0.5, 0.2])
+    return grid, xs, ys, ds, part, le, te, X, Y, G
+
+
+def _brute(grid, xs, ys, ds, part, p, specs):
+    """Dense bordered system in (f, s0_j, Gamma_i)."""
+    ns = len(xs)
+    nb = len(specs)
+    Linv = dense_inverse_laplacian(grid)
+    E, nodes = surface_matrix(grid, xs, ys)
+    Es = np.zeros((ns, grid.n * grid.n))
+    Es[:, nodes[:, 1] * grid.n + nodes[:, 0]] = E
+    Rs = Es.T * (ds[None, :] / grid.dx ** 2)
+    w = regularize_vortices(grid, p.X, p.Y, p.G).ravel()
+    body = body_setup(grid, xs, ys, ds)
+    edges = [(j, k, z, (b.fbounds[i] if b.fbounds else (0.0, 0.0)))
+             for j, b in enumerate(specs) if b.mode == "shed"
+             for i, (k, z) in enumerate(zip(b.edges, b.znew))]
+    m = len(edges)
+    N = ns + nb + m
+    A = np.zeros((N, N))
+    r = np.zeros(N)
+    sb = np.empty(ns)
+    for j, b in enumerate(specs):
+        on = part == j
+        sb[on] = ((b.ub - p.u_inf) * ys[on] - (b.vb - p.v_inf) * xs[on]
+                  - 0.5 * b.omega * (xs[on] ** 2 + ys[on] ** 2))
+    A[:ns, :ns] = -Es @ Linv @ Rs
+    for j in range(nb):
+        A[:ns, ns + j] = (part == j)
+    for i, (_, _, z, _) in enumerate(edges):
+        A[:ns, ns + nb + i] = -Es @ (Linv @ unit_vortex(grid, z[0], z[1]).ravel())
+    r[:ns] = sb + Es @ (Linv @ w)
+    for j, b in enumerate(specs):
+        row = ns + j
+        if b.mode == "kutta":
+            A[row, b.edges[0]] = 1.0
+        else:
+            A[row, :ns] = ds * (part == j)
+            if b.mode == "circulation":
+                r[row] = b.gamma_b
+            else:
+                for i, e in enumerate(edges):
+                    if e[0] == j:
+                        A[row, ns + nb + i] = 1.0
+                r[row] = -b.gamma_w
+    for i, (j, k, z, (lo, hi)) in enumerate(edges):
+        row = ns + nb + i
+        if lo == hi:
+            A[row, k] = 1.0
+            r[row] = body.f0[k] * lo
+        else:
+            A[row, ns + nb + i] = 1.0
+    x = np.linalg.solve(A, r)
+    return body, x[:ns], x[ns:ns + nb], x[ns + nb:]
+
+
+@pytest.mark.parametrize("plate_mode,fb", [("shed", ()), ("shed", ((0.3, 0.3), FREE)),
+                                            ("kutta", ()), ("circulation", ())])
+def test_two_bodies_equal_brute_force(plate_mode, fb):
+    grid, xs, ys, ds, part, le, te, X, Y, G = _two_bodies()
+    specs = [BodySpec("circulation", gamma_b=0.25, ub=0.1, omega=0.2)]
+    if plate_mode == "shed":
+        specs.append(BodySpec("shed", vb=-0.1, edges=(le, te),
+                              znew=((0.6 - 0.5, 0.18), (0.6 + 0.5, -0.3)),
+                              gamma_w=0.05, fbounds=fb))
+    elif plate_mode == "kutta":
+        specs.append(BodySpec("kutta", edges=(te,)))
+    else:
+        specs.append(BodySpec("circulation", gamma_b=-0.4))
+    p = MultiProblem(grid, X, Y, G, specs, u_inf=1.0, v_inf=0.2)
+    body, f, s0, gam = _brute(grid, xs, ys, ds, part, p, specs)
+    got = solve_multi(p, body, part)
+    assert np.max(np.abs(got.f - f)) <= 1e-10 * np.max(np.abs(f))
+    assert np.max(np.abs(got.s0 - s0)) <= 1e-10 * max(1.0, np.max(np.abs(s0)))
+    if len(gam):
+        assert np.max(np.abs(got.gamma_new - gam)) <= 1e-10 * max(1.0, np.max(np.abs(gam)))
+    # rows hold
+    assert abs(got.gamma_b[0] - 0.25) <= 1e-12
+    if plate_mode == "shed":
+        assert abs(got.gamma_b[1] + got.gamma_new.sum() + 0.05) <= 1e-12
+    if plate_mode == "kutta":
+        assert abs(got.ftilde[te]) <= 1e-12
+
+
+def test_mirror_images_carry_opposite_sheets():
+    grid = Grid.centered(96, 0.04)
+    th = 2 * np.pi * (np.arange(40) + 0.5) / 40
+    x1 = wl.f32(-0.8 + 0.4 * np.cos(th))
+    y1 = wl.f32(0.4 * np.sin(th))
+    xs, ys = np.r_[x1, -x1], np.r_[y1, y1]
+    ds = np.full(80, 2 * np.pi * 0.4 / 40)
+    part = np.r_[np.zeros(40, int), np.ones(40, int)]
+    body = body_setup(grid, xs, ys, ds)
+    X1 = np.array([-0.2, -1.5, -0.6]); Y1 = np.array([0.7, -0.3, -0.9]); G1 = np.array([0.4, -0.2, 0.3])
+    X, Y, G = np.r_[X1, -X1], np.r_[Y1, Y1], np.r_[G1, -G1]
+    specs = [BodySpec("circulation", gamma_b=0.3), BodySpec("circulation", gamma_b=-0.3)]
+    res = solve_multi(MultiProblem(grid, X, Y, G, specs, u_inf=0.0, v_inf=1.0), body, part)
+    sc = np.max(np.abs(res.f))
+    assert np.max(np.abs(res.f[:40] + res.f[40:])) <= 1e-10 * sc
+    assert np.max(np.abs(res.u[:3] + res.u[3:])) <= 1e-10 * np.max(np.abs(res.u))
+    assert np.max(np.abs(res.v[:3] - res.v[3:])) <= 1e-10 * np.max(np.abs(res.v))
+    assert abs(res.s0[0] + res.s0[1]) <= 1e-10 * max(1.0, abs(res.s0[0]))
