@@ -101,14 +101,31 @@ typedef enum {
   GPF_CIRCULATION = 1,     /* prescribed bound circulation gamma_b (eq. circsystem) */
   GPF_KUTTA_STEADY = 2,    /* Kutta condition at the body's first edge, bound
                               circulation free (eq. kuttasystem)               */
-  GPF_KUTTA_SHED = 3       /* Kutta condition at the body's m edges, each with a
+  GPF_KUTTA_SHED = 3,      /* Kutta condition at the body's m edges, each with a
                               new vortex, total circulation zero (eqs.
                               kuttasystem2, kuttasystem3); with the edge
                               bounds fmin/fmax, the generalized edge
                               conditions (eq. twovortex-gen)                   */
+  GPF_PARTS = 4            /* a body of several parts (gpf_body_set_parts),
+                              each with its own uniform value s0_j and its own
+                              constraint from in->parts (Sec. 2.7, eq.
+                              kuttasystem4)                                    */
 } gpf_mode;
 
 #define GPF_MAX_EDGES 8
+#define GPF_MAX_PARTS 8
+
+/* One part of a several-part body (mode GPF_PARTS). */
+typedef struct {
+  int mode;                /* GPF_CIRCULATION, GPF_KUTTA_STEADY (at the part's
+                              first edge) or GPF_KUTTA_SHED (a new vortex at
+                              each of the part's edges, Kelvin's theorem for
+                              the part)                                        */
+  double gamma_b;          /* GPF_CIRCULATION: the part's bound circulation    */
+  double gamma_w;          /* GPF_KUTTA_SHED: circulation of the vortices this
+                              part released before                             */
+  double ub, vb, omega;    /* rigid motion of the part (eqs. velsurf, sfsurf)  */
+} gpf_part;
 
 typedef struct gpf_ctx gpf_ctx;
 typedef struct gpf_plan gpf_plan;
@@ -153,6 +170,13 @@ typedef struct {
                                           parameter map as f~ = -2 pi c sigma /
                                           Gamma0.  fmin > fmax or NaN:
                                           GPF_E_INVALID.                        */
+  int nparts;                          /* GPF_PARTS: the body's part count;
+                                          then ub, vb, omega, gamma_b and
+                                          gamma_w above are unused, and m,
+                                          h_xnew/h_ynew and fmin/fmax list the
+                                          edges of the GPF_KUTTA_SHED parts in
+                                          the body's edge order               */
+  gpf_part parts[GPF_MAX_PARTS];       /* GPF_PARTS: one entry per part        */
 } gpf_inputs;
 
 typedef struct {
@@ -162,11 +186,16 @@ typedef struct {
                               uniform flow (nullable)                          */
   double *d_f;             /* ns bound sheet strength f (nullable)            */
   double *d_ftilde;        /* ns non-singular part f / f0 (nullable)          */
-  double *d_scalars;       /* 4 + GPF_MAX_EDGES doubles (nullable):
+  double *d_scalars;       /* 4 + GPF_MAX_EDGES + 2 GPF_MAX_PARTS doubles
+                              (nullable):
                               [0] circulation of the vortices sum Gamma_q,
                               [1] total circulation of the final source,
-                              [2] s0, [3] bound circulation <1, f>,
-                              [4..] strengths of the new vortices            */
+                              [2] s0 (of part 0 with GPF_PARTS),
+                              [3] bound circulation <1, f> (all parts),
+                              [4..11] strengths of the new vortices,
+                              [12..19] GPF_PARTS: s0_j of each part,
+                              [20..27] GPF_PARTS: bound circulation of each
+                              part                                            */
   unsigned int *d_status;  /* device status word, OR-ed with GPF_DEV_* bits
                               (required; the caller clears it)                */
   double *d_impulse;       /* 3 doubles (nullable): linear impulse P_x, P_y
@@ -222,6 +251,14 @@ gpf_status gpf_body_f0(const gpf_body *body, double *h_f0);
  * taken as having zero thickness, like a plate, whose two faces cancel in
  * those terms.  Non-finite values: GPF_E_INVALID.  Blocking. */
 gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double *h_ny);
+
+/* Split the body's points into nparts parts (2..GPF_MAX_PARTS; h_part[p]
+ * is the part of point p, every part non-empty) for mode GPF_PARTS: the
+ * parts share one Schur complement (they see each other) and each has its
+ * own uniform value and constraint (Sec. 2.7).  Computes per part
+ * S^-1 1_j, S^-T (dS o 1_j) and the circulations of the former.  Edges
+ * belong to the part of their point.  Blocking. */
+gpf_status gpf_body_set_parts(gpf_body *body, int nparts, const int *h_part);
 
 /* Enclosed area V = (<x_s, n_x> + <y_s, n_y>)/2 and centroid
  * X_c = <x_s^2 + y_s^2, n_x>/(2V), Y_c likewise with n_y (eq. centroid).

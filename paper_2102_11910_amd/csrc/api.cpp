@@ -316,6 +316,7 @@ struct GroupCfg {
   bool body = false;
   bool fp64_plan = false;  // all fields FP64
   bool conv1_fp64 = false; // FP32 plan with an FP64 first convolution
+  bool parts = false;      // a body of several parts (GPF_PARTS)
 };
 
 struct ProblemRef {
@@ -333,12 +334,13 @@ GroupCfg config_of(const ProblemRef &r) {
   c.body = r.in->mode != GPF_NOBODY;
   c.fp64_plan = r.plan->fp64;
   c.conv1_fp64 = !c.fp64_plan && c.body && r.body->conv1_fp64;
+  c.parts = r.in->mode == GPF_PARTS;
   return c;
 }
 
 bool same_cfg(const GroupCfg &a, const GroupCfg &b) {
   return a.n == b.n && a.body == b.body && a.fp64_plan == b.fp64_plan &&
-         a.conv1_fp64 == b.conv1_fp64;
+         a.conv1_fp64 == b.conv1_fp64 && a.parts == b.parts;
 }
 
 // fill the descriptors of one problem
@@ -385,7 +387,7 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   sv.gamma_b = in->gamma_b;
   sv.gamma_w_in = in->gamma_w;
   sv.mode = in->mode;
-  sv.m = in->mode == GPF_KUTTA_SHED ? in->m : 0;
+  sv.m = (in->mode == GPF_KUTTA_SHED || in->mode == GPF_PARTS) ? in->m : 0;
   sv.znew_from = r.znew_from;
   for (int j = 0; j < sv.m; ++j) {
     sv.xnew[j] = in->h_xnew[j];
@@ -424,6 +426,37 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   }
   const gpf_body *b = r.body;
   for (int e = 0; e < b->nedge; ++e) sv.edges[e] = b->edges[e];
+  if (in->mode == GPF_PARTS) {
+    // per part: mode, constraint values, motion; new vortices at the edges
+    // of the shedding parts (body edge order); each steady-Kutta part's edge
+    sv.m = in->m;
+    sv.nparts = in->nparts;
+    for (int j = 0; j < in->nparts; ++j) {
+      const gpf_part &q = in->parts[j];
+      sv.pmode[j] = q.mode;
+      sv.pgb[j] = q.gamma_b;
+      sv.pgw[j] = q.gamma_w;
+      sv.pub[j] = q.ub;
+      sv.pvb[j] = q.vb;
+      sv.pom[j] = q.omega;
+      sv.kedge[j] = -1;
+    }
+    int i = 0;
+    for (int e = 0; e < b->nedge; ++e) {
+      const int j = b->edge_part[e];
+      if (in->parts[j].mode == GPF_KUTTA_SHED) {
+        sv.edges[i] = b->edges[e];
+        sv.epart[i] = j;
+        ++i;
+      } else if (in->parts[j].mode == GPF_KUTTA_STEADY && sv.kedge[j] < 0) {
+        sv.kedge[j] = b->edges[e];
+      }
+    }
+    pd.part = b->part.as<int>();
+    pd.gpart = b->gpart.as<double>();
+    pd.zpart = b->zpart.as<double>();
+    pd.cpart = b->cpart.as<double>();
+  }
   pd.ns = b->ns;
   pd.xs = b->xs.as<double>();
   pd.ys = b->ys.as<double>();
@@ -471,7 +504,10 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
   GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body, s)));
   if (cfg.body) {
     GPF_HIP(launch_surface_rhs<T1>(pd, nb, ns_max, m_max, s));
-    GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, s));
+    if (cfg.parts)
+      GPF_HIP(launch_schur_apply_parts<TW>(pd, nb, ns_max, s));
+    else
+      GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, s));
     GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, false, s)));
   }
   GPF_HIP(launch_vortex_velocity<T2>(pd, nb, nv_max, s));
@@ -524,7 +560,7 @@ gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs
   if (!is_finite(in->u_inf) || !is_finite(in->v_inf) || !is_finite(in->ub) || !is_finite(in->vb) ||
       !is_finite(in->omega))
     return fail(GPF_E_INVALID, "solve: non-finite freestream or body motion");
-  if (in->mode < GPF_NOBODY || in->mode > GPF_KUTTA_SHED) return fail(GPF_E_INVALID, "solve: unknown mode");
+  if (in->mode < GPF_NOBODY || in->mode > GPF_PARTS) return fail(GPF_E_INVALID, "solve: unknown mode");
   if (in->mode != GPF_NOBODY) {
     if (!body) return fail(GPF_E_INVALID, "solve: this mode needs a body");
     if (body->plan != plan) return fail(GPF_E_INVALID, "solve: body belongs to another plan");
@@ -545,6 +581,33 @@ gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs
     }
     if (!std::isnan(in->gamma_w) && !is_finite(in->gamma_w))
       return fail(GPF_E_INVALID, "solve: gamma_w must be finite or NaN");
+  }
+  if (in->mode == GPF_PARTS) {
+    if (body->nparts < 2 || in->nparts != body->nparts)
+      return fail(GPF_E_INVALID, "solve: GPF_PARTS needs a body split by gpf_body_set_parts, "
+                                 "with nparts equal to its part count");
+    int nshed = 0;
+    for (int j = 0; j < in->nparts; ++j) {
+      const gpf_part &q = in->parts[j];
+      if (q.mode != GPF_CIRCULATION && q.mode != GPF_KUTTA_STEADY && q.mode != GPF_KUTTA_SHED)
+        return fail(GPF_E_INVALID, "solve: a part's mode must be circulation, steady Kutta or shedding");
+      if (!is_finite(q.gamma_b) || !is_finite(q.gamma_w) || !is_finite(q.ub) || !is_finite(q.vb) ||
+          !is_finite(q.omega))
+        return fail(GPF_E_INVALID, "solve: non-finite part value");
+      int edges = 0;
+      for (int e = 0; e < body->nedge; ++e) edges += body->edge_part[e] == j;
+      if (q.mode == GPF_KUTTA_STEADY && edges < 1)
+        return fail(GPF_E_INVALID, "solve: a steady-Kutta part needs an edge");
+      if (q.mode == GPF_KUTTA_SHED) nshed += edges;
+    }
+    if (in->m != nshed)
+      return fail(GPF_E_INVALID, "solve: m must equal the edge count of the shedding parts");
+    for (int i = 0; i < in->m; ++i) {
+      if (!is_finite(in->h_xnew[i]) || !is_finite(in->h_ynew[i]))
+        return fail(GPF_E_INVALID, "solve: non-finite new vortex position");
+      if (!(in->fmin[i] <= in->fmax[i]))
+        return fail(GPF_E_INVALID, "solve: edge bounds need fmin <= fmax");
+    }
   }
   return GPF_OK;
 }
@@ -795,6 +858,60 @@ gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double
     body->xc = cx / (2.0 * V);
     body->yc = cy / (2.0 * V);
   }
+  return GPF_OK;
+}
+
+gpf_status gpf_body_set_parts(gpf_body *body, int nparts, const int *h_part) {
+  if (!body || !h_part) return fail(GPF_E_INVALID, "gpf_body_set_parts: null argument");
+  if (nparts < 2 || nparts > GPF_MAX_PARTS)
+    return fail(GPF_E_UNSUPPORTED, "gpf_body_set_parts: nparts must be in [2, GPF_MAX_PARTS]");
+  const int ns = body->ns;
+  std::vector<int> count(nparts, 0);
+  for (int p = 0; p < ns; ++p) {
+    if (h_part[p] < 0 || h_part[p] >= nparts)
+      return fail(GPF_E_INVALID, "gpf_body_set_parts: part index out of range");
+    ++count[h_part[p]];
+  }
+  for (int j = 0; j < nparts; ++j)
+    if (count[j] == 0) return fail(GPF_E_INVALID, "gpf_body_set_parts: empty part");
+  GPF_HIP(hipSetDevice(body->plan->ctx->device));
+  const size_t vb = ns * sizeof(double);
+  // indicator columns 1_j and dS o 1_j
+  std::vector<double> ind((size_t)nparts * ns, 0.0), wind((size_t)nparts * ns, 0.0);
+  for (int p = 0; p < ns; ++p) {
+    ind[(size_t)h_part[p] * ns + p] = 1.0;
+    wind[(size_t)h_part[p] * ns + p] = body->hds[p];
+  }
+  DevBuf dInd, dW, part, gpart, zpart, cpart;
+  GPF_TRY(dInd.alloc(nparts * vb));
+  GPF_TRY(dW.alloc(nparts * vb));
+  GPF_TRY(part.alloc(ns * sizeof(int)));
+  GPF_TRY(gpart.alloc(nparts * vb));
+  GPF_TRY(zpart.alloc(nparts * vb));
+  GPF_TRY(cpart.alloc((size_t)nparts * nparts * sizeof(double)));
+  hipStream_t s = nullptr;
+  GPF_HIP(hipMemcpy(dInd.p, ind.data(), nparts * vb, hipMemcpyHostToDevice));
+  GPF_HIP(hipMemcpy(dW.p, wind.data(), nparts * vb, hipMemcpyHostToDevice));
+  GPF_HIP(hipMemcpy(part.p, h_part, ns * sizeof(int), hipMemcpyHostToDevice));
+  // z_j = S^-1 1_j; g_j = S^-T (dS o 1_j)
+  GPF_HIP(launch_gemv(ns, nparts, body->sinv.as<double>(), dInd.as<double>(), zpart.as<double>(), s));
+  for (int j = 0; j < nparts; ++j)
+    GPF_HIP(launch_gemv_t(ns, body->sinv.as<double>(), dW.as<double>() + (size_t)j * ns,
+                          gpart.as<double>() + (size_t)j * ns, s));
+  // C_jl = sum over part j of dS z_l (host, FP64)
+  std::vector<double> z((size_t)nparts * ns), C((size_t)nparts * nparts, 0.0);
+  GPF_HIP(hipMemcpy(z.data(), zpart.p, nparts * vb, hipMemcpyDeviceToHost));
+  for (int l = 0; l < nparts; ++l)
+    for (int p = 0; p < ns; ++p) C[(size_t)h_part[p] * nparts + l] += body->hds[p] * z[(size_t)l * ns + p];
+  GPF_HIP(hipMemcpy(cpart.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
+  GPF_HIP(hipDeviceSynchronize());
+  body->nparts = nparts;
+  body->hpart.assign(h_part, h_part + ns);
+  for (int e = 0; e < body->nedge; ++e) body->edge_part[e] = h_part[body->edges[e]];
+  body->part.swap(part);
+  body->gpart.swap(gpart);
+  body->zpart.swap(zpart);
+  body->cpart.swap(cpart);
   return GPF_OK;
 }
 
@@ -1155,7 +1272,7 @@ gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs
   if (!plan || !in || !out || (in->nv > 0 && (!d_x || !d_y)) || !is_finite(dt))
     return fail(GPF_E_INVALID, "gpf_rk2_create: bad arguments");
   *out = nullptr;
-  if (in->mode == GPF_KUTTA_SHED)
+  if (in->mode == GPF_KUTTA_SHED || (in->mode == GPF_PARTS && in->m > 0))
     return fail(GPF_E_UNSUPPORTED, "gpf_rk2_create: the shedding mode needs a vortex release rule");
   GPF_HIP(hipSetDevice(plan->ctx->device));
   std::unique_ptr<gpf_rk2> rk(new gpf_rk2);

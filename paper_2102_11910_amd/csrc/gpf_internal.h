@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/gpf.h"
@@ -59,6 +60,10 @@ struct DevBuf {
   ~DevBuf();
   gpf_status alloc(size_t nbytes);  // keeps the buffer if it is large enough
   template <class T> T *as() const { return static_cast<T *>(p); }
+  void swap(DevBuf &o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
 };
 
 // Per-kernel event timing (opt-in).  Launchers bracket their kernels with
@@ -117,7 +122,9 @@ enum ScalarSlot {
   SC_S0 = 2,
   SC_GAMMA_B = 3,
   SC_GAMMA_NEW = 4,   // .. 4 + GPF_MAX_EDGES
-  SC_COUNT = 4 + GPF_MAX_EDGES,
+  SC_PART_S0 = 4 + GPF_MAX_EDGES,                 // GPF_PARTS: s0_j
+  SC_PART_GB = 4 + GPF_MAX_EDGES + GPF_MAX_PARTS, // GPF_PARTS: bound circulation per part
+  SC_COUNT = 4 + GPF_MAX_EDGES + 2 * GPF_MAX_PARTS,
   AUX_DOUBLES = 32,
   AUX_BYTES = AUX_DOUBLES * 8
 };
@@ -131,6 +138,14 @@ struct SolveScalars {
   double fmin[GPF_MAX_EDGES], fmax[GPF_MAX_EDGES];   // edge bounds on f~
   int znew_from;   // >= 0: new vortex j sits at vortex znew_from + j (device
                    // arrays) instead of (xnew[j], ynew[j])
+  // GPF_PARTS: per part its mode, constraint values and motion; the part of
+  // each new vortex's edge; the steady-Kutta edge of each part (or -1)
+  int nparts;
+  int pmode[GPF_MAX_PARTS];
+  double pgb[GPF_MAX_PARTS], pgw[GPF_MAX_PARTS];
+  double pub[GPF_MAX_PARTS], pvb[GPF_MAX_PARTS], pom[GPF_MAX_PARTS];
+  int epart[GPF_MAX_EDGES];
+  int kedge[GPF_MAX_PARTS];
 };
 
 // one convolution of one problem: out = conv(in) - c * gamma[0]
@@ -183,6 +198,10 @@ struct ProbDesc {
   double *u, *v, *f_out, *ft_out, *sc_out;
   double *imp_out;              // impulse (P_x, P_y, Pi_O), or null
   const double *nx, *ny;        // body normals into the fluid (zeros: thin body)
+  // GPF_PARTS: part of each point; per part S^-T (dS o 1_j) and S^-1 1_j
+  // (ns each, part-major) and the circulations C_jl of S^-1 1_l over part j
+  const int *part;
+  const double *gpart, *zpart, *cpart;
   int psi_total;                // psi holds s + s_inf: velocities add no U_inf
   SolveScalars sv;
 };
@@ -208,6 +227,9 @@ template <class T>
 hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
 template <class T>
 hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
+// the same for bodies of several parts (mode GPF_PARTS)
+template <class T>
+hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
 template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
 
@@ -309,6 +331,11 @@ struct gpf_body {
   bool has_normals = false;
   double area = 0.0, xc = 0.0, yc = 0.0;   // enclosed area and centroid
   std::vector<double> hxs, hys, hds, hf0;  // host copies of the geometry and f0
+  // parts (gpf_body_set_parts); nparts = 1 without
+  int nparts = 1;
+  std::vector<int> hpart;
+  int edge_part[GPF_MAX_EDGES] = {0};
+  gpf::DevBuf part, gpart, zpart, cpart;
   double mom_x = 0.0, mom_y = 0.0, mom_r2 = 0.0;  // moments of fhat0 = dS f0
 };
 

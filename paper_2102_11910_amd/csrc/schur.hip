@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_impulse(const ProbDesc *__restrict__ d)
     a1 += P.partials[1 * (size_t)kPartStride + b];
     a2 += P.partials[3 * (size_t)kPartStride + b];
   }
-  if (sv.mode == GPF_KUTTA_SHED && tid < sv.m) {
+  if (tid < sv.m) {
     const double g = P.aux[SC_GAMMA_NEW + tid];
     const double x = sv.znew_from >= 0 ? P.xv[sv.znew_from + tid] : sv.xnew[tid];
     const double y = sv.znew_from >= 0 ? P.yv[sv.znew_from + tid] : sv.ynew[tid];
@@ -200,10 +200,12 @@ __global__ __launch_bounds__(256) void k_impulse(const ProbDesc *__restrict__ d)
     a2 += g * (x * x + y * y);
   }
   if (P.ns > 0 && P.f_out) {
-    const double ux = sv.ub - sv.u_inf, uy = sv.vb - sv.v_inf, om = sv.omega;
     for (int p = tid; p < P.ns; p += 256) {
       const double x = P.xs[p], y = P.ys[p];
-      const double vx = ux - om * y, vy = uy + om * x;
+      const int j = P.part ? P.part[p] : 0;
+      const double ub = P.part ? sv.pub[j] : sv.ub, vb = P.part ? sv.pvb[j] : sv.vb;
+      const double om = P.part ? sv.pom[j] : sv.omega;
+      const double vx = ub - sv.u_inf - om * y, vy = vb - sv.v_inf + om * x;
       const double q = P.ds[p] * (P.f_out[p] + P.nx[p] * vy - P.ny[p] * vx);
       a0 += y * q;
       a1 += x * q;
@@ -256,12 +258,18 @@ __global__ __launch_bounds__(kRB) void k_surface_rhs(const ProbDesc *__restrict_
       acc += ew[4 + b] * r;
     }
     const double x = P.xs[p], y = P.ys[p];
-    const double sb = (sv.ub - sv.u_inf) * y - (sv.vb - sv.v_inf) * x -
-                      0.5 * sv.omega * (x * x + y * y);
+    double ub = sv.ub, vb = sv.vb, om = sv.omega;
+    if (P.part) {   // several parts: the motion of this point's part
+      const int j = P.part[p];
+      ub = sv.pub[j];
+      vb = sv.pvb[j];
+      om = sv.pom[j];
+    }
+    const double sb = (ub - sv.u_inf) * y - (vb - sv.v_inf) * x - 0.5 * om * (x * x + y * y);
     P.rhs[p] = sb - acc;
     return;
   }
-  if (sv.mode != GPF_KUTTA_SHED) return;
+  if (sv.m <= 0) return;
   const int m = sv.m;
   const int pj = ((int)blockIdx.x - nbe) * (kRB / 16) + (int)threadIdx.x / 16;
   const int lane = threadIdx.x & 15;
@@ -582,6 +590,296 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   }
 }
 
+// Surface solve for a body of several parts (Sec. 2.7, eq. kuttasystem4).
+// Part j has its own uniform value s0_j, so
+//     f = y_0 + sum_i Gamma_i y_i - sum_j s0_j z_j,
+// y_c = S^-1 r_c (rhs columns), z_j = S^-1 1_j (per body).  The rows, one per
+// part and one per new vortex, need the part circulations of each column
+// (gpart_j . r_c), the columns at the edge points (rows of S^-1) and the
+// body constants C_jl (circulation of z_l over part j) and z_l at the edges.
+// Every workgroup forms and solves the (nparts + m) system itself (a second
+// time when edge bounds make some edges shed), then finishes its rows as in
+// k_schur_apply.
+constexpr int kMaxUnk = GPF_MAX_PARTS + GPF_MAX_EDGES;
+constexpr int kMaxERows = GPF_MAX_EDGES + GPF_MAX_PARTS;
+
+// Gauss-Jordan with partial pivoting on A (n x n, augmented); false when a
+// pivot is below 1e-13 of the largest entry
+__device__ bool solve_small(double (*A)[kMaxUnk + 1], int n, double *x) {
+  double amax = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) amax = fmax(amax, fabs(A[i][j]));
+  for (int c = 0; c < n; ++c) {
+    int pr = c;
+    for (int i = c + 1; i < n; ++i)
+      if (fabs(A[i][c]) > fabs(A[pr][c])) pr = i;
+    if (!(fabs(A[pr][c]) > 1e-13 * amax)) return false;
+    if (pr != c)
+      for (int j = 0; j <= n; ++j) {
+        const double t = A[c][j];
+        A[c][j] = A[pr][j];
+        A[pr][j] = t;
+      }
+    for (int i = 0; i < n; ++i) {
+      if (i == c) continue;
+      const double fct = A[i][c] / A[c][c];
+      for (int j = c; j <= n; ++j) A[i][j] -= fct * A[c][j];
+    }
+  }
+  for (int i = 0; i < n; ++i) x[i] = A[i][n] / A[i][i];
+  return true;
+}
+
+template <class T>
+__global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__restrict__ d) {
+  __shared__ double rs[kRStage];
+  __shared__ double red[4][GPF_MAX_PARTS][kMaxCol];
+  __shared__ double circ[GPF_MAX_PARTS][kMaxCol];   // gpart_j . r_c
+  __shared__ double ye[kMaxERows][kMaxCol];         // (S^-1 r_c) at the edge rows
+  __shared__ double yr[kCRows][kMaxCol];            // (S^-1 r_c) at this workgroup's rows
+  __shared__ double A[kMaxUnk][kMaxUnk + 1];
+  __shared__ double sol[kMaxUnk];                   // s0_1.., Gamma_1..
+  const ProbDesc &P = d[blockIdx.y];
+  const int ns = P.ns;
+  const int row0 = blockIdx.x * kCRows;
+  if (row0 >= ns) return;
+  const SolveScalars &sv = P.sv;
+  const int np = sv.nparts, m = sv.m, ncol = 1 + m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // edge rows: the m new-vortex edges, then each steady-Kutta part's edge
+  __shared__ int erow_k[kMaxERows];
+  int ne = m;
+  for (int j = 0; j < np; ++j) ne += sv.pmode[j] == GPF_KUTTA_STEADY;
+  if (tid == 0) {
+    int e = 0;
+    for (int i = 0; i < m; ++i) erow_k[e++] = sv.edges[i];
+    for (int j = 0; j < np; ++j)
+      if (sv.pmode[j] == GPF_KUTTA_STEADY) erow_k[e++] = sv.kedge[j];
+  }
+  __syncthreads();
+
+  const double gw_dev = P.aux[SC_GAMMA_W];
+  const double *R = P.rhs;
+  if (ncol * ns <= kRStage) {
+#pragma unroll 4
+    for (int k = tid; k < ncol * ns; k += kCB) rs[k] = P.rhs[k];
+    __syncthreads();
+    R = rs;
+  }
+  size_t coff[kMaxCol];
+#pragma unroll
+  for (int c = 0; c < kMaxCol; ++c) coff[c] = (size_t)min(c, ncol - 1) * ns;
+  // part circulations of every column, one sweep per part
+  for (int j = 0; j < np; ++j) {
+    const double *g = P.gpart + (size_t)j * ns;
+    double acc[kMaxCol];
+#pragma unroll
+    for (int c = 0; c < kMaxCol; ++c) acc[c] = 0.0;
+#pragma unroll 2
+    for (int q = tid; q < ns; q += kCB) {
+      const double gq = g[q];
+#pragma unroll
+      for (int c = 0; c < kMaxCol; ++c) acc[c] += gq * R[coff[c] + q];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCol; ++c) {
+      if (c < ncol) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) red[wave][j][c] = v;
+      }
+    }
+  }
+  // the columns at the edge rows, one wave each
+  for (int e = wave; e < ne; e += 4) {
+    const double *a = P.sinv + (size_t)erow_k[e] * ns;
+    double acc[kMaxCol];
+#pragma unroll
+    for (int c = 0; c < kMaxCol; ++c) acc[c] = 0.0;
+#pragma unroll 4
+    for (int q = lane; q < ns; q += 64) {
+      const double aq = a[q];
+#pragma unroll
+      for (int c = 0; c < kMaxCol; ++c) acc[c] += aq * R[coff[c] + q];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCol; ++c) {
+      if (c < ncol) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) ye[e][c] = v;
+      }
+    }
+  }
+  // this workgroup's rows
+  {
+    const int r0 = row0 + wave * kRowsPerWave;
+    const int nr = min(kRowsPerWave, ns - r0);
+    double acc[kRowsPerWave][kMaxCol];
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+      for (int c = 0; c < kMaxCol; ++c) acc[r][c] = 0.0;
+    if (nr > 0) {
+      const double *arow[kRowsPerWave];
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) arow[r] = P.sinv + (size_t)min(r0 + r, ns - 1) * ns;
+#pragma unroll 2
+      for (int q = lane; q < ns; q += 64) {
+        double aq[kRowsPerWave], rq[kMaxCol];
+#pragma unroll
+        for (int r = 0; r < kRowsPerWave; ++r) aq[r] = arow[r][q];
+#pragma unroll
+        for (int c = 0; c < kMaxCol; ++c) rq[c] = R[coff[c] + q];
+#pragma unroll
+        for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+          for (int c = 0; c < kMaxCol; ++c) acc[r][c] += aq[r] * rq[c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) {
+      if (r < nr) {
+#pragma unroll
+        for (int c = 0; c < kMaxCol; ++c) {
+          if (c < ncol) {
+            const double v = wave_sum(acc[r][c]);
+            if (lane == 0) yr[wave * kRowsPerWave + r][c] = v;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  if (tid == 0) {
+    for (int j = 0; j < np; ++j)
+      for (int c = 0; c < ncol; ++c)
+        circ[j][c] = red[0][j][c] + red[1][j][c] + red[2][j][c] + red[3][j][c];
+    const int N = np + m;
+    const double *C = P.cpart;
+    const double *Z = P.zpart;
+    bool active[GPF_MAX_EDGES];
+    double tgt[GPF_MAX_EDGES];
+    for (int i = 0; i < m; ++i) {
+      active[i] = false;
+      tgt[i] = 0.0;
+    }
+    bool ok = true;
+    for (int pass = 0; pass < 2; ++pass) {
+      // one row per part
+      int kr = m;   // next steady-Kutta edge row
+      for (int j = 0; j < np; ++j) {
+        const int mode = sv.pmode[j];
+        if (mode == GPF_KUTTA_STEADY) {
+          const int e = kr++;
+          const int k = erow_k[e];
+          for (int l = 0; l < np; ++l) A[j][l] = -Z[(size_t)l * ns + k];
+          for (int i = 0; i < m; ++i) A[j][np + i] = ye[e][1 + i];
+          A[j][N] = -ye[e][0];
+        } else {
+          for (int l = 0; l < np; ++l) A[j][l] = -C[j * np + l];
+          for (int i = 0; i < m; ++i)
+            A[j][np + i] = circ[j][1 + i] + ((mode == GPF_KUTTA_SHED && sv.epart[i] == j) ? 1.0 : 0.0);
+          A[j][N] = (mode == GPF_CIRCULATION ? sv.pgb[j] : -sv.pgw[j]) - circ[j][0];
+        }
+      }
+      // one row per new vortex: held at its target, or shedding nothing
+      for (int i = 0; i < m; ++i) {
+        const int r = np + i;
+        for (int c = 0; c <= N; ++c) A[r][c] = 0.0;
+        if (active[i]) {
+          const int k = sv.edges[i];
+          for (int l = 0; l < np; ++l) A[r][l] = -Z[(size_t)l * ns + k];
+          for (int i2 = 0; i2 < m; ++i2) A[r][np + i2] = ye[i][1 + i2];
+          A[r][N] = P.f0[k] * tgt[i] - ye[i][0];
+        } else {
+          A[r][np + i] = 1.0;
+        }
+      }
+      ok = solve_small(A, N, sol);
+      if (!ok || pass == 1) break;
+      // which edges shed: the sheet with nothing shed against the bounds
+      bool any = false;
+      for (int i = 0; i < m; ++i) {
+        const int k = sv.edges[i];
+        double fk = ye[i][0];
+        for (int l = 0; l < np; ++l) fk -= sol[l] * Z[(size_t)l * ns + k];
+        const double ft = fk / P.f0[k];
+        if (ft < sv.fmin[i]) { active[i] = true; tgt[i] = sv.fmin[i]; any = true; }
+        else if (ft > sv.fmax[i]) { active[i] = true; tgt[i] = sv.fmax[i]; any = true; }
+      }
+      if (!any) break;
+    }
+    if (!ok) {
+      for (int c = 0; c < N; ++c) sol[c] = 0.0;
+      if (blockIdx.x == 0) atomicOr(P.status, GPF_DEV_SINGULAR);
+    }
+    if (blockIdx.x == 0) {
+      double gsum = 0.0, gb_tot = 0.0;
+      for (int i = 0; i < m; ++i) gsum += sol[np + i];
+      for (int j = 0; j < np; ++j) {
+        double gb = circ[j][0];
+        for (int i = 0; i < m; ++i) gb += sol[np + i] * circ[j][1 + i];
+        for (int l = 0; l < np; ++l) gb -= sol[l] * C[j * np + l];
+        gb_tot += gb;
+        P.aux[SC_PART_S0 + j] = sol[j];
+        P.aux[SC_PART_GB + j] = gb;
+        if (P.sc_out) {
+          P.sc_out[SC_PART_S0 + j] = sol[j];
+          P.sc_out[SC_PART_GB + j] = gb;
+        }
+      }
+      P.aux[SC_GAMMA_SRC2] = gw_dev + gb_tot + gsum;
+      P.aux[SC_S0] = sol[0];
+      P.aux[SC_GAMMA_B] = gb_tot;
+      for (int i = 0; i < GPF_MAX_EDGES; ++i) P.aux[SC_GAMMA_NEW + i] = i < m ? sol[np + i] : 0.0;
+      if (P.sc_out) {
+        P.sc_out[SC_GAMMA_W] = gw_dev;
+        P.sc_out[SC_GAMMA_SRC2] = gw_dev + gb_tot + gsum;
+        P.sc_out[SC_S0] = sol[0];
+        P.sc_out[SC_GAMMA_B] = gb_tot;
+        for (int i = 0; i < GPF_MAX_EDGES; ++i) P.sc_out[SC_GAMMA_NEW + i] = i < m ? sol[np + i] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+
+  // f, f~ of the rows; 16 lanes per row add R_s f at its 16 stencil nodes
+  const int n = P.n;
+  T *w = static_cast<T *>(P.w);
+  const double inv_dx2 = 1.0 / (P.dx * P.dx);
+  {
+    const int lr = tid >> 4, node = tid & 15;
+    const int p = row0 + lr;
+    if (p < ns) {
+      double f = yr[lr][0];
+      for (int i = 0; i < m; ++i) f += sol[np + i] * yr[lr][1 + i];
+      for (int l = 0; l < np; ++l) f -= sol[l] * P.zpart[(size_t)l * ns + p];
+      if (node == 0) {
+        if (P.f_out) P.f_out[p] = f;
+        if (P.ft_out) P.ft_out[p] = f / P.f0[p];
+      }
+      const int a = node & 3, b = node >> 2;
+      const int i0 = P.st_i[2 * p], j0 = P.st_i[2 * p + 1];
+      const double amp = P.ds[p] * f * inv_dx2;
+      atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
+                 (T)(amp * P.st_w[8 * p + a] * P.st_w[8 * p + 4 + b]));
+    }
+  }
+  if (blockIdx.x == 0 && tid < 16 * m) {
+    const int j = tid >> 4, node = tid & 15;
+    const double zx = sv.znew_from >= 0 ? P.xv[sv.znew_from + j] : sv.xnew[j];
+    const double zy = sv.znew_from >= 0 ? P.yv[sv.znew_from + j] : sv.ynew[j];
+    const double xi = (zx - P.x0) / P.dx, eta = (zy - P.y0) / P.dx;
+    if (xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0) {
+      const int i0 = (int)floor(xi) - 1, j0 = (int)floor(eta) - 1;
+      const double fx = xi - floor(xi), fy = eta - floor(eta);
+      const int a = node & 3, b = node >> 2;
+      atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
+                 (T)(sol[np + j] * inv_dx2 * m4p(fy + 1.0 - b) * m4p(fx + 1.0 - a)));
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_schur_build(int n, int ns, const int *st_i, const double *st_w,
@@ -654,5 +952,15 @@ hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, hipStream_t
 }
 template hipError_t launch_schur_apply<float>(const ProbDesc *, int, int, hipStream_t);
 template hipError_t launch_schur_apply<double>(const ProbDesc *, int, int, hipStream_t);
+
+template <class T>
+hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s) {
+  hipLaunchKernelGGL((k_schur_apply_parts<T>), dim3((ns_max + kCRows - 1) / kCRows, nb), dim3(kCB),
+                     0, s, d);
+  timer_end(s);
+  return hipGetLastError();
+}
+template hipError_t launch_schur_apply_parts<float>(const ProbDesc *, int, int, hipStream_t);
+template hipError_t launch_schur_apply_parts<double>(const ProbDesc *, int, int, hipStream_t);
 
 }  // namespace gpf

@@ -43,7 +43,7 @@ GPF_NOBODY, GPF_CIRCULATION, GPF_KUTTA_STEADY, GPF_KUTTA_SHED = 0, 1, 2, 3
 MODES = {"none": GPF_NOBODY, "circulation": GPF_CIRCULATION, "kutta": GPF_KUTTA_STEADY,
          "shed": GPF_KUTTA_SHED}
 GPF_MAX_EDGES = 8
-N_SCALARS = 4 + GPF_MAX_EDGES
+N_SCALARS = 4 + GPF_MAX_EDGES + 2 * 8
 
 
 class GpfError(RuntimeError):
@@ -56,6 +56,15 @@ class gpf_grid(C.Structure):
     _fields_ = [("n", C.c_int), ("dx", C.c_double), ("x0", C.c_double), ("y0", C.c_double)]
 
 
+GPF_PARTS = 4
+GPF_MAX_PARTS = 8
+
+
+class gpf_part(C.Structure):
+    _fields_ = [("mode", C.c_int), ("gamma_b", C.c_double), ("gamma_w", C.c_double),
+                ("ub", C.c_double), ("vb", C.c_double), ("omega", C.c_double)]
+
+
 class gpf_inputs(C.Structure):
     _fields_ = [("nv", C.c_int), ("d_xv", C.c_void_p), ("d_yv", C.c_void_p), ("d_gv", C.c_void_p),
                 ("u_inf", C.c_double), ("v_inf", C.c_double),
@@ -63,7 +72,8 @@ class gpf_inputs(C.Structure):
                 ("mode", C.c_int), ("gamma_b", C.c_double), ("m", C.c_int),
                 ("h_xnew", C.c_double * GPF_MAX_EDGES), ("h_ynew", C.c_double * GPF_MAX_EDGES),
                 ("gamma_w", C.c_double),
-                ("fmin", C.c_double * GPF_MAX_EDGES), ("fmax", C.c_double * GPF_MAX_EDGES)]
+                ("fmin", C.c_double * GPF_MAX_EDGES), ("fmax", C.c_double * GPF_MAX_EDGES),
+                ("nparts", C.c_int), ("parts", gpf_part * GPF_MAX_PARTS)]
 
 
 class gpf_outputs(C.Structure):
@@ -97,6 +107,7 @@ def _load():
         "gpf_body_set_normals": (I, [P, DP, DP]),
         "gpf_body_geometry": (I, [P, DP, DP, DP]),
         "gpf_body_added_mass": (I, [P, D, DP]),
+        "gpf_body_set_parts": (I, [P, I, C.POINTER(C.c_int)]),
         "gpf_solve": (I, [P, P, C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
         "gpf_regularize_vortices": (I, [P, I, P, P, P, P, I, P, P]),
         "gpf_convolve": (I, [P, P, P, D, P]),
@@ -267,6 +278,15 @@ class Body:
         assert len(ax) == len(ay) == self.ns
         check(lib.gpf_body_set_normals(self.h, px, py), "gpf_body_set_normals")
 
+    def set_parts(self, part):
+        """Split the points into parts: part[p] = part of point p."""
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(part, dtype=np.int32))
+        assert len(a) == self.ns
+        self.nparts = int(a.max()) + 1
+        check(lib.gpf_body_set_parts(self.h, self.nparts, a.ctypes.data_as(C.POINTER(C.c_int))),
+              "gpf_body_set_parts")
+
     def geometry(self):
         """(area, x_c, y_c)."""
         v = [C.c_double() for _ in range(3)]
@@ -313,6 +333,23 @@ def make_inputs(X, Y, G, u_inf=0.0, v_inf=0.0, ub=0.0, vb=0.0, omega=0.0, mode="
     for j, (lo, hi) in enumerate(fbounds):
         inp.fmin[j] = lo
         inp.fmax[j] = hi
+    return inp
+
+
+def make_parts_inputs(X, Y, G, parts, znew=(), fbounds=(), u_inf=0.0, v_inf=0.0) -> gpf_inputs:
+    """gpf_inputs for mode GPF_PARTS.  parts: one dict per part with keys
+    mode ("circulation" | "kutta" | "shed"), and optionally gamma_b,
+    gamma_w, ub, vb, omega; znew / fbounds: one entry per edge of the
+    shedding parts, in the body's edge order."""
+    inp = make_inputs(X, Y, G, u_inf, v_inf, mode=GPF_PARTS, znew=znew, fbounds=fbounds)
+    inp.nparts = len(parts)
+    for j, q in enumerate(parts):
+        inp.parts[j].mode = MODES[q["mode"]]
+        inp.parts[j].gamma_b = q.get("gamma_b", 0.0)
+        inp.parts[j].gamma_w = q.get("gamma_w", 0.0)
+        inp.parts[j].ub = q.get("ub", 0.0)
+        inp.parts[j].vb = q.get("vb", 0.0)
+        inp.parts[j].omega = q.get("omega", 0.0)
     return inp
 
 
@@ -542,6 +579,9 @@ class Shed:
     @property
     def nv(self) -> int:
         return lib.gpf_shed_count(self.h)
+
+    def sync(self, stream=None):
+        check(lib.gpf_sync(_stream_ptr(stream), C.c_void_p(self.out.d_status)), "gpf_sync")
 
     def close(self):
         if self.h:

@@ -342,3 +342,107 @@ def random_case(seed: int, n: int, dx: float, nv: int, surface: str | None = "cy
         c.edges = surf.edges
         c.znew = plate_new_vortices(surf, 4.0 * dx)
     return c
+
+
+# ----------------------------------------------------------------------------
+# several bodies (Sec. 2.7)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class MultiCase:
+    """Several bodies in one window: surfaces in order, one entry of `parts`
+    per surface (mode and its values, motion), new-vortex positions for the
+    edges of the shedding parts in the bodies' edge order."""
+    name: str
+    n: int
+    dx: float
+    X: np.ndarray
+    Y: np.ndarray
+    G: np.ndarray
+    surfaces: list
+    parts: list
+    znew: tuple = ()
+    fbounds: tuple = ()
+    u_inf: float = 0.0
+    v_inf: float = 0.0
+
+    @property
+    def nv(self) -> int:
+        return len(self.X)
+
+    @property
+    def xs(self):
+        return np.concatenate([s.xs for s in self.surfaces])
+
+    @property
+    def ys(self):
+        return np.concatenate([s.ys for s in self.surfaces])
+
+    @property
+    def ds(self):
+        return np.concatenate([s.ds for s in self.surfaces])
+
+    @property
+    def part(self):
+        return np.concatenate([np.full(s.ns, j, np.int32) for j, s in enumerate(self.surfaces)])
+
+    @property
+    def edges(self):
+        out, off = [], 0
+        for s in self.surfaces:
+            out += [off + e for e in s.edges]
+            off += s.ns
+        return tuple(out)
+
+    def part_edges(self, j):
+        off = sum(s.ns for s in self.surfaces[:j])
+        return tuple(off + e for e in self.surfaces[j].edges)
+
+
+def _cloud_outside(rng, nv, half, surfaces, margin):
+    def keep(p):
+        ok = np.ones(len(p), bool)
+        for s in surfaces:
+            ok &= outside_surface(s, p, margin)
+        return ok
+    return _accept_first(rng, nv, lambda k: rng.uniform(-half, half, size=(k, 2)), keep)
+
+
+def two_plates_case(seed: int = 16, n: int = 256, chord: float = 1.0, nv: int = 2000) -> MultiCase:
+    """Two plates of chord c at 60 deg, one above the other c/2 apart (the
+    arrangement of Fig. 16), dx = 2.4c/n (dS/dx = 2), uniform flow (1, 0),
+    Kutta at both edges of both plates with a new vortex 2dx beyond each;
+    vortices uniform in the window outside the plates, Gamma ~ N(0, 1e-3^2)."""
+    rng = np.random.default_rng(seed)
+    dx = 2.4 * chord / n
+    ns = int(round(chord / (2.0 * dx)))
+    top = flat_plate(chord, 60.0, ns, center=(0.0, 0.25 * chord))
+    bot = flat_plate(chord, 60.0, ns, center=(0.0, -0.25 * chord))
+    half = (n - 1) * dx / 2.0 - 4.0 * dx
+    pts = _cloud_outside(rng, nv, half, [top, bot], 2.0 * dx)
+    G = rng.normal(0.0, 1e-3, size=nv)
+    znew = plate_new_vortices(top, 2.0 * dx) + plate_new_vortices(bot, 2.0 * dx)
+    parts = [{"mode": "shed", "gamma_w": 0.0}, {"mode": "shed", "gamma_w": 0.0}]
+    return MultiCase(f"two plates {n}^2", n, dx, f32(pts[:, 0]), f32(pts[:, 1]), f32(G),
+                     [top, bot], parts, znew, (), u_inf=1.0)
+
+
+def mixed_bodies_case(seed: int = 17, n: int = 128, nv: int = 400) -> MultiCase:
+    """A moving cylinder with a prescribed circulation, a plate held by a
+    steady Kutta condition at its trailing edge, and a shedding plate (both
+    edges), in a uniform flow with a vertical component."""
+    rng = np.random.default_rng(seed)
+    dx = 2.0 / n
+    cyl = cylinder(0.22, int(round(2 * np.pi * 0.22 / (1.6 * dx))), center=(-0.45, 0.35))
+    p1 = flat_plate(0.5, 15.0, int(round(0.5 / (1.5 * dx))), center=(0.35, 0.4))
+    p1.edges = (p1.edges[1],)      # its trailing edge only
+    p2 = flat_plate(0.6, 30.0, int(round(0.6 / (1.5 * dx))), center=(0.0, -0.4))
+    half = (n - 1) * dx / 2.0 - 4.0 * dx
+    pts = _cloud_outside(rng, nv, half, [cyl, p1, p2], 2.0 * dx)
+    G = rng.normal(0.0, 1e-2, size=nv)
+    parts = [{"mode": "circulation", "gamma_b": 0.15, "ub": 0.1, "vb": -0.05, "omega": 0.3},
+             {"mode": "kutta"},
+             {"mode": "shed", "gamma_w": 0.02, "vb": 0.05}]
+    return MultiCase(f"mixed bodies {n}^2", n, dx, f32(pts[:, 0]), f32(pts[:, 1]), f32(G),
+                     [cyl, p1, p2], parts, plate_new_vortices(p2, 4.0 * dx), (),
+                     u_inf=1.0, v_inf=0.2)

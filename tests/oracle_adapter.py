@@ -45,3 +45,30 @@ def intermediate_sheet(case, body=None):
     gamma_w = float(np.sum(p.G)) if p.gamma_w is None else p.gamma_w
     ft_kel = ft_star - (body.fhat0 @ ft_star + gamma_w) / body.gamma0
     return ft_star, ft_kel, ft_j
+
+
+def multi_of(mc):
+    """A several-body workload case as the oracle's problem, body and parts."""
+    from oracle.multibody import BodySpec, MultiProblem
+    grid = grid_of(mc)
+    specs = []
+    fb = list(mc.fbounds)
+    zi = 0
+    for j, q in enumerate(mc.parts):
+        edges = mc.part_edges(j)
+        spec = BodySpec(mode=q["mode"], gamma_b=q.get("gamma_b", 0.0), ub=q.get("ub", 0.0),
+                        vb=q.get("vb", 0.0), omega=q.get("omega", 0.0),
+                        gamma_w=q.get("gamma_w", 0.0))
+        if q["mode"] == "kutta":
+            spec.edges = edges[:1]
+        elif q["mode"] == "shed":
+            spec.edges = edges
+            spec.znew = tuple(mc.znew[zi:zi + len(edges)])
+            if fb:
+                spec.fbounds = tuple(fb[zi:zi + len(edges)])
+            zi += len(edges)
+        specs.append(spec)
+    p = MultiProblem(grid, np.asarray(mc.X, np.float64), np.asarray(mc.Y, np.float64),
+                     np.asarray(mc.G, np.float64), specs, mc.u_inf, mc.v_inf)
+    body = body_setup(grid, mc.xs, mc.ys, mc.ds)
+    return p, body, mc.part

@@ -62,7 +62,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("no gcc")
     inc = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include")
-    structs = [gpf.gpf_grid, gpf.gpf_inputs, gpf.gpf_outputs]
+    structs = [gpf.gpf_grid, gpf.gpf_part, gpf.gpf_inputs, gpf.gpf_outputs]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gpf.h"', "int main(void) {"]
     for st in structs:
         name = st.__name__

@@ -1,0 +1,202 @@
+"""Several bodies on the GPU (mode GPF_PARTS, Sec. 2.7, eq. kuttasystem4)
+against the oracle's several-body solve: a moving cylinder with a
+prescribed circulation, a plate held by a steady Kutta condition and a
+shedding plate in one window; the two plates of Fig. 16 shedding at all
+four edges; edge bounds; the impulse with a motion per part; batches that
+mix several-part and one-body problems; argument checks."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2102_11910_amd import gpf  # noqa: E402
+from paper_2102_11910_amd import workloads as wl  # noqa: E402
+from oracle.impulse import impulse as oracle_impulse  # noqa: E402
+from oracle.multibody import solve_multi  # noqa: E402
+from tests.conftest import rell2  # noqa: E402
+from tests.oracle_adapter import multi_of  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+INF = math.inf
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpf.Context(0)
+
+
+class MultiRun:
+    def __init__(self, ctx, mc, flags, impulse=False):
+        self.mc = mc
+        self.plan = gpf.Plan(ctx, mc.n, mc.dx, flags=flags)
+        self.body = gpf.Body(self.plan, mc.xs, mc.ys, mc.ds, mc.edges)
+        self.body.set_parts(mc.part)
+        t = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float64).to(DEV)
+        self.X, self.Y, self.G = t(mc.X), t(mc.Y), t(mc.G)
+        ns = len(mc.xs)
+        self.psi = torch.empty((mc.n, mc.n), dtype=self.plan.field_dtype, device=DEV)
+        self.u = torch.zeros(mc.nv, dtype=torch.float64, device=DEV)
+        self.v = torch.zeros(mc.nv, dtype=torch.float64, device=DEV)
+        self.f = torch.zeros(ns, dtype=torch.float64, device=DEV)
+        self.ft = torch.zeros(ns, dtype=torch.float64, device=DEV)
+        self.sc = torch.zeros(gpf.N_SCALARS, dtype=torch.float64, device=DEV)
+        self.status = torch.zeros(1, dtype=torch.int32, device=DEV)
+        self.imp = torch.zeros(3, dtype=torch.float64, device=DEV) if impulse else None
+        self.inp = gpf.make_parts_inputs(self.X, self.Y, self.G, mc.parts, mc.znew, mc.fbounds,
+                                         mc.u_inf, mc.v_inf)
+        self.out = gpf.make_outputs(self.psi, self.u, self.v, self.f, self.ft, self.sc,
+                                    self.status, self.imp)
+
+    def solve(self):
+        gpf.gpf_solve(self.plan, self.body, self.inp, self.out)
+        gpf.gpf_sync(self.status)
+        h = lambda a: a.cpu().numpy().astype(np.float64)
+        return {"s": h(self.psi), "u": h(self.u), "v": h(self.v), "f": h(self.f),
+                "ft": h(self.ft), "sc": h(self.sc)}
+
+
+def compare(mc, got, ref, fp64, label):
+    tol_s, tol_f, tol_u, tol_g = (1e-9, 1e-8, 1e-9, 1e-9) if fp64 else (1e-5, 1e-4, 1e-4, 1e-5)
+    np_ = len(mc.parts)
+    sc = got["sc"]
+    es = rell2(got["s"], ref.s)
+    eu = rell2(np.r_[got["u"], got["v"]], np.r_[ref.u, ref.v])
+    ef = rell2(got["f"], ref.f)
+    s0 = sc[12:12 + np_]
+    gb = sc[20:20 + np_]
+    e0 = np.max(np.abs(s0 - ref.s0)) / max(1.0, np.max(np.abs(ref.s0)))
+    eb = np.max(np.abs(gb - ref.gamma_b)) / max(1e-3, np.max(np.abs(ref.gamma_b)))
+    m = len(ref.gamma_new)
+    eg = (np.max(np.abs(sc[4:4 + m] - ref.gamma_new)) / max(1e-3, np.max(np.abs(ref.gamma_new)))
+          if m else 0.0)
+    say(f"   {label}: s {es:.2e} uv {eu:.2e} f {ef:.2e} s0 {e0:.2e} gamma_b {eb:.2e} "
+        f"gamma_new {eg:.2e}")
+    assert es <= tol_s and eu <= tol_u and ef <= tol_f, label
+    assert e0 <= tol_g and eb <= tol_g and eg <= tol_g, label
+    assert abs(sc[3] - ref.gamma_b.sum()) <= tol_g * max(1.0, np.abs(ref.gamma_b).sum())
+    if m:
+        assert np.array_equal(sc[4:4 + m] == 0.0, ref.gamma_new == 0.0)
+
+
+@pytest.mark.parametrize("flags", [gpf.GPF_FP64, gpf.GPF_POLICY_AUTO])
+def test_mixed_bodies_match_oracle(ctx, flags):
+    say(f"[parts] cylinder + steady-Kutta plate + shedding plate, flags={flags}")
+    mc = wl.mixed_bodies_case()
+    got = MultiRun(ctx, mc, flags).solve()
+    ref = solve_multi(*multi_of(mc))
+    compare(mc, got, ref, flags == gpf.GPF_FP64, f"mixed flags={flags}")
+
+
+@pytest.mark.parametrize("flags", [gpf.GPF_FP64, gpf.GPF_POLICY_AUTO])
+def test_two_plates_match_oracle(ctx, flags):
+    say(f"[parts] two plates at 60 deg, four new vortices, flags={flags}")
+    mc = wl.two_plates_case()
+    got = MultiRun(ctx, mc, flags).solve()
+    ref = solve_multi(*multi_of(mc))
+    compare(mc, got, ref, flags == gpf.GPF_FP64, f"two plates flags={flags}")
+
+
+def test_parts_with_edge_bounds(ctx):
+    """Bounds around the oracle's sheet with nothing shed: the leading edge
+    of the lower plate held at a bound, its trailing edge and the upper
+    plate's leading edge free, the upper trailing edge by Kutta."""
+    from oracle.multibody import solve_multi as sm
+    mc = wl.two_plates_case(n=128, nv=300)
+    p, body, part = multi_of(mc)
+    free = [(-INF, INF)] * 4
+    for b in p.bodies:
+        b.fbounds = ((-1e30, 1e30), (-1e30, 1e30))
+    keep = sm(p, body, part)                        # nothing shed
+    k = mc.edges
+    v = keep.ftilde[k[2]]
+    d = 0.25 * max(1.0, abs(v))
+    fb = ((-INF, INF), (0.0, 0.0), (v + d, v + 3 * d), (-INF, INF))
+    mc.fbounds = fb
+    got = MultiRun(ctx, mc, gpf.GPF_FP64).solve()
+    ref = solve_multi(*multi_of(mc))
+    assert ref.gamma_new[0] == 0.0 and ref.gamma_new[3] == 0.0 and ref.gamma_new[2] != 0.0
+    compare(mc, got, ref, True, "bounds")
+    assert abs(got["ft"][k[2]] - (v + d)) <= 1e-9 * max(1.0, abs(v))
+
+
+def test_parts_impulse(ctx):
+    """Each part's own motion enters the impulse's motion term."""
+    say("[parts] impulse")
+    mc = wl.mixed_bodies_case()
+    run = MultiRun(ctx, mc, gpf.GPF_FP64, impulse=True)
+    got = run.solve()
+    p, body, part = multi_of(mc)
+    ref = solve_multi(p, body, part)
+    ub = np.array([mc.parts[j].get("ub", 0.0) for j in part])
+    vb = np.array([mc.parts[j].get("vb", 0.0) for j in part])
+    om = np.array([mc.parts[j].get("omega", 0.0) for j in part])
+    vx = ub - mc.u_inf - om * body.ys
+    vy = vb - mc.v_inf + om * body.xs
+    nx = np.concatenate([s.nx if s.nx is not None else np.zeros(s.ns) for s in mc.surfaces])
+    ny = np.concatenate([s.ny if s.ny is not None else np.zeros(s.ns) for s in mc.surfaces])
+    run.body.set_normals(nx, ny)
+    got = run.solve()
+    X = np.r_[p.X, [z[0] for z in mc.znew]]
+    Y = np.r_[p.Y, [z[1] for z in mc.znew]]
+    G = np.r_[p.G, ref.gamma_new]
+    want = oracle_impulse(p.grid, X, Y, G, body.xs, body.ys, body.ds, ref.f, nx, ny, vx, vy)
+    err = np.max(np.abs(run.imp.cpu().numpy() - want)) / np.max(np.abs(want))
+    say(f"   impulse err {err:.2e}")
+    assert err <= 1e-9
+
+
+def test_batch_mixes_parts_and_single_bodies(ctx):
+    """A batch of several-part and one-body problems on one grid: each as
+    solved alone."""
+    mc = wl.two_plates_case(n=128, nv=300)
+    runs = [MultiRun(ctx, mc, gpf.GPF_FP64) for _ in range(2)]
+    alone = runs[0].solve()
+    case = wl.random_case(18, 128, mc.dx, 200, surface="plate", mode="shed")
+    single = gpf.Solver(ctx, case.n, case.dx, case.surface, flags=gpf.GPF_FP64,
+                        edges=tuple(case.edges))
+    Xs, Ys, Gs = single.upload(case)
+    s_inp = single.inputs_for(case, Xs, Ys, Gs)
+    single.solve(s_inp, Xs)
+    gpf.gpf_sync(single.status)
+    ref_single = single.psi.cpu().numpy().copy()
+    b = gpf.Batch(ctx, 4)
+    runs[1].status.zero_()
+    single.status.zero_()
+    s_out = single.outputs(case.nv)
+    b.solve([runs[1].plan, single.plan], [runs[1].body, single.body], [runs[1].inp, s_inp],
+            [runs[1].out, s_out])
+    gpf.gpf_sync(runs[1].status)
+    gpf.gpf_sync(single.status)
+    assert rell2(runs[1].psi.cpu().numpy(), alone["s"]) <= 1e-12
+    assert rell2(single.psi.cpu().numpy(), ref_single) <= 1e-12
+
+
+def test_parts_arguments_checked(ctx):
+    mc = wl.two_plates_case(n=128, nv=50)
+    run = MultiRun(ctx, mc, gpf.GPF_FP64)
+    run.inp.nparts = 3
+    with pytest.raises(gpf.GpfError) as e:
+        gpf.gpf_solve(run.plan, run.body, run.inp, run.out)
+    assert e.value.status == gpf.GPF_E_INVALID
+    run.inp.nparts = 2
+    run.inp.m = 3                    # four shedding edges
+    with pytest.raises(gpf.GpfError) as e:
+        gpf.gpf_solve(run.plan, run.body, run.inp, run.out)
+    assert e.value.status == gpf.GPF_E_INVALID
+    plan = gpf.Plan(ctx, mc.n, mc.dx, flags=gpf.GPF_FP64)
+    body = gpf.Body(plan, mc.xs, mc.ys, mc.ds, mc.edges)
+    with pytest.raises(gpf.GpfError) as e:
+        body.set_parts(np.r_[np.zeros(len(mc.xs) - 1, int), 5])
+    assert e.value.status in (gpf.GPF_E_INVALID, gpf.GPF_E_UNSUPPORTED)
