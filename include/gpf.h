@@ -245,12 +245,38 @@ gpf_status gpf_body_info(const gpf_body *body, double *gamma0, double *amp,
 /* Copy the body's f0 = S^-1 1 (ns doubles) to host memory.  Blocking. */
 gpf_status gpf_body_f0(const gpf_body *body, double *h_f0);
 
-/* Unit surface normals pointing into the fluid (ns doubles each, host),
- * used by the impulse's body-motion term and the body's area and centroid
- * (appendix on discrete surfaces).  A body without normals (the default) is
- * taken as having zero thickness, like a plate, whose two faces cancel in
- * those terms.  Non-finite values: GPF_E_INVALID.  Blocking. */
-gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double *h_ny);
+/* Unit surface normals (ns doubles each, host).  closed = 1: the points
+ * enclose a region and the normals point into the fluid; they enter the
+ * impulse's body-motion term and the body's area and centroid (appendix on
+ * discrete surfaces).  closed = 0: a body of zero thickness (a plate); the
+ * normals only orient its two sides for the pressure (+ side = the side
+ * the normal points to) and the motion term and area are zero, its two
+ * faces cancelling.  A body without normals counts as of zero thickness
+ * and has no pressure.  Also builds the pressure operator
+ * Q = -(C_s L^-1 C_s^T)^+ C_s L^-1 R_s (Sec. 2.6.1; a closed surface's
+ * uniform direction removed, dS-weighted mean of dphi zero) when every
+ * point lies two nodes inside the window and ns <= 4096.  Non-finite
+ * values: GPF_E_INVALID.  Blocking. */
+gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double *h_ny, int closed);
+
+/* Pressure of a solved problem (Sec. 2.6.1).  d_psi and d_f are the
+ * solve's field and sheet (same plan, body, inputs `in`: uniform flow,
+ * body or part motion).  Writes on the device:
+ *   d_dphi (ns): the potential jump across the surface, dphi = Q f;
+ *   d_dp (ns): the pressure jump p+ - p- from the surface Bernoulli
+ *     equation (eq. surfbernoulli), d(dphi)/dt = (dphi - d_dphi_prev)/dt
+ *     when d_dphi_prev (the previous time level's d_dphi) is given, else 0;
+ *   d_p (n*n, nullable): the grid pressure on the cell centres
+ *     (x0 + (i+1/2) dx, y0 + (j+1/2) dx) at [j*n + i], i, j < n-1 (eq.
+ *     pgrid; last row and column zero), up to a uniform value;
+ *   d_pside (2 ns, nullable, needs d_p): p+ then p- on the two sides,
+ *     E_c p +- dp/2.
+ * rho is the fluid density.  Asynchronous on hip_stream; the body needs
+ * normals (GPF_E_INVALID) and its pressure operator (GPF_E_UNSUPPORTED). */
+gpf_status gpf_pressure(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
+                        const void *d_psi, const double *d_f, const double *d_dphi_prev,
+                        double dt, double rho, double *d_dphi, double *d_dp, double *d_p,
+                        double *d_pside, void *hip_stream);
 
 /* Split the body's points into nparts parts (2..GPF_MAX_PARTS; h_part[p]
  * is the part of point p, every part non-empty) for mode GPF_PARTS: the

@@ -35,7 +35,8 @@ y-faces (x_i + dx/2, y_j) ((n) x (n-1)); the pressure on the cell centres
 Readings: the operator C_s L^-1 C_s^T of a closed surface has the uniform
 vector in its null space (the paper; numerically a small eigenvalue), so
 dphi, which is defined up to a constant there, is computed with that
-direction removed: the dS-weighted mean of dphi is zero.  An open surface (a
+direction removed: the dS-weighted mean of dphi is zero (per part for
+several closed bodies).  An open surface (a
 plate) has no such freedom; its operator is inverted as it is, with the
 normal of one side.  d(dphi)/dt is supplied by the caller (a difference of
 two time levels).
@@ -121,8 +122,10 @@ def jump_operator(grid: Grid, xs, ys, ds, nx, ny, table=None) -> np.ndarray:
     return M
 
 
-def potential_jump(grid: Grid, xs, ys, ds, nx, ny, f, closed: bool, M=None, table=None):
-    """dphi = -M^+ C_s L^-1 R_s f; closed surfaces: dS-weighted mean zero."""
+def potential_jump(grid: Grid, xs, ys, ds, nx, ny, f, closed: bool, M=None, table=None,
+                   part=None):
+    """dphi = -M^+ C_s L^-1 R_s f; closed surfaces: dS-weighted mean zero
+    (on each part of a several-part body, each part being closed)."""
     xs, ys, ds = (np.asarray(a, np.float64) for a in (xs, ys, ds))
     if M is None:
         M = jump_operator(grid, xs, ys, ds, nx, ny, table)
@@ -131,11 +134,14 @@ def potential_jump(grid: Grid, xs, ys, ds, nx, ny, f, closed: bool, M=None, tabl
     if not closed:
         return np.linalg.solve(M, b)
     ns = len(xs)
-    A = np.zeros((ns + 1, ns + 1))
+    part = np.zeros(ns, int) if part is None else np.asarray(part)
+    nb = int(part.max()) + 1
+    A = np.zeros((ns + nb, ns + nb))
     A[:ns, :ns] = M
-    A[:ns, ns] = 1.0
-    A[ns, :ns] = ds
-    x = np.linalg.solve(A, np.r_[b, 0.0])
+    for j in range(nb):
+        A[:ns, ns + j] = part == j
+        A[ns + j, :ns] = ds * (part == j)
+    x = np.linalg.solve(A, np.r_[b, np.zeros(nb)])
     return x[:ns]
 
 

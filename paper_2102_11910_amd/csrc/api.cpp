@@ -832,32 +832,218 @@ gpf_status gpf_body_f0(const gpf_body *body, double *h_f0) {
   return GPF_OK;
 }
 
-gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double *h_ny) {
+namespace {
+
+// Pressure operators of a body with normals (Sec. 2.6.1):
+// Q = -(C_s L^-1 C_s^T)^+ C_s L^-1 R_s; for a closed surface the operator's
+// uniform direction is removed by bordering it with 1 and dS (dS-weighted
+// mean of dphi zero), an open one is inverted as it is.
+gpf_status pressure_setup(gpf_body *b) {
+  b->has_pressure = false;
+  const gpf_plan *pl = b->plan;
+  const gpf_grid &g = pl->grid;
+  const int ns = b->ns;
+  for (int p = 0; p < ns; ++p) {   // face stencils need one more node of margin
+    const double xi = (b->hxs[p] - g.x0) / g.dx, eta = (b->hys[p] - g.y0) / g.dx;
+    if (!(xi >= 2.0 && xi < g.n - 3.0 && eta >= 2.0 && eta < g.n - 3.0)) return GPF_OK;
+  }
+  if (ns > 4096) return GPF_OK;
+  hipStream_t s = nullptr;
+  const size_t vb = ns * sizeof(double);
+  GPF_TRY(b->pst.alloc(ns * sizeof(PresStencil)));
+  GPF_TRY(b->qpres.alloc((size_t)ns * vb));
+  const int nb = b->nparts;
+  const int N = b->closed ? ns + nb : ns;
+  DevBuf M, K, A, Ainv;
+  GPF_TRY(M.alloc((size_t)ns * vb));
+  GPF_TRY(K.alloc((size_t)ns * vb));
+  GPF_TRY(A.alloc((size_t)N * N * sizeof(double)));
+  GPF_TRY(Ainv.alloc((size_t)N * N * sizeof(double)));
+  GPF_HIP(launch_pres_stencils(ns, b->xs.as<double>(), b->ys.as<double>(), g.x0, g.y0, g.dx,
+                               b->pst.as<PresStencil>(), s));
+  GPF_HIP(launch_pres_build(g.n, ns, b->pst.as<PresStencil>(), b->pnx.as<double>(),
+                            b->pny.as<double>(), b->st_i.as<int>(), b->st_w.as<double>(),
+                            b->ds.as<double>(), g.dx, pl->lgf.as<double>(), M.as<double>(),
+                            K.as<double>(), s));
+  if (b->closed) {
+    // [M 1_j; (dS o 1_j)^T 0], one border per part, assembled on the host
+    std::vector<double> hm((size_t)ns * ns), ha((size_t)N * N, 0.0);
+    GPF_HIP(hipMemcpy(hm.data(), M.p, (size_t)ns * vb, hipMemcpyDeviceToHost));
+    for (int p = 0; p < ns; ++p) {
+      const int j = nb > 1 ? b->hpart[p] : 0;
+      for (int q = 0; q < ns; ++q) ha[(size_t)p * N + q] = hm[(size_t)p * ns + q];
+      ha[(size_t)p * N + ns + j] = 1.0;
+      ha[(size_t)(ns + j) * N + p] = b->hds[p];
+    }
+    GPF_HIP(hipMemcpy(A.p, ha.data(), ha.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    GPF_HIP(hipMemcpy(A.p, M.p, (size_t)ns * vb, hipMemcpyDeviceToDevice));
+  }
+  double min_piv = 0.0;
+  GPF_TRY(invert_fp64(N, A.as<double>(), Ainv.as<double>(), s, &min_piv));
+  if (!(min_piv > 1e-14)) return GPF_OK;
+  GPF_HIP(launch_pres_q(ns, N, Ainv.as<double>(), K.as<double>(), b->qpres.as<double>(), s));
+  GPF_HIP(hipDeviceSynchronize());
+  b->has_pressure = true;
+  return GPF_OK;
+}
+
+}  // namespace
+
+gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double *h_ny, int closed) {
   if (!body || !h_nx || !h_ny) return fail(GPF_E_INVALID, "gpf_body_set_normals: null argument");
   const int ns = body->ns;
   for (int p = 0; p < ns; ++p)
     if (!is_finite(h_nx[p]) || !is_finite(h_ny[p]))
       return fail(GPF_E_INVALID, "gpf_body_set_normals: non-finite normal");
   GPF_HIP(hipSetDevice(body->plan->ctx->device));
-  GPF_HIP(hipMemcpy(body->nx.p, h_nx, ns * sizeof(double), hipMemcpyHostToDevice));
-  GPF_HIP(hipMemcpy(body->ny.p, h_ny, ns * sizeof(double), hipMemcpyHostToDevice));
-  // area and centroid (eq. centroid); the area as the mean of its two forms
-  double vx = 0.0, vy = 0.0, cx = 0.0, cy = 0.0;
-  for (int p = 0; p < ns; ++p) {
-    const double x = body->hxs[p], y = body->hys[p], w = body->hds[p];
-    const double r2 = x * x + y * y;
-    vx += w * x * h_nx[p];
-    vy += w * y * h_ny[p];
-    cx += w * r2 * h_nx[p];
-    cy += w * r2 * h_ny[p];
-  }
-  const double V = 0.5 * (vx + vy);
+  const size_t vb = ns * sizeof(double);
+  GPF_TRY(body->pnx.alloc(vb));
+  GPF_TRY(body->pny.alloc(vb));
+  GPF_HIP(hipMemcpy(body->pnx.p, h_nx, vb, hipMemcpyHostToDevice));
+  GPF_HIP(hipMemcpy(body->pny.p, h_ny, vb, hipMemcpyHostToDevice));
+  body->closed = closed != 0;
   body->has_normals = true;
-  body->area = V;
-  if (V != 0.0) {
-    body->xc = cx / (2.0 * V);
-    body->yc = cy / (2.0 * V);
+  if (body->closed) {
+    // the impulse's motion term, area and centroid (eq. centroid); the area
+    // as the mean of its two forms
+    GPF_HIP(hipMemcpy(body->nx.p, h_nx, vb, hipMemcpyHostToDevice));
+    GPF_HIP(hipMemcpy(body->ny.p, h_ny, vb, hipMemcpyHostToDevice));
+    double vx = 0.0, vy = 0.0, cx = 0.0, cy = 0.0;
+    for (int p = 0; p < ns; ++p) {
+      const double x = body->hxs[p], y = body->hys[p], w = body->hds[p];
+      const double r2 = x * x + y * y;
+      vx += w * x * h_nx[p];
+      vy += w * y * h_ny[p];
+      cx += w * r2 * h_nx[p];
+      cy += w * r2 * h_ny[p];
+    }
+    const double V = 0.5 * (vx + vy);
+    body->area = V;
+    if (V != 0.0) {
+      body->xc = cx / (2.0 * V);
+      body->yc = cy / (2.0 * V);
+    }
+  } else {
+    // zero thickness: its two faces cancel in the motion term
+    GPF_HIP(hipMemset(body->nx.p, 0, vb));
+    GPF_HIP(hipMemset(body->ny.p, 0, vb));
+    body->area = 0.0;
+    double L = 0.0, sx = 0.0, sy = 0.0;
+    for (int p = 0; p < ns; ++p) {
+      L += body->hds[p];
+      sx += body->hds[p] * body->hxs[p];
+      sy += body->hds[p] * body->hys[p];
+    }
+    body->xc = sx / L;
+    body->yc = sy / L;
   }
+  return pressure_setup(body);
+}
+
+gpf_status gpf_pressure(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in, const void *d_psi,
+                        const double *d_f, const double *d_dphi_prev, double dt, double rho,
+                        double *d_dphi, double *d_dp, double *d_p, double *d_pside,
+                        void *hip_stream) {
+  if (!plan || !body || !in || !d_psi || !d_f || !d_dphi || !d_dp || !is_finite(rho) ||
+      (d_dphi_prev && !(dt > 0.0 && is_finite(dt))) || (d_pside && !d_p))
+    return fail(GPF_E_INVALID, "gpf_pressure: bad arguments");
+  if (body->plan != plan) return fail(GPF_E_INVALID, "gpf_pressure: body belongs to another plan");
+  if (!body->has_normals) return fail(GPF_E_INVALID, "gpf_pressure: the body has no normals");
+  if (!body->has_pressure)
+    return fail(GPF_E_UNSUPPORTED, "gpf_pressure: no pressure operators for this body (surface "
+                                   "within two nodes of the window edge, ns > 4096, or singular)");
+  GPF_HIP(hipSetDevice(plan->ctx->device));
+  hipStream_t s = as_stream(hip_stream);
+  const gpf_grid &g = plan->grid;
+  const int n = g.n, ns = body->ns;
+  GPF_TRY(plan->pres_ddt.alloc(ns * sizeof(double)));
+  PresDesc D;
+  std::memset(&D, 0, sizeof(D));
+  D.n = n;
+  D.ns = ns;
+  D.psi_total = (plan->flags & GPF_PSI_TOTAL) ? 1 : 0;
+  D.dx = g.dx;
+  D.x0 = g.x0;
+  D.y0 = g.y0;
+  D.rho = rho;
+  D.dt = d_dphi_prev ? dt : 1.0;
+  D.u_inf = in->u_inf;
+  D.v_inf = in->v_inf;
+  D.ub = in->ub;
+  D.vb = in->vb;
+  D.omega = in->omega;
+  D.psi = d_psi;
+  D.f = d_f;
+  D.Q = body->qpres.as<double>();
+  D.dphi_prev = d_dphi_prev;
+  D.xs = body->xs.as<double>();
+  D.ys = body->ys.as<double>();
+  D.ds = body->ds.as<double>();
+  D.pnx = body->pnx.as<double>();
+  D.pny = body->pny.as<double>();
+  D.st = body->pst.as<PresStencil>();
+  D.st_i = body->st_i.as<int>();
+  D.st_w = body->st_w.as<double>();
+  if (in->mode == GPF_PARTS && body->nparts > 1) {
+    D.part = body->part.as<int>();
+    for (int j = 0; j < in->nparts && j < GPF_MAX_PARTS; ++j) {
+      D.pub[j] = in->parts[j].ub;
+      D.pvb[j] = in->parts[j].vb;
+      D.pom[j] = in->parts[j].omega;
+    }
+  }
+  D.dphi = d_dphi;
+  D.dp = d_dp;
+  D.ddt = plan->pres_ddt.as<double>();
+  if (plan->fp64)
+    GPF_HIP(launch_pres_surface_part<double>(D, s));
+  else
+    GPF_HIP(launch_pres_surface_part<float>(D, s));
+  if (!d_p) return GPF_OK;
+  // grid pressure: source on the cells, one FP64 convolution, finish
+  const size_t fb = (size_t)n * n * sizeof(double);
+  GPF_TRY(plan->ensure_fp64());
+  GPF_TRY(plan->pres_w.alloc(fb));
+  GPF_TRY(plan->pres_fx.alloc(fb));
+  GPF_TRY(plan->pres_fy.alloc(fb));
+  GPF_TRY(plan->pres_src.alloc(fb));
+  GPF_TRY(plan->pres_tmp.alloc(fb));
+  GPF_TRY(plan->pres_X.alloc((size_t)(n + 1) * n * 16));
+  GPF_HIP(launch_fill(plan->pres_w.p, fb, s));
+  GPF_HIP(launch_fill(plan->pres_fx.p, fb, s));
+  GPF_HIP(launch_fill(plan->pres_fy.p, fb, s));
+  D.wsheet = plan->pres_w.as<double>();
+  D.fx = plan->pres_fx.as<double>();
+  D.fy = plan->pres_fy.as<double>();
+  D.src = plan->pres_src.as<double>();
+  D.tmp = plan->pres_tmp.as<double>();
+  D.p = d_p;
+  D.pside = d_pside;
+  if (plan->fp64)
+    GPF_HIP(launch_pres_field_part<double>(D, s));
+  else
+    GPF_HIP(launch_pres_field_part<float>(D, s));
+  ConvDesc cd;
+  std::memset(&cd, 0, sizeof(cd));
+  cd.in = D.src;
+  cd.X = plan->pres_X.p;
+  cd.out = D.tmp;
+  cd.spec = plan->spec64.p;
+  cd.tw = plan->tw64.p;
+  cd.gamma = nullptr;
+  cd.gamma_val = 0.0;   // a divergence: no net source; the pressure's constant is free
+  cd.c = plan->gauge_c;
+  cd.zero_in = 0;
+  cd.row_lo = 0;
+  cd.row_hi = n - 1;
+  void *dev = nullptr;
+  GPF_TRY(plan->ring.push(&cd, sizeof(cd), s, &dev));
+  GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, plan->ctx->xcds, false, s)));
+  if (plan->fp64)
+    GPF_HIP(launch_pres_finish<double>(D, s));
+  else
+    GPF_HIP(launch_pres_finish<float>(D, s));
   return GPF_OK;
 }
 
@@ -912,6 +1098,7 @@ gpf_status gpf_body_set_parts(gpf_body *body, int nparts, const int *h_part) {
   body->gpart.swap(gpart);
   body->zpart.swap(zpart);
   body->cpart.swap(cpart);
+  if (body->has_normals) return pressure_setup(body);   // one border per part
   return GPF_OK;
 }
 

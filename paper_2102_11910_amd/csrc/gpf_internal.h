@@ -234,6 +234,41 @@ template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
 
 // xo = x + a u, yo = y + a v (in place allowed)
+// pressure (Sec. 2.6.1): three-point weights of a surface point on the
+// u-faces (x_i, y_j + dx/2) and the v-faces (x_i + dx/2, y_j)
+struct PresStencil {
+  int iu, ju, iv, jv;
+  double wxu[4], wyu[4], wxv[4], wyv[4];
+};
+struct PresDesc {
+  int n, ns, psi_total;
+  double dx, x0, y0, rho, dt, u_inf, v_inf, ub, vb, omega;
+  const void *psi;             // final field of the solve (plan field type)
+  const double *f, *Q, *dphi_prev;
+  const double *xs, *ys, *ds, *pnx, *pny;
+  const PresStencil *st;
+  const int *st_i;
+  const double *st_w;
+  const int *part;             // GPF_PARTS: part of each point, else null
+  double pub[GPF_MAX_PARTS], pvb[GPF_MAX_PARTS], pom[GPF_MAX_PARTS];
+  double *dphi, *dp, *ddt;     // ns each
+  double *wsheet, *fx, *fy, *src, *tmp;   // n x n FP64 work fields
+  double *p, *pside;           // outputs of the field part (nullable)
+};
+hipError_t launch_pres_stencils(int ns, const double *xs, const double *ys, double x0, double y0,
+                                double dx, PresStencil *st, hipStream_t s);
+hipError_t launch_pres_build(int n, int ns, const PresStencil *st, const double *pnx, const double *pny,
+                             const int *st_i, const double *st_w, const double *ds, double dx,
+                             const double *lgf, double *M, double *K, hipStream_t s);
+// Q = -A K (A: leading dimension lda, first ns rows/columns; K, Q column-major)
+hipError_t launch_pres_q(int ns, int lda, const double *A, const double *K, double *Q, hipStream_t s);
+template <class T>
+hipError_t launch_pres_surface_part(const PresDesc &D, hipStream_t s);
+template <class T>
+hipError_t launch_pres_field_part(const PresDesc &D, hipStream_t s);
+template <class T>
+hipError_t launch_pres_finish(const PresDesc &D, hipStream_t s);
+
 // shedding steps (nv counts the new vortices; nv >= m >= 1)
 struct ShedGeom {
   int m;
@@ -311,6 +346,9 @@ struct gpf_plan {
   std::vector<std::unique_ptr<gpf_stream_slot>> slots;   // GPF_PLAN_MULTISTREAM
   gpf_status ensure_fp64();
   gpf_status slot_for(hipStream_t s, gpf_stream_slot **out);
+  // pressure work fields (n x n FP64: sheet vorticity, face terms, source,
+  // convolution result) and the FP64 convolution intermediate; ns scratch
+  gpf::DevBuf pres_w, pres_fx, pres_fy, pres_src, pres_tmp, pres_X, pres_ddt;
 };
 
 struct gpf_body {
@@ -327,8 +365,12 @@ struct gpf_body {
   gpf::DevBuf sinv;           // ns x ns S^-1, row-major, FP64
   gpf::DevBuf f0;             // S^-1 1
   gpf::DevBuf ghat;           // S^-T dS
-  gpf::DevBuf nx, ny;         // unit normals into the fluid (zeros until set)
+  gpf::DevBuf nx, ny;         // normals of the impulse's motion term (zeros: thin body)
   bool has_normals = false;
+  // pressure: unit normals of the sides (+ side = normal side), the
+  // stencils and Q = -(C_s L^-1 C_s^T)^+ C_s L^-1 R_s (column-major)
+  bool closed = false, has_pressure = false;
+  gpf::DevBuf pnx, pny, pst, qpres;
   double area = 0.0, xc = 0.0, yc = 0.0;   // enclosed area and centroid
   std::vector<double> hxs, hys, hds, hf0;  // host copies of the geometry and f0
   // parts (gpf_body_set_parts); nparts = 1 without

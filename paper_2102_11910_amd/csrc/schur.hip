@@ -15,16 +15,11 @@
 //       sum_j (1 + fhat0.P_{k_i} f~_j) Gamma_j = -(Gamma_w + fhat0.P_{k_i} f~*),
 //       x = f~* + sum Gamma_j f~_j, s0 = mean_i x_{k_i}, f~ = x - s0
 #include "gpf_internal.h"
+#include "weights.h"
 
 namespace gpf {
 namespace {
 
-__device__ __forceinline__ double m4p(double r) {
-  r = fabs(r);
-  if (r <= 1.0) return 1.0 - 2.5 * r * r + 1.5 * r * r * r;
-  if (r <= 2.0) return 0.5 * (2.0 - r) * (2.0 - r) * (1.0 - r);
-  return 0.0;
-}
 
 // S[p][q], one thread per entry
 __global__ __launch_bounds__(256) void k_schur_build(int n, int ns, const int *__restrict__ st_i,

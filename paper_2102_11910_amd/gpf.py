@@ -104,7 +104,8 @@ def _load():
         "gpf_body_destroy": (None, [P]),
         "gpf_body_info": (I, [P, DP, DP, C.POINTER(C.c_int)]),
         "gpf_body_f0": (I, [P, DP]),
-        "gpf_body_set_normals": (I, [P, DP, DP]),
+        "gpf_body_set_normals": (I, [P, DP, DP, I]),
+        "gpf_pressure": (I, [P, P, C.POINTER(gpf_inputs), P, P, P, D, D, P, P, P, P, P]),
         "gpf_body_geometry": (I, [P, DP, DP, DP]),
         "gpf_body_added_mass": (I, [P, D, DP]),
         "gpf_body_set_parts": (I, [P, I, C.POINTER(C.c_int)]),
@@ -272,11 +273,12 @@ class Body:
         check(lib.gpf_body_f0(self.h, out.ctypes.data_as(C.POINTER(C.c_double))), "gpf_body_f0")
         return out
 
-    def set_normals(self, nx, ny):
+    def set_normals(self, nx, ny, closed: bool = True):
+        """Unit normals; closed=False for a zero-thickness body (a plate)."""
         ax, px = _dp(nx)
         ay, py = _dp(ny)
         assert len(ax) == len(ay) == self.ns
-        check(lib.gpf_body_set_normals(self.h, px, py), "gpf_body_set_normals")
+        check(lib.gpf_body_set_normals(self.h, px, py, int(bool(closed))), "gpf_body_set_normals")
 
     def set_parts(self, part):
         """Split the points into parts: part[p] = part of point p."""
@@ -351,6 +353,16 @@ def make_parts_inputs(X, Y, G, parts, znew=(), fbounds=(), u_inf=0.0, v_inf=0.0)
         inp.parts[j].vb = q.get("vb", 0.0)
         inp.parts[j].omega = q.get("omega", 0.0)
     return inp
+
+
+def gpf_pressure(plan: Plan, body: Body, inp: gpf_inputs, psi, f, dphi, dp, p=None, pside=None,
+                 dphi_prev=None, dt: float = 0.0, rho: float = 1.0, stream=None):
+    """Pressure of a solved problem into the given device tensors."""
+    check(lib.gpf_pressure(plan.h, body.h, C.byref(inp), _ptr(psi), _ptr(f),
+                           None if dphi_prev is None else _ptr(dphi_prev), float(dt), float(rho),
+                           _ptr(dphi), _ptr(dp), None if p is None else _ptr(p),
+                           None if pside is None else _ptr(pside), _stream_ptr(stream)),
+          "gpf_pressure")
 
 
 def make_outputs(psi, u=None, v=None, f=None, ftilde=None, scalars=None, status=None,

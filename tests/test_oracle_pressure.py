@@ -116,3 +116,30 @@ def test_open_plate_jump_operator_is_invertible():
     M = pr.jump_operator(grid, surf.xs, surf.ys, surf.ds, nx, ny)
     ev = np.linalg.eigvalsh(0.5 * (M + M.T))
     assert ev[-1] < 0 and abs(ev[-1]) >= 1e-3 * abs(ev[0])
+
+
+def test_two_cylinders_mirror_potential_jump():
+    """Two mirror-image cylinders (several-part body, each part closed) in a
+    uniform flow along the mirror line, with mirrored vortices of opposite
+    strength: the potential jump is even under the reflection (the sheet,
+    its derivative along the surface, is odd), and each part's dS-weighted
+    mean is zero."""
+    from oracle.multibody import BodySpec, MultiProblem, solve_multi
+    grid = Grid.centered(96, 0.04)
+    th = 2 * np.pi * (np.arange(40) + 0.5) / 40
+    x1 = wl.f32(-0.8 + 0.4 * np.cos(th))
+    y1 = wl.f32(0.4 * np.sin(th))
+    xs, ys = np.r_[x1, -x1], np.r_[y1, y1]
+    ds = np.full(80, 2 * np.pi * 0.4 / 40)
+    nx1, ny1 = np.cos(th), np.sin(th)
+    nx, ny = np.r_[nx1, -nx1], np.r_[ny1, ny1]
+    part = np.r_[np.zeros(40, int), np.ones(40, int)]
+    body = body_setup(grid, xs, ys, ds)
+    X1 = np.array([-0.2, -1.5]); Y1 = np.array([0.7, -0.3]); G1 = np.array([0.4, -0.2])
+    specs = [BodySpec("circulation", gamma_b=0.3), BodySpec("circulation", gamma_b=-0.3)]
+    res = solve_multi(MultiProblem(grid, np.r_[X1, -X1], np.r_[Y1, Y1], np.r_[G1, -G1], specs,
+                                   u_inf=0.0, v_inf=1.0), body, part)
+    dphi = pr.potential_jump(grid, xs, ys, ds, nx, ny, res.f, True, part=part)
+    assert np.max(np.abs(dphi[:40] - dphi[40:])) <= 1e-9 * np.max(np.abs(dphi))
+    for j in range(2):
+        assert abs(np.dot(ds * (part == j), dphi)) <= 1e-10
