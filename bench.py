@@ -308,6 +308,61 @@ def shed_leg(gpf, torch, np, ctx, log, wl, steps=200):
     return res
 
 
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def diagnostics_leg(gpf, torch, np, ctx, log, wl, reps=50):
+    """The adjacent parts on the 512^2 plate workload: a solve with and
+    without the impulse, the pressure (surface part, and with the grid
+    pressure), and a several-body solve (the two plates of Fig. 16 at 256^2,
+    four new vortices)."""
+    dev = torch.device("cuda", 0)
+    case = wl.config2()
+    s = gpf.Solver(ctx, case.n, case.dx, case.surface, flags=gpf.GPF_POLICY_AUTO,
+                   edges=tuple(case.edges))
+    al = np.deg2rad(case.surface.params["alpha_deg"])
+    ns = case.surface.ns
+    s.body.set_normals(np.full(ns, np.sin(al)), np.full(ns, np.cos(al)), False)
+    X, Y, G = s.upload(case)
+    inp = s.inputs_for(case, X, Y, G)
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device=dev)
+    imp = z(3)
+    out_plain = s.outputs(case.nv, velocities=True)
+    out_imp = gpf.make_outputs(s.psi, s.u, s.v, s.f, s.ftilde, s.scalars, s.status, imp)
+    res = {"workload": f"{case.name}, nv={case.nv}"}
+    res["solve_ms"] = _timed(torch, lambda: gpf.gpf_solve(s.plan, s.body, inp, out_plain), reps)
+    res["solve_with_impulse_ms"] = _timed(torch, lambda: gpf.gpf_solve(s.plan, s.body, inp, out_imp),
+                                          reps)
+    dphi, dp, P, side = z(ns), z(ns), z(case.n * case.n), z(2 * ns)
+    res["pressure_surface_ms"] = _timed(
+        torch, lambda: gpf.gpf_pressure(s.plan, s.body, inp, s.psi, s.f, dphi, dp), reps)
+    res["pressure_with_field_ms"] = _timed(
+        torch, lambda: gpf.gpf_pressure(s.plan, s.body, inp, s.psi, s.f, dphi, dp, P, side), reps)
+    gpf.gpf_sync(s.status)
+    mc = wl.two_plates_case()
+    plan = gpf.Plan(ctx, mc.n, mc.dx, flags=gpf.GPF_POLICY_AUTO)
+    body = gpf.Body(plan, mc.xs, mc.ys, mc.ds, mc.edges)
+    body.set_parts(mc.part)
+    t = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float64).to(dev)
+    Xm, Ym, Gm = t(mc.X), t(mc.Y), t(mc.G)
+    psi = torch.empty((mc.n, mc.n), dtype=plan.field_dtype, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    minp = gpf.make_parts_inputs(Xm, Ym, Gm, mc.parts, mc.znew, (), mc.u_inf, mc.v_inf)
+    mout = gpf.make_outputs(psi, z(mc.nv), z(mc.nv), z(len(mc.xs)), None, z(gpf.N_SCALARS), st)
+    res["two_plates_workload"] = f"{mc.name}, nv={mc.nv}, ns={len(mc.xs)}, 4 new vortices"
+    res["two_plates_solve_ms"] = _timed(torch, lambda: gpf.gpf_solve(plan, body, minp, mout), reps)
+    gpf.gpf_sync(st)
+    log(f"[bench] diagnostics: {res}")
+    return res
+
+
 def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
     """64 independent problems of uneven size (n 128..1024, 1e3..1e5 vortices,
     ellipses): grid points per second batched vs solved one after another."""
@@ -600,6 +655,7 @@ def main() -> int:
     res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
     res["rk2"] = rk2_leg(gpf, torch, np, ctx, log, wl)
     res["shed"] = shed_leg(gpf, torch, np, ctx, log, wl)
+    res["diagnostics"] = diagnostics_leg(gpf, torch, np, ctx, log, wl)
     res["c4"] = c4_leg(gpf, torch, np, ctx, log, wl)
     res["c5"] = c5_leg(gpf, torch, np, ctx, log, wl)
     if not args.no_cpu_baseline:
