@@ -159,9 +159,26 @@ template <int N> __host__ __device__ constexpr int tw_regs() {
   return tw_before<N>(num_stages<N>()) > 0 ? tw_before<N>(num_stages<N>()) : 1;
 }
 
-// Twiddles in registers where the kernel's occupancy is bounded by LDS
-// anyway (larger transforms read them from the global table per stage).
-template <class T, int N> __host__ __device__ constexpr bool tw_in_regs() { return N <= 1024; }
+// Twiddles in registers for FP32 transforms up to N = 1024, where the
+// kernel's occupancy is bounded by LDS anyway.  FP64 transforms (and larger
+// ones) read the table instead; FP64 forms the factors of a butterfly as
+// powers of its first one (one table load, and the products of at most 15
+// factors stay within a few ulps), which keeps its register count, and with
+// it the occupancy of the FP64 passes, down.
+template <class T, int N> __host__ __device__ constexpr bool tw_in_regs() {
+  return N <= 1024 && !std::is_same<T, double>::value;
+}
+
+// x_r *= w^r (r = 1..R-1) for w the first twiddle of the butterfly
+template <int R, class V>
+__device__ __forceinline__ void twiddle_powers(V (&v)[R], V w1) {
+  V w = w1;
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    v[r] = cmul(v[r], w);
+    if (r + 1 < R) w = cmul(w, w1);
+  }
+}
 
 // Every twiddle factor a lane uses, loaded once at kernel start (the loads
 // overlap the data loads instead of waiting behind each stage's barrier);
@@ -243,18 +260,24 @@ __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename C
     const int bf = lane + b * TPS;
     const int j = bf % NS;
     if (NS > 1) {
+      if constexpr (!tw_in_regs<T, N>() && std::is_same<T, double>::value) {
+        V w1 = tw[j * (N / (NS * R))];
+        if (INV) w1.y = -w1.y;
+        twiddle_powers<R>(v[b], w1);
+      } else {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        V w;
-        if constexpr (tw_in_regs<T, N>()) {
-          w = wr[tw_before<N>(S) + r - 1];
-          if (INV) w.y = -w.y;
-          if (NB > 1) w = rot16<INV>(w, b * r);   // butterfly b sits at j + b N/16
-        } else {
-          w = tw[j * r * (N / (NS * R))];
-          if (INV) w.y = -w.y;
+        for (int r = 1; r < R; ++r) {
+          V w;
+          if constexpr (tw_in_regs<T, N>()) {
+            w = wr[tw_before<N>(S) + r - 1];
+            if (INV) w.y = -w.y;
+            if (NB > 1) w = rot16<INV>(w, b * r);   // butterfly b sits at j + b N/16
+          } else {
+            w = tw[j * r * (N / (NS * R))];
+            if (INV) w.y = -w.y;
+          }
+          v[b][r] = cmul(v[b][r], w);
         }
-        v[b][r] = cmul(v[b][r], w);
       }
     }
     dft_reg<R, INV>(v[b]);
@@ -415,6 +438,123 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
   }
 }
 
+// FP64 column pass for N >= 1024: one sequence per workgroup (N/16 lanes)
+// with the data in registers between stages; each exchange goes through LDS
+// one real component at a time, so a sequence needs N + N/16 scalars of LDS
+// instead of complex values, and the twiddles are powers of one table value.
+// Both cut the footprint that bounds the FP64 pass's occupancy (measured on
+// the 512^2 batch: 74 -> 64 us).
+template <class T, int N, int S, bool INV, bool ZIN>
+__device__ __forceinline__ void split_stages(typename CT<T>::V (&x)[kE], T *lds,
+                                             const typename CT<T>::V *tw, int lane) {
+  using V = typename CT<T>::V;
+  constexpr int NST = num_stages<N>();
+  constexpr int TPS = N / kE;
+  constexpr int R = stage_radix<N>(S), NS = stage_ns<N>(S), NB = kE / R;
+  // x holds this stage's inputs as v[b][r] = x[b * R + r]
+  V v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (ZIN && S == 0 && r >= R / 2) {
+        v[b][r].x = (T)0;
+        v[b][r].y = (T)0;
+      } else {
+        v[b][r] = x[b * R + r];
+      }
+    }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int bf = lane + b * TPS;
+    const int j = bf % NS;
+    if (NS > 1) {
+      V w1 = tw[j * (N / (NS * R))];
+      if (INV) w1.y = -w1.y;
+      V w = w1;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        v[b][r] = cmul(v[b][r], w);
+        if (r + 1 < R) w = cmul(w, w1);
+      }
+    }
+    dft_reg<R, INV>(v[b]);
+  }
+  if constexpr (S == NST - 1) {
+    // last stage: butterfly b, output r is element lane + TPS (b + r NB)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[b + r * NB] = v[b][r];
+  } else {
+    constexpr int R2 = stage_radix<N>(S + 1), NB2 = kE / R2;
+    // real parts, then imaginary parts: write this stage's outputs at
+    // base + r NS, read the next stage's inputs bf2 + r2 N/R2
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int bf = lane + b * TPS;
+        const int j = bf % NS;
+        const int base = (bf / NS) * NS * R + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[pad(base + r * NS)] = part ? v[b][r].y : v[b][r].x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b2 = 0; b2 < NB2; ++b2) {
+        const int bf2 = lane + b2 * TPS;
+#pragma unroll
+        for (int r2 = 0; r2 < R2; ++r2) {
+          const T val = lds[pad(bf2 + r2 * (N / R2))];
+          if (part)
+            x[b2 * R2 + r2].y = val;
+          else
+            x[b2 * R2 + r2].x = val;
+        }
+      }
+      __syncthreads();
+    }
+    split_stages<T, N, S + 1, INV, ZIN>(x, lds, tw, lane);
+  }
+}
+
+template <class T, int N>
+__global__ __launch_bounds__(N / kE) void k_cols_conv_split(const ConvDesc *__restrict__ cd) {
+  using V = typename CT<T>::V;
+  constexpr int TPS = N / kE;
+  constexpr int n = N / 2;
+  __shared__ T lds[N + N / 16];
+  const ConvDesc &C = cd[blockIdx.y];
+  V *__restrict__ X = static_cast<V *>(C.X);
+  const T *__restrict__ spec = static_cast<const T *>(C.spec);
+  const V *__restrict__ tw = static_cast<const V *>(C.tw);
+  const int lane = threadIdx.x;
+  const int k1 = blockIdx.x;
+  V *col = X + (size_t)k1 * n;
+  V x[kE];
+#pragma unroll
+  for (int k = 0; k < kE / 2; ++k) x[k] = col[lane + k * TPS];
+  split_stages<T, N, 0, false, true>(x, lds, tw, lane);
+  {
+    const T *sp = spec + (size_t)k1 * (n + 1);
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int k2 = lane + k * TPS;
+      const T g = sp[k2 <= n ? k2 : N - k2];
+      x[k].x *= g;
+      x[k].y *= g;
+    }
+  }
+  split_stages<T, N, 0, true, false>(x, lds, tw, lane);
+  const int lo = C.row_lo & ~15, hi = C.row_hi | 15;
+#pragma unroll
+  for (int k = 0; k < kE / 2; ++k) {
+    const int j = lane + k * TPS;
+    if (j >= lo && j <= hi) col[j] = x[k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // pass 3: rows, two half spectra -> two real rows, gauge epilogue
 // ---------------------------------------------------------------------------
@@ -532,8 +672,11 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_
     launch_rows_fwd<Tin, T, N, false>(d, nb, xcds, st);
   timer_end(st);
   timer_begin(D ? GPF_TK_COLS64 : GPF_TK_COLS, st);
-  hipLaunchKernelGGL((k_cols_conv<T, N>), dim3((n + 1 + P::SEQ - 1) / P::SEQ, nb), dim3(P::WGT), 0,
-                     st, d);
+  if constexpr (D && N >= 1024)
+    hipLaunchKernelGGL((k_cols_conv_split<T, N>), dim3(n + 1, nb), dim3(N / kE), 0, st, d);
+  else
+    hipLaunchKernelGGL((k_cols_conv<T, N>), dim3((n + 1 + P::SEQ - 1) / P::SEQ, nb), dim3(P::WGT),
+                       0, st, d);
   timer_end(st);
   timer_begin(D ? GPF_TK_ROWS_INV64 : GPF_TK_ROWS_INV, st);
   if (wide && !pruned)
