@@ -358,7 +358,23 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_fwd(const C
     }
   }
   if (C.zero_in) {
-    __syncthreads();
+    // the source is cleared after it is read, which needs a barrier; the
+    // same barrier tells whether the workgroup's rows hold anything.  Rows
+    // that hold nothing (a band away from the vortices and the body)
+    // transform to nothing: the workgroup then only stores zeros, and has
+    // nothing to clear.
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < kE / 2; ++k) nz = nz || x[k].x != (T)0 || x[k].y != (T)0;
+    if (!__syncthreads_or(nz)) {
+      constexpr int RW0 = 2 * P::SEQ;
+      V zero;
+      zero.x = (T)0;
+      zero.y = (T)0;
+      for (int idx = tid; idx < (n + 1) * RW0; idx += P::WGT)
+        X[(size_t)(idx / RW0) * n + j0 + idx % RW0] = zero;
+      return;
+    }
     for (int idx = tid; idx < 2 * P::SEQ * n; idx += P::WGT) w[(size_t)j0 * n + idx] = (Tin)0;
   }
   fft_seq<T, N, false, true, false, true, false>(x, lds + q * P::LDS_SEQ, wr, tw, lane);

@@ -634,6 +634,9 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
   __shared__ double yr[kCRows][kMaxCol];            // (S^-1 r_c) at this workgroup's rows
   __shared__ double A[kMaxUnk][kMaxUnk + 1];
   __shared__ double sol[kMaxUnk];                   // s0_1.., Gamma_1..
+  __shared__ double zed[GPF_MAX_PARTS][kMaxERows];  // z_l at the edge rows
+  __shared__ double cjl[GPF_MAX_PARTS * GPF_MAX_PARTS];
+  __shared__ double f0e[kMaxERows];
   const ProbDesc &P = d[blockIdx.y];
   const int ns = P.ns;
   const int row0 = blockIdx.x * kCRows;
@@ -652,6 +655,13 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
       if (sv.pmode[j] == GPF_KUTTA_STEADY) erow_k[e++] = sv.kedge[j];
   }
   __syncthreads();
+  // the body constants the constraint rows read, staged in parallel
+  for (int t = tid; t < np * ne; t += kCB) {
+    const int l = t / ne, e = t % ne;
+    zed[l][e] = P.zpart[(size_t)l * ns + erow_k[e]];
+  }
+  for (int t = tid; t < np * np; t += kCB) cjl[t] = P.cpart[t];
+  for (int e = tid; e < ne; e += kCB) f0e[e] = P.f0[erow_k[e]];
 
   const double gw_dev = P.aux[SC_GAMMA_W];
   const double *R = P.rhs;
@@ -750,8 +760,7 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
       for (int c = 0; c < ncol; ++c)
         circ[j][c] = red[0][j][c] + red[1][j][c] + red[2][j][c] + red[3][j][c];
     const int N = np + m;
-    const double *C = P.cpart;
-    const double *Z = P.zpart;
+    const double *C = cjl;
     bool active[GPF_MAX_EDGES];
     double tgt[GPF_MAX_EDGES];
     for (int i = 0; i < m; ++i) {
@@ -766,8 +775,7 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
         const int mode = sv.pmode[j];
         if (mode == GPF_KUTTA_STEADY) {
           const int e = kr++;
-          const int k = erow_k[e];
-          for (int l = 0; l < np; ++l) A[j][l] = -Z[(size_t)l * ns + k];
+          for (int l = 0; l < np; ++l) A[j][l] = -zed[l][e];
           for (int i = 0; i < m; ++i) A[j][np + i] = ye[e][1 + i];
           A[j][N] = -ye[e][0];
         } else {
@@ -782,10 +790,9 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
         const int r = np + i;
         for (int c = 0; c <= N; ++c) A[r][c] = 0.0;
         if (active[i]) {
-          const int k = sv.edges[i];
-          for (int l = 0; l < np; ++l) A[r][l] = -Z[(size_t)l * ns + k];
+          for (int l = 0; l < np; ++l) A[r][l] = -zed[l][i];
           for (int i2 = 0; i2 < m; ++i2) A[r][np + i2] = ye[i][1 + i2];
-          A[r][N] = P.f0[k] * tgt[i] - ye[i][0];
+          A[r][N] = f0e[i] * tgt[i] - ye[i][0];
         } else {
           A[r][np + i] = 1.0;
         }
@@ -795,10 +802,9 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
       // which edges shed: the sheet with nothing shed against the bounds
       bool any = false;
       for (int i = 0; i < m; ++i) {
-        const int k = sv.edges[i];
         double fk = ye[i][0];
-        for (int l = 0; l < np; ++l) fk -= sol[l] * Z[(size_t)l * ns + k];
-        const double ft = fk / P.f0[k];
+        for (int l = 0; l < np; ++l) fk -= sol[l] * zed[l][i];
+        const double ft = fk / f0e[i];
         if (ft < sv.fmin[i]) { active[i] = true; tgt[i] = sv.fmin[i]; any = true; }
         else if (ft > sv.fmax[i]) { active[i] = true; tgt[i] = sv.fmax[i]; any = true; }
       }
