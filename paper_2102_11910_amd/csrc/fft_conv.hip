@@ -460,6 +460,10 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
 // instead of complex values, and the twiddles are powers of one table value.
 // Both cut the footprint that bounds the FP64 pass's occupancy (measured on
 // the 512^2 batch: 74 -> 64 us).
+// one padding scalar per 16 (8 and 32 per measured slower on the 512^2 batch)
+constexpr int kSplitPad = 4;
+__device__ __forceinline__ int spad(int i) { return i + (i >> kSplitPad); }
+
 template <class T, int N, int S, bool INV, bool ZIN>
 __device__ __forceinline__ void split_stages(typename CT<T>::V (&x)[kE], T *lds,
                                              const typename CT<T>::V *tw, int lane) {
@@ -514,7 +518,7 @@ __device__ __forceinline__ void split_stages(typename CT<T>::V (&x)[kE], T *lds,
         const int j = bf % NS;
         const int base = (bf / NS) * NS * R + j;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[pad(base + r * NS)] = part ? v[b][r].y : v[b][r].x;
+        for (int r = 0; r < R; ++r) lds[spad(base + r * NS)] = part ? v[b][r].y : v[b][r].x;
       }
       __syncthreads();
 #pragma unroll
@@ -522,7 +526,7 @@ __device__ __forceinline__ void split_stages(typename CT<T>::V (&x)[kE], T *lds,
         const int bf2 = lane + b2 * TPS;
 #pragma unroll
         for (int r2 = 0; r2 < R2; ++r2) {
-          const T val = lds[pad(bf2 + r2 * (N / R2))];
+          const T val = lds[spad(bf2 + r2 * (N / R2))];
           if (part)
             x[b2 * R2 + r2].y = val;
           else
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(N / kE) void k_cols_conv_split(const ConvDesc *__re
   using V = typename CT<T>::V;
   constexpr int TPS = N / kE;
   constexpr int n = N / 2;
-  __shared__ T lds[N + N / 16];
+  __shared__ T lds[N + (N >> kSplitPad)];
   const ConvDesc &C = cd[blockIdx.y];
   V *__restrict__ X = static_cast<V *>(C.X);
   const T *__restrict__ spec = static_cast<const T *>(C.spec);
