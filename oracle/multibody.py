@@ -169,3 +169,64 @@ def solve_multi(p: MultiProblem, body: Body, part, table=None) -> MultiResult:
     gb = np.array([np.dot(body.ds * (part == j), f) for j in range(nb)])
     return MultiResult(s=s, u=u, v=v, f=f, ftilde=ftilde, s0=s0, gamma_new=gamma_new,
                        gamma_b=gb, w_total=w_total)
+
+
+@dataclass
+class MultiShedState:
+    """Vortices of a several-body shedding run, per new-vortex edge the index
+    of its last nonzero release (-1 before the first), and per body the
+    circulation it has released (its Gamma_w)."""
+    X: np.ndarray
+    Y: np.ndarray
+    G: np.ndarray
+    last: list
+    gw: list
+
+
+def shed_step_multi(p: MultiProblem, body: Body, part, st: MultiShedState, dt: float, first,
+                    table=None):
+    """One forward Euler shedding step of several bodies (Sec. 2.4.1 with the
+    rows of Sec. 2.7): every edge of a shedding body places a new vortex as
+    for one body (a third of the way to its last release, or at the edge
+    point plus first[i] before the first), the solve gives their strengths,
+    each body's released circulation grows by the strengths of its new
+    vortices, and every vortex moves by x <- x + dt u(x).  Returns the new
+    state, the result and the problem solved."""
+    import dataclasses
+    edges, owners = [], []
+    for j, b in enumerate(p.bodies):
+        if b.mode == "shed":
+            for k in b.edges:
+                edges.append(k)
+                owners.append(j)
+    znew = []
+    for i, k in enumerate(edges):
+        ex, ey = body.xs[k], body.ys[k]
+        l = st.last[i]
+        if l >= 0:
+            znew.append((ex + (st.X[l] - ex) / 3.0, ey + (st.Y[l] - ey) / 3.0))
+        else:
+            znew.append((ex + first[i][0], ey + first[i][1]))
+    nv = len(st.X)
+    m = len(edges)
+    X = np.concatenate([st.X, [z[0] for z in znew]])
+    Y = np.concatenate([st.Y, [z[1] for z in znew]])
+    G = np.concatenate([st.G, np.zeros(m)])
+    specs, i0 = [], 0
+    for j, b in enumerate(p.bodies):
+        nb = dataclasses.replace(b)
+        if b.mode == "shed":
+            ne = len(b.edges)
+            nb.znew = tuple(znew[i0:i0 + ne])
+            nb.gamma_w = st.gw[j]
+            i0 += ne
+        specs.append(nb)
+    q = MultiProblem(p.grid, X, Y, G, specs, p.u_inf, p.v_inf)
+    res = solve_multi(q, body, part, table)
+    G1 = G.copy()
+    G1[nv:] = res.gamma_new
+    gw = list(st.gw)
+    for g, j in zip(res.gamma_new, owners):
+        gw[j] += g
+    last = [nv + i if res.gamma_new[i] != 0.0 else st.last[i] for i in range(m)]
+    return MultiShedState(X + dt * res.u, Y + dt * res.v, G1, last, gw), res, q

@@ -171,3 +171,36 @@ def test_mirror_images_carry_opposite_sheets():
     assert np.max(np.abs(res.u[:3] + res.u[3:])) <= 1e-10 * np.max(np.abs(res.u))
     assert np.max(np.abs(res.v[:3] - res.v[3:])) <= 1e-10 * np.max(np.abs(res.v))
     assert abs(res.s0[0] + res.s0[1]) <= 1e-10 * max(1.0, abs(res.s0[0]))
+
+
+def test_two_plates_shedding_keep_kelvin_per_body():
+    """Two plates (Fig. 16) shedding at all four edges for a few steps: each
+    plate's bound circulation cancels the circulation it has released, the
+    edges keep their Kutta condition, and one step with a single body
+    equals the one-body shedding step."""
+    from oracle.multibody import MultiShedState, shed_step_multi
+    from oracle.solve import ShedState, shed_step
+    from tests.oracle_adapter import multi_of
+    mc = wl.two_plates_case(n=96, nv=0)
+    p, body, part = multi_of(mc)
+    first = [(z[0] - body.xs[k], z[1] - body.ys[k]) for z, k in zip(mc.znew, mc.edges)]
+    st = MultiShedState(np.zeros(0), np.zeros(0), np.zeros(0), [-1] * 4, [0.0, 0.0])
+    for _ in range(3):
+        st, res, q = shed_step_multi(p, body, part, st, 0.01, first)
+        for j in range(2):
+            assert abs(res.gamma_b[j] + st.gw[j]) <= 1e-12
+        for k in mc.edges:
+            assert abs(res.ftilde[k]) <= 1e-12
+    # one body: the same as the one-body step
+    case = wl.random_case(26, 64, 0.04, 20, surface="plate", mode="shed")
+    case.ub = case.vb = case.omega = 0.0
+    pp, bb = problem_of(case), body_of(case)
+    first1 = [(z[0] - bb.xs[k], z[1] - bb.ys[k]) for z, k in zip(case.znew, case.edges)]
+    s1, r1, _ = shed_step(pp, bb, ShedState(pp.X.copy(), pp.Y.copy(), pp.G.copy(), [-1, -1]), 0.01,
+                          first1)
+    spec = BodySpec("shed", edges=tuple(case.edges), gamma_w=float(np.sum(pp.G)))
+    mp = MultiProblem(pp.grid, pp.X, pp.Y, pp.G, [spec], pp.u_inf, pp.v_inf)
+    s2, r2, _ = shed_step_multi(mp, bb, np.zeros(bb.xs.size, int),
+                                MultiShedState(pp.X.copy(), pp.Y.copy(), pp.G.copy(), [-1, -1],
+                                               [float(np.sum(pp.G))]), 0.01, first1)
+    assert np.max(np.abs(s1.X - s2.X)) <= 1e-12 and np.max(np.abs(s1.G - s2.G)) <= 1e-12
