@@ -74,7 +74,7 @@ KERNEL_SOURCES = {
     "cols": ("fft_conv.hip", ("k_cols_conv<float",)),
     "rows_inv": ("fft_conv.hip", ("k_rows_inv<float",)),
     "rows_fwd64": ("fft_conv.hip", ("k_rows_fwd<double, double",)),
-    "cols64": ("fft_conv.hip", ("k_cols_conv<double",)),
+    "cols64": ("fft_conv.hip", ("k_cols_conv<double", "k_cols_conv_split<double")),
     "rows_inv64": ("fft_conv.hip", ("k_rows_inv<double",)),
     "surface": ("schur.hip", ("k_surface_rhs", "k_schur_apply")),
     "velocity": ("transfer.hip", ("k_vortex_velocity",)),
