@@ -428,7 +428,14 @@ void gpf_rk2_destroy(gpf_rk2 *rk);
  *   3. stores Gamma_j and advances every vortex: x <- x + dt u(x).
  * in->mode must be GPF_KUTTA_SHED with in->m equal to the body's edge
  * count; in->h_xnew/h_ynew and in->gamma_w are ignored (Gamma_w is the sum
- * of the strengths).  The body stays in place: ub, vb, omega must be zero
+ * of the strengths).  Several bodies (Sec. 2.7): in->mode GPF_PARTS on a
+ * body split by gpf_body_set_parts, with in->m equal to the edge count of
+ * the parts in GPF_KUTTA_SHED mode; every such edge sheds (body edge order,
+ * which h_first follows too), parts[j].gamma_w is the circulation part j
+ * has released before the first step, and each step adds the strengths of
+ * its edges' new vortices to it (kept on the device), so that each shedding
+ * part keeps its bound circulation equal to minus what it has released.
+ * The body stays in place: ub, vb, omega (and every part's) must be zero
  * (GPF_E_UNSUPPORTED otherwise; a translating body is the same flow as a
  * body at rest in the opposite uniform flow).  d_x, d_y, d_g are device arrays of `capacity`
  * doubles owned by the caller: the first in->nv hold the initial vortices

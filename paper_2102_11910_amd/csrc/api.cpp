@@ -326,6 +326,7 @@ struct ProblemRef {
   const gpf_outputs *out;
   gpf_workspace *ws;
   int znew_from = -1;   // >= 0: the new vortices are vortices znew_from.. of in
+  const double *pgw_dev = nullptr;   // GPF_PARTS: per-part Gamma_w on the device
 };
 
 GroupCfg config_of(const ProblemRef &r) {
@@ -456,6 +457,7 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
     pd.gpart = b->gpart.as<double>();
     pd.zpart = b->zpart.as<double>();
     pd.cpart = b->cpart.as<double>();
+    pd.pgw_dev = r.pgw_dev;
   }
   pd.ns = b->ns;
   pd.xs = b->xs.as<double>();
@@ -1575,11 +1577,12 @@ gpf_status shed_enqueue(gpf_shed *sh, const ShedGeom &geom, hipStream_t s) {
   sh->in.nv = nv;
   gpf_outputs o = sh->out;   // the impulse, if asked for, goes to this step's row
   if (o.d_impulse) o.d_impulse += 3 * (size_t)sh->steps;
-  ProblemRef r{plan, sh->body, &sh->in, &o, &plan->ws, sh->nv};
+  double *gw = sh->in.mode == GPF_PARTS ? sh->gw.as<double>() : nullptr;
+  ProblemRef r{plan, sh->body, &sh->in, &o, &plan->ws, sh->nv, gw};
   const GroupCfg cfg = config_of(r);
   std::vector<ProblemRef> one{r};
   GPF_TRY(run_group(cfg, one, plan->ring, plan->ctx->xcds, s));
-  GPF_HIP(launch_shed_advance(sh->m, nv, sh->out.d_scalars, last, x, y, g, sh->out.d_u,
+  GPF_HIP(launch_shed_advance(geom, nv, sh->out.d_scalars, last, gw, x, y, g, sh->out.d_u,
                               sh->out.d_v, sh->dt, s));
   sh->nv = nv;
   ++sh->steps;
@@ -1598,13 +1601,37 @@ gpf_status gpf_shed_create(gpf_plan *plan, const gpf_body *body, const gpf_input
   *psh = nullptr;
   if (!out->d_u || !out->d_v || !out->d_scalars)
     return fail(GPF_E_INVALID, "gpf_shed_create: d_u, d_v and d_scalars are required");
-  if (in->mode != GPF_KUTTA_SHED)
-    return fail(GPF_E_INVALID, "gpf_shed_create: needs the shedding mode");
+  const bool parts = in->mode == GPF_PARTS;
+  if (in->mode != GPF_KUTTA_SHED && !parts)
+    return fail(GPF_E_INVALID, "gpf_shed_create: needs the shedding mode or GPF_PARTS");
   if (in->ub != 0.0 || in->vb != 0.0 || in->omega != 0.0)
     return fail(GPF_E_UNSUPPORTED,
                 "gpf_shed_create: the body stays in place; give a translation as the uniform flow");
-  const int m = body->nedge;
-  if (m < 1 || in->m != m) return fail(GPF_E_INVALID, "gpf_shed_create: one new vortex per body edge");
+  // the shedding edges, in body edge order, and the part of each
+  int m = 0;
+  int edge_idx[GPF_MAX_EDGES], epart[GPF_MAX_EDGES] = {};
+  if (parts) {
+    if (body->nparts < 2 || in->nparts != body->nparts)
+      return fail(GPF_E_INVALID, "gpf_shed_create: GPF_PARTS needs a body split into in->nparts parts");
+    for (int j = 0; j < in->nparts; ++j) {
+      const gpf_part &q = in->parts[j];
+      if (q.ub != 0.0 || q.vb != 0.0 || q.omega != 0.0)
+        return fail(GPF_E_UNSUPPORTED, "gpf_shed_create: every part stays in place");
+    }
+    for (int e = 0; e < body->nedge; ++e) {
+      const int j = body->edge_part[e];
+      if (j >= 0 && j < in->nparts && in->parts[j].mode == GPF_KUTTA_SHED) {
+        edge_idx[m] = body->edges[e];
+        epart[m] = j;
+        ++m;
+      }
+    }
+  } else {
+    m = body->nedge;
+    for (int e = 0; e < m; ++e) edge_idx[e] = body->edges[e];
+  }
+  if (m < 1 || in->m != m)
+    return fail(GPF_E_INVALID, "gpf_shed_create: one new vortex per shedding edge");
   if (capacity < in->nv + m) return fail(GPF_E_INVALID, "gpf_shed_create: capacity below nv + m");
   for (int j = 0; j < 2 * m; ++j)
     if (!is_finite(h_first[j])) return fail(GPF_E_INVALID, "gpf_shed_create: non-finite h_first");
@@ -1618,7 +1645,8 @@ gpf_status gpf_shed_create(gpf_plan *plan, const gpf_body *body, const gpf_input
   sh->dt = dt;
   for (int j = 0; j < 2 * m; ++j) sh->first[j] = h_first[j];
   for (int j = 0; j < m; ++j) {
-    const size_t k = (size_t)body->edges[j];
+    sh->epart[j] = epart[j];
+    const size_t k = (size_t)edge_idx[j];
     GPF_HIP(hipMemcpy(&sh->edge_xy[2 * j], body->xs.as<double>() + k, sizeof(double),
                       hipMemcpyDeviceToHost));
     GPF_HIP(hipMemcpy(&sh->edge_xy[2 * j + 1], body->ys.as<double>() + k, sizeof(double),
@@ -1626,6 +1654,12 @@ gpf_status gpf_shed_create(gpf_plan *plan, const gpf_body *body, const gpf_input
   }
   GPF_TRY(sh->last.alloc(GPF_MAX_EDGES * sizeof(int)));
   GPF_HIP(hipMemset(sh->last.p, 0xff, GPF_MAX_EDGES * sizeof(int)));   // -1: nothing released
+  if (parts) {
+    double gw0[GPF_MAX_PARTS] = {};
+    for (int j = 0; j < in->nparts; ++j) gw0[j] = in->parts[j].gamma_w;
+    GPF_TRY(sh->gw.alloc(GPF_MAX_PARTS * sizeof(double)));
+    GPF_HIP(hipMemcpy(sh->gw.p, gw0, sizeof(gw0), hipMemcpyHostToDevice));
+  }
   sh->x = d_x;
   sh->y = d_y;
   sh->g = d_g;
@@ -1659,6 +1693,7 @@ gpf_status gpf_shed_run(gpf_shed *sh, int nsteps, void *hip_stream) {
     geom.ey[j] = sh->edge_xy[2 * j + 1];
     geom.fx[j] = sh->first[2 * j];
     geom.fy[j] = sh->first[2 * j + 1];
+    geom.epart[j] = sh->epart[j];
   }
   TimerScope scope(sh->plan->timing ? &sh->plan->timer : nullptr);
   for (int k = 0; k < nsteps; ++k) GPF_TRY(shed_enqueue(sh, geom, s));

@@ -202,6 +202,8 @@ struct ProbDesc {
   // (ns each, part-major) and the circulations C_jl of S^-1 1_l over part j
   const int *part;
   const double *gpart, *zpart, *cpart;
+  const double *pgw_dev;        // GPF_PARTS: per-part released circulation on
+                                // the device (replaces sv.pgw), or null
   int psi_total;                // psi holds s + s_inf: velocities add no U_inf
   SolveScalars sv;
 };
@@ -274,11 +276,15 @@ struct ShedGeom {
   int m;
   double ex[GPF_MAX_EDGES], ey[GPF_MAX_EDGES];   // edge points
   double fx[GPF_MAX_EDGES], fy[GPF_MAX_EDGES];   // offsets of the first release
+  int epart[GPF_MAX_EDGES];                       // GPF_PARTS: part of each edge
 };
 hipError_t launch_shed_place(const ShedGeom &sg, int nv, const int *last, double *x, double *y,
                              double *g, hipStream_t s);
-hipError_t launch_shed_advance(int m, int nv, const double *sc, int *last, double *x, double *y,
-                               double *g, const double *u, const double *v, double dt,
+// gw (nullable): per-part released circulation, to which each new vortex
+// adds its strength (part sg.epart[j])
+hipError_t launch_shed_advance(const ShedGeom &sg, int nv, const double *sc, int *last, double *gw,
+                               double *x, double *y, double *g, const double *u, const double *v,
+                               double dt,
                                hipStream_t s);
 hipError_t launch_axpy2(int nv, const double *x, const double *y, const double *u,
                         const double *v, double a, double *xo, double *yo, hipStream_t s);
@@ -407,6 +413,10 @@ struct gpf_shed {
   double edge_xy[2 * GPF_MAX_EDGES] = {};   // edge points
   double *x = nullptr, *y = nullptr, *g = nullptr;   // caller's vortex arrays
   gpf::DevBuf last;   // per edge: index of its last nonzero release, or -1
+  // GPF_PARTS: part of each shedding edge, and per part the circulation it
+  // has released (device, GPF_MAX_PARTS doubles)
+  int epart[GPF_MAX_EDGES] = {};
+  gpf::DevBuf gw;
 };
 
 struct gpf_rk2 {

@@ -782,7 +782,8 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
           for (int l = 0; l < np; ++l) A[j][l] = -C[j * np + l];
           for (int i = 0; i < m; ++i)
             A[j][np + i] = circ[j][1 + i] + ((mode == GPF_KUTTA_SHED && sv.epart[i] == j) ? 1.0 : 0.0);
-          A[j][N] = (mode == GPF_CIRCULATION ? sv.pgb[j] : -sv.pgw[j]) - circ[j][0];
+          const double gw = P.pgw_dev ? P.pgw_dev[j] : sv.pgw[j];
+          A[j][N] = (mode == GPF_CIRCULATION ? sv.pgb[j] : -gw) - circ[j][0];
         }
       }
       // one row per new vortex: held at its target, or shedding nothing

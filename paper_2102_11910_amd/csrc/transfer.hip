@@ -413,16 +413,22 @@ __global__ void k_shed_place(ShedGeom sg, int nv, const int *__restrict__ last, 
 
 // Shedding step, after the solve: the new vortices (the last m of nv) take
 // their strengths from the scalar block; an edge that shed a nonzero
-// strength records its new vortex as its last release; every vortex moves
-// by forward Euler.
-__global__ void k_shed_advance(int m, int nv, const double *__restrict__ sc, int *last,
-                               double *x, double *y, double *g, const double *__restrict__ u,
-                               const double *__restrict__ v, double dt) {
+// strength records its new vortex as its last release; with several parts
+// each part's released circulation grows by its edges' strengths (one lane,
+// in edge order); every vortex moves by forward Euler.
+__global__ void k_shed_advance(ShedGeom sg, int nv, const double *__restrict__ sc, int *last,
+                               double *gw, double *x, double *y, double *g,
+                               const double *__restrict__ u, const double *__restrict__ v,
+                               double dt) {
+  const int m = sg.m;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < m) {
     const double gj = sc[SC_GAMMA_NEW + q];
     g[nv - m + q] = gj;
     if (gj != 0.0) last[q] = nv - m + q;
+  }
+  if (gw && q == 0) {
+    for (int j = 0; j < m; ++j) gw[sg.epart[j]] += sc[SC_GAMMA_NEW + j];
   }
   if (q < nv) {
     x[q] += dt * u[q];
@@ -438,11 +444,11 @@ hipError_t launch_shed_place(const ShedGeom &sg, int nv, const int *last, double
   return hipGetLastError();
 }
 
-hipError_t launch_shed_advance(int m, int nv, const double *sc, int *last, double *x, double *y,
-                               double *g, const double *u, const double *v, double dt,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_shed_advance, dim3((nv + 255) / 256), dim3(256), 0, s, m, nv, sc, last, x,
-                     y, g, u, v, dt);
+hipError_t launch_shed_advance(const ShedGeom &sg, int nv, const double *sc, int *last, double *gw,
+                               double *x, double *y, double *g, const double *u, const double *v,
+                               double dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_shed_advance, dim3((nv + 255) / 256), dim3(256), 0, s, sg, nv, sc, last, gw,
+                     x, y, g, u, v, dt);
   return hipGetLastError();
 }
 

@@ -571,7 +571,9 @@ class Shed:
     tensors of `capacity` entries whose first inp.nv hold the initial
     vortices; run() appends one vortex per edge each step and moves them all
     in place.  out: gpf_outputs with u, v of `capacity` entries, scalars and
-    status.  first: ((dx, dy), ...) offset of each edge's first release."""
+    status.  first: ((dx, dy), ...) offset of each shedding edge's first
+    release.  inp may be a GPF_PARTS input (several bodies): then every edge
+    of a shedding part sheds, in body edge order."""
 
     def __init__(self, plan: Plan, body: Body, inp: gpf_inputs, out: gpf_outputs, X, Y, G,
                  dt: float, first):

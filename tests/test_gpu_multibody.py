@@ -200,3 +200,120 @@ def test_parts_arguments_checked(ctx):
     with pytest.raises(gpf.GpfError) as e:
         body.set_parts(np.r_[np.zeros(len(mc.xs) - 1, int), 5])
     assert e.value.status in (gpf.GPF_E_INVALID, gpf.GPF_E_UNSUPPORTED)
+
+
+def _at_rest(mc, keep=0.7):
+    """The case with every part at rest and the vortices kept in the middle
+    of the window, so that a few shedding steps stay inside it."""
+    for q in mc.parts:
+        q["ub"] = q["vb"] = q["omega"] = 0.0
+    half = (mc.n - 1) * mc.dx / 2.0
+    sel = (np.abs(mc.X) <= keep * half) & (np.abs(mc.Y) <= keep * half)
+    mc.X, mc.Y, mc.G = mc.X[sel], mc.Y[sel], mc.G[sel]
+    return mc
+
+
+class MultiShedRun:
+    """A GPU several-body shedding run (gpf_shed_* on a GPF_PARTS input)."""
+
+    def __init__(self, ctx, mc, flags, dt, capacity):
+        self.mc, self.dt = mc, dt
+        self.plan = gpf.Plan(ctx, mc.n, mc.dx, flags=flags)
+        self.body = gpf.Body(self.plan, mc.xs, mc.ys, mc.ds, mc.edges)
+        self.body.set_parts(mc.part)
+        part = mc.part
+        self.shed_edges = [k for k in mc.edges if mc.parts[part[k]]["mode"] == "shed"]
+        self.epart = [int(part[k]) for k in self.shed_edges]
+        xs, ys = mc.xs, mc.ys
+        self.first = [(z[0] - xs[k], z[1] - ys[k]) for z, k in zip(mc.znew, self.shed_edges)]
+        nv = mc.nv
+        t = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float64).to(DEV)
+        pad = lambda a: np.r_[np.asarray(a, np.float64), np.zeros(capacity - nv)]
+        self.X, self.Y, self.G = t(pad(mc.X)), t(pad(mc.Y)), t(pad(mc.G))
+        ns = len(xs)
+        self.u = torch.zeros(capacity, dtype=torch.float64, device=DEV)
+        self.v = torch.zeros(capacity, dtype=torch.float64, device=DEV)
+        self.psi = torch.empty((mc.n, mc.n), dtype=self.plan.field_dtype, device=DEV)
+        self.f = torch.zeros(ns, dtype=torch.float64, device=DEV)
+        self.ft = torch.zeros(ns, dtype=torch.float64, device=DEV)
+        self.sc = torch.zeros(gpf.N_SCALARS, dtype=torch.float64, device=DEV)
+        self.status = torch.zeros(1, dtype=torch.int32, device=DEV)
+        self.inp = gpf.make_parts_inputs(self.X, self.Y, self.G, mc.parts, mc.znew, mc.fbounds,
+                                         mc.u_inf, mc.v_inf)
+        self.inp.nv = nv
+        out = gpf.make_outputs(self.psi, self.u, self.v, self.f, self.ft, self.sc, self.status)
+        self.shed = gpf.Shed(self.plan, self.body, self.inp, out, self.X, self.Y, self.G, dt,
+                             self.first)
+        self.oracle = multi_of(mc)
+        self.nv0 = nv
+
+    def state(self):
+        gpf.gpf_sync(self.status)
+        nv = self.shed.nv
+        h = lambda t: t[:nv].cpu().numpy().copy()
+        return h(self.X), h(self.Y), h(self.G)
+
+    def released(self, G):
+        """Per part: its initial Gamma_w plus what its edges have shed."""
+        m = len(self.shed_edges)
+        gw = [q.get("gamma_w", 0.0) for q in self.mc.parts]
+        new = G[self.nv0:].reshape(-1, m) if len(G) > self.nv0 else np.zeros((0, m))
+        for i, j in enumerate(self.epart):
+            gw[j] += float(np.sum(new[:, i]))
+        return gw
+
+
+@pytest.mark.parametrize("which", ["two_plates", "mixed"])
+@pytest.mark.parametrize("flags", [gpf.GPF_FP64, gpf.GPF_POLICY_AUTO])
+def test_several_bodies_shedding_steps(ctx, which, flags):
+    """Shedding of several bodies with forward Euler steps, each step
+    against the oracle's several-body step from the GPU's own state; each
+    shedding part's bound circulation cancels what it has released."""
+    from oracle.multibody import MultiShedState, shed_step_multi
+    if which == "two_plates":
+        mc = _at_rest(wl.two_plates_case(n=128, nv=300))
+    else:
+        mc = _at_rest(wl.mixed_bodies_case(n=128, nv=300))
+    say(f"[multi-shed] {mc.name}, {mc.nv} vortices, flags={flags}")
+    fp64 = flags == gpf.GPF_FP64
+    dt, steps = 0.005, 4
+    m = len(mc.znew)
+    run = MultiShedRun(ctx, mc, flags, dt, capacity=mc.nv + m * steps)
+    p, body, part = run.oracle
+    last = [-1] * m
+    tol_x, tol_g = (1e-9, 1e-9) if fp64 else (1e-4, 1e-5)
+    for k in range(steps):
+        X0, Y0, G0 = run.state()
+        gw = run.released(G0)
+        ost, res, _ = shed_step_multi(p, body, part,
+                                      MultiShedState(X0, Y0, G0, list(last), list(gw)), dt,
+                                      run.first)
+        run.shed.run(1)
+        X, Y, G = run.state()
+        nv = len(X)
+        assert nv == len(ost.X)
+        u, v = run.u[:nv].cpu().numpy(), run.v[:nv].cpu().numpy()
+        su = np.max(np.abs(np.r_[res.u, res.v]))
+        ex = np.max(np.abs(np.r_[X - ost.X, Y - ost.Y])) / (dt * su)
+        eu = np.max(np.abs(np.r_[u - res.u, v - res.v])) / su
+        eg = np.max(np.abs(G - ost.G)) / np.max(np.abs(ost.G))
+        sc = run.sc.cpu().numpy()
+        gb = sc[20:20 + len(mc.parts)]
+        gw1 = run.released(G)
+        kel = max(abs(gb[j] + gw1[j]) for j, q in enumerate(mc.parts) if q["mode"] == "shed")
+        say(f"   step {k}: x {ex:.2e} (of dt |u|), u {eu:.2e}, G {eg:.2e}, Kelvin {kel:.1e}")
+        assert ex <= tol_x and eu <= tol_x and eg <= tol_g
+        assert kel <= (1e-10 if fp64 else 1e-6)
+        assert np.array_equal(G[nv - m:] == 0.0, res.gamma_new == 0.0)
+        last = ost.last
+
+
+def test_several_bodies_shedding_rejects_moving_parts(ctx):
+    mc = wl.mixed_bodies_case(n=64, nv=50)
+    mc.parts[0]["ub"] = 0.0
+    mc.parts[0]["vb"] = 0.0
+    mc.parts[0]["omega"] = 0.2        # a rotating cylinder: not supported
+    mc.parts[2]["vb"] = 0.0
+    with pytest.raises(gpf.GpfError) as e:
+        MultiShedRun(ctx, mc, gpf.GPF_FP64, 0.01, capacity=mc.nv + 8)
+    assert e.value.status == gpf.GPF_E_UNSUPPORTED
