@@ -243,7 +243,7 @@ constexpr size_t kProblemDescBytes = sizeof(ProbDesc) + 2 * sizeof(ConvDesc);
 
 using namespace gpf;
 
-gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns) {
+gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns, int band) {
   const size_t cells = (size_t)nn * nn, half = (size_t)(nn + 1) * nn;
   // source fields start zeroed; the last reader of a source leaves it zero
   auto zeroed = [&](DevBuf &b, size_t bytes) -> gpf_status {
@@ -263,6 +263,7 @@ gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns) {
   }
   GPF_TRY(zeroed(aux, AUX_BYTES));
   GPF_TRY(part.alloc(sizeof(double) * 4 * (size_t)kPartStride));
+  if (band > 0) GPF_TRY(xb.alloc((size_t)(nn + 1) * band * 16));   // complex FP64 at most
   if (nns > 0) {
     const size_t cols = 1 + GPF_MAX_EDGES;
     GPF_TRY(rhs.alloc(cols * nns * sizeof(double)));
@@ -343,6 +344,9 @@ bool same_cfg(const GroupCfg &a, const GroupCfg &b) {
   return a.n == b.n && a.body == b.body && a.fp64_plan == b.fp64_plan &&
          a.conv1_fp64 == b.conv1_fp64 && a.parts == b.parts;
 }
+
+// rows of a body's band: the 16-row groups spanning its surface stencils
+int body_band(const gpf_body *b) { return (b->row_hi | 15) - (b->row_lo & ~15) + 1; }
 
 // fill the descriptors of one problem
 void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &c1, ConvDesc &c2) {
@@ -485,6 +489,13 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   c1.zero_in = 0;
   c1.row_lo = b->row_lo;   // only the surface stencils read this field
   c1.row_hi = b->row_hi;
+  {
+    const int band = body_band(b);
+    if (ws->xb.bytes >= (size_t)(p->grid.n + 1) * band * (w64 ? 16 : 8)) {
+      c1.Xb = ws->xb.p;
+      c1.band_pitch = band;
+    }
+  }
   pd.s1 = c1.out;
   // final convolution of all vorticity
   c2.in = pd.w;
@@ -501,16 +512,16 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
 template <class TW, class T1, class T2>
 gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const ConvDesc *c1,
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, bool impulse,
-                        int xcds, hipStream_t s) {
+                        int band, int xcds, hipStream_t s) {
   GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
-  GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body, s)));
+  GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body ? band : 0, s)));
   if (cfg.body) {
     GPF_HIP(launch_surface_rhs<T1>(pd, nb, ns_max, m_max, s));
     if (cfg.parts)
       GPF_HIP(launch_schur_apply_parts<TW>(pd, nb, ns_max, s));
     else
-      GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, s));
-    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, false, s)));
+      GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, m_max, s));
+    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s)));
   }
   GPF_HIP(launch_vortex_velocity<T2>(pd, nb, nv_max, s));
   if (impulse) GPF_HIP(launch_impulse(pd, nb, s));
@@ -526,12 +537,14 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   ConvDesc *c1 = reinterpret_cast<ConvDesc *>(blk.data() + nb * sizeof(ProbDesc));
   ConvDesc *c2 = c1 + nb;
   int nv_max = 0, ns_max = 0, m_max = 0;
+  int band = 0;   // rows of the first convolution's last pass (16-row groups)
   bool impulse = false;
   for (int i = 0; i < nb; ++i) {
     describe(probs[i], cfg, pd[i], c1[i], c2[i]);
     nv_max = std::max(nv_max, pd[i].nv);
     ns_max = std::max(ns_max, pd[i].ns);
     m_max = std::max(m_max, pd[i].sv.m);
+    band = std::max(band, (c1[i].row_hi | 15) - (c1[i].row_lo & ~15) + 1);
     impulse = impulse || pd[i].imp_out != nullptr;
   }
   void *dev = nullptr;
@@ -542,12 +555,12 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   const ConvDesc *dc2 = dc1 + nb;
   if (cfg.fp64_plan)
     return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   xcds, s);
+                                                   band, xcds, s);
   if (cfg.conv1_fp64)
     return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   xcds, s);
+                                                   band, xcds, s);
   return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   xcds, s);
+                                                   band, xcds, s);
 }
 
 gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
@@ -749,7 +762,7 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
     b->xc = sx / L;
     b->yc = sy / L;
   }
-  GPF_TRY(plan->ws.ensure(g.n, !plan->fp64, plan->fp64, ns));
+  GPF_TRY(plan->ws.ensure(g.n, !plan->fp64, plan->fp64, ns, body_band(b.get())));
   GPF_HIP(hipMemcpy(b->xs.p, h_xs, vb, hipMemcpyHostToDevice));
   GPF_HIP(hipMemcpy(b->ys.p, h_ys, vb, hipMemcpyHostToDevice));
   GPF_HIP(hipMemcpy(b->ds.p, h_ds, vb, hipMemcpyHostToDevice));
@@ -1041,7 +1054,7 @@ gpf_status gpf_pressure(gpf_plan *plan, const gpf_body *body, const gpf_inputs *
   cd.row_hi = n - 1;
   void *dev = nullptr;
   GPF_TRY(plan->ring.push(&cd, sizeof(cd), s, &dev));
-  GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, plan->ctx->xcds, false, s)));
+  GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, plan->ctx->xcds, 0, s)));
   if (plan->fp64)
     GPF_HIP(launch_pres_finish<double>(D, s));
   else
@@ -1234,9 +1247,9 @@ gpf_status gpf_convolve(gpf_plan *plan, const void *d_w, void *d_s, double gamma
   const int n = plan->grid.n;
   const int x = plan->ctx->xcds;
   if (plan->fp64)
-    GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, x, false, s)));
+    GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, x, 0, s)));
   else
-    GPF_HIP((launch_convolve<float, float>(n, static_cast<ConvDesc *>(dev), 1, x, false, s)));
+    GPF_HIP((launch_convolve<float, float>(n, static_cast<ConvDesc *>(dev), 1, x, 0, s)));
   return GPF_OK;
 }
 
@@ -1318,7 +1331,7 @@ gpf_status gpf_solve(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
   ProblemRef r{plan, in->mode == GPF_NOBODY ? nullptr : body, in, out, ws};
   const GroupCfg cfg = config_of(r);
   GPF_TRY(ws->ensure(cfg.n, !cfg.fp64_plan, cfg.fp64_plan || cfg.conv1_fp64,
-                     r.body ? r.body->ns : 0));
+                     r.body ? r.body->ns : 0, r.body ? body_band(r.body) : 0));
   GPF_TRY(ws->ensure_vortices(in->nv));
   TimerScope scope(plan->timing && ws == &plan->ws ? &plan->timer : nullptr);
   std::vector<ProblemRef> one{r};
@@ -1378,7 +1391,8 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
                  batch->ws[i]};
     const GroupCfg cfg = config_of(r);
     const bool w64 = cfg.fp64_plan || cfg.conv1_fp64;
-    GPF_TRY(r.ws->ensure(cfg.n, !cfg.fp64_plan, w64, r.body ? r.body->ns : 0));
+    GPF_TRY(r.ws->ensure(cfg.n, !cfg.fp64_plan, w64, r.body ? r.body->ns : 0,
+                         r.body ? body_band(r.body) : 0));
     GPF_TRY(r.ws->ensure_vortices(inputs[i].nv));
     refs.push_back(r);
   }
@@ -1674,7 +1688,8 @@ gpf_status gpf_shed_create(gpf_plan *plan, const gpf_body *body, const gpf_input
   GPF_TRY(validate(plan, body, &sh->in, &sh->out));
   ProblemRef r{plan, body, &sh->in, &sh->out, &plan->ws, in->nv};
   const GroupCfg cfg = config_of(r);
-  GPF_TRY(plan->ws.ensure(cfg.n, !cfg.fp64_plan, cfg.fp64_plan || cfg.conv1_fp64, body->ns));
+  GPF_TRY(plan->ws.ensure(cfg.n, !cfg.fp64_plan, cfg.fp64_plan || cfg.conv1_fp64, body->ns,
+                          body_band(body)));
   GPF_TRY(plan->ws.ensure_vortices(capacity));
   *psh = sh.release();
   return GPF_OK;

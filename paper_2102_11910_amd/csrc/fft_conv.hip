@@ -318,13 +318,18 @@ __device__ __forceinline__ void fft_seq(typename CT<T>::V (&x)[kE], typename CT<
   fft_stages<T, N, 0, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, wr, tw, lane);
 }
 
-// logical block index: consecutive logical blocks on one XCD (blocks are
-// dispatched round-robin over the XCDs), so that blocks touching the same
-// cache lines of the k-major intermediate share an L2.
+// Row-pass block index.  Workgroups are dispatched round-robin over the
+// XCDs.  A wide workgroup stores whole 128-byte runs of every k-major row,
+// so the plain order keeps the XCDs evenly loaded even where some rows are
+// empty or skipped.  A narrow workgroup shares cache lines with its
+// neighbour, so neighbours are paired on one XCD (the pairs still rotate
+// over the XCDs).
+template <bool WIDE>
 __device__ __forceinline__ int xcd_block(int xcds) {
   const int nb = gridDim.x, b = blockIdx.x;
-  if (xcds <= 1 || nb % xcds) return b;
-  return (b % xcds) * (nb / xcds) + b / xcds;
+  if (WIDE || xcds <= 1 || nb % (2 * xcds)) return b;
+  const int x = b % xcds, k = b / xcds;
+  return 2 * (x + xcds * (k / 2)) + (k & 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,7 +347,7 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_fwd(const C
   V *__restrict__ X = static_cast<V *>(C.X);
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
-  const int j0 = xcd_block(xcds) * 2 * P::SEQ;
+  const int j0 = xcd_block<WIDE>(xcds) * 2 * P::SEQ;
 
   const int q = tid / P::TPS, lane = tid % P::TPS;
   V x[kE];
@@ -446,10 +451,11 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
     // pairs inside 16-row-aligned workgroups, and an unwritten (stale) partner
     // row would add its rounding noise, so whole 16-row groups are kept.
     const int lo = C.row_lo & ~15, hi = C.row_hi | 15;
+    V *dst = C.Xb ? static_cast<V *>(C.Xb) + (size_t)k1 * C.band_pitch - lo : col;
 #pragma unroll
     for (int k = 0; k < kE / 2; ++k) {
       const int j = lane + k * P::TPS;
-      if (j >= lo && j <= hi) col[j] = x[k];
+      if (j >= lo && j <= hi) dst[j] = x[k];
     }
   }
 }
@@ -568,10 +574,11 @@ __global__ __launch_bounds__(N / kE) void k_cols_conv_split(const ConvDesc *__re
   }
   split_stages<T, N, 0, true, false>(x, lds, tw, lane);
   const int lo = C.row_lo & ~15, hi = C.row_hi | 15;
+  V *dst = C.Xb ? static_cast<V *>(C.Xb) + (size_t)k1 * C.band_pitch - lo : col;
 #pragma unroll
   for (int k = 0; k < kE / 2; ++k) {
     const int j = lane + k * TPS;
-    if (j >= lo && j <= hi) col[j] = x[k];
+    if (j >= lo && j <= hi) dst[j] = x[k];
   }
 }
 
@@ -580,19 +587,24 @@ __global__ __launch_bounds__(N / kE) void k_cols_conv_split(const ConvDesc *__re
 // ---------------------------------------------------------------------------
 template <class T, int N, bool WIDE>
 __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const ConvDesc *__restrict__ cd,
-                                                                 int xcds) {
+                                                                 int xcds, int band) {
   using V = typename CT<T>::V;
   using V2 = typename CT<T>::V2;
   using P = RowPlan<T, N, WIDE>;
   constexpr int n = N / 2;
   __shared__ V lds[P::SEQ * P::LDS_SEQ];
   const ConvDesc &C = cd[blockIdx.y];
-  const V *__restrict__ X = static_cast<const V *>(C.X);
   T *__restrict__ s = static_cast<T *>(C.out);
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
-  const int j0 = xcd_block(xcds) * 2 * P::SEQ;
+  // band: the grid covers the rows from the 16-row group of row_lo on, read
+  // from the compact band when the column pass stored one
+  const int lo = band ? C.row_lo & ~15 : 0;
+  const int j0 = lo + xcd_block<WIDE>(xcds) * 2 * P::SEQ;
   if (j0 + 2 * P::SEQ <= C.row_lo || j0 > C.row_hi) return;  // rows nobody reads
+  const bool compact = band && C.Xb;
+  const V *__restrict__ X = compact ? static_cast<const V *>(C.Xb) - lo : static_cast<const V *>(C.X);
+  const int pitch = compact ? C.band_pitch : n;
   V wr[tw_regs<N>()];
   if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, tid % P::TPS);
 
@@ -604,7 +616,7 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const C
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
     const int idx = min(tid + it * P::WGT, ITEMS - 1);
-    abv[it] = *reinterpret_cast<const V2 *>(X + (size_t)(idx / P::SEQ) * n + j0 + 2 * (idx % P::SEQ));
+    abv[it] = *reinterpret_cast<const V2 *>(X + (size_t)(idx / P::SEQ) * pitch + j0 + 2 * (idx % P::SEQ));
   }
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
@@ -671,15 +683,18 @@ void launch_rows_fwd(const ConvDesc *d, int nb, int xcds, hipStream_t st) {
   hipLaunchKernelGGL((k_rows_fwd<Tin, T, N, WIDE>), dim3(N / 2 / (2 * RP::SEQ), nb), dim3(RP::WGT),
                      0, st, d, xcds);
 }
+// band > 0: only that many rows per problem, from its row_lo's 16-row group
 template <class T, int N, bool WIDE>
-void launch_rows_inv(const ConvDesc *d, int nb, int xcds, hipStream_t st) {
+void launch_rows_inv(const ConvDesc *d, int nb, int xcds, int band, hipStream_t st) {
   using RP = RowPlan<T, N, WIDE>;
-  hipLaunchKernelGGL((k_rows_inv<T, N, WIDE>), dim3(N / 2 / (2 * RP::SEQ), nb), dim3(RP::WGT), 0,
-                     st, d, xcds);
+  const int rows = band > 0 ? std::min(band, N / 2) : N / 2;
+  hipLaunchKernelGGL((k_rows_inv<T, N, WIDE>), dim3((rows + 2 * RP::SEQ - 1) / (2 * RP::SEQ), nb),
+                     dim3(RP::WGT), 0, st, d, xcds, band > 0 ? 1 : 0);
 }
 
 template <class Tin, class T, int N>
-hipError_t run_conv(const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_t st) {
+hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, hipStream_t st) {
+  const bool pruned = band > 0;
   using P = Plan<N>;
   constexpr int n = N / 2;
   // wide row blocks when they still give two or more workgroups per CU
@@ -700,9 +715,9 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_
   timer_end(st);
   timer_begin(D ? GPF_TK_ROWS_INV64 : GPF_TK_ROWS_INV, st);
   if (wide && !pruned)
-    launch_rows_inv<T, N, true>(d, nb, xcds, st);
+    launch_rows_inv<T, N, true>(d, nb, xcds, 0, st);
   else
-    launch_rows_inv<T, N, false>(d, nb, xcds, st);
+    launch_rows_inv<T, N, false>(d, nb, xcds, band, st);
   timer_end(st);
   return hipGetLastError();
 }
@@ -710,22 +725,22 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_
 }  // namespace
 
 template <class Tin, class T>
-hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_t st) {
+hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t st) {
   switch (n) {
-    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, pruned, st);
-    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, pruned, st);
-    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, pruned, st);
-    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, pruned, st);
-    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, pruned, st);
-    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, pruned, st);
-    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, pruned, st);
-    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, pruned, st);
+    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, band, st);
+    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, band, st);
+    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, band, st);
+    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, band, st);
+    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, band, st);
+    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, band, st);
+    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, band, st);
+    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, band, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_convolve<float, float>(int, const ConvDesc *, int, int, bool, hipStream_t);
-template hipError_t launch_convolve<double, double>(int, const ConvDesc *, int, int, bool, hipStream_t);
-template hipError_t launch_convolve<double, float>(int, const ConvDesc *, int, int, bool, hipStream_t);
+template hipError_t launch_convolve<float, float>(int, const ConvDesc *, int, int, int, hipStream_t);
+template hipError_t launch_convolve<double, double>(int, const ConvDesc *, int, int, int, hipStream_t);
+template hipError_t launch_convolve<double, float>(int, const ConvDesc *, int, int, int, hipStream_t);
 
 }  // namespace gpf

@@ -160,6 +160,11 @@ struct ConvDesc {
   double c;            // gauge shift of the spectrum
   int zero_in;
   int row_lo, row_hi;  // rows of `out` that are needed (inclusive)
+  // optional compact band: the column pass stores rows (row_lo & ~15) ..
+  // (row_hi | 15) as Xb[k1 * band_pitch + j - (row_lo & ~15)] and the band
+  // inverse row pass reads them from there (null: in place in X)
+  void *Xb;
+  int band_pitch;
   int add_inf;         // add s_inf = inf_u (oy + j h) - inf_v (ox + i h) to the output
   double inf_u, inf_v, ox, oy, h;
 };
@@ -222,13 +227,15 @@ int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n 
 // (which must hold zeros, or the values to add to)
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s);
-// pruned: the descriptors restrict the output rows (narrow inverse rows)
+// band > 0: the descriptors restrict the output rows, and no problem needs
+// more than `band` rows from the 16-row group of its row_lo (narrow inverse
+// rows over that band only); 0: every row
 template <class Tin, class T>
-hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, bool pruned, hipStream_t s);
+hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t s);
 template <class T>
 hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
 template <class T>
-hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
+hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
 // the same for bodies of several parts (mode GPF_PARTS)
 template <class T>
 hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
@@ -322,8 +329,10 @@ struct gpf_ctx {
 struct gpf_workspace {
   int n = 0, ns = 0, nv = 0;
   gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs;
+  gpf::DevBuf xb;   // compact band of the first convolution's column pass
   gpf::DevBuf bin_cnt, bin_start, tile_list, rank, sorted;
-  gpf_status ensure(int n, bool need32, bool need64, int ns);
+  // band: rows of a body's band (16-row groups), 0 without a body
+  gpf_status ensure(int n, bool need32, bool need64, int ns, int band = 0);
   gpf_status ensure_vortices(int nv);
 };
 

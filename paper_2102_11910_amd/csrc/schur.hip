@@ -320,15 +320,20 @@ constexpr int kCRows = 4 * kRowsPerWave;       // surface rows per workgroup
 constexpr int kMaxCol = 1 + GPF_MAX_EDGES;
 constexpr int kRStage = 6144;                  // rhs doubles staged in LDS
 
-template <class T>
+constexpr int kPre = 4;   // slices of 64 of each S^-1 row a wave loads up front
+
+// MC: columns of the rhs a launch can have (1 + the largest m)
+template <class T, int MC>
 __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict__ d) {
   __shared__ double rs[kRStage];
-  __shared__ double red[4][kMaxCol];             // per-wave parts of ghat . rhs_c
-  __shared__ double ye[GPF_MAX_EDGES][kMaxCol];  // y_c / f0 at the edge points
-  __shared__ double yr[kCRows][kMaxCol];         // y_c at this workgroup's rows
+  __shared__ double red[4][MC];                  // per-wave parts of ghat . rhs_c
+  __shared__ double ye[GPF_MAX_EDGES][MC];       // y_c / f0 at the edge points
+  __shared__ double yr[kCRows][MC];              // y_c at this workgroup's rows
   __shared__ double scal[3 + GPF_MAX_EDGES];     // c1, s0, Gamma_b, Gamma_j
-  __shared__ double circ[kMaxCol];               // ghat . rhs_c
+  __shared__ double circ[MC];                    // ghat . rhs_c
   __shared__ double A[GPF_MAX_EDGES][GPF_MAX_EDGES + 1];
+  __shared__ double gsrc2;                       // circulation of the final source
+  __shared__ int singular_flag;
   const ProbDesc &P = d[blockIdx.y];
   const int ns = P.ns;
   const int row0 = blockIdx.x * kCRows;
@@ -342,7 +347,19 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
 
   // Loads below are unconditional, with indices clamped into range, so
   // that each wave keeps many of them in flight; sums of clamped terms
-  // are discarded.
+  // are discarded.  The first slices of this wave's rows of S^-1 and of
+  // ghat do not depend on the rhs: they are issued before it is staged.
+  const int r0 = row0 + wave * kRowsPerWave;
+  const int nr = min(kRowsPerWave, ns - r0);
+  const double *arow[kRowsPerWave];
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) arow[r] = P.sinv + (size_t)min(r0 + r, ns - 1) * ns;
+  double apre[kPre][kRowsPerWave];
+#pragma unroll
+  for (int i = 0; i < kPre; ++i)
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) apre[i][r] = arow[r][min(lane + 64 * i, ns - 1)];
+  const double gpre = P.ghat[min(tid, ns - 1)];
   const double gw_dev = P.aux[SC_GAMMA_W];
   const double *R = P.rhs;
   if (ncol * ns <= kRStage) {
@@ -351,22 +368,22 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
     __syncthreads();
     R = rs;
   }
-  size_t coff[kMaxCol];   // column offsets, clamped to the last column
+  size_t coff[MC];   // column offsets, clamped to the last column
 #pragma unroll
-  for (int c = 0; c < kMaxCol; ++c) coff[c] = (size_t)min(c, ncol - 1) * ns;
+  for (int c = 0; c < MC; ++c) coff[c] = (size_t)min(c, ncol - 1) * ns;
   // ghat . rhs_c, all columns in one sweep
   {
-    double acc[kMaxCol];
+    double acc[MC];
 #pragma unroll
-    for (int c = 0; c < kMaxCol; ++c) acc[c] = 0.0;
+    for (int c = 0; c < MC; ++c) acc[c] = tid < ns ? gpre * R[coff[c] + min(tid, ns - 1)] : 0.0;
 #pragma unroll 2
-    for (int q = tid; q < ns; q += kCB) {
+    for (int q = tid + kCB; q < ns; q += kCB) {
       const double g = P.ghat[q];
 #pragma unroll
-      for (int c = 0; c < kMaxCol; ++c) acc[c] += g * R[coff[c] + q];
+      for (int c = 0; c < MC; ++c) acc[c] += g * R[coff[c] + q];
     }
 #pragma unroll
-    for (int c = 0; c < kMaxCol; ++c) {
+    for (int c = 0; c < MC; ++c) {
       if (c < ncol) {
         const double v = wave_sum(acc[c]);
         if (lane == 0) red[wave][c] = v;
@@ -378,17 +395,17 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
     const int k = sv.edges[e];
     const double inv_f0 = 1.0 / P.f0[k];
     const double *a = P.sinv + (size_t)k * ns;
-    double acc[kMaxCol];
+    double acc[MC];
 #pragma unroll
-    for (int c = 0; c < kMaxCol; ++c) acc[c] = 0.0;
+    for (int c = 0; c < MC; ++c) acc[c] = 0.0;
 #pragma unroll 4
     for (int q = lane; q < ns; q += 64) {
       const double aq = a[q];
 #pragma unroll
-      for (int c = 0; c < kMaxCol; ++c) acc[c] += aq * R[coff[c] + q];
+      for (int c = 0; c < MC; ++c) acc[c] += aq * R[coff[c] + q];
     }
 #pragma unroll
-    for (int c = 0; c < kMaxCol; ++c) {
+    for (int c = 0; c < MC; ++c) {
       if (c < ncol) {
         const double v = wave_sum(acc[c]);
         if (lane == 0) ye[e][c] = v * inv_f0;
@@ -397,35 +414,43 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   }
   // this workgroup's rows: kRowsPerWave per wave, interleaved over q
   {
-    const int r0 = row0 + wave * kRowsPerWave;
-    const int nr = min(kRowsPerWave, ns - r0);
-    double acc[kRowsPerWave][kMaxCol];
+    double acc[kRowsPerWave][MC];
 #pragma unroll
     for (int r = 0; r < kRowsPerWave; ++r)
 #pragma unroll
-      for (int c = 0; c < kMaxCol; ++c) acc[r][c] = 0.0;
+      for (int c = 0; c < MC; ++c) acc[r][c] = 0.0;
     if (nr > 0) {
-      const double *arow[kRowsPerWave];
 #pragma unroll
-      for (int r = 0; r < kRowsPerWave; ++r) arow[r] = P.sinv + (size_t)min(r0 + r, ns - 1) * ns;
+      for (int i = 0; i < kPre; ++i) {
+        const int q = lane + 64 * i;
+        if (q < ns) {
+          double rq[MC];
+#pragma unroll
+          for (int c = 0; c < MC; ++c) rq[c] = R[coff[c] + q];
+#pragma unroll
+          for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+            for (int c = 0; c < MC; ++c) acc[r][c] += apre[i][r] * rq[c];
+        }
+      }
 #pragma unroll 2
-      for (int q = lane; q < ns; q += 64) {
-        double aq[kRowsPerWave], rq[kMaxCol];
+      for (int q = lane + 64 * kPre; q < ns; q += 64) {
+        double aq[kRowsPerWave], rq[MC];
 #pragma unroll
         for (int r = 0; r < kRowsPerWave; ++r) aq[r] = arow[r][q];
 #pragma unroll
-        for (int c = 0; c < kMaxCol; ++c) rq[c] = R[coff[c] + q];
+        for (int c = 0; c < MC; ++c) rq[c] = R[coff[c] + q];
 #pragma unroll
         for (int r = 0; r < kRowsPerWave; ++r)
 #pragma unroll
-          for (int c = 0; c < kMaxCol; ++c) acc[r][c] += aq[r] * rq[c];
+          for (int c = 0; c < MC; ++c) acc[r][c] += aq[r] * rq[c];
       }
     }
 #pragma unroll
     for (int r = 0; r < kRowsPerWave; ++r) {
       if (r < nr) {
 #pragma unroll
-        for (int c = 0; c < kMaxCol; ++c) {
+        for (int c = 0; c < MC; ++c) {
           if (c < ncol) {
             const double v = wave_sum(acc[r][c]);
             if (lane == 0) yr[wave * kRowsPerWave + r][c] = v;
@@ -441,6 +466,7 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
     for (int c = 0; c < ncol; ++c) circ[c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
     const double g0 = P.gamma0;
     double c1 = 0.0, s0 = 0.0, gb = 0.0, gsum = 0.0;
+    singular_flag = 0;
     double *gam = scal + 3;
     for (int j = 0; j < GPF_MAX_EDGES; ++j) gam[j] = 0.0;
     if (mode == GPF_CIRCULATION) {
@@ -499,7 +525,7 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
           }
         }
         for (int r = 0; r < na; ++r) gam[act[r]] = singular ? 0.0 : A[r][na] / A[r][r];
-        if (singular && blockIdx.x == 0) atomicOr(P.status, GPF_DEV_SINGULAR);
+        singular_flag = singular ? 1 : 0;
         if (na > 0) {
           // s0: mean over the active edges of x_k - t, x = f~* + sum_j Gamma_j f~_j
           for (int r = 0; r < na; ++r) {
@@ -523,19 +549,7 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
     scal[0] = c1;
     scal[1] = s0;
     scal[2] = gb;
-    if (blockIdx.x == 0) {
-      P.aux[SC_GAMMA_SRC2] = gw_dev + gb + gsum;
-      P.aux[SC_S0] = s0;
-      P.aux[SC_GAMMA_B] = gb;
-      for (int j = 0; j < GPF_MAX_EDGES; ++j) P.aux[SC_GAMMA_NEW + j] = gam[j];
-      if (P.sc_out) {
-        P.sc_out[SC_GAMMA_W] = gw_dev;
-        P.sc_out[SC_GAMMA_SRC2] = gw_dev + gb + gsum;
-        P.sc_out[SC_S0] = s0;
-        P.sc_out[SC_GAMMA_B] = gb;
-        for (int j = 0; j < GPF_MAX_EDGES; ++j) P.sc_out[SC_GAMMA_NEW + j] = gam[j];
-      }
-    }
+    gsrc2 = gw_dev + gb + gsum;
   }
   __syncthreads();
 
@@ -582,6 +596,22 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
       atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
                  (T)(scal[3 + j] * inv_dx2 * m4p(fy + 1.0 - b) * m4p(fx + 1.0 - a)));
     }
+  }
+  // workgroup 0 writes the scalars last, so that no barrier waits on them
+  if (blockIdx.x == 0 && tid == 0) {
+    const double s0 = scal[1], gb = scal[2];
+    P.aux[SC_GAMMA_SRC2] = gsrc2;
+    P.aux[SC_S0] = s0;
+    P.aux[SC_GAMMA_B] = gb;
+    for (int j = 0; j < GPF_MAX_EDGES; ++j) P.aux[SC_GAMMA_NEW + j] = scal[3 + j];
+    if (P.sc_out) {
+      P.sc_out[SC_GAMMA_W] = gw_dev;
+      P.sc_out[SC_GAMMA_SRC2] = gsrc2;
+      P.sc_out[SC_S0] = s0;
+      P.sc_out[SC_GAMMA_B] = gb;
+      for (int j = 0; j < GPF_MAX_EDGES; ++j) P.sc_out[SC_GAMMA_NEW + j] = scal[3 + j];
+    }
+    if (singular_flag) atomicOr(P.status, GPF_DEV_SINGULAR);
   }
 }
 
@@ -947,13 +977,17 @@ template hipError_t launch_surface_rhs<float>(const ProbDesc *, int, int, int, h
 template hipError_t launch_surface_rhs<double>(const ProbDesc *, int, int, int, hipStream_t);
 
 template <class T>
-hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, hipStream_t s) {
-  hipLaunchKernelGGL((k_schur_apply<T>), dim3((ns_max + kCRows - 1) / kCRows, nb), dim3(kCB), 0, s, d);
+hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s) {
+  const dim3 grid((ns_max + kCRows - 1) / kCRows, nb);
+  if (m_max <= 2)
+    hipLaunchKernelGGL((k_schur_apply<T, 3>), grid, dim3(kCB), 0, s, d);
+  else
+    hipLaunchKernelGGL((k_schur_apply<T, kMaxCol>), grid, dim3(kCB), 0, s, d);
   timer_end(s);
   return hipGetLastError();
 }
-template hipError_t launch_schur_apply<float>(const ProbDesc *, int, int, hipStream_t);
-template hipError_t launch_schur_apply<double>(const ProbDesc *, int, int, hipStream_t);
+template hipError_t launch_schur_apply<float>(const ProbDesc *, int, int, int, hipStream_t);
+template hipError_t launch_schur_apply<double>(const ProbDesc *, int, int, int, hipStream_t);
 
 template <class T>
 hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s) {
