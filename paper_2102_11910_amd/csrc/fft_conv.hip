@@ -321,15 +321,13 @@ __device__ __forceinline__ void fft_seq(typename CT<T>::V (&x)[kE], typename CT<
 // Row-pass block index.  Workgroups are dispatched round-robin over the
 // XCDs.  A wide workgroup stores whole 128-byte runs of every k-major row,
 // so the plain order keeps the XCDs evenly loaded even where some rows are
-// empty or skipped.  A narrow workgroup shares cache lines with its
-// neighbour, so neighbours are paired on one XCD (the pairs still rotate
-// over the XCDs).
+// empty or skipped.  Narrow workgroups share cache lines with their
+// neighbours, so consecutive logical blocks go to one XCD and share its L2.
 template <bool WIDE>
 __device__ __forceinline__ int xcd_block(int xcds) {
   const int nb = gridDim.x, b = blockIdx.x;
-  if (WIDE || xcds <= 1 || nb % (2 * xcds)) return b;
-  const int x = b % xcds, k = b / xcds;
-  return 2 * (x + xcds * (k / 2)) + (k & 1);
+  if (WIDE || xcds <= 1 || nb % xcds) return b;
+  return (b % xcds) * (nb / xcds) + b / xcds;
 }
 
 // ---------------------------------------------------------------------------
