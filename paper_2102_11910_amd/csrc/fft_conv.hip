@@ -121,6 +121,8 @@ template <class T, int N, bool WIDE> struct RowPlan {
   }
   static constexpr int SEQ = WIDE ? fit(64 / ELEM) : Plan<N>::SEQ;
   static constexpr int WGT = TPS * SEQ;
+  // a workgroup's run of each k-major row fills whole 128-byte lines
+  static constexpr bool FULL_LINES = 2 * SEQ * ELEM >= 128;
 };
 
 // radix of stage `s` for a length-N transform with 16 values per lane
@@ -319,14 +321,15 @@ __device__ __forceinline__ void fft_seq(typename CT<T>::V (&x)[kE], typename CT<
 }
 
 // Row-pass block index.  Workgroups are dispatched round-robin over the
-// XCDs.  A wide workgroup stores whole 128-byte runs of every k-major row,
-// so the plain order keeps the XCDs evenly loaded even where some rows are
-// empty or skipped.  Narrow workgroups share cache lines with their
-// neighbours, so consecutive logical blocks go to one XCD and share its L2.
-template <bool WIDE>
+// XCDs.  A workgroup whose run of each k-major row fills whole 128-byte
+// lines keeps the plain order, which spreads every band of rows over all
+// XCDs even where some rows are empty or skipped.  Workgroups with shorter
+// runs share lines with their neighbours, so consecutive logical blocks go
+// to one XCD and share its L2.
+template <bool FULL_LINES>
 __device__ __forceinline__ int xcd_block(int xcds) {
   const int nb = gridDim.x, b = blockIdx.x;
-  if (WIDE || xcds <= 1 || nb % xcds) return b;
+  if (FULL_LINES || xcds <= 1 || nb % xcds) return b;
   return (b % xcds) * (nb / xcds) + b / xcds;
 }
 
@@ -345,7 +348,7 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_fwd(const C
   V *__restrict__ X = static_cast<V *>(C.X);
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
-  const int j0 = xcd_block<WIDE>(xcds) * 2 * P::SEQ;
+  const int j0 = xcd_block<P::FULL_LINES>(xcds) * 2 * P::SEQ;
 
   const int q = tid / P::TPS, lane = tid % P::TPS;
   V x[kE];
@@ -598,7 +601,7 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const C
   // band: the grid covers the rows from the 16-row group of row_lo on, read
   // from the compact band when the column pass stored one
   const int lo = band ? C.row_lo & ~15 : 0;
-  const int j0 = lo + xcd_block<WIDE>(xcds) * 2 * P::SEQ;
+  const int j0 = lo + xcd_block<P::FULL_LINES>(xcds) * 2 * P::SEQ;
   if (j0 + 2 * P::SEQ <= C.row_lo || j0 > C.row_hi) return;  // rows nobody reads
   const bool compact = band && C.Xb;
   const V *__restrict__ X = compact ? static_cast<const V *>(C.Xb) - lo : static_cast<const V *>(C.X);
