@@ -397,8 +397,10 @@ void gpf_server_destroy(gpf_server *srv);
  * in->d_gv holds the strengths; in->d_xv, in->d_yv are ignored.  With
  * use_graph = 1 one step is captured once into a HIP graph (two solves and
  * two position updates) and every step replays it; the captured descriptors
- * stay reserved until gpf_rk2_destroy.  The object owns the field, velocity,
- * sheet and status buffers of the last stage (gpf_rk2_fields). */
+ * stay reserved until gpf_rk2_destroy.  The object owns its workspace, so
+ * other calls on the same plan (which may grow the plan's workspace) leave
+ * the captured step valid, and the field, velocity, sheet and status buffers
+ * of the last stage (gpf_rk2_fields). */
 gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
                           double *d_x, double *d_y, double dt, int use_graph,
                           gpf_rk2 **out);

@@ -1453,8 +1453,8 @@ namespace {
 // one step: two solves and two position updates, enqueued on s
 gpf_status rk2_enqueue(gpf_rk2 *rk, hipStream_t s) {
   gpf_plan *plan = rk->plan;
-  ProblemRef r1{plan, rk->body, &rk->in1, &rk->out1, &plan->ws};
-  ProblemRef r2{plan, rk->body, &rk->in2, &rk->out2, &plan->ws};
+  ProblemRef r1{plan, rk->body, &rk->in1, &rk->out1, &rk->ws};
+  ProblemRef r2{plan, rk->body, &rk->in2, &rk->out2, &rk->ws};
   const GroupCfg cfg = config_of(r1);
   std::vector<ProblemRef> one{r1};
   GPF_TRY(run_group(cfg, one, plan->ring, plan->ctx->xcds, s));
@@ -1520,7 +1520,15 @@ gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs
   rk->out2.d_u = rk->u2.as<double>();
   rk->out2.d_v = rk->v2.as<double>();
   GPF_TRY(validate(plan, rk->body, &rk->in1, &rk->out1));
-  GPF_TRY(plan->ws.ensure_vortices(in->nv));
+  {
+    // a workspace of its own: a captured step keeps pointing at it, and
+    // other calls on the plan may grow (reallocate) the plan's workspace
+    ProblemRef r{plan, rk->body, &rk->in1, &rk->out1, &rk->ws};
+    const GroupCfg cfg = config_of(r);
+    GPF_TRY(rk->ws.ensure(cfg.n, !cfg.fp64_plan, cfg.fp64_plan || cfg.conv1_fp64,
+                          rk->body ? rk->body->ns : 0, rk->body ? body_band(rk->body) : 0));
+    GPF_TRY(rk->ws.ensure_vortices(in->nv));
+  }
   if (rk->use_graph) {
     GPF_HIP(hipStreamCreateWithFlags(&rk->cap, hipStreamNonBlocking));
     // capture one step; descriptors pushed while capturing stay reserved

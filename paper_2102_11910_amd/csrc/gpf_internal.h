@@ -438,6 +438,7 @@ struct gpf_rk2 {
   int nv = 0;
   bool use_graph = false;
   gpf::DevBuf xm, ym, u1, v1, u2, v2, psi, f, ft, sc, status;
+  gpf_workspace ws;   // private: a captured step refers to its buffers
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

@@ -99,3 +99,47 @@ def test_rk2_rejects_shedding(ctx):
     with pytest.raises(gpf.GpfError) as e:
         gpf.Rk2(plan, body, inp, X, Y, 1e-3)
     assert e.value.status == gpf.GPF_E_UNSUPPORTED
+
+
+def test_rk2_graph_after_plan_workspace_grows(ctx):
+    """A captured step keeps using the object's own workspace: solves on the
+    same plan that grow the plan's workspace (more vortices, a body with more
+    points) leave graph replays equal to eager steps."""
+    case = wl.random_case(44, 128, 2.0 / 128, 400, surface="ellipse")
+    dt = 0.08 * case.dx
+    plan, body, X1, Y1, G, inp = make(ctx, case, flags=gpf.GPF_FP64)
+    X2, Y2 = X1.clone(), Y1.clone()
+    rk_g = gpf.Rk2(plan, body, inp, X1, Y1, dt, use_graph=True)
+    rk_e = gpf.Rk2(plan, body, inp, X2, Y2, dt, use_graph=False)
+
+    def step_both(k):
+        rk_g.run(k)
+        rk_g.sync()
+        rk_e.run(k)
+        rk_e.sync()
+        torch.cuda.synchronize()
+        return float(torch.max(torch.abs(X1 - X2)).item() + torch.max(torch.abs(Y1 - Y2)).item())
+
+    assert step_both(3) <= 1e-9
+    # grow the plan's workspace: a body with more points and more vortices
+    big = wl.cylinder(0.5, 3 * body.ns, center=(0.0, 0.0))
+    body2 = gpf.Body(plan, big.xs, big.ys, big.ds)
+    rng = np.random.default_rng(7)
+    nv2 = 20 * case.nv
+    r = 0.55 + 0.35 * rng.random(nv2)
+    t = 2.0 * np.pi * rng.random(nv2)
+    Xb = torch.as_tensor(r * np.cos(t), dtype=torch.float64).to(DEV)
+    Yb = torch.as_tensor(r * np.sin(t), dtype=torch.float64).to(DEV)
+    Gb = torch.as_tensor(rng.normal(0.0, 1e-3, nv2), dtype=torch.float64).to(DEV)
+    inp2 = gpf.make_inputs(Xb, Yb, Gb, 1.0, 0.0, mode="circulation", gamma_b=0.0)
+    psi = torch.empty((case.n, case.n), dtype=plan.field_dtype, device=DEV)
+    u = torch.empty(nv2, dtype=torch.float64, device=DEV)
+    v = torch.empty_like(u)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    out2 = gpf.make_outputs(psi, u, v, status=st)
+    say(f"[rk2 workspace] plain solve on the plan: ns {body2.ns} (rk2 body {body.ns}), nv {nv2}")
+    gpf.gpf_solve(plan, body2, inp2, out2)
+    gpf.gpf_sync(st)
+    d = step_both(3)
+    say(f"[rk2 workspace] after the growth: max |dx| graph vs eager = {d:.2e}")
+    assert d <= 1e-9
