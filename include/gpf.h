@@ -492,6 +492,50 @@ gpf_status gpf_vortex_velocity(gpf_plan *plan, const void *d_s, int nv,
                                double *d_v, unsigned int *d_status,
                                void *hip_stream);
 
+/* ---- convolution schedules and the autotuner --------------------------- */
+
+/* How the three passes of the convolution (Sec. 2.1, the zero-padded LGF
+ * convolution) map onto workgroups and XCDs.  Every schedule performs the
+ * same transforms; they differ in speed only, and in the last bits of FP64
+ * column results (the two column kernels form their twiddles differently).
+ *   rows:  row passes; 0 by rule (wide workgroups when a launch gives two or
+ *          more per CU), 1 narrow (2-8 sequences), 2 wide (128-byte runs of
+ *          the k-major intermediate);
+ *   order: row-pass XCD order; 0 by rule (dispatch order where a workgroup's
+ *          runs fill whole 128-byte lines, else consecutive row blocks per
+ *          XCD), 1 dispatch order, 2 consecutive row blocks per XCD;
+ *   cols:  FP64 column pass for n >= 512; 0 or 2 split exchange (real and
+ *          imaginary parts through LDS in turn), 1 complex exchange. */
+typedef struct {
+  int rows, order, cols;
+} gpf_schedule;
+
+/* Schedules live in the context, keyed by grid size n, precision (fp64 =
+ * 1: the FP64 transforms, 0: FP32) and batch-size class of nb (1, 2-7, 8-31,
+ * 32 and more).  Solves, batched solves and the building blocks on that
+ * context use the entry of their group (the first convolution of a body
+ * under the precision policy uses its FP64 entry).  gpf_schedule_set stores
+ * *s (NULL: drop the entry, back to the rules); values outside the ranges
+ * above give GPF_E_INVALID.  gpf_schedule_get writes the entry in force
+ * (zeros where there is none). */
+gpf_status gpf_schedule_set(gpf_ctx *ctx, int n, int fp64, int nb, const gpf_schedule *s);
+gpf_status gpf_schedule_get(gpf_ctx *ctx, int n, int fp64, int nb, gpf_schedule *s);
+
+/* Autotuner: times every schedule (rows 1-2 x order 1-2 x, for FP64 from
+ * n = 512, cols 1-2) on nb convolutions of the plan's grid in the given
+ * precision (synthetic zero sources; the time does not depend on the values),
+ * stores the fastest in the context as by gpf_schedule_set, and returns it
+ * in *chosen and its mean time per batched convolution (microseconds) in
+ * *us (both nullable).  cache_path (nullable) names a text file of earlier
+ * results, one per line "arch n fp64 class rows order cols us": a matching
+ * line (same device architecture, n, precision and class) is used without
+ * timing; a new result is appended.  Blocks until the timing is done;
+ * allocates about 4 nb n^2 sizeof(T) bytes of device memory while it runs
+ * (T: float or double).  nb must be in [1, 1024]; GPF_E_NOMEM beyond
+ * 16 GiB. */
+gpf_status gpf_autotune(gpf_plan *plan, int fp64, int nb, const char *cache_path,
+                        gpf_schedule *chosen, double *us);
+
 /* ---- kernel timing ----------------------------------------------------- */
 
 /* Kernel classes timed by HIP events recorded on the launch stream. */

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -512,16 +513,17 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
 template <class TW, class T1, class T2>
 gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const ConvDesc *c1,
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, bool impulse,
-                        int band, int xcds, hipStream_t s) {
+                        int band, int xcds, const ConvSched &sc1, const ConvSched &sc2,
+                        hipStream_t s) {
   GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
-  GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body ? band : 0, s)));
+  GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body ? band : 0, s, sc1)));
   if (cfg.body) {
     GPF_HIP(launch_surface_rhs<T1>(pd, nb, ns_max, m_max, s));
     if (cfg.parts)
       GPF_HIP(launch_schur_apply_parts<TW>(pd, nb, ns_max, s));
     else
       GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, m_max, s));
-    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s)));
+    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2)));
   }
   GPF_HIP(launch_vortex_velocity<T2>(pd, nb, nv_max, s));
   if (impulse) GPF_HIP(launch_impulse(pd, nb, s));
@@ -553,14 +555,18 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   const ConvDesc *dc1 =
       reinterpret_cast<const ConvDesc *>(static_cast<char *>(dev) + nb * sizeof(ProbDesc));
   const ConvDesc *dc2 = dc1 + nb;
+  gpf_ctx *ctx = probs[0].plan->ctx;
+  const bool d1 = cfg.fp64_plan || cfg.conv1_fp64;
+  const ConvSched sc1 = ctx->sched_for(cfg.n, d1, nb);
+  const ConvSched sc2 = ctx->sched_for(cfg.n, cfg.fp64_plan, nb);
   if (cfg.fp64_plan)
     return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   band, xcds, s);
+                                                   band, xcds, sc1, sc2, s);
   if (cfg.conv1_fp64)
     return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   band, xcds, s);
+                                                   band, xcds, sc1, sc2, s);
   return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   band, xcds, s);
+                                                   band, xcds, sc1, sc2, s);
 }
 
 gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
@@ -665,6 +671,9 @@ gpf_status gpf_ctx_create(int device, gpf_ctx **out) {
   c->device = device;
   c->num_cu = prop.multiProcessorCount;
   c->xcds = xcd_count(device);
+  std::snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
+  for (char *q = c->arch; *q; ++q)   // the target name without its feature suffixes
+    if (*q == ':' || *q == ' ') { *q = 0; break; }
   *out = c;
   return GPF_OK;
 }
@@ -1054,7 +1063,8 @@ gpf_status gpf_pressure(gpf_plan *plan, const gpf_body *body, const gpf_inputs *
   cd.row_hi = n - 1;
   void *dev = nullptr;
   GPF_TRY(plan->ring.push(&cd, sizeof(cd), s, &dev));
-  GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, plan->ctx->xcds, 0, s)));
+  GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, plan->ctx->xcds, 0, s,
+                                            plan->ctx->sched_for(n, true, 1))));
   if (plan->fp64)
     GPF_HIP(launch_pres_finish<double>(D, s));
   else
@@ -1246,10 +1256,11 @@ gpf_status gpf_convolve(gpf_plan *plan, const void *d_w, void *d_s, double gamma
   GPF_TRY(plan->ring.push(&cd, sizeof(cd), s, &dev));
   const int n = plan->grid.n;
   const int x = plan->ctx->xcds;
+  const ConvSched sc = plan->ctx->sched_for(n, plan->fp64, 1);
   if (plan->fp64)
-    GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, x, 0, s)));
+    GPF_HIP((launch_convolve<double, double>(n, static_cast<ConvDesc *>(dev), 1, x, 0, s, sc)));
   else
-    GPF_HIP((launch_convolve<float, float>(n, static_cast<ConvDesc *>(dev), 1, x, 0, s)));
+    GPF_HIP((launch_convolve<float, float>(n, static_cast<ConvDesc *>(dev), 1, x, 0, s, sc)));
   return GPF_OK;
 }
 
@@ -1759,3 +1770,192 @@ gpf_status gpf_sync(void *hip_stream, unsigned int *d_status) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// convolution schedules and the autotuner
+// ---------------------------------------------------------------------------
+
+int sched_class(int nb) { return nb <= 1 ? 0 : (nb < 8 ? 1 : (nb < 32 ? 2 : 3)); }
+
+namespace {
+long long sched_key(int n, bool fp64, int cls) {
+  return ((long long)n << 8) | ((fp64 ? 1 : 0) << 4) | cls;
+}
+bool sched_valid(const gpf_schedule &s) {
+  return s.rows >= 0 && s.rows <= 2 && s.order >= 0 && s.order <= 2 && s.cols >= 0 && s.cols <= 2;
+}
+}  // namespace
+
+gpf::ConvSched gpf_ctx::sched_for(int n, bool fp64, int nb) {
+  std::lock_guard<std::mutex> lk(sched_mu);
+  auto it = sched.find(sched_key(n, fp64, sched_class(nb)));
+  return it == sched.end() ? gpf::ConvSched{} : it->second;
+}
+
+gpf_status gpf_schedule_set(gpf_ctx *ctx, int n, int fp64, int nb, const gpf_schedule *s) {
+  if (!ctx || nb < 1) return fail(GPF_E_INVALID, "gpf_schedule_set: bad arguments");
+  if (s && !sched_valid(*s)) return fail(GPF_E_INVALID, "gpf_schedule_set: value out of range");
+  std::lock_guard<std::mutex> lk(ctx->sched_mu);
+  const long long key = sched_key(n, fp64 != 0, sched_class(nb));
+  if (s) {
+    gpf::ConvSched c;
+    c.rows = s->rows;
+    c.order = s->order;
+    c.cols = s->cols;
+    ctx->sched[key] = c;
+  } else {
+    ctx->sched.erase(key);
+  }
+  return GPF_OK;
+}
+
+gpf_status gpf_schedule_get(gpf_ctx *ctx, int n, int fp64, int nb, gpf_schedule *s) {
+  if (!ctx || nb < 1 || !s) return fail(GPF_E_INVALID, "gpf_schedule_get: bad arguments");
+  const gpf::ConvSched c = ctx->sched_for(n, fp64 != 0, nb);
+  s->rows = c.rows;
+  s->order = c.order;
+  s->cols = c.cols;
+  return GPF_OK;
+}
+
+namespace gpf {
+namespace {
+
+// a cached result for (arch, n, precision, class), or false
+bool tune_cache_read(const char *path, const char *arch, int n, int fp64, int cls, ConvSched *sc,
+                     double *us) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char a[64];
+    int nn, d, c, r, o, k;
+    double t;
+    if (std::sscanf(line, "%63s %d %d %d %d %d %d %lf", a, &nn, &d, &c, &r, &o, &k, &t) != 8) continue;
+    if (std::strcmp(a, arch) || nn != n || d != fp64 || c != cls) continue;
+    gpf_schedule g{r, o, k};
+    if (!sched_valid(g)) continue;
+    sc->rows = r;
+    sc->order = o;
+    sc->cols = k;
+    *us = t;
+    found = true;   // the last matching line wins
+  }
+  std::fclose(f);
+  return found;
+}
+
+template <class T>
+gpf_status tune_precision(gpf_plan *plan, int nb, ConvSched *best, double *best_us) {
+  const int n = plan->grid.n;
+  constexpr bool D = std::is_same<T, double>::value;
+  const size_t cells = (size_t)n * n, half = (size_t)(n + 1) * n;
+  const size_t per = cells * sizeof(T) * 2 + half * 2 * sizeof(T);
+  if ((double)per * nb > 16.0 * (1ull << 30)) return fail(GPF_E_NOMEM, "gpf_autotune: more than 16 GiB");
+  DevBuf src, X, out, desc;
+  GPF_TRY(src.alloc(cells * sizeof(T) * nb));
+  GPF_TRY(X.alloc(half * 2 * sizeof(T) * nb));
+  GPF_TRY(out.alloc(cells * sizeof(T) * nb));
+  GPF_TRY(desc.alloc(sizeof(ConvDesc) * nb));
+  GPF_HIP(hipMemset(src.p, 0, src.bytes));
+  std::vector<ConvDesc> cd(nb);
+  for (int i = 0; i < nb; ++i) {
+    ConvDesc &c = cd[i];
+    std::memset(&c, 0, sizeof(c));
+    c.in = src.as<char>() + cells * sizeof(T) * i;
+    c.X = X.as<char>() + half * 2 * sizeof(T) * i;
+    c.out = out.as<char>() + cells * sizeof(T) * i;
+    c.spec = D ? plan->spec64.p : plan->spec32.p;
+    c.tw = D ? plan->tw64.p : plan->tw32.p;
+    c.c = plan->gauge_c;
+    c.row_lo = 0;
+    c.row_hi = n - 1;
+  }
+  GPF_HIP(hipMemcpy(desc.p, cd.data(), sizeof(ConvDesc) * nb, hipMemcpyHostToDevice));
+  const ConvDesc *d = desc.as<const ConvDesc>();
+  std::vector<ConvSched> cands;
+  const int ncols = (D && n >= 512) ? 2 : 1;
+  for (int r = 1; r <= 2; ++r)
+    for (int o = 1; o <= 2; ++o)
+      for (int k = 0; k < ncols; ++k) {
+        ConvSched c;
+        c.rows = r;
+        c.order = o;
+        c.cols = ncols == 2 ? 1 + k : 0;
+        cands.push_back(c);
+      }
+  hipStream_t s = nullptr;
+  GPF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  gpf_status st = GPF_OK;
+  auto run = [&]() -> gpf_status {
+    GPF_HIP(hipEventCreate(&e0));
+    GPF_HIP(hipEventCreate(&e1));
+    const int xcds = plan->ctx->xcds;
+    constexpr int kReps = 10;
+    *best_us = 1e30;
+    for (const ConvSched &c : cands) {
+      for (int w = 0; w < 2; ++w) GPF_HIP((launch_convolve<T, T>(n, d, nb, xcds, 0, s, c)));
+      double t_min = 1e30;
+      for (int round = 0; round < 2; ++round) {
+        GPF_HIP(hipEventRecord(e0, s));
+        for (int k = 0; k < kReps; ++k) GPF_HIP((launch_convolve<T, T>(n, d, nb, xcds, 0, s, c)));
+        GPF_HIP(hipEventRecord(e1, s));
+        GPF_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        GPF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t_min = std::min(t_min, 1e3 * ms / kReps);
+      }
+      if (t_min < *best_us) {
+        *best_us = t_min;
+        *best = c;
+      }
+    }
+    return GPF_OK;
+  };
+  {
+    TimerScope none(nullptr);
+    st = run();
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return st;
+}
+
+}  // namespace
+}  // namespace gpf
+
+gpf_status gpf_autotune(gpf_plan *plan, int fp64, int nb, const char *cache_path,
+                        gpf_schedule *chosen, double *us) {
+  if (!plan || nb < 1 || nb > 1024) return fail(GPF_E_INVALID, "gpf_autotune: bad arguments");
+  GPF_HIP(hipSetDevice(plan->ctx->device));
+  gpf_ctx *ctx = plan->ctx;
+  const int n = plan->grid.n;
+  const int cls = sched_class(nb);
+  ConvSched best;
+  double t = 0.0;
+  if (!(cache_path && tune_cache_read(cache_path, ctx->arch, n, fp64 ? 1 : 0, cls, &best, &t))) {
+    if (fp64) {
+      if (!plan->spec64.p) GPF_TRY(upload_spectrum<double>(plan, plan->spec64, plan->tw64));
+      GPF_TRY(tune_precision<double>(plan, nb, &best, &t));
+    } else {
+      if (!plan->spec32.p) GPF_TRY(upload_spectrum<float>(plan, plan->spec32, plan->tw32));
+      GPF_TRY(tune_precision<float>(plan, nb, &best, &t));
+    }
+    if (cache_path) {
+      FILE *f = std::fopen(cache_path, "a");
+      if (!f) return fail(GPF_E_INVALID, "gpf_autotune: cannot append to the cache file");
+      std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", ctx->arch, n, fp64 ? 1 : 0, cls, best.rows,
+                   best.order, best.cols, t);
+      std::fclose(f);
+    }
+  }
+  gpf_schedule g{best.rows, best.order, best.cols};
+  GPF_TRY(gpf_schedule_set(ctx, n, fp64, nb, &g));
+  if (chosen) *chosen = g;
+  if (us) *us = t;
+  return GPF_OK;
+}

@@ -321,16 +321,15 @@ __device__ __forceinline__ void fft_seq(typename CT<T>::V (&x)[kE], typename CT<
 }
 
 // Row-pass block index.  Workgroups are dispatched round-robin over the
-// XCDs.  A workgroup whose run of each k-major row fills whole 128-byte
-// lines keeps the plain order, which spreads every band of rows over all
-// XCDs even where some rows are empty or skipped.  Workgroups with shorter
-// runs share lines with their neighbours, so consecutive logical blocks go
-// to one XCD and share its L2.
-template <bool FULL_LINES>
-__device__ __forceinline__ int xcd_block(int xcds) {
+// XCDs.  remap <= 1 keeps that order, which spreads every band of rows over
+// all XCDs even where some rows are empty or skipped; remap = the XCD count
+// puts consecutive logical blocks on one XCD, so that workgroups whose runs
+// of each k-major row share cache lines also share an L2.  The launcher
+// picks it (see row_remap).
+__device__ __forceinline__ int xcd_block(int remap) {
   const int nb = gridDim.x, b = blockIdx.x;
-  if (FULL_LINES || xcds <= 1 || nb % xcds) return b;
-  return (b % xcds) * (nb / xcds) + b / xcds;
+  if (remap <= 1 || nb % remap) return b;
+  return (b % remap) * (nb / remap) + b / remap;
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +337,7 @@ __device__ __forceinline__ int xcd_block(int xcds) {
 // ---------------------------------------------------------------------------
 template <class Tin, class T, int N, bool WIDE>
 __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_fwd(const ConvDesc *__restrict__ cd,
-                                                                 int xcds) {
+                                                                 int remap) {
   using V = typename CT<T>::V;
   using P = RowPlan<T, N, WIDE>;
   constexpr int n = N / 2;
@@ -348,7 +347,7 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_fwd(const C
   V *__restrict__ X = static_cast<V *>(C.X);
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
-  const int j0 = xcd_block<P::FULL_LINES>(xcds) * 2 * P::SEQ;
+  const int j0 = xcd_block(remap) * 2 * P::SEQ;
 
   const int q = tid / P::TPS, lane = tid % P::TPS;
   V x[kE];
@@ -588,7 +587,7 @@ __global__ __launch_bounds__(N / kE) void k_cols_conv_split(const ConvDesc *__re
 // ---------------------------------------------------------------------------
 template <class T, int N, bool WIDE>
 __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const ConvDesc *__restrict__ cd,
-                                                                 int xcds, int band) {
+                                                                 int remap, int band) {
   using V = typename CT<T>::V;
   using V2 = typename CT<T>::V2;
   using P = RowPlan<T, N, WIDE>;
@@ -601,7 +600,7 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const C
   // band: the grid covers the rows from the 16-row group of row_lo on, read
   // from the compact band when the column pass stored one
   const int lo = band ? C.row_lo & ~15 : 0;
-  const int j0 = lo + xcd_block<P::FULL_LINES>(xcds) * 2 * P::SEQ;
+  const int j0 = lo + xcd_block(remap) * 2 * P::SEQ;
   if (j0 + 2 * P::SEQ <= C.row_lo || j0 > C.row_hi) return;  // rows nobody reads
   const bool compact = band && C.Xb;
   const V *__restrict__ X = compact ? static_cast<const V *>(C.Xb) - lo : static_cast<const V *>(C.X);
@@ -678,47 +677,67 @@ int num_cus() {
   return cus;
 }
 
+// XCD order of a row pass (ConvSched::order): 0 plain where a workgroup's
+// runs fill whole 128-byte lines, consecutive blocks per XCD otherwise;
+// 1 plain; 2 consecutive blocks
+template <class T, int N, bool WIDE>
+int row_remap(const ConvSched &sc, int xcds) {
+  if (sc.order == 1) return 1;
+  if (sc.order == 2) return xcds;
+  return RowPlan<T, N, WIDE>::FULL_LINES ? 1 : xcds;
+}
+
 template <class Tin, class T, int N, bool WIDE>
-void launch_rows_fwd(const ConvDesc *d, int nb, int xcds, hipStream_t st) {
+void launch_rows_fwd(const ConvDesc *d, int nb, int xcds, const ConvSched &sc, hipStream_t st) {
   using RP = RowPlan<T, N, WIDE>;
   hipLaunchKernelGGL((k_rows_fwd<Tin, T, N, WIDE>), dim3(N / 2 / (2 * RP::SEQ), nb), dim3(RP::WGT),
-                     0, st, d, xcds);
+                     0, st, d, row_remap<T, N, WIDE>(sc, xcds));
 }
 // band > 0: only that many rows per problem, from its row_lo's 16-row group
 template <class T, int N, bool WIDE>
-void launch_rows_inv(const ConvDesc *d, int nb, int xcds, int band, hipStream_t st) {
+void launch_rows_inv(const ConvDesc *d, int nb, int xcds, int band, const ConvSched &sc,
+                     hipStream_t st) {
   using RP = RowPlan<T, N, WIDE>;
   const int rows = band > 0 ? std::min(band, N / 2) : N / 2;
   hipLaunchKernelGGL((k_rows_inv<T, N, WIDE>), dim3((rows + 2 * RP::SEQ - 1) / (2 * RP::SEQ), nb),
-                     dim3(RP::WGT), 0, st, d, xcds, band > 0 ? 1 : 0);
+                     dim3(RP::WGT), 0, st, d, row_remap<T, N, WIDE>(sc, xcds), band > 0 ? 1 : 0);
 }
 
 template <class Tin, class T, int N>
-hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, hipStream_t st) {
+hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, const ConvSched &sc,
+                    hipStream_t st) {
   const bool pruned = band > 0;
   using P = Plan<N>;
   constexpr int n = N / 2;
   // wide row blocks when they still give two or more workgroups per CU
-  const bool wide = (n / (2 * RowPlan<T, N, true>::SEQ)) * nb >= 2 * num_cus();
+  // (ConvSched::rows 0), or as the schedule says
+  const bool wide = sc.rows == 2 ||
+                    (sc.rows == 0 && (n / (2 * RowPlan<T, N, true>::SEQ)) * nb >= 2 * num_cus());
   constexpr bool D = std::is_same<T, double>::value;
   timer_begin(D ? GPF_TK_ROWS_FWD64 : GPF_TK_ROWS_FWD, st);
   if (wide)
-    launch_rows_fwd<Tin, T, N, true>(d, nb, xcds, st);
+    launch_rows_fwd<Tin, T, N, true>(d, nb, xcds, sc, st);
   else
-    launch_rows_fwd<Tin, T, N, false>(d, nb, xcds, st);
+    launch_rows_fwd<Tin, T, N, false>(d, nb, xcds, sc, st);
   timer_end(st);
   timer_begin(D ? GPF_TK_COLS64 : GPF_TK_COLS, st);
-  if constexpr (D && N >= 1024)
-    hipLaunchKernelGGL((k_cols_conv_split<T, N>), dim3(n + 1, nb), dim3(N / kE), 0, st, d);
-  else
+  // FP64 from N = 1024 on: the split-exchange column pass unless the
+  // schedule asks for the complex exchange
+  bool split = false;
+  if constexpr (D && N >= 1024) split = sc.cols != 1;
+  if (split) {
+    if constexpr (D && N >= 1024)
+      hipLaunchKernelGGL((k_cols_conv_split<T, N>), dim3(n + 1, nb), dim3(N / kE), 0, st, d);
+  } else {
     hipLaunchKernelGGL((k_cols_conv<T, N>), dim3((n + 1 + P::SEQ - 1) / P::SEQ, nb), dim3(P::WGT),
                        0, st, d);
+  }
   timer_end(st);
   timer_begin(D ? GPF_TK_ROWS_INV64 : GPF_TK_ROWS_INV, st);
   if (wide && !pruned)
-    launch_rows_inv<T, N, true>(d, nb, xcds, 0, st);
+    launch_rows_inv<T, N, true>(d, nb, xcds, 0, sc, st);
   else
-    launch_rows_inv<T, N, false>(d, nb, xcds, band, st);
+    launch_rows_inv<T, N, false>(d, nb, xcds, band, sc, st);
   timer_end(st);
   return hipGetLastError();
 }
@@ -726,22 +745,26 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, hipStream_t s
 }  // namespace
 
 template <class Tin, class T>
-hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t st) {
+hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t st,
+                           const ConvSched &sc) {
   switch (n) {
-    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, band, st);
-    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, band, st);
-    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, band, st);
-    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, band, st);
-    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, band, st);
-    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, band, st);
-    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, band, st);
-    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, band, st);
+    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, band, sc, st);
+    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, band, sc, st);
+    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, band, sc, st);
+    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, band, sc, st);
+    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, band, sc, st);
+    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, band, sc, st);
+    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, band, sc, st);
+    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, band, sc, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_convolve<float, float>(int, const ConvDesc *, int, int, int, hipStream_t);
-template hipError_t launch_convolve<double, double>(int, const ConvDesc *, int, int, int, hipStream_t);
-template hipError_t launch_convolve<double, float>(int, const ConvDesc *, int, int, int, hipStream_t);
+template hipError_t launch_convolve<float, float>(int, const ConvDesc *, int, int, int, hipStream_t,
+                                                     const ConvSched &);
+template hipError_t launch_convolve<double, double>(int, const ConvDesc *, int, int, int, hipStream_t,
+                                                     const ConvSched &);
+template hipError_t launch_convolve<double, float>(int, const ConvDesc *, int, int, int, hipStream_t,
+                                                     const ConvSched &);
 
 }  // namespace gpf

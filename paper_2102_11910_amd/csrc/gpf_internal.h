@@ -9,6 +9,7 @@
 
 #include <cstdint>
 #include <memory>
+#include <map>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -148,6 +149,14 @@ struct SolveScalars {
   int kedge[GPF_MAX_PARTS];
 };
 
+// Launch schedule of the convolution passes (the same arithmetic in every
+// schedule; they differ in how work maps to workgroups and XCDs).
+struct ConvSched {
+  int rows = 0;    // row passes: 0 wide when it gives two workgroups per CU, 1 narrow, 2 wide
+  int order = 0;   // row-pass XCD order: 0 by line fill, 1 dispatch order, 2 blocks per XCD
+  int cols = 0;    // FP64 column pass from N = 1024: 0 or 2 split exchange, 1 complex exchange
+};
+
 // one convolution of one problem: out = conv(in) - c * gamma[0]
 struct ConvDesc {
   void *in;            // n*n source (zeroed after it is read when zero_in)
@@ -229,9 +238,10 @@ template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s);
 // band > 0: the descriptors restrict the output rows, and no problem needs
 // more than `band` rows from the 16-row group of its row_lo (narrow inverse
-// rows over that band only); 0: every row
+// rows over that band only); 0: every row.  sc: launch schedule.
 template <class Tin, class T>
-hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t s);
+hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t s,
+                           const ConvSched &sc);
 template <class T>
 hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
 template <class T>
@@ -322,7 +332,15 @@ struct gpf_ctx {
   int device = 0;
   int num_cu = 0;
   int xcds = 8;
+  char arch[64] = {};
+  // convolution schedules by (n, precision, batch-size class); absent
+  // entries use the default rules
+  std::mutex sched_mu;
+  std::map<long long, gpf::ConvSched> sched;
+  gpf::ConvSched sched_for(int n, bool fp64, int nb);
 };
+// batch-size classes of the schedule table: 1, 2-7, 8-31, 32 and more
+int sched_class(int nb);
 
 // Workspace of one problem slot: source fields, intermediates, first
 // convolution output, aux block and Schur vectors.

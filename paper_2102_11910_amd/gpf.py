@@ -56,6 +56,10 @@ class gpf_grid(C.Structure):
     _fields_ = [("n", C.c_int), ("dx", C.c_double), ("x0", C.c_double), ("y0", C.c_double)]
 
 
+class gpf_schedule(C.Structure):
+    _fields_ = [("rows", C.c_int), ("order", C.c_int), ("cols", C.c_int)]
+
+
 GPF_PARTS = 4
 GPF_MAX_PARTS = 8
 
@@ -115,6 +119,9 @@ def _load():
         "gpf_interpolate_surface": (I, [P, P, P, P]),
         "gpf_vortex_velocity": (I, [P, P, I, P, P, D, D, P, P, P, P]),
         "gpf_lgf_table": (I, [I, DP]),
+        "gpf_schedule_set": (I, [P, I, I, I, C.POINTER(gpf_schedule)]),
+        "gpf_schedule_get": (I, [P, I, I, I, C.POINTER(gpf_schedule)]),
+        "gpf_autotune": (I, [P, I, I, C.c_char_p, C.POINTER(gpf_schedule), DP]),
         "gpf_timing_enable": (I, [P, I]),
         "gpf_timing_read": (I, [P, I, C.POINTER(C.c_longlong), DP]),
         "gpf_batch_create": (I, [P, I, PP]),
@@ -400,6 +407,31 @@ class Outputs:
 def gpf_solve(plan: Plan, body: Body | None, inp: gpf_inputs, out: gpf_outputs, stream=None):
     check(lib.gpf_solve(plan.h, None if body is None else body.h, C.byref(inp), C.byref(out),
                         _stream_ptr(stream)), "gpf_solve")
+
+
+def schedule_set(ctx: Context, n: int, fp64: bool, nb: int, sched=None):
+    """sched: {"rows", "order", "cols"} or None (back to the rules)."""
+    ptr = None
+    if sched is not None:
+        ptr = C.byref(gpf_schedule(int(sched["rows"]), int(sched["order"]), int(sched["cols"])))
+    check(lib.gpf_schedule_set(ctx.h, int(n), int(bool(fp64)), int(nb), ptr), "gpf_schedule_set")
+
+
+def schedule_get(ctx: Context, n: int, fp64: bool, nb: int) -> dict:
+    g = gpf_schedule()
+    check(lib.gpf_schedule_get(ctx.h, int(n), int(bool(fp64)), int(nb), C.byref(g)),
+          "gpf_schedule_get")
+    return {"rows": g.rows, "order": g.order, "cols": g.cols}
+
+
+def autotune(plan: Plan, fp64: bool, nb: int, cache_path=None):
+    """Time the convolution schedules for nb problems of the plan's grid;
+    returns (chosen schedule, microseconds per batched convolution)."""
+    g, us = gpf_schedule(), C.c_double()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    check(lib.gpf_autotune(plan.h, int(bool(fp64)), int(nb), path, C.byref(g), C.byref(us)),
+          "gpf_autotune")
+    return {"rows": g.rows, "order": g.order, "cols": g.cols}, us.value
 
 
 def timing_enable(plan: Plan, enable: bool = True):
