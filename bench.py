@@ -383,12 +383,8 @@ def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
     batch = gpf.Batch(ctx, len(cases))
     pl = [plans[c.n] for c in cases]
     gp = float(sum(c.n * c.n for c in cases))
-    # schedules per grid size for the group each size forms in the batch
-    for nn, p in plans.items():
-        group = [b for c, b in zip(cases, bodies) if c.n == nn]
-        gpf.autotune(p, False, len(group))
-        if any(b.info()["conv1_fp64"] for b in group):
-            gpf.autotune(p, True, len(group))
+    # schedules of every group of the batch, tuned on the batch itself
+    batch.autotune(pl, bodies, ins, [o.struct for o in outs])
 
     def batched():
         batch.solve(pl, bodies, ins, [o.struct for o in outs])
@@ -568,13 +564,12 @@ def main() -> int:
         keep.append((X, Y, G, psi, u, v, f, ft, sc, st))
     batch = gpf.Batch(ctx, B)
     plans, bodies = [plan] * B, [body] * B
-    # convolution schedules for this grid and batch size, chosen by the
-    # library's autotuner before anything is timed (both precisions the step
-    # uses: the FP64 first convolution and the FP32 second one)
-    tuned = {}
-    for fp64 in (True, False):
-        sched, us = gpf.autotune(plan, fp64, B)
-        tuned["fp64" if fp64 else "fp32"] = dict(sched, us_per_batched_convolution=round(us, 2))
+    # convolution schedules of this workload, chosen by the library's
+    # autotuner on the batched step itself before anything is timed (both
+    # precisions the step uses: the FP64 first convolution and the FP32
+    # second one)
+    batch.autotune(plans, bodies, ins, outs)
+    tuned = {"fp64": gpf.schedule_get(ctx, n, True, B), "fp32": gpf.schedule_get(ctx, n, False, B)}
     log(f"[bench] autotuned convolution schedules: {tuned}")
 
     def step_batched():

@@ -521,8 +521,8 @@ typedef struct {
 gpf_status gpf_schedule_set(gpf_ctx *ctx, int n, int fp64, int nb, const gpf_schedule *s);
 gpf_status gpf_schedule_get(gpf_ctx *ctx, int n, int fp64, int nb, gpf_schedule *s);
 
-/* Autotuner: times every schedule (rows 1-2 x order 1-2 x, for FP64 from
- * n = 512, cols 1-2) on nb convolutions of the plan's grid in the given
+/* Autotuner: times the rules and every schedule (rows 1-2 x order 1-2 x,
+ * for FP64 from n = 512, cols 1-2) on nb convolutions of the plan's grid in the given
  * precision (synthetic zero sources; the time does not depend on the values),
  * stores the fastest in the context as by gpf_schedule_set, and returns it
  * in *chosen and its mean time per batched convolution (microseconds) in
@@ -535,6 +535,19 @@ gpf_status gpf_schedule_get(gpf_ctx *ctx, int n, int fp64, int nb, gpf_schedule 
  * 16 GiB. */
 gpf_status gpf_autotune(gpf_plan *plan, int fp64, int nb, const char *cache_path,
                         gpf_schedule *chosen, double *us);
+
+/* Autotuner on a real workload: for every schedule entry the batch's groups
+ * use (per grid size and precision; a body's first convolution under the
+ * precision policy uses the FP64 entry, its second the field precision),
+ * tries the rules and every explicit shape in turn, timing the whole
+ * batched solve (gpf_solve_batched with these arguments, which it runs
+ * about seven times per shape on hip_stream, overwriting the outputs), and
+ * keeps the fastest in the context.  Entries are tuned one after another,
+ * the others staying at their current values.  Blocks until done; the
+ * outputs then hold the result of the last solve. */
+gpf_status gpf_autotune_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
+                                const gpf_body *const *bodies, const gpf_inputs *inputs,
+                                const gpf_outputs *outputs, void *hip_stream);
 
 /* ---- kernel timing ----------------------------------------------------- */
 

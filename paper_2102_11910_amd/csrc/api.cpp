@@ -1821,6 +1821,22 @@ gpf_status gpf_schedule_get(gpf_ctx *ctx, int n, int fp64, int nb, gpf_schedule 
 namespace gpf {
 namespace {
 
+// the schedules the tuners try: the rules first, then every explicit shape
+std::vector<ConvSched> sched_candidates(bool fp64, int n) {
+  std::vector<ConvSched> c(1);
+  const int ncols = (fp64 && n >= 512) ? 2 : 1;
+  for (int r = 1; r <= 2; ++r)
+    for (int o = 1; o <= 2; ++o)
+      for (int k = 0; k < ncols; ++k) {
+        ConvSched x;
+        x.rows = r;
+        x.order = o;
+        x.cols = ncols == 2 ? 1 + k : 0;
+        c.push_back(x);
+      }
+  return c;
+}
+
 // a cached result for (arch, n, precision, class), or false
 bool tune_cache_read(const char *path, const char *arch, int n, int fp64, int cls, ConvSched *sc,
                      double *us) {
@@ -1874,17 +1890,7 @@ gpf_status tune_precision(gpf_plan *plan, int nb, ConvSched *best, double *best_
   }
   GPF_HIP(hipMemcpy(desc.p, cd.data(), sizeof(ConvDesc) * nb, hipMemcpyHostToDevice));
   const ConvDesc *d = desc.as<const ConvDesc>();
-  std::vector<ConvSched> cands;
-  const int ncols = (D && n >= 512) ? 2 : 1;
-  for (int r = 1; r <= 2; ++r)
-    for (int o = 1; o <= 2; ++o)
-      for (int k = 0; k < ncols; ++k) {
-        ConvSched c;
-        c.rows = r;
-        c.order = o;
-        c.cols = ncols == 2 ? 1 + k : 0;
-        cands.push_back(c);
-      }
+  const std::vector<ConvSched> cands = sched_candidates(D, n);
   hipStream_t s = nullptr;
   GPF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1958,4 +1964,89 @@ gpf_status gpf_autotune(gpf_plan *plan, int fp64, int nb, const char *cache_path
   if (chosen) *chosen = g;
   if (us) *us = t;
   return GPF_OK;
+}
+
+gpf_status gpf_autotune_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
+                                const gpf_body *const *bodies, const gpf_inputs *inputs,
+                                const gpf_outputs *outputs, void *hip_stream) {
+  if (!batch || nprob < 1 || nprob > batch->max_problems || !plans || !inputs || !outputs)
+    return fail(GPF_E_INVALID, "gpf_autotune_batched: bad arguments");
+  GPF_HIP(hipSetDevice(batch->ctx->device));
+  gpf_ctx *ctx = batch->ctx;
+  // the groups gpf_solve_batched forms, and the schedule entries they use
+  std::vector<GroupCfg> cfgs;
+  std::vector<int> counts;
+  for (int i = 0; i < nprob; ++i) {
+    const gpf_body *b = bodies ? bodies[i] : nullptr;
+    GPF_TRY(validate(plans[i], b, &inputs[i], &outputs[i]));
+    ProblemRef r{plans[i], inputs[i].mode == GPF_NOBODY ? nullptr : b, &inputs[i], &outputs[i],
+                 batch->ws[i]};
+    const GroupCfg cfg = config_of(r);
+    size_t g = 0;
+    while (g < cfgs.size() && !same_cfg(cfgs[g], cfg)) ++g;
+    if (g == cfgs.size()) {
+      cfgs.push_back(cfg);
+      counts.push_back(0);
+    }
+    ++counts[g];
+  }
+  const int lanes = std::min(batch->lanes, nprob);
+  struct Key {
+    int n, nb;
+    bool fp64;
+  };
+  std::vector<Key> keys;
+  auto add = [&](int n, bool fp64, int nb) {
+    for (const Key &k : keys)
+      if (k.n == n && k.fp64 == fp64 && sched_class(k.nb) == sched_class(nb)) return;
+    keys.push_back(Key{n, nb, fp64});
+  };
+  for (size_t g = 0; g < cfgs.size(); ++g) {
+    const int nb = lanes > 1 ? (counts[g] + lanes - 1) / lanes : counts[g];
+    add(cfgs[g].n, cfgs[g].fp64_plan || cfgs[g].conv1_fp64, nb);
+    if (cfgs[g].body) add(cfgs[g].n, cfgs[g].fp64_plan, nb);
+  }
+  hipStream_t s = as_stream(hip_stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GPF_HIP(hipEventCreate(&e0));
+  GPF_HIP(hipEventCreate(&e1));
+  auto timed = [&](double *us) -> gpf_status {
+    GPF_TRY(gpf_solve_batched(batch, nprob, plans, bodies, inputs, outputs, hip_stream));
+    constexpr int kReps = 3;
+    double best = 1e30;
+    for (int round = 0; round < 2; ++round) {
+      GPF_HIP(hipEventRecord(e0, s));
+      for (int k = 0; k < kReps; ++k)
+        GPF_TRY(gpf_solve_batched(batch, nprob, plans, bodies, inputs, outputs, hip_stream));
+      GPF_HIP(hipEventRecord(e1, s));
+      GPF_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      GPF_HIP(hipEventElapsedTime(&ms, e0, e1));
+      best = std::min(best, 1e3 * ms / kReps);
+    }
+    *us = best;
+    return GPF_OK;
+  };
+  gpf_status st = GPF_OK;
+  for (const Key &k : keys) {
+    ConvSched best;
+    double best_us = 1e30;
+    for (const ConvSched &c : sched_candidates(k.fp64, k.n)) {
+      gpf_schedule g{c.rows, c.order, c.cols};
+      st = gpf_schedule_set(ctx, k.n, k.fp64, k.nb, &g);
+      double us = 0.0;
+      if (st == GPF_OK) st = timed(&us);
+      if (st != GPF_OK) break;
+      if (us < best_us) {
+        best_us = us;
+        best = c;
+      }
+    }
+    if (st != GPF_OK) break;
+    gpf_schedule g{best.rows, best.order, best.cols};
+    GPF_TRY(gpf_schedule_set(ctx, k.n, k.fp64, k.nb, &g));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
 }

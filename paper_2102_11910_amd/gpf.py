@@ -122,6 +122,8 @@ def _load():
         "gpf_schedule_set": (I, [P, I, I, I, C.POINTER(gpf_schedule)]),
         "gpf_schedule_get": (I, [P, I, I, I, C.POINTER(gpf_schedule)]),
         "gpf_autotune": (I, [P, I, I, C.c_char_p, C.POINTER(gpf_schedule), DP]),
+        "gpf_autotune_batched": (I, [P, I, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
         "gpf_timing_enable": (I, [P, I]),
         "gpf_timing_read": (I, [P, I, C.POINTER(C.c_longlong), DP]),
         "gpf_batch_create": (I, [P, I, PP]),
@@ -497,6 +499,18 @@ class Batch:
         oa = (gpf_outputs * k)(*outputs)
         check(lib.gpf_solve_batched(self.h, k, pa, ba, ia, oa, _stream_ptr(stream)),
               "gpf_solve_batched")
+
+    def autotune(self, plans, bodies, inputs, outputs, stream=None):
+        """Choose the convolution schedules of this workload by timing the
+        batched solve under each (gpf_autotune_batched); the outputs then
+        hold the result of the last solve."""
+        k = len(plans)
+        pa = (C.c_void_p * k)(*[p.h.value for p in plans])
+        ba = (C.c_void_p * k)(*[(b.h.value if b is not None else None) for b in bodies])
+        ia = (gpf_inputs * k)(*inputs)
+        oa = (gpf_outputs * k)(*outputs)
+        check(lib.gpf_autotune_batched(self.h, k, pa, ba, ia, oa, _stream_ptr(stream)),
+              "gpf_autotune_batched")
 
     def close(self):
         if self.h:

@@ -104,7 +104,7 @@ def test_autotune_picks_a_schedule_and_caches_it(ctx, tmp_path, fp64):
     cache = tmp_path / "tune.txt"
     chosen, us = gpf.autotune(plan, fp64, B, cache)
     say(f"[autotune] n={c.n} fp64={fp64} nb={B}: {chosen}, {us:.1f} us per batched convolution")
-    assert chosen in schedules(fp64, c.n)
+    assert chosen in [{"rows": 0, "order": 0, "cols": 0}] + schedules(fp64, c.n)
     assert us > 0.0 and math.isfinite(us)
     assert gpf.schedule_get(ctx, c.n, fp64, B) == chosen
     # batch sizes of the same class share the entry; other classes do not
@@ -136,3 +136,29 @@ def test_schedule_arguments_checked(ctx):
     with pytest.raises(gpf.GpfError) as e:
         gpf.autotune(plan, False, 2000)
     assert e.value.status == gpf.GPF_E_INVALID
+
+
+def test_batched_autotuner_tunes_the_entries_the_batch_uses(ctx):
+    """On the plate batch the tuner sets the FP64 entry (first convolution)
+    and the FP32 entry (second) of the batch's class, and the solves that
+    follow still match the oracle."""
+    pb = PlateBatch(ctx)
+    n = pb.cases[0].n
+    for fp64 in (False, True):
+        gpf.schedule_set(ctx, n, fp64, B, None)
+    pb.batch.autotune([pb.plan] * B, [pb.body] * B, pb.ins, [o.struct for o in pb.outs])
+    s64, s32 = gpf.schedule_get(ctx, n, True, B), gpf.schedule_get(ctx, n, False, B)
+    say(f"[autotune batched] FP64 {s64}, FP32 {s32}")
+    assert s64 in [{"rows": 0, "order": 0, "cols": 0}] + schedules(True, n)
+    assert s32 in [{"rows": 0, "order": 0, "cols": 0}] + schedules(False, n)
+    # classes the batch does not use are untouched
+    assert gpf.schedule_get(ctx, n, True, 1) == {"rows": 0, "order": 0, "cols": 0}
+    got = pb.solve()
+    table = lgf_table(n)
+    for i in (0, B - 1):
+        ref = oracle_solve(problem_of(pb.cases[i]), body_of(pb.cases[i], table), table)
+        es, ef = rell2(got[i]["s"], ref.s), rell2(got[i]["f"], ref.f)
+        say(f"   problem {i}: s {es:.1e} f {ef:.1e}")
+        assert es <= 1e-5 and ef <= 1e-4
+    for fp64 in (False, True):
+        gpf.schedule_set(ctx, n, fp64, B, None)
