@@ -144,7 +144,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, command: str) -> None:
             continue
         fb = sum(fetch[k] for k in ks) / ff
         wb = sum(write.get(k, 0.0) for k in ks) / fw
-        matched = ",".join(p for p in prefixes if any(p in k for k in ks))
+        matched = ",".join(p.replace(" ", "") for p in prefixes if any(p in k for k in ks))
         lines.append(f"class {cls}: fetch_bytes={fb:.0f} write_bytes={wb:.0f} "
                      f"source={src}@{source_hash(src)} kernels={len(ks)} matched={matched}")
     lines += ["", "| kernel | dispatches | FETCH (MB, raw) | WRITE (MB, raw) |", "|---|---|---|---|"]
@@ -166,10 +166,10 @@ def measured_traffic(cls: str, kernel_prefix=None):
     with open(TRAFFIC_SUMMARY) as fh:
         for line in fh:
             if line.startswith(f"class {cls}:"):
-                kv = dict(t.split("=", 1) for t in line.split(":", 1)[1].split())
-                if kv["source"] != f"{src}@{source_hash(src)}":
+                kv = dict(t.split("=", 1) for t in line.split(":", 1)[1].split() if "=" in t)
+                if kv.get("source") != f"{src}@{source_hash(src)}":
                     return None
-                if kernel_prefix is not None and kv.get("matched") != kernel_prefix:
+                if kernel_prefix is not None and kv.get("matched") != kernel_prefix.replace(" ", ""):
                     return None
                 return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
     return None

@@ -1,0 +1,52 @@
+"""Host logic of bench.py that needs no GPU: the algorithmic byte model,
+the kept-row fraction of the benchmark plate, the traffic-summary lookup
+(source hash and kernel match), and the refusal of more than one GPU."""
+import subprocess
+import sys
+
+import pytest
+
+import bench
+from paper_2102_11910_amd import workloads as wl
+
+
+def test_kernel_bytes_match_the_convolution_model():
+    n = 512
+    kb = bench.kernel_bytes(n, 10000, 256, 2, True, 1.0)
+    # one FP32 convolution: 44 n^2 to leading order (rows 12, cols 20, rows 12)
+    conv32 = kb["rows_fwd"] - 8 * n * n + 4 * n * n + kb["cols"] + kb["rows_inv"]
+    assert abs(conv32 / (44.0 * n * n) - 1.0) < 0.02
+    # the FP64 column pass reads and writes complex doubles and a real FP64 spectrum
+    assert kb["cols64"] == 32 * n * (n + 1) + 8 * (n + 1) ** 2
+
+
+def test_kept_rows_of_the_benchmark_plate():
+    keep = bench.kept_rows(wl.config2())
+    # the 20 degree plate spans about 70 rows; whole 16-row groups: 96 of 512
+    assert keep == 96 / 512
+
+
+def test_traffic_lookup_checks_source_and_kernel(tmp_path, monkeypatch):
+    src = bench.source_hash("fft_conv.hip")
+    f = tmp_path / "traffic.md"
+    f.write_text(
+        f"class cols64: fetch_bytes=100 write_bytes=20 source=fft_conv.hip@{src} kernels=1 "
+        "matched=k_cols_conv_split<double\n"
+        f"class rows_fwd: fetch_bytes=7 write_bytes=3 source=fft_conv.hip@{src} kernels=1 "
+        "matched=k_rows_fwd<double,float\n"
+        "class cols: fetch_bytes=1 write_bytes=1 source=fft_conv.hip@0000 kernels=1 "
+        "matched=k_cols_conv<float\n")
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(f))
+    assert bench.measured_traffic("cols64", "k_cols_conv_split<double") == 120.0
+    assert bench.measured_traffic("cols64") == 120.0
+    assert bench.measured_traffic("cols64", "k_cols_conv<double") is None   # another kernel
+    assert bench.measured_traffic("rows_fwd", "k_rows_fwd<double, float") == 10.0
+    assert bench.measured_traffic("cols") is None                            # stale source
+    assert bench.measured_traffic("velocity") is None                        # not measured
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
