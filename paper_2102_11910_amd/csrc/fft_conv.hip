@@ -211,6 +211,21 @@ template <bool INV, class V> __device__ __forceinline__ V rot16(V w, int k) {
   return cmul(w, c);
 }
 
+// Exchange barrier of one sequence.  Where a sequence lies inside one
+// wavefront (N / 16 <= 64 lanes) and no other wavefront touches its LDS rows,
+// the wavefront orders its own LDS traffic (its LDS instructions execute in
+// order), so only the compiler must keep the order: a wavefront-scope fence,
+// with no wait for the stores and no workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void seq_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage.  Lane `lane` of the group owning a sequence handles
 // butterflies bf = lane + b * TPS (b < 16/R), each reading elements
 // bf + r * N/R and writing base + r * NS.  With IN_REGS the stage reads its
@@ -219,7 +234,7 @@ template <bool INV, class V> __device__ __forceinline__ V rot16(V w, int k) {
 // again as x[k] = element lane + k * TPS: in the last stage the butterfly
 // b, output r lands at lane + TPS * (b + r * 16/R).
 template <class T, int N, int S, bool INV, bool ZERO_UPPER, bool LOWER_OUT, bool IN_REGS,
-          bool OUT_REGS>
+          bool OUT_REGS, bool WAVE>
 __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
                                           const typename CT<T>::V (&wr)[tw_regs<N>()],
                                           const typename CT<T>::V *tw, int lane) {
@@ -255,7 +270,7 @@ __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename C
         }
       }
     }
-    __syncthreads();
+    seq_sync<WAVE>();
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -295,29 +310,34 @@ __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename C
       }
     }
   }
-  if (!OUT_REGS) __syncthreads();
+  if (!OUT_REGS) seq_sync<WAVE>();
 }
 
-template <class T, int N, int S, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS>
+template <class T, int N, int S, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS,
+          bool WAVE>
 __device__ __forceinline__ void fft_stages(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
                                            const typename CT<T>::V (&wr)[tw_regs<N>()],
                                            const typename CT<T>::V *tw, int lane) {
   constexpr int NST = num_stages<N>();
   if constexpr (S < NST) {
     fft_stage<T, N, S, INV, ZIN && S == 0, LOUT && S == NST - 1, IN_REGS && S == 0,
-              OUT_REGS && S == NST - 1>(x, lds, wr, tw, lane);
-    fft_stages<T, N, S + 1, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, wr, tw, lane);
+              OUT_REGS && S == NST - 1, WAVE>(x, lds, wr, tw, lane);
+    fft_stages<T, N, S + 1, INV, ZIN, LOUT, IN_REGS, OUT_REGS, WAVE>(x, lds, wr, tw, lane);
   }
 }
 
 // Length-N transform of one sequence; all threads of the block must call it
-// (it synchronizes the block).  IN_REGS / OUT_REGS: input / output in x[]
+// (it synchronizes the block, or with WAVE only the compiler's order: for
+// callers whose sequences each lie inside one wavefront and whose LDS rows
+// no other wavefront touches).  IN_REGS / OUT_REGS: input / output in x[]
 // (x[k] = element lane + k * N/16), otherwise in natural order in lds.
-template <class T, int N, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS>
+template <class T, int N, bool INV, bool ZIN, bool LOUT, bool IN_REGS, bool OUT_REGS,
+          bool WAVE = false>
 __device__ __forceinline__ void fft_seq(typename CT<T>::V (&x)[kE], typename CT<T>::V *lds,
                                         const typename CT<T>::V (&wr)[tw_regs<N>()],
                                         const typename CT<T>::V *tw, int lane) {
-  fft_stages<T, N, 0, INV, ZIN, LOUT, IN_REGS, OUT_REGS>(x, lds, wr, tw, lane);
+  static_assert(!WAVE || N / kE <= 64, "a wavefront-ordered sequence fits one wavefront");
+  fft_stages<T, N, 0, INV, ZIN, LOUT, IN_REGS, OUT_REGS, WAVE>(x, lds, wr, tw, lane);
 }
 
 // Row-pass block index.  Workgroups are dispatched round-robin over the
@@ -438,13 +458,15 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
   V wr[tw_regs<N>()];
   if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, lane);
   V *L = lds + q * P::LDS_SEQ;
-  fft_seq<T, N, false, true, false, true, true>(x, L, wr, tw, lane);
+  // each sequence is one wavefront's (or part of one) and so are its LDS rows
+  constexpr bool kWave = P::TPS <= 64;
+  fft_seq<T, N, false, true, false, true, true, kWave>(x, L, wr, tw, lane);
 #pragma unroll
   for (int k = 0; k < kE; ++k) {
     x[k].x *= g[k];
     x[k].y *= g[k];
   }
-  fft_seq<T, N, true, false, true, true, true>(x, L, wr, tw, lane);
+  fft_seq<T, N, true, false, true, true, true, kWave>(x, L, wr, tw, lane);
   if (c0 + q <= n) {
     // only the rows the last pass reads: all, unless the first convolution
     // feeds the surface stencils alone.  The last pass transforms rows in
@@ -526,7 +548,7 @@ __device__ __forceinline__ void split_stages(typename CT<T>::V (&x)[kE], T *lds,
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[spad(base + r * NS)] = part ? v[b][r].y : v[b][r].x;
       }
-      __syncthreads();
+      seq_sync<(TPS <= 64)>();   // the workgroup is the sequence
 #pragma unroll
       for (int b2 = 0; b2 < NB2; ++b2) {
         const int bf2 = lane + b2 * TPS;
@@ -539,7 +561,7 @@ __device__ __forceinline__ void split_stages(typename CT<T>::V (&x)[kE], T *lds,
             x[b2 * R2 + r2].x = val;
         }
       }
-      __syncthreads();
+      seq_sync<(TPS <= 64)>();
     }
     split_stages<T, N, S + 1, INV, ZIN>(x, lds, tw, lane);
   }
