@@ -375,3 +375,37 @@ def test_invalid_arguments(ctx):
     inp = gpf.make_inputs(X, X, X, u_inf=math.inf)
     with pytest.raises(gpf.GpfError):
         s.solve(inp, X)
+
+
+@pytest.mark.parametrize("flags", [gpf.GPF_FP64, gpf.GPF_FP32])
+def test_window_limits_nodes_and_coincident_vortices(ctx, flags):
+    """Vortices exactly at the lowest allowed cell index (xi = 2) and just
+    below the highest (n - 3), on nodes, and thousands at one point (one
+    tile, one LDS window, heavy atomic traffic), against the oracle; the
+    first index outside the window on either side is reported."""
+    n = 64
+    case = wl.random_case(77, n, 2.0 / n, 0)
+    dx, x0 = case.dx, -(n - 1) * case.dx / 2          # both exact in binary
+    lo, hi = 2.0, (n - 3) - 2.0 ** -20
+    rng = np.random.default_rng(77)
+    xi = [lo, hi, lo, hi, 30.0, 30.5, 17.0]
+    eta = [lo, hi, hi, lo, 30.0, 30.5, 40.25]
+    k = 3000
+    xi += [33.37] * k
+    eta += [21.81] * k
+    G = np.r_[[0.3, -0.2, 0.1, 0.25, -0.4, 0.15, 0.05], rng.normal(0.0, 1e-2, k)]
+    case.X = x0 + dx * np.asarray(xi)
+    case.Y = x0 + dx * np.asarray(eta)
+    case.G = wl.f32(G)
+    say(f"[window] n={n}, {len(case.X)} vortices, flags={flags}")
+    got = run_solve(ctx, case, flags)
+    ref = oracle_solve(problem_of(case), body_of(case))
+    compare(case, got, ref, flags == gpf.GPF_FP64, f"window limits, flags={flags}")
+    s = gpf.Solver(ctx, n, dx, flags=flags)
+    for bad in (n - 3.0, 2.0 - 2.0 ** -20):
+        X = dt([x0 + dx * 30.0, x0 + dx * bad])
+        Y = dt([x0 + dx * 30.0, x0 + dx * 30.0])
+        s.solve(gpf.make_inputs(X, Y, dt([1.0, 1.0])), X)
+        with pytest.raises(gpf.GpfError) as e:
+            gpf.gpf_sync(s.status)
+        assert e.value.status == gpf.GPF_E_OUT_OF_GRID, bad
