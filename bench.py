@@ -364,6 +364,18 @@ def diagnostics_leg(gpf, torch, np, ctx, log, wl, reps=50):
     res["two_plates_workload"] = f"{mc.name}, nv={mc.nv}, ns={len(mc.xs)}, 4 new vortices"
     res["two_plates_solve_ms"] = _timed(torch, lambda: gpf.gpf_solve(plan, body, minp, mout), reps)
     gpf.gpf_sync(st)
+    # the plate's Schur complement: the exact FP64 build of body creation
+    # (host-timed, with the inversion and the probes), and the column build
+    # from 256 unit sheets in batches of 32, FP32 and FP64 fields, against it
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sb = gpf.Body(s.plan, case.surface.xs, case.surface.ys, case.surface.ds, tuple(case.edges))
+    torch.cuda.synchronize()
+    res["schur"] = {"body_create_ms": 1e3 * (time.perf_counter() - t0)}
+    for fp64 in (False, True):
+        rs, rf, ms = sb.schur_by_convolution(fp64=fp64, batch=32)
+        res["schur"]["columns_" + ("fp64" if fp64 else "fp32")] = {
+            "rel_S": rs, "rel_f_unit_flow": rf, "ms": ms}
     log(f"[bench] diagnostics: {res}")
     return res
 

@@ -492,6 +492,24 @@ gpf_status gpf_vortex_velocity(gpf_plan *plan, const void *d_s, int nv,
                                double *d_v, unsigned int *d_status,
                                void *hip_stream);
 
+/* ---- the Schur complement built from batched right-hand sides ----------- */
+
+/* The Schur complement S = -E_s L^-1 R_s (Sec. 2.2.2, eq. basicblock) built
+ * column by column: the unit sheets e_q pass through the regularization
+ * R_s, the convolution and the interpolation E_s, `batch` columns per
+ * batched launch sequence, with FP32 (fp64 = 0) or FP64 fields; the first
+ * convolution's row band and the plan's schedules apply.  The result is
+ * compared with the body's exact S (built from the LGF table in FP64, as
+ * gpf_body_create does): *h_rel_s = ||S_conv - S||_F / ||S||_F, and
+ * *h_rel_f = relL2 of S_conv^-1 r against S^-1 r for r = -y_s (the sheet of
+ * a unit uniform flow, S_conv inverted in FP64); *h_ms = the time of the
+ * column build (ms).  All three nullable; *h_rel_f is infinite when S_conv
+ * is singular.  A diagnostic of the build: the body keeps its exact S.
+ * Blocks until done; allocates about batch (4 n^2 sizeof(T)) bytes plus
+ * 3 ns^2 doubles; batch in [1, 1024], GPF_E_NOMEM beyond 16 GiB. */
+gpf_status gpf_body_schur_by_convolution(gpf_body *body, int fp64, int batch, double *h_rel_s,
+                                         double *h_rel_f, double *h_ms);
+
 /* ---- convolution schedules and the autotuner --------------------------- */
 
 /* How the three passes of the convolution (Sec. 2.1, the zero-padded LGF

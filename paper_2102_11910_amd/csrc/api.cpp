@@ -2050,3 +2050,127 @@ gpf_status gpf_autotune_batched(gpf_batch *batch, int nprob, gpf_plan *const *pl
   (void)hipEventDestroy(e1);
   return st;
 }
+
+// ---------------------------------------------------------------------------
+// Schur complement built column by column through batched convolutions
+// ---------------------------------------------------------------------------
+
+namespace gpf {
+namespace {
+
+template <class T>
+gpf_status schur_by_columns(gpf_body *b, int batch, double *S, hipStream_t s) {
+  gpf_plan *pl = b->plan;
+  const int n = pl->grid.n, ns = b->ns;
+  constexpr bool D = std::is_same<T, double>::value;
+  const size_t cells = (size_t)n * n, half = (size_t)(n + 1) * n;
+  DevBuf w, X, out, desc;
+  GPF_TRY(w.alloc(cells * sizeof(T) * batch));
+  GPF_TRY(X.alloc(half * 2 * sizeof(T) * batch));
+  GPF_TRY(out.alloc(cells * sizeof(T) * batch));
+  GPF_TRY(desc.alloc(sizeof(ConvDesc) * batch));
+  GPF_HIP(launch_fill(w.p, w.bytes, s));   // sources start zero; the row pass leaves them zero
+  std::vector<ConvDesc> cd(batch);
+  const int band = body_band(b);
+  for (int q0 = 0; q0 < ns; q0 += batch) {
+    const int nb = std::min(batch, ns - q0);
+    for (int i = 0; i < nb; ++i) {
+      ConvDesc &c = cd[i];
+      std::memset(&c, 0, sizeof(c));
+      c.in = w.as<char>() + cells * sizeof(T) * i;
+      c.X = X.as<char>() + half * 2 * sizeof(T) * i;
+      c.out = out.as<char>() + cells * sizeof(T) * i;
+      c.spec = D ? pl->spec64.p : pl->spec32.p;
+      c.tw = D ? pl->tw64.p : pl->tw32.p;
+      c.gamma_val = b->hds[q0 + i];   // circulation of the unit sheet: dS_q
+      c.c = pl->gauge_c;
+      c.zero_in = 1;
+      c.row_lo = b->row_lo;            // only the surface stencils read the result
+      c.row_hi = b->row_hi;
+    }
+    GPF_HIP(hipMemcpyAsync(desc.p, cd.data(), sizeof(ConvDesc) * nb, hipMemcpyHostToDevice, s));
+    GPF_HIP(launch_unit_sheets<T>(n, ns, q0, nb, pl->grid.dx, b->st_i.as<int>(),
+                                  b->st_w.as<double>(), b->ds.as<double>(), w.as<T>(), cells, s));
+    GPF_HIP((launch_convolve<T, T>(n, desc.as<const ConvDesc>(), nb, pl->ctx->xcds, band, s,
+                                   pl->ctx->sched_for(n, D, nb))));
+    GPF_HIP(launch_interp_columns<T>(n, ns, q0, nb, b->st_i.as<int>(), b->st_w.as<double>(),
+                                     out.as<const T>(), cells, S, s));
+    GPF_HIP(hipStreamSynchronize(s));   // the descriptors are rewritten for the next batch
+  }
+  return GPF_OK;
+}
+
+}  // namespace
+}  // namespace gpf
+
+gpf_status gpf_body_schur_by_convolution(gpf_body *body, int fp64, int batch, double *h_rel_s,
+                                         double *h_rel_f, double *h_ms) {
+  if (!body || batch < 1 || batch > 1024)
+    return fail(GPF_E_INVALID, "gpf_body_schur_by_convolution: bad arguments");
+  gpf_plan *pl = body->plan;
+  GPF_HIP(hipSetDevice(pl->ctx->device));
+  const int n = pl->grid.n, ns = body->ns;
+  const size_t T = fp64 ? 8 : 4;
+  if ((double)batch * ((double)n * n * 2 * T + (double)(n + 1) * n * 2 * T) > 16.0 * (1ull << 30))
+    return fail(GPF_E_NOMEM, "gpf_body_schur_by_convolution: more than 16 GiB");
+  if (fp64) {
+    if (!pl->spec64.p) GPF_TRY(upload_spectrum<double>(pl, pl->spec64, pl->tw64));
+  } else {
+    if (!pl->spec32.p) GPF_TRY(upload_spectrum<float>(pl, pl->spec32, pl->tw32));
+  }
+  hipStream_t s = nullptr;
+  const size_t mb = (size_t)ns * ns * sizeof(double);
+  DevBuf Sc, Se, Sinv, R, F;
+  GPF_TRY(Sc.alloc(mb));
+  GPF_TRY(Se.alloc(mb));
+  GPF_TRY(Sinv.alloc(mb));
+  GPF_TRY(R.alloc(ns * sizeof(double)));
+  GPF_TRY(F.alloc(2 * ns * sizeof(double)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GPF_HIP(hipDeviceSynchronize());
+  GPF_HIP(hipEventCreate(&e0));
+  GPF_HIP(hipEventCreate(&e1));
+  gpf_status st;
+  {
+    TimerScope none(nullptr);
+    GPF_HIP(hipEventRecord(e0, s));
+    st = fp64 ? schur_by_columns<double>(body, batch, Sc.as<double>(), s)
+              : schur_by_columns<float>(body, batch, Sc.as<double>(), s);
+    GPF_HIP(hipEventRecord(e1, s));
+  }
+  GPF_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  GPF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  GPF_TRY(st);
+  // the exact S, from the LGF table, and the two sheets of a unit uniform flow
+  GPF_HIP(launch_schur_build(n, ns, body->st_i.as<int>(), body->st_w.as<double>(),
+                             body->ds.as<double>(), pl->lgf.as<double>(), Se.as<double>(), s));
+  std::vector<double> hc((size_t)ns * ns), he((size_t)ns * ns);
+  GPF_HIP(hipMemcpy(hc.data(), Sc.p, mb, hipMemcpyDeviceToHost));
+  GPF_HIP(hipMemcpy(he.data(), Se.p, mb, hipMemcpyDeviceToHost));
+  double dn = 0.0, en = 0.0;
+  for (size_t k = 0; k < hc.size(); ++k) {
+    dn += (hc[k] - he[k]) * (hc[k] - he[k]);
+    en += he[k] * he[k];
+  }
+  double min_piv = 0.0;
+  GPF_TRY(invert_fp64(ns, Sc.as<double>(), Sinv.as<double>(), s, &min_piv));
+  std::vector<double> r(ns);
+  for (int p = 0; p < ns; ++p) r[p] = -body->hys[p];
+  GPF_HIP(hipMemcpy(R.p, r.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+  GPF_HIP(launch_gemv(ns, 1, Sinv.as<double>(), R.as<double>(), F.as<double>(), s));
+  GPF_HIP(launch_gemv(ns, 1, body->sinv.as<double>(), R.as<double>(), F.as<double>() + ns, s));
+  std::vector<double> hf(2 * (size_t)ns);
+  GPF_HIP(hipMemcpy(hf.data(), F.p, 2 * ns * sizeof(double), hipMemcpyDeviceToHost));
+  double df = 0.0, fn = 0.0;
+  for (int p = 0; p < ns; ++p) {
+    df += (hf[p] - hf[ns + p]) * (hf[p] - hf[ns + p]);
+    fn += hf[ns + p] * hf[ns + p];
+  }
+  if (h_rel_s) *h_rel_s = std::sqrt(dn / en);
+  if (h_rel_f) *h_rel_f = min_piv > 1e-14 ? std::sqrt(df / fn) : INFINITY;
+  if (h_ms) *h_ms = ms;
+  return GPF_OK;
+}

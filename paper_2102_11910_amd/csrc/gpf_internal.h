@@ -308,6 +308,16 @@ hipError_t launch_axpy2(int nv, const double *x, const double *y, const double *
 
 // single-problem helpers used at setup and by the building blocks
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);   // zero bytes (a multiple of 4)
+// Schur build by columns: field b (stride elements apart) gets R_s e_{q0+b};
+// column q0 + b of the row-major S gets E_s of field b
+template <class T>
+hipError_t launch_unit_sheets(int n, int ns, int q0, int nb, double dx, const int *st_i,
+                              const double *st_w, const double *ds, T *w, size_t stride,
+                              hipStream_t s);
+template <class T>
+hipError_t launch_interp_columns(int n, int ns, int q0, int nb, const int *st_i,
+                                 const double *st_w, const T *f, size_t stride, double *S,
+                                 hipStream_t s);
 hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
                                    const double *xs, const double *ys, int *st_i,
                                    double *st_w, unsigned *status, hipStream_t s);

@@ -334,6 +334,44 @@ __global__ void k_interp_surface(int n, int ns, const int *__restrict__ st_i,
   r[p] = acc;
 }
 
+// Unit sheets for a column-by-column Schur build: field b of the batch gets
+// R_s e_q, q = q0 + b, i.e. dS_q / dx^2 times the 4 x 4 stencil weights of
+// surface point q (distinct nodes: plain stores into a zeroed field).
+template <class T>
+__global__ void k_unit_sheets(int n, int ns, int q0, double inv_dx2, const int *__restrict__ st_i,
+                              const double *__restrict__ st_w, const double *__restrict__ ds,
+                              T *w, size_t stride) {
+  const int q = q0 + blockIdx.x;
+  if (q >= ns || threadIdx.x >= 16) return;
+  const int a = threadIdx.x & 3, b = threadIdx.x >> 2;
+  const int i0 = st_i[2 * q], j0 = st_i[2 * q + 1];
+  w[stride * blockIdx.x + (size_t)(j0 + b) * n + i0 + a] =
+      (T)(ds[q] * inv_dx2 * st_w[8 * q + a] * st_w[8 * q + 4 + b]);
+}
+
+// E_s of field b of the batch at every surface point, into column q0 + b of
+// the row-major ns x ns matrix S
+template <class T>
+__global__ void k_interp_columns(int n, int ns, int q0, const int *__restrict__ st_i,
+                                 const double *__restrict__ st_w, const T *__restrict__ f,
+                                 size_t stride, double *__restrict__ S) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = q0 + blockIdx.y;
+  if (p >= ns || q >= ns) return;
+  const T *fb = f + stride * blockIdx.y;
+  const int i0 = st_i[2 * p], j0 = st_i[2 * p + 1];
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double rowacc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      rowacc += st_w[8 * p + a] * (double)fb[(size_t)(j0 + b) * n + i0 + a];
+    acc += st_w[8 * p + 4 + b] * rowacc;
+  }
+  S[(size_t)p * ns + q] = acc;
+}
+
 // velocity at the vortices: u = (s[j+1] - s[j-1]) / 2dx, v = -(s[i+1] - s[i-1]) / 2dx
 // at the 4 x 4 stencil nodes, interpolated with M4' weights, plus the
 // uniform flow.
@@ -509,6 +547,34 @@ template hipError_t launch_interp_surface<float>(int, int, const int *, const do
                                                  const float *, double *, hipStream_t);
 template hipError_t launch_interp_surface<double>(int, int, const int *, const double *,
                                                   const double *, double *, hipStream_t);
+
+template <class T>
+hipError_t launch_unit_sheets(int n, int ns, int q0, int nb, double dx, const int *st_i,
+                              const double *st_w, const double *ds, T *w, size_t stride,
+                              hipStream_t s) {
+  hipLaunchKernelGGL((k_unit_sheets<T>), dim3(nb), dim3(64), 0, s, n, ns, q0, 1.0 / (dx * dx), st_i,
+                     st_w, ds, w, stride);
+  return hipGetLastError();
+}
+template hipError_t launch_unit_sheets<float>(int, int, int, int, double, const int *,
+                                              const double *, const double *, float *, size_t,
+                                              hipStream_t);
+template hipError_t launch_unit_sheets<double>(int, int, int, int, double, const int *,
+                                               const double *, const double *, double *, size_t,
+                                               hipStream_t);
+
+template <class T>
+hipError_t launch_interp_columns(int n, int ns, int q0, int nb, const int *st_i,
+                                 const double *st_w, const T *f, size_t stride, double *S,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL((k_interp_columns<T>), dim3((ns + 127) / 128, nb), dim3(128), 0, s, n, ns, q0,
+                     st_i, st_w, f, stride, S);
+  return hipGetLastError();
+}
+template hipError_t launch_interp_columns<float>(int, int, int, int, const int *, const double *,
+                                                 const float *, size_t, double *, hipStream_t);
+template hipError_t launch_interp_columns<double>(int, int, int, int, const int *, const double *,
+                                                  const double *, size_t, double *, hipStream_t);
 
 template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s) {
