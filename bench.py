@@ -673,7 +673,9 @@ def main() -> int:
                                "shared launches",
                    "n": n, "nv": case.nv, "ns": case.surface.ns, "batch": B, "path": "batched",
                    "precision": "FP32 fields; FP64 first convolution (noise amplification "
-                                f"{info['amp']:.3g} > 500), FP64 Schur/constraints"},
+                                f"{info['amp']:.3g} > 500), FP64 Schur/constraints; S built "
+                                "exactly in FP64 from the LGF table (its build from 256 "
+                                "batched unit sheets, FP32 and FP64, under diagnostics.schur)"},
         "latency_ms": {"p50": float(np.percentile(lat_b, 50)),
                        "p99": float(np.percentile(lat_b, 99)),
                        "per": f"batch of {B} solves"},
