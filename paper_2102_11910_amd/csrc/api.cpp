@@ -268,6 +268,7 @@ gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns, int 
   if (nns > 0) {
     const size_t cols = 1 + GPF_MAX_EDGES;
     GPF_TRY(rhs.alloc(cols * nns * sizeof(double)));
+    GPF_TRY(y.alloc(cols * nns * sizeof(double)));
     ns = std::max(ns, nns);
   }
   n = std::max(n, nn);
@@ -514,15 +515,17 @@ template <class TW, class T1, class T2>
 gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const ConvDesc *c1,
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, bool impulse,
                         int band, int xcds, const ConvSched &sc1, const ConvSched &sc2,
-                        hipStream_t s) {
+                        bool shared, const double *shared_sinv, hipStream_t s) {
   GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
   GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body ? band : 0, s, sc1)));
   if (cfg.body) {
     GPF_HIP(launch_surface_rhs<T1>(pd, nb, ns_max, m_max, s));
-    if (cfg.parts)
+    if (cfg.parts) {
       GPF_HIP(launch_schur_apply_parts<TW>(pd, nb, ns_max, s));
-    else
+    } else {
+      if (shared) GPF_HIP(launch_schur_gemm(pd, nb, ns_max, m_max, shared_sinv, s));
       GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, m_max, s));
+    }
     GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2)));
   }
   GPF_HIP(launch_vortex_velocity<T2>(pd, nb, nv_max, s));
@@ -549,6 +552,13 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
     band = std::max(band, (c1[i].row_hi | 15) - (c1[i].row_lo & ~15) + 1);
     impulse = impulse || pd[i].imp_out != nullptr;
   }
+  // problems that share one body (one-part modes): S^-1 is applied to all
+  // their right-hand sides as one product on the matrix cores
+  bool shared = cfg.body && !cfg.parts && nb >= 2;
+  for (int i = 1; i < nb && shared; ++i) shared = probs[i].body == probs[0].body;
+  for (int i = 0; i < nb && shared; ++i) shared = probs[i].ws->y.p != nullptr;
+  if (shared)
+    for (int i = 0; i < nb; ++i) pd[i].y = probs[i].ws->y.as<double>();
   void *dev = nullptr;
   GPF_TRY(ring.push(blk.data(), blk.size(), s, &dev));
   const ProbDesc *dpd = static_cast<const ProbDesc *>(dev);
@@ -561,12 +571,15 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   const ConvSched sc2 = ctx->sched_for(cfg.n, cfg.fp64_plan, nb);
   if (cfg.fp64_plan)
     return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   band, xcds, sc1, sc2, s);
+                                                   band, xcds, sc1, sc2, shared,
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, s);
   if (cfg.conv1_fp64)
     return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   band, xcds, sc1, sc2, s);
+                                                   band, xcds, sc1, sc2, shared,
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, s);
   return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
-                                                   band, xcds, sc1, sc2, s);
+                                                   band, xcds, sc1, sc2, shared,
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, s);
 }
 
 gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,

@@ -207,6 +207,8 @@ struct ProbDesc {
   double gamma0;
   double mom_x, mom_y, mom_r2;  // sums of fhat0 x, fhat0 y, fhat0 (x^2 + y^2)
   double *rhs;                  // Schur right-hand sides: ns x (1+m)
+  double *y;                    // S^-1 rhs, formed for the whole launch (problems sharing
+                                // one body), or null: each workgroup forms its rows
   // outputs (nullable)
   const void *psi;              // final field (velocities read it)
   double *u, *v, *f_out, *ft_out, *sc_out;
@@ -246,6 +248,10 @@ template <class T>
 hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
 template <class T>
 hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
+// y = S^-1 rhs for nb problems that share one body (ns points, S^-1 = sinv),
+// on the matrix cores; every descriptor's y must be set
+hipError_t launch_schur_gemm(const ProbDesc *d, int nb, int ns, int m_max, const double *sinv,
+                             hipStream_t s);
 // the same for bodies of several parts (mode GPF_PARTS)
 template <class T>
 hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
@@ -356,7 +362,7 @@ int sched_class(int nb);
 // convolution output, aux block and Schur vectors.
 struct gpf_workspace {
   int n = 0, ns = 0, nv = 0;
-  gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs;
+  gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y;
   gpf::DevBuf xb;   // compact band of the first convolution's column pass
   gpf::DevBuf bin_cnt, bin_start, tile_list, rank, sorted;
   // band: rows of a body's band (16-row groups), 0 without a body

@@ -345,6 +345,39 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   const int ne = mode == GPF_KUTTA_SHED ? m : (mode == GPF_KUTTA_STEADY ? 1 : 0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
+  const double gw_dev = P.aux[SC_GAMMA_W];
+  size_t coff[MC];   // column offsets, clamped to the last column
+#pragma unroll
+  for (int c = 0; c < MC; ++c) coff[c] = (size_t)min(c, ncol - 1) * ns;
+  if (P.y) {
+    // y_c = S^-1 r_c was formed for the whole launch: ghat . r_c = dS . y_c,
+    // and the edge rows and this workgroup's rows are read from y
+    const double *Y = P.y;
+    double acc[MC];
+#pragma unroll
+    for (int c = 0; c < MC; ++c) acc[c] = 0.0;
+    for (int q = tid; q < ns; q += kCB) {
+      const double w = P.ds[q];
+#pragma unroll
+      for (int c = 0; c < MC; ++c) acc[c] += w * Y[coff[c] + q];
+    }
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+      if (c < ncol) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) red[wave][c] = v;
+      }
+    }
+    if (tid < ne * MC) {
+      const int e = tid / MC, c = tid - e * MC;
+      const int kp = sv.edges[e];
+      if (c < ncol) ye[e][c] = Y[(size_t)c * ns + kp] / P.f0[kp];
+    }
+    if (tid < kCRows * MC) {
+      const int rr = tid / MC, c = tid - rr * MC;
+      if (c < ncol && row0 + rr < ns) yr[rr][c] = Y[(size_t)c * ns + row0 + rr];
+    }
+  } else {
   // Loads below are unconditional, with indices clamped into range, so
   // that each wave keeps many of them in flight; sums of clamped terms
   // are discarded.  The first slices of this wave's rows of S^-1 and of
@@ -360,7 +393,6 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
 #pragma unroll
     for (int r = 0; r < kRowsPerWave; ++r) apre[i][r] = arow[r][min(lane + 64 * i, ns - 1)];
   const double gpre = P.ghat[min(tid, ns - 1)];
-  const double gw_dev = P.aux[SC_GAMMA_W];
   const double *R = P.rhs;
   if (ncol * ns <= kRStage) {
 #pragma unroll 4
@@ -368,9 +400,6 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
     __syncthreads();
     R = rs;
   }
-  size_t coff[MC];   // column offsets, clamped to the last column
-#pragma unroll
-  for (int c = 0; c < MC; ++c) coff[c] = (size_t)min(c, ncol - 1) * ns;
   // ghat . rhs_c, all columns in one sweep
   {
     double acc[MC];
@@ -458,6 +487,7 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
         }
       }
     }
+  }
   }
   __syncthreads();
 
@@ -612,6 +642,62 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
       for (int j = 0; j < GPF_MAX_EDGES; ++j) P.sc_out[SC_GAMMA_NEW + j] = scal[3 + j];
     }
     if (singular_flag) atomicOr(P.status, GPF_DEV_SINGULAR);
+  }
+}
+
+// y = S^-1 rhs for problems that share one body: the right-hand-side
+// columns of all problems side by side (problem b's column c at b * ncol + c)
+// times S^-1, a dense FP64 product on the matrix cores.  One workgroup of
+// four wavefronts per 16 x 16 tile of y; wavefront w takes the quarter w of
+// the k range, 16 steps of v_mfma_f64_16x16x4f64 at a time with all their
+// operands loaded first (lane l holds A[l % 16][k + l / 16] and
+// B[k + l / 16][l % 16]; output item r of lane l is row 4 r + l / 16,
+// column l % 16 of the tile), and the four partial tiles are summed in LDS.
+typedef double double4v __attribute__((ext_vector_type(4)));
+constexpr int kGemmSteps = 16;
+__global__ __launch_bounds__(256) void k_schur_gemm(const ProbDesc *__restrict__ d, int nb,
+                                                    int ncol, int ns,
+                                                    const double *__restrict__ A) {
+  __shared__ double part[3][64][4];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  const int i0 = blockIdx.x * 16;
+  const int g = blockIdx.y * 16 + li;   // column of the launch
+  const int b = min(g / ncol, nb - 1), c = g - (g / ncol) * ncol;
+  // this lane's problem: its column count and buffers, loaded together
+  const ProbDesc &P = d[b];
+  const int mode = P.sv.mode, mm = P.sv.m;
+  const double *Rb = P.rhs + (size_t)c * ns;
+  double *Yb = P.y + (size_t)c * ns;
+  const bool colok = g / ncol < nb && c <= (mode == GPF_KUTTA_SHED ? mm : 0);
+  const double *Ar = A + (size_t)min(i0 + li, ns - 1) * ns;
+  const int kq = (((ns + 3) / 4 + 3) / 4) * 4;   // this wavefront's k range, a multiple of 4
+  const int kbeg = wave * kq, kend = min(ns, kbeg + kq);
+  double4v acc = {0.0, 0.0, 0.0, 0.0};
+  for (int kc = kbeg; kc < kend; kc += 4 * kGemmSteps) {
+    double av[kGemmSteps], bv[kGemmSteps];
+#pragma unroll
+    for (int t = 0; t < kGemmSteps; ++t) {
+      const int k = kc + 4 * t + lk;
+      const bool in = k < kend;
+      av[t] = in ? Ar[k] : 0.0;
+      bv[t] = (colok && in) ? Rb[k] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kGemmSteps; ++t)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wave - 1][l][r] = acc[r];
+  }
+  __syncthreads();
+  if (wave == 0 && colok) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = i0 + 4 * r + lk;
+      const double v = acc[r] + part[0][l][r] + part[1][l][r] + part[2][l][r];
+      if (row < ns) Yb[row] = v;
+    }
   }
 }
 
@@ -975,6 +1061,14 @@ hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, 
 }
 template hipError_t launch_surface_rhs<float>(const ProbDesc *, int, int, int, hipStream_t);
 template hipError_t launch_surface_rhs<double>(const ProbDesc *, int, int, int, hipStream_t);
+
+hipError_t launch_schur_gemm(const ProbDesc *d, int nb, int ns, int m_max, const double *sinv,
+                             hipStream_t s) {
+  const int cols = nb * (1 + m_max);
+  hipLaunchKernelGGL(k_schur_gemm, dim3((ns + 15) / 16, (cols + 15) / 16), dim3(256), 0, s, d, nb,
+                     1 + m_max, ns, sinv);
+  return hipGetLastError();
+}
 
 template <class T>
 hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s) {
