@@ -364,6 +364,31 @@ def diagnostics_leg(gpf, torch, np, ctx, log, wl, reps=50):
     res["two_plates_workload"] = f"{mc.name}, nv={mc.nv}, ns={len(mc.xs)}, 4 new vortices"
     res["two_plates_solve_ms"] = _timed(torch, lambda: gpf.gpf_solve(plan, body, minp, mout), reps)
     gpf.gpf_sync(st)
+    # the paper's airfoil demonstration: NACA 0012 at 20 deg started
+    # impulsively, shedding at the trailing edge for 3 convective times
+    nc = wl.naca0012_demo()
+    nsteps = 40
+    nplan = gpf.Plan(ctx, nc.n, nc.dx, flags=gpf.GPF_POLICY_AUTO)
+    sfn = nc.surface
+    nbody = gpf.Body(nplan, sfn.xs, sfn.ys, sfn.ds, tuple(nc.edges))
+    Xn, Yn, Gn = z(nsteps), z(nsteps), z(nsteps)
+    nsc = z(gpf.N_SCALARS)
+    nout = gpf.make_outputs(torch.empty((nc.n, nc.n), dtype=nplan.field_dtype, device=dev),
+                            z(nsteps), z(nsteps), z(sfn.ns), z(sfn.ns), nsc,
+                            torch.zeros(1, dtype=torch.int32, device=dev))
+    ninp = gpf.make_inputs(Xn, Yn, Gn, nc.u_inf, nc.v_inf, mode="shed", znew=nc.znew)
+    ninp.nv = 0
+    first = [(zz[0] - sfn.xs[k], zz[1] - sfn.ys[k]) for zz, k in zip(nc.znew, nc.edges)]
+    shed = gpf.Shed(nplan, nbody, ninp, nout, Xn, Yn, Gn, nc.extra["dt"], first)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    shed.run(nsteps)
+    shed.sync()
+    torch.cuda.synchronize()
+    res["naca0012_demo"] = {"workload": f"{nc.name}, ns={sfn.ns}, {nsteps} steps of dt U/c = "
+                                        f"{nc.extra['dt']}", "ms_per_step":
+                            1e3 * (time.perf_counter() - t0) / nsteps,
+                            "gamma_b_end": float(nsc[3].item())}
     # the plate's Schur complement: the exact FP64 build of body creation
     # (host-timed, with the inversion and the probes), and the column build
     # from 256 unit sheets in batches of 32, FP32 and FP64 fields, against it

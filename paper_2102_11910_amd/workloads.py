@@ -92,6 +92,74 @@ def ellipse(a: float, b: float, ns: int, rotation: float = 0.0, center=(0.0, 0.0
                    c * nxl - s * nyl, s * nxl + c * nyl)
 
 
+def _closed_airfoil(xd, yd, ns: int, alpha_deg: float, center, kind: str, params: dict) -> Surface:
+    """Resample a dense closed contour (counter-clockwise, starting and
+    ending at the trailing edge, chord along x with the leading edge at
+    x = -c/2) to ns points equispaced in arc length from the trailing edge
+    (point 0, the body's edge), then set it at incidence alpha (nose up)."""
+    seg = np.hypot(np.diff(xd), np.diff(yd))
+    arc = np.concatenate([[0.0], np.cumsum(seg)])
+    perim = arc[-1]
+    sp = np.arange(ns) * perim / ns
+    x, y = np.interp(sp, arc, xd), np.interp(sp, arc, yd)
+    # outward normals from the contour's direction at each point (counter-clockwise)
+    h = 1e-6 * perim
+    tx = np.interp(np.mod(sp + h, perim), arc, xd) - np.interp(np.mod(sp - h, perim), arc, xd)
+    ty = np.interp(np.mod(sp + h, perim), arc, yd) - np.interp(np.mod(sp - h, perim), arc, yd)
+    nrm = np.hypot(tx, ty)
+    nxl, nyl = ty / nrm, -tx / nrm
+    a = np.deg2rad(alpha_deg)
+    ca, sa = np.cos(a), np.sin(a)
+    xs = center[0] + ca * x + sa * y
+    ys = center[1] - sa * x + ca * y
+    ds = np.full(ns, perim / ns)
+    params = dict(params, alpha_deg=alpha_deg, center=center, perimeter=perim)
+    return Surface(kind, f32(xs), f32(ys), f32(ds), (0,), params,
+                   ca * nxl + sa * nyl, -sa * nxl + ca * nyl)
+
+
+def naca4_symmetric(thickness: float, chord: float, alpha_deg: float, ns: int,
+                    center=(0.0, 0.0)) -> Surface:
+    """Symmetric NACA four-digit section (00tt: thickness ratio t) with the
+    closed trailing edge form of the thickness polynomial, at incidence
+    alpha (nose up); points equispaced in arc length from the trailing edge
+    (point 0, the edge), counter-clockwise (upper surface first)."""
+    beta = np.linspace(0.0, np.pi, 20001)
+    xc = 0.5 * (1.0 - np.cos(beta))                  # 0 .. 1, clustered at both ends
+    yt = 5.0 * thickness * (0.2969 * np.sqrt(xc) - 0.1260 * xc - 0.3516 * xc ** 2
+                            + 0.2843 * xc ** 3 - 0.1036 * xc ** 4)
+    xu, yu = xc[::-1], yt[::-1]                      # upper: trailing edge to leading edge
+    xd = np.concatenate([xu, xc[1:]]) * chord - 0.5 * chord
+    yd = np.concatenate([yu, -yt[1:]]) * chord
+    yd[0] = yd[-1] = 0.0
+    return _closed_airfoil(xd, yd, ns, alpha_deg, center, "naca",
+                           {"thickness": thickness, "chord": chord})
+
+
+def joukowski(eps_over_b: float, chord: float, alpha_deg: float, ns: int,
+              center=(0.0, 0.0)) -> Surface:
+    """Symmetric Joukowski airfoil: the circle of radius a = b (1 + e)
+    centred at -b e mapped by z = zeta + b^2 / zeta, scaled to the given
+    chord, at incidence alpha (nose up).  Potential flow with the Kutta
+    condition at its cusp gives the bound circulation -4 pi U a sin(alpha)
+    exactly (a after scaling: params["radius"]).  Points equispaced in arc
+    length from the cusp (point 0, the edge), counter-clockwise."""
+    b = 1.0
+    eps = eps_over_b * b
+    a = b + eps
+    th = np.linspace(0.0, 2.0 * np.pi, 200001)
+    zeta = -eps + a * np.exp(1j * th)
+    z = zeta + b * b / zeta
+    te = 2.0 * b
+    le = -(b + 2.0 * eps) - b * b / (b + 2.0 * eps)
+    scale = chord / (te - le)
+    z = (z - 0.5 * (te + le)) * scale
+    xd, yd = z.real, z.imag
+    yd[0] = yd[-1] = 0.0
+    return _closed_airfoil(xd, yd, ns, alpha_deg, center, "joukowski",
+                           {"eps_over_b": eps_over_b, "chord": chord, "radius": a * scale})
+
+
 # ----------------------------------------------------------------------------
 # vortex clouds
 # ----------------------------------------------------------------------------
@@ -306,6 +374,26 @@ def config5_request(rng, nv_max: int = 1000000) -> Case:
         c.edges = surf.edges
         c.znew = plate_new_vortices(surf, 4.0 * dx)
     return c
+
+
+def naca0012_demo(n: int = 1024) -> Case:
+    """The paper's airfoil demonstration: NACA 0012, chord 1, at 20 deg in a
+    unit uniform flow started impulsively, dx/c = 0.01, dS/dx = 1.5, shedding
+    at the trailing edge (Kutta) with dt U/c = 0.075 (extra["dt"]); no vortex
+    at the start.  The section sits 3.5 chords upstream of the window's
+    centre so that 3 convective times of wake stay inside the 1024^2 window.
+    The first release is one step's travel downstream of the trailing edge."""
+    dx, chord, alpha = 0.01, 1.0, 20.0
+    per = naca4_symmetric(0.12, chord, alpha, 16).params["perimeter"]
+    surf = naca4_symmetric(0.12, chord, alpha, int(round(per / (1.5 * dx))), center=(-3.5, 0.0))
+    dt = 0.075
+    te = (float(surf.xs[0]), float(surf.ys[0]))
+    z = np.zeros(0)
+    case = Case(f"NACA 0012 at 20 deg, {n}^2", n, dx, z, z, z, surf, u_inf=1.0, mode="shed")
+    case.edges = (0,)
+    case.znew = ((te[0] + dt, te[1]),)
+    case.extra["dt"] = dt
+    return case
 
 
 def random_case(seed: int, n: int, dx: float, nv: int, surface: str | None = "cylinder",
