@@ -446,8 +446,10 @@ def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
     batch = gpf.Batch(ctx, len(cases))
     pl = [plans[c.n] for c in cases]
     gp = float(sum(c.n * c.n for c in cases))
-    # schedules of every group of the batch, tuned on the batch itself
+    # lane count and schedules of every group of the batch, tuned on the
+    # batch itself
     batch.autotune(pl, bodies, ins, [o.struct for o in outs])
+    log(f"[bench] C4 lanes chosen: {batch.lanes}")
 
     def batched():
         batch.solve(pl, bodies, ins, [o.struct for o in outs])
@@ -458,7 +460,7 @@ def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
 
     res = {"workload": f"{len(cases)} ellipse problems, n in {sorted(plans)}, "
                        f"nv {min(c.nv for c in cases)}..{max(c.nv for c in cases)}",
-           "grid_points_per_batch": gp}
+           "grid_points_per_batch": gp, "lanes": batch.lanes}
     for name, fn in (("batched", batched), ("plain", plain)):
         for _ in range(2):
             fn()

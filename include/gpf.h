@@ -314,13 +314,21 @@ gpf_status gpf_solve(gpf_plan *plan, const gpf_body *body,
 gpf_status gpf_batch_create(gpf_ctx *ctx, int max_problems, gpf_batch **out);
 void gpf_batch_destroy(gpf_batch *batch);
 
-/* Split each configuration group of a batch over `lanes` (1..4) internal
- * streams: the caller's stream is forked to them with an event before the
- * solve and joined after it, so that the latency-bound kernels of one part
- * overlap the bandwidth-bound passes of another.  Results are unchanged;
- * lanes = 1 (the default) runs everything on the caller's stream.  The
- * fork and join are events, so a captured graph records them. */
+/* Run a batch over `lanes` (1..4) internal streams: the caller's stream is
+ * forked to them with an event before the solve and joined after it, so
+ * that the latency-bound kernels of one part overlap the bandwidth-bound
+ * passes of another.  A batch of several configuration groups (grid sizes,
+ * precisions) puts whole groups on the lanes, the costliest first on the
+ * least loaded lane (cost ~ problems x n^2), so that small grids run beside
+ * large ones; a batch of one group deals its members out over the lanes.
+ * Results are unchanged; lanes = 1 (the default) runs everything on the
+ * caller's stream.  The fork and join are events, so a captured graph
+ * records them. */
 gpf_status gpf_batch_set_lanes(gpf_batch *batch, int lanes);
+
+/* The batch's current lane count (1 after create, then as set by
+ * gpf_batch_set_lanes or chosen by gpf_autotune_batched); 0 for NULL. */
+int gpf_batch_get_lanes(const gpf_batch *batch);
 
 /* Solve nprob independent problems (each as in gpf_solve; bodies may be
  * NULL or hold NULL for GPF_NOBODY problems).  Problems are grouped by grid
@@ -554,15 +562,17 @@ gpf_status gpf_schedule_get(gpf_ctx *ctx, int n, int fp64, int nb, gpf_schedule 
 gpf_status gpf_autotune(gpf_plan *plan, int fp64, int nb, const char *cache_path,
                         gpf_schedule *chosen, double *us);
 
-/* Autotuner on a real workload: for every schedule entry the batch's groups
+/* Autotuner on a real workload: first the batch's lane count (1..4, as by
+ * gpf_batch_set_lanes), then, for every schedule entry the batch's groups
  * use (per grid size and precision; a body's first convolution under the
  * precision policy uses the FP64 entry, its second the field precision),
- * tries the rules and every explicit shape in turn, timing the whole
+ * the rules and every explicit shape in turn, each choice timing the whole
  * batched solve (gpf_solve_batched with these arguments, which it runs
- * about seven times per shape on hip_stream, overwriting the outputs), and
- * keeps the fastest in the context.  Entries are tuned one after another,
- * the others staying at their current values.  Blocks until done; the
- * outputs then hold the result of the last solve. */
+ * about seven times per trial on hip_stream, overwriting the outputs) and
+ * keeping the fastest (the lane count in the batch, the schedules in the
+ * context).  Entries are tuned one after another, the others staying at
+ * their current values.  Blocks until done; the outputs then hold the
+ * result of the last solve. */
 gpf_status gpf_autotune_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
                                 const gpf_body *const *bodies, const gpf_inputs *inputs,
                                 const gpf_outputs *outputs, void *hip_stream);

@@ -1394,6 +1394,8 @@ gpf_status gpf_batch_set_lanes(gpf_batch *batch, int lanes) {
   return GPF_OK;
 }
 
+int gpf_batch_get_lanes(const gpf_batch *batch) { return batch ? batch->lanes : 0; }
+
 gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
                              const gpf_body *const *bodies, const gpf_inputs *inputs,
                              const gpf_outputs *outputs, void *hip_stream) {
@@ -1428,9 +1430,10 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
     GPF_HIP(hipEventRecord(batch->fork_ev, s));
     for (int l = 0; l < lanes; ++l) GPF_HIP(hipStreamWaitEvent(batch->lane_stream[l], batch->fork_ev, 0));
   }
-  // group by configuration, keeping the first-seen order of the groups;
-  // with lanes, the members of each group are dealt out over the lanes
+  // group by configuration, keeping the first-seen order of the groups
   std::vector<char> done(nprob, 0);
+  std::vector<GroupCfg> cfgs;
+  std::vector<std::vector<ProblemRef>> groups;
   for (int i = 0; i < nprob; ++i) {
     if (done[i]) continue;
     const GroupCfg cfg = config_of(refs[i]);
@@ -1440,16 +1443,35 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
         grp.push_back(refs[k]);
         done[k] = 1;
       }
-    if (lanes == 1) {
-      GPF_TRY(run_group(cfg, grp, batch->ring, batch->ctx->xcds, s));
-      continue;
+    cfgs.push_back(cfg);
+    groups.push_back(std::move(grp));
+  }
+  const int ng = (int)groups.size();
+  if (lanes == 1) {
+    for (int g = 0; g < ng; ++g) GPF_TRY(run_group(cfgs[g], groups[g], batch->ring, batch->ctx->xcds, s));
+  } else if (ng >= 2) {
+    // several groups: whole groups to lanes, the costliest first to the
+    // least loaded lane (cost ~ problems x n^2), so that small grids run
+    // beside large ones
+    std::vector<int> order(ng);
+    for (int g = 0; g < ng; ++g) order[g] = g;
+    auto cost = [&](int g) { return (double)groups[g].size() * cfgs[g].n * cfgs[g].n; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<double> load(lanes, 0.0);
+    for (int g : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[l] += cost(g);
+      GPF_TRY(run_group(cfgs[g], groups[g], batch->ring, batch->ctx->xcds, batch->lane_stream[l]));
     }
+  } else {
+    // one group: its members dealt out over the lanes
+    const std::vector<ProblemRef> &grp = groups[0];
     const int per = ((int)grp.size() + lanes - 1) / lanes;
     for (int l = 0; l < lanes; ++l) {
       const int a = l * per, b = std::min((int)grp.size(), a + per);
       if (a >= b) break;
       std::vector<ProblemRef> part(grp.begin() + a, grp.begin() + b);
-      GPF_TRY(run_group(cfg, part, batch->ring, batch->ctx->xcds, batch->lane_stream[l]));
+      GPF_TRY(run_group(cfgs[0], part, batch->ring, batch->ctx->xcds, batch->lane_stream[l]));
     }
   }
   if (lanes > 1) {
@@ -2003,22 +2025,6 @@ gpf_status gpf_autotune_batched(gpf_batch *batch, int nprob, gpf_plan *const *pl
     }
     ++counts[g];
   }
-  const int lanes = std::min(batch->lanes, nprob);
-  struct Key {
-    int n, nb;
-    bool fp64;
-  };
-  std::vector<Key> keys;
-  auto add = [&](int n, bool fp64, int nb) {
-    for (const Key &k : keys)
-      if (k.n == n && k.fp64 == fp64 && sched_class(k.nb) == sched_class(nb)) return;
-    keys.push_back(Key{n, nb, fp64});
-  };
-  for (size_t g = 0; g < cfgs.size(); ++g) {
-    const int nb = lanes > 1 ? (counts[g] + lanes - 1) / lanes : counts[g];
-    add(cfgs[g].n, cfgs[g].fp64_plan || cfgs[g].conv1_fp64, nb);
-    if (cfgs[g].body) add(cfgs[g].n, cfgs[g].fp64_plan, nb);
-  }
   hipStream_t s = as_stream(hip_stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   GPF_HIP(hipEventCreate(&e0));
@@ -2041,7 +2047,41 @@ gpf_status gpf_autotune_batched(gpf_batch *batch, int nprob, gpf_plan *const *pl
     return GPF_OK;
   };
   gpf_status st = GPF_OK;
+  // the lane count first, with the schedules as they stand
+  {
+    int best_l = batch->lanes;
+    double best_us = 1e30;
+    for (int l = 1; l <= gpf_batch::kMaxLanes && st == GPF_OK; ++l) {
+      st = gpf_batch_set_lanes(batch, l);
+      double us = 0.0;
+      if (st == GPF_OK) st = timed(&us);
+      if (st == GPF_OK && us < best_us) {
+        best_us = us;
+        best_l = l;
+      }
+    }
+    if (st == GPF_OK) st = gpf_batch_set_lanes(batch, best_l);
+  }
+  const int lanes = std::min(batch->lanes, nprob);
+  struct Key {
+    int n, nb;
+    bool fp64;
+  };
+  std::vector<Key> keys;
+  auto add = [&](int n, bool fp64, int nb) {
+    for (const Key &k : keys)
+      if (k.n == n && k.fp64 == fp64 && sched_class(k.nb) == sched_class(nb)) return;
+    keys.push_back(Key{n, nb, fp64});
+  };
+  for (size_t g = 0; g < cfgs.size(); ++g) {
+    // launch size of the group: whole groups go to lanes when there are
+    // several, a single group is dealt out over them
+    const int nb = (lanes > 1 && cfgs.size() == 1) ? (counts[g] + lanes - 1) / lanes : counts[g];
+    add(cfgs[g].n, cfgs[g].fp64_plan || cfgs[g].conv1_fp64, nb);
+    if (cfgs[g].body) add(cfgs[g].n, cfgs[g].fp64_plan, nb);
+  }
   for (const Key &k : keys) {
+    if (st != GPF_OK) break;
     ConvSched best;
     double best_us = 1e30;
     for (const ConvSched &c : sched_candidates(k.fp64, k.n)) {

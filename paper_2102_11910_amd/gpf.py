@@ -130,6 +130,7 @@ def _load():
         "gpf_batch_create": (I, [P, I, PP]),
         "gpf_batch_destroy": (None, [P]),
         "gpf_batch_set_lanes": (I, [P, I]),
+        "gpf_batch_get_lanes": (I, [P]),
         "gpf_solve_batched": (I, [P, I, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                   C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
         "gpf_rk2_create": (I, [P, P, C.POINTER(gpf_inputs), P, P, D, I, PP]),
@@ -512,9 +513,10 @@ class Batch:
               "gpf_solve_batched")
 
     def autotune(self, plans, bodies, inputs, outputs, stream=None):
-        """Choose the convolution schedules of this workload by timing the
-        batched solve under each (gpf_autotune_batched); the outputs then
-        hold the result of the last solve."""
+        """Choose the lane count and the convolution schedules of this
+        workload by timing the batched solve under each
+        (gpf_autotune_batched); the outputs then hold the result of the last
+        solve, and self.lanes the chosen lane count."""
         k = len(plans)
         pa = (C.c_void_p * k)(*[p.h.value for p in plans])
         ba = (C.c_void_p * k)(*[(b.h.value if b is not None else None) for b in bodies])
@@ -522,6 +524,7 @@ class Batch:
         oa = (gpf_outputs * k)(*outputs)
         check(lib.gpf_autotune_batched(self.h, k, pa, ba, ia, oa, _stream_ptr(stream)),
               "gpf_autotune_batched")
+        self.lanes = int(lib.gpf_batch_get_lanes(self.h))
 
     def close(self):
         if self.h:
