@@ -462,16 +462,23 @@ def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
                        f"nv {min(c.nv for c in cases)}..{max(c.nv for c in cases)}",
            "grid_points_per_batch": gp, "lanes": batch.lanes}
     for name, fn in (("batched", batched), ("plain", plain)):
-        for _ in range(2):
+        for _ in range(3):
             fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            fn()
-        torch.cuda.synchronize()
-        el = (time.perf_counter() - t0) / reps
-        res[name] = {"ms_per_batch": 1e3 * el, "grid_points_per_s": gp / el}
-        log(f"[bench] C4 {name}: {1e3 * el:.3f} ms per 64 problems, {gp / el:.3g} GP/s")
+        # median of five rounds, so that a one-off host stall in a round
+        # does not stand for the rate
+        rounds = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            rounds.append((time.perf_counter() - t0) / reps)
+        el = sorted(rounds)[len(rounds) // 2]
+        res[name] = {"ms_per_batch": 1e3 * el, "grid_points_per_s": gp / el,
+                     "rounds_ms": [round(1e3 * r, 3) for r in rounds]}
+        log(f"[bench] C4 {name}: {1e3 * el:.3f} ms per 64 problems (median of rounds "
+            f"{[round(1e3 * r, 3) for r in rounds]}), {gp / el:.3g} GP/s")
     for o in outs:
         gpf.gpf_sync(o.status)
     res["speedup"] = res["batched"]["grid_points_per_s"] / res["plain"]["grid_points_per_s"]
