@@ -139,20 +139,26 @@ def test_schedule_arguments_checked(ctx):
 
 
 def test_batched_autotuner_tunes_the_entries_the_batch_uses(ctx):
-    """On the plate batch the tuner sets the FP64 entry (first convolution)
-    and the FP32 entry (second) of the batch's class, and the solves that
-    follow still match the oracle."""
+    """On the plate batch the tuner chooses a lane count (read back with
+    gpf_batch_get_lanes), then the FP64 entry (first convolution) and the
+    FP32 entry (second) of the class its launches fall in, and the solves
+    that follow, on those lanes, still match the oracle."""
     pb = PlateBatch(ctx)
     n = pb.cases[0].n
     for fp64 in (False, True):
         gpf.schedule_set(ctx, n, fp64, B, None)
     pb.batch.autotune([pb.plan] * B, [pb.body] * B, pb.ins, [o.struct for o in pb.outs])
-    s64, s32 = gpf.schedule_get(ctx, n, True, B), gpf.schedule_get(ctx, n, False, B)
-    say(f"[autotune batched] FP64 {s64}, FP32 {s32}")
+    # the lane count comes first; a batch of one group is dealt out over the
+    # lanes, so its launches (and the schedule class) hold ceil(B / lanes)
+    lanes = pb.batch.lanes
+    assert 1 <= lanes <= 4 and lanes == gpf.lib.gpf_batch_get_lanes(pb.batch.h)
+    nb = -(-B // lanes)
+    s64, s32 = gpf.schedule_get(ctx, n, True, nb), gpf.schedule_get(ctx, n, False, nb)
+    say(f"[autotune batched] lanes {lanes}, FP64 {s64}, FP32 {s32}")
     assert s64 in [{"rows": 0, "order": 0, "cols": 0}] + schedules(True, n)
     assert s32 in [{"rows": 0, "order": 0, "cols": 0}] + schedules(False, n)
     # classes the batch does not use are untouched
-    assert gpf.schedule_get(ctx, n, True, 1) == {"rows": 0, "order": 0, "cols": 0}
+    assert gpf.schedule_get(ctx, n, True, 32) == {"rows": 0, "order": 0, "cols": 0}
     got = pb.solve()
     table = lgf_table(n)
     for i in (0, B - 1):
@@ -161,4 +167,4 @@ def test_batched_autotuner_tunes_the_entries_the_batch_uses(ctx):
         say(f"   problem {i}: s {es:.1e} f {ef:.1e}")
         assert es <= 1e-5 and ef <= 1e-4
     for fp64 in (False, True):
-        gpf.schedule_set(ctx, n, fp64, B, None)
+        gpf.schedule_set(ctx, n, fp64, nb, None)
