@@ -280,3 +280,44 @@ def test_batch_lanes_equal_one_lane(ctx, lanes):
             worst = max(worst, rell2(b[k], a[k]) if np.any(a[k]) else float(np.max(np.abs(b[k]))))
     say(f"[lanes {lanes}] worst relL2 against one lane: {worst:.2e}")
     assert worst <= 1e-5
+
+
+def test_graph_capture_of_a_laned_batch(ctx):
+    """A batch of several groups on two lanes, captured into a graph (the
+    fork and join events become graph edges), replays the one-lane eager
+    results; several replays with eager work and synchronizations between."""
+    cases = mixed_cases()
+    solvers = [solver_for(ctx, c) for c in cases]
+    uploads = [s.upload(c) for s, c in zip(solvers, cases)]
+    inputs = [s.inputs_for(c, *u) for s, c, u in zip(solvers, cases, uploads)]
+    plans, bodies = [s.plan for s in solvers], [s.body for s in solvers]
+    outs = [s.outputs(int(u[0].numel())) for s, u in zip(solvers, uploads)]
+    one = gpf.Batch(ctx, len(cases))
+    one.solve(plans, bodies, inputs, outs)
+    for s in solvers:
+        gpf.gpf_sync(s.status)
+    eager = [snapshot(s) for s in solvers]
+    laned = gpf.Batch(ctx, len(cases), lanes=2)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        laned.solve(plans, bodies, inputs, outs, stream=stream)   # warm-up on the capture stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        laned.solve(plans, bodies, inputs, outs, stream=stream)
+    for rep in range(3):
+        for s in solvers:
+            s.psi.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        worst = 0.0
+        for s, e in zip(solvers, eager):
+            got = snapshot(s)
+            for k in e:
+                worst = max(worst, rell2(got[k], e[k]) if np.any(e[k]) else float(np.max(np.abs(got[k]))))
+        say(f"[laned graph replay {rep}] worst relL2 against one eager lane: {worst:.2e}")
+        assert worst <= 1e-5
+        # eager work between replays
+        one.solve(plans, bodies, inputs, outs)
+        for s in solvers:
+            gpf.gpf_sync(s.status)
