@@ -706,6 +706,17 @@ def main() -> int:
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom, dom_kernel), "bytes_per_launch": int(B * kb1[dom]),
                 "avg_us": round(d["avg_us"], 3)}
+    # the batched step's convolutions as a whole (all row and column passes
+    # of both): algorithmic bytes over the event-timed time of those passes
+    conv_cls = [k for k in ("rows_fwd", "cols", "rows_inv", "rows_fwd64", "cols64", "rows_inv64")
+                if k in per_kernel]
+    conv_bytes = sum(B * kb1[k] for k in conv_cls)
+    conv_us = sum(per_kernel[k]["avg_us"] for k in conv_cls)
+    conv_batched = {"passes": conv_cls, "bytes_per_step": int(conv_bytes), "us_per_step": round(conv_us, 3),
+                    "GBps": round(conv_bytes / (conv_us * 1e-6) / 1e9, 1),
+                    "frac": round(conv_bytes / (conv_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"[bench] batched convolutions: {conv_bytes / 1e6:.1f} MB in {conv_us:.1f} us, "
+        f"frac {conv_batched['frac']:.3f} of HBM peak")
     log("[bench] kernels (batched): " + json.dumps(
         {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_kernel.items()}))
 
@@ -741,6 +752,7 @@ def main() -> int:
         "schedules": tuned,
         "value_with_kernel_events": B * n * n * K / wall_b,
         "roofline": roofline,
+        "convolution_batched": conv_batched,
         "kernels": {k: {"avg_us": round(v["avg_us"], 3), "GBps": round(v["GBps"], 1),
                         "launches": v["launches"]} for k, v in per_kernel.items()},
     }
