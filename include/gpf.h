@@ -404,8 +404,9 @@ void gpf_server_destroy(gpf_server *srv);
  * doubles, device) are the vortex positions, updated in place by each step;
  * in->d_gv holds the strengths; in->d_xv, in->d_yv are ignored.  With
  * use_graph = 1 one step is captured once into a HIP graph (two solves and
- * two position updates) and every step replays it; the captured descriptors
- * stay reserved until gpf_rk2_destroy.  The object owns its workspace, so
+ * two position updates) and every step replays it; the descriptor slots of
+ * the plan that the capture took stay reserved until gpf_rk2_destroy, which
+ * releases them (a failed capture releases them at once).  The object owns its workspace, so
  * other calls on the same plan (which may grow the plan's workspace) leave
  * the captured step valid, and the field, velocity, sheet and status buffers
  * of the last stage (gpf_rk2_fields). */
@@ -422,9 +423,12 @@ gpf_status gpf_rk2_run(gpf_rk2 *rk, int nsteps, void *hip_stream);
 gpf_status gpf_rk2_fields(const gpf_rk2 *rk, const void **d_psi, const double **d_u,
                           const double **d_v, const double **d_f,
                           const double **d_scalars, unsigned int **d_status);
+/* Waits for the replays enqueued by the last gpf_rk2_run (replays enqueued
+ * earlier on other streams must be complete), then frees the object and
+ * returns its descriptor slots to the plan.  Destroy before the plan. */
 void gpf_rk2_destroy(gpf_rk2 *rk);
 
-/* Vortex shedding with forward Euler steps (Sec. 2.4.1: new vortices go one
+/* Vortex shedding with forward Euler steps (Sec. 2.4.2: new vortices go one
  * third of the way from the edge to the last vortex released there, and the
  * vortices move with forward Euler; Sec. 2.5 for edge bounds).  Each step:
  *   1. places one new vortex per body edge k_j, at e + (z_last - e)/3, e the

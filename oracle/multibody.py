@@ -185,7 +185,7 @@ class MultiShedState:
 
 def shed_step_multi(p: MultiProblem, body: Body, part, st: MultiShedState, dt: float, first,
                     table=None):
-    """One forward Euler shedding step of several bodies (Sec. 2.4.1 with the
+    """One forward Euler shedding step of several bodies (Sec. 2.4.2 with the
     rows of Sec. 2.7): every edge of a shedding body places a new vortex as
     for one body (a third of the way to its last release, or at the edge
     point plus first[i] before the first), the solve gives their strengths,

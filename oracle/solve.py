@@ -42,7 +42,7 @@ Modes
 * ``none``         no body: s = s*.
 
 Time stepping: ``rk2_step`` (explicit midpoint, fixed modes) and
-``shed_step`` (forward Euler with one new vortex per edge, Sec. 2.4.1).
+``shed_step`` (forward Euler with one new vortex per edge, Sec. 2.4.2).
 
 E_s s* here equals -E_s L^-1 w of the paper's formulas.
 """
@@ -228,7 +228,7 @@ class ShedState:
 
 
 def shed_step(p: Problem, body: Body, st: ShedState, dt: float, first, table=None):
-    """One forward Euler step of vortex shedding (Sec. 2.4.1; Sec. 2.5 with
+    """One forward Euler step of vortex shedding (Sec. 2.4.2; Sec. 2.5 with
     edge bounds).
 
     New vortex j goes one third of the way from edge point k_j to the

@@ -1488,9 +1488,15 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
 // ---------------------------------------------------------------------------
 
 gpf_rk2::~gpf_rk2() {
+  // the ring slots the graph replays are released once its last replay is done
+  if (done) {
+    (void)hipEventSynchronize(done);
+    (void)hipEventDestroy(done);
+  }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cap) (void)hipStreamDestroy(cap);
+  for (int k : held) plan->ring.unpin(k);
 }
 
 namespace gpf {
@@ -1577,7 +1583,10 @@ gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs
   }
   if (rk->use_graph) {
     GPF_HIP(hipStreamCreateWithFlags(&rk->cap, hipStreamNonBlocking));
+    GPF_HIP(hipEventCreateWithFlags(&rk->done, hipEventDisableTiming));
     // capture one step; descriptors pushed while capturing stay reserved
+    // (rk->held) until the handle is destroyed
+    const std::vector<char> pinned_before = plan->ring.pinned;
     GPF_HIP(hipStreamBeginCapture(rk->cap, hipStreamCaptureModeThreadLocal));
     gpf_status st;
     {
@@ -1586,9 +1595,11 @@ gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs
     }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(rk->cap, &g);
+    for (int k = 0; k < plan->ring.slots; ++k)
+      if (plan->ring.pinned[k] && !pinned_before[k]) rk->held.push_back(k);
     if (st != GPF_OK) {
       if (g) (void)hipGraphDestroy(g);
-      return st;
+      return st;   // ~gpf_rk2 releases the slots: nothing was replayed
     }
     GPF_HIP(e);
     rk->graph = g;
@@ -1610,6 +1621,7 @@ gpf_status gpf_rk2_run(gpf_rk2 *rk, int nsteps, void *hip_stream) {
       GPF_TRY(rk2_enqueue(rk, s));
     }
   }
+  if (rk->use_graph && nsteps > 0) GPF_HIP(hipEventRecord(rk->done, s));
   return GPF_OK;
 }
 

@@ -96,7 +96,8 @@ struct TimerScope {
 // Ring of descriptor slots: host staging in pinned memory, copied to device
 // memory on the caller's stream.  A slot is reused only after the event
 // recorded behind its copy has completed; slots taken while the stream is
-// being captured into a graph are never reused.
+// being captured into a graph stay reserved until unpin() (called by the
+// owner of the graph once no replay can still read them).
 struct DescRing {
   int slots = 0;
   size_t slot_bytes = 0;
@@ -111,6 +112,10 @@ struct DescRing {
   ~DescRing();
   gpf_status init(int nslots, size_t bytes_per_slot);
   gpf_status push(const void *src, size_t bytes, hipStream_t s, void **dptr);
+  void unpin(int slot) {
+    pinned[slot] = 0;
+    busy[slot] = 0;
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -476,5 +481,7 @@ struct gpf_rk2 {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<int> held;          // descriptor-ring slots the captured step replays
+  hipEvent_t done = nullptr;      // recorded behind the last replay
   ~gpf_rk2();
 };

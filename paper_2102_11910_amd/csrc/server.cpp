@@ -283,8 +283,15 @@ gpf_status gpf_server_wait(gpf_server *srv, unsigned long long request_id, doubl
   std::unique_lock<std::mutex> lk(srv->mu);
   auto it = srv->states.find(request_id);
   if (it == srv->states.end()) return gpf::fail(GPF_E_INVALID, "gpf_server_wait: unknown request");
-  srv->cv_done.wait(lk, [&] { return srv->states[request_id].done; });
+  // another thread may poll the same id to completion and erase it: stop
+  // waiting when the entry is gone (never re-insert it)
+  srv->cv_done.wait(lk, [&] {
+    auto jt = srv->states.find(request_id);
+    return jt == srv->states.end() || jt->second.done;
+  });
   it = srv->states.find(request_id);
+  if (it == srv->states.end())
+    return gpf::fail(GPF_E_INVALID, "gpf_server_wait: the request was collected by another caller");
   if (latency_s) *latency_s = it->second.latency;
   const gpf_status st = it->second.st;
   srv->states.erase(it);

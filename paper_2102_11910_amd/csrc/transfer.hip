@@ -429,7 +429,7 @@ __global__ void k_axpy2(int nv, const double *__restrict__ x, const double *__re
 }
 
 // Shedding step, before the solve: new vortex j goes one third of the way
-// from edge point e_j to the last vortex that edge released (Sec. 2.4.1),
+// from edge point e_j to the last vortex that edge released (Sec. 2.4.2),
 // or to e_j + first_j before the first release; appended with strength 0.
 __global__ void k_shed_place(ShedGeom sg, int nv, const int *__restrict__ last, double *x,
                              double *y, double *g) {

@@ -143,3 +143,35 @@ def test_rk2_graph_after_plan_workspace_grows(ctx):
     d = step_both(3)
     say(f"[rk2 workspace] after the growth: max |dx| graph vs eager = {d:.2e}")
     assert d <= 1e-9
+
+
+def test_rk2_destroy_returns_descriptor_slots(ctx):
+    """Each captured step holds descriptor slots of the plan until the
+    handle is destroyed: 40 create/destroy cycles on one plan (more than its
+    ring could hold if they leaked) leave plain solves working, and the last
+    one matches the oracle."""
+    from oracle.solve import solve as oracle_solve
+    case = wl.random_case(45, 128, 2.0 / 128, 200, surface="ellipse")
+    dt = 0.05 * case.dx
+    plan, body, X, Y, G, inp = make(ctx, case, flags=gpf.GPF_FP64)
+    for k in range(40):
+        Xk, Yk = X.clone(), Y.clone()
+        rk = gpf.Rk2(plan, body, inp, Xk, Yk, dt, use_graph=True)
+        if k % 2:
+            rk.run(1)
+        rk.close()
+    say("[rk2 slots] 40 graph objects created and destroyed on one plan")
+    psi = torch.empty((case.n, case.n), dtype=plan.field_dtype, device=DEV)
+    u = torch.empty(case.nv, dtype=torch.float64, device=DEV)
+    v = torch.empty_like(u)
+    f = torch.empty(body.ns, dtype=torch.float64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    out = gpf.make_outputs(psi, u, v, f=f, status=st)
+    gpf.gpf_solve(plan, body, inp, out)
+    gpf.gpf_sync(st)
+    torch.cuda.synchronize()
+    ref = oracle_solve(problem_of(case), body_of(case))
+    es = rell2(psi.double().cpu().numpy(), ref.s)
+    ef = rell2(f.cpu().numpy(), ref.f)
+    say(f"[rk2 slots] plain solve after the cycles: relL2 s {es:.2e}, f {ef:.2e}")
+    assert es <= 1e-10 and ef <= 1e-8

@@ -1,5 +1,5 @@
 """Shedding with forward Euler steps on the GPU (gpf_shed_*), against the
-oracle's shedding step (Sec. 2.4.1 insertion rule, Sec. 2.5 edge bounds).
+oracle's shedding step (Sec. 2.4.2 insertion rule, Sec. 2.5 edge bounds).
 
 Parity is per step: the oracle advances the GPU's own state by one step,
 and positions, strengths and velocities are compared, so that the chaotic

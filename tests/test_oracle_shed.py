@@ -1,4 +1,4 @@
-"""Pins of the oracle's shedding loop (forward Euler, Sec. 2.4.1; edge
+"""Pins of the oracle's shedding loop (forward Euler, Sec. 2.4.2; edge
 bounds of Sec. 2.5).
 
 Every step is one pinned solve in the shedding mode (test_oracle_solve);
