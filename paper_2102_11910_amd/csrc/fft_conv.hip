@@ -101,7 +101,7 @@ constexpr int kE = 16;  // values per lane
 
 template <int N> struct Plan {
   static constexpr int TPS = N / kE;          // lanes per sequence
-  static constexpr int SEQ = N <= 256 ? 8 : (N == 512 ? 4 : 2);
+  static constexpr int SEQ = N <= 256 ? 8 : (N == 512 ? 4 : (N <= 2048 ? 2 : 1));
   static constexpr int WGT = TPS * SEQ;        // threads per workgroup
   static constexpr int LDS_SEQ = N + N / 16;   // padded elements per sequence
 };
@@ -168,7 +168,7 @@ template <int N> __host__ __device__ constexpr int tw_regs() {
 // factors stay within a few ulps), which keeps its register count, and with
 // it the occupancy of the FP64 passes, down.
 template <class T, int N> __host__ __device__ constexpr bool tw_in_regs() {
-  return N <= 1024 && !std::is_same<T, double>::value;
+  return N <= 4096 && !std::is_same<T, double>::value;
 }
 
 // x_r *= w^r (r = 1..R-1) for w the first twiddle of the butterfly
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(N / kE) void k_cols_conv_split(const ConvDesc *__re
 // pass 3: rows, two half spectra -> two real rows, gauge epilogue
 // ---------------------------------------------------------------------------
 template <class T, int N, bool WIDE>
-__global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_inv(const ConvDesc *__restrict__ cd,
+__global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT), (std::is_same<T, float>::value ? 4 : 1)) void k_rows_inv(const ConvDesc *__restrict__ cd,
                                                                  int remap, int band) {
   using V = typename CT<T>::V;
   using V2 = typename CT<T>::V2;
