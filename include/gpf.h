@@ -493,6 +493,21 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv,
 gpf_status gpf_convolve(gpf_plan *plan, const void *d_w, void *d_s,
                         double gamma_src, void *hip_stream);
 
+/* gpf_convolve for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and result as gpf_convolve; calls no hipMalloc,
+ * hipFree or other allocating routine and enqueues no host-to-device copy.
+ * The (n+1) x n complex intermediate and the launch descriptor live in a
+ * fixed device array of 32.8 MiB per device (held until the process ends),
+ * whose address is taken when a context is created on the device.  Limit:
+ * FP32 plans up to n = 2048, FP64 plans up to n = 1024; larger grids return
+ * GPF_E_UNSUPPORTED.  Every call on one device shares that array, so calls
+ * that overlap on one device (two streams, two threads) race: serialize
+ * them.  d_w and d_s belong to the caller (n*n of the plan's field type, may
+ * alias); nothing of the array needs to be cleared between calls. */
+gpf_status gpf_convolve_noalloc(gpf_plan *plan, const void *d_w, void *d_s,
+                                double gamma_src, void *hip_stream);
+
 /* r = E_s s at the body's surface points (Sec. 2.2.1); d_r: ns doubles. */
 gpf_status gpf_interpolate_surface(const gpf_body *body, const void *d_s,
                                    double *d_r, void *hip_stream);

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpf.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["api.cpp", "server.cpp", "lgf_host.cpp", "fft_conv.hip", "transfer.hip", "schur.hip",
-           "pressure.hip"]
+           "pressure.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

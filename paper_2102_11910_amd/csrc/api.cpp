@@ -680,6 +680,8 @@ gpf_status gpf_ctx_create(int device, gpf_ctx **out) {
   GPF_HIP(hipSetDevice(device));
   hipDeviceProp_t prop;
   GPF_HIP(hipGetDeviceProperties(&prop, device));
+  // the allocation-free entry point's scratch address on this device
+  GPF_TRY(noalloc_init(device));
   auto *c = new gpf_ctx;
   c->device = device;
   c->num_cu = prop.multiProcessorCount;

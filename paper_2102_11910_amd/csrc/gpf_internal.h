@@ -249,6 +249,10 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
 template <class Tin, class T>
 hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t s,
                            const ConvSched &sc);
+// the fixed device scratch of gpf_convolve_noalloc: its address on `device`
+// (which must be current) is taken once; called when a context is created
+gpf_status noalloc_init(int device);
+size_t noalloc_scratch_bytes();
 template <class T>
 hipError_t launch_surface_rhs(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s);
 template <class T>

@@ -117,6 +117,7 @@ def _load():
         "gpf_solve": (I, [P, P, C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
         "gpf_regularize_vortices": (I, [P, I, P, P, P, P, I, P, P]),
         "gpf_convolve": (I, [P, P, P, D, P]),
+        "gpf_convolve_noalloc": (I, [P, P, P, D, P]),
         "gpf_interpolate_surface": (I, [P, P, P, P]),
         "gpf_vortex_velocity": (I, [P, P, I, P, P, D, D, P, P, P, P]),
         "gpf_lgf_table": (I, [I, DP]),
@@ -476,6 +477,11 @@ def gpf_regularize_vortices(plan: Plan, X, Y, G, w, accumulate=False, status=Non
 def gpf_convolve(plan: Plan, w, s, gamma_src: float, stream=None):
     check(lib.gpf_convolve(plan.h, _ptr(w), _ptr(s), float(gamma_src), _stream_ptr(stream)),
           "gpf_convolve")
+
+
+def gpf_convolve_noalloc(plan: Plan, w, s, gamma_src: float, stream=None):
+    check(lib.gpf_convolve_noalloc(plan.h, _ptr(w), _ptr(s), float(gamma_src),
+                                   _stream_ptr(stream)), "gpf_convolve_noalloc")
 
 
 def gpf_interpolate_surface(body: Body, s, r, stream=None):
