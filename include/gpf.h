@@ -330,11 +330,23 @@ gpf_status gpf_batch_set_lanes(gpf_batch *batch, int lanes);
  * gpf_batch_set_lanes or chosen by gpf_autotune_batched); 0 for NULL. */
 int gpf_batch_get_lanes(const gpf_batch *batch);
 
+/* merge = 1 (the default) lets gpf_solve_batched run a batch of several
+ * grid sizes merged (see below); 0 makes it run such a batch group by group
+ * on its lanes, the path the merged one is compared with. */
+gpf_status gpf_batch_set_merge(gpf_batch *batch, int merge);
+
 /* Solve nprob independent problems (each as in gpf_solve; bodies may be
- * NULL or hold NULL for GPF_NOBODY problems).  Problems are grouped by grid
- * size and precision; each group runs as one launch sequence whose kernels
- * cover all of its problems (one grid dimension indexes the problem), so
- * that small problems share launches instead of paying one launch each.
+ * NULL or hold NULL for GPF_NOBODY problems).  A batch whose problems have
+ * one-part bodies and FP32 fields on grids of n = 64 .. 2048 (any mix of
+ * sizes, and of FP32 and FP64 first convolutions) runs merged: every stage
+ * of the solve is one launch per precision of the first convolution over all
+ * grid sizes, and the FP32 transform passes take their blocks from one work
+ * list ordered by decreasing grid size (the largest transforms start first,
+ * the small ones fill in behind them).  Otherwise problems are grouped by
+ * grid size and precision and each group runs as one launch sequence whose
+ * kernels cover all of its problems (one grid dimension indexes the
+ * problem), on the batch's lanes.  Either way small problems share launches
+ * instead of paying one launch each.
  * Problem i uses workspace i of the batch; plans and bodies may repeat.
  * Every problem needs its own output buffers and status word (a status word
  * may be shared).  Asynchronous on hip_stream; the batch serves one stream

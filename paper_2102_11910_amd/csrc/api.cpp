@@ -263,7 +263,7 @@ gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns, int 
     GPF_TRY(s64.alloc(cells * 8));
   }
   GPF_TRY(zeroed(aux, AUX_BYTES));
-  GPF_TRY(part.alloc(sizeof(double) * 4 * (size_t)kPartStride));
+  GPF_TRY(part.alloc(sizeof(double) * 5 * (size_t)kPartStride));
   if (band > 0) GPF_TRY(xb.alloc((size_t)(nn + 1) * band * 16));   // complex FP64 at most
   if (nns > 0) {
     const size_t cols = 1 + GPF_MAX_EDGES;
@@ -580,6 +580,136 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
                                                    shared ? probs[0].body->sinv.as<double>() : nullptr, s);
+}
+
+// A batch can run merged when its problems differ only in grid size and in
+// the precision of the first convolution: bodies of one part, FP32 fields,
+// grids the multi-size transforms cover (n from 64 to 2048).
+bool mergeable(const GroupCfg &c) {
+  return c.body && !c.parts && !c.fp64_plan && c.n >= 64 && c.n <= 2048;
+}
+
+// Bytes of the descriptor block of a merged batch of nb problems: the
+// problem and convolution descriptors, then the work tables of the
+// multi-size passes (three per convolution, two convolutions, two classes).
+size_t merged_block_bytes(int nb) {
+  return ((size_t)nb * kProblemDescBytes + 15) / 16 * 16 + 9 * (size_t)nb * sizeof(MultiEntry);
+}
+
+// Every stage of the solve as one launch per precision class over problems
+// of all grid sizes (class A: FP32 first convolution, class B: FP64 first
+// convolution).  The transforms of FP32 fields are the multi-size passes,
+// whose work lists take the largest grids first; FP64 first convolutions
+// run per grid size (in order of decreasing n).
+gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, hipStream_t s) {
+  const int nb = (int)probs.size();
+  // class A before class B, each by decreasing n (stable: input order kept)
+  std::stable_sort(probs.begin(), probs.end(), [](const ProblemRef &a, const ProblemRef &b) {
+    const GroupCfg ca = config_of(a), cb = config_of(b);
+    if (ca.conv1_fp64 != cb.conv1_fp64) return !ca.conv1_fp64;
+    return ca.n > cb.n;
+  });
+  int na = 0;
+  while (na < nb && !config_of(probs[na]).conv1_fp64) ++na;
+  const int nbb = nb - na;
+  std::vector<char> blk(merged_block_bytes(nb), 0);
+  ProbDesc *pd = reinterpret_cast<ProbDesc *>(blk.data());
+  ConvDesc *c1 = reinterpret_cast<ConvDesc *>(blk.data() + nb * sizeof(ProbDesc));
+  ConvDesc *c2 = c1 + nb;
+  const size_t tab_off = ((size_t)nb * kProblemDescBytes + 15) / 16 * 16;
+  MultiEntry *tab = reinterpret_cast<MultiEntry *>(blk.data() + tab_off);
+  struct ClassInfo {
+    int nv_max = 0, ns_max = 0, m_max = 0, n_max = 0;
+  } ca, cbi;
+  bool impulse = false;
+  for (int i = 0; i < nb; ++i) {
+    const GroupCfg cfg = config_of(probs[i]);
+    describe(probs[i], cfg, pd[i], c1[i], c2[i]);
+    ClassInfo &ci = i < na ? ca : cbi;
+    ci.nv_max = std::max(ci.nv_max, pd[i].nv);
+    ci.ns_max = std::max(ci.ns_max, pd[i].ns);
+    ci.m_max = std::max(ci.m_max, pd[i].sv.m);
+    ci.n_max = std::max(ci.n_max, cfg.n);
+    impulse = impulse || pd[i].imp_out != nullptr;
+  }
+  // work tables: pass kind per table (0 rows forward, 1 columns, 2 band rows
+  // inverse, 3 all rows inverse) over problems [lo, hi) of `cd`
+  int used = 0;
+  auto make_table = [&](int kind, const ConvDesc *cd, int lo, int hi, MultiPass *mp) {
+    MultiEntry *e = tab + used;
+    int first = 0;
+    for (int i = lo; i < hi; ++i) {
+      const int n = pd[i].n;
+      int lg = 0;
+      while ((1 << lg) < n) ++lg;
+      e[i - lo].first = first;
+      e[i - lo].prob = i - lo;
+      e[i - lo].logn = lg;
+      e[i - lo].band = kind == 2 ? 1 : 0;
+      first += multi_blocks(kind == 3 ? 0 : kind, n, cd[i]);
+    }
+    mp->nprob = hi - lo;
+    mp->total = first;
+    mp->e = reinterpret_cast<const MultiEntry *>(tab_off + used * sizeof(MultiEntry));  // offset for now
+    used += hi - lo;
+  };
+  MultiPass mp1a[3], mp2a[3], mp2b[3];
+  if (na > 0) {
+    make_table(0, c1, 0, na, &mp1a[0]);
+    make_table(1, c1, 0, na, &mp1a[1]);
+    make_table(2, c1, 0, na, &mp1a[2]);
+    make_table(0, c2, 0, na, &mp2a[0]);
+    make_table(1, c2, 0, na, &mp2a[1]);
+    make_table(3, c2, 0, na, &mp2a[2]);
+  }
+  if (nbb > 0) {
+    make_table(0, c2, na, nb, &mp2b[0]);
+    make_table(1, c2, na, nb, &mp2b[1]);
+    make_table(3, c2, na, nb, &mp2b[2]);
+  }
+  void *dev = nullptr;
+  GPF_TRY(ring.push(blk.data(), blk.size(), s, &dev));
+  char *base = static_cast<char *>(dev);
+  auto fix = [&](MultiPass *mp) {   // table offsets -> device addresses
+    for (int k = 0; k < 3; ++k) mp[k].e = reinterpret_cast<const MultiEntry *>(base + (size_t)mp[k].e);
+  };
+  if (na > 0) {
+    fix(mp1a);
+    fix(mp2a);
+  }
+  if (nbb > 0) fix(mp2b);
+  const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
+  const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
+  const ConvDesc *dc2 = dc1 + nb;
+  gpf_ctx *ctx = probs[0].plan->ctx;
+  // R_v
+  if (na > 0) GPF_HIP(launch_scatter_vortices<float>(dpd, na, ca.n_max, ca.nv_max, s));
+  if (nbb > 0) GPF_HIP(launch_scatter_vortices<double>(dpd + na, nbb, cbi.n_max, cbi.nv_max, s));
+  // first convolution (surface band only)
+  if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc1, mp1a, s)));
+  for (int i = na; i < nb;) {
+    int j = i;
+    int band = 0;
+    while (j < nb && pd[j].n == pd[i].n) {
+      band = std::max(band, (c1[j].row_hi | 15) - (c1[j].row_lo & ~15) + 1);
+      ++j;
+    }
+    const ConvSched sc = ctx->sched_for(pd[i].n, true, j - i);
+    GPF_HIP((launch_convolve<double, double>(pd[i].n, dc1 + i, j - i, xcds, band, s, sc)));
+    i = j;
+  }
+  // surface right-hand sides, Schur complement and constraints, R_s f
+  if (na > 0) GPF_HIP(launch_surface_rhs<float>(dpd, na, ca.ns_max, ca.m_max, s));
+  if (nbb > 0) GPF_HIP(launch_surface_rhs<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
+  if (na > 0) GPF_HIP(launch_schur_apply<float>(dpd, na, ca.ns_max, ca.m_max, s));
+  if (nbb > 0) GPF_HIP(launch_schur_apply<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
+  // final convolution of all vorticity
+  if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc2, mp2a, s)));
+  if (nbb > 0) GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, s)));
+  // velocities of every problem, then impulses where asked
+  GPF_HIP(launch_vortex_velocity<float>(dpd, nb, std::max(ca.nv_max, cbi.nv_max), s));
+  if (impulse) GPF_HIP(launch_impulse(dpd, nb, s));
+  return GPF_OK;
 }
 
 gpf_status validate(const gpf_plan *plan, const gpf_body *body, const gpf_inputs *in,
@@ -1231,6 +1361,7 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   pd.yv = d_yv;
   pd.gv = d_gv;
   pd.w = d_w;
+  pd.w_accumulate = accumulate ? 1 : 0;
   pd.aux = plan->ws.aux.as<double>();
   pd.partials = plan->ws.part.as<double>();
   pd.bin_cnt = plan->ws.bin_cnt.as<int>();
@@ -1374,7 +1505,7 @@ gpf_status gpf_batch_create(gpf_ctx *ctx, int max_problems, gpf_batch **out) {
   b->max_problems = max_problems;
   b->ws.resize(max_problems, nullptr);
   for (auto &w : b->ws) w = new gpf_workspace;
-  GPF_TRY(b->ring.init(16, (size_t)max_problems * kProblemDescBytes));
+  GPF_TRY(b->ring.init(16, merged_block_bytes(max_problems)));
   *out = b.release();
   return GPF_OK;
 }
@@ -1397,6 +1528,12 @@ gpf_status gpf_batch_set_lanes(gpf_batch *batch, int lanes) {
 }
 
 int gpf_batch_get_lanes(const gpf_batch *batch) { return batch ? batch->lanes : 0; }
+
+gpf_status gpf_batch_set_merge(gpf_batch *batch, int merge) {
+  if (!batch) return fail(GPF_E_INVALID, "gpf_batch_set_merge: null batch");
+  batch->merge = merge ? 1 : 0;
+  return GPF_OK;
+}
 
 gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
                              const gpf_body *const *bodies, const gpf_inputs *inputs,
@@ -1449,7 +1586,13 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
     groups.push_back(std::move(grp));
   }
   const int ng = (int)groups.size();
-  if (lanes == 1) {
+  bool merge = batch->merge && ng >= 2 && nprob <= kMaxMultiProblems;
+  for (int g = 0; g < ng && merge; ++g) merge = mergeable(cfgs[g]);
+  if (merge) {
+    // one launch per stage and precision class over every grid size; the
+    // lanes, if any, wait for nothing and join at once
+    GPF_TRY(run_merged(refs, batch->ring, batch->ctx->xcds, s));
+  } else if (lanes == 1) {
     for (int g = 0; g < ng; ++g) GPF_TRY(run_group(cfgs[g], groups[g], batch->ring, batch->ctx->xcds, s));
   } else if (ng >= 2) {
     // several groups: whole groups to lanes, the costliest first to the

@@ -111,7 +111,14 @@ template <int N> struct Plan {
 // 128-byte runs within about 72 KB of LDS (two workgroups per CU).
 // The wide shape suits launches with many row blocks (batches); single
 // problems and row-pruned passes keep the narrow shape for more workgroups.
-template <class T, int N, bool WIDE> struct RowPlan {
+// Shapes of a pass: narrow and wide as above; multi = the 256-thread
+// workgroup of the launches that cover problems of several grid sizes at once
+// (N / 16 lanes per sequence, 4096 / N sequences: the same LDS footprint for
+// every N).
+constexpr int kNarrow = 0, kWide = 1, kMulti = 2;
+constexpr int kMultiThreads = 256;
+
+template <class T, int N, int SH> struct RowPlan {
   static constexpr int TPS = N / kE;
   static constexpr int LDS_SEQ = N + N / 16;
   static constexpr int ELEM = 2 * (int)sizeof(T);
@@ -119,7 +126,8 @@ template <class T, int N, bool WIDE> struct RowPlan {
     while (s > 1 && s * LDS_SEQ * ELEM > 72 * 1024) s /= 2;
     return s;
   }
-  static constexpr int SEQ = WIDE ? fit(64 / ELEM) : Plan<N>::SEQ;
+  static constexpr int SEQ = SH == kMulti ? kMultiThreads / TPS
+                                          : (SH == kWide ? fit(64 / ELEM) : Plan<N>::SEQ);
   static constexpr int WGT = TPS * SEQ;
   // a workgroup's run of each k-major row fills whole 128-byte lines
   static constexpr bool FULL_LINES = 2 * SEQ * ELEM >= 128;
@@ -355,19 +363,17 @@ __device__ __forceinline__ int xcd_block(int remap) {
 // ---------------------------------------------------------------------------
 // pass 1: rows, real -> half spectrum, stored k-major
 // ---------------------------------------------------------------------------
-template <class Tin, class T, int N, bool WIDE>
-__global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_fwd(const ConvDesc *__restrict__ cd,
-                                                                 int remap) {
+// row-pair block `blk` of one problem (rows 2 SEQ blk ..), LDS of SEQ rows
+template <class Tin, class T, int N, int SH>
+__device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, typename CT<T>::V *lds) {
   using V = typename CT<T>::V;
-  using P = RowPlan<T, N, WIDE>;
+  using P = RowPlan<T, N, SH>;
   constexpr int n = N / 2;
-  __shared__ V lds[P::SEQ * P::LDS_SEQ];
-  const ConvDesc &C = cd[blockIdx.y];
   Tin *__restrict__ w = static_cast<Tin *>(C.in);
   V *__restrict__ X = static_cast<V *>(C.X);
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
-  const int j0 = xcd_block(remap) * 2 * P::SEQ;
+  const int j0 = blk * 2 * P::SEQ;
 
   const int q = tid / P::TPS, lane = tid % P::TPS;
   V x[kE];
@@ -423,21 +429,28 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT)) void k_rows_fwd(const C
   }
 }
 
+template <class Tin, class T, int N, bool WIDE>
+__global__ __launch_bounds__((RowPlan<T, N, WIDE ? kWide : kNarrow>::WGT)) void k_rows_fwd(
+    const ConvDesc *__restrict__ cd, int remap) {
+  using P = RowPlan<T, N, WIDE ? kWide : kNarrow>;
+  __shared__ typename CT<T>::V lds[P::SEQ * P::LDS_SEQ];
+  rows_fwd_body<Tin, T, N, WIDE ? kWide : kNarrow>(cd[blockIdx.y], xcd_block(remap), lds);
+}
+
 // ---------------------------------------------------------------------------
 // pass 2: columns, forward FFT x spectrum x inverse FFT
 // ---------------------------------------------------------------------------
-template <class T, int N>
-__global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__restrict__ cd) {
+// column block `blk` of one problem: columns SEQ blk .. (SEQ sequences)
+template <class T, int N, int SEQ>
+__device__ __forceinline__ void cols_body(const ConvDesc &C, int blk, typename CT<T>::V *lds) {
   using V = typename CT<T>::V;
-  using P = Plan<N>;
+  using P = Plan<N>;   // lanes per sequence and padded sequence length
   constexpr int n = N / 2;
-  __shared__ V lds[P::SEQ * P::LDS_SEQ];
-  const ConvDesc &C = cd[blockIdx.y];
   V *__restrict__ X = static_cast<V *>(C.X);
   const T *__restrict__ spec = static_cast<const T *>(C.spec);
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
-  const int c0 = blockIdx.x * P::SEQ;
+  const int c0 = blk * SEQ;
   const int q = tid / P::TPS, lane = tid % P::TPS;
   const int k1 = min(c0 + q, n);   // blocks past the last column redo it and store nothing
   V *col = X + (size_t)k1 * n;
@@ -480,6 +493,13 @@ __global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__re
       if (j >= lo && j <= hi) dst[j] = x[k];
     }
   }
+}
+
+template <class T, int N>
+__global__ __launch_bounds__(Plan<N>::WGT) void k_cols_conv(const ConvDesc *__restrict__ cd) {
+  using P = Plan<N>;
+  __shared__ typename CT<T>::V lds[P::SEQ * P::LDS_SEQ];
+  cols_body<T, N, P::SEQ>(cd[blockIdx.y], blockIdx.x, lds);
 }
 
 // FP64 column pass for N >= 1024: one sequence per workgroup (N/16 lanes)
@@ -607,22 +627,24 @@ __global__ __launch_bounds__(N / kE) void k_cols_conv_split(const ConvDesc *__re
 // ---------------------------------------------------------------------------
 // pass 3: rows, two half spectra -> two real rows, gauge epilogue
 // ---------------------------------------------------------------------------
-template <class T, int N, bool WIDE>
-__global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT), (std::is_same<T, float>::value ? 4 : 1)) void k_rows_inv(const ConvDesc *__restrict__ cd,
-                                                                 int remap, int band) {
+// row-pair block `blk` of one problem; band: blocks count from the 16-row
+// group of row_lo, and rows past the band's last 16-row group (a workgroup
+// of more than 16 rows can reach them) are neither read nor written
+template <class T, int N, int SH>
+__device__ __forceinline__ void rows_inv_body(const ConvDesc &C, int blk, int band,
+                                              typename CT<T>::V *lds) {
   using V = typename CT<T>::V;
   using V2 = typename CT<T>::V2;
-  using P = RowPlan<T, N, WIDE>;
+  using P = RowPlan<T, N, SH>;
   constexpr int n = N / 2;
-  __shared__ V lds[P::SEQ * P::LDS_SEQ];
-  const ConvDesc &C = cd[blockIdx.y];
   T *__restrict__ s = static_cast<T *>(C.out);
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
   // band: the grid covers the rows from the 16-row group of row_lo on, read
   // from the compact band when the column pass stored one
   const int lo = band ? C.row_lo & ~15 : 0;
-  const int j0 = lo + xcd_block(remap) * 2 * P::SEQ;
+  const int hi_row = band ? (C.row_hi | 15) : n - 1;
+  const int j0 = lo + blk * 2 * P::SEQ;
   if (j0 + 2 * P::SEQ <= C.row_lo || j0 > C.row_hi) return;  // rows nobody reads
   const bool compact = band && C.Xb;
   const V *__restrict__ X = compact ? static_cast<const V *>(C.Xb) - lo : static_cast<const V *>(C.X);
@@ -638,7 +660,11 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT), (std::is_same<T, float>
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
     const int idx = min(tid + it * P::WGT, ITEMS - 1);
-    abv[it] = *reinterpret_cast<const V2 *>(X + (size_t)(idx / P::SEQ) * pitch + j0 + 2 * (idx % P::SEQ));
+    if (P::SEQ * 2 > 16 && j0 + 2 * (idx % P::SEQ) > hi_row) {
+      abv[it].x = abv[it].y = abv[it].z = abv[it].w = (T)0;   // past the band
+    } else {
+      abv[it] = *reinterpret_cast<const V2 *>(X + (size_t)(idx / P::SEQ) * pitch + j0 + 2 * (idx % P::SEQ));
+    }
   }
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
@@ -667,6 +693,7 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT), (std::is_same<T, float>
   fft_seq<T, N, true, false, true, false, true>(x, lds + q * P::LDS_SEQ, wr, tw, lane);
   const T shift = (T)(C.c * (C.gamma ? C.gamma[0] : C.gamma_val));
   const int j = j0 + 2 * q;
+  if (P::SEQ * 2 > 16 && j > hi_row) return;   // past the band: nothing to store
   const size_t row = (size_t)j * n;
   if (C.add_inf) {
     // total psi: + U_inf y - V_inf x, added in FP64 before the one rounding
@@ -688,6 +715,15 @@ __global__ __launch_bounds__((RowPlan<T, N, WIDE>::WGT), (std::is_same<T, float>
   }
 }
 
+template <class T, int N, bool WIDE>
+__global__ __launch_bounds__((RowPlan<T, N, WIDE ? kWide : kNarrow>::WGT),
+                             (std::is_same<T, float>::value ? 4 : 1)) void k_rows_inv(
+    const ConvDesc *__restrict__ cd, int remap, int band) {
+  using P = RowPlan<T, N, WIDE ? kWide : kNarrow>;
+  __shared__ typename CT<T>::V lds[P::SEQ * P::LDS_SEQ];
+  rows_inv_body<T, N, WIDE ? kWide : kNarrow>(cd[blockIdx.y], xcd_block(remap), band, lds);
+}
+
 int num_cus() {
   static int cus = 0;
   if (!cus) {
@@ -706,12 +742,12 @@ template <class T, int N, bool WIDE>
 int row_remap(const ConvSched &sc, int xcds) {
   if (sc.order == 1) return 1;
   if (sc.order == 2) return xcds;
-  return RowPlan<T, N, WIDE>::FULL_LINES ? 1 : xcds;
+  return RowPlan<T, N, WIDE ? kWide : kNarrow>::FULL_LINES ? 1 : xcds;
 }
 
 template <class Tin, class T, int N, bool WIDE>
 void launch_rows_fwd(const ConvDesc *d, int nb, int xcds, const ConvSched &sc, hipStream_t st) {
-  using RP = RowPlan<T, N, WIDE>;
+  using RP = RowPlan<T, N, WIDE ? kWide : kNarrow>;
   hipLaunchKernelGGL((k_rows_fwd<Tin, T, N, WIDE>), dim3(N / 2 / (2 * RP::SEQ), nb), dim3(RP::WGT),
                      0, st, d, row_remap<T, N, WIDE>(sc, xcds));
 }
@@ -719,7 +755,7 @@ void launch_rows_fwd(const ConvDesc *d, int nb, int xcds, const ConvSched &sc, h
 template <class T, int N, bool WIDE>
 void launch_rows_inv(const ConvDesc *d, int nb, int xcds, int band, const ConvSched &sc,
                      hipStream_t st) {
-  using RP = RowPlan<T, N, WIDE>;
+  using RP = RowPlan<T, N, WIDE ? kWide : kNarrow>;
   const int rows = band > 0 ? std::min(band, N / 2) : N / 2;
   hipLaunchKernelGGL((k_rows_inv<T, N, WIDE>), dim3((rows + 2 * RP::SEQ - 1) / (2 * RP::SEQ), nb),
                      dim3(RP::WGT), 0, st, d, row_remap<T, N, WIDE>(sc, xcds), band > 0 ? 1 : 0);
@@ -734,7 +770,7 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, const ConvSch
   // wide row blocks when they still give two or more workgroups per CU
   // (ConvSched::rows 0), or as the schedule says
   const bool wide = sc.rows == 2 ||
-                    (sc.rows == 0 && (n / (2 * RowPlan<T, N, true>::SEQ)) * nb >= 2 * num_cus());
+                    (sc.rows == 0 && (n / (2 * RowPlan<T, N, kWide>::SEQ)) * nb >= 2 * num_cus());
   constexpr bool D = std::is_same<T, double>::value;
   timer_begin(D ? GPF_TK_ROWS_FWD64 : GPF_TK_ROWS_FWD, st);
   if (wide)
@@ -764,7 +800,140 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, const ConvSch
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// passes over problems of several grid sizes in one launch
+// ---------------------------------------------------------------------------
+// The launch's blocks form one work list: the table orders the problems by
+// decreasing grid size and gives each its first block, so the largest
+// transforms are dispatched first and the small ones fill in behind them as
+// workgroups retire.  (A persistent loop over a work counter was compiled
+// too: the loop around the transform bodies raised the register count from
+// 113 to 178-214, i.e. from four waves per SIMD to two, so each workgroup
+// takes one block.)  Block g belongs to the last entry whose first block is
+// <= g: every wave loads the table (up to 256 entries, four per lane), counts
+// the entries at or below g by ballots and reads the entry from its lane.
+constexpr int kMultiLds = kMultiThreads * 17;   // SEQ (N + N/16) elements for every N
+
+__device__ __forceinline__ void multi_locate(const MultiPass &mp, int *prob, int *logn, int *band,
+                                             int *blk) {
+  const int g = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  int e[4][4];
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k * 64 < mp.nprob) {
+      const int i = lane + 64 * k;
+      if (i < mp.nprob) {
+        const int4 v = *reinterpret_cast<const int4 *>(mp.e + i);
+        e[k][0] = v.x; e[k][1] = v.y; e[k][2] = v.z; e[k][3] = v.w;
+      } else {
+        e[k][0] = 0x7fffffff; e[k][1] = e[k][2] = e[k][3] = 0;
+      }
+      cnt += __popcll(__ballot(e[k][0] <= g));
+    }
+  }
+  const int idx = __builtin_amdgcn_readfirstlane(cnt - 1);
+  const int k = idx >> 6, l = idx & 63;
+  int f[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    f[c] = k == 0 ? e[0][c] : (k == 1 ? e[1][c] : (k == 2 ? e[2][c] : e[3][c]));
+  const int first = __builtin_amdgcn_readlane(f[0], l);
+  *prob = __builtin_amdgcn_readlane(f[1], l);
+  *logn = __builtin_amdgcn_readlane(f[2], l);
+  *band = __builtin_amdgcn_readlane(f[3], l);
+  *blk = g - first;
+}
+
+template <class Tin, class T>
+__global__ __launch_bounds__(kMultiThreads) void k_rows_fwd_multi(const ConvDesc *__restrict__ cd,
+                                                                  MultiPass mp) {
+  __shared__ typename CT<T>::V lds[kMultiLds];
+  int p, logn, band, blk;
+  multi_locate(mp, &p, &logn, &band, &blk);
+  const ConvDesc &C = cd[p];
+  switch (logn) {
+    case 6: rows_fwd_body<Tin, T, 128, kMulti>(C, blk, lds); break;
+    case 7: rows_fwd_body<Tin, T, 256, kMulti>(C, blk, lds); break;
+    case 8: rows_fwd_body<Tin, T, 512, kMulti>(C, blk, lds); break;
+    case 9: rows_fwd_body<Tin, T, 1024, kMulti>(C, blk, lds); break;
+    case 10: rows_fwd_body<Tin, T, 2048, kMulti>(C, blk, lds); break;
+    case 11: rows_fwd_body<Tin, T, 4096, kMulti>(C, blk, lds); break;
+    default: break;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kMultiThreads) void k_cols_multi(const ConvDesc *__restrict__ cd,
+                                                              MultiPass mp) {
+  __shared__ typename CT<T>::V lds[kMultiLds];
+  int p, logn, band, blk;
+  multi_locate(mp, &p, &logn, &band, &blk);
+  const ConvDesc &C = cd[p];
+  switch (logn) {
+    case 6: cols_body<T, 128, kMultiThreads / 8>(C, blk, lds); break;
+    case 7: cols_body<T, 256, kMultiThreads / 16>(C, blk, lds); break;
+    case 8: cols_body<T, 512, kMultiThreads / 32>(C, blk, lds); break;
+    case 9: cols_body<T, 1024, kMultiThreads / 64>(C, blk, lds); break;
+    case 10: cols_body<T, 2048, kMultiThreads / 128>(C, blk, lds); break;
+    case 11: cols_body<T, 4096, kMultiThreads / 256>(C, blk, lds); break;
+    default: break;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kMultiThreads) void k_rows_inv_multi(const ConvDesc *__restrict__ cd,
+                                                                  MultiPass mp) {
+  __shared__ typename CT<T>::V lds[kMultiLds];
+  int p, logn, band, blk;
+  multi_locate(mp, &p, &logn, &band, &blk);
+  const ConvDesc &C = cd[p];
+  switch (logn) {
+    case 6: rows_inv_body<T, 128, kMulti>(C, blk, band, lds); break;
+    case 7: rows_inv_body<T, 256, kMulti>(C, blk, band, lds); break;
+    case 8: rows_inv_body<T, 512, kMulti>(C, blk, band, lds); break;
+    case 9: rows_inv_body<T, 1024, kMulti>(C, blk, band, lds); break;
+    case 10: rows_inv_body<T, 2048, kMulti>(C, blk, band, lds); break;
+    case 11: rows_inv_body<T, 4096, kMulti>(C, blk, band, lds); break;
+    default: break;
+  }
+}
+
 }  // namespace
+
+int multi_blocks(int pass, int n, const ConvDesc &c) {
+  const int rows = 4096 / n;              // rows per workgroup (two per sequence)
+  if (pass == 1) {
+    const int seq = 2048 / n;             // columns per workgroup
+    return (n + 1 + seq - 1) / seq;
+  }
+  if (pass == 2) {                        // band of the first convolution
+    const int band = (c.row_hi | 15) - (c.row_lo & ~15) + 1;
+    return (band + rows - 1) / rows;
+  }
+  return n / rows;
+}
+
+template <class Tin, class T>
+hipError_t launch_convolve_multi(const ConvDesc *d, const MultiPass *mp, hipStream_t st) {
+  static_assert(std::is_same<T, float>::value, "multi-size passes are FP32 transforms");
+  timer_begin(GPF_TK_ROWS_FWD, st);
+  hipLaunchKernelGGL((k_rows_fwd_multi<Tin, T>), dim3(mp[0].total),
+                     dim3(kMultiThreads), 0, st, d, mp[0]);
+  timer_end(st);
+  timer_begin(GPF_TK_COLS, st);
+  hipLaunchKernelGGL((k_cols_multi<T>), dim3(mp[1].total),
+                     dim3(kMultiThreads), 0, st, d, mp[1]);
+  timer_end(st);
+  timer_begin(GPF_TK_ROWS_INV, st);
+  hipLaunchKernelGGL((k_rows_inv_multi<T>), dim3(mp[2].total),
+                     dim3(kMultiThreads), 0, st, d, mp[2]);
+  timer_end(st);
+  return hipGetLastError();
+}
+template hipError_t launch_convolve_multi<float, float>(const ConvDesc *, const MultiPass *, hipStream_t);
+template hipError_t launch_convolve_multi<double, float>(const ConvDesc *, const MultiPass *, hipStream_t);
 
 template <class Tin, class T>
 hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t st,

@@ -131,6 +131,7 @@ enum ScalarSlot {
   SC_PART_S0 = 4 + GPF_MAX_EDGES,                 // GPF_PARTS: s0_j
   SC_PART_GB = 4 + GPF_MAX_EDGES + GPF_MAX_PARTS, // GPF_PARTS: bound circulation per part
   SC_COUNT = 4 + GPF_MAX_EDGES + 2 * GPF_MAX_PARTS,
+  SC_RV_SCALE = 31,   // R_v: power-of-two scale of the fixed-point sums
   AUX_DOUBLES = 32,
   AUX_BYTES = AUX_DOUBLES * 8
 };
@@ -193,6 +194,7 @@ struct ProbDesc {
   const double *xv, *yv, *gv;
   // fields
   void *w;                      // source field (zero on entry, or the values R_v adds to)
+  int w_accumulate;             // 1: w holds values R_v adds to; 0: w is zero on entry
   const void *s1;               // result of the first convolution
   // per-problem aux: scalars and partial sums
   double *aux;
@@ -233,16 +235,37 @@ struct ProbDesc {
 // kernel launchers (asynchronous on `s`; `nb` problems, same n)
 // ---------------------------------------------------------------------------
 int scatter_blocks(int nv_max);
-// binning partials per workgroup of vortices, four planes of kPartStride:
-// sum Gamma, sum Gamma x, sum Gamma y, sum Gamma (x^2 + y^2)
+// binning partials per workgroup of vortices, five planes of kPartStride:
+// sum Gamma, sum Gamma x, sum Gamma y, sum Gamma (x^2 + y^2), sum |Gamma|
 constexpr int kMaxVortices = 1 << 22;
 constexpr int kPartStride = kMaxVortices / 256;
 int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n < 32)
 // R_v: bin and sort the vortices by tile, then one workgroup per tile sums
-// its vortices in an LDS window and adds the window to the source field
-// (which must hold zeros, or the values to add to)
+// the vortices of its 3 x 3 tile neighbourhood that reach its nodes, in
+// fixed point (order-independent, so the field is bitwise repeatable), and
+// adds them to the source field (zero, or the values to add to)
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s);
+// Launches that cover problems of several grid sizes (FP32 transforms, n from
+// 64 to 2048): entry i of a pass's table gives the first of its blocks,
+// problem `prob` (an index into the launch's ConvDesc array) and log2 n;
+// entries are ordered by decreasing n, firsts ascending.  band = 1 in the
+// last pass of a first convolution (only the band of surface rows).
+constexpr int kMaxMultiProblems = 256;
+struct MultiEntry {
+  int first, prob, logn, band;
+};
+struct MultiPass {
+  const MultiEntry *e;  // device table of nprob entries (16-byte aligned)
+  int nprob;
+  int total;            // blocks of the launch
+};
+// blocks of one problem in a multi-size pass (0 rows forward, 1 columns,
+// 2 rows inverse over the band of the descriptor, 3 rows inverse, all rows)
+int multi_blocks(int pass, int n, const ConvDesc &c);
+// the three passes of one convolution per problem; mp[0..2] the passes' tables
+template <class Tin, class T>
+hipError_t launch_convolve_multi(const ConvDesc *d, const MultiPass *mp, hipStream_t s);
 // band > 0: the descriptors restrict the output rows, and no problem needs
 // more than `band` rows from the 16-row group of its row_lo (narrow inverse
 // rows over that band only); 0: every row.  sc: launch schedule.
@@ -448,6 +471,9 @@ struct gpf_batch {
   // lanes > 1: the batch is split over that many internal streams, forked
   // from and joined to the caller's stream with events
   int lanes = 1;
+  // batches of several grid sizes run merged (one launch per stage over all
+  // sizes) unless this is cleared
+  int merge = 1;
   hipStream_t lane_stream[kMaxLanes] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
   ~gpf_batch();

@@ -44,12 +44,20 @@ __global__ void k_fill(unsigned *p, size_t words) {
 }
 
 // ---------------------------------------------------------------------------
-// R_v by tiles of ts x ts cells: the vortices are counted and sorted by the
-// tile of their base cell floor(xi), then each tile's vortices are summed in
-// an LDS window by one workgroup.
+// R_v by tiles of ts x ts cells.  The vortices are counted and sorted by the
+// tile of their cell floor(xi); a vortex's 4 x 4 stencil (nodes floor(xi)-1
+// .. floor(xi)+2) then reaches only its own tile and the eight around it.
+// One workgroup per tile owns that tile's nodes: it takes the vortices of
+// the 3 x 3 tiles around it, adds the stencil weights that land on its
+// nodes in LDS, and adds each node to the field once, with a plain store.
+// The LDS sums are 64-bit fixed point with a per-problem power-of-two scale
+// (2^61 / sum |Gamma| / dx^2 at most, so no sum can overflow), so they do not
+// depend on the order of the additions: the field is the same bits on every
+// run, and no global atomic is needed.
 // ---------------------------------------------------------------------------
-__host__ __device__ inline int tile_cells(int n) { return n <= 16 ? n : (n <= 1024 ? 16 : 32); }
+__host__ __device__ inline int tile_cells(int n) { return n <= 32 ? n : 32; }
 constexpr int kMaxTiles = 4096;
+constexpr int kMaxTileCells = 32;
 
 __device__ __forceinline__ int vortex_tile(int i0, int j0, int ts, int tps) {
   return ((j0 + 1) / ts) * tps + (i0 + 1) / ts;
@@ -58,11 +66,15 @@ __device__ __forceinline__ int vortex_tile(int i0, int j0, int ts, int tps) {
 // 1. count vortices per tile.  A workgroup histograms its vortices in LDS,
 //    then adds each non-empty bin to the global count once; a vortex's rank
 //    in its tile = the workgroup's offset for the tile + its rank within the
-//    workgroup.  Each workgroup also stores its partial circulation.
+//    workgroup.  Each workgroup also stores its partial circulation, the
+//    moments of the circulation and the partial sum of |Gamma|.
 __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__restrict__ d) {
   __shared__ int hist[kMaxTiles];
-  __shared__ double red[4][kScatterBlock / 64];
+  __shared__ double red[5][kScatterBlock / 64];
   const ProbDesc &P = d[blockIdx.y];
+  // workgroups past this problem's vortices (the grid covers the largest
+  // problem of the launch) have nothing to do
+  if (blockIdx.x * kScatterBlock >= (unsigned)max(P.nv, 1)) return;
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
   for (int t = threadIdx.x; t < ntiles; t += kScatterBlock) hist[t] = 0;
   __syncthreads();
@@ -105,34 +117,34 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
   __syncthreads();
   if (q < P.nv) P.rank[q] = tile >= 0 ? hist[tile] + lrank : -1;
   // circulation and its first and second moments (the impulse of the
-  // vortices: the M4' weights reproduce x, y and x^2 + y^2 exactly)
-  double mom[4] = {gq, gq * xq, gq * yq, gq * (xq * xq + yq * yq)};
+  // vortices: the M4' weights reproduce x, y and x^2 + y^2 exactly), and
+  // sum |Gamma| for the fixed-point scale
+  double mom[5] = {gq, gq * xq, gq * yq, gq * (xq * xq + yq * yq), fabs(gq)};
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 5; ++c) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mom[c] += __shfl_xor(mom[c], off);
   }
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) red[c][threadIdx.x >> 6] = mom[c];
+    for (int c = 0; c < 5; ++c) red[c][threadIdx.x >> 6] = mom[c];
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 5) {
     double s = 0.0;
     for (int w = 0; w < kScatterBlock / 64; ++w) s += red[threadIdx.x][w];
     P.partials[(size_t)threadIdx.x * kPartStride + blockIdx.x] = s;
   }
 }
 
-// 2. every workgroup scans the tile counts into tile starts (workgroup 0
-//    also stores them and the circulation, summed over the partials in
-//    order), then writes each of its vortices to slot start + rank of the
-//    tile-sorted list as (xi, eta, Gamma / dx^2).
-__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d) {
-  __shared__ int start[kMaxTiles + 1];
+// 2. one workgroup per problem: tile starts (exclusive scan of the counts),
+//    the list of non-empty tiles, the circulation and sum |Gamma| (partials
+//    summed in a fixed order, so every solve gives the same bits) and the
+//    fixed-point scale.
+__global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__restrict__ d) {
   __shared__ int wsum[kScatterBlock / 64];
-  __shared__ double gsum[kScatterBlock / 64];
-  const ProbDesc &P = d[blockIdx.y];
+  __shared__ double gsum[2][kScatterBlock / 64];
+  const ProbDesc &P = d[blockIdx.x];
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int kPer = kMaxTiles / kScatterBlock;
@@ -151,6 +163,23 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__r
     if (lane >= off) incl += v;
   }
   if (lane == 63) wsum[wave] = incl;
+  // circulation and sum |Gamma| over the bin_count partials, strided per
+  // thread, then waves, in a fixed order
+  double g = 0.0, ga = 0.0;
+  const int nvb = (P.nv + kScatterBlock - 1) / kScatterBlock;   // workgroups of bin_count
+  for (int b = tid; b < nvb; b += kScatterBlock) {
+    g += P.partials[b];
+    ga += P.partials[4 * (size_t)kPartStride + b];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    g += __shfl_xor(g, off);
+    ga += __shfl_xor(ga, off);
+  }
+  if (lane == 0) {
+    gsum[0][wave] = g;
+    gsum[1][wave] = ga;
+  }
   __syncthreads();
   int pos = incl - run, total = 0;
 #pragma unroll
@@ -158,20 +187,14 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__r
     if (w < wave) pos += wsum[w];
     total += wsum[w];
   }
-  const bool store = blockIdx.x == 0;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     if (k < per && lo + k < ntiles) {
-      start[lo + k] = pos;
-      if (store) P.bin_start[lo + k] = pos;
+      P.bin_start[lo + k] = pos;
       pos += cnts[k];
     }
   }
-  if (tid == 0) {
-    start[ntiles] = total;
-    if (store) P.bin_start[ntiles] = total;
-  }
-  if (store) {
+  {
     // list of the non-empty tiles, in tile order: tile_list[0] = count
     int ne = 0;
 #pragma unroll
@@ -196,59 +219,92 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__r
       if (cnts[k] != 0) P.tile_list[1 + at++] = lo + k;
     if (tid == 0) P.tile_list[0] = tot_ne;
   }
-  if (store) {
-    // circulation: the partials summed in a fixed order (strided per
-    // thread, then waves), so every solve gives the same bits
-    double g = 0.0;
-    const int nvb = (P.nv + kScatterBlock - 1) / kScatterBlock;   // workgroups of bin_count
-    for (int b = tid; b < nvb; b += kScatterBlock) g += P.partials[b];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off);
-    if (lane == 0) gsum[wave] = g;
+  if (tid == 0) {
+    P.bin_start[ntiles] = total;
+    double gw = 0.0, gabs = 0.0;
+    for (int w = 0; w < kScatterBlock / 64; ++w) {
+      gw += gsum[0][w];
+      gabs += gsum[1][w];
+    }
+    P.aux[SC_GAMMA_W] = gw;
+    if (P.sc_out) P.sc_out[SC_GAMMA_W] = gw;
+    // no node sum exceeds sum |Gamma| / dx^2 (each 1-D weight is at most 1
+    // in magnitude); the sums are scaled to below 2^B (FixedPoint<T>)
+    const double smax = gabs / (P.dx * P.dx);
+    int e = 0;
+    if (smax > 0.0) {
+      frexp(smax, &e);   // smax < 2^e
+    }
+    P.aux[SC_RV_SCALE] = (double)e;   // sum |Gamma| / dx^2 < 2^e
   }
-  __syncthreads();
-  if (store && tid == 0) {
-    double g = 0.0;
-    for (int w = 0; w < kScatterBlock / 64; ++w) g += gsum[w];
-    P.aux[SC_GAMMA_W] = g;
-    if (P.sc_out) P.sc_out[SC_GAMMA_W] = g;
-  }
-  // several vortices per thread when there are many (every workgroup
-  // repeats the scan above)
-  for (int q = blockIdx.x * kScatterBlock + tid; q < P.nv; q += gridDim.x * kScatterBlock) {
+}
+
+// 3. write each vortex to slot start + rank of the tile-sorted list as
+//    (xi, eta, Gamma / dx^2)
+__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d) {
+  const ProbDesc &P = d[blockIdx.y];
+  const int n = P.n, ts = tile_cells(n), tps = n / ts;
+  for (int q = blockIdx.x * kScatterBlock + threadIdx.x; q < P.nv; q += gridDim.x * kScatterBlock) {
     const int r = P.rank[q];
     if (r < 0) continue;
     const double xi = (P.xv[q] - P.x0) / P.dx, eta = (P.yv[q] - P.y0) / P.dx;
     const int t = vortex_tile((int)floor(xi) - 1, (int)floor(eta) - 1, ts, tps);
-    double *o = P.sorted + 3 * (size_t)(start[t] + r);
+    double *o = P.sorted + 3 * (size_t)(P.bin_start[t] + r);
     o[0] = xi;
     o[1] = eta;
     o[2] = P.gv[q] / (P.dx * P.dx);
   }
 }
 
-// 3. workgroups take the non-empty tiles in turn: the tile's vortices add their 4 x 4
-//    stencils into an LDS window of (ts+3)^2 nodes (nodes X0-1 .. X0+ts+1),
-//    which is then added to the field (zero, or the values to add to); only
-//    window nodes that received weight take a global atomic, and each node
-//    lies in at most four windows.  The tile's count is cleared for the next
-//    solve.
+// 4. workgroups take the non-empty tiles in turn: the tile's vortices add
+//    their 4 x 4 stencils to an LDS window of (ts+3)^2 nodes (nodes X0-1 ..
+//    X0+ts+1) in 64-bit fixed point, so the window's sums do not depend on
+//    the order of the additions.  The window is then added to the field
+//    (zero, or the values to add to).  Nodes of the tile that no other
+//    tile's window reaches (window-local 3 .. ts-1 on both axes: the left
+//    and lower neighbours reach 2 nodes in, the right and upper ones 1) are
+//    this workgroup's alone and are stored; the others, shared with up to
+//    three other windows, take one global atomic each where the window
+//    holds weight.  The tile's count is cleared for the next solve.
 constexpr int kTileBlock = 256;
+constexpr int kMaxWin = (kMaxTileCells + 3) * (kMaxTileCells + 3);
+
+// Fixed point of the window sums: terms scaled to below 2^B in magnitude.
+// FP32 fields: B = 50, where one add of 1.5 * 2^52 rounds a term to an
+// integer in its low mantissa bits (exact below 2^51), a resolution of
+// 2^-50 of the largest possible sum, far below the FP32 rounding of the
+// field.  FP64 fields: B = 61 and the exact double -> int64 conversion.
+template <class T> struct FixedPoint;
+template <> struct FixedPoint<float> {
+  static constexpr int B = 50;
+  static __device__ __forceinline__ long long to_int(double x) {
+    const double t = x + 6755399441055744.0;   // 1.5 * 2^52
+    return __double_as_longlong(t) - 0x4338000000000000LL;
+  }
+};
+template <> struct FixedPoint<double> {
+  static constexpr int B = 61;
+  static __device__ __forceinline__ long long to_int(double x) { return __double2ll_rn(x); }
+};
 
 template <class T>
 __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__restrict__ d) {
-  __shared__ T win[35 * 35];
+  __shared__ long long win[kMaxWin];
   const ProbDesc &P = d[blockIdx.y];
   const int n = P.n, ts = tile_cells(n), tps = n / ts;
   const int tid = threadIdx.x;
   const int bw = ts + 3, nwin = bw * bw;
   const int cnt = P.tile_list[0];
+  if ((int)blockIdx.x >= cnt) return;
+  const int sexp = FixedPoint<T>::B - (int)P.aux[SC_RV_SCALE];
+  const double scale = ldexp(1.0, sexp), inv = ldexp(1.0, -sexp);
+  T *w = static_cast<T *>(P.w);
   for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
     const int t = P.tile_list[1 + i];
     const int b0 = P.bin_start[t], b1 = P.bin_start[t + 1];
     if (tid == 0) P.bin_cnt[t] = 0;
     const int X0 = (t % tps) * ts - 1, Y0 = (t / tps) * ts - 1;   // window origin
-    for (int k = tid; k < nwin; k += kTileBlock) win[k] = (T)0;
+    for (int k = tid; k < nwin; k += kTileBlock) win[k] = 0;
     __syncthreads();
     // records are taken kBatch at a time per thread, their loads issued
     // before any is used (dense tiles hold hundreds of vortices)
@@ -266,26 +322,37 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
 #pragma unroll
       for (int j = 0; j < kBatch; ++j) {
         if (k0 + j * kTileBlock + tid >= b1) continue;
-        const double xi = rec[j][0], eta = rec[j][1], amp = rec[j][2];
+        const double xi = rec[j][0], eta = rec[j][1], amp = rec[j][2] * scale;
         const double flx = floor(xi), fly = floor(eta);
         const double fx = xi - flx, fy = eta - fly;
         double wx[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) wx[a] = m4p(fx + 1.0 - a);
-        T *row = win + ((int)fly - 1 - Y0) * bw + ((int)flx - 1 - X0);
+        long long *row = win + ((int)fly - 1 - Y0) * bw + ((int)flx - 1 - X0);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const double ab = amp * m4p(fy + 1.0 - b);
 #pragma unroll
-          for (int a = 0; a < 4; ++a) atomicAdd(row + b * bw + a, (T)(ab * wx[a]));
+          for (int a = 0; a < 4; ++a) {
+            const long long v = FixedPoint<T>::to_int(ab * wx[a]);
+            if (v != 0)
+              atomicAdd(reinterpret_cast<unsigned long long *>(row + b * bw + a), (unsigned long long)v);
+          }
         }
       }
     }
     __syncthreads();
-    T *w = static_cast<T *>(P.w);
     for (int k = tid; k < nwin; k += kTileBlock) {
-      const T v = win[k];
-      if (v != (T)0) atomic_add(w + (size_t)(Y0 + k / bw) * n + X0 + k % bw, v);
+      const long long v = win[k];
+      if (v == 0) continue;
+      const int kx = k % bw, ky = k / bw;
+      T *node = w + (size_t)(Y0 + ky) * n + X0 + kx;
+      const T val = (T)((double)v * inv);
+      if (kx >= 3 && kx <= ts - 1 && ky >= 3 && ky <= ts - 1) {
+        *node = P.w_accumulate ? *node + val : val;   // this tile's alone
+      } else {
+        atomic_add(node, val);
+      }
     }
     __syncthreads();   // the window is cleared for the next tile
   }
@@ -517,8 +584,8 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   timer_begin(GPF_TK_SCATTER, s);
   const int vb = scatter_blocks(nv_max);
   hipLaunchKernelGGL(k_bin_count, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
-  const int pb = std::max(std::min(vb, 64), (vb + 7) / 8);
-  hipLaunchKernelGGL(k_bin_place, dim3(pb, nb), dim3(kScatterBlock), 0, s, d);
+  hipLaunchKernelGGL(k_bin_scan, dim3(nb), dim3(kScatterBlock), 0, s, d);
+  hipLaunchKernelGGL(k_bin_place, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
   // about one workgroup per 64 vortices, looping over the non-empty tiles
   const int tb = std::max(1, std::min(bin_tiles(n), (nv_max + 63) / 64));
   hipLaunchKernelGGL((k_tile_scatter<T>), dim3(tb, nb), dim3(kTileBlock), 0, s, d);

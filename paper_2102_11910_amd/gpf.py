@@ -132,6 +132,7 @@ def _load():
         "gpf_batch_destroy": (None, [P]),
         "gpf_batch_set_lanes": (I, [P, I]),
         "gpf_batch_get_lanes": (I, [P]),
+        "gpf_batch_set_merge": (I, [P, I]),
         "gpf_solve_batched": (I, [P, I, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                   C.POINTER(gpf_inputs), C.POINTER(gpf_outputs), P]),
         "gpf_rk2_create": (I, [P, P, C.POINTER(gpf_inputs), P, P, D, I, PP]),
@@ -499,7 +500,7 @@ def gpf_vortex_velocity(plan: Plan, s, X, Y, u_inf, v_inf, u, v, status=None, st
 class Batch:
     """Workspaces for up to max_problems problems solved in shared launches."""
 
-    def __init__(self, ctx: Context, max_problems: int, lanes: int = 1):
+    def __init__(self, ctx: Context, max_problems: int, lanes: int = 1, merge: bool = True):
         h = C.c_void_p()
         check(lib.gpf_batch_create(ctx.h, max_problems, C.byref(h)), "gpf_batch_create")
         self.h = h
@@ -508,6 +509,9 @@ class Batch:
         if lanes != 1:
             check(lib.gpf_batch_set_lanes(h, int(lanes)), "gpf_batch_set_lanes")
         self.lanes = lanes
+        if not merge:
+            check(lib.gpf_batch_set_merge(h, 0), "gpf_batch_set_merge")
+        self.merge = bool(merge)
 
     def solve(self, plans, bodies, inputs, outputs, stream=None):
         k = len(plans)

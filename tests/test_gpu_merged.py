@@ -1,0 +1,180 @@
+"""Batches of several grid sizes run merged: every stage of the solve is one
+launch per precision of the first convolution over all grid sizes, and the
+FP32 transform passes take their blocks from one work list (largest grids
+first).  Each problem must equal the same problem solved in the grouped
+path (one launch sequence per configuration) and alone, within the FP32
+reordering of atomic additions, and meet the oracle tolerances."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2102_11910_amd import gpf  # noqa: E402
+from paper_2102_11910_amd import workloads as wl  # noqa: E402
+from oracle.solve import solve as oracle_solve  # noqa: E402
+from tests.conftest import rell2  # noqa: E402
+from tests.oracle_adapter import body_of, problem_of  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpf.Context(0)
+
+
+def _edge_case(seed, n, top):
+    """A small cylinder whose surface stencils reach the first (top=False)
+    or last (top=True) rows a body may use: the band of the first
+    convolution then sits at the window's edge, where the workgroups of
+    small grids (32 or 64 rows) reach past it."""
+    dx = 2.0 / n
+    rng = np.random.default_rng(seed)
+    half = (n - 1) * dx / 2.0
+    r = 4.0 * dx
+    cy = (half - 3.5 * dx - r) * (1.0 if top else -1.0)
+    surf = wl.cylinder(r, 16, center=(0.1 * half, cy))
+    cloud = wl._uniform_cloud(rng, 80, half - 4.0 * dx, surf, 2.0 * dx)
+    X, Y = wl.f32(cloud[:, 0]), wl.f32(cloud[:, 1])
+    G = wl.f32(rng.normal(0.0, 1e-2, size=80))
+    return wl.Case(f"edge band n={n} {'top' if top else 'bottom'}", n, dx, X, Y, G, surf,
+                   u_inf=1.0, v_inf=0.1, mode="circulation", gamma_b=float(-np.sum(G)))
+
+
+def mixed_sizes():
+    """Every grid size of the merged passes, every one-part mode, both first
+    convolution precisions (the 512^2 plate's noise amplification takes its
+    first convolution to FP64 under GPF_POLICY_AUTO) and repeated sizes."""
+    return [
+        wl.random_case(201, 2048, 2.56 / 2048, 4000, surface="cylinder", ns=700),
+        wl.random_case(202, 1024, 2.56 / 1024, 3000, surface="plate", mode="shed"),
+        wl.config2(seed=203, nv=2500),
+        wl.random_case(204, 512, 2.56 / 512, 1500, surface="ellipse"),
+        wl.random_case(205, 256, 2.56 / 256, 900, surface="plate", mode="kutta"),
+        wl.random_case(206, 128, 2.0 / 128, 400, surface="cylinder"),
+        wl.random_case(207, 128, 2.0 / 128, 333, surface="ellipse"),
+        wl.random_case(208, 64, 2.0 / 64, 90, surface="plate", mode="shed"),
+        _edge_case(209, 64, True),
+        _edge_case(210, 128, False),
+        _edge_case(211, 128, True),
+    ]
+
+
+class Setup:
+    def __init__(self, ctx, cases, total_psi_for=()):
+        self.cases = cases
+        self.plans, self.bodies, self.ins, self.keep = [], [], [], []
+        plans = {}
+        for i, c in enumerate(cases):
+            flags = gpf.GPF_POLICY_AUTO | (gpf.GPF_PSI_TOTAL if i in total_psi_for else 0)
+            key = (c.n, c.dx, flags)
+            if key not in plans:
+                plans[key] = gpf.Plan(ctx, c.n, c.dx, flags=flags)
+            p = plans[key]
+            sf = c.surface
+            edges = tuple(c.edges) if c.mode in ("kutta", "shed") else ()
+            self.plans.append(p)
+            self.bodies.append(gpf.Body(p, sf.xs, sf.ys, sf.ds, edges))
+            X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(DEV) for a in (c.X, c.Y, c.G))
+            self.keep.append((X, Y, G))
+            self.ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, c.ub, c.vb, c.omega, c.mode,
+                                            c.gamma_b, c.znew))
+        self._plans = plans
+
+    def outputs(self):
+        return [gpf.Outputs(c.n, c.nv, c.surface.ns) for c in self.cases]
+
+
+def _host(o):
+    torch.cuda.synchronize()
+    return {"s": o.psi.double().cpu().numpy(), "f": o.f.cpu().numpy(),
+            "uv": np.r_[o.u.cpu().numpy(), o.v.cpu().numpy()]}
+
+
+def _compare(a, b, tag):
+    es, ef, eu = rell2(a["s"], b["s"]), rell2(a["f"], b["f"]), rell2(a["uv"], b["uv"])
+    msg = f"{tag}: s {es:.1e} f {ef:.1e} uv {eu:.1e}"
+    say(msg)
+    assert es <= 1e-6 and ef <= 1e-5 and eu <= 1e-5, msg
+
+
+def test_merged_equals_grouped_alone_and_oracle(ctx):
+    cases = mixed_sizes()
+    st = Setup(ctx, cases, total_psi_for=(3,))
+    say(f"[merged] sizes {[c.n for c in cases]}, FP64 first convolution: "
+        f"{[i for i, b in enumerate(st.bodies) if b.info()['conv1_fp64']]}")
+    assert any(b.info()["conv1_fp64"] for b in st.bodies)
+    merged = gpf.Batch(ctx, len(cases))
+    grouped = gpf.Batch(ctx, len(cases), merge=False)
+    om, og = st.outputs(), st.outputs()
+    for rep in range(2):   # the second call reuses the zeroed workspaces
+        for o in om:
+            o.psi.fill_(float("nan"))
+        merged.solve(st.plans, st.bodies, st.ins, [o.struct for o in om])
+        for o in om:
+            gpf.gpf_sync(o.status)
+    grouped.solve(st.plans, st.bodies, st.ins, [o.struct for o in og])
+    for o in og:
+        gpf.gpf_sync(o.status)
+    for i, c in enumerate(cases):
+        oa = gpf.Outputs(c.n, c.nv, c.surface.ns)
+        gpf.gpf_solve(st.plans[i], st.bodies[i], st.ins[i], oa.struct)
+        gpf.gpf_sync(oa.status)
+        hm = _host(om[i])
+        _compare(hm, _host(og[i]), f"[merged vs grouped] {c.name}")
+        _compare(hm, _host(oa), f"[merged vs alone] {c.name}")
+        if c.n <= 512:
+            ref = oracle_solve(problem_of(c), body_of(c))
+            s_ref = ref.s
+            if i == 3:   # total streamfunction stored: psi = s + U_inf y - V_inf x
+                grid_x = -(c.n - 1) * c.dx / 2 + c.dx * np.arange(c.n)
+                s_ref = ref.s + c.u_inf * grid_x[:, None] - c.v_inf * grid_x[None, :]
+            es, ef = rell2(hm["s"], s_ref), rell2(hm["f"], ref.f)
+            eu = rell2(hm["uv"], np.r_[ref.u, ref.v])
+            say(f"   oracle: s {es:.2e} f {ef:.2e} uv {eu:.2e}")
+            assert es <= 1e-5 and ef <= 1e-4 and eu <= 1e-4
+
+
+def test_merged_batch_graph_replays(ctx):
+    """A merged batch captured into a graph replays the eager result, with
+    eager work and synchronizations between replays."""
+    cases = [wl.random_case(221, 512, 2.56 / 512, 700, surface="cylinder"),
+             wl.random_case(222, 256, 2.56 / 256, 500, surface="plate", mode="shed"),
+             wl.random_case(223, 128, 2.0 / 128, 300, surface="ellipse"),
+             wl.random_case(224, 128, 2.0 / 128, 200, surface="plate", mode="kutta")]
+    st = Setup(ctx, cases)
+    batch = gpf.Batch(ctx, len(cases))
+    outs = st.outputs()
+    structs = [o.struct for o in outs]
+    batch.solve(st.plans, st.bodies, st.ins, structs)
+    for o in outs:
+        gpf.gpf_sync(o.status)
+    eager = [_host(o) for o in outs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch.solve(st.plans, st.bodies, st.ins, structs, stream=stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        batch.solve(st.plans, st.bodies, st.ins, structs, stream=stream)
+    for rep in range(3):
+        for o in outs:
+            o.psi.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            _compare(_host(o), eager[i], f"[merged graph replay {rep}] {cases[i].name}")
+        batch.solve(st.plans, st.bodies, st.ins, structs)
+        for o in outs:
+            gpf.gpf_sync(o.status)
