@@ -1,19 +1,20 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the grid potential-flow solve on one MI355X.
 
-Workload: flat plate of chord 1 at 20 deg, Ns = 256 surface points, Kutta
-condition at both edges with one new vortex per edge; 512 x 512 grid,
-dx = 0.005; 1e4 vortices from a Gaussian blob behind the trailing edge.
-One full solve is R_v -> L^-1 -> E_s -> Schur and edge constraints -> R_s
--> L^-1 -> E_v.  A step solves a batch of such problems (different vortex
-seeds around the same plate) in shared launches; the plain path (one solve
-per step, one launch per stage) is timed beside it.  The plan (LGF table,
-spectrum) and the body (S^-1, f0) are resident; inputs are in HBM before
-the timed region.
+Headline workload: 64 independent problems of uneven size (grids n in
+{128, 256, 512, 1024} with dx = 2.56/n, ellipses of random aspect and
+rotation with 64..512 surface points, 1e3..1e5 vortices, prescribed
+circulation), solved together as one merged batch: every stage of the solve
+is one launch over all grid sizes.  One full solve is R_v -> L^-1 -> E_s ->
+Schur and constraint solve -> R_s -> L^-1 -> E_v; a step solves the whole
+batch.  The plain path (the 64 problems one after another, one launch per
+stage) is timed beside it.  Plans (LGF table, spectrum) and bodies (S^-1,
+f0) are resident and the inputs are in HBM before the timed region.
 
 Prints one JSON line: grid points solved per second (n^2 per full solve),
-per-step latency p50/p99, the roofline of the dominant kernel from HIP
-events on the launch stream, and the FP64 CPU oracle timed on the host.
+per-step latency p50/p99 and the served-request latency p50/p99, the
+roofline of the dominant kernel from HIP events on the launch stream, and
+the FP64 CPU oracle timed on the host (one thread and all cores).
 """
 from __future__ import annotations
 
@@ -43,7 +44,7 @@ def kernel_bytes(n: int, nv: int, ns: int, m: int, w_fp64: bool, keep: float = 1
     """
     win = 8 if w_fp64 else 4
     return {
-        "scatter": 24 * nv + 16 * 2 * win * nv,          # positions+strength, 16 RMW
+        "scatter": 24 * nv + win * n * n,                # positions and strengths in, field out
         "rows_fwd": win * n * n + 8 * n * (n + 1),
         "cols": 16 * n * (n + 1) + 4 * (n + 1) ** 2,
         "rows_inv": 8 * n * (n + 1) + 4 * n * n,
@@ -51,8 +52,39 @@ def kernel_bytes(n: int, nv: int, ns: int, m: int, w_fp64: bool, keep: float = 1
         "cols64": 16 * n * (n + 1) * (1 + keep) + 8 * (n + 1) ** 2,
         "rows_inv64": keep * (16 * n * (n + 1) + 8 * n * n),
         "surface": 8 * ns * ns + 8 * ns * (4 + 3 * (1 + m)),
-        "velocity": 24 * nv + 16 * nv,
+        "velocity": 16 * nv + 16 * nv,                   # positions in, FP64 velocities out
     }
+
+
+def problem_bytes(n: int, nv: int, ns: int, m: int, conv1_fp64: bool, band: int) -> dict:
+    """Algorithmic bytes of one problem of the merged batch, per kernel class
+    of the step: the FP32 passes of both convolutions (the first one keeps
+    only the `band` rows the surface stencils read), or the FP64 passes of a
+    first convolution the precision policy puts in FP64."""
+    w = 8 if conv1_fp64 else 4
+    half = n * (n + 1)
+    out = {"scatter": 24 * nv + w * n * n,
+           "surface": 8 * ns * ns + 8 * ns * (4 + 3 * (1 + m)),
+           "velocity": 32 * nv,
+           # second convolution, FP32 transforms (source in the w type)
+           "rows_fwd": w * n * n + 8 * half,
+           "cols": 16 * half + 4 * (n + 1) ** 2,
+           "rows_inv": 8 * half + 4 * n * n}
+    if conv1_fp64:
+        out["rows_fwd64"] = 8 * n * n + 16 * half
+        out["cols64"] = 16 * half + 8 * (n + 1) ** 2 + 16 * (n + 1) * band
+        out["rows_inv64"] = 16 * (n + 1) * band + 8 * n * band
+    else:
+        out["rows_fwd"] += 4 * n * n + 8 * half
+        out["cols"] += 8 * half + 4 * (n + 1) ** 2 + 8 * (n + 1) * band
+        out["rows_inv"] += 8 * (n + 1) * band + 4 * n * band
+    return out
+
+
+def band_rows(case) -> int:
+    """Rows of the first convolution's band: the 16-row groups of the surface
+    stencils (base row floor(eta) - 1 to + 3)."""
+    return int(round(kept_rows(case) * case.n))
 
 
 def kept_rows(case) -> float:
@@ -69,17 +101,17 @@ def kept_rows(case) -> float:
 
 # kernel class -> (source file, kernel-name prefixes in a profiler trace)
 KERNEL_SOURCES = {
-    "scatter": ("transfer.hip", ("k_bin_count", "k_bin_place", "k_tile_scatter")),
-    "rows_fwd": ("fft_conv.hip", ("k_rows_fwd<double, float",)),
-    "cols": ("fft_conv.hip", ("k_cols_conv<float",)),
-    "rows_inv": ("fft_conv.hip", ("k_rows_inv<float",)),
+    "scatter": ("transfer.hip", ("k_bin_count", "k_bin_scan", "k_bin_place", "k_tile_scatter")),
+    "rows_fwd": ("fft_conv.hip", ("k_rows_fwd_multi",)),
+    "cols": ("fft_conv.hip", ("k_cols_multi<float",)),
+    "rows_inv": ("fft_conv.hip", ("k_rows_inv_multi<float",)),
     "rows_fwd64": ("fft_conv.hip", ("k_rows_fwd<double, double",)),
     "cols64": ("fft_conv.hip", ("k_cols_conv<double", "k_cols_conv_split<double")),
     "rows_inv64": ("fft_conv.hip", ("k_rows_inv<double",)),
     "surface": ("schur.hip", ("k_surface_rhs", "k_schur_apply")),
     "velocity": ("transfer.hip", ("k_vortex_velocity",)),
 }
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "plate512_batch32_hbm_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "c4_batch64_hbm_traffic.md")
 COPY_BYTES = 1 << 28   # calibration copy: 256 MiB read + 256 MiB written
 
 
@@ -131,7 +163,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, command: str) -> None:
     copy = [k for k in fetch if "copy" in k.lower()]
     copy_k = max(copy, key=lambda k: fetch_max[k])
     ff, fw = fetch_max[copy_k] / COPY_BYTES, write_max.get(copy_k, COPY_BYTES) / COPY_BYTES
-    lines = ["# HBM traffic per launch, 512^2 plate workload, batch of 32 problems", "",
+    lines = ["# HBM traffic per launch, 64 uneven problems (n 128..1024) as one merged batch", "",
              "Two rocprofv3 counter runs of the batched step (FETCH_SIZE, then WRITE_SIZE),",
              "each scaled by the reading of the same counter for a 256 MiB device copy.", "",
              f"command_fetch: {command.format(counter='FETCH_SIZE', out=fetch_dir)}",
@@ -175,37 +207,87 @@ def measured_traffic(cls: str, kernel_prefix=None):
     return None
 
 
-def cpu_baseline(case, budget_s: float = 12.0) -> dict:
-    """The FP64 oracle, single-threaded, on a bounded sample of full solves."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
+def _oracle_setup(c, tables):
+    """Plan and body of one problem for the oracle (not timed: the GPU's
+    plans and bodies are resident too)."""
     from oracle.body import body_setup
     from oracle.lgf import lgf_table
     from oracle.operators import Grid
-    from oracle.solve import Problem, solve
+    from oracle.solve import Problem
+    if c.n not in tables:
+        tables[c.n] = lgf_table(c.n)
+    grid = Grid.centered(c.n, c.dx)
+    sf = c.surface
+    body = body_setup(grid, sf.xs, sf.ys, sf.ds, tables[c.n])
+    p = Problem(grid=grid, X=c.X, Y=c.Y, G=c.G, u_inf=c.u_inf, v_inf=c.v_inf, mode=c.mode,
+                gamma_b=c.gamma_b, edges=tuple(c.edges), znew=tuple(c.znew))
+    return p, body
 
+
+def _oracle_worker(idx, barrier):
+    """One process of the all-cores baseline: sets up its problems of the
+    64-problem batch, waits for the others, then solves them; returns the
+    wall-clock interval of its solves and their grid points."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.solve import solve
+    from paper_2102_11910_amd import workloads as wl
+    cases = wl.config4()
     with threadpool_limits(limits=1):
-        grid = Grid.centered(case.n, case.dx)
-        table = lgf_table(case.n)
-        sf = case.surface
-        body = body_setup(grid, sf.xs, sf.ys, sf.ds, table)
-        p = Problem(grid=grid, X=case.X, Y=case.Y, G=case.G, u_inf=case.u_inf,
-                    v_inf=case.v_inf, mode=case.mode, gamma_b=case.gamma_b,
-                    edges=tuple(case.edges), znew=tuple(case.znew))
-        solve(p, body, table)            # warm caches
-        t0 = time.perf_counter()
-        k = 0
-        while True:
-            solve(p, body, table)
-            k += 1
-            el = time.perf_counter() - t0
-            if el >= budget_s or k >= 1000:
-                break
-    return {"value": case.n * case.n * k / el, "unit": "grid points/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{k} full solves of the same 512^2 plate workload (FP64 NumPy, one "
-                      f"thread; plan and body set up beforehand), {el:.1f} s"}
+        tables, work = {}, []
+        for i in idx:
+            p, body = _oracle_setup(cases[i], tables)
+            work.append((p, body, tables[cases[i].n], cases[i].n ** 2))
+        barrier.wait()
+        t0 = time.time()
+        for p, body, tab, _ in work:
+            solve(p, body, tab)
+        t1 = time.time()
+    return t0, t1, sum(w[3] for w in work)
+
+
+def cpu_baseline(budget_s: float = 12.0, workers: int = 0) -> dict:
+    """The FP64 oracle on the 64-problem batch.  One thread: problems in
+    order, each set up untimed and solved once, until the solves have taken
+    budget_s.  All cores (workers > 1): the whole batch dealt out to that
+    many processes (largest grids first, round robin), solves started
+    together; the rate is the batch's grid points over the span of all
+    solves."""
+    from paper_2102_11910_amd import workloads as wl
+    cases = wl.config4()
+    if workers <= 1:
+        from threadpoolctl import threadpool_limits
+
+        from oracle.solve import solve
+        with threadpool_limits(limits=1):
+            tables, el, gp, k = {}, 0.0, 0.0, 0
+            for c in cases:
+                p, body = _oracle_setup(c, tables)
+                t0 = time.perf_counter()
+                solve(p, body, tables[c.n])
+                el += time.perf_counter() - t0
+                gp += c.n * c.n
+                k += 1
+                if el >= budget_s:
+                    break
+        return {"value": gp / el, "unit": "grid points/s", "cores": 1, "kind": "oracle",
+                "sample": f"the first {k} of the 64 problems of the batch, each solved once (FP64 "
+                          f"NumPy, one thread; plan and body set up untimed), {el:.1f} s of solves"}
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    order = sorted(range(len(cases)), key=lambda i: -cases[i].n ** 2)
+    parts = [order[w::workers] for w in range(workers)]
+    ctxm = mp.get_context("spawn")
+    with ctxm.Manager() as man:
+        barrier = man.Barrier(workers)
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctxm) as ex:
+            res = list(ex.map(_oracle_worker, parts, [barrier] * workers))
+    t0 = min(r[0] for r in res)
+    t1 = max(r[1] for r in res)
+    gp = sum(r[2] for r in res)
+    return {"value": gp / (t1 - t0), "unit": "grid points/s", "cores": workers, "kind": "oracle",
+            "sample": f"all 64 problems of the batch, solved once by {workers} one-thread processes "
+                      f"(FP64 NumPy; plans and bodies set up untimed), {t1 - t0:.1f} s span"}
 
 
 def conv_roofline(gpf, torch, np, ctx, log, sizes=(1024, 2048), reps=20):
@@ -385,31 +467,6 @@ def diagnostics_leg(gpf, torch, np, ctx, log, wl, reps=50):
     res["two_plates_workload"] = f"{mc.name}, nv={mc.nv}, ns={len(mc.xs)}, 4 new vortices"
     res["two_plates_solve_ms"] = _timed(torch, lambda: gpf.gpf_solve(plan, body, minp, mout), reps)
     gpf.gpf_sync(st)
-    # the paper's airfoil demonstration: NACA 0012 at 20 deg started
-    # impulsively, shedding at the trailing edge for 3 convective times
-    nc = wl.naca0012_demo()
-    nsteps = 40
-    nplan = gpf.Plan(ctx, nc.n, nc.dx, flags=gpf.GPF_POLICY_AUTO)
-    sfn = nc.surface
-    nbody = gpf.Body(nplan, sfn.xs, sfn.ys, sfn.ds, tuple(nc.edges))
-    Xn, Yn, Gn = z(nsteps), z(nsteps), z(nsteps)
-    nsc = z(gpf.N_SCALARS)
-    nout = gpf.make_outputs(torch.empty((nc.n, nc.n), dtype=nplan.field_dtype, device=dev),
-                            z(nsteps), z(nsteps), z(sfn.ns), z(sfn.ns), nsc,
-                            torch.zeros(1, dtype=torch.int32, device=dev))
-    ninp = gpf.make_inputs(Xn, Yn, Gn, nc.u_inf, nc.v_inf, mode="shed", znew=nc.znew)
-    ninp.nv = 0
-    first = [(zz[0] - sfn.xs[k], zz[1] - sfn.ys[k]) for zz, k in zip(nc.znew, nc.edges)]
-    shed = gpf.Shed(nplan, nbody, ninp, nout, Xn, Yn, Gn, nc.extra["dt"], first)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    shed.run(nsteps)
-    shed.sync()
-    torch.cuda.synchronize()
-    res["naca0012_demo"] = {"workload": f"{nc.name}, ns={sfn.ns}, {nsteps} steps of dt U/c = "
-                                        f"{nc.extra['dt']}", "ms_per_step":
-                            1e3 * (time.perf_counter() - t0) / nsteps,
-                            "gamma_b_end": float(nsc[3].item())}
     # the plate's Schur complement: the exact FP64 build of body creation
     # (host-timed, with the inversion and the probes), and the column build
     # from 256 unit sheets in batches of 32, FP32 and FP64 fields, against it
@@ -426,131 +483,132 @@ def diagnostics_leg(gpf, torch, np, ctx, log, wl, reps=50):
     return res
 
 
-def c4_leg(gpf, torch, np, ctx, log, wl, reps=10):
-    """64 independent problems of uneven size (n 128..1024, 1e3..1e5 vortices,
-    ellipses): grid points per second batched vs solved one after another."""
-    cases = wl.config4()
-    dev = torch.device("cuda", 0)
-    plans = {}
-    for c in cases:
-        if c.n not in plans:
-            plans[c.n] = gpf.Plan(ctx, c.n, c.dx, flags=gpf.GPF_POLICY_AUTO)
-    bodies, ins, outs, keep = [], [], [], []
-    for c in cases:
-        sf = c.surface
-        bodies.append(gpf.Body(plans[c.n], sf.xs, sf.ys, sf.ds))
-        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
-        keep.append((X, Y, G))
-        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, gamma_b=c.gamma_b))
-        outs.append(gpf.Outputs(c.n, c.nv, sf.ns))
-    batch = gpf.Batch(ctx, len(cases))
-    pl = [plans[c.n] for c in cases]
-    gp = float(sum(c.n * c.n for c in cases))
-    # lane count and schedules of every group of the batch, tuned on the
-    # batch itself
-    batch.autotune(pl, bodies, ins, [o.struct for o in outs])
-    log(f"[bench] C4 lanes chosen: {batch.lanes}")
-
-    def batched():
-        batch.solve(pl, bodies, ins, [o.struct for o in outs])
-
-    def plain():
-        for p, b, i, o in zip(pl, bodies, ins, outs):
-            gpf.gpf_solve(p, b, i, o.struct)
-
-    res = {"workload": f"{len(cases)} ellipse problems, n in {sorted(plans)}, "
-                       f"nv {min(c.nv for c in cases)}..{max(c.nv for c in cases)}",
-           "grid_points_per_batch": gp, "lanes": batch.lanes}
-    for name, fn in (("batched", batched), ("plain", plain)):
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        # median of five rounds, so that a one-off host stall in a round
-        # does not stand for the rate
-        rounds = []
-        for _ in range(5):
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                fn()
-            torch.cuda.synchronize()
-            rounds.append((time.perf_counter() - t0) / reps)
-        el = sorted(rounds)[len(rounds) // 2]
-        res[name] = {"ms_per_batch": 1e3 * el, "grid_points_per_s": gp / el,
-                     "rounds_ms": [round(1e3 * r, 3) for r in rounds]}
-        log(f"[bench] C4 {name}: {1e3 * el:.3f} ms per 64 problems (median of rounds "
-            f"{[round(1e3 * r, 3) for r in rounds]}), {gp / el:.3g} GP/s")
-    for o in outs:
-        gpf.gpf_sync(o.status)
-    res["speedup"] = res["batched"]["grid_points_per_s"] / res["plain"]["grid_points_per_s"]
-    return res
+def _device_cloud(torch, gen, nv, surf, dx, dev):
+    """nv vortices uniform in [-1.2, 1.2]^2 at least 2 dx from the body (the
+    cylinder's circle or the plate's segment), strengths N(0, 1e-3^2), drawn
+    on the device from `gen` and rounded to FP32 values (the serving
+    requests' clouds: C5's distributions, drawn where they are used)."""
+    p = surf.params
+    if surf.kind == "cylinder":
+        cx, cy = p["center"]
+        r_min = p["radius"] + 2.0 * dx
+    else:
+        import math
+        a = math.radians(p["alpha_deg"])
+        tx, ty = math.cos(a), -math.sin(a)
+        cx, cy = p["center"]
+        h = 0.5 * p["chord"]
+    got, have = [], 0
+    while have < nv:
+        k = 2 * (nv - have) + 64
+        P = torch.rand((k, 2), generator=gen, device=dev, dtype=torch.float64) * 2.4 - 1.2
+        if surf.kind == "cylinder":
+            ok = torch.hypot(P[:, 0] - cx, P[:, 1] - cy) > r_min
+        else:   # distance to the segment centre +- h (tx, ty)
+            rx, ry = P[:, 0] - cx, P[:, 1] - cy
+            s = torch.clamp(rx * tx + ry * ty, -h, h)
+            ok = torch.hypot(rx - s * tx, ry - s * ty) > 2.0 * dx
+        P = P[ok][: nv - have]
+        got.append(P)
+        have += P.shape[0]
+    P = torch.cat(got).float().double()
+    G = (torch.randn(nv, generator=gen, device=dev, dtype=torch.float64) * 1e-3).float().double()
+    return P[:, 0].contiguous(), P[:, 1].contiguous(), G
 
 
-def c5_leg(gpf, torch, np, ctx, log, wl, npool=16, copies=6, nsat=480, nopen=960):
-    """Serving: requests (n 256..2048, up to 1e6 vortices, cylinders with a
-    prescribed circulation and plates with Kutta at both edges) through
-    gpf_server with 32 slots and a 64 GiB budget.  A pool of distinct
-    requests is cycled (each pool entry has `copies` output sets, so requests
-    in flight never share outputs).  Closed loop: saturated throughput mu.
-    Open loop: Poisson arrivals at 0.5 mu and 0.8 mu, latency from submission
-    to observed completion (server clock), p50/p99."""
+def c5_leg(gpf, torch, np, ctx, log, wl, nreq=2000, slots=32):
+    """Serving (C5): nreq fresh requests through gpf_server with `slots`
+    slots and a 64 GiB budget.  Each request draws its grid (n in {256, 512,
+    1024, 2048}, dx = 2.56/n), its body (half cylinders a = 0.5 with the
+    prescribed circulation -sum Gamma, half plates c = 1 at 0..30 deg with
+    Kutta at both edges and new vortices; N_s = min(1024, round(pi a/dx)) or
+    min(1024, round(c/2dx))) and 10^U[3,6] vortices of its own (seeded,
+    drawn on the device).  Bodies are resident (one per grid, kind and
+    angle).  Closed loop: saturated throughput mu.  Open loop: Poisson
+    arrivals at 0.5 mu and 0.8 mu; latency from submission to observed
+    completion (server clock), p50/p99 overall and per grid size."""
     rng = np.random.default_rng(5)
-    pool = [wl.config5_request(rng) for _ in range(npool)]
     dev = torch.device("cuda", 0)
-    srv = gpf.Server(ctx, 64 << 30, max_slots=32, flags=gpf.GPF_POLICY_AUTO)
-    bodies, plans, ins, keep, outs = {}, [], [], [], []
-    for c in pool:
-        plan = srv.plan(c.n, c.dx)
-        sf = c.surface
-        key = (c.n, sf.kind, sf.ns, round(float(sf.xs[0]), 9), round(float(sf.ys[0]), 9))
+    srv = gpf.Server(ctx, 64 << 30, max_slots=slots, flags=gpf.GPF_POLICY_AUTO)
+    surfs, bodies, plans = {}, {}, {}
+    reqs = []
+    t_gen = time.perf_counter()
+    for k in range(nreq):
+        n = int(rng.choice([256, 512, 1024, 2048]))
+        dx = 2.56 / n
+        if rng.uniform() < 0.5:
+            key = (n, "cylinder", 0.0)
+            if key not in surfs:
+                surfs[key] = wl.cylinder(0.5, int(min(1024, round(np.pi * 0.5 / dx))))
+        else:
+            alpha = float(rng.choice(np.arange(0, 35, 5)))
+            key = (n, "plate", alpha)
+            if key not in surfs:
+                surfs[key] = wl.flat_plate(1.0, alpha, int(min(1024, round(1.0 / (2.0 * dx)))))
+        nv = int(round(10 ** rng.uniform(3, 6)))
+        seed = int(rng.integers(1 << 62))
+        if n not in plans:
+            plans[n] = srv.plan(n, dx)
+        surf = surfs[key]
         if key not in bodies:
-            edges = tuple(c.edges) if c.mode == "shed" else ()
-            bodies[key] = gpf.Body(plan, sf.xs, sf.ys, sf.ds, edges)
-        plans.append((plan, bodies[key]))
-        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
-        keep.append((X, Y, G))
-        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, gamma_b=c.gamma_b,
-                                   znew=c.znew))
-        outs.append([gpf.Outputs(c.n, c.nv, sf.ns) for _ in range(copies)])
-    window = npool * copies
+            edges = surf.edges if surf.kind == "plate" else ()
+            bodies[key] = gpf.Body(plans[n], surf.xs, surf.ys, surf.ds, edges)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed)
+        X, Y, G = _device_cloud(torch, gen, nv, surf, dx, dev)
+        if surf.kind == "cylinder":
+            inp = gpf.make_inputs(X, Y, G, 1.0, 0.0, mode="circulation",
+                                  gamma_b=-float(G.sum().item()))
+        else:
+            inp = gpf.make_inputs(X, Y, G, 1.0, 0.0, mode="shed",
+                                  znew=wl.plate_new_vortices(surf, 4.0 * dx))
+        out = gpf.Outputs(n, nv, surf.ns)
+        reqs.append((n, plans[n], bodies[key], inp, out, (X, Y, G)))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    log(f"[bench] C5: {nreq} requests drawn in {t_gen:.1f} s, {len(bodies)} resident bodies")
 
-    def run(count, arrivals=None):
-        ids, lats = [], []
+    def run(order, arrivals=None):
+        ids = []
         t0 = time.perf_counter()
-        for i in range(count):
-            if i >= window:
-                lats.append(srv.wait(ids[i - window]))
+        for i, r in enumerate(order):
             if arrivals is not None:
                 while time.perf_counter() - t0 < arrivals[i]:
                     pass
-            k = i % npool
-            plan, body = plans[k]
-            ids.append(srv.submit(plan, body, ins[k], outs[k][(i // npool) % copies].struct))
-        for r in ids[max(0, count - window):]:
-            lats.append(srv.wait(r))
-        return time.perf_counter() - t0, np.array(lats)
+            n, plan, body, inp, out, _ = reqs[r]
+            ids.append(srv.submit(plan, body, inp, out.struct))
+        lats = np.array([srv.wait(q) for q in ids])
+        return time.perf_counter() - t0, lats
 
-    run(2 * window)                       # warm-up: plans, workspaces, first launches
-    gp_req = np.mean([c.n * c.n for c in pool])
-    el, _ = run(nsat)
-    mu = nsat / el
-    res = {"workload": f"{npool} distinct requests cycled: n {sorted(set(c.n for c in pool))}, "
-                       f"nv {min(c.nv for c in pool)}..{max(c.nv for c in pool)}, "
-                       f"{sum(c.mode == 'shed' for c in pool)} plates with Kutta x2, "
-                       f"{sum(c.mode == 'circulation' for c in pool)} cylinders",
-           "slots": 32, "saturated_requests_per_s": mu, "saturated_grid_points_per_s": mu * gp_req}
+    run(range(min(nreq, 4 * slots)))          # warm-up: workspaces and first launches
+    ns_of = np.array([r[0] for r in reqs])
+    gp_req = float(np.mean(ns_of.astype(np.float64) ** 2))
+    el, _ = run(range(nreq))
+    mu = nreq / el
+    res = {"workload": f"{nreq} fresh requests: n in {sorted(set(ns_of.tolist()))}, "
+                       f"nv 1e3..1e6 (mean {np.mean([r[5][0].numel() for r in reqs]):.0f}), "
+                       f"cylinders with prescribed circulation and plates with Kutta at both edges, "
+                       f"{len(bodies)} resident bodies",
+           "slots": slots, "requests": nreq, "saturated_requests_per_s": mu,
+           "saturated_grid_points_per_s": mu * gp_req}
     log(f"[bench] C5 saturated: {mu:.0f} requests/s, {mu * gp_req:.3g} GP/s")
     for frac in (0.5, 0.8):
         lam = frac * mu
-        arr = np.cumsum(rng.exponential(1.0 / lam, size=nopen))
-        el, lats = run(nopen, arr)
-        res[f"load_{frac}"] = {"offered_per_s": lam, "achieved_per_s": nopen / el,
-                               "p50_ms": 1e3 * float(np.percentile(lats, 50)),
-                               "p99_ms": 1e3 * float(np.percentile(lats, 99))}
-        log(f"[bench] C5 at {frac} mu: p50 {res[f'load_{frac}']['p50_ms']:.3f} ms, "
-            f"p99 {res[f'load_{frac}']['p99_ms']:.3f} ms")
-    for o in outs:
-        for x in o:
-            gpf.gpf_sync(x.status)
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=nreq))
+        el, lats = run(range(nreq), arr)
+        entry = {"offered_per_s": lam, "achieved_per_s": nreq / el,
+                 "p50_ms": 1e3 * float(np.percentile(lats, 50)),
+                 "p99_ms": 1e3 * float(np.percentile(lats, 99)), "by_n": {}}
+        for n in sorted(set(ns_of.tolist())):
+            ln = lats[ns_of == n]
+            entry["by_n"][str(n)] = {"count": int(ln.size),
+                                     "p50_ms": round(1e3 * float(np.percentile(ln, 50)), 3),
+                                     "p99_ms": round(1e3 * float(np.percentile(ln, 99)), 3)}
+        res[f"load_{frac}"] = entry
+        log(f"[bench] C5 at {frac} mu: p50 {entry['p50_ms']:.3f} ms, p99 {entry['p99_ms']:.3f} ms, "
+            f"by n {entry['by_n']}")
+    for r in reqs:
+        gpf.gpf_sync(r[4].status)
     del bodies
     srv.close()
     return res
@@ -577,14 +635,87 @@ def timed(run_step, K, plan, gpf, torch, np, with_events=True):
     return wall, lat, kt
 
 
+def plate_batch_leg(gpf, torch, np, ctx, log, wl, B=32, K=50):
+    """The 512^2 plate (Kutta at both edges, 1e4 vortices) as a batch of B
+    problems sharing one body: grid points per second and the FP64 column
+    pass of its first convolution (the precision policy's FP64 pass)."""
+    cases = [wl.config2(seed=2 + i) for i in range(B)]
+    case = cases[0]
+    n = case.n
+    solver = gpf.Solver(ctx, n, case.dx, case.surface, flags=gpf.GPF_POLICY_AUTO)
+    plan, body = solver.plan, solver.body
+    info = body.info()
+    dev = solver.dev
+    ins, outs, keep = [], [], []
+    for c in cases:
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
+        o = gpf.Outputs(n, c.nv, body.ns)
+        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, znew=c.znew))
+        outs.append(o.struct)
+        keep.append((X, Y, G, o))
+    batch = gpf.Batch(ctx, B)
+    batch.autotune([plan] * B, [body] * B, ins, outs)
+    step = lambda: batch.solve([plan] * B, [body] * B, ins, outs)
+    for _ in range(5):
+        step()
+    wall, _, kt = timed(step, K, plan, gpf, torch, np)
+    wall2, _, _ = timed(step, K, plan, gpf, torch, np, with_events=False)
+    kb = kernel_bytes(n, int(np.mean([c.nv for c in cases])), case.surface.ns, len(case.znew),
+                      info["conv1_fp64"], kept_rows(case))
+    res = {"workload": f"{B} x {case.name} (one body), nv={case.nv}", "batch": B,
+           "grid_points_per_s": B * n * n * K / wall2, "ms_per_step": 1e3 * wall2 / K}
+    if "cols64" in kt and kt["cols64"][0]:
+        cnt, ms = kt["cols64"]
+        us = 1e3 * ms / cnt
+        res["cols64"] = {"avg_us": round(us, 3), "GBps": round(B * kb["cols64"] / (us * 1e-6) / 1e9, 1),
+                         "frac": round(B * kb["cols64"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"[bench] plate batch: {res}")
+    for k in keep:
+        gpf.gpf_sync(k[3].status)
+    return res
+
+
+def c4_setup(gpf, torch, np, ctx, wl):
+    """The 64-problem batch: resident plans (one per grid) and bodies, inputs
+    in HBM, output buffers, and the batch's workspaces."""
+    cases = wl.config4()
+    dev = torch.device("cuda", 0)
+    plans = {}
+    for c in cases:
+        if c.n not in plans:
+            plans[c.n] = gpf.Plan(ctx, c.n, c.dx, flags=gpf.GPF_POLICY_AUTO)
+    bodies, ins, outs, keep = [], [], [], []
+    for c in cases:
+        sf = c.surface
+        bodies.append(gpf.Body(plans[c.n], sf.xs, sf.ys, sf.ds))
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
+        keep.append((X, Y, G))
+        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, gamma_b=c.gamma_b))
+        outs.append(gpf.Outputs(c.n, c.nv, sf.ns))
+    return {"cases": cases, "plans": [plans[c.n] for c in cases], "bodies": bodies, "ins": ins,
+            "outs": outs, "structs": [o.struct for o in outs], "keep": keep,
+            "gp": float(sum(c.n * c.n for c in cases))}
+
+
+def c4_bytes(c4) -> dict:
+    """Algorithmic bytes of one batched step per kernel class."""
+    tot = {}
+    for c, b in zip(c4["cases"], c4["bodies"]):
+        pb = problem_bytes(c.n, c.nv, c.surface.ns, 0, b.info()["conv1_fp64"], band_rows(c))
+        for k, v in pb.items():
+            tot[k] = tot.get(k, 0) + v
+    return tot
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--batch", type=int, default=32, help="problems per batched step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--legs", default="all",
+                    help="comma list of extra legs: conv,plate,rk2,shed,diag,c5 (all: every leg)")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="only a few batched steps and a 256 MiB copy, for counter runs")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -600,6 +731,20 @@ def main() -> int:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent problems shard one per GPU with no exchange).", file=sys.stderr)
         return 2
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    # the FP64 oracle on the host first, before the GPU is touched (its
+    # all-cores run spawns worker processes)
+    cpu = None
+    if not args.no_cpu_baseline and not args.pmc_workload:
+        log("[bench] timing the FP64 oracle on the host ...")
+        cores = min(16, len(os.sched_getaffinity(0)))
+        one = cpu_baseline(args.cpu_budget)
+        allc = cpu_baseline(workers=cores) if cores > 1 else None
+        cpu = dict(one)
+        if allc:
+            cpu["all_cores"] = allc
+        log(f"[bench] CPU oracle: {cpu}")
 
     import numpy as np
     import torch
@@ -607,58 +752,27 @@ def main() -> int:
     from paper_2102_11910_amd import gpf
     from paper_2102_11910_amd import workloads as wl
 
-    B = args.batch
-    cases = [wl.config2(seed=2 + i) for i in range(B)]
-    case = cases[0]
-    n = case.n
-    log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    log(f"[bench] setup: {case.name}, nv={case.nv}, ns={case.surface.ns}, batch={B}")
     ctx = gpf.Context(0)
     t0 = time.perf_counter()
-    solver = gpf.Solver(ctx, n, case.dx, case.surface, flags=gpf.GPF_POLICY_AUTO)
-    plan, body = solver.plan, solver.body
-    info = body.info()
-    log(f"[bench] plan+body {time.perf_counter() - t0:.2f} s, body {info}")
-    dev = solver.dev
-    # one set of inputs/outputs per problem of the batch
-    ins, outs, keep = [], [], []
-    for c in cases:
-        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(dev) for a in (c.X, c.Y, c.G))
-        psi = torch.empty((n, n), dtype=torch.float32, device=dev)
-        u = torch.empty(c.nv, dtype=torch.float64, device=dev)
-        v = torch.empty_like(u)
-        f = torch.empty(body.ns, dtype=torch.float64, device=dev)
-        ft = torch.empty_like(f)
-        sc = torch.zeros(gpf.N_SCALARS, dtype=torch.float64, device=dev)
-        st = torch.zeros(1, dtype=torch.int32, device=dev)
-        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, mode=c.mode, znew=c.znew))
-        outs.append(gpf.make_outputs(psi, u, v, f, ft, sc, st))
-        keep.append((X, Y, G, psi, u, v, f, ft, sc, st))
+    c4 = c4_setup(gpf, torch, np, ctx, wl)
+    log(f"[bench] C4 setup {time.perf_counter() - t0:.1f} s: {len(c4['cases'])} problems, "
+        f"FP64 first convolution in {sum(b.info()['conv1_fp64'] for b in c4['bodies'])}")
+    B = len(c4["cases"])
     batch = gpf.Batch(ctx, B)
-    plans, bodies = [plan] * B, [body] * B
-    # convolution schedules of this workload, chosen by the library's
-    # autotuner on the batched step itself before anything is timed (both
-    # precisions the step uses: the FP64 first convolution and the FP32
-    # second one).  The counter runs keep the default rules, so that their
-    # dispatches are the three steps alone; the FP64 column kernel of the
-    # rules is the split one, and the traffic is reported below only when
-    # the tuned run launched that kernel too.
-    if not args.pmc_workload:
-        batch.autotune(plans, bodies, ins, outs)
-    tuned = {"fp64": gpf.schedule_get(ctx, n, True, B), "fp32": gpf.schedule_get(ctx, n, False, B)}
-    log(f"[bench] convolution schedules: {tuned}")
+    P, Bo, I, O = c4["plans"], c4["bodies"], c4["ins"], c4["structs"]
 
     def step_batched():
-        batch.solve(plans, bodies, ins, outs)
+        batch.solve(P, Bo, I, O)
 
     def step_plain():
-        gpf.gpf_solve(plan, body, ins[0], outs[0])
+        for p, b, i, o in zip(P, Bo, I, O):
+            gpf.gpf_solve(p, b, i, o)
 
     if args.pmc_workload:
         for _ in range(3):
             step_batched()
         torch.cuda.synchronize()
-        a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
@@ -668,58 +782,53 @@ def main() -> int:
 
     for _ in range(args.warmup):
         step_batched()
+    for _ in range(3):
         step_plain()
-    for k in keep:
-        gpf.gpf_sync(k[-1])
+    for o in c4["outs"]:
+        gpf.gpf_sync(o.status)
     torch.cuda.synchronize()
 
     K = args.steps
-    # batched: K steps of B problems, kernel events on the launch stream
-    wall_b, lat_b, kt = timed(step_batched, K, plan, gpf, torch, np)
-    wall_b_noev, _, _ = timed(step_batched, K, plan, gpf, torch, np, with_events=False)
-    # plain: one problem per step, each stage its own launch
-    Kp = 4 * K
-    wall_p, lat_p, _ = timed(step_plain, Kp, plan, gpf, torch, np, with_events=False)
-    for k in keep:
-        gpf.gpf_sync(k[-1])
+    # batched: K steps with per-kernel events on the launch stream, then K
+    # steps without (the headline rate)
+    wall_ev, lat_b, kt = timed(step_batched, K, P[0], gpf, torch, np)
+    wall_b, lat_b2, _ = timed(step_batched, K, P[0], gpf, torch, np, with_events=False)
+    Kp = max(5, K // 20)
+    wall_p, lat_p, _ = timed(step_plain, Kp, P[0], gpf, torch, np, with_events=False)
+    for o in c4["outs"]:
+        gpf.gpf_sync(o.status)
+    gp = c4["gp"]
+    value = gp * K / wall_b
+    value_plain = gp * Kp / wall_p
 
-    value = B * n * n * K / wall_b_noev
-    value_plain = n * n * Kp / wall_p
-    m = len(case.znew)
-    nv_mean = int(np.mean([c.nv for c in cases]))
-    keep = kept_rows(case)
-    kb1 = kernel_bytes(n, nv_mean, case.surface.ns, m, info["conv1_fp64"], keep)
+    cb = c4_bytes(c4)
     per_kernel = {}
     for name, (cnt, ms) in kt.items():
-        if cnt:
-            avg_ms = ms / cnt
-            per_kernel[name] = {"launches": cnt, "avg_us": 1e3 * avg_ms,
-                                "GBps": B * kb1[name] / (avg_ms * 1e-3) / 1e9}
-    dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"] * per_kernel[k]["launches"])
-    # the kernel of the class this run launched, where a class has two
-    dom_kernel = None
-    if dom == "cols64":
-        dom_kernel = "k_cols_conv<double" if tuned["fp64"]["cols"] == 1 else "k_cols_conv_split<double"
+        if cnt and name in cb:
+            per_step_us = 1e3 * ms / K
+            per_kernel[name] = {"launches_per_step": cnt / K, "us_per_step": per_step_us,
+                                "avg_us": 1e3 * ms / cnt, "bytes_per_step": cb[name],
+                                "GBps": cb[name] / (per_step_us * 1e-6) / 1e9}
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["us_per_step"])
     d = per_kernel[dom]
     achieved = d["GBps"]
+    bytes_per_launch = d["bytes_per_step"] / d["launches_per_step"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, dom_kernel), "bytes_per_launch": int(B * kb1[dom]),
-                "avg_us": round(d["avg_us"], 3)}
-    # the batched step's convolutions as a whole (all row and column passes
-    # of both): algorithmic bytes over the event-timed time of those passes
+                "traffic": measured_traffic(dom), "bytes_per_launch": int(bytes_per_launch),
+                "avg_us": round(d["avg_us"], 3), "launches_per_step": d["launches_per_step"]}
     conv_cls = [k for k in ("rows_fwd", "cols", "rows_inv", "rows_fwd64", "cols64", "rows_inv64")
                 if k in per_kernel]
-    conv_bytes = sum(B * kb1[k] for k in conv_cls)
-    conv_us = sum(per_kernel[k]["avg_us"] for k in conv_cls)
+    conv_bytes = sum(per_kernel[k]["bytes_per_step"] for k in conv_cls)
+    conv_us = sum(per_kernel[k]["us_per_step"] for k in conv_cls)
     conv_batched = {"passes": conv_cls, "bytes_per_step": int(conv_bytes), "us_per_step": round(conv_us, 3),
                     "GBps": round(conv_bytes / (conv_us * 1e-6) / 1e9, 1),
                     "frac": round(conv_bytes / (conv_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
-    log(f"[bench] batched convolutions: {conv_bytes / 1e6:.1f} MB in {conv_us:.1f} us, "
-        f"frac {conv_batched['frac']:.3f} of HBM peak")
-    log("[bench] kernels (batched): " + json.dumps(
-        {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_kernel.items()}))
-
+    log(f"[bench] C4 merged: {1e3 * wall_b / K:.3f} ms/step, {value:.3g} GP/s; plain "
+        f"{1e3 * wall_p / Kp:.3f} ms, {value_plain:.3g} GP/s; convolutions {conv_batched}")
+    log("[bench] kernels: " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
+                                          for k, v in per_kernel.items()}))
+    cases = c4["cases"]
     res = {
         "metric": METRIC,
         "value": value,
@@ -727,44 +836,54 @@ def main() -> int:
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall_b_noev / K,
+        "ms_per_step": 1e3 * wall_b / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "flat plate c=1 at 20 deg, Ns=256, Kutta at both edges with "
-                               "new vortices; 512^2 grid dx=0.005; 1e4 vortices (Gaussian blob); "
-                               f"a step solves {B} such problems (different vortex seeds) in "
-                               "shared launches",
-                   "n": n, "nv": case.nv, "ns": case.surface.ns, "batch": B, "path": "batched",
-                   "precision": "FP32 fields; FP64 first convolution (noise amplification "
-                                f"{info['amp']:.3g} > 500), FP64 Schur/constraints; S built "
-                                "exactly in FP64 from the LGF table (its build from 256 "
-                                "batched unit sheets, FP32 and FP64, under diagnostics.schur)"},
-        "latency_ms": {"p50": float(np.percentile(lat_b, 50)),
-                       "p99": float(np.percentile(lat_b, 99)),
-                       "per": f"batch of {B} solves"},
-        "plain": {"value": value_plain, "ms_per_solve": 1e3 * wall_p / Kp,
+        "config": {"workload": "64 independent problems of uneven size solved as one merged batch: "
+                               "n in {128, 256, 512, 1024}, dx = 2.56/n, ellipses a = 0.5 of aspect "
+                               "U[0.1, 1] and random rotation, Ns 64..512 (dS/dx in [1.5, 4]), "
+                               "10^U[3, 5] vortices uniform in [-1.2, 1.2]^2, prescribed circulation "
+                               "-sum Gamma, U_inf = (1, 0); seed 4",
+                   "problems": B, "grid_points_per_step": gp,
+                   "n_mix": {str(n): sum(c.n == n for c in cases) for n in sorted(set(c.n for c in cases))},
+                   "nv_total": int(sum(c.nv for c in cases)), "path": "batched (merged launches)",
+                   "precision": "FP32 fields and transforms; FP64 first convolution for the "
+                                f"{sum(b.info()['conv1_fp64'] for b in c4['bodies'])} bodies whose "
+                                "noise amplification exceeds 500; FP64 Schur/constraints"},
+        "latency_ms": {"p50": float(np.percentile(lat_b2, 50)), "p99": float(np.percentile(lat_b2, 99)),
+                       "per": f"batched step of {B} solves"},
+        "plain": {"value": value_plain, "ms_per_batch": 1e3 * wall_p / Kp,
                   "latency_ms": {"p50": float(np.percentile(lat_p, 50)),
                                  "p99": float(np.percentile(lat_p, 99))}},
         "speedup_vs_plain": value / value_plain,
-        "schedules": tuned,
-        "value_with_kernel_events": B * n * n * K / wall_b,
+        "value_with_kernel_events": gp * K / wall_ev,
         "roofline": roofline,
         "convolution_batched": conv_batched,
-        "kernels": {k: {"avg_us": round(v["avg_us"], 3), "GBps": round(v["GBps"], 1),
-                        "launches": v["launches"]} for k, v in per_kernel.items()},
+        "kernels": {k: {"avg_us": round(v["avg_us"], 3), "us_per_step": round(v["us_per_step"], 3),
+                        "GBps": round(v["GBps"], 1), "launches_per_step": v["launches_per_step"]}
+                    for k, v in per_kernel.items()},
     }
-    res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
-    res["rk2"] = rk2_leg(gpf, torch, np, ctx, log, wl)
-    res["shed"] = shed_leg(gpf, torch, np, ctx, log, wl)
-    res["diagnostics"] = diagnostics_leg(gpf, torch, np, ctx, log, wl)
-    res["c4"] = c4_leg(gpf, torch, np, ctx, log, wl)
-    res["c5"] = c5_leg(gpf, torch, np, ctx, log, wl)
-    if not args.no_cpu_baseline:
-        log("[bench] timing the FP64 oracle on the host ...")
-        res["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)
+    legs = set(args.legs.split(",")) if args.legs != "all" else {"conv", "plate", "rk2", "shed",
+                                                                   "diag", "c5"}
+    if "conv" in legs:
+        res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
+    if "plate" in legs:
+        res["plate_batch"] = plate_batch_leg(gpf, torch, np, ctx, log, wl)
+    if "rk2" in legs:
+        res["rk2"] = rk2_leg(gpf, torch, np, ctx, log, wl)
+    if "shed" in legs:
+        res["shed"] = shed_leg(gpf, torch, np, ctx, log, wl)
+    if "diag" in legs:
+        res["diagnostics"] = diagnostics_leg(gpf, torch, np, ctx, log, wl)
+    if "c5" in legs:
+        res["c5"] = c5_leg(gpf, torch, np, ctx, log, wl)
+        res["latency_ms_served"] = {k: {"p50": res["c5"][k]["p50_ms"], "p99": res["c5"][k]["p99_ms"]}
+                                    for k in ("load_0.5", "load_0.8")}
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
     return 0
 

@@ -50,3 +50,17 @@ def test_more_than_one_gpu_is_refused():
                        timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_problem_bytes_of_the_merged_batch():
+    """Per problem of the merged batch: two FP32 convolutions (the first
+    keeping a band of rows) to 88 n^2 at full band, or the FP64 first
+    convolution in its own classes."""
+    n, band = 1024, 1024
+    pb = bench.problem_bytes(n, 5000, 300, 0, False, band)
+    conv = pb["rows_fwd"] + pb["cols"] + pb["rows_inv"]
+    assert abs(conv / (88.0 * n * n) - 1.0) < 0.02
+    assert pb["scatter"] == 24 * 5000 + 4 * n * n
+    p64 = bench.problem_bytes(n, 5000, 300, 0, True, 96)
+    assert "cols64" in p64 and p64["rows_fwd"] == 8 * n * n + 8 * n * (n + 1)
+    assert p64["cols64"] == 16 * n * (n + 1) + 8 * (n + 1) ** 2 + 16 * (n + 1) * 96
