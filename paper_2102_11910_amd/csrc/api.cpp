@@ -288,7 +288,7 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
   if (nvv > nv || !rank.p) {
     const size_t cap = std::max<size_t>(1024, (size_t)nvv);
     GPF_TRY(rank.alloc(cap * sizeof(int)));
-    GPF_TRY(sorted.alloc(3 * cap * sizeof(double)));
+    GPF_TRY(sorted.alloc(4 * cap * sizeof(double)));
     nv = (int)cap;
   }
   return GPF_OK;
@@ -366,6 +366,8 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.dx = p->grid.dx;
   pd.x0 = p->grid.x0;
   pd.y0 = p->grid.y0;
+  // dense clouds: velocities tile by tile through LDS
+  pd.vel_tiles = (long long)in->nv * 4 >= (long long)p->grid.n * p->grid.n ? 1 : 0;
   pd.lgf = p->lgf.as<double>();
   pd.nv = in->nv;
   pd.xv = in->d_xv;
@@ -528,7 +530,7 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
     }
     GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2)));
   }
-  GPF_HIP(launch_vortex_velocity<T2>(pd, nb, nv_max, s));
+  GPF_HIP(launch_solve_velocity<T2>(pd, nb, cfg.n, nv_max, s));
   if (impulse) GPF_HIP(launch_impulse(pd, nb, s));
   return GPF_OK;
 }
@@ -593,7 +595,8 @@ bool mergeable(const GroupCfg &c) {
 // problem and convolution descriptors, then the work tables of the
 // multi-size passes (three per convolution, two convolutions, two classes).
 size_t merged_block_bytes(int nb) {
-  return ((size_t)nb * kProblemDescBytes + 15) / 16 * 16 + 9 * (size_t)nb * sizeof(MultiEntry);
+  return ((size_t)nb * kProblemDescBytes + 15) / 16 * 16 + 9 * (size_t)nb * sizeof(MultiEntry) +
+         4 * (size_t)nb * sizeof(FlatEntry);
 }
 
 // Every stage of the solve as one launch per precision class over problems
@@ -650,9 +653,48 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     }
     mp->nprob = hi - lo;
     mp->total = first;
+    // row passes: neighbouring row blocks share cache lines, so each XCD
+    // takes a contiguous part of the list; column blocks share nothing
+    mp->xcds = kind == 1 ? 1 : std::max(1, xcds);
     mp->e = reinterpret_cast<const MultiEntry *>(tab_off + used * sizeof(MultiEntry));  // offset for now
     used += hi - lo;
   };
+  // flat grids of the binning, tile and velocity kernels: problem i of
+  // [lo, hi) takes blocks(i) blocks (maps of the binning and tile kernels
+  // per class, velocity maps over every problem)
+  const size_t flat_off = tab_off + 9 * (size_t)nb * sizeof(MultiEntry);
+  FlatEntry *ftab = reinterpret_cast<FlatEntry *>(blk.data() + flat_off);
+  int fused = 0;
+  auto make_flat = [&](int lo, int hi, auto blocks, FlatMap *fm) {
+    FlatEntry *e = ftab + fused;
+    int first = 0;
+    for (int i = lo; i < hi; ++i) {
+      const int k = blocks(i);
+      e[i - lo] = FlatEntry{first, i - lo, k, 0};
+      first += k;
+    }
+    fm->nprob = hi - lo;
+    fm->total = first;
+    fm->e = reinterpret_cast<const FlatEntry *>(flat_off + fused * sizeof(FlatEntry));  // offset for now
+    fused += hi - lo;
+  };
+  auto bin_blocks = [&](int i) { return std::max(1, (pd[i].nv + 255) / 256); };
+  auto tile_blocks = [&](int i) {
+    return std::max(1, std::min(bin_tiles(pd[i].n), (pd[i].nv + 63) / 64));
+  };
+  auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
+  auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
+  FlatMap fsa[2], fsb[2], fvel[2];
+  if (na > 0) {
+    make_flat(0, na, bin_blocks, &fsa[0]);
+    make_flat(0, na, tile_blocks, &fsa[1]);
+  }
+  if (nbb > 0) {
+    make_flat(na, nb, bin_blocks, &fsb[0]);
+    make_flat(na, nb, tile_blocks, &fsb[1]);
+  }
+  make_flat(0, nb, vel_gather, &fvel[0]);
+  make_flat(0, nb, vel_tiles, &fvel[1]);
   MultiPass mp1a[3], mp2a[3], mp2b[3];
   if (na > 0) {
     make_table(0, c1, 0, na, &mp1a[0]);
@@ -678,13 +720,19 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     fix(mp2a);
   }
   if (nbb > 0) fix(mp2b);
+  auto fixf = [&](FlatMap *fm, int k) {
+    for (int i = 0; i < k; ++i) fm[i].e = reinterpret_cast<const FlatEntry *>(base + (size_t)fm[i].e);
+  };
+  if (na > 0) fixf(fsa, 2);
+  if (nbb > 0) fixf(fsb, 2);
+  fixf(fvel, 2);
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
   const ConvDesc *dc2 = dc1 + nb;
   gpf_ctx *ctx = probs[0].plan->ctx;
   // R_v
-  if (na > 0) GPF_HIP(launch_scatter_vortices<float>(dpd, na, ca.n_max, ca.nv_max, s));
-  if (nbb > 0) GPF_HIP(launch_scatter_vortices<double>(dpd + na, nbb, cbi.n_max, cbi.nv_max, s));
+  if (na > 0) GPF_HIP(launch_scatter_vortices<float>(dpd, na, ca.n_max, ca.nv_max, s, fsa));
+  if (nbb > 0) GPF_HIP(launch_scatter_vortices<double>(dpd + na, nbb, cbi.n_max, cbi.nv_max, s, fsb));
   // first convolution (surface band only)
   if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc1, mp1a, s)));
   for (int i = na; i < nb;) {
@@ -707,7 +755,8 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc2, mp2a, s)));
   if (nbb > 0) GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, s)));
   // velocities of every problem, then impulses where asked
-  GPF_HIP(launch_vortex_velocity<float>(dpd, nb, std::max(ca.nv_max, cbi.nv_max), s));
+  GPF_HIP(launch_solve_velocity<float>(dpd, nb, std::max(ca.n_max, cbi.n_max),
+                                       std::max(ca.nv_max, cbi.nv_max), s, fvel));
   if (impulse) GPF_HIP(launch_impulse(dpd, nb, s));
   return GPF_OK;
 }

@@ -268,11 +268,14 @@ __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename C
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int bf = lane + b * TPS;
+      const int pbf = pad(bf);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (ZERO_UPPER && r >= R / 2) {
           v[b][r].x = (T)0;
           v[b][r].y = (T)0;
+        } else if constexpr ((N / R) % 16 == 0) {
+          v[b][r] = lds[pbf + r * (N / R) + r * (N / R) / 16];
         } else {
           v[b][r] = lds[pad(bf + r * (N / R))];
         }
@@ -311,10 +314,19 @@ __device__ __forceinline__ void fft_stage(typename CT<T>::V (&x)[kE], typename C
       for (int r = 0; r < R; ++r) x[b + r * NB] = v[b][r];
     } else {
       const int base = (bf / NS) * NS * R + j;
+      // NS a multiple of 16: constant offsets from pad(base); NS = 1 with a
+      // radix-16 step: base = 16 bf, so pad(base + r) = 17 bf + r
+      const int pbase = (NS == 1 && R == 16) ? 17 * bf : pad(base);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (LOWER_OUT && r >= R / 2) continue;
-        lds[pad(base + r * NS)] = v[b][r];
+        if constexpr (NS % 16 == 0) {
+          lds[pbase + r * NS + r * NS / 16] = v[b][r];
+        } else if constexpr (NS == 1 && R == 16) {
+          lds[pbase + r] = v[b][r];
+        } else {
+          lds[pad(base + r * NS)] = v[b][r];
+        }
       }
     }
   }
@@ -461,12 +473,11 @@ __device__ __forceinline__ void cols_body(const ConvDesc &C, int blk, typename C
   // up front, beside the column
   T g[kE];
   {
+    // element lane + k TPS: below n for k < 8 (8 TPS = n), else mirrored;
+    // at k = 8, lane 0 both forms give n
     const T *sp = spec + (size_t)k1 * (n + 1);
 #pragma unroll
-    for (int k = 0; k < kE; ++k) {
-      const int k2 = lane + k * P::TPS;
-      g[k] = sp[k2 <= n ? k2 : N - k2];
-    }
+    for (int k = 0; k < kE; ++k) g[k] = k < kE / 2 ? sp[lane + k * P::TPS] : sp[N - lane - k * P::TPS];
   }
   V wr[tw_regs<N>()];
   if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, lane);
@@ -814,9 +825,16 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, const ConvSch
 // the entries at or below g by ballots and reads the entry from its lane.
 constexpr int kMultiLds = kMultiThreads * 17;   // SEQ (N + N/16) elements for every N
 
-__device__ __forceinline__ void multi_locate(const MultiPass &mp, int *prob, int *logn, int *band,
+__device__ __forceinline__ bool multi_locate(const MultiPass &mp, int *prob, int *logn, int *band,
                                              int *blk) {
-  const int g = blockIdx.x;
+  // workgroups are dealt round-robin to the XCDs; every block of these
+  // passes is the same work (4096 transform points), so each XCD takes one
+  // contiguous 1/xcds of the list (the grid is padded to a multiple of
+  // xcds), and neighbouring row blocks, whose runs share cache lines, share
+  // an L2
+  const int per = gridDim.x / mp.xcds;
+  const int g = (blockIdx.x % mp.xcds) * per + blockIdx.x / mp.xcds;
+  if (g >= mp.total) return false;
   const int lane = threadIdx.x & 63;
   int e[4][4];
   int cnt = 0;
@@ -844,6 +862,7 @@ __device__ __forceinline__ void multi_locate(const MultiPass &mp, int *prob, int
   *logn = __builtin_amdgcn_readlane(f[2], l);
   *band = __builtin_amdgcn_readlane(f[3], l);
   *blk = g - first;
+  return true;
 }
 
 template <class Tin, class T>
@@ -851,7 +870,7 @@ __global__ __launch_bounds__(kMultiThreads) void k_rows_fwd_multi(const ConvDesc
                                                                   MultiPass mp) {
   __shared__ typename CT<T>::V lds[kMultiLds];
   int p, logn, band, blk;
-  multi_locate(mp, &p, &logn, &band, &blk);
+  if (!multi_locate(mp, &p, &logn, &band, &blk)) return;
   const ConvDesc &C = cd[p];
   switch (logn) {
     case 6: rows_fwd_body<Tin, T, 128, kMulti>(C, blk, lds); break;
@@ -869,7 +888,7 @@ __global__ __launch_bounds__(kMultiThreads) void k_cols_multi(const ConvDesc *__
                                                               MultiPass mp) {
   __shared__ typename CT<T>::V lds[kMultiLds];
   int p, logn, band, blk;
-  multi_locate(mp, &p, &logn, &band, &blk);
+  if (!multi_locate(mp, &p, &logn, &band, &blk)) return;
   const ConvDesc &C = cd[p];
   switch (logn) {
     case 6: cols_body<T, 128, kMultiThreads / 8>(C, blk, lds); break;
@@ -887,7 +906,7 @@ __global__ __launch_bounds__(kMultiThreads) void k_rows_inv_multi(const ConvDesc
                                                                   MultiPass mp) {
   __shared__ typename CT<T>::V lds[kMultiLds];
   int p, logn, band, blk;
-  multi_locate(mp, &p, &logn, &band, &blk);
+  if (!multi_locate(mp, &p, &logn, &band, &blk)) return;
   const ConvDesc &C = cd[p];
   switch (logn) {
     case 6: rows_inv_body<T, 128, kMulti>(C, blk, band, lds); break;
@@ -918,17 +937,15 @@ int multi_blocks(int pass, int n, const ConvDesc &c) {
 template <class Tin, class T>
 hipError_t launch_convolve_multi(const ConvDesc *d, const MultiPass *mp, hipStream_t st) {
   static_assert(std::is_same<T, float>::value, "multi-size passes are FP32 transforms");
+  auto grid = [](const MultiPass &m) { return dim3((m.total + m.xcds - 1) / m.xcds * m.xcds); };
   timer_begin(GPF_TK_ROWS_FWD, st);
-  hipLaunchKernelGGL((k_rows_fwd_multi<Tin, T>), dim3(mp[0].total),
-                     dim3(kMultiThreads), 0, st, d, mp[0]);
+  hipLaunchKernelGGL((k_rows_fwd_multi<Tin, T>), grid(mp[0]), dim3(kMultiThreads), 0, st, d, mp[0]);
   timer_end(st);
   timer_begin(GPF_TK_COLS, st);
-  hipLaunchKernelGGL((k_cols_multi<T>), dim3(mp[1].total),
-                     dim3(kMultiThreads), 0, st, d, mp[1]);
+  hipLaunchKernelGGL((k_cols_multi<T>), grid(mp[1]), dim3(kMultiThreads), 0, st, d, mp[1]);
   timer_end(st);
   timer_begin(GPF_TK_ROWS_INV, st);
-  hipLaunchKernelGGL((k_rows_inv_multi<T>), dim3(mp[2].total),
-                     dim3(kMultiThreads), 0, st, d, mp[2]);
+  hipLaunchKernelGGL((k_rows_inv_multi<T>), grid(mp[2]), dim3(kMultiThreads), 0, st, d, mp[2]);
   timer_end(st);
   return hipGetLastError();
 }

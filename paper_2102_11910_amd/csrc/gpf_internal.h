@@ -195,6 +195,7 @@ struct ProbDesc {
   // fields
   void *w;                      // source field (zero on entry, or the values R_v adds to)
   int w_accumulate;             // 1: w holds values R_v adds to; 0: w is zero on entry
+  int vel_tiles;                // 1: velocities tile by tile through LDS (dense clouds)
   const void *s1;               // result of the first convolution
   // per-problem aux: scalars and partial sums
   double *aux;
@@ -240,12 +241,70 @@ int scatter_blocks(int nv_max);
 constexpr int kMaxVortices = 1 << 22;
 constexpr int kPartStride = kMaxVortices / 256;
 int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n < 32)
+
+// Flat grids of merged batches for the kernels that read n, nv and ns from
+// their descriptors: entry i gives the first block of problem `prob` in the
+// launch and its number of blocks (entries ordered, firsts ascending; a
+// problem with no blocks has an entry of nblk 0).  Without a table (e ==
+// nullptr) blockIdx.y is the problem and gridDim.x its block count.
+struct FlatEntry {
+  int first, prob, nblk, pad;
+};
+struct FlatMap {
+  const FlatEntry *e;   // device table of nprob entries (16-byte aligned), or nullptr
+  int nprob;
+  int total;            // blocks of the launch
+};
+struct FlatBlock {
+  int prob, blk, nblk;
+};
+// this workgroup's problem and block; false past the last block.  Every wave
+// loads the table (up to 256 entries, four per lane) and counts the entries
+// at or below its block by ballots.
+__device__ __forceinline__ bool flat_block(const FlatMap &fm, FlatBlock *fb) {
+  int prob = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  bool ok = true;
+  if (fm.e) {
+    const int g = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    int first = 0, pr = 0, nb = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k * 64 < fm.nprob) {
+        const int i = lane + 64 * k;
+        int4 v = make_int4(0x7fffffff, 0, 0, 0);
+        if (i < fm.nprob) v = *reinterpret_cast<const int4 *>(fm.e + i);
+        const int c = __popcll(__ballot(v.x <= g));
+        // the entry sits in this quarter when the count ends inside it
+        const int idx = __builtin_amdgcn_readfirstlane(cnt + c - 1);
+        if (c > 0 && idx >= 64 * k) {
+          const int l = idx & 63;
+          first = __builtin_amdgcn_readlane(v.x, l);
+          pr = __builtin_amdgcn_readlane(v.y, l);
+          nb = __builtin_amdgcn_readlane(v.z, l);
+        }
+        cnt += c;
+      }
+    }
+    prob = pr;
+    blk = g - first;
+    nblk = nb;
+    ok = g < fm.total;
+  }
+  fb->prob = prob;
+  fb->blk = blk;
+  fb->nblk = nblk;
+  return ok;
+}
 // R_v: bin and sort the vortices by tile, then one workgroup per tile sums
 // the vortices of its 3 x 3 tile neighbourhood that reach its nodes, in
 // fixed point (order-independent, so the field is bitwise repeatable), and
 // adds them to the source field (zero, or the values to add to)
+// fm (merged batches): fm[0] the binning kernels' map (one block per 256
+// vortices), fm[1] the tile kernel's; nullptr: a 2-D grid of nb problems
 template <class T>
-hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s);
+hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
+                                   const FlatMap *fm = nullptr);
 // Launches that cover problems of several grid sizes (FP32 transforms, n from
 // 64 to 2048): entry i of a pass's table gives the first of its blocks,
 // problem `prob` (an index into the launch's ConvDesc array) and log2 n;
@@ -259,6 +318,7 @@ struct MultiPass {
   const MultiEntry *e;  // device table of nprob entries (16-byte aligned)
   int nprob;
   int total;            // blocks of the launch
+  int xcds;             // XCDs the workgroups are dealt to (>= 1)
 };
 // blocks of one problem in a multi-size pass (0 rows forward, 1 columns,
 // 2 rows inverse over the band of the descriptor, 3 rows inverse, all rows)
@@ -289,6 +349,15 @@ template <class T>
 hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
 template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
+// velocities of a solve's vortices: problems with vel_tiles set from their
+// tile-sorted records (after launch_scatter_vortices of the same solve), tile
+// by tile through LDS, the others vortex by vortex; n the largest grid of
+// the launch
+// fm (merged batches): fm[0] the vortex-by-vortex kernel's map, fm[1] the
+// tile kernel's; nullptr: 2-D grids of nb problems
+template <class T>
+hipError_t launch_solve_velocity(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
+                                 const FlatMap *fm = nullptr);
 
 // xo = x + a u, yo = y + a v (in place allowed)
 // pressure (Sec. 2.6.1): three-point weights of a surface point on the

@@ -68,17 +68,19 @@ __device__ __forceinline__ int vortex_tile(int i0, int j0, int ts, int tps) {
 //    in its tile = the workgroup's offset for the tile + its rank within the
 //    workgroup.  Each workgroup also stores its partial circulation, the
 //    moments of the circulation and the partial sum of |Gamma|.
-__global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__restrict__ d) {
+__global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__restrict__ d, FlatMap fm) {
   __shared__ int hist[kMaxTiles];
   __shared__ double red[5][kScatterBlock / 64];
-  const ProbDesc &P = d[blockIdx.y];
-  // workgroups past this problem's vortices (the grid covers the largest
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  // workgroups past this problem's vortices (a 2-D grid covers the largest
   // problem of the launch) have nothing to do
-  if (blockIdx.x * kScatterBlock >= (unsigned)max(P.nv, 1)) return;
+  if (fb.blk * kScatterBlock >= max(P.nv, 1)) return;
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
   for (int t = threadIdx.x; t < ntiles; t += kScatterBlock) hist[t] = 0;
   __syncthreads();
-  const int q = blockIdx.x * kScatterBlock + threadIdx.x;
+  const int q = fb.blk * kScatterBlock + threadIdx.x;
   double gq = 0.0, xq = 0.0, yq = 0.0;
   int tile = -1, lrank = 0;
   if (q < P.nv) {
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
   if (threadIdx.x < 5) {
     double s = 0.0;
     for (int w = 0; w < kScatterBlock / 64; ++w) s += red[threadIdx.x][w];
-    P.partials[(size_t)threadIdx.x * kPartStride + blockIdx.x] = s;
+    P.partials[(size_t)threadIdx.x * kPartStride + fb.blk] = s;
   }
 }
 
@@ -240,19 +242,31 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
 }
 
 // 3. write each vortex to slot start + rank of the tile-sorted list as
-//    (xi, eta, Gamma / dx^2)
-__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d) {
-  const ProbDesc &P = d[blockIdx.y];
+//    (xi, eta, Gamma / dx^2, q): 32 bytes, the vortex's own index last (the
+//    tile velocity kernel writes its result there).  A vortex outside the
+//    window (already reported) gets no record and NaN velocities.
+__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d, FlatMap fm) {
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
   const int n = P.n, ts = tile_cells(n), tps = n / ts;
-  for (int q = blockIdx.x * kScatterBlock + threadIdx.x; q < P.nv; q += gridDim.x * kScatterBlock) {
+  for (int q = fb.blk * kScatterBlock + threadIdx.x; q < P.nv; q += fb.nblk * kScatterBlock) {
     const int r = P.rank[q];
-    if (r < 0) continue;
+    if (r < 0) {
+      if (P.u) {
+        P.u[q] = NAN;
+        P.v[q] = NAN;
+      }
+      continue;
+    }
     const double xi = (P.xv[q] - P.x0) / P.dx, eta = (P.yv[q] - P.y0) / P.dx;
     const int t = vortex_tile((int)floor(xi) - 1, (int)floor(eta) - 1, ts, tps);
-    double *o = P.sorted + 3 * (size_t)(P.bin_start[t] + r);
-    o[0] = xi;
-    o[1] = eta;
-    o[2] = P.gv[q] / (P.dx * P.dx);
+    double4 o;
+    o.x = xi;
+    o.y = eta;
+    o.z = P.gv[q] / (P.dx * P.dx);
+    o.w = (double)q;
+    *reinterpret_cast<double4 *>(P.sorted + 4 * (size_t)(P.bin_start[t] + r)) = o;
   }
 }
 
@@ -288,18 +302,20 @@ template <> struct FixedPoint<double> {
 };
 
 template <class T>
-__global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__restrict__ d) {
+__global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__restrict__ d, FlatMap fm) {
   __shared__ long long win[kMaxWin];
-  const ProbDesc &P = d[blockIdx.y];
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
   const int n = P.n, ts = tile_cells(n), tps = n / ts;
   const int tid = threadIdx.x;
   const int bw = ts + 3, nwin = bw * bw;
   const int cnt = P.tile_list[0];
-  if ((int)blockIdx.x >= cnt) return;
+  if (fb.blk >= cnt) return;
   const int sexp = FixedPoint<T>::B - (int)P.aux[SC_RV_SCALE];
   const double scale = ldexp(1.0, sexp), inv = ldexp(1.0, -sexp);
   T *w = static_cast<T *>(P.w);
-  for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+  for (int i = fb.blk; i < cnt; i += fb.nblk) {
     const int t = P.tile_list[1 + i];
     const int b0 = P.bin_start[t], b1 = P.bin_start[t + 1];
     if (tid == 0) P.bin_cnt[t] = 0;
@@ -314,7 +330,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
 #pragma unroll
       for (int j = 0; j < kBatch; ++j) {
         const int k = min(k0 + j * kTileBlock + tid, b1 - 1);
-        const double *r = P.sorted + 3 * (size_t)k;
+        const double *r = P.sorted + 4 * (size_t)k;
         rec[j][0] = r[0];
         rec[j][1] = r[1];
         rec[j][2] = k0 + j * kTileBlock + tid < b1 ? r[2] : 0.0;   // clamped duplicates add zero
@@ -442,11 +458,81 @@ __global__ void k_interp_columns(int n, int ns, int q0, const int *__restrict__ 
 // velocity at the vortices: u = (s[j+1] - s[j-1]) / 2dx, v = -(s[i+1] - s[i-1]) / 2dx
 // at the 4 x 4 stencil nodes, interpolated with M4' weights, plus the
 // uniform flow.
+// Velocities of the binned vortices (E_v of the node velocities, Sec. 2.1),
+// tile by tile, for dense clouds (at least one vortex per four nodes; the
+// vortex-by-vortex kernel's 36 scattered loads per vortex then cost more
+// than loading the field once): a workgroup loads the window of s its tile's vortices read
+// (nodes X0-2 .. X0+ts+3 on each axis: the 4 x 4 stencil of a vortex in the
+// tile, plus the one-node halo of the centred differences) into LDS with
+// row-wise coalesced loads, then every vortex of the tile forms its
+// velocity from LDS and writes it at its own index.
+constexpr int kVelWin = kMaxTileCells + 6;
+
 template <class T>
-__global__ __launch_bounds__(256) void k_vortex_velocity(const ProbDesc *__restrict__ d) {
-  const ProbDesc &P = d[blockIdx.y];
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P.nv || P.u == nullptr) return;
+__global__ __launch_bounds__(kTileBlock) void k_tile_velocity(const ProbDesc *__restrict__ d, FlatMap fm) {
+  __shared__ T win[kVelWin * kVelWin];
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  if (P.u == nullptr || !P.vel_tiles) return;
+  const int n = P.n, ts = tile_cells(n), tps = n / ts;
+  const int tid = threadIdx.x;
+  const int bw = ts + 6, nwin = bw * bw;
+  const int cnt = P.tile_list[0];
+  const T *s = static_cast<const T *>(P.psi);
+  const double h = 0.5 / P.dx;
+  const double ui = P.psi_total ? 0.0 : P.sv.u_inf, vi = P.psi_total ? 0.0 : P.sv.v_inf;
+  for (int i = fb.blk; i < cnt; i += fb.nblk) {
+    const int t = P.tile_list[1 + i];
+    const int b0 = P.bin_start[t], b1 = P.bin_start[t + 1];
+    const int X0 = (t % tps) * ts - 2, Y0 = (t / tps) * ts - 2;   // window origin
+    for (int k = tid; k < nwin; k += kTileBlock) {
+      const int gx = X0 + k % bw, gy = Y0 + k / bw;
+      win[k] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? s[(size_t)gy * n + gx] : (T)0;
+    }
+    __syncthreads();
+    for (int k = b0 + tid; k < b1; k += kTileBlock) {
+      const double4 rec = *reinterpret_cast<const double4 *>(P.sorted + 4 * (size_t)k);
+      const double flx = floor(rec.x), fly = floor(rec.y);
+      const double fx = rec.x - flx, fy = rec.y - fly;
+      double wx[4], wy[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        wx[a] = m4p(fx + 1.0 - a);
+        wy[a] = m4p(fy + 1.0 - a);
+      }
+      // rows j0-1 .. j0+4, columns i0-1 .. i0+4 of s, j0 = floor(eta) - 1
+      const T *base = win + ((int)fly - 2 - Y0) * bw + ((int)flx - 2 - X0);
+      double uacc = 0.0, vacc = 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        double ur = 0.0, vr = 0.0;
+        const T *rm = base + b * bw;   // row j0+b-1
+        const T *rc = rm + bw;         // row j0+b
+        const T *rp = rc + bw;         // row j0+b+1
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ur += wx[a] * ((double)rp[a + 1] - (double)rm[a + 1]);
+          vr += wx[a] * ((double)rc[a + 2] - (double)rc[a]);
+        }
+        uacc += wy[b] * ur;
+        vacc += wy[b] * vr;
+      }
+      const int q = (int)rec.w;
+      P.u[q] = uacc * h + ui;
+      P.v[q] = -vacc * h + vi;
+    }
+    __syncthreads();   // the window is reloaded for the next tile
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_vortex_velocity(const ProbDesc *__restrict__ d, FlatMap fm) {
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  const int q = fb.blk * blockDim.x + threadIdx.x;
+  if (q >= P.nv || P.u == nullptr || P.vel_tiles) return;
   const int n = P.n;
   int i0, j0;
   double fx, fy;
@@ -579,21 +665,32 @@ int bin_tiles(int n) {
   return (n / ts) * (n / ts);
 }
 
+// grid of a launch: the flat map's blocks, or nb problems of `per` blocks
+static dim3 grid_of(const FlatMap *fm, int per, int nb) {
+  return fm ? dim3(std::max(1, fm->total)) : dim3(per, nb);
+}
+
 template <class T>
-hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s) {
+hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
+                                   const FlatMap *fm) {
   timer_begin(GPF_TK_SCATTER, s);
+  const FlatMap none{nullptr, 0, 0};
+  const FlatMap mb = fm ? fm[0] : none, mt = fm ? fm[1] : none;
   const int vb = scatter_blocks(nv_max);
-  hipLaunchKernelGGL(k_bin_count, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
+  hipLaunchKernelGGL(k_bin_count, grid_of(fm ? &mb : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mb);
   hipLaunchKernelGGL(k_bin_scan, dim3(nb), dim3(kScatterBlock), 0, s, d);
-  hipLaunchKernelGGL(k_bin_place, dim3(vb, nb), dim3(kScatterBlock), 0, s, d);
+  hipLaunchKernelGGL(k_bin_place, grid_of(fm ? &mb : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mb);
   // about one workgroup per 64 vortices, looping over the non-empty tiles
   const int tb = std::max(1, std::min(bin_tiles(n), (nv_max + 63) / 64));
-  hipLaunchKernelGGL((k_tile_scatter<T>), dim3(tb, nb), dim3(kTileBlock), 0, s, d);
+  hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tb, nb), dim3(kTileBlock), 0, s,
+                     d, mt);
   timer_end(s);
   return hipGetLastError();
 }
-template hipError_t launch_scatter_vortices<float>(const ProbDesc *, int, int, int, hipStream_t);
-template hipError_t launch_scatter_vortices<double>(const ProbDesc *, int, int, int, hipStream_t);
+template hipError_t launch_scatter_vortices<float>(const ProbDesc *, int, int, int, hipStream_t,
+                                                   const FlatMap *);
+template hipError_t launch_scatter_vortices<double>(const ProbDesc *, int, int, int, hipStream_t,
+                                                    const FlatMap *);
 
 hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
                                    const double *xs, const double *ys, int *st_i, double *st_w,
@@ -644,10 +741,33 @@ template hipError_t launch_interp_columns<double>(int, int, int, int, const int 
                                                   const double *, size_t, double *, hipStream_t);
 
 template <class T>
+hipError_t launch_solve_velocity(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
+                                 const FlatMap *fm) {
+  if (nv_max <= 0) return hipSuccess;
+  timer_begin(GPF_TK_VELOCITY, s);
+  const FlatMap none{nullptr, 0, 0};
+  const FlatMap mg = fm ? fm[0] : none, mt = fm ? fm[1] : none;
+  if (!fm || mg.total > 0)
+    hipLaunchKernelGGL((k_vortex_velocity<T>), grid_of(fm ? &mg : nullptr, (nv_max + 255) / 256, nb),
+                       dim3(256), 0, s, d, mg);
+  const int tb = std::max(1, std::min(bin_tiles(n), (nv_max + 63) / 64));
+  if (!fm || mt.total > 0)
+    hipLaunchKernelGGL((k_tile_velocity<T>), grid_of(fm ? &mt : nullptr, tb, nb), dim3(kTileBlock), 0, s,
+                       d, mt);
+  timer_end(s);
+  return hipGetLastError();
+}
+template hipError_t launch_solve_velocity<float>(const ProbDesc *, int, int, int, hipStream_t,
+                                                 const FlatMap *);
+template hipError_t launch_solve_velocity<double>(const ProbDesc *, int, int, int, hipStream_t,
+                                                  const FlatMap *);
+
+template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s) {
   if (nv_max <= 0) return hipSuccess;
   timer_begin(GPF_TK_VELOCITY, s);
-  hipLaunchKernelGGL((k_vortex_velocity<T>), dim3((nv_max + 255) / 256, nb), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((k_vortex_velocity<T>), dim3((nv_max + 255) / 256, nb), dim3(256), 0, s, d,
+                     FlatMap{nullptr, 0, 0});
   timer_end(s);
   return hipGetLastError();
 }

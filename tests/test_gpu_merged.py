@@ -178,3 +178,29 @@ def test_merged_batch_graph_replays(ctx):
         batch.solve(st.plans, st.bodies, st.ins, structs)
         for o in outs:
             gpf.gpf_sync(o.status)
+
+
+def test_dense_clouds_velocity_tiles(ctx):
+    """Clouds of at least one vortex per four nodes take the tile-by-tile
+    velocity kernel (the field window of a tile through LDS): alone, in a
+    merged batch with sparse problems, and against the oracle."""
+    cases = [wl.random_case(231, 128, 2.0 / 128, 6000, surface="cylinder"),
+             wl.random_case(232, 64, 2.0 / 64, 2500, surface="plate", mode="shed"),
+             wl.random_case(233, 256, 2.56 / 256, 300, surface="ellipse")]
+    st = Setup(ctx, cases)
+    batch = gpf.Batch(ctx, len(cases))
+    outs = st.outputs()
+    batch.solve(st.plans, st.bodies, st.ins, [o.struct for o in outs])
+    for o in outs:
+        gpf.gpf_sync(o.status)
+    for i, c in enumerate(cases):
+        oa = gpf.Outputs(c.n, c.nv, c.surface.ns)
+        gpf.gpf_solve(st.plans[i], st.bodies[i], st.ins[i], oa.struct)
+        gpf.gpf_sync(oa.status)
+        hm = _host(outs[i])
+        _compare(hm, _host(oa), f"[dense batch vs alone] {c.name} nv={c.nv}")
+        ref = oracle_solve(problem_of(c), body_of(c))
+        eu = rell2(hm["uv"], np.r_[ref.u, ref.v])
+        es = rell2(hm["s"], ref.s)
+        say(f"   oracle: s {es:.2e} uv {eu:.2e} (vortices per node {c.nv / c.n ** 2:.2f})")
+        assert es <= 1e-5 and eu <= 1e-4
