@@ -109,9 +109,15 @@ KERNEL_SOURCES = {
     "cols64": ("fft_conv.hip", ("k_cols_conv<double", "k_cols_conv_split<double")),
     "rows_inv64": ("fft_conv.hip", ("k_rows_inv<double",)),
     "surface": ("schur.hip", ("k_surface_rhs", "k_schur_apply")),
-    "velocity": ("transfer.hip", ("k_vortex_velocity",)),
+    "velocity": ("transfer.hip", ("k_vortex_velocity", "k_tile_velocity")),
 }
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "c4_batch64_hbm_traffic.md")
+TRACE_SUMMARY = os.path.join(ROOT, "profiles", "c4_batch64_kernel_trace.md")
+SQ_SUMMARY = os.path.join(ROOT, "profiles", "c4_batch64_sq_counters.md")
+# profiled commands, run from /tmp with the repository at <repo>
+TRACE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d {out} -o c4 -- python3 "
+                 "<repo>/bench.py --steps 20 --warmup 5 --no-cpu-baseline --legs none --batched-only")
+PMC_COMMAND = "rocprofv3 --pmc {counters} --output-format csv -d {out} -o pmc -- python3 <repo>/bench.py --pmc-workload"
 COPY_BYTES = 1 << 28   # calibration copy: 256 MiB read + 256 MiB written
 
 
@@ -185,6 +191,101 @@ def summarize_pmc(fetch_dir: str, write_dir: str, command: str) -> None:
     with open(TRAFFIC_SUMMARY, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("wrote", TRAFFIC_SUMMARY)
+
+
+def _short(name: str) -> str:
+    import re
+    name = name.replace("void ", "").replace("gpf::(anonymous namespace)::", "").replace("gpf::", "")
+    return re.sub(r"\(.*", "", name)
+
+
+def summarize_trace(trace_dir: str, bench_json: str) -> None:
+    """Writes the kernel-trace summary of the batched step from a rocprofv3
+    --kernel-trace --stats run of TRACE_COMMAND: the per-kernel statistics,
+    and per kernel class the profiler's time per step beside the event
+    timing of the same run (its JSON line)."""
+    import csv
+    import glob
+    with open(bench_json) as fh:
+        res = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    nsteps = res["warmup"] + 2 * res["steps"]      # warmup, event-timed, plain-timed
+    fs = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not fs:
+        raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
+    with open(fs[0]) as fh:
+        stats = list(csv.DictReader(fh))
+    lines = ["# Kernel trace, 64 uneven problems (n 128..1024) as one merged batch", "",
+             "Command (on one MI355X; only merged batched steps run):", "",
+             "```", "cd /tmp && " + TRACE_COMMAND.format(out=trace_dir), "```", "",
+             f"Batched steps in the run: {nsteps} ({res['warmup']} warmup, {res['steps']} with "
+             f"per-class events, {res['steps']} without).  Under the profiler the step took "
+             f"{res['ms_per_step']:.3f} ms.", "",
+             "## Per kernel class: profiler time per step vs the run's own event timing", "",
+             "| class | kernels | profiler us/step | profiler avg us/dispatch | dispatches/step "
+             "| events us/step | events avg us/launch |", "|---|---|---|---|---|---|---|"]
+    for cls, (_, prefixes) in KERNEL_SOURCES.items():
+        ks = [r for r in stats if any(p in r["Name"] for p in prefixes)]
+        if not ks:
+            continue
+        tot = sum(float(r["TotalDurationNs"]) for r in ks) / 1e3
+        calls = sum(int(r["Calls"]) for r in ks)
+        ev = res.get("kernels", {}).get(cls, {})
+        lines.append(f"| {cls} | {len(ks)} | {tot / nsteps:.2f} | {tot / calls:.2f} | "
+                     f"{calls / nsteps:.2f} | {ev.get('us_per_step', float('nan')):.2f} | "
+                     f"{ev.get('avg_us', float('nan')):.2f} |")
+    rf = res["roofline"]
+    lines += ["", f"Dominant class of the run: {rf['kernel']} ({rf['avg_us']:.2f} us per launch by "
+                  f"events, {rf['achieved']:.1f} GB/s algorithmic, {rf['frac']:.3f} of 8 TB/s).", "",
+              "## Kernel statistics (rocprofv3 --stats)", "",
+              "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| {_short(r['Name'])[:80]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    with open(TRACE_SUMMARY, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote", TRACE_SUMMARY)
+
+
+def summarize_sq(dirs) -> None:
+    """Writes the SQ-counter summary from rocprofv3 --pmc runs of PMC_COMMAND
+    (one directory per counter set): per kernel, the mean of each counter per
+    dispatch, and per wave the VALU, LDS and vector-memory instructions."""
+    import collections
+    agg = collections.OrderedDict()
+    sets = []
+    for d in dirs:
+        rows = _pmc_rows(d)
+        names = sorted({r["Counter_Name"] for r in rows})
+        sets.append(" ".join(names))
+        per = collections.defaultdict(dict)
+        for r in rows:
+            per[r["Dispatch_Id"]].setdefault("name", _short(r["Kernel_Name"]))
+            per[r["Dispatch_Id"]][r["Counter_Name"]] = float(r["Counter_Value"])
+        for disp in per.values():
+            a = agg.setdefault(disp["name"], collections.defaultdict(list))
+            for k, v in disp.items():
+                if k != "name":
+                    a[k].append(v)
+    lines = ["# SQ counters, 64 uneven problems (n 128..1024) as one merged batch", "",
+             "Commands (on one MI355X; three batched steps and a copy):", ""]
+    for d, cs in zip(dirs, sets):
+        lines.append("    cd /tmp && " + PMC_COMMAND.format(counters=cs, out=d))
+    lines += ["", "Means per dispatch; per-wave figures divide by SQ_WAVES.", "",
+              "| kernel | dispatches | waves | VALU/wave | LDS/wave | VMEM rd/wave | VMEM wr/wave "
+              "| SALU/wave | LDS bank conflict cycles/wave | busy cycles |",
+              "|---|---|---|---|---|---|---|---|---|---|"]
+    mean = lambda a, k: sum(a[k]) / len(a[k]) if a.get(k) else float("nan")
+    for nm, a in sorted(agg.items(), key=lambda kv: -mean(kv[1], "SQ_BUSY_CYCLES")):
+        w = mean(a, "SQ_WAVES")
+        pw = lambda k: mean(a, k) / w if w == w and w > 0 else float("nan")
+        lines.append(f"| {nm[:70]} | {min(len(v) for v in a.values())} | {w:.0f} | {pw('SQ_INSTS_VALU'):.0f} | "
+                     f"{pw('SQ_INSTS_LDS'):.0f} | {pw('SQ_INSTS_VMEM_RD'):.1f} | {pw('SQ_INSTS_VMEM_WR'):.1f} | "
+                     f"{pw('SQ_INSTS_SALU'):.0f} | {pw('SQ_LDS_BANK_CONFLICT'):.1f} | "
+                     f"{mean(a, 'SQ_BUSY_CYCLES'):.0f} |")
+    with open(SQ_SUMMARY, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote", SQ_SUMMARY)
 
 
 def measured_traffic(cls: str, kernel_prefix=None):
@@ -720,11 +821,22 @@ def main() -> int:
                     help="only a few batched steps and a 256 MiB copy, for counter runs")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM-traffic summary from two counter runs")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the merged batched step (no one-by-one leg), for kernel traces")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="write the kernel-trace summary from a profiled --batched-only run")
+    ap.add_argument("--summarize-sq", nargs="+", metavar="PMC_DIR",
+                    help="write the SQ-counter summary from counter runs of --pmc-workload")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return 0
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq)
+        return 0
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc,
-                      command="rocprofv3 --pmc {counter} --output-format csv -d {out} -o pmc "
-                              "-- python3 bench.py --pmc-workload")
+                      command="cd /tmp && " + PMC_COMMAND.replace("{counters}", "{counter}"))
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -782,7 +894,7 @@ def main() -> int:
 
     for _ in range(args.warmup):
         step_batched()
-    for _ in range(3):
+    for _ in range(0 if args.batched_only else 3):
         step_plain()
     for o in c4["outs"]:
         gpf.gpf_sync(o.status)
@@ -794,7 +906,10 @@ def main() -> int:
     wall_ev, lat_b, kt = timed(step_batched, K, P[0], gpf, torch, np)
     wall_b, lat_b2, _ = timed(step_batched, K, P[0], gpf, torch, np, with_events=False)
     Kp = max(5, K // 20)
-    wall_p, lat_p, _ = timed(step_plain, Kp, P[0], gpf, torch, np, with_events=False)
+    if args.batched_only:
+        wall_p, lat_p = float("nan"), [float("nan")]
+    else:
+        wall_p, lat_p, _ = timed(step_plain, Kp, P[0], gpf, torch, np, with_events=False)
     for o in c4["outs"]:
         gpf.gpf_sync(o.status)
     gp = c4["gp"]

@@ -283,7 +283,6 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
       GPF_HIP(hipMemset(bin_cnt.p, 0, bin_cnt.bytes));  // counts start (and end) at zero
     }
     GPF_TRY(bin_start.alloc(tiles * sizeof(int)));
-    GPF_TRY(tile_list.alloc(tiles * sizeof(int)));
   }
   if (nvv > nv || !rank.p) {
     const size_t cap = std::max<size_t>(1024, (size_t)nvv);
@@ -291,6 +290,7 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
     GPF_TRY(sorted.alloc(4 * cap * sizeof(double)));
     nv = (int)cap;
   }
+  if (n > 0) GPF_TRY(items.alloc(4 * sizeof(int) * (1 + (size_t)tile_items_max(n, nv))));
   return GPF_OK;
 }
 
@@ -378,7 +378,7 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.partials = ws->part.as<double>();
   pd.bin_cnt = ws->bin_cnt.as<int>();
   pd.bin_start = ws->bin_start.as<int>();
-  pd.tile_list = ws->tile_list.as<int>();
+  pd.items = ws->items.as<int>();
   pd.rank = ws->rank.as<int>();
   pd.sorted = ws->sorted.as<double>();
   pd.status = out->d_status;
@@ -679,9 +679,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     fused += hi - lo;
   };
   auto bin_blocks = [&](int i) { return std::max(1, (pd[i].nv + 255) / 256); };
-  auto tile_blocks = [&](int i) {
-    return std::max(1, std::min(bin_tiles(pd[i].n), (pd[i].nv + 63) / 64));
-  };
+  auto tile_blocks = [&](int i) { return tile_items_max(pd[i].n, pd[i].nv); };
   auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
   FlatMap fsa[2], fsb[2], fvel[2];
@@ -1415,7 +1413,7 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   pd.partials = plan->ws.part.as<double>();
   pd.bin_cnt = plan->ws.bin_cnt.as<int>();
   pd.bin_start = plan->ws.bin_start.as<int>();
-  pd.tile_list = plan->ws.tile_list.as<int>();
+  pd.items = plan->ws.items.as<int>();
   pd.rank = plan->ws.rank.as<int>();
   pd.sorted = plan->ws.sorted.as<double>();
   if (d_status) pd.status = d_status;

@@ -204,7 +204,9 @@ struct ProbDesc {
   // vortex binning by tiles of cells: counts (zero between solves), tile
   // starts, rank of each vortex in its tile, tile-sorted (xi, eta, Gamma/dx^2)
   int *bin_cnt, *bin_start, *rank;
-  int *tile_list;               // [0] = number of non-empty tiles, then their indices
+  int *items;                   // work list of the tile kernels, 4 ints per item:
+                                // [0] = {count, 0, 0, 0}, then {tile, first record,
+                                // end record, 1 if the tile has other items}
   double *sorted;
   // body
   int ns;
@@ -241,6 +243,10 @@ int scatter_blocks(int nv_max);
 constexpr int kMaxVortices = 1 << 22;
 constexpr int kPartStride = kMaxVortices / 256;
 int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n < 32)
+// A tile of more than kTileChunk vortices is split into items of at most
+// kTileChunk records each; tile_items_max bounds the items of a problem.
+constexpr int kTileChunk = 512;
+int tile_items_max(int n, int nv);
 
 // Flat grids of merged batches for the kernels that read n, nv and ns from
 // their descriptors: entry i gives the first block of problem `prob` in the
@@ -349,10 +355,10 @@ template <class T>
 hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
 template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
-// velocities of a solve's vortices: problems with vel_tiles set from their
-// tile-sorted records (after launch_scatter_vortices of the same solve), tile
-// by tile through LDS, the others vortex by vortex; n the largest grid of
-// the launch
+// velocities of a solve's vortices from their tile-sorted records (after
+// launch_scatter_vortices of the same solve): problems with vel_tiles set
+// tile by tile through LDS, the others vortex by vortex in record order; n
+// the largest grid of the launch
 // fm (merged batches): fm[0] the vortex-by-vortex kernel's map, fm[1] the
 // tile kernel's; nullptr: 2-D grids of nb problems
 template <class T>
@@ -465,7 +471,7 @@ struct gpf_workspace {
   int n = 0, ns = 0, nv = 0;
   gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y;
   gpf::DevBuf xb;   // compact band of the first convolution's column pass
-  gpf::DevBuf bin_cnt, bin_start, tile_list, rank, sorted;
+  gpf::DevBuf bin_cnt, bin_start, items, rank, sorted;
   // band: rows of a body's band (16-row groups), 0 without a body
   gpf_status ensure(int n, bool need32, bool need64, int ns, int band = 0);
   gpf_status ensure_vortices(int nv);

@@ -47,13 +47,12 @@ __global__ void k_fill(unsigned *p, size_t words) {
 // R_v by tiles of ts x ts cells.  The vortices are counted and sorted by the
 // tile of their cell floor(xi); a vortex's 4 x 4 stencil (nodes floor(xi)-1
 // .. floor(xi)+2) then reaches only its own tile and the eight around it.
-// One workgroup per tile owns that tile's nodes: it takes the vortices of
-// the 3 x 3 tiles around it, adds the stencil weights that land on its
-// nodes in LDS, and adds each node to the field once, with a plain store.
-// The LDS sums are 64-bit fixed point with a per-problem power-of-two scale
-// (2^61 / sum |Gamma| / dx^2 at most, so no sum can overflow), so they do not
-// depend on the order of the additions: the field is the same bits on every
-// run, and no global atomic is needed.
+// A workgroup takes one item of a work list (a tile, or up to kTileChunk
+// records of a dense tile), sums its stencils in an LDS window around the
+// tile in 64-bit fixed point with a per-problem power-of-two scale (no sum
+// can overflow, and the window's sums do not depend on the order of the
+// additions), and adds the window to the field: plain stores on the nodes
+// only this item reaches, one global atomic on the others.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int tile_cells(int n) { return n <= 32 ? n : 32; }
 constexpr int kMaxTiles = 4096;
@@ -189,6 +188,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
     if (w < wave) pos += wsum[w];
     total += wsum[w];
   }
+  const int pos0 = pos;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     if (k < per && lo + k < ntiles) {
@@ -197,11 +197,12 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
     }
   }
   {
-    // list of the non-empty tiles, in tile order: tile_list[0] = count
-    int ne = 0;
+    // work list of the tile kernels, in tile order: a non-empty tile of c
+    // records gives ceil(c / kTileChunk) items of consecutive records
+    int ni = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) ne += cnts[k] != 0;
-    int inc = ne;
+    for (int k = 0; k < kPer; ++k) ni += (cnts[k] + kTileChunk - 1) / kTileChunk;
+    int inc = ni;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const int v = __shfl_up(inc, off);
@@ -210,16 +211,26 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
     __syncthreads();   // wsum is reused
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
-    int at = inc - ne, tot_ne = 0;
+    int at = inc - ni, tot_items = 0;
 #pragma unroll
     for (int w = 0; w < kScatterBlock / 64; ++w) {
       if (w < wave) at += wsum[w];
-      tot_ne += wsum[w];
+      tot_items += wsum[w];
     }
+    int r = pos0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if (cnts[k] != 0) P.tile_list[1 + at++] = lo + k;
-    if (tid == 0) P.tile_list[0] = tot_ne;
+    for (int k = 0; k < kPer; ++k) {
+      const int c = cnts[k];
+      const int parts = (c + kTileChunk - 1) / kTileChunk;
+      for (int j = 0; j < parts; ++j) {
+        // last field: 0 the tile's only item, 1 the first of several, 2 a later one
+        const int4 it = make_int4(lo + k, r + j * kTileChunk, min(r + c, r + (j + 1) * kTileChunk),
+                                  parts == 1 ? 0 : (j == 0 ? 1 : 2));
+        *reinterpret_cast<int4 *>(P.items + 4 * (1 + at++)) = it;
+      }
+      r += c;
+    }
+    if (tid == 0) *reinterpret_cast<int4 *>(P.items) = make_int4(tot_items, 0, 0, 0);
   }
   if (tid == 0) {
     P.bin_start[ntiles] = total;
@@ -270,17 +281,27 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__r
   }
 }
 
-// 4. workgroups take the non-empty tiles in turn: the tile's vortices add
-//    their 4 x 4 stencils to an LDS window of (ts+3)^2 nodes (nodes X0-1 ..
-//    X0+ts+1) in 64-bit fixed point, so the window's sums do not depend on
-//    the order of the additions.  The window is then added to the field
-//    (zero, or the values to add to).  Nodes of the tile that no other
-//    tile's window reaches (window-local 3 .. ts-1 on both axes: the left
-//    and lower neighbours reach 2 nodes in, the right and upper ones 1) are
-//    this workgroup's alone and are stored; the others, shared with up to
-//    three other windows, take one global atomic each where the window
-//    holds weight.  The tile's count is cleared for the next solve.
-constexpr int kTileBlock = 256;
+// 4. one workgroup per item of the work list (a tile, or a part of a dense
+//    tile's records): the item's vortices add their 4 x 4 stencils to an
+//    LDS window of (ts+3)^2 nodes (nodes X0-1 .. X0+ts+1) in 64-bit fixed
+//    point, so the window's sums do not depend on the order of the
+//    additions.  The window is then added to the field (zero, or the values
+//    to add to).  Nodes of the tile that no other tile's window reaches
+//    (window-local 3 .. ts-1 on both axes: the left and lower neighbours
+//    reach 2 nodes in, the right and upper ones 1) are the item's alone when
+//    the tile has one item, and are stored; every other node, shared with
+//    other windows, takes one global atomic where the window holds weight.
+//    The tile's count is cleared for the next solve.
+constexpr int kTileBlock = 128;
+static_assert(kTileChunk % kTileBlock == 0, "an item's records are a whole number per thread");
+
+// Workgroup barrier that orders LDS accesses only: global stores and atomics
+// issued before it stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 constexpr int kMaxWin = (kMaxTileCells + 3) * (kMaxTileCells + 3);
 
 // Fixed point of the window sums: terms scaled to below 2^B in magnitude.
@@ -307,70 +328,71 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
   FlatBlock fb;
   if (!flat_block(fm, &fb)) return;
   const ProbDesc &P = d[fb.prob];
+  const int cnt = P.items[0];
+  if (fb.blk >= cnt) return;
   const int n = P.n, ts = tile_cells(n), tps = n / ts;
   const int tid = threadIdx.x;
   const int bw = ts + 3, nwin = bw * bw;
-  const int cnt = P.tile_list[0];
-  if (fb.blk >= cnt) return;
   const int sexp = FixedPoint<T>::B - (int)P.aux[SC_RV_SCALE];
   const double scale = ldexp(1.0, sexp), inv = ldexp(1.0, -sexp);
   T *w = static_cast<T *>(P.w);
+  // one item per workgroup when the launch covers the work list (it is
+  // sized for the most items a problem can have)
   for (int i = fb.blk; i < cnt; i += fb.nblk) {
-    const int t = P.tile_list[1 + i];
-    const int b0 = P.bin_start[t], b1 = P.bin_start[t + 1];
-    if (tid == 0) P.bin_cnt[t] = 0;
+    const int4 it = *reinterpret_cast<const int4 *>(P.items + 4 * (1 + i));
+    const int t = it.x, b0 = it.y, b1 = it.z;
+    const bool alone = it.w == 0;
+    if (tid == 0 && it.w <= 1) P.bin_cnt[t] = 0;
     const int X0 = (t % tps) * ts - 1, Y0 = (t / tps) * ts - 1;   // window origin
+    // the item's records (at most kTileChunk), loaded before the window is
+    // cleared; clamped duplicates past the end add zero
+    constexpr int kPer = kTileChunk / kTileBlock;
+    double rec[kPer][3];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int k = b0 + j * kTileBlock + tid;
+      const double *r = P.sorted + 4 * (size_t)min(k, b1 - 1);
+      rec[j][0] = r[0];
+      rec[j][1] = r[1];
+      rec[j][2] = k < b1 ? r[2] : 0.0;
+    }
     for (int k = tid; k < nwin; k += kTileBlock) win[k] = 0;
-    __syncthreads();
-    // records are taken kBatch at a time per thread, their loads issued
-    // before any is used (dense tiles hold hundreds of vortices)
-    constexpr int kBatch = 4;
-    for (int k0 = b0; k0 < b1; k0 += kBatch * kTileBlock) {
-      double rec[kBatch][3];
+    lds_barrier();
 #pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        const int k = min(k0 + j * kTileBlock + tid, b1 - 1);
-        const double *r = P.sorted + 4 * (size_t)k;
-        rec[j][0] = r[0];
-        rec[j][1] = r[1];
-        rec[j][2] = k0 + j * kTileBlock + tid < b1 ? r[2] : 0.0;   // clamped duplicates add zero
-      }
+    for (int j = 0; j < kPer; ++j) {
+      if (b0 + j * kTileBlock + tid >= b1) continue;
+      const double xi = rec[j][0], eta = rec[j][1], amp = rec[j][2] * scale;
+      const double flx = floor(xi), fly = floor(eta);
+      const double fx = xi - flx, fy = eta - fly;
+      double wx[4];
 #pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        if (k0 + j * kTileBlock + tid >= b1) continue;
-        const double xi = rec[j][0], eta = rec[j][1], amp = rec[j][2] * scale;
-        const double flx = floor(xi), fly = floor(eta);
-        const double fx = xi - flx, fy = eta - fly;
-        double wx[4];
+      for (int a = 0; a < 4; ++a) wx[a] = m4p(fx + 1.0 - a);
+      long long *row = win + ((int)fly - 1 - Y0) * bw + ((int)flx - 1 - X0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) wx[a] = m4p(fx + 1.0 - a);
-        long long *row = win + ((int)fly - 1 - Y0) * bw + ((int)flx - 1 - X0);
+      for (int b = 0; b < 4; ++b) {
+        const double ab = amp * m4p(fy + 1.0 - b);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const double ab = amp * m4p(fy + 1.0 - b);
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const long long v = FixedPoint<T>::to_int(ab * wx[a]);
-            if (v != 0)
-              atomicAdd(reinterpret_cast<unsigned long long *>(row + b * bw + a), (unsigned long long)v);
-          }
+        for (int a = 0; a < 4; ++a) {
+          const long long v = FixedPoint<T>::to_int(ab * wx[a]);
+          if (v != 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(row + b * bw + a), (unsigned long long)v);
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     for (int k = tid; k < nwin; k += kTileBlock) {
       const long long v = win[k];
       if (v == 0) continue;
       const int kx = k % bw, ky = k / bw;
       T *node = w + (size_t)(Y0 + ky) * n + X0 + kx;
       const T val = (T)((double)v * inv);
-      if (kx >= 3 && kx <= ts - 1 && ky >= 3 && ky <= ts - 1) {
-        *node = P.w_accumulate ? *node + val : val;   // this tile's alone
+      if (alone && kx >= 3 && kx <= ts - 1 && ky >= 3 && ky <= ts - 1) {
+        *node = P.w_accumulate ? *node + val : val;   // this item's alone
       } else {
         atomic_add(node, val);
       }
     }
-    __syncthreads();   // the window is cleared for the next tile
+    if (i + fb.nblk < cnt) lds_barrier();   // the window is cleared for the next item
   }
 }
 
@@ -455,17 +477,47 @@ __global__ void k_interp_columns(int n, int ns, int q0, const int *__restrict__ 
   S[(size_t)p * ns + q] = acc;
 }
 
-// velocity at the vortices: u = (s[j+1] - s[j-1]) / 2dx, v = -(s[i+1] - s[i-1]) / 2dx
-// at the 4 x 4 stencil nodes, interpolated with M4' weights, plus the
-// uniform flow.
-// Velocities of the binned vortices (E_v of the node velocities, Sec. 2.1),
-// tile by tile, for dense clouds (at least one vortex per four nodes; the
-// vortex-by-vortex kernel's 36 scattered loads per vortex then cost more
-// than loading the field once): a workgroup loads the window of s its tile's vortices read
-// (nodes X0-2 .. X0+ts+3 on each axis: the 4 x 4 stencil of a vortex in the
-// tile, plus the one-node halo of the centred differences) into LDS with
-// row-wise coalesced loads, then every vortex of the tile forms its
-// velocity from LDS and writes it at its own index.
+// Velocity at a vortex (E_v of the node velocities, Sec. 2.1): the centred
+// differences u = (s[j+1] - s[j-1]) / 2dx, v = -(s[i+1] - s[i-1]) / 2dx at
+// the 4 x 4 stencil nodes, interpolated with M4' weights.  s points at node
+// (i0 - 1, j0 - 1) of a field of row pitch `pitch`: rows j0-1 .. j0+4 and
+// columns i0-1 .. i0+4 are read.
+template <class T>
+__device__ __forceinline__ void stencil_velocity(const T *s, int pitch, double fx, double fy,
+                                                 double h, double *u, double *v) {
+  double wx[4], wy[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    wx[a] = m4p(fx + 1.0 - a);
+    wy[a] = m4p(fy + 1.0 - a);
+  }
+  double uacc = 0.0, vacc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double ur = 0.0, vr = 0.0;
+    const T *rm = s + (size_t)b * pitch;   // row j0+b-1
+    const T *rc = rm + pitch;              // row j0+b
+    const T *rp = rc + pitch;              // row j0+b+1
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ur += wx[a] * ((double)rp[a + 1] - (double)rm[a + 1]);
+      vr += wx[a] * ((double)rc[a + 2] - (double)rc[a]);
+    }
+    uacc += wy[b] * ur;
+    vacc += wy[b] * vr;
+  }
+  *u = uacc * h;
+  *v = -vacc * h;
+}
+
+// Velocities of the binned vortices tile by tile, for dense clouds (at
+// least one vortex per four nodes; the vortex-by-vortex kernel's 36
+// scattered loads per vortex then cost more than loading the field once):
+// a workgroup takes one item of the work list, loads the window of s its
+// tile's vortices read (nodes X0-2 .. X0+ts+3 on each axis: the 4 x 4
+// stencil of a vortex in the tile, plus the one-node halo of the centred
+// differences) into LDS with row-wise coalesced loads, then every vortex of
+// the item forms its velocity from LDS and writes it at its own index.
 constexpr int kVelWin = kMaxTileCells + 6;
 
 template <class T>
@@ -475,101 +527,87 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_velocity(const ProbDesc *__
   if (!flat_block(fm, &fb)) return;
   const ProbDesc &P = d[fb.prob];
   if (P.u == nullptr || !P.vel_tiles) return;
+  const int cnt = P.items[0];
+  if (fb.blk >= cnt) return;
   const int n = P.n, ts = tile_cells(n), tps = n / ts;
   const int tid = threadIdx.x;
   const int bw = ts + 6, nwin = bw * bw;
-  const int cnt = P.tile_list[0];
   const T *s = static_cast<const T *>(P.psi);
   const double h = 0.5 / P.dx;
   const double ui = P.psi_total ? 0.0 : P.sv.u_inf, vi = P.psi_total ? 0.0 : P.sv.v_inf;
+  constexpr int kPer = kTileChunk / kTileBlock;
   for (int i = fb.blk; i < cnt; i += fb.nblk) {
-    const int t = P.tile_list[1 + i];
-    const int b0 = P.bin_start[t], b1 = P.bin_start[t + 1];
+    const int4 it = *reinterpret_cast<const int4 *>(P.items + 4 * (1 + i));
+    const int t = it.x, b0 = it.y, b1 = it.z;
     const int X0 = (t % tps) * ts - 2, Y0 = (t / tps) * ts - 2;   // window origin
+    double4 rec[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+      rec[j] = *reinterpret_cast<const double4 *>(P.sorted + 4 * (size_t)min(b0 + j * kTileBlock + tid, b1 - 1));
     for (int k = tid; k < nwin; k += kTileBlock) {
       const int gx = X0 + k % bw, gy = Y0 + k / bw;
       win[k] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? s[(size_t)gy * n + gx] : (T)0;
     }
-    __syncthreads();
-    for (int k = b0 + tid; k < b1; k += kTileBlock) {
-      const double4 rec = *reinterpret_cast<const double4 *>(P.sorted + 4 * (size_t)k);
-      const double flx = floor(rec.x), fly = floor(rec.y);
-      const double fx = rec.x - flx, fy = rec.y - fly;
-      double wx[4], wy[4];
+    lds_barrier();
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        wx[a] = m4p(fx + 1.0 - a);
-        wy[a] = m4p(fy + 1.0 - a);
-      }
-      // rows j0-1 .. j0+4, columns i0-1 .. i0+4 of s, j0 = floor(eta) - 1
-      const T *base = win + ((int)fly - 2 - Y0) * bw + ((int)flx - 2 - X0);
-      double uacc = 0.0, vacc = 0.0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        double ur = 0.0, vr = 0.0;
-        const T *rm = base + b * bw;   // row j0+b-1
-        const T *rc = rm + bw;         // row j0+b
-        const T *rp = rc + bw;         // row j0+b+1
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          ur += wx[a] * ((double)rp[a + 1] - (double)rm[a + 1]);
-          vr += wx[a] * ((double)rc[a + 2] - (double)rc[a]);
-        }
-        uacc += wy[b] * ur;
-        vacc += wy[b] * vr;
-      }
-      const int q = (int)rec.w;
-      P.u[q] = uacc * h + ui;
-      P.v[q] = -vacc * h + vi;
+    for (int j = 0; j < kPer; ++j) {
+      if (b0 + j * kTileBlock + tid >= b1) continue;
+      const double flx = floor(rec[j].x), fly = floor(rec[j].y);
+      // rows j0-1 .. j0+4, columns i0-1 .. i0+4 of s, i0 = floor(xi) - 1
+      double u, v;
+      stencil_velocity(win + ((int)fly - 2 - Y0) * bw + ((int)flx - 2 - X0), bw, rec[j].x - flx,
+                       rec[j].y - fly, h, &u, &v);
+      const int q = (int)rec[j].w;
+      P.u[q] = u + ui;
+      P.v[q] = v + vi;
     }
-    __syncthreads();   // the window is reloaded for the next tile
+    if (i + fb.nblk < cnt) lds_barrier();   // the window is reloaded for the next item
   }
 }
 
+// Velocities vortex by vortex, reading s from global memory.  After R_v of
+// the same solve (from_records) the threads take the tile-sorted records, so
+// neighbouring threads read neighbouring rows of s; the records hold only
+// vortices inside the window (the others got NaN velocities when sorted).
+// Otherwise they take the vortices in input order and check the window.
 template <class T>
-__global__ __launch_bounds__(256) void k_vortex_velocity(const ProbDesc *__restrict__ d, FlatMap fm) {
+__global__ __launch_bounds__(256) void k_vortex_velocity(const ProbDesc *__restrict__ d, FlatMap fm,
+                                                         int from_records) {
   FlatBlock fb;
   if (!flat_block(fm, &fb)) return;
   const ProbDesc &P = d[fb.prob];
-  const int q = fb.blk * blockDim.x + threadIdx.x;
-  if (q >= P.nv || P.u == nullptr || P.vel_tiles) return;
+  if (P.u == nullptr || P.vel_tiles) return;
   const int n = P.n;
-  int i0, j0;
+  const int k = fb.blk * blockDim.x + threadIdx.x;
+  int i0, j0, q;
   double fx, fy;
-  if (!(cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx) &&
-        cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy))) {
-    atomicOr(P.status, GPF_DEV_OUT_OF_GRID);
-    P.u[q] = NAN;
-    P.v[q] = NAN;
-    return;
-  }
-  double wx[4], wy[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    wx[a] = m4p(fx + 1.0 - a);
-    wy[a] = m4p(fy + 1.0 - a);
-  }
-  // rows j0-1 .. j0+4, columns i0-1 .. i0+4 of s
-  double uacc = 0.0, vacc = 0.0;
-  const T *base = static_cast<const T *>(P.psi) + (size_t)(j0 - 1) * n + (i0 - 1);
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    double ur = 0.0, vr = 0.0;
-    const T *rm = base + (size_t)b * n;       // row j0+b-1
-    const T *rc = rm + n;                      // row j0+b
-    const T *rp = rc + n;                      // row j0+b+1
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      ur += wx[a] * ((double)rp[a + 1] - (double)rm[a + 1]);
-      vr += wx[a] * ((double)rc[a + 2] - (double)rc[a]);
+  if (from_records) {
+    const int ts = tile_cells(n), tps = n / ts;
+    if (k >= P.bin_start[tps * tps]) return;
+    const double4 rec = *reinterpret_cast<const double4 *>(P.sorted + 4 * (size_t)k);
+    const double flx = floor(rec.x), fly = floor(rec.y);
+    i0 = (int)flx - 1;
+    j0 = (int)fly - 1;
+    fx = rec.x - flx;
+    fy = rec.y - fly;
+    q = (int)rec.w;
+  } else {
+    q = k;
+    if (q >= P.nv) return;
+    if (!(cell(P.xv[q], P.x0, P.dx, 2, n - 3, &i0, &fx) &&
+          cell(P.yv[q], P.y0, P.dx, 2, n - 3, &j0, &fy))) {
+      atomicOr(P.status, GPF_DEV_OUT_OF_GRID);
+      P.u[q] = NAN;
+      P.v[q] = NAN;
+      return;
     }
-    uacc += wy[b] * ur;
-    vacc += wy[b] * vr;
   }
-  const double h = 0.5 / P.dx;
+  double u, v;
+  stencil_velocity(static_cast<const T *>(P.psi) + (size_t)(j0 - 1) * n + (i0 - 1), n, fx, fy,
+                   0.5 / P.dx, &u, &v);
   const double ui = P.psi_total ? 0.0 : P.sv.u_inf, vi = P.psi_total ? 0.0 : P.sv.v_inf;
-  P.u[q] = uacc * h + ui;
-  P.v[q] = -vacc * h + vi;
+  P.u[q] = u + ui;
+  P.v[q] = v + vi;
 }
 
 __global__ void k_axpy2(int nv, const double *__restrict__ x, const double *__restrict__ y,
@@ -665,9 +703,17 @@ int bin_tiles(int n) {
   return (n / ts) * (n / ts);
 }
 
+// items of a problem: one per non-empty tile (at most min(tiles, nv)) plus
+// one per further kTileChunk records of a tile (sum over tiles of
+// floor((c - 1) / kTileChunk) <= nv / kTileChunk)
+int tile_items_max(int n, int nv) {
+  if (nv <= 0) return 0;
+  return std::min(bin_tiles(n), nv) + nv / kTileChunk;
+}
+
 // grid of a launch: the flat map's blocks, or nb problems of `per` blocks
 static dim3 grid_of(const FlatMap *fm, int per, int nb) {
-  return fm ? dim3(std::max(1, fm->total)) : dim3(per, nb);
+  return fm ? dim3(std::max(1, fm->total)) : dim3(std::max(1, per), nb);
 }
 
 template <class T>
@@ -680,10 +726,9 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   hipLaunchKernelGGL(k_bin_count, grid_of(fm ? &mb : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mb);
   hipLaunchKernelGGL(k_bin_scan, dim3(nb), dim3(kScatterBlock), 0, s, d);
   hipLaunchKernelGGL(k_bin_place, grid_of(fm ? &mb : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mb);
-  // about one workgroup per 64 vortices, looping over the non-empty tiles
-  const int tb = std::max(1, std::min(bin_tiles(n), (nv_max + 63) / 64));
-  hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tb, nb), dim3(kTileBlock), 0, s,
-                     d, mt);
+  // one workgroup per item of the work list
+  hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
+                     dim3(kTileBlock), 0, s, d, mt);
   timer_end(s);
   return hipGetLastError();
 }
@@ -749,11 +794,10 @@ hipError_t launch_solve_velocity(const ProbDesc *d, int nb, int n, int nv_max, h
   const FlatMap mg = fm ? fm[0] : none, mt = fm ? fm[1] : none;
   if (!fm || mg.total > 0)
     hipLaunchKernelGGL((k_vortex_velocity<T>), grid_of(fm ? &mg : nullptr, (nv_max + 255) / 256, nb),
-                       dim3(256), 0, s, d, mg);
-  const int tb = std::max(1, std::min(bin_tiles(n), (nv_max + 63) / 64));
+                       dim3(256), 0, s, d, mg, 1);
   if (!fm || mt.total > 0)
-    hipLaunchKernelGGL((k_tile_velocity<T>), grid_of(fm ? &mt : nullptr, tb, nb), dim3(kTileBlock), 0, s,
-                       d, mt);
+    hipLaunchKernelGGL((k_tile_velocity<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
+                       dim3(kTileBlock), 0, s, d, mt);
   timer_end(s);
   return hipGetLastError();
 }
@@ -767,7 +811,7 @@ hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStre
   if (nv_max <= 0) return hipSuccess;
   timer_begin(GPF_TK_VELOCITY, s);
   hipLaunchKernelGGL((k_vortex_velocity<T>), dim3((nv_max + 255) / 256, nb), dim3(256), 0, s, d,
-                     FlatMap{nullptr, 0, 0});
+                     FlatMap{nullptr, 0, 0}, 0);
   timer_end(s);
   return hipGetLastError();
 }

@@ -64,3 +64,51 @@ def test_problem_bytes_of_the_merged_batch():
     p64 = bench.problem_bytes(n, 5000, 300, 0, True, 96)
     assert "cols64" in p64 and p64["rows_fwd"] == 8 * n * n + 8 * n * (n + 1)
     assert p64["cols64"] == 16 * n * (n + 1) + 8 * (n + 1) ** 2 + 16 * (n + 1) * 96
+
+
+def test_trace_and_counter_summaries(tmp_path, monkeypatch):
+    """The profile summarizers read rocprofv3's CSV layout and write one row
+    per kernel class and per kernel."""
+    import csv
+    import json
+    td = tmp_path / "trace" / "host"
+    td.mkdir(parents=True)
+    names = ["void gpf::(anonymous namespace)::k_cols_multi<float>(gpf::ConvDesc const*, gpf::MultiPass)",
+             "gpf::(anonymous namespace)::k_bin_count(gpf::ProbDesc const*, gpf::FlatMap)"]
+    with open(td / "c4_kernel_stats.csv", "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"])
+        w.writerow([names[0], 135, 135 * 97000, 97000, 60.0, 90000, 110000])
+        w.writerow([names[1], 90, 90 * 20000, 20000, 40.0, 1000, 50000])
+    res = {"warmup": 5, "steps": 20, "ms_per_step": 1.2,
+           "roofline": {"kernel": "cols", "avg_us": 97.5, "achieved": 2900.0, "frac": 0.36},
+           "kernels": {"cols": {"us_per_step": 292.0, "avg_us": 97.5}}}
+    bj = tmp_path / "bench.json"
+    bj.write_text("[bench] log line\n" + json.dumps(res) + "\n")
+    out = tmp_path / "trace.md"
+    monkeypatch.setattr(bench, "TRACE_SUMMARY", str(out))
+    bench.summarize_trace(str(tmp_path / "trace"), str(bj))
+    text = out.read_text()
+    # 135 dispatches of 97 us over 45 steps: 3 per step, 291 us per step
+    assert "| cols | 1 | 291.00 | 97.00 | 3.00 | 292.00 | 97.50 |" in text
+    assert "| k_bin_count | 90 | 20.00 |" in text
+
+    sq = []
+    for i, counters in enumerate((("SQ_WAVES", "SQ_INSTS_VALU"), ("SQ_WAVES", "SQ_BUSY_CYCLES"))):
+        d = tmp_path / f"sq{i}" / "host"
+        d.mkdir(parents=True)
+        with open(d / "pmc_counter_collection.csv", "w", newline="") as fh:
+            w = csv.DictWriter(fh, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for disp in range(2):
+                for c in counters:
+                    v = {"SQ_WAVES": 100.0, "SQ_INSTS_VALU": 5000.0 * (disp + 1), "SQ_BUSY_CYCLES": 7.0}[c]
+                    w.writerow({"Dispatch_Id": disp, "Kernel_Name": names[0], "Counter_Name": c,
+                                "Counter_Value": v})
+        sq.append(str(tmp_path / f"sq{i}"))
+    out = tmp_path / "sq.md"
+    monkeypatch.setattr(bench, "SQ_SUMMARY", str(out))
+    bench.summarize_sq(sq)
+    text = out.read_text()
+    assert "--pmc SQ_INSTS_VALU SQ_WAVES" in text and "--pmc SQ_BUSY_CYCLES SQ_WAVES" in text
+    assert "| k_cols_multi<float> | 2 | 100 | 75 |" in text

@@ -204,3 +204,47 @@ def test_dense_clouds_velocity_tiles(ctx):
         es = rell2(hm["s"], ref.s)
         say(f"   oracle: s {es:.2e} uv {eu:.2e} (vortices per node {c.nv / c.n ** 2:.2f})")
         assert es <= 1e-5 and eu <= 1e-4
+
+
+def _cluster_case(seed, n, nv, center, radius):
+    """All vortices in a disc a few cells across: one or a few tiles hold
+    thousands of records, so R_v splits them into several work items whose
+    windows all add to the field atomically."""
+    dx = 2.56 / n
+    rng = np.random.default_rng(seed)
+    r = radius * np.sqrt(rng.uniform(0.0, 1.0, nv))
+    th = rng.uniform(0.0, 2.0 * np.pi, nv)
+    X, Y = wl.f32(center[0] + r * np.cos(th)), wl.f32(center[1] + r * np.sin(th))
+    G = wl.f32(rng.normal(0.0, 1e-3, size=nv))
+    surf = wl.cylinder(0.2, 64)
+    return wl.Case(f"cluster n={n} nv={nv}", n, dx, X, Y, G, surf, u_inf=1.0, v_inf=0.0,
+                   mode="circulation", gamma_b=float(-np.sum(G)))
+
+
+def test_dense_tiles_split_into_items(ctx):
+    """Tiles of more than 512 vortices are split into several items: a
+    uniform cloud of about 1200 per tile, one of exactly 512 and 513 per
+    tile on average, and a tight cluster inside one tile (thousands of
+    records); alone, merged, and against the oracle."""
+    cases = [wl.random_case(241, 128, 2.0 / 128, 20000, surface="cylinder"),
+             _cluster_case(242, 256, 4000, (0.6, -0.55), 6.0 * 2.56 / 256),
+             _cluster_case(243, 256, 513, (-0.4, 0.5), 3.0 * 2.56 / 256),
+             wl.random_case(244, 64, 2.0 / 64, 2100, surface="plate", mode="shed")]
+    st = Setup(ctx, cases)
+    batch = gpf.Batch(ctx, len(cases))
+    outs = st.outputs()
+    for rep in range(2):   # the second call reuses the cleared tile counts
+        batch.solve(st.plans, st.bodies, st.ins, [o.struct for o in outs])
+        for o in outs:
+            gpf.gpf_sync(o.status)
+    for i, c in enumerate(cases):
+        oa = gpf.Outputs(c.n, c.nv, c.surface.ns)
+        gpf.gpf_solve(st.plans[i], st.bodies[i], st.ins[i], oa.struct)
+        gpf.gpf_sync(oa.status)
+        hm = _host(outs[i])
+        _compare(hm, _host(oa), f"[split items batch vs alone] {c.name}")
+        ref = oracle_solve(problem_of(c), body_of(c))
+        es, ef = rell2(hm["s"], ref.s), rell2(hm["f"], ref.f)
+        eu = rell2(hm["uv"], np.r_[ref.u, ref.v])
+        say(f"   oracle: s {es:.2e} f {ef:.2e} uv {eu:.2e}")
+        assert es <= 1e-5 and ef <= 1e-4 and eu <= 1e-4
