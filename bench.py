@@ -443,6 +443,9 @@ def rk2_leg(gpf, torch, np, ctx, log, wl, steps=100):
                                    ("fp64_plain", gpf.GPF_FP64, False)):
         plan = gpf.Plan(ctx, case.n, case.dx, flags=flags)
         body = gpf.Body(plan, case.surface.xs, case.surface.ys, case.surface.ds)
+        info = body.info()
+        out[f"{name}_conv1"] = ("fp64" if flags == gpf.GPF_FP64 or info["conv1_fp64"] else "fp32")
+        out[f"{name}_amp"] = info["amp"]
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev)
         X, Y, G = t(case.X), t(case.Y), t(case.G)
         inp = gpf.make_inputs(X, Y, G, case.u_inf, case.v_inf, case.ub, case.vb, case.omega,
@@ -776,6 +779,45 @@ def plate_batch_leg(gpf, torch, np, ctx, log, wl, B=32, K=50):
     return res
 
 
+def setup_leg(gpf, torch, np, ctx, log, wl):
+    """Body setup at N_s = 1024 (a cylinder on the 1024^2 grid, dS/dx = 1.6):
+    S from the LGF table, its FP64 inverse, f0, Gamma_0 and the probes;
+    and the FP64 inverse alone, blocked (n = 1024 and 2048, the largest
+    blocked size) beside the column-by-column elimination (n = 2100)."""
+    n, dx, ns = 1024, 2.56 / 1024, 1024
+    radius = ns * 1.6 * dx / (2.0 * np.pi)
+    surf = wl.cylinder(radius, ns)
+    plan = gpf.Plan(ctx, n, dx, flags=gpf.GPF_POLICY_AUTO)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        body = gpf.Body(plan, surf.xs, surf.ys, surf.ds)
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0))
+        body.close()
+    out = {"body_ns1024_ms": float(np.median(times)), "body_ns1024_runs_ms": times,
+           "workload": f"cylinder r={radius:.4f}, ns={ns}, n={n}, dx={dx}"}
+    rng = np.random.default_rng(3)
+    for m in (1024, 2048, 2100):
+        a = torch.as_tensor(rng.standard_normal((m, m)) + 4.0 * np.sqrt(m) * np.eye(m),
+                            dtype=torch.float64).cuda()
+        x = torch.empty_like(a)
+        gpf.gpf_invert_fp64(ctx, a, x)
+        ts = []
+        for _ in range(3 if m <= 2048 else 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gpf.gpf_invert_fp64(ctx, a, x)
+            ts.append(1e3 * (time.perf_counter() - t0))
+        res = float((x @ a - torch.eye(m, dtype=torch.float64, device="cuda")).abs().max())
+        out[f"invert_{m}_ms"] = float(np.median(ts))
+        out[f"invert_{m}_residual"] = res
+        out[f"invert_{m}_path"] = "blocked (MFMA panels)" if m <= 2048 else "column by column"
+    log(f"[bench] setup: {out}")
+    return out
+
+
 def c4_setup(gpf, torch, np, ctx, wl):
     """The 64-problem batch: resident plans (one per grid) and bodies, inputs
     in HBM, output buffers, and the batch's workspaces."""
@@ -816,7 +858,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--legs", default="all",
-                    help="comma list of extra legs: conv,plate,rk2,shed,diag,c5 (all: every leg)")
+                    help="comma list of extra legs: conv,plate,rk2,shed,diag,c5,setup (all: every leg)")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="only a few batched steps and a 256 MiB copy, for counter runs")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -965,6 +1007,9 @@ def main() -> int:
                    "problems": B, "grid_points_per_step": gp,
                    "n_mix": {str(n): sum(c.n == n for c in cases) for n in sorted(set(c.n for c in cases))},
                    "nv_total": int(sum(c.nv for c in cases)), "path": "batched (merged launches)",
+                   "conv1_fp64_by_n": {str(n): sum(b.info()["conv1_fp64"] for c, b in zip(cases, c4["bodies"])
+                                                   if c.n == n) for n in sorted(set(c.n for c in cases))},
+                   "conv1_fp64_problems": [i for i, b in enumerate(c4["bodies"]) if b.info()["conv1_fp64"]],
                    "precision": "FP32 fields and transforms; FP64 first convolution for the "
                                 f"{sum(b.info()['conv1_fp64'] for b in c4['bodies'])} bodies whose "
                                 "noise amplification exceeds 500; FP64 Schur/constraints"},
@@ -982,7 +1027,7 @@ def main() -> int:
                     for k, v in per_kernel.items()},
     }
     legs = set(args.legs.split(",")) if args.legs != "all" else {"conv", "plate", "rk2", "shed",
-                                                                   "diag", "c5"}
+                                                                   "diag", "c5", "setup"}
     if "conv" in legs:
         res["convolution"] = conv_roofline(gpf, torch, np, ctx, log)
     if "plate" in legs:
@@ -993,6 +1038,8 @@ def main() -> int:
         res["shed"] = shed_leg(gpf, torch, np, ctx, log, wl)
     if "diag" in legs:
         res["diagnostics"] = diagnostics_leg(gpf, torch, np, ctx, log, wl)
+    if "setup" in legs:
+        res["setup"] = setup_leg(gpf, torch, np, ctx, log, wl)
     if "c5" in legs:
         res["c5"] = c5_leg(gpf, torch, np, ctx, log, wl)
         res["latency_ms_served"] = {k: {"p50": res["c5"][k]["p50_ms"], "p99": res["c5"][k]["p99_ms"]}

@@ -634,6 +634,20 @@ gpf_status gpf_timing_read(gpf_plan *plan, int kind, long long *count,
 
 /* ---- host utilities ---------------------------------------------------- */
 
+/* FP64 inverse of a dense n x n matrix on the device, the operation the
+ * library applies to the Schur complement S of a body (Sec. 2.2.2, App. A):
+ * d_a and d_ainv are row-major device arrays of n*n doubles (d_a is read
+ * only; they must not overlap), on ctx's device, queued on hip_stream (null:
+ * the default stream), which the call waits for before it returns.  Gauss-
+ * Jordan elimination with partial pivoting (largest |entry| of the column,
+ * lowest row on ties); n <= 2048 in 16-column panels whose updates run on
+ * FP64 matrix cores, larger n column by column.  *min_pivot_rel (may be
+ * null) receives min |pivot| / max |a_ij|: values near 1e-14 or below mean
+ * a numerically singular matrix, whose inverse is not meaningful.
+ * GPF_E_INVALID for n outside [1, 8192] or null arrays. */
+gpf_status gpf_invert_fp64(gpf_ctx *ctx, int n, const double *d_a, double *d_ainv,
+                           void *hip_stream, double *min_pivot_rel);
+
 /* Lattice Green's function table T[a*(nmax+1)+b] = G(a, b), 0 <= a,b <= nmax,
  * G(0,0) = 0 (host computation, no device needed). */
 gpf_status gpf_lgf_table(int nmax, double *h_table);

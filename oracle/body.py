@@ -66,23 +66,3 @@ def body_setup(grid: Grid, xs, ys, ds, table=None) -> Body:
     f0 = sla.lu_solve(lu, np.ones(len(xs)))
     gamma0 = float(np.dot(ds, f0))
     return Body(xs, ys, ds, S, lu, f0, gamma0, ds * f0)
-
-
-def noise_amplification(body: Body, eps: float = 1e-6, probes: int = 4,
-                        seed: int = 0) -> float:
-    """Median over white probes of relL2(delta f) / eps for the rhs -y_s.
-
-    Measures how strongly S^-1 amplifies relative noise of size eps (times
-    max |rhs|) on a unit-freestream right-hand side; the paper notes that the
-    sheet strength is sensitive to noise because S^-1 discretizes an ill-posed
-    first-kind integral equation (Sec. 2.2.2).
-    """
-    rhs = -body.ys
-    f = body.solve(rhs)
-    rng = np.random.default_rng(seed)
-    amps = []
-    for _ in range(probes):
-        d = rng.standard_normal(len(rhs)) * eps * np.abs(rhs).max()
-        df = body.solve(rhs + d) - f
-        amps.append(np.linalg.norm(df) / np.linalg.norm(f) / eps)
-    return float(np.median(amps))

@@ -842,6 +842,17 @@ extern "C" {
 const char *gpf_last_error(void) { return g_last_error.c_str(); }
 const char *gpf_version(void) { return "gpf 0.2 (gfx950)"; }
 
+gpf_status gpf_invert_fp64(gpf_ctx *ctx, int n, const double *d_a, double *d_ainv,
+                           void *hip_stream, double *min_pivot_rel) {
+  if (!ctx || n < 1 || n > 8192 || !d_a || !d_ainv || d_a == d_ainv)
+    return fail(GPF_E_INVALID, "gpf_invert_fp64: bad arguments");
+  GPF_HIP(hipSetDevice(ctx->device));
+  double mp = 0.0;
+  GPF_TRY(invert_fp64(n, const_cast<double *>(d_a), d_ainv, as_stream(hip_stream), &mp));
+  if (min_pivot_rel) *min_pivot_rel = mp;
+  return GPF_OK;
+}
+
 gpf_status gpf_lgf_table(int nmax, double *h_table) {
   if (nmax < 0 || nmax > 8192 || !h_table) return fail(GPF_E_INVALID, "gpf_lgf_table: bad arguments");
   lgf_table_host(nmax, h_table);

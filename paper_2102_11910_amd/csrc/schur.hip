@@ -998,6 +998,252 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Blocked in-place Gauss-Jordan inverse with partial pivoting (the FP64
+// inverse of the Schur complement S, Sec. 2.2.2 and App. A), by panels of
+// kGjPanel columns K, out of place between two buffers (cur -> next):
+//  1. k_bgj_panel: one workgroup holds the n x |K| panel in registers and
+//     runs the column steps of K on it (pivot row = largest |entry| among
+//     the rows not yet pivotal, row exchange, in-place sweep), so that the
+//     panel's pivot rows hold A_KK^-1 and its other rows -A_IK A_KK^-1 (in
+//     the exchanged row order).  It records the pivots and the source row of
+//     every row after the exchanges.
+//  2. k_bgj_update: the other columns J, on FP64 matrix cores:
+//     next[K, J] = A_KK^-1 A_KJ,  next[I, J] = A_IJ - A_IK A_KK^-1 A_KJ,
+//     i.e. next[i, J] = (i in K ? 0 : cur[src(i), J]) + panel[i, :] cur[src(K), J].
+// After the last panel the exchanges are undone on the columns (k_bgj_order,
+// k_bgj_gather).
+// ---------------------------------------------------------------------------
+constexpr int kGjPanel = 16;
+constexpr int kGjThreads = 512;
+constexpr int kGjMaxN = 4 * kGjThreads;   // rows a panel workgroup holds (4 per thread)
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int R>
+__global__ __launch_bounds__(kGjThreads) void k_bgj_panel(int n, int k0, const double *__restrict__ cur,
+                                                         double *__restrict__ next, int *__restrict__ src,
+                                                         int *__restrict__ piv, double *__restrict__ pval) {
+  constexpr int NW = kGjThreads / 64;
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
+  __shared__ double prow_s[kGjPanel], swap_s[kGjPanel];
+  __shared__ int pr_s[kGjPanel], pos_s[2 * kGjPanel], from_s[2 * kGjPanel];
+  const int w = min(kGjPanel, n - k0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double v[R][kGjPanel];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + r * kGjThreads;
+#pragma unroll
+    for (int c = 0; c < kGjPanel; ++c) v[r][c] = (i < n && c < w) ? cur[(size_t)i * n + k0 + c] : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < kGjPanel; ++c) {
+    if (c >= w) continue;
+    const int k = k0 + c;
+    // pivot: largest |entry| of column k among rows >= k, lowest row on
+    // ties; row k itself when no entry compares (all NaN), so the pivot
+    // row is always in [k, n)
+    double bv = -1.0;
+    int bi = k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + r * kGjThreads;
+      const double a = fabs(v[r][c]);
+      if (i >= k && i < n && a > bv) {
+        bv = a;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[wave] = bv;
+      red_i[wave] = bi;
+    }
+    __syncthreads();
+    double pbest = red_v[0];
+    int pr = red_i[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+      const double ov = red_v[q];
+      const int oi = red_i[q];
+      if (ov > pbest || (ov == pbest && oi < pr)) {
+        pbest = ov;
+        pr = oi;
+      }
+    }
+    if (tid == 0) pr_s[c] = pr;
+    // the pivot row to LDS; row k to LDS when it moves to row pr
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + r * kGjThreads;
+      if (i == pr) {
+#pragma unroll
+        for (int cc = 0; cc < kGjPanel; ++cc) prow_s[cc] = v[r][cc];
+      }
+      if (i == k && pr != k) {
+#pragma unroll
+        for (int cc = 0; cc < kGjPanel; ++cc) swap_s[cc] = v[r][cc];
+      }
+    }
+    __syncthreads();
+    double prow[kGjPanel];
+#pragma unroll
+    for (int cc = 0; cc < kGjPanel; ++cc) prow[cc] = prow_s[cc];
+    const double p = prow[c];
+    if (tid == 0) {
+      piv[k] = pr;
+      pval[k] = p;
+    }
+    const double ip = p != 0.0 ? 1.0 / p : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < kGjPanel; ++cc) prow[cc] = cc == c ? ip : prow[cc] * ip;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + r * kGjThreads;
+      if (i == pr && pr != k) {
+#pragma unroll
+        for (int cc = 0; cc < kGjPanel; ++cc) v[r][cc] = swap_s[cc];
+      }
+      if (i == k) {
+#pragma unroll
+        for (int cc = 0; cc < kGjPanel; ++cc) v[r][cc] = prow[cc];
+      } else {
+        const double m = v[r][c];
+#pragma unroll
+        for (int cc = 0; cc < kGjPanel; ++cc) v[r][cc] = cc == c ? -m * ip : v[r][cc] - m * prow[cc];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + r * kGjThreads;
+    if (i < n) {
+#pragma unroll
+      for (int c = 0; c < kGjPanel; ++c)
+        if (c < w) next[(size_t)i * n + k0 + c] = v[r][c];
+      src[i] = i;
+    }
+  }
+  __syncthreads();   // the identity map is in place before the moved rows overwrite it
+  if (tid == 0) {
+    // rows the exchanges moved: replay them on the (at most 2w) rows involved
+    int m = 0;
+    for (int c = 0; c < w; ++c) {
+      const int a = k0 + c, b = pr_s[c];
+      int ia = -1, ib = -1;
+      for (int q = 0; q < m; ++q) {
+        if (pos_s[q] == a) ia = q;
+        if (pos_s[q] == b) ib = q;
+      }
+      if (ia < 0) {
+        pos_s[m] = a;
+        from_s[m] = a;
+        ia = m++;
+      }
+      if (ib < 0) {
+        pos_s[m] = b;
+        from_s[m] = b;
+        ib = m++;
+      }
+      const int t = from_s[ia];
+      from_s[ia] = from_s[ib];
+      from_s[ib] = t;
+    }
+    for (int q = 0; q < m; ++q) src[pos_s[q]] = from_s[q];
+  }
+}
+
+// next[i, j] for j outside the panel: 64 x 64 tiles, one 16-row band per
+// wave, 16 x 16 x 4 FP64 MFMA (lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
+// and, in accumulator register e = 0..3, D[4 e + l / 16][l % 16])
+__global__ __launch_bounds__(256) void k_bgj_update(int n, int k0, const double *__restrict__ cur,
+                                                    double *__restrict__ next, const int *__restrict__ src) {
+  const int w = min(kGjPanel, n - k0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = blockIdx.y * 64 + wave * 16, col0 = blockIdx.x * 64;
+  const int lr = lane & 15, lk = lane >> 4;
+  // A operand: panel rows of this band (already in the exchanged order)
+  double a[kGjPanel / 4];
+#pragma unroll
+  for (int kk = 0; kk < kGjPanel / 4; ++kk) {
+    const int c = 4 * kk + lk, i = row0 + lr;
+    a[kk] = (c < w && i < n) ? next[(size_t)i * n + k0 + c] : 0.0;
+  }
+  // B operand rows: cur at the source rows of the panel rows
+  int srck[kGjPanel / 4];
+#pragma unroll
+  for (int kk = 0; kk < kGjPanel / 4; ++kk) {
+    const int c = 4 * kk + lk;
+    srck[kk] = c < w ? src[k0 + c] : 0;
+  }
+  f64x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = col0 + 16 * t + lr;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = row0 + 4 * e + lk;
+      acc[t][e] = (i < n && j < n && (i < k0 || i >= k0 + w)) ? cur[(size_t)src[i] * n + j] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < kGjPanel / 4; ++kk) {
+    const int c = 4 * kk + lk;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = col0 + 16 * t + lr;
+      const double b = (c < w && j < n) ? cur[(size_t)srck[kk] * n + j] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = col0 + 16 * t + lr;
+    if (j >= n || (j >= k0 && j < k0 + w)) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = row0 + 4 * e + lk;
+      if (i < n) next[(size_t)i * n + j] = acc[t][e];
+    }
+  }
+}
+
+// column order of the inverse: the row exchanges replayed, in reverse, on
+// an index array (one workgroup; the array in LDS)
+__global__ __launch_bounds__(256) void k_bgj_order(int n, const int *__restrict__ piv, int *__restrict__ idx) {
+  __shared__ int ix[kGjMaxN];
+  for (int j = threadIdx.x; j < n; j += 256) ix[j] = j;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = n - 1; k >= 0; --k) {
+      const int r = piv[k];
+      const int t = ix[k];
+      ix[k] = ix[r];
+      ix[r] = t;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += 256) idx[j] = ix[j];
+}
+
+__global__ void k_bgj_gather(int n, const double *__restrict__ M, const int *__restrict__ idx,
+                             double *__restrict__ Ainv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= n) return;
+  Ainv[(size_t)i * n + j] = M[(size_t)i * n + idx[j]];
+}
 }  // namespace
 
 hipError_t launch_schur_build(int n, int ns, const int *st_i, const double *st_w,
@@ -1007,7 +1253,56 @@ hipError_t launch_schur_build(int n, int ns, const int *st_i, const double *st_w
   return hipGetLastError();
 }
 
+static gpf_status invert_blocked(int n, const double *A, double *Ainv, hipStream_t s, DevBuf &pval) {
+  DevBuf W0, W1, src, piv, idx;
+  gpf_status st;
+  const size_t mb = (size_t)n * n * sizeof(double);
+  if ((st = W0.alloc(mb)) != GPF_OK) return st;
+  if ((st = W1.alloc(mb)) != GPF_OK) return st;
+  if ((st = src.alloc((size_t)n * sizeof(int))) != GPF_OK) return st;
+  if ((st = piv.alloc((size_t)n * sizeof(int))) != GPF_OK) return st;
+  if ((st = idx.alloc((size_t)n * sizeof(int))) != GPF_OK) return st;
+  if ((st = pval.alloc((size_t)n * sizeof(double))) != GPF_OK) return st;
+  const int R = (n + kGjThreads - 1) / kGjThreads;
+  const dim3 gu((n + 63) / 64, (n + 63) / 64);
+  const double *cur = A;
+  double *next = W0.as<double>();
+  for (int k0 = 0; k0 < n; k0 += kGjPanel) {
+    if (R <= 1)
+      hipLaunchKernelGGL(k_bgj_panel<1>, dim3(1), dim3(kGjThreads), 0, s, n, k0, cur, next, src.as<int>(),
+                         piv.as<int>(), pval.as<double>());
+    else if (R == 2)
+      hipLaunchKernelGGL(k_bgj_panel<2>, dim3(1), dim3(kGjThreads), 0, s, n, k0, cur, next, src.as<int>(),
+                         piv.as<int>(), pval.as<double>());
+    else
+      hipLaunchKernelGGL(k_bgj_panel<4>, dim3(1), dim3(kGjThreads), 0, s, n, k0, cur, next, src.as<int>(),
+                         piv.as<int>(), pval.as<double>());
+    hipLaunchKernelGGL(k_bgj_update, gu, dim3(256), 0, s, n, k0, cur, next, src.as<int>());
+    cur = next;
+    next = next == W0.as<double>() ? W1.as<double>() : W0.as<double>();
+  }
+  hipLaunchKernelGGL(k_bgj_order, dim3(1), dim3(256), 0, s, n, piv.as<int>(), idx.as<int>());
+  hipLaunchKernelGGL(k_bgj_gather, dim3((n + 255) / 256, n), dim3(256), 0, s, n, cur, idx.as<int>(), Ainv);
+  GPF_HIP(hipGetLastError());
+  GPF_HIP(hipStreamSynchronize(s));   // the work buffers are freed on return
+  return GPF_OK;
+}
+
 gpf_status invert_fp64(int ns, double *A, double *Ainv, hipStream_t s, double *min_pivot_rel) {
+  if (ns <= kGjMaxN) {
+    DevBuf pval;
+    GPF_TRY(invert_blocked(ns, A, Ainv, s, pval));
+    std::vector<double> hp(ns), ha((size_t)ns * ns);
+    GPF_HIP(hipMemcpyAsync(hp.data(), pval.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    GPF_HIP(hipMemcpyAsync(ha.data(), A, (size_t)ns * ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    GPF_HIP(hipStreamSynchronize(s));
+    double amax = 0.0, pmin = 1e300;
+    for (double v : ha) amax = std::max(amax, std::fabs(v));
+    for (double v : hp) pmin = std::min(pmin, std::fabs(v));
+    *min_pivot_rel = amax > 0.0 ? pmin / amax : 0.0;
+    return GPF_OK;
+  }
+  // larger systems: Gauss-Jordan on [A | I], two launches per column
   DevBuf M, col, piv;
   gpf_status st;
   if ((st = M.alloc((size_t)ns * 2 * ns * sizeof(double))) != GPF_OK) return st;

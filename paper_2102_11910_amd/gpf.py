@@ -121,6 +121,7 @@ def _load():
         "gpf_interpolate_surface": (I, [P, P, P, P]),
         "gpf_vortex_velocity": (I, [P, P, I, P, P, D, D, P, P, P, P]),
         "gpf_lgf_table": (I, [I, DP]),
+        "gpf_invert_fp64": (I, [P, I, P, P, P, DP]),
         "gpf_schedule_set": (I, [P, I, I, I, C.POINTER(gpf_schedule)]),
         "gpf_schedule_get": (I, [P, I, I, I, C.POINTER(gpf_schedule)]),
         "gpf_autotune": (I, [P, I, I, C.c_char_p, C.POINTER(gpf_schedule), DP]),
@@ -483,6 +484,16 @@ def gpf_convolve(plan: Plan, w, s, gamma_src: float, stream=None):
 def gpf_convolve_noalloc(plan: Plan, w, s, gamma_src: float, stream=None):
     check(lib.gpf_convolve_noalloc(plan.h, _ptr(w), _ptr(s), float(gamma_src),
                                    _stream_ptr(stream)), "gpf_convolve_noalloc")
+
+
+def gpf_invert_fp64(ctx: Context, a, ainv, stream=None) -> float:
+    """ainv = a^-1 for a square FP64 device tensor (row-major, contiguous);
+    returns min |pivot| / max |a_ij|."""
+    n = int(a.shape[0])
+    mp = C.c_double(0.0)
+    check(lib.gpf_invert_fp64(ctx.h, n, _ptr(a), _ptr(ainv), _stream_ptr(stream), C.byref(mp)),
+          "gpf_invert_fp64")
+    return mp.value
 
 
 def gpf_interpolate_surface(body: Body, s, r, stream=None):

@@ -62,3 +62,28 @@ def test_schur_columns_arguments_checked(ctx):
     with pytest.raises(gpf.GpfError) as e:
         body.schur_by_convolution(batch=0)
     assert e.value.status == gpf.GPF_E_INVALID
+
+
+def test_amplification_probe_on_the_oracle_schur(ctx):
+    """The precision policy's probe `amp`: how much more S^-1 amplifies the
+    alternating vector (+-max|y_s|, the finest pattern the surface carries)
+    than the smooth freestream right-hand side -y_s, relative to their
+    sizes.  The device value (from its FP64 inverse) equals the same
+    quantity formed with the oracle's LU factors of S, for the well
+    conditioned cylinder and the amplifying plate."""
+    import numpy as np
+    import scipy.linalg as sla
+    from tests.oracle_adapter import body_of
+    # the cylinder stays under the policy threshold (500), the plate exceeds it
+    for case, lo, hi in ((wl.config1(), 0.0, 500.0), (wl.config2(), 500.0, np.inf)):
+        _, body = body_for(ctx, case)
+        ob = body_of(case)
+        ys = np.asarray(case.surface.ys, np.float64)
+        r = -ys
+        a = np.where(np.arange(len(ys)) % 2 == 1, -1.0, 1.0) * np.abs(ys).max()
+        fr, fa = sla.lu_solve(ob.lu, r), sla.lu_solve(ob.lu, a)
+        ref = (np.linalg.norm(fa) / np.linalg.norm(fr)) * (np.linalg.norm(r) / np.linalg.norm(a))
+        amp = body.info()["amp"]
+        say(f"[amp] {case.name}: device {amp:.6g} oracle {ref:.6g}")
+        assert abs(amp - ref) <= 1e-8 * ref
+        assert lo <= amp <= hi
