@@ -713,6 +713,9 @@ def c5_leg(gpf, torch, np, ctx, log, wl, nreq=2000, slots=32):
             f"by n {entry['by_n']}")
     for r in reqs:
         gpf.gpf_sync(r[4].status)
+    nbatch, most = srv.stats()
+    res["server_batches"] = nbatch
+    res["server_most_batches_in_flight"] = most
     del bodies
     srv.close()
     return res

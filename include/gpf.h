@@ -359,13 +359,14 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
 /* ---- serving ----------------------------------------------------------- */
 
 /* A request server for independent solves (many callers, mixed grid sizes).
- * The server owns one resident plan per grid (gpf_server_plan), a HIP
- * stream, two sets of max_slots problem workspaces and a worker thread.
- * The worker takes queued requests in arrival order, up to max_slots at a
- * time, and solves them as one batch (gpf_solve_batched) while the previous
- * batch may still run on the device; completion is observed with an event
- * per batch.  Admission: a request is refused with GPF_E_NOMEM when the
- * server's resident plans plus both workspace sets at the largest grid seen
+ * The server owns one resident plan per grid (gpf_server_plan), three sets
+ * of max_slots problem workspaces, each with its own non-blocking HIP
+ * stream, and a worker thread.  The worker takes queued requests in arrival
+ * order, up to max_slots at a time, and solves them as one batch
+ * (gpf_solve_batched) on a free set's stream, so up to three batches run on
+ * the device at once; completion is observed with an event per batch.
+ * Admission: a request is refused with GPF_E_NOMEM when the server's
+ * resident plans plus the three workspace sets at the largest grid seen
  * would exceed hbm_budget_bytes (bodies belong to the caller and are not
  * counted), and with GPF_E_BUSY when 64 * max_slots requests are already
  * waiting.  plan_flags (GPF_FP32, GPF_POLICY_AUTO, ...) apply to every
@@ -382,8 +383,11 @@ gpf_status gpf_server_plan(gpf_server *srv, const gpf_grid *grid, gpf_plan **out
 /* Queue one solve (as gpf_solve) on the server plan of *grid; body may be
  * NULL for GPF_NOBODY and must otherwise have been created on that plan.
  * The inputs and outputs structs are copied; the device buffers they name
- * must stay valid and untouched until the request is done, and no two
- * requests in flight may share an output field.  Data-dependent errors go to
+ * must hold their final contents when the request is submitted (the
+ * server's streams do not wait for other streams: synchronize the stream
+ * that wrote or cleared them), stay valid and untouched until the request
+ * is done, and no two requests in flight may share an output field.
+ * Data-dependent errors go to
  * the request's d_status as with gpf_solve.  *request_id identifies the
  * request for gpf_server_poll / gpf_server_wait. */
 gpf_status gpf_server_submit(gpf_server *srv, const gpf_grid *grid, const gpf_body *body,
@@ -403,6 +407,10 @@ gpf_status gpf_server_wait(gpf_server *srv, unsigned long long request_id, doubl
 
 /* Finish every queued request, then free the server and its plans. */
 void gpf_server_destroy(gpf_server *srv);
+
+/* Batches dispatched so far and the most that were in flight on the device
+ * at once (at most three); either pointer may be null. */
+gpf_status gpf_server_stats(gpf_server *srv, unsigned long long *batches, int *max_inflight);
 
 /* ---- time stepping ------------------------------------------------------ */
 

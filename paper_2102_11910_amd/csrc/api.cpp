@@ -236,6 +236,16 @@ gpf_status upload_spectrum(gpf_plan *p, DevBuf &spec, DevBuf &tw) {
   return GPF_OK;
 }
 
+// Fill device memory and wait for the fill: the memory is then ready for
+// work on any stream, including non-blocking ones, which do not order after
+// the null stream that hipMemset runs on.  Used where buffers are created or
+// grown, never in a launch sequence.
+gpf_status fill_now(void *p, int value, size_t bytes) {
+  GPF_HIP(hipMemset(p, value, bytes));
+  GPF_HIP(hipStreamSynchronize(nullptr));
+  return GPF_OK;
+}
+
 constexpr int kPlanRingSlots = 64;
 constexpr size_t kProblemDescBytes = sizeof(ProbDesc) + 2 * sizeof(ConvDesc);
 
@@ -250,7 +260,7 @@ gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns, int 
   auto zeroed = [&](DevBuf &b, size_t bytes) -> gpf_status {
     if (b.bytes >= bytes) return GPF_OK;
     GPF_TRY(b.alloc(bytes));
-    GPF_HIP(hipMemset(b.p, 0, b.bytes));
+    GPF_TRY(fill_now(b.p, 0, b.bytes));
     return GPF_OK;
   };
   if (need32) {
@@ -280,7 +290,7 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
     const size_t tiles = (size_t)bin_tiles(n) + 1;
     if (bin_cnt.bytes < tiles * sizeof(int)) {
       GPF_TRY(bin_cnt.alloc(tiles * sizeof(int)));
-      GPF_HIP(hipMemset(bin_cnt.p, 0, bin_cnt.bytes));  // counts start (and end) at zero
+      GPF_TRY(fill_now(bin_cnt.p, 0, bin_cnt.bytes));  // counts start (and end) at zero
     }
     GPF_TRY(bin_start.alloc(tiles * sizeof(int)));
   }
@@ -908,7 +918,7 @@ gpf_status gpf_plan_create(gpf_ctx *ctx, const gpf_grid *grid, unsigned flags, g
     GPF_TRY(p->ws.ensure(n, true, false, 0));
   }
   GPF_TRY(p->status_scratch.alloc(256));
-  GPF_HIP(hipMemset(p->status_scratch.p, 0, 256));
+  GPF_TRY(fill_now(p->status_scratch.p, 0, 256));
   GPF_TRY(p->ring.init(kPlanRingSlots, kProblemDescBytes));
   GPF_HIP(hipDeviceSynchronize());
   *out = p.release();
@@ -958,8 +968,8 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   GPF_TRY(b->ghat.alloc(vb));
   GPF_TRY(b->nx.alloc(vb));
   GPF_TRY(b->ny.alloc(vb));
-  GPF_HIP(hipMemset(b->nx.p, 0, vb));
-  GPF_HIP(hipMemset(b->ny.p, 0, vb));
+  GPF_TRY(fill_now(b->nx.p, 0, vb));
+  GPF_TRY(fill_now(b->ny.p, 0, vb));
   b->hxs.assign(h_xs, h_xs + ns);
   b->hys.assign(h_ys, h_ys + ns);
   b->hds.assign(h_ds, h_ds + ns);
@@ -1008,7 +1018,7 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   GPF_HIP(hipMemcpy(Y.data(), dY.p, 3 * vb, hipMemcpyDeviceToHost));
   unsigned hstatus = 0;
   GPF_HIP(hipMemcpy(&hstatus, status, sizeof(unsigned), hipMemcpyDeviceToHost));
-  GPF_HIP(hipMemset(status, 0, sizeof(unsigned)));
+  GPF_TRY(fill_now(status, 0, sizeof(unsigned)));
   if (hstatus & GPF_DEV_OUT_OF_GRID) return fail(GPF_E_OUT_OF_GRID, "gpf_body_create: stencil outside grid");
   double g0 = 0.0, nr = 0.0, nf = 0.0, nrhs = 0.0, npert = 0.0;
   double mx = 0.0, my = 0.0, mr2 = 0.0;
@@ -1153,8 +1163,8 @@ gpf_status gpf_body_set_normals(gpf_body *body, const double *h_nx, const double
     }
   } else {
     // zero thickness: its two faces cancel in the motion term
-    GPF_HIP(hipMemset(body->nx.p, 0, vb));
-    GPF_HIP(hipMemset(body->ny.p, 0, vb));
+    GPF_TRY(fill_now(body->nx.p, 0, vb));
+    GPF_TRY(fill_now(body->ny.p, 0, vb));
     body->area = 0.0;
     double L = 0.0, sx = 0.0, sy = 0.0;
     for (int p = 0; p < ns; ++p) {
@@ -1755,7 +1765,7 @@ gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs
   GPF_TRY(rk->ft.alloc(ns * sizeof(double)));
   GPF_TRY(rk->sc.alloc(SC_COUNT * sizeof(double)));
   GPF_TRY(rk->status.alloc(sizeof(unsigned)));
-  GPF_HIP(hipMemset(rk->status.p, 0, sizeof(unsigned)));
+  GPF_TRY(fill_now(rk->status.p, 0, sizeof(unsigned)));
   rk->in1 = *in;
   rk->in1.d_xv = d_x;
   rk->in1.d_yv = d_y;
@@ -1936,7 +1946,7 @@ gpf_status gpf_shed_create(gpf_plan *plan, const gpf_body *body, const gpf_input
                       hipMemcpyDeviceToHost));
   }
   GPF_TRY(sh->last.alloc(GPF_MAX_EDGES * sizeof(int)));
-  GPF_HIP(hipMemset(sh->last.p, 0xff, GPF_MAX_EDGES * sizeof(int)));   // -1: nothing released
+  GPF_TRY(fill_now(sh->last.p, 0xff, GPF_MAX_EDGES * sizeof(int)));   // -1: nothing released
   if (parts) {
     double gw0[GPF_MAX_PARTS] = {};
     for (int j = 0; j < in->nparts; ++j) gw0[j] = in->parts[j].gamma_w;
@@ -2124,7 +2134,7 @@ gpf_status tune_precision(gpf_plan *plan, int nb, ConvSched *best, double *best_
   GPF_TRY(X.alloc(half * 2 * sizeof(T) * nb));
   GPF_TRY(out.alloc(cells * sizeof(T) * nb));
   GPF_TRY(desc.alloc(sizeof(ConvDesc) * nb));
-  GPF_HIP(hipMemset(src.p, 0, src.bytes));
+  GPF_TRY(fill_now(src.p, 0, src.bytes));
   std::vector<ConvDesc> cd(nb);
   for (int i = 0; i < nb; ++i) {
     ConvDesc &c = cd[i];

@@ -1,7 +1,9 @@
 // Request server for independent solves: callers queue requests from any
 // thread; one worker thread solves them in arrival order as batches of up to
-// max_slots problems on the server's stream, two batches in flight (one
-// workspace set each), and records each request's completion.
+// max_slots problems and records each request's completion.  It keeps
+// kServerSets workspace sets, each with its own stream: a batch goes to a
+// free set, so batches of different requests run on the device at the same
+// time (a small batch is not held behind a large one).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +36,8 @@ size_t slot_bytes(int n, int nv, int ns) {
   const size_t cap = nv > 1024 ? (size_t)nv : 1024;
   return 44 * (size_t)(n + 1) * n + 28 * cap + 72 * (size_t)ns + (1u << 20);
 }
+
+constexpr int kServerSets = 3;
 
 bool same_grid(const gpf_grid &a, const gpf_grid &b) {
   return a.n == b.n && a.dx == b.dx && a.x0 == b.x0 && a.y0 == b.y0;
@@ -73,11 +77,13 @@ struct gpf_server {
   unsigned long long next_id = 1;
   bool stop = false;
 
-  gpf_batch *batch[2] = {nullptr, nullptr};
-  hipStream_t stream = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  std::vector<Req> inflight[2];
-  bool busy[2] = {false, false};
+  gpf_batch *batch[kServerSets] = {};
+  hipStream_t stream[kServerSets] = {};
+  hipEvent_t ev[kServerSets] = {};
+  std::vector<Req> inflight[kServerSets];
+  bool busy[kServerSets] = {};
+  unsigned long long batches = 0;   // dispatched batches
+  int max_busy = 0;                 // most batches in flight at once
   std::thread worker;
 
   void run();
@@ -104,9 +110,9 @@ void gpf_server::retire(int k) {
   busy[k] = false;
 }
 
-// Solve one batch on the server stream (called without the lock held).  A
-// batch that the library refuses is retried request by request, so that one
-// bad request fails alone.
+// Solve one batch on the stream of workspace set k (called without the lock
+// held).  A batch that the library refuses is retried request by request, so
+// that one bad request fails alone.
 gpf_status gpf_server::dispatch(int k, std::vector<Req> &rs) {
   const int m = (int)rs.size();
   std::vector<gpf_plan *> pl(m);
@@ -119,11 +125,11 @@ gpf_status gpf_server::dispatch(int k, std::vector<Req> &rs) {
     in[i] = rs[i].in;
     out[i] = rs[i].out;
   }
-  gpf_status st = gpf_solve_batched(batch[k], m, pl.data(), bo.data(), in.data(), out.data(), stream);
+  gpf_status st = gpf_solve_batched(batch[k], m, pl.data(), bo.data(), in.data(), out.data(), stream[k]);
   if (st == GPF_OK) return GPF_OK;
   std::vector<Req> ok;
   for (int i = 0; i < m; ++i) {
-    const gpf_status s1 = gpf_solve_batched(batch[k], 1, &pl[i], &bo[i], &in[i], &out[i], stream);
+    const gpf_status s1 = gpf_solve_batched(batch[k], 1, &pl[i], &bo[i], &in[i], &out[i], stream[k]);
     if (s1 == GPF_OK) {
       ok.push_back(rs[i]);
     } else {
@@ -138,33 +144,41 @@ gpf_status gpf_server::dispatch(int k, std::vector<Req> &rs) {
 void gpf_server::run() {
   if (hipSetDevice(ctx->device) != hipSuccess) return;
   std::unique_lock<std::mutex> lk(mu);
-  int next = 0;   // workspace set of the next batch (sets alternate)
+  int next = 0;   // first workspace set to try (round robin)
   for (;;) {
-    for (int k = 0; k < 2; ++k)
+    int nbusy = 0;
+    for (int k = 0; k < kServerSets; ++k) {
       if (busy[k] && hipEventQuery(ev[k]) == hipSuccess) retire(k);
-    if (!queue.empty() && !busy[next]) {
+      nbusy += busy[k] ? 1 : 0;
+    }
+    int k = -1;
+    for (int q = 0; q < kServerSets && k < 0; ++q)
+      if (!busy[(next + q) % kServerSets]) k = (next + q) % kServerSets;
+    if (!queue.empty() && k >= 0) {
       std::vector<Req> rs;
       while (!queue.empty() && (int)rs.size() < max_slots) {
         rs.push_back(queue.front());
         queue.pop_front();
       }
       lk.unlock();
-      dispatch(next, rs);
+      dispatch(k, rs);
       const bool any = !rs.empty();
-      const hipError_t e = any ? hipEventRecord(ev[next], stream) : hipSuccess;
+      const hipError_t e = any ? hipEventRecord(ev[k], stream[k]) : hipSuccess;
       lk.lock();
       if (!any) continue;
       if (e != hipSuccess) {
         finish(rs, GPF_E_DEVICE);
         continue;
       }
-      inflight[next] = std::move(rs);
-      busy[next] = true;
-      next ^= 1;
+      inflight[k] = std::move(rs);
+      busy[k] = true;
+      ++batches;
+      max_busy = std::max(max_busy, nbusy + 1);
+      next = (k + 1) % kServerSets;
       continue;
     }
-    if (stop && queue.empty() && !busy[0] && !busy[1]) break;
-    if (busy[0] || busy[1])
+    if (stop && queue.empty() && nbusy == 0) break;
+    if (nbusy > 0)
       cv_work.wait_for(lk, std::chrono::microseconds(20));   // poll the in-flight batches
     else
       cv_work.wait(lk);
@@ -172,11 +186,11 @@ void gpf_server::run() {
 }
 
 gpf_server::~gpf_server() {
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < kServerSets; ++k) {
     if (ev[k]) (void)hipEventDestroy(ev[k]);
     gpf_batch_destroy(batch[k]);
+    if (stream[k]) (void)hipStreamDestroy(stream[k]);
   }
-  if (stream) (void)hipStreamDestroy(stream);
   for (auto &p : plans) gpf_plan_destroy(p.second);
 }
 
@@ -195,11 +209,11 @@ gpf_status gpf_server_create(gpf_ctx *ctx, size_t hbm_budget_bytes, int max_slot
   s->budget = hbm_budget_bytes;
   s->max_slots = max_slots;
   s->flags = plan_flags;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < kServerSets; ++k) {
     GPF_TRY(gpf_batch_create(ctx, max_slots, &s->batch[k]));
     GPF_HIP(hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming));
+    GPF_HIP(hipStreamCreateWithFlags(&s->stream[k], hipStreamNonBlocking));
   }
-  GPF_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
   gpf_server *raw = s.get();
   s->worker = std::thread([raw] { raw->run(); });
   *out = s.release();
@@ -215,7 +229,7 @@ gpf_status gpf_server_plan(gpf_server *srv, const gpf_grid *grid, gpf_plan **out
       return GPF_OK;
     }
   const size_t need = srv->plans_total + plan_bytes(grid->n) +
-                      2 * (size_t)srv->max_slots *
+                      kServerSets * (size_t)srv->max_slots *
                           slot_bytes(std::max(srv->n_hw, grid->n), srv->nv_hw, srv->ns_hw);
   if (need > srv->budget)
     return gpf::fail(GPF_E_NOMEM, "gpf_server_plan: the plan would exceed the server's HBM budget");
@@ -239,12 +253,12 @@ gpf_status gpf_server_submit(gpf_server *srv, const gpf_grid *grid, const gpf_bo
   if (body && body->plan != plan)
     return gpf::fail(GPF_E_INVALID, "gpf_server_submit: body not created on the server plan of this grid");
   {
-    // admission: both workspace sets at the high-water sizes must fit
+    // admission: every workspace set at the high-water sizes must fit
     std::lock_guard<std::mutex> lk(srv->plan_mu);
     const int n = std::max(srv->n_hw, grid->n);
     const int nv = std::max(srv->nv_hw, in->nv);
     const int ns = std::max(srv->ns_hw, body ? body->ns : 0);
-    if (srv->plans_total + 2 * (size_t)srv->max_slots * slot_bytes(n, nv, ns) > srv->budget)
+    if (srv->plans_total + kServerSets * (size_t)srv->max_slots * slot_bytes(n, nv, ns) > srv->budget)
       return gpf::fail(GPF_E_NOMEM, "gpf_server_submit: request exceeds the server's HBM budget");
     srv->n_hw = n;
     srv->nv_hw = nv;
@@ -307,8 +321,17 @@ void gpf_server_destroy(gpf_server *srv) {
     srv->cv_work.notify_all();
   }
   if (srv->worker.joinable()) srv->worker.join();
-  (void)hipStreamSynchronize(srv->stream);
+  for (int k = 0; k < kServerSets; ++k)
+    if (srv->stream[k]) (void)hipStreamSynchronize(srv->stream[k]);
   delete srv;
+}
+
+gpf_status gpf_server_stats(gpf_server *srv, unsigned long long *batches, int *max_inflight) {
+  if (!srv) return gpf::fail(GPF_E_INVALID, "gpf_server_stats: null server");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (batches) *batches = srv->batches;
+  if (max_inflight) *max_inflight = srv->max_busy;
+  return GPF_OK;
 }
 
 }  // extern "C"

@@ -152,6 +152,7 @@ def _load():
         "gpf_server_poll": (I, [P, C.c_ulonglong, C.POINTER(C.c_int), DP]),
         "gpf_server_wait": (I, [P, C.c_ulonglong, DP]),
         "gpf_server_destroy": (None, [P]),
+        "gpf_server_stats": (I, [P, C.POINTER(C.c_ulonglong), C.POINTER(C.c_int)]),
         "gpf_sync": (I, [P, P]),
         "gpf_last_error": (C.c_char_p, []),
         "gpf_version": (C.c_char_p, []),
@@ -417,6 +418,8 @@ class Outputs:
         self.ft = torch.empty_like(self.f) if ns else None
         self.scalars = torch.zeros(N_SCALARS, dtype=torch.float64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        # the clears are done before any stream (the server's are non-blocking) writes
+        torch.cuda.current_stream(dev).synchronize()
         self.struct = make_outputs(self.psi, self.u if nv else None, self.v if nv else None,
                                    self.f, self.ft, self.scalars, self.status)
 
@@ -597,6 +600,12 @@ class Server:
         lat = C.c_double()
         check(lib.gpf_server_wait(self.h, rid, C.byref(lat)), "gpf_server_wait")
         return lat.value
+
+    def stats(self):
+        """(batches dispatched, most batches in flight at once)"""
+        b, m = C.c_ulonglong(), C.c_int()
+        check(lib.gpf_server_stats(self.h, C.byref(b), C.byref(m)), "gpf_server_stats")
+        return b.value, m.value
 
     def close(self):
         if self.h:

@@ -100,3 +100,43 @@ def test_server_errors(ctx):
         tiny.plan(256, 0.01)
     assert e.value.status == gpf.GPF_E_NOMEM
     tiny.close()
+
+
+def test_batches_overlap_on_the_device(ctx):
+    """One request per batch, a dozen large requests queued at once: the
+    worker puts consecutive batches on different workspace sets and streams
+    before the earlier ones finish, and every result still equals the same
+    request solved alone."""
+    srv = gpf.Server(ctx, 16 << 30, max_slots=1)
+    cases = [wl.random_case(300 + k, 1024, 2.56 / 1024, 20000 + 3000 * k,
+                            surface=("cylinder", "ellipse", "plate")[k % 3],
+                            mode="shed" if k % 3 == 2 else None) for k in range(12)]
+    plan = srv.plan(1024, 2.56 / 1024)
+    bodies, ins, keep = [], [], []
+    for c in cases:
+        sf = c.surface
+        edges = tuple(c.edges) if c.mode == "shed" else ()
+        bodies.append(gpf.Body(plan, sf.xs, sf.ys, sf.ds, edges))
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(DEV) for a in (c.X, c.Y, c.G))
+        keep.append((X, Y, G))
+        ins.append(gpf.make_inputs(X, Y, G, c.u_inf, c.v_inf, c.ub, c.vb, c.omega, c.mode,
+                                   c.gamma_b, znew=c.znew))
+    outs = [gpf.Outputs(c.n, c.nv, c.surface.ns) for c in cases]
+    say(f"[server overlap] {len(cases)} requests on 1024^2, one per batch")
+    ids = [srv.submit(plan, b, i, o.struct) for b, i, o in zip(bodies, ins, outs)]
+    for r in ids:
+        srv.wait(r)
+    for o in outs:
+        gpf.gpf_sync(o.status)
+    nbatch, most = srv.stats()
+    say(f"   batches {nbatch}, most in flight at once {most}")
+    assert nbatch == len(cases) and 2 <= most <= 3
+    for c, b, i, o in zip(cases, bodies, ins, outs):
+        ref = gpf.Outputs(c.n, c.nv, c.surface.ns)
+        gpf.gpf_solve(plan, b, i, ref.struct)
+        gpf.gpf_sync(ref.status)
+        es = rell2(o.psi.double().cpu().numpy(), ref.psi.double().cpu().numpy())
+        eu = rell2(np.r_[o.u.cpu().numpy(), o.v.cpu().numpy()], np.r_[ref.u.cpu().numpy(), ref.v.cpu().numpy()])
+        ef = rell2(o.f.cpu().numpy(), ref.f.cpu().numpy())
+        assert es <= 1e-5 and eu <= 1e-5 and ef <= 1e-4, (c.name, es, eu, ef)
+    srv.close()
