@@ -300,7 +300,10 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
     GPF_TRY(sorted.alloc(4 * cap * sizeof(double)));
     nv = (int)cap;
   }
-  if (n > 0) GPF_TRY(items.alloc(4 * sizeof(int) * (1 + (size_t)tile_items_max(n, nv))));
+  if (n > 0) {
+    GPF_TRY(items.alloc(4 * sizeof(int) * (1 + (size_t)tile_items_max(n, nv))));
+    GPF_TRY(halo.alloc(sizeof(double) * kHaloRing * (size_t)std::max(1, bin_tiles(n))));
+  }
   return GPF_OK;
 }
 
@@ -389,6 +392,7 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.bin_cnt = ws->bin_cnt.as<int>();
   pd.bin_start = ws->bin_start.as<int>();
   pd.items = ws->items.as<int>();
+  pd.halo = ws->halo.p;
   pd.rank = ws->rank.as<int>();
   pd.sorted = ws->sorted.as<double>();
   pd.status = out->d_status;
@@ -602,11 +606,13 @@ bool mergeable(const GroupCfg &c) {
 }
 
 // Bytes of the descriptor block of a merged batch of nb problems: the
-// problem and convolution descriptors, then the work tables of the
-// multi-size passes (three per convolution, two convolutions, two classes).
+// problem and convolution descriptors, the work tables of the multi-size
+// passes (three per convolution, two convolutions, two classes), then the
+// flat block maps (binning, tile scatter, halo fix-up, two velocity kernels:
+// five entries per problem).
 size_t merged_block_bytes(int nb) {
   return ((size_t)nb * kProblemDescBytes + 15) / 16 * 16 + 9 * (size_t)nb * sizeof(MultiEntry) +
-         4 * (size_t)nb * sizeof(FlatEntry);
+         5 * (size_t)nb * sizeof(FlatEntry);
 }
 
 // Every stage of the solve as one launch per precision class over problems
@@ -692,14 +698,17 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto tile_blocks = [&](int i) { return tile_items_max(pd[i].n, pd[i].nv); };
   auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
-  FlatMap fsa[2], fsb[2], fvel[2];
+  auto halo_blocks = [&](int i) { return pd[i].nv > 0 ? fixup_blocks(pd[i].n) : 0; };
+  FlatMap fsa[3], fsb[3], fvel[2];
   if (na > 0) {
     make_flat(0, na, bin_blocks, &fsa[0]);
     make_flat(0, na, tile_blocks, &fsa[1]);
+    make_flat(0, na, halo_blocks, &fsa[2]);
   }
   if (nbb > 0) {
     make_flat(na, nb, bin_blocks, &fsb[0]);
     make_flat(na, nb, tile_blocks, &fsb[1]);
+    make_flat(na, nb, halo_blocks, &fsb[2]);
   }
   make_flat(0, nb, vel_gather, &fvel[0]);
   make_flat(0, nb, vel_tiles, &fvel[1]);
@@ -731,8 +740,8 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto fixf = [&](FlatMap *fm, int k) {
     for (int i = 0; i < k; ++i) fm[i].e = reinterpret_cast<const FlatEntry *>(base + (size_t)fm[i].e);
   };
-  if (na > 0) fixf(fsa, 2);
-  if (nbb > 0) fixf(fsb, 2);
+  if (na > 0) fixf(fsa, 3);
+  if (nbb > 0) fixf(fsb, 3);
   fixf(fvel, 2);
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
@@ -1435,6 +1444,7 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   pd.bin_cnt = plan->ws.bin_cnt.as<int>();
   pd.bin_start = plan->ws.bin_start.as<int>();
   pd.items = plan->ws.items.as<int>();
+  pd.halo = plan->ws.halo.p;
   pd.rank = plan->ws.rank.as<int>();
   pd.sorted = plan->ws.sorted.as<double>();
   if (d_status) pd.status = d_status;

@@ -204,6 +204,8 @@ struct ProbDesc {
   // vortex binning by tiles of cells: counts (zero between solves), tile
   // starts, rank of each vortex in its tile, tile-sorted (xi, eta, Gamma/dx^2)
   int *bin_cnt, *bin_start, *rank;
+  void *halo;                   // per tile, the window nodes its neighbours own
+                                // (kHaloRing values of the field type)
   int *items;                   // work list of the tile kernels, 4 ints per item:
                                 // [0] = {count, 0, 0, 0}, then {tile, first record,
                                 // end record, 1 if the tile has other items}
@@ -247,6 +249,10 @@ int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n 
 // kTileChunk records each; tile_items_max bounds the items of a problem.
 constexpr int kTileChunk = 512;
 int tile_items_max(int n, int nv);
+// A tile's window (ts + 3)^2 nodes minus its own ts^2: 6 ts + 9 at most.
+constexpr int kHaloRing = 6 * 32 + 9;
+int halo_tiles(int n);   // tiles that neighbours' windows reach (0 for one tile)
+int fixup_blocks(int n); // workgroups of the halo pass of one problem
 
 // Flat grids of merged batches for the kernels that read n, nv and ns from
 // their descriptors: entry i gives the first block of problem `prob` in the
@@ -302,12 +308,15 @@ __device__ __forceinline__ bool flat_block(const FlatMap &fm, FlatBlock *fb) {
   fb->nblk = nblk;
   return ok;
 }
-// R_v: bin and sort the vortices by tile, then one workgroup per tile sums
-// the vortices of its 3 x 3 tile neighbourhood that reach its nodes, in
-// fixed point (order-independent, so the field is bitwise repeatable), and
-// adds them to the source field (zero, or the values to add to)
+// R_v: bin and sort the vortices by tile; one workgroup per work item sums
+// its vortices' stencils in an LDS window in fixed point, stores the tile's
+// own nodes into the source field (zero, or the values to add to) and the
+// nodes its neighbours own into the tile's halo slot; then one workgroup per
+// tile adds the neighbours' halos to its border nodes in a fixed order, so
+// the field is the same bits on every run (split dense tiles use atomics)
 // fm (merged batches): fm[0] the binning kernels' map (one block per 256
-// vortices), fm[1] the tile kernel's; nullptr: a 2-D grid of nb problems
+// vortices), fm[1] the tile kernel's, fm[2] the halo kernel's; nullptr: a
+// 2-D grid of nb problems
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
                                    const FlatMap *fm = nullptr);
@@ -471,7 +480,7 @@ struct gpf_workspace {
   int n = 0, ns = 0, nv = 0;
   gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y;
   gpf::DevBuf xb;   // compact band of the first convolution's column pass
-  gpf::DevBuf bin_cnt, bin_start, items, rank, sorted;
+  gpf::DevBuf bin_cnt, bin_start, items, rank, sorted, halo;
   // band: rows of a body's band (16-row groups), 0 without a body
   gpf_status ensure(int n, bool need32, bool need64, int ns, int band = 0);
   gpf_status ensure_vortices(int nv);

@@ -139,9 +139,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
 }
 
 // 2. one workgroup per problem: tile starts (exclusive scan of the counts),
-//    the list of non-empty tiles, the circulation and sum |Gamma| (partials
-//    summed in a fixed order, so every solve gives the same bits) and the
-//    fixed-point scale.
+//    the work list of the tile kernels, the circulation and sum |Gamma|
+//    (partials summed in a fixed order, so every solve gives the same bits)
+//    and the fixed-point scale; the halo slots of split tiles are cleared.
+template <class T>
 __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__restrict__ d) {
   __shared__ int wsum[kScatterBlock / 64];
   __shared__ double gsum[2][kScatterBlock / 64];
@@ -222,6 +223,11 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
     for (int k = 0; k < kPer; ++k) {
       const int c = cnts[k];
       const int parts = (c + kTileChunk - 1) / kTileChunk;
+      if (parts > 1) {
+        // the items of a split tile add their halos to the tile's slot
+        T *hal = static_cast<T *>(P.halo) + (size_t)(lo + k) * kHaloRing;
+        for (int h = 0; h < kHaloRing; ++h) hal[h] = (T)0;
+      }
       for (int j = 0; j < parts; ++j) {
         // last field: 0 the tile's only item, 1 the first of several, 2 a later one
         const int4 it = make_int4(lo + k, r + j * kTileChunk, min(r + c, r + (j + 1) * kTileChunk),
@@ -285,15 +291,29 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__r
 //    tile's records): the item's vortices add their 4 x 4 stencils to an
 //    LDS window of (ts+3)^2 nodes (nodes X0-1 .. X0+ts+1) in 64-bit fixed
 //    point, so the window's sums do not depend on the order of the
-//    additions.  The window is then added to the field (zero, or the values
-//    to add to).  Nodes of the tile that no other tile's window reaches
-//    (window-local 3 .. ts-1 on both axes: the left and lower neighbours
-//    reach 2 nodes in, the right and upper ones 1) are the item's alone when
-//    the tile has one item, and are stored; every other node, shared with
-//    other windows, takes one global atomic where the window holds weight.
-//    The tile's count is cleared for the next solve.
+//    additions.  The tile's own ts^2 nodes (window-local 1 .. ts) are then
+//    stored into the field (zero, or the values to add to); the other
+//    6 ts + 9 window nodes belong to neighbouring tiles and are stored in
+//    the tile's halo slot, which step 5 adds to their owners.  No global
+//    atomic is needed, and the field is the same bits on every run.  The
+//    items of a split tile (more than kTileChunk records) add their own
+//    nodes and their halos with atomics instead (the slot was cleared by
+//    step 2).  The tile's count is cleared for the next solve.
+// 5. one workgroup per tile whose neighbours' windows can reach it: each of
+//    its 6 ts - 9 border nodes (local 0, 1 or ts-1 on an axis) adds, in a
+//    fixed order, the halo values of the non-empty neighbours that reach it.
 constexpr int kTileBlock = 128;
 static_assert(kTileChunk % kTileBlock == 0, "an item's records are a whole number per thread");
+
+// index in a tile's halo slot of window node (kx, ky), a node outside the
+// tile's own 1 .. ts range on some axis: the row ky = 0, the rows ts+1 and
+// ts+2, then columns 0, ts+1 and ts+2 of rows 1 .. ts
+__device__ __forceinline__ int halo_index(int kx, int ky, int ts) {
+  const int bw = ts + 3;
+  if (ky == 0) return kx;
+  if (ky > ts) return bw + (ky - ts - 1) * bw + kx;
+  return 3 * bw + (ky - 1) * 3 + (kx == 0 ? 0 : kx - ts);
+}
 
 // Workgroup barrier that orders LDS accesses only: global stores and atomics
 // issued before it stay in flight.
@@ -336,6 +356,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
   const int sexp = FixedPoint<T>::B - (int)P.aux[SC_RV_SCALE];
   const double scale = ldexp(1.0, sexp), inv = ldexp(1.0, -sexp);
   T *w = static_cast<T *>(P.w);
+  T *halo = static_cast<T *>(P.halo);
   // one item per workgroup when the launch covers the work list (it is
   // sized for the most items a problem can have)
   for (int i = fb.blk; i < cnt; i += fb.nblk) {
@@ -380,19 +401,96 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
       }
     }
     lds_barrier();
+    T *hal = halo + (size_t)t * kHaloRing;
     for (int k = tid; k < nwin; k += kTileBlock) {
       const long long v = win[k];
-      if (v == 0) continue;
       const int kx = k % bw, ky = k / bw;
-      T *node = w + (size_t)(Y0 + ky) * n + X0 + kx;
       const T val = (T)((double)v * inv);
-      if (alone && kx >= 3 && kx <= ts - 1 && ky >= 3 && ky <= ts - 1) {
-        *node = P.w_accumulate ? *node + val : val;   // this item's alone
-      } else {
-        atomic_add(node, val);
+      if (kx >= 1 && kx <= ts && ky >= 1 && ky <= ts) {
+        if (v == 0) continue;
+        T *node = w + (size_t)(Y0 + ky) * n + X0 + kx;
+        if (alone)
+          *node = P.w_accumulate ? *node + val : val;
+        else
+          atomic_add(node, val);
+      } else if (alone) {
+        hal[halo_index(kx, ky, ts)] = val;   // every entry, zeros included
+      } else if (v != 0) {
+        atomic_add(hal + halo_index(kx, ky, ts), val);
       }
     }
     if (i + fb.nblk < cnt) lds_barrier();   // the window is cleared for the next item
+  }
+}
+
+// 5.: kFixupTiles tiles per workgroup, a few border nodes per thread; every
+// load a node needs (the neighbours' tile counts, their halo entries, the
+// node) is issued before any is used, and a neighbour without vortices
+// (whose halo slot holds nothing of this solve) is dropped by a select.
+constexpr int kFixupBlock = 256;
+constexpr int kFixupTiles = 4;
+constexpr int kBorderNodes = 6 * 32 - 9;   // of a 32 x 32 tile
+constexpr int kFixupPer = (kFixupTiles * kBorderNodes + kFixupBlock - 1) / kFixupBlock;
+
+template <class T>
+__global__ __launch_bounds__(kFixupBlock) void k_halo_fixup(const ProbDesc *__restrict__ d, FlatMap fm) {
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
+  if (tps < 2 || P.nv <= 0) return;
+  const T *__restrict__ halo = static_cast<const T *>(P.halo);
+  const int *__restrict__ start = P.bin_start;
+  T *w = static_cast<T *>(P.w);
+  size_t at[kFixupPer];
+  T own[kFixupPer], h[kFixupPer][3];
+  bool ok[kFixupPer], valid[kFixupPer][3];
+#pragma unroll
+  for (int u = 0; u < kFixupPer; ++u) {
+    const int e = threadIdx.x + u * kFixupBlock;
+    const int t = fb.blk * kFixupTiles + e / kBorderNodes, i = e % kBorderNodes;
+    ok[u] = e < kFixupTiles * kBorderNodes && t < ntiles;
+    // border node i of tile t: rows 0, 1 and ts-1, then columns 0, 1 and
+    // ts-1 of rows 2 .. ts-2
+    int lx, ly;
+    if (i < 3 * ts) {
+      const int r = i / ts;
+      ly = r < 2 ? r : ts - 1;
+      lx = i % ts;
+    } else {
+      const int j = i - 3 * ts, c = j % 3;
+      ly = 2 + j / 3;
+      lx = c < 2 ? c : ts - 1;
+    }
+    const int tc = ok[u] ? t : 0;
+    const int tx = tc % tps, ty = tc / tps;
+    const int x = tx * ts + lx, y = ty * ts + ly;
+    at[u] = (size_t)y * n + x;
+    own[u] = ok[u] ? w[at[u]] : (T)0;
+    // the (up to three) neighbours whose windows reach the node: the
+    // left/lower ones reach local 0 and 1, the right/upper ones local ts-1
+    const int sx = lx <= 1 ? -1 : (lx == ts - 1 ? 1 : 0);
+    const int sy = ly <= 1 ? -1 : (ly == ts - 1 ? 1 : 0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int dx = q == 1 ? 0 : sx, dy = q == 0 ? 0 : sy;   // (sx,0), (0,sy), (sx,sy)
+      const int nx = tx + dx, ny = ty + dy;
+      valid[u][q] = ok[u] && (dx != 0 || dy != 0) && !(q == 2 && (dx == 0 || dy == 0)) &&
+                    nx >= 0 && nx < tps && ny >= 0 && ny < tps;
+      const int nt = valid[u][q] ? ny * tps + nx : 0;
+      const int kx = x - (nx * ts - 1), ky = y - (ny * ts - 1);
+      h[u][q] = valid[u][q] ? halo[(size_t)nt * kHaloRing + halo_index(kx, ky, ts)] : (T)0;
+      // a neighbour without vortices wrote no halo: its count decides
+      valid[u][q] = valid[u][q] && start[nt + 1] != start[nt];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kFixupPer; ++u) {
+    if (!(valid[u][0] || valid[u][1] || valid[u][2])) continue;
+    T add = (T)0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) add += valid[u][q] ? h[u][q] : (T)0;
+    w[at[u]] = own[u] + add;
   }
 }
 
@@ -703,6 +801,10 @@ int bin_tiles(int n) {
   return (n / ts) * (n / ts);
 }
 
+int halo_tiles(int n) { return bin_tiles(n) > 1 ? bin_tiles(n) : 0; }
+
+int fixup_blocks(int n) { return (halo_tiles(n) + kFixupTiles - 1) / kFixupTiles; }
+
 // items of a problem: one per non-empty tile (at most min(tiles, nv)) plus
 // one per further kTileChunk records of a tile (sum over tiles of
 // floor((c - 1) / kTileChunk) <= nv / kTileChunk)
@@ -721,14 +823,17 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
                                    const FlatMap *fm) {
   timer_begin(GPF_TK_SCATTER, s);
   const FlatMap none{nullptr, 0, 0};
-  const FlatMap mb = fm ? fm[0] : none, mt = fm ? fm[1] : none;
+  const FlatMap mb = fm ? fm[0] : none, mt = fm ? fm[1] : none, mh = fm ? fm[2] : none;
   const int vb = scatter_blocks(nv_max);
   hipLaunchKernelGGL(k_bin_count, grid_of(fm ? &mb : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mb);
-  hipLaunchKernelGGL(k_bin_scan, dim3(nb), dim3(kScatterBlock), 0, s, d);
+  hipLaunchKernelGGL((k_bin_scan<T>), dim3(nb), dim3(kScatterBlock), 0, s, d);
   hipLaunchKernelGGL(k_bin_place, grid_of(fm ? &mb : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mb);
-  // one workgroup per item of the work list
+  // one workgroup per item of the work list, then one per tile for the halos
   hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
                      dim3(kTileBlock), 0, s, d, mt);
+  if (fm ? mh.total > 0 : (nv_max > 0 && halo_tiles(n) > 0))
+    hipLaunchKernelGGL((k_halo_fixup<T>), grid_of(fm ? &mh : nullptr, fixup_blocks(n), nb), dim3(kFixupBlock),
+                       0, s, d, mh);
   timer_end(s);
   return hipGetLastError();
 }
