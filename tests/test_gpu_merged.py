@@ -248,3 +248,30 @@ def test_dense_tiles_split_into_items(ctx):
         eu = rell2(hm["uv"], np.r_[ref.u, ref.v])
         say(f"   oracle: s {es:.2e} f {ef:.2e} uv {eu:.2e}")
         assert es <= 1e-5 and ef <= 1e-4 and eu <= 1e-4
+
+
+def test_scattered_field_repeats_bit_for_bit(ctx):
+    """R_v without atomics (tiles of at most 512 vortices): the source field
+    is the same bits on every call, whatever order the workgroups run in
+    (sparse and dense clouds, one and several tiles per grid, overwrite and
+    accumulate).  Full solves are not compared this way: R_s f still adds
+    with atomics."""
+    cases = [wl.random_case(251, 512, 2.56 / 512, 20000, surface="ellipse"),
+             wl.random_case(252, 256, 2.56 / 256, 3000, surface="plate", mode="shed"),
+             wl.random_case(253, 1024, 2.56 / 1024, 4000, surface="cylinder"),
+             wl.random_case(254, 128, 2.0 / 128, 6000, surface="cylinder"),
+             wl.random_case(255, 32, 2.0 / 32, 300, surface=None)]
+    for c in cases:
+        plan = gpf.Plan(ctx, c.n, c.dx)
+        X, Y, G = (torch.as_tensor(a, dtype=torch.float64).to(DEV) for a in (c.X, c.Y, c.G))
+        fields = []
+        for rep in range(3):
+            w = torch.full((c.n, c.n), float("nan"), dtype=plan.field_dtype, device=DEV)
+            gpf.gpf_regularize_vortices(plan, X, Y, G, w)
+            gpf.gpf_regularize_vortices(plan, X, Y, G, w, accumulate=True)   # 2 R_v
+            torch.cuda.synchronize()
+            fields.append(w.cpu().numpy())
+        same = all(np.array_equal(fields[0], f) for f in fields[1:])
+        ok = np.isfinite(fields[0]).all() and np.abs(fields[0]).max() > 0
+        say(f"[R_v repeat] {c.name} nv={c.nv}: bit-identical {same}, finite {ok}")
+        assert same and ok, c.name
