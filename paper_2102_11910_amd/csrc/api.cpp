@@ -531,7 +531,7 @@ template <class TW, class T1, class T2>
 gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const ConvDesc *c1,
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, bool impulse,
                         int band, int xcds, const ConvSched &sc1, const ConvSched &sc2,
-                        bool shared, const double *shared_sinv, hipStream_t s) {
+                        bool shared, const double *shared_sinv, int vel_kinds, hipStream_t s) {
   GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
   GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body ? band : 0, s, sc1)));
   if (cfg.body) {
@@ -544,7 +544,7 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
     }
     GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2)));
   }
-  GPF_HIP(launch_solve_velocity<T2>(pd, nb, cfg.n, nv_max, s));
+  GPF_HIP(launch_solve_velocity<T2>(pd, nb, cfg.n, nv_max, s, nullptr, vel_kinds));
   if (impulse) GPF_HIP(launch_impulse(pd, nb, s));
   return GPF_OK;
 }
@@ -560,8 +560,10 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   int nv_max = 0, ns_max = 0, m_max = 0;
   int band = 0;   // rows of the first convolution's last pass (16-row groups)
   bool impulse = false;
+  int vel_kinds = 0;   // velocity kernels the group needs: 1 vortex by vortex, 2 tile by tile
   for (int i = 0; i < nb; ++i) {
     describe(probs[i], cfg, pd[i], c1[i], c2[i]);
+    if (pd[i].u && pd[i].nv > 0) vel_kinds |= pd[i].vel_tiles ? 2 : 1;
     nv_max = std::max(nv_max, pd[i].nv);
     ns_max = std::max(ns_max, pd[i].ns);
     m_max = std::max(m_max, pd[i].sv.m);
@@ -588,14 +590,14 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   if (cfg.fp64_plan)
     return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, s);
   if (cfg.conv1_fp64)
     return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, s);
   return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, s);
 }
 
 // A batch can run merged when its problems differ only in grid size and in

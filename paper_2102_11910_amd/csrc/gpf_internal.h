@@ -369,10 +369,11 @@ hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStre
 // tile by tile through LDS, the others vortex by vortex in record order; n
 // the largest grid of the launch
 // fm (merged batches): fm[0] the vortex-by-vortex kernel's map, fm[1] the
-// tile kernel's; nullptr: 2-D grids of nb problems
+// tile kernel's; nullptr: 2-D grids of nb problems, of the kernels `kinds`
+// asks for (1 vortex by vortex, 2 tile by tile, 3 both)
 template <class T>
 hipError_t launch_solve_velocity(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
-                                 const FlatMap *fm = nullptr);
+                                 const FlatMap *fm = nullptr, int kinds = 3);
 
 // xo = x + a u, yo = y + a v (in place allowed)
 // pressure (Sec. 2.6.1): three-point weights of a surface point on the

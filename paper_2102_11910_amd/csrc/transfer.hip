@@ -892,24 +892,24 @@ template hipError_t launch_interp_columns<double>(int, int, int, int, const int 
 
 template <class T>
 hipError_t launch_solve_velocity(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
-                                 const FlatMap *fm) {
+                                 const FlatMap *fm, int kinds) {
   if (nv_max <= 0) return hipSuccess;
   timer_begin(GPF_TK_VELOCITY, s);
   const FlatMap none{nullptr, 0, 0};
   const FlatMap mg = fm ? fm[0] : none, mt = fm ? fm[1] : none;
-  if (!fm || mg.total > 0)
+  if (fm ? mg.total > 0 : (kinds & 1) != 0)
     hipLaunchKernelGGL((k_vortex_velocity<T>), grid_of(fm ? &mg : nullptr, (nv_max + 255) / 256, nb),
                        dim3(256), 0, s, d, mg, 1);
-  if (!fm || mt.total > 0)
+  if (fm ? mt.total > 0 : (kinds & 2) != 0)
     hipLaunchKernelGGL((k_tile_velocity<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
                        dim3(kTileBlock), 0, s, d, mt);
   timer_end(s);
   return hipGetLastError();
 }
 template hipError_t launch_solve_velocity<float>(const ProbDesc *, int, int, int, hipStream_t,
-                                                 const FlatMap *);
+                                                 const FlatMap *, int);
 template hipError_t launch_solve_velocity<double>(const ProbDesc *, int, int, int, hipStream_t,
-                                                  const FlatMap *);
+                                                  const FlatMap *, int);
 
 template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s) {
