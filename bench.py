@@ -347,6 +347,21 @@ def _oracle_worker(idx, barrier):
     return t0, t1, sum(w[3] for w in work)
 
 
+def host_cpu() -> dict:
+    """The host the oracle ran on: CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0)),
+            "os_cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(budget_s: float = 12.0, workers: int = 0) -> dict:
     """The FP64 oracle on the 64-problem batch.  One thread: problems in
     order, each set up untimed and solved once, until the solves have taken
@@ -901,6 +916,7 @@ def main() -> int:
         cpu = dict(one)
         if allc:
             cpu["all_cores"] = allc
+        cpu["host"] = host_cpu()
         log(f"[bench] CPU oracle: {cpu}")
 
     import numpy as np
@@ -1022,6 +1038,9 @@ def main() -> int:
                   "latency_ms": {"p50": float(np.percentile(lat_p, 50)),
                                  "p99": float(np.percentile(lat_p, 99))}},
         "speedup_vs_plain": value / value_plain,
+        # two R -> L^-1 -> E passes per solve (R_v, L^-1, E_s; then R_s, L^-1, E_v)
+        "secondary": {"passes_grid_points_per_s": 2.0 * value,
+                      "plain_passes_grid_points_per_s": 2.0 * value_plain},
         "value_with_kernel_events": gp * K / wall_ev,
         "roofline": roofline,
         "convolution_batched": conv_batched,
