@@ -60,14 +60,20 @@ def problem_bytes(n: int, nv: int, ns: int, m: int, conv1_fp64: bool, band: int)
     """Algorithmic bytes of one problem of the merged batch, per kernel class
     of the step: the FP32 passes of both convolutions (the first one keeps
     only the `band` rows the surface stencils read), or the FP64 passes of a
-    first convolution the precision policy puts in FP64."""
+    first convolution the precision policy puts in FP64.  When both
+    convolutions are FP32 and no new vortices are added (m = 0), the source
+    changes between them only in the band rows (R_s f), and the second
+    forward row pass transforms only those rows: the other rows of the
+    intermediate are the first pass's."""
     w = 8 if conv1_fp64 else 4
     half = n * (n + 1)
+    reuse = not conv1_fp64 and m == 0
+    fwd_rows = band if reuse else n
     out = {"scatter": 24 * nv + w * n * n,
            "surface": 8 * ns * ns + 8 * ns * (4 + 3 * (1 + m)),
            "velocity": 32 * nv,
            # second convolution, FP32 transforms (source in the w type)
-           "rows_fwd": w * n * n + 8 * half,
+           "rows_fwd": fwd_rows * (w * n + 8 * (n + 1)),
            "cols": 16 * half + 4 * (n + 1) ** 2,
            "rows_inv": 8 * half + 4 * n * n}
     if conv1_fp64:

@@ -375,6 +375,10 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   std::memset(&c2, 0, sizeof(c2));
   c1.row_lo = c2.row_lo = 0;
   c1.row_hi = c2.row_hi = p->grid.n - 1;
+  c1.fwd_lo = c2.fwd_lo = 0;
+  c1.fwd_hi = c2.fwd_hi = p->grid.n - 1;
+  c1.keep_lo = c2.keep_lo = 0;   // empty: nothing kept
+  c1.keep_end = c2.keep_end = 0;
   pd.n = p->grid.n;
   pd.dx = p->grid.dx;
   pd.x0 = p->grid.x0;
@@ -525,13 +529,29 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   c2.c = p->gauge_c;
   c2.zero_in = 1;   // the last reader of the source: leave it zero
   set_inf(c2);
+  // Between the two convolutions the source changes only where R_s f lands,
+  // the rows of the surface stencils (no new vortices in the modes without
+  // them).  When both convolutions share the intermediate (the first one's
+  // column pass writes only its band rows to X, or none), the second one's
+  // forward row pass redoes only the band rows: the others of X still hold
+  // the first pass's transforms.  The first pass then clears the rows
+  // outside the band, the second the band rows.
+  if (c1.X == c2.X && pd.sv.m == 0 && !pd.w_accumulate) {
+    const int lo = b->row_lo & ~15, hi = std::min(p->grid.n - 1, b->row_hi | 15);
+    c1.zero_in = 1;
+    c1.keep_lo = lo;
+    c1.keep_end = hi + 1;
+    c2.fwd_lo = lo;
+    c2.fwd_hi = hi;
+  }
 }
 
 template <class TW, class T1, class T2>
 gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const ConvDesc *c1,
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, bool impulse,
                         int band, int xcds, const ConvSched &sc1, const ConvSched &sc2,
-                        bool shared, const double *shared_sinv, int vel_kinds, hipStream_t s) {
+                        bool shared, const double *shared_sinv, int vel_kinds, int fband2,
+                        hipStream_t s) {
   GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
   GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body ? band : 0, s, sc1)));
   if (cfg.body) {
@@ -542,7 +562,7 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
       if (shared) GPF_HIP(launch_schur_gemm(pd, nb, ns_max, m_max, shared_sinv, s));
       GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, m_max, s));
     }
-    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2)));
+    GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2, fband2)));
   }
   GPF_HIP(launch_solve_velocity<T2>(pd, nb, cfg.n, nv_max, s, nullptr, vel_kinds));
   if (impulse) GPF_HIP(launch_impulse(pd, nb, s));
@@ -561,8 +581,10 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   int band = 0;   // rows of the first convolution's last pass (16-row groups)
   bool impulse = false;
   int vel_kinds = 0;   // velocity kernels the group needs: 1 vortex by vortex, 2 tile by tile
+  int fband2 = 0;      // source rows the second forward row pass transforms (most of any problem)
   for (int i = 0; i < nb; ++i) {
     describe(probs[i], cfg, pd[i], c1[i], c2[i]);
+    fband2 = std::max(fband2, c2[i].fwd_hi - c2[i].fwd_lo + 1);
     if (pd[i].u && pd[i].nv > 0) vel_kinds |= pd[i].vel_tiles ? 2 : 1;
     nv_max = std::max(nv_max, pd[i].nv);
     ns_max = std::max(ns_max, pd[i].ns);
@@ -590,14 +612,14 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   if (cfg.fp64_plan)
     return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, s);
   if (cfg.conv1_fp64)
     return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, s);
   return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, s);
 }
 
 // A batch can run merged when its problems differ only in grid size and in
@@ -666,8 +688,10 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
       e[i - lo].first = first;
       e[i - lo].prob = i - lo;
       e[i - lo].logn = lg;
-      e[i - lo].band = kind == 2 ? 1 : 0;
-      first += multi_blocks(kind == 3 ? 0 : kind, n, cd[i]);
+      // band flag: the inverse pass of a first convolution covers its output
+      // band; a forward pass covers its source rows fwd_lo .. fwd_hi
+      e[i - lo].band = kind == 2 || kind == 0 ? 1 : 0;
+      first += multi_blocks(kind, n, cd[i]);
     }
     mp->nprob = hi - lo;
     mp->total = first;

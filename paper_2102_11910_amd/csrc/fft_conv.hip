@@ -377,7 +377,8 @@ __device__ __forceinline__ int xcd_block(int remap) {
 // ---------------------------------------------------------------------------
 // row-pair block `blk` of one problem (rows 2 SEQ blk ..), LDS of SEQ rows
 template <class Tin, class T, int N, int SH>
-__device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, typename CT<T>::V *lds) {
+__device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, int band,
+                                              typename CT<T>::V *lds) {
   using V = typename CT<T>::V;
   using P = RowPlan<T, N, SH>;
   constexpr int n = N / 2;
@@ -385,9 +386,16 @@ __device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, typena
   V *__restrict__ X = static_cast<V *>(C.X);
   const V *__restrict__ tw = static_cast<const V *>(C.tw);
   const int tid = threadIdx.x;
-  const int j0 = blk * 2 * P::SEQ;
+  // band: the grid covers source rows fwd_lo .. fwd_hi only (the other rows
+  // of X keep an earlier pass's transforms); a workgroup of more than 16
+  // rows may reach past fwd_hi and neither transforms nor stores those rows
+  const int lo = band ? C.fwd_lo : 0;
+  const int hi_row = band ? C.fwd_hi : n - 1;
+  const int j0 = lo + blk * 2 * P::SEQ;
+  if (j0 > hi_row) return;
 
   const int q = tid / P::TPS, lane = tid % P::TPS;
+  const bool live = j0 + 2 * q <= hi_row;   // this sequence's row pair is transformed
   V x[kE];
   V wr[tw_regs<N>()];
   if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, lane);
@@ -396,36 +404,39 @@ __device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, typena
     const size_t row = (size_t)(j0 + 2 * q) * n;
 #pragma unroll
     for (int k = 0; k < kE / 2; ++k) {
-      x[k].x = (T)w[row + lane + k * P::TPS];
-      x[k].y = (T)w[row + n + lane + k * P::TPS];
+      x[k].x = live ? (T)w[row + lane + k * P::TPS] : (T)0;
+      x[k].y = live ? (T)w[row + n + lane + k * P::TPS] : (T)0;
     }
   }
+  constexpr int RW = 2 * P::SEQ;
   if (C.zero_in) {
     // the source is cleared after it is read, which needs a barrier; the
     // same barrier tells whether the workgroup's rows hold anything.  Rows
     // that hold nothing (a band away from the vortices and the body)
     // transform to nothing: the workgroup then only stores zeros, and has
-    // nothing to clear.
+    // nothing to clear.  Rows keep_lo .. keep_end-1 stay for a later pass.
     bool nz = false;
 #pragma unroll
     for (int k = 0; k < kE / 2; ++k) nz = nz || x[k].x != (T)0 || x[k].y != (T)0;
     if (!__syncthreads_or(nz)) {
-      constexpr int RW0 = 2 * P::SEQ;
       V zero;
       zero.x = (T)0;
       zero.y = (T)0;
-      for (int idx = tid; idx < (n + 1) * RW0; idx += P::WGT)
-        X[(size_t)(idx / RW0) * n + j0 + idx % RW0] = zero;
+      for (int idx = tid; idx < (n + 1) * RW; idx += P::WGT)
+        if (j0 + idx % RW <= hi_row) X[(size_t)(idx / RW) * n + j0 + idx % RW] = zero;
       return;
     }
-    for (int idx = tid; idx < 2 * P::SEQ * n; idx += P::WGT) w[(size_t)j0 * n + idx] = (Tin)0;
+    for (int idx = tid; idx < RW * n; idx += P::WGT) {
+      const int r = j0 + idx / n;
+      if (r <= hi_row && (r < C.keep_lo || r >= C.keep_end)) w[(size_t)j0 * n + idx] = (Tin)0;
+    }
   }
   fft_seq<T, N, false, true, false, true, false>(x, lds + q * P::LDS_SEQ, wr, tw, lane);
 
   // unpack: A = (Z[k] + conj Z[N-k]) / 2, B = (Z[k] - conj Z[N-k]) / (2i)
-  constexpr int RW = 2 * P::SEQ;
   for (int idx = tid; idx < (n + 1) * RW; idx += P::WGT) {
     const int k = idx / RW, jj = idx % RW;
+    if (j0 + jj > hi_row) continue;
     const V *L = lds + (jj >> 1) * P::LDS_SEQ;
     const V zk = L[pad(k)];
     const V zm = L[pad((N - k) & (N - 1))];
@@ -443,10 +454,10 @@ __device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, typena
 
 template <class Tin, class T, int N, bool WIDE>
 __global__ __launch_bounds__((RowPlan<T, N, WIDE ? kWide : kNarrow>::WGT)) void k_rows_fwd(
-    const ConvDesc *__restrict__ cd, int remap) {
+    const ConvDesc *__restrict__ cd, int remap, int band) {
   using P = RowPlan<T, N, WIDE ? kWide : kNarrow>;
   __shared__ typename CT<T>::V lds[P::SEQ * P::LDS_SEQ];
-  rows_fwd_body<Tin, T, N, WIDE ? kWide : kNarrow>(cd[blockIdx.y], xcd_block(remap), lds);
+  rows_fwd_body<Tin, T, N, WIDE ? kWide : kNarrow>(cd[blockIdx.y], xcd_block(remap), band, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -757,10 +768,13 @@ int row_remap(const ConvSched &sc, int xcds) {
 }
 
 template <class Tin, class T, int N, bool WIDE>
-void launch_rows_fwd(const ConvDesc *d, int nb, int xcds, const ConvSched &sc, hipStream_t st) {
+// fband > 0: only that many source rows per problem, from its fwd_lo on
+void launch_rows_fwd(const ConvDesc *d, int nb, int xcds, const ConvSched &sc, hipStream_t st,
+                     int fband) {
   using RP = RowPlan<T, N, WIDE ? kWide : kNarrow>;
-  hipLaunchKernelGGL((k_rows_fwd<Tin, T, N, WIDE>), dim3(N / 2 / (2 * RP::SEQ), nb), dim3(RP::WGT),
-                     0, st, d, row_remap<T, N, WIDE>(sc, xcds));
+  const int rows = fband > 0 ? std::min(fband, N / 2) : N / 2;
+  hipLaunchKernelGGL((k_rows_fwd<Tin, T, N, WIDE>), dim3((rows + 2 * RP::SEQ - 1) / (2 * RP::SEQ), nb),
+                     dim3(RP::WGT), 0, st, d, row_remap<T, N, WIDE>(sc, xcds), fband > 0 ? 1 : 0);
 }
 // band > 0: only that many rows per problem, from its row_lo's 16-row group
 template <class T, int N, bool WIDE>
@@ -774,7 +788,7 @@ void launch_rows_inv(const ConvDesc *d, int nb, int xcds, int band, const ConvSc
 
 template <class Tin, class T, int N>
 hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, const ConvSched &sc,
-                    hipStream_t st) {
+                    hipStream_t st, int fband) {
   const bool pruned = band > 0;
   using P = Plan<N>;
   constexpr int n = N / 2;
@@ -785,9 +799,9 @@ hipError_t run_conv(const ConvDesc *d, int nb, int xcds, int band, const ConvSch
   constexpr bool D = std::is_same<T, double>::value;
   timer_begin(D ? GPF_TK_ROWS_FWD64 : GPF_TK_ROWS_FWD, st);
   if (wide)
-    launch_rows_fwd<Tin, T, N, true>(d, nb, xcds, sc, st);
+    launch_rows_fwd<Tin, T, N, true>(d, nb, xcds, sc, st, fband);
   else
-    launch_rows_fwd<Tin, T, N, false>(d, nb, xcds, sc, st);
+    launch_rows_fwd<Tin, T, N, false>(d, nb, xcds, sc, st, fband);
   timer_end(st);
   timer_begin(D ? GPF_TK_COLS64 : GPF_TK_COLS, st);
   // FP64 from N = 1024 on: the split-exchange column pass unless the
@@ -873,12 +887,12 @@ __global__ __launch_bounds__(kMultiThreads) void k_rows_fwd_multi(const ConvDesc
   if (!multi_locate(mp, &p, &logn, &band, &blk)) return;
   const ConvDesc &C = cd[p];
   switch (logn) {
-    case 6: rows_fwd_body<Tin, T, 128, kMulti>(C, blk, lds); break;
-    case 7: rows_fwd_body<Tin, T, 256, kMulti>(C, blk, lds); break;
-    case 8: rows_fwd_body<Tin, T, 512, kMulti>(C, blk, lds); break;
-    case 9: rows_fwd_body<Tin, T, 1024, kMulti>(C, blk, lds); break;
-    case 10: rows_fwd_body<Tin, T, 2048, kMulti>(C, blk, lds); break;
-    case 11: rows_fwd_body<Tin, T, 4096, kMulti>(C, blk, lds); break;
+    case 6: rows_fwd_body<Tin, T, 128, kMulti>(C, blk, band, lds); break;
+    case 7: rows_fwd_body<Tin, T, 256, kMulti>(C, blk, band, lds); break;
+    case 8: rows_fwd_body<Tin, T, 512, kMulti>(C, blk, band, lds); break;
+    case 9: rows_fwd_body<Tin, T, 1024, kMulti>(C, blk, band, lds); break;
+    case 10: rows_fwd_body<Tin, T, 2048, kMulti>(C, blk, band, lds); break;
+    case 11: rows_fwd_body<Tin, T, 4096, kMulti>(C, blk, band, lds); break;
     default: break;
   }
 }
@@ -931,7 +945,8 @@ int multi_blocks(int pass, int n, const ConvDesc &c) {
     const int band = (c.row_hi | 15) - (c.row_lo & ~15) + 1;
     return (band + rows - 1) / rows;
   }
-  return n / rows;
+  if (pass == 0) return (c.fwd_hi - c.fwd_lo + 1 + rows - 1) / rows;   // source rows transformed
+  return n / rows;                        // 3: every row of the inverse
 }
 
 template <class Tin, class T>
@@ -954,25 +969,25 @@ template hipError_t launch_convolve_multi<double, float>(const ConvDesc *, const
 
 template <class Tin, class T>
 hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t st,
-                           const ConvSched &sc) {
+                           const ConvSched &sc, int fband) {
   switch (n) {
-    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, band, sc, st);
-    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, band, sc, st);
-    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, band, sc, st);
-    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, band, sc, st);
-    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, band, sc, st);
-    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, band, sc, st);
-    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, band, sc, st);
-    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, band, sc, st);
+    case 16: return run_conv<Tin, T, 32>(d, nb, xcds, band, sc, st, fband);
+    case 32: return run_conv<Tin, T, 64>(d, nb, xcds, band, sc, st, fband);
+    case 64: return run_conv<Tin, T, 128>(d, nb, xcds, band, sc, st, fband);
+    case 128: return run_conv<Tin, T, 256>(d, nb, xcds, band, sc, st, fband);
+    case 256: return run_conv<Tin, T, 512>(d, nb, xcds, band, sc, st, fband);
+    case 512: return run_conv<Tin, T, 1024>(d, nb, xcds, band, sc, st, fband);
+    case 1024: return run_conv<Tin, T, 2048>(d, nb, xcds, band, sc, st, fband);
+    case 2048: return run_conv<Tin, T, 4096>(d, nb, xcds, band, sc, st, fband);
     default: return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_convolve<float, float>(int, const ConvDesc *, int, int, int, hipStream_t,
-                                                     const ConvSched &);
+                                                     const ConvSched &, int);
 template hipError_t launch_convolve<double, double>(int, const ConvDesc *, int, int, int, hipStream_t,
-                                                     const ConvSched &);
+                                                     const ConvSched &, int);
 template hipError_t launch_convolve<double, float>(int, const ConvDesc *, int, int, int, hipStream_t,
-                                                     const ConvSched &);
+                                                     const ConvSched &, int);
 
 }  // namespace gpf

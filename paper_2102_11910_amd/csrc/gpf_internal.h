@@ -182,6 +182,13 @@ struct ConvDesc {
   int band_pitch;
   int add_inf;         // add s_inf = inf_u (oy + j h) - inf_v (ox + i h) to the output
   double inf_u, inf_v, ox, oy, h;
+  // forward row pass: with its band flag it transforms only source rows
+  // fwd_lo .. fwd_hi (fwd_lo a multiple of 16), the other rows of X holding
+  // the transforms of an earlier pass over the same source; when it clears
+  // the source (zero_in) it leaves rows keep_lo <= j < keep_end for a later
+  // pass (a zeroed descriptor keeps nothing)
+  int fwd_lo, fwd_hi;
+  int keep_lo, keep_end;
 };
 
 struct ProbDesc {
@@ -335,18 +342,22 @@ struct MultiPass {
   int total;            // blocks of the launch
   int xcds;             // XCDs the workgroups are dealt to (>= 1)
 };
-// blocks of one problem in a multi-size pass (0 rows forward, 1 columns,
-// 2 rows inverse over the band of the descriptor, 3 rows inverse, all rows)
+// blocks of one problem in a multi-size pass (0 rows forward over the
+// descriptor's source rows fwd_lo .. fwd_hi, 1 columns, 2 rows inverse over
+// the band of the descriptor, 3 rows inverse, all rows)
 int multi_blocks(int pass, int n, const ConvDesc &c);
 // the three passes of one convolution per problem; mp[0..2] the passes' tables
 template <class Tin, class T>
 hipError_t launch_convolve_multi(const ConvDesc *d, const MultiPass *mp, hipStream_t s);
 // band > 0: the descriptors restrict the output rows, and no problem needs
 // more than `band` rows from the 16-row group of its row_lo (narrow inverse
-// rows over that band only); 0: every row.  sc: launch schedule.
+// rows over that band only); 0: every row.  fband > 0: the forward row pass
+// transforms only each descriptor's source rows fwd_lo .. fwd_hi, at most
+// fband of them (the other rows of X are kept); 0: every row.  sc: launch
+// schedule.
 template <class Tin, class T>
 hipError_t launch_convolve(int n, const ConvDesc *d, int nb, int xcds, int band, hipStream_t s,
-                           const ConvSched &sc);
+                           const ConvSched &sc, int fband = 0);
 // the fixed device scratch of gpf_convolve_noalloc: its address on `device`
 // (which must be current) is taken once; called when a context is created
 gpf_status noalloc_init(int device);
