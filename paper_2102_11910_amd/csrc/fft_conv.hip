@@ -400,15 +400,24 @@ __device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, int ba
   V wr[tw_regs<N>()];
   if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, lane);
   {
-    // elements lane + k * TPS of the packed row pair; k >= 8 is the zero half
-    const size_t row = (size_t)(j0 + 2 * q) * n;
+    // elements lane + k * TPS of the packed row pair; k >= 8 is the zero half.
+    // A sequence past the range reads the workgroup's first pair (j0 is even
+    // and hi_row odd, so j0 + 1 <= hi_row) and drops it by a select: the
+    // loads stay unconditional and are issued together.
+    const size_t row = (size_t)(live ? j0 + 2 * q : j0) * n;
 #pragma unroll
     for (int k = 0; k < kE / 2; ++k) {
-      x[k].x = live ? (T)w[row + lane + k * P::TPS] : (T)0;
-      x[k].y = live ? (T)w[row + n + lane + k * P::TPS] : (T)0;
+      const T a = (T)w[row + lane + k * P::TPS];
+      const T b = (T)w[row + n + lane + k * P::TPS];
+      x[k].x = live ? a : (T)0;
+      x[k].y = live ? b : (T)0;
     }
   }
   constexpr int RW = 2 * P::SEQ;
+  // rows j0 .. j0 + nr - 1 of the workgroup are covered; nr < RW only where
+  // a band ends inside the workgroup, and the guarded loops below run only
+  // there
+  const int nr = min(RW, hi_row - j0 + 1);
   if (C.zero_in) {
     // the source is cleared after it is read, which needs a barrier; the
     // same barrier tells whether the workgroup's rows hold anything.  Rows
@@ -423,20 +432,23 @@ __device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, int ba
       zero.x = (T)0;
       zero.y = (T)0;
       for (int idx = tid; idx < (n + 1) * RW; idx += P::WGT)
-        if (j0 + idx % RW <= hi_row) X[(size_t)(idx / RW) * n + j0 + idx % RW] = zero;
+        if (idx % RW < nr) X[(size_t)(idx / RW) * n + j0 + idx % RW] = zero;
       return;
     }
-    for (int idx = tid; idx < RW * n; idx += P::WGT) {
-      const int r = j0 + idx / n;
-      if (r <= hi_row && (r < C.keep_lo || r >= C.keep_end)) w[(size_t)j0 * n + idx] = (Tin)0;
+    if (nr == RW && (C.keep_end <= j0 || C.keep_lo >= j0 + RW)) {
+      for (int idx = tid; idx < RW * n; idx += P::WGT) w[(size_t)j0 * n + idx] = (Tin)0;
+    } else {
+      for (int idx = tid; idx < RW * n; idx += P::WGT) {
+        const int r = j0 + idx / n;
+        if (r - j0 < nr && (r < C.keep_lo || r >= C.keep_end)) w[(size_t)j0 * n + idx] = (Tin)0;
+      }
     }
   }
   fft_seq<T, N, false, true, false, true, false>(x, lds + q * P::LDS_SEQ, wr, tw, lane);
 
   // unpack: A = (Z[k] + conj Z[N-k]) / 2, B = (Z[k] - conj Z[N-k]) / (2i)
-  for (int idx = tid; idx < (n + 1) * RW; idx += P::WGT) {
+  auto unpack = [&](int idx) {
     const int k = idx / RW, jj = idx % RW;
-    if (j0 + jj > hi_row) continue;
     const V *L = lds + (jj >> 1) * P::LDS_SEQ;
     const V zk = L[pad(k)];
     const V zm = L[pad((N - k) & (N - 1))];
@@ -449,6 +461,12 @@ __device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, int ba
       o.y = (T)0.5 * (zm.x - zk.x);
     }
     X[(size_t)k * n + j0 + jj] = o;
+  };
+  if (nr == RW) {
+    for (int idx = tid; idx < (n + 1) * RW; idx += P::WGT) unpack(idx);
+  } else {
+    for (int idx = tid; idx < (n + 1) * RW; idx += P::WGT)
+      if (idx % RW < nr) unpack(idx);
   }
 }
 
