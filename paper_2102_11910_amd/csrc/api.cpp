@@ -636,7 +636,7 @@ bool mergeable(const GroupCfg &c) {
 // five entries per problem).
 size_t merged_block_bytes(int nb) {
   return ((size_t)nb * kProblemDescBytes + 15) / 16 * 16 + 9 * (size_t)nb * sizeof(MultiEntry) +
-         5 * (size_t)nb * sizeof(FlatEntry);
+         6 * (size_t)nb * sizeof(FlatEntry);   // four binning maps per class, two velocity maps
 }
 
 // Every stage of the solve as one launch per precision class over problems
@@ -720,21 +720,24 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     fm->e = reinterpret_cast<const FlatEntry *>(flat_off + fused * sizeof(FlatEntry));  // offset for now
     fused += hi - lo;
   };
-  auto bin_blocks = [&](int i) { return std::max(1, (pd[i].nv + 255) / 256); };
+  auto bin_blocks = [&](int i) { return pd[i].nv > 0 ? bin_count_blocks(pd[i].nv) : 1; };
+  auto place_blocks = [&](int i) { return std::max(1, (pd[i].nv + 255) / 256); };
   auto tile_blocks = [&](int i) { return tile_items_max(pd[i].n, pd[i].nv); };
   auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
   auto halo_blocks = [&](int i) { return pd[i].nv > 0 ? fixup_blocks(pd[i].n) : 0; };
-  FlatMap fsa[3], fsb[3], fvel[2];
+  FlatMap fsa[4], fsb[4], fvel[2];
   if (na > 0) {
     make_flat(0, na, bin_blocks, &fsa[0]);
     make_flat(0, na, tile_blocks, &fsa[1]);
     make_flat(0, na, halo_blocks, &fsa[2]);
+    make_flat(0, na, place_blocks, &fsa[3]);
   }
   if (nbb > 0) {
     make_flat(na, nb, bin_blocks, &fsb[0]);
     make_flat(na, nb, tile_blocks, &fsb[1]);
     make_flat(na, nb, halo_blocks, &fsb[2]);
+    make_flat(na, nb, place_blocks, &fsb[3]);
   }
   make_flat(0, nb, vel_gather, &fvel[0]);
   make_flat(0, nb, vel_tiles, &fvel[1]);
@@ -766,8 +769,8 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto fixf = [&](FlatMap *fm, int k) {
     for (int i = 0; i < k; ++i) fm[i].e = reinterpret_cast<const FlatEntry *>(base + (size_t)fm[i].e);
   };
-  if (na > 0) fixf(fsa, 3);
-  if (nbb > 0) fixf(fsb, 3);
+  if (na > 0) fixf(fsa, 4);
+  if (nbb > 0) fixf(fsb, 4);
   fixf(fvel, 2);
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));

@@ -251,6 +251,25 @@ int scatter_blocks(int nv_max);
 // sum Gamma, sum Gamma x, sum Gamma y, sum Gamma (x^2 + y^2), sum |Gamma|
 constexpr int kMaxVortices = 1 << 22;
 constexpr int kPartStride = kMaxVortices / 256;
+// Vortices per thread of the binning count (256 threads per workgroup), a
+// power of two from 1 to 16.  A workgroup adds one device atomic per
+// non-empty tile to the tile counts, and the atomics on one counter are
+// carried out one after another; a thread's vortices, on the other hand,
+// are a serial chain of FP64 cell arithmetic and LDS atomics.  About 64
+// workgroups per problem measured best (32, 128 and 256, and one vortex
+// per thread, were slower on the 64-problem batch and the 1e5-vortex
+// single solve).
+__host__ __device__ inline int bin_per_thread(int nv) {
+  const int want = (nv + 256 * 64 - 1) / (256 * 64);
+  int p = 1;
+  while (p < want && p < 16) p *= 2;
+  return p;
+}
+// workgroups of the binning count of a problem (one partial each)
+__host__ __device__ inline int bin_count_blocks(int nv) {
+  const int per = 256 * bin_per_thread(nv);
+  return nv > 0 ? (nv + per - 1) / per : 1;
+}
 int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n < 32)
 // A tile of more than kTileChunk vortices is split into items of at most
 // kTileChunk records each; tile_items_max bounds the items of a problem.

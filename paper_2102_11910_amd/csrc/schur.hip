@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_impulse(const ProbDesc *__restrict__ d)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const SolveScalars &sv = P.sv;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;   // sums of (y, x, x^2 + y^2) times strength
-  const int nvb = (P.nv + 255) / 256;
+  const int nvb = P.nv > 0 ? bin_count_blocks(P.nv) : 0;   // workgroups of the binning count
   for (int b = tid; b < nvb; b += 256) {
     a0 += P.partials[2 * (size_t)kPartStride + b];
     a1 += P.partials[1 * (size_t)kPartStride + b];

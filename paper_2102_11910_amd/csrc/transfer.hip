@@ -62,36 +62,51 @@ __device__ __forceinline__ int vortex_tile(int i0, int j0, int ts, int tps) {
   return ((j0 + 1) / ts) * tps + (i0 + 1) / ts;
 }
 
-// 1. count vortices per tile.  A workgroup histograms its vortices in LDS,
-//    then adds each non-empty bin to the global count once; a vortex's rank
-//    in its tile = the workgroup's offset for the tile + its rank within the
-//    workgroup.  Each workgroup also stores its partial circulation, the
-//    moments of the circulation and the partial sum of |Gamma|.
-__global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__restrict__ d, FlatMap fm) {
-  __shared__ int hist[kMaxTiles];
-  __shared__ double red[5][kScatterBlock / 64];
-  FlatBlock fb;
-  if (!flat_block(fm, &fb)) return;
-  const ProbDesc &P = d[fb.prob];
-  // workgroups past this problem's vortices (a 2-D grid covers the largest
-  // problem of the launch) have nothing to do
-  if (fb.blk * kScatterBlock >= max(P.nv, 1)) return;
+// 1. count vortices per tile.  A workgroup histograms its 256 PER vortices
+//    in LDS, then adds each non-empty bin to the global count once; a
+//    vortex's rank in its tile = the workgroup's offset for the tile + its
+//    rank within the workgroup.  Each workgroup also stores its partial
+//    circulation, the moments of the circulation and the partial sum of
+//    |Gamma|, summed per thread in vortex order, then across the workgroup
+//    in a fixed order.
+template <int PER>
+__device__ __forceinline__ void bin_count_body(const ProbDesc &P, int blk, int *hist,
+                                               double (*red)[kScatterBlock / 64]) {
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
   for (int t = threadIdx.x; t < ntiles; t += kScatterBlock) hist[t] = 0;
+  // every load first; a thread past the last vortex reads the last one again
+  // and counts nothing
+  const int base = blk * kScatterBlock * PER + threadIdx.x;
+  double xs[PER], ys[PER], gs[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int q = min(base + k * kScatterBlock, P.nv - 1);
+    xs[k] = P.xv[q];
+    ys[k] = P.yv[q];
+    gs[k] = P.gv[q];
+  }
   __syncthreads();
-  const int q = fb.blk * kScatterBlock + threadIdx.x;
-  double gq = 0.0, xq = 0.0, yq = 0.0;
-  int tile = -1, lrank = 0;
-  if (q < P.nv) {
+  int tile[PER], lrank[PER];
+  double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    tile[k] = -1;
+    lrank[k] = 0;
+    if (base + k * kScatterBlock >= P.nv) continue;
     int i0, j0;
     double fx, fy;
-    const double x = P.xv[q], y = P.yv[q];
-    if (cell(x, P.x0, P.dx, 2, n - 3, &i0, &fx) && cell(y, P.y0, P.dx, 2, n - 3, &j0, &fy)) {
-      gq = P.gv[q];
-      xq = x;
-      yq = y;
-      tile = vortex_tile(i0, j0, ts, tps);
-      lrank = atomicAdd(hist + tile, 1);
+    if (cell(xs[k], P.x0, P.dx, 2, n - 3, &i0, &fx) && cell(ys[k], P.y0, P.dx, 2, n - 3, &j0, &fy)) {
+      // circulation and its first and second moments (the impulse of the
+      // vortices: the M4' weights reproduce x, y and x^2 + y^2 exactly), and
+      // sum |Gamma| for the fixed-point scale
+      const double g = gs[k], x = xs[k], y = ys[k];
+      mom[0] += g;
+      mom[1] += g * x;
+      mom[2] += g * y;
+      mom[3] += g * (x * x + y * y);
+      mom[4] += fabs(g);
+      tile[k] = vortex_tile(i0, j0, ts, tps);
+      lrank[k] = atomicAdd(hist + tile[k], 1);
     } else {
       atomicOr(P.status, GPF_DEV_OUT_OF_GRID);
     }
@@ -116,11 +131,11 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
     }
   }
   __syncthreads();
-  if (q < P.nv) P.rank[q] = tile >= 0 ? hist[tile] + lrank : -1;
-  // circulation and its first and second moments (the impulse of the
-  // vortices: the M4' weights reproduce x, y and x^2 + y^2 exactly), and
-  // sum |Gamma| for the fixed-point scale
-  double mom[5] = {gq, gq * xq, gq * yq, gq * (xq * xq + yq * yq), fabs(gq)};
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int q = base + k * kScatterBlock;
+    if (q < P.nv) P.rank[q] = tile[k] >= 0 ? hist[tile[k]] + lrank[k] : -1;
+  }
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
 #pragma unroll
@@ -134,7 +149,25 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
   if (threadIdx.x < 5) {
     double s = 0.0;
     for (int w = 0; w < kScatterBlock / 64; ++w) s += red[threadIdx.x][w];
-    P.partials[(size_t)threadIdx.x * kPartStride + fb.blk] = s;
+    P.partials[(size_t)threadIdx.x * kPartStride + blk] = s;
+  }
+}
+
+__global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__restrict__ d, FlatMap fm) {
+  __shared__ int hist[kMaxTiles];
+  __shared__ double red[5][kScatterBlock / 64];
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  // workgroups past this problem's vortices (a 2-D grid covers the largest
+  // problem of the launch) have nothing to do
+  if (P.nv <= 0 || fb.blk >= bin_count_blocks(P.nv)) return;
+  switch (bin_per_thread(P.nv)) {
+    case 1: bin_count_body<1>(P, fb.blk, hist, red); break;
+    case 2: bin_count_body<2>(P, fb.blk, hist, red); break;
+    case 4: bin_count_body<4>(P, fb.blk, hist, red); break;
+    case 8: bin_count_body<8>(P, fb.blk, hist, red); break;
+    default: bin_count_body<16>(P, fb.blk, hist, red); break;
   }
 }
 
@@ -168,7 +201,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
   // circulation and sum |Gamma| over the bin_count partials, strided per
   // thread, then waves, in a fixed order
   double g = 0.0, ga = 0.0;
-  const int nvb = (P.nv + kScatterBlock - 1) / kScatterBlock;   // workgroups of bin_count
+  const int nvb = P.nv > 0 ? bin_count_blocks(P.nv) : 0;   // workgroups of bin_count
   for (int b = tid; b < nvb; b += kScatterBlock) {
     g += P.partials[b];
     ga += P.partials[4 * (size_t)kPartStride + b];
@@ -824,10 +857,13 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   timer_begin(GPF_TK_SCATTER, s);
   const FlatMap none{nullptr, 0, 0};
   const FlatMap mb = fm ? fm[0] : none, mt = fm ? fm[1] : none, mh = fm ? fm[2] : none;
-  const int vb = scatter_blocks(nv_max);
-  hipLaunchKernelGGL(k_bin_count, grid_of(fm ? &mb : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mb);
+  const FlatMap mp = fm ? fm[3] : none;
+  // the count's workgroups take up to 4096 vortices (bin_per_thread); the
+  // place kernel one per thread
+  const int cb = nv_max > 0 ? bin_count_blocks(nv_max) : 1, vb = scatter_blocks(nv_max);
+  hipLaunchKernelGGL(k_bin_count, grid_of(fm ? &mb : nullptr, cb, nb), dim3(kScatterBlock), 0, s, d, mb);
   hipLaunchKernelGGL((k_bin_scan<T>), dim3(nb), dim3(kScatterBlock), 0, s, d);
-  hipLaunchKernelGGL(k_bin_place, grid_of(fm ? &mb : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mb);
+  hipLaunchKernelGGL(k_bin_place, grid_of(fm ? &mp : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mp);
   // one workgroup per item of the work list, then one per tile for the halos
   hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
                      dim3(kTileBlock), 0, s, d, mt);
