@@ -322,13 +322,17 @@ constexpr int kRStage = 6144;                  // rhs doubles staged in LDS
 
 constexpr int kPre = 4;   // slices of 64 of each S^-1 row a wave loads up front
 
-// MC: columns of the rhs a launch can have (1 + the largest m)
-template <class T, int MC>
+// MC: columns of the rhs a launch can have (1 + the largest m).  RPW: rows
+// of S^-1 per wave (4 rows per workgroup and wave count); launches with few
+// workgroups take one row per wave, so that more workgroups share the rows.
+template <class T, int MC, int RPW>
 __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict__ d) {
+  constexpr int CR = 4 * RPW;      // surface rows per workgroup
+  constexpr int PRE = 16 / RPW;    // slices of 64 of each row a wave loads up front
   __shared__ double rs[kRStage];
   __shared__ double red[4][MC];                  // per-wave parts of ghat . rhs_c
   __shared__ double ye[GPF_MAX_EDGES][MC];       // y_c / f0 at the edge points
-  __shared__ double yr[kCRows][MC];              // y_c at this workgroup's rows
+  __shared__ double yr[CR][MC];              // y_c at this workgroup's rows
   __shared__ double scal[3 + GPF_MAX_EDGES];     // c1, s0, Gamma_b, Gamma_j
   __shared__ double circ[MC];                    // ghat . rhs_c
   __shared__ double A[GPF_MAX_EDGES][GPF_MAX_EDGES + 1];
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   __shared__ int singular_flag;
   const ProbDesc &P = d[blockIdx.y];
   const int ns = P.ns;
-  const int row0 = blockIdx.x * kCRows;
+  const int row0 = blockIdx.x * CR;
   if (row0 >= ns) return;
   const SolveScalars &sv = P.sv;
   const int mode = sv.mode;
@@ -346,6 +350,13 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   const double gw_dev = P.aux[SC_GAMMA_W];
+  // the finishing step's loads (this thread's row and stencil node) do not
+  // depend on the solve: issued first
+  const int lr = tid >> 4, node = tid & 15;
+  const int pf = min(row0 + min(lr, CR - 1), ns - 1);
+  const double f0p = P.f0[pf], dsp = P.ds[pf];
+  const int sti = P.st_i[2 * pf], stj = P.st_i[2 * pf + 1];
+  const double swa = P.st_w[8 * pf + (node & 3)], swb = P.st_w[8 * pf + 4 + (node >> 2)];
   size_t coff[MC];   // column offsets, clamped to the last column
 #pragma unroll
   for (int c = 0; c < MC; ++c) coff[c] = (size_t)min(c, ncol - 1) * ns;
@@ -373,7 +384,7 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
       const int kp = sv.edges[e];
       if (c < ncol) ye[e][c] = Y[(size_t)c * ns + kp] / P.f0[kp];
     }
-    if (tid < kCRows * MC) {
+    if (tid < CR * MC) {
       const int rr = tid / MC, c = tid - rr * MC;
       if (c < ncol && row0 + rr < ns) yr[rr][c] = Y[(size_t)c * ns + row0 + rr];
     }
@@ -382,16 +393,16 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   // that each wave keeps many of them in flight; sums of clamped terms
   // are discarded.  The first slices of this wave's rows of S^-1 and of
   // ghat do not depend on the rhs: they are issued before it is staged.
-  const int r0 = row0 + wave * kRowsPerWave;
-  const int nr = min(kRowsPerWave, ns - r0);
-  const double *arow[kRowsPerWave];
+  const int r0 = row0 + wave * RPW;
+  const int nr = min(RPW, ns - r0);
+  const double *arow[RPW];
 #pragma unroll
-  for (int r = 0; r < kRowsPerWave; ++r) arow[r] = P.sinv + (size_t)min(r0 + r, ns - 1) * ns;
-  double apre[kPre][kRowsPerWave];
+  for (int r = 0; r < RPW; ++r) arow[r] = P.sinv + (size_t)min(r0 + r, ns - 1) * ns;
+  double apre[PRE][RPW];
 #pragma unroll
-  for (int i = 0; i < kPre; ++i)
+  for (int i = 0; i < PRE; ++i)
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) apre[i][r] = arow[r][min(lane + 64 * i, ns - 1)];
+    for (int r = 0; r < RPW; ++r) apre[i][r] = arow[r][min(lane + 64 * i, ns - 1)];
   const double gpre = P.ghat[min(tid, ns - 1)];
   const double *R = P.rhs;
   if (ncol * ns <= kRStage) {
@@ -441,48 +452,48 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
       }
     }
   }
-  // this workgroup's rows: kRowsPerWave per wave, interleaved over q
+  // this workgroup's rows: RPW per wave, interleaved over q
   {
-    double acc[kRowsPerWave][MC];
+    double acc[RPW][MC];
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r)
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
       for (int c = 0; c < MC; ++c) acc[r][c] = 0.0;
     if (nr > 0) {
 #pragma unroll
-      for (int i = 0; i < kPre; ++i) {
+      for (int i = 0; i < PRE; ++i) {
         const int q = lane + 64 * i;
         if (q < ns) {
           double rq[MC];
 #pragma unroll
           for (int c = 0; c < MC; ++c) rq[c] = R[coff[c] + q];
 #pragma unroll
-          for (int r = 0; r < kRowsPerWave; ++r)
+          for (int r = 0; r < RPW; ++r)
 #pragma unroll
             for (int c = 0; c < MC; ++c) acc[r][c] += apre[i][r] * rq[c];
         }
       }
 #pragma unroll 2
-      for (int q = lane + 64 * kPre; q < ns; q += 64) {
-        double aq[kRowsPerWave], rq[MC];
+      for (int q = lane + 64 * PRE; q < ns; q += 64) {
+        double aq[RPW], rq[MC];
 #pragma unroll
-        for (int r = 0; r < kRowsPerWave; ++r) aq[r] = arow[r][q];
+        for (int r = 0; r < RPW; ++r) aq[r] = arow[r][q];
 #pragma unroll
         for (int c = 0; c < MC; ++c) rq[c] = R[coff[c] + q];
 #pragma unroll
-        for (int r = 0; r < kRowsPerWave; ++r)
+        for (int r = 0; r < RPW; ++r)
 #pragma unroll
           for (int c = 0; c < MC; ++c) acc[r][c] += aq[r] * rq[c];
       }
     }
 #pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) {
+    for (int r = 0; r < RPW; ++r) {
       if (r < nr) {
 #pragma unroll
         for (int c = 0; c < MC; ++c) {
           if (c < ncol) {
             const double v = wave_sum(acc[r][c]);
-            if (lane == 0) yr[wave * kRowsPerWave + r][c] = v;
+            if (lane == 0) yr[wave * RPW + r][c] = v;
           }
         }
       }
@@ -589,10 +600,8 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   T *w = static_cast<T *>(P.w);
   const double inv_dx2 = 1.0 / (P.dx * P.dx);
   {
-    const int lr = tid >> 4, node = tid & 15;
     const int p = row0 + lr;
-    if (p < ns) {
-      const double f0p = P.f0[p];
+    if (lr < CR && p < ns) {
       double ft, f;
       if (mode == GPF_CIRCULATION) {
         f = yr[lr][0] - s0 * f0p;
@@ -608,10 +617,8 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
         if (P.ft_out) P.ft_out[p] = ft;
       }
       const int a = node & 3, b = node >> 2;
-      const int i0 = P.st_i[2 * p], j0 = P.st_i[2 * p + 1];
-      const double amp = P.ds[p] * f * inv_dx2;
-      atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
-                 (T)(amp * P.st_w[8 * p + a] * P.st_w[8 * p + 4 + b]));
+      const double amp = dsp * f * inv_dx2;
+      atomic_add(w + (size_t)(stj + b) * n + sti + a, (T)(amp * swa * swb));
     }
   }
   if (blockIdx.x == 0 && mode == GPF_KUTTA_SHED && tid < 16 * m) {
@@ -1367,11 +1374,21 @@ hipError_t launch_schur_gemm(const ProbDesc *d, int nb, int ns, int m_max, const
 
 template <class T>
 hipError_t launch_schur_apply(const ProbDesc *d, int nb, int ns_max, int m_max, hipStream_t s) {
-  const dim3 grid((ns_max + kCRows - 1) / kCRows, nb);
-  if (m_max <= 2)
-    hipLaunchKernelGGL((k_schur_apply<T, 3>), grid, dim3(kCB), 0, s, d);
-  else
-    hipLaunchKernelGGL((k_schur_apply<T, kMaxCol>), grid, dim3(kCB), 0, s, d);
+  // one row per wave unless that makes more than 2048 workgroups
+  const int narrow = (ns_max + 3) / 4;
+  if ((long)narrow * nb <= 2048) {
+    const dim3 grid(narrow, nb);
+    if (m_max <= 2)
+      hipLaunchKernelGGL((k_schur_apply<T, 3, 1>), grid, dim3(kCB), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_schur_apply<T, kMaxCol, 1>), grid, dim3(kCB), 0, s, d);
+  } else {
+    const dim3 grid((ns_max + 15) / 16, nb);
+    if (m_max <= 2)
+      hipLaunchKernelGGL((k_schur_apply<T, 3, 4>), grid, dim3(kCB), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_schur_apply<T, kMaxCol, 4>), grid, dim3(kCB), 0, s, d);
+  }
   timer_end(s);
   return hipGetLastError();
 }
