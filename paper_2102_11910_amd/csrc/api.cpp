@@ -426,6 +426,11 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   const void *tw2 = cfg.fp64_plan ? p->tw64.p : p->tw32.p;
   void *x2 = cfg.fp64_plan ? ws->x64.p : ws->x32.p;
   c1.in = pd.w;
+  // Every reader of the field in a solve is a convolution's forward row
+  // pass (the surface step only adds to it): those passes add R_v's tile
+  // halos as they read, and the scatter skips its halo pass
+  pd.halo_defer = pd.nv > 0 && halo_tiles(p->grid.n) > 0 ? 1 : 0;
+  c1.halo = pd.halo_defer ? pd.halo : nullptr;
   c1.c = p->gauge_c;
   c1.gamma = pd.aux + SC_GAMMA_W;
   // the final convolution adds s_inf when the plan stores the total psi
@@ -521,6 +526,7 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.s1 = c1.out;
   // final convolution of all vorticity
   c2.in = pd.w;
+  c2.halo = c1.halo;
   c2.X = x2;
   c2.out = out->d_psi;
   c2.spec = spec2;
@@ -551,8 +557,8 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, bool impulse,
                         int band, int xcds, const ConvSched &sc1, const ConvSched &sc2,
                         bool shared, const double *shared_sinv, int vel_kinds, int fband2,
-                        hipStream_t s) {
-  GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s));
+                        bool halo_pass, hipStream_t s) {
+  GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s, nullptr, halo_pass));
   GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body ? band : 0, s, sc1)));
   if (cfg.body) {
     GPF_HIP(launch_surface_rhs<T1>(pd, nb, ns_max, m_max, s));
@@ -582,8 +588,10 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   bool impulse = false;
   int vel_kinds = 0;   // velocity kernels the group needs: 1 vortex by vortex, 2 tile by tile
   int fband2 = 0;      // source rows the second forward row pass transforms (most of any problem)
+  bool halo_pass = false;   // some problem's halos are added by the scatter's halo pass
   for (int i = 0; i < nb; ++i) {
     describe(probs[i], cfg, pd[i], c1[i], c2[i]);
+    halo_pass = halo_pass || (pd[i].nv > 0 && !pd[i].halo_defer);
     fband2 = std::max(fband2, c2[i].fwd_hi - c2[i].fwd_lo + 1);
     if (pd[i].u && pd[i].nv > 0) vel_kinds |= pd[i].vel_tiles ? 2 : 1;
     nv_max = std::max(nv_max, pd[i].nv);
@@ -612,14 +620,14 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   if (cfg.fp64_plan)
     return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, s);
   if (cfg.conv1_fp64)
     return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, s);
   return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, s);
 }
 
 // A batch can run merged when its problems differ only in grid size and in
@@ -690,7 +698,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
       e[i - lo].logn = lg;
       // band flag: the inverse pass of a first convolution covers its output
       // band; a forward pass covers its source rows fwd_lo .. fwd_hi
-      e[i - lo].band = kind == 2 || kind == 0 ? 1 : 0;
+      e[i - lo].band = kind == 2 || (kind == 0 && (cd[i].fwd_lo != 0 || cd[i].fwd_hi != n - 1)) ? 1 : 0;
       first += multi_blocks(kind, n, cd[i]);
     }
     mp->nprob = hi - lo;
@@ -725,7 +733,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto tile_blocks = [&](int i) { return tile_items_max(pd[i].n, pd[i].nv); };
   auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
-  auto halo_blocks = [&](int i) { return pd[i].nv > 0 ? fixup_blocks(pd[i].n) : 0; };
+  auto halo_blocks = [&](int i) { return pd[i].nv > 0 && !pd[i].halo_defer ? fixup_blocks(pd[i].n) : 0; };
   FlatMap fsa[4], fsb[4], fvel[2];
   if (na > 0) {
     make_flat(0, na, bin_blocks, &fsa[0]);

@@ -375,6 +375,82 @@ __device__ __forceinline__ int xcd_block(int remap) {
 // ---------------------------------------------------------------------------
 // pass 1: rows, real -> half spectrum, stored k-major
 // ---------------------------------------------------------------------------
+// R_v halos added as the source is read.  The scatter stores each 32 x 32
+// cell tile's own nodes into the field and the window nodes its neighbours
+// own into the tile's halo slot (a ring of kHaloRing entries: window row 0,
+// rows 33 and 34, then columns 0, 33 and 34 of rows 1 .. 32; a tile without
+// vortices holds zeros).  A node on a tile's columns 0, 1 (31) takes the
+// left (right) neighbour's entry, a node on rows 0, 1 (31) the lower (upper)
+// neighbour's, a corner node also the diagonal one's: added in that order to
+// source rows ja, ja + 1 (ja even, so both lie in one tile row) at columns
+// lane + k TPS.  Each part is one branch whose loads are issued together;
+// a neighbour outside the grid is replaced by the own tile (a valid
+// address) and its value dropped.
+template <class Tin, int N>
+__device__ __forceinline__ void add_halos(const Tin *__restrict__ hal, Tin (&ra)[kE / 2],
+                                          Tin (&rb)[kE / 2], int ja, int lane) {
+  constexpr int n = N / 2;
+  if constexpr (n >= 64) {
+    constexpr int TPS = N / kE, bw = 32 + 3, tps = n / 32, R = kHaloRing;
+    const int ty = ja >> 5, la = ja & 31;
+    bool anyc = false;
+#pragma unroll
+    for (int k = 0; k < kE / 2; ++k) {
+      const int lx = (lane + k * TPS) & 31;
+      anyc = anyc || lx <= 1 || lx == 31;
+    }
+    if (anyc) {
+      Tin ha[kE / 2], hb[kE / 2];
+      bool ok[kE / 2];
+#pragma unroll
+      for (int k = 0; k < kE / 2; ++k) {
+        const int i = lane + k * TPS, tx = i >> 5, lx = i & 31;
+        const int hx = lx <= 1 ? tx - 1 : tx + 1;
+        ok[k] = (lx <= 1 || lx == 31) && hx >= 0 && hx < tps;
+        // window column 33, 34 of the left neighbour, 0 of the right one
+        const size_t at = (size_t)(ty * tps + (ok[k] ? hx : tx)) * R + 3 * bw + 3 * la +
+                          (lx <= 1 ? lx + 1 : 0);
+        ha[k] = hal[at];
+        hb[k] = hal[at + 3];
+      }
+#pragma unroll
+      for (int k = 0; k < kE / 2; ++k) {
+        ra[k] += ok[k] ? ha[k] : (Tin)0;
+        rb[k] += ok[k] ? hb[k] : (Tin)0;
+      }
+    }
+    // rows 0 and 1 of a tile take window rows 33 and 34 of the lower
+    // neighbour; row 31 (the second row of the pair at la = 30) window row 0
+    // of the upper one.  One row at a time, to keep fewer values live.
+    const bool low = la == 0 && ty > 0, up = la == 30 && ty + 1 < tps;
+    if (low || up) {
+      const int vy = low ? ty - 1 : ty + 1;
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) {
+        if (rr == 0 && !low) continue;
+        const int off = rr == 0 ? bw : (low ? 2 * bw : 0);
+        Tin (&r)[kE / 2] = rr == 0 ? ra : rb;
+        Tin v[kE / 2], dg[kE / 2];
+        bool okd[kE / 2];
+#pragma unroll
+        for (int k = 0; k < kE / 2; ++k) {
+          const int i = lane + k * TPS, tx = i >> 5, lx = i & 31;
+          const int hx = lx <= 1 ? tx - 1 : tx + 1;
+          okd[k] = (lx <= 1 || lx == 31) && hx >= 0 && hx < tps;
+          v[k] = hal[(size_t)(vy * tps + tx) * R + off + lx + 1];
+          dg[k] = hal[(size_t)(vy * tps + (okd[k] ? hx : tx)) * R + off + (lx <= 1 ? lx + 33 : 0)];
+        }
+#pragma unroll
+        for (int k = 0; k < kE / 2; ++k) {
+          r[k] += v[k];
+          r[k] += okd[k] ? dg[k] : (Tin)0;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // row-pair block `blk` of one problem (rows 2 SEQ blk ..), LDS of SEQ rows
 template <class Tin, class T, int N, int SH>
 __device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, int band,
@@ -398,21 +474,28 @@ __device__ __forceinline__ void rows_fwd_body(const ConvDesc &C, int blk, int ba
   const bool live = j0 + 2 * q <= hi_row;   // this sequence's row pair is transformed
   V x[kE];
   V wr[tw_regs<N>()];
-  if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, lane);
   {
     // elements lane + k * TPS of the packed row pair; k >= 8 is the zero half.
     // A sequence past the range reads the workgroup's first pair (j0 is even
     // and hi_row odd, so j0 + 1 <= hi_row) and drops it by a select: the
     // loads stay unconditional and are issued together.
-    const size_t row = (size_t)(live ? j0 + 2 * q : j0) * n;
+    const int ja = live ? j0 + 2 * q : j0;
+    const size_t row = (size_t)ja * n;
+    Tin ra[kE / 2], rb[kE / 2];
 #pragma unroll
     for (int k = 0; k < kE / 2; ++k) {
-      const T a = (T)w[row + lane + k * P::TPS];
-      const T b = (T)w[row + n + lane + k * P::TPS];
-      x[k].x = live ? a : (T)0;
-      x[k].y = live ? b : (T)0;
+      ra[k] = w[row + lane + k * P::TPS];
+      rb[k] = w[row + n + lane + k * P::TPS];
+    }
+    if (C.halo) add_halos<Tin, N>(static_cast<const Tin *>(C.halo), ra, rb, ja, lane);
+#pragma unroll
+    for (int k = 0; k < kE / 2; ++k) {
+      x[k].x = live ? (T)ra[k] : (T)0;
+      x[k].y = live ? (T)rb[k] : (T)0;
     }
   }
+  // the first stage needs no twiddles: loaded after the source
+  if constexpr (tw_in_regs<T, N>()) load_twiddles<T, N, 0>(wr, tw, lane);
   constexpr int RW = 2 * P::SEQ;
   // rows j0 .. j0 + nr - 1 of the workgroup are covered; nr < RW only where
   // a band ends inside the workgroup, and the guarded loops below run only

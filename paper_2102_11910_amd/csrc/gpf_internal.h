@@ -189,6 +189,10 @@ struct ConvDesc {
   // pass (a zeroed descriptor keeps nothing)
   int fwd_lo, fwd_hi;
   int keep_lo, keep_end;
+  // halo slots of the source's R_v tiles (32 x 32 cells, n / 32 per side,
+  // kHaloRing entries each, of the source's type), added to the border
+  // nodes of every source row the forward row pass reads; nullptr: none
+  const void *halo;
 };
 
 struct ProbDesc {
@@ -202,6 +206,8 @@ struct ProbDesc {
   // fields
   void *w;                      // source field (zero on entry, or the values R_v adds to)
   int w_accumulate;             // 1: w holds values R_v adds to; 0: w is zero on entry
+  int halo_defer;               // 1: the solve's convolutions add the tiles' halos as
+                                // they read w (no halo pass); 0: the halo pass adds them
   int vel_tiles;                // 1: velocities tile by tile through LDS (dense clouds)
   const void *s1;               // result of the first convolution
   // per-problem aux: scalars and partial sums
@@ -272,7 +278,8 @@ __host__ __device__ inline int bin_count_blocks(int nv) {
 }
 int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n < 32)
 // A tile of more than kTileChunk vortices is split into items of at most
-// kTileChunk records each; tile_items_max bounds the items of a problem.
+// kTileChunk records each, and a tile without vortices is one empty item
+// (it clears its halo slot); tile_items_max bounds the items of a problem.
 constexpr int kTileChunk = 512;
 int tile_items_max(int n, int nv);
 // A tile's window (ts + 3)^2 nodes minus its own ts^2: 6 ts + 9 at most.
@@ -339,13 +346,16 @@ __device__ __forceinline__ bool flat_block(const FlatMap &fm, FlatBlock *fb) {
 // own nodes into the source field (zero, or the values to add to) and the
 // nodes its neighbours own into the tile's halo slot; then one workgroup per
 // tile adds the neighbours' halos to its border nodes in a fixed order, so
-// the field is the same bits on every run (split dense tiles use atomics)
-// fm (merged batches): fm[0] the binning kernels' map (one block per 256
-// vortices), fm[1] the tile kernel's, fm[2] the halo kernel's; nullptr: a
-// 2-D grid of nb problems
+// the field is the same bits on every run (split dense tiles use atomics).
+// Problems with halo_defer skip that last pass: their convolutions add the
+// halos as they read the field.
+// fm (merged batches): fm[0] the count's map, fm[1] the tile kernel's,
+// fm[2] the halo kernel's, fm[3] the place kernel's (one block per 256
+// vortices); nullptr: a 2-D grid of nb problems, with the halo pass when
+// `halo_pass` is set
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
-                                   const FlatMap *fm = nullptr);
+                                   const FlatMap *fm = nullptr, bool halo_pass = true);
 // Launches that cover problems of several grid sizes (FP32 transforms, n from
 // 64 to 2048): entry i of a pass's table gives the first of its blocks,
 // problem `prob` (an index into the launch's ConvDesc array) and log2 n;

@@ -231,11 +231,15 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
     }
   }
   {
-    // work list of the tile kernels, in tile order: a non-empty tile of c
-    // records gives ceil(c / kTileChunk) items of consecutive records
+    // work list of the tile kernels, in tile order: a tile of c records
+    // gives ceil(c / kTileChunk) items of consecutive records, an empty tile
+    // one empty item (which clears the tile's halo slot)
+    auto parts_of = [&](int k) {
+      return k < per && lo + k < ntiles ? max(1, (cnts[k] + kTileChunk - 1) / kTileChunk) : 0;
+    };
     int ni = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) ni += (cnts[k] + kTileChunk - 1) / kTileChunk;
+    for (int k = 0; k < kPer; ++k) ni += parts_of(k);
     int inc = ni;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int c = cnts[k];
-      const int parts = (c + kTileChunk - 1) / kTileChunk;
+      const int parts = parts_of(k);
       if (parts > 1) {
         // the items of a split tile add their halos to the tile's slot
         T *hal = static_cast<T *>(P.halo) + (size_t)(lo + k) * kHaloRing;
@@ -396,6 +400,13 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
     const int4 it = *reinterpret_cast<const int4 *>(P.items + 4 * (1 + i));
     const int t = it.x, b0 = it.y, b1 = it.z;
     const bool alone = it.w == 0;
+    if (b0 == b1) {
+      // a tile without vortices: its halo slot holds zeros for the readers
+      // that add every neighbour's slot (the LDS window is not touched)
+      T *hal = halo + (size_t)t * kHaloRing;
+      for (int k = tid; k < kHaloRing; k += kTileBlock) hal[k] = (T)0;
+      continue;
+    }
     if (tid == 0 && it.w <= 1) P.bin_cnt[t] = 0;
     const int X0 = (t % tps) * ts - 1, Y0 = (t / tps) * ts - 1;   // window origin
     // the item's records (at most kTileChunk), loaded before the window is
@@ -471,7 +482,7 @@ __global__ __launch_bounds__(kFixupBlock) void k_halo_fixup(const ProbDesc *__re
   if (!flat_block(fm, &fb)) return;
   const ProbDesc &P = d[fb.prob];
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
-  if (tps < 2 || P.nv <= 0) return;
+  if (tps < 2 || P.nv <= 0 || P.halo_defer) return;
   const T *__restrict__ halo = static_cast<const T *>(P.halo);
   const int *__restrict__ start = P.bin_start;
   T *w = static_cast<T *>(P.w);
@@ -670,6 +681,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_velocity(const ProbDesc *__
   for (int i = fb.blk; i < cnt; i += fb.nblk) {
     const int4 it = *reinterpret_cast<const int4 *>(P.items + 4 * (1 + i));
     const int t = it.x, b0 = it.y, b1 = it.z;
+    if (b0 == b1) continue;   // an empty tile's item
     const int X0 = (t % tps) * ts - 2, Y0 = (t / tps) * ts - 2;   // window origin
     double4 rec[kPer];
 #pragma unroll
@@ -838,12 +850,11 @@ int halo_tiles(int n) { return bin_tiles(n) > 1 ? bin_tiles(n) : 0; }
 
 int fixup_blocks(int n) { return (halo_tiles(n) + kFixupTiles - 1) / kFixupTiles; }
 
-// items of a problem: one per non-empty tile (at most min(tiles, nv)) plus
-// one per further kTileChunk records of a tile (sum over tiles of
-// floor((c - 1) / kTileChunk) <= nv / kTileChunk)
+// items of a problem: one per tile plus one per further kTileChunk records
+// of a tile (sum over tiles of floor((c - 1) / kTileChunk) <= nv / kTileChunk)
 int tile_items_max(int n, int nv) {
   if (nv <= 0) return 0;
-  return std::min(bin_tiles(n), nv) + nv / kTileChunk;
+  return bin_tiles(n) + nv / kTileChunk;
 }
 
 // grid of a launch: the flat map's blocks, or nb problems of `per` blocks
@@ -853,7 +864,7 @@ static dim3 grid_of(const FlatMap *fm, int per, int nb) {
 
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
-                                   const FlatMap *fm) {
+                                   const FlatMap *fm, bool halo_pass) {
   timer_begin(GPF_TK_SCATTER, s);
   const FlatMap none{nullptr, 0, 0};
   const FlatMap mb = fm ? fm[0] : none, mt = fm ? fm[1] : none, mh = fm ? fm[2] : none;
@@ -867,16 +878,16 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   // one workgroup per item of the work list, then one per tile for the halos
   hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
                      dim3(kTileBlock), 0, s, d, mt);
-  if (fm ? mh.total > 0 : (nv_max > 0 && halo_tiles(n) > 0))
+  if (fm ? mh.total > 0 : (halo_pass && nv_max > 0 && halo_tiles(n) > 0))
     hipLaunchKernelGGL((k_halo_fixup<T>), grid_of(fm ? &mh : nullptr, fixup_blocks(n), nb), dim3(kFixupBlock),
                        0, s, d, mh);
   timer_end(s);
   return hipGetLastError();
 }
 template hipError_t launch_scatter_vortices<float>(const ProbDesc *, int, int, int, hipStream_t,
-                                                   const FlatMap *);
+                                                   const FlatMap *, bool);
 template hipError_t launch_scatter_vortices<double>(const ProbDesc *, int, int, int, hipStream_t,
-                                                    const FlatMap *);
+                                                    const FlatMap *, bool);
 
 hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
                                    const double *xs, const double *ys, int *st_i, double *st_w,

@@ -377,6 +377,31 @@ def test_invalid_arguments(ctx):
         s.solve(inp, X)
 
 
+@pytest.mark.parametrize("n,surface", [(64, None), (256, None), (256, "cylinder")])
+@pytest.mark.parametrize("flags", [gpf.GPF_FP64, gpf.GPF_FP32, gpf.GPF_CONV1_FP64])
+def test_tile_borders_beside_empty_tiles(ctx, n, surface, flags):
+    """A few vortices in the cells on either side of the 32-cell tile
+    borders (their stencils reach the neighbouring tiles' border nodes,
+    corners included) and most tiles without vortices: the solves add every
+    neighbour's halo entries as they read the field, and an empty tile's
+    entries must count as zero.  Against the oracle."""
+    case = wl.random_case(400 + n, n, 2.0 / n, 0, surface=surface,
+                          mode="circulation" if surface else "none")
+    dx, x0 = case.dx, -(n - 1) * case.dx / 2
+    rng = np.random.default_rng(n)
+    cells = [32 * k + d for k in range(1, n // 32) for d in (-2, -1, 0, 1)]
+    picks = rng.choice(len(cells) ** 2, size=min(60, len(cells) ** 2), replace=False)
+    xi = [cells[p % len(cells)] + 0.37 for p in picks]
+    eta = [cells[p // len(cells)] + 0.61 for p in picks]
+    case.X = x0 + dx * np.asarray(xi)
+    case.Y = x0 + dx * np.asarray(eta)
+    case.G = wl.f32(rng.normal(0.0, 1.0, len(xi)))
+    say(f"[tile borders] n={n} surface={surface} flags={flags}, {len(xi)} vortices")
+    got = run_solve(ctx, case, flags)
+    ref = oracle_solve(problem_of(case), body_of(case))
+    compare(case, got, ref, flags == gpf.GPF_FP64, f"tile borders n={n} {surface} flags={flags}")
+
+
 @pytest.mark.parametrize("flags", [gpf.GPF_FP64, gpf.GPF_FP32])
 def test_window_limits_nodes_and_coincident_vortices(ctx, flags):
     """Vortices exactly at the lowest allowed cell index (xi = 2) and just
