@@ -58,8 +58,12 @@ __host__ __device__ inline int tile_cells(int n) { return n <= 32 ? n : 32; }
 constexpr int kMaxTiles = 4096;
 constexpr int kMaxTileCells = 32;
 
+// log2 of a power of two
+__device__ __forceinline__ int ilog2(int x) { return 31 - __clz(x); }
+// grid sizes are powers of two, so are ts and n / ts: shifts, not divisions
 __device__ __forceinline__ int vortex_tile(int i0, int j0, int ts, int tps) {
-  return ((j0 + 1) / ts) * tps + (i0 + 1) / ts;
+  const int sh = ilog2(ts);
+  return ((j0 + 1) >> sh) * tps + ((i0 + 1) >> sh);
 }
 
 // 1. count vortices per tile.  A workgroup histograms its 256 PER vortices
@@ -379,15 +383,14 @@ template <> struct FixedPoint<double> {
   static __device__ __forceinline__ long long to_int(double x) { return __double2ll_rn(x); }
 };
 
-template <class T>
-__global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__restrict__ d, FlatMap fm) {
-  __shared__ long long win[kMaxWin];
-  FlatBlock fb;
-  if (!flat_block(fm, &fb)) return;
-  const ProbDesc &P = d[fb.prob];
+// TS: the tile size when it is known at compile time (32, every grid of
+// n >= 32), 0 otherwise: the window loops then divide by constants
+template <class T, int TS>
+__device__ __forceinline__ void tile_scatter_body(const ProbDesc &P, const FlatBlock &fb,
+                                                  long long *win) {
   const int cnt = P.items[0];
   if (fb.blk >= cnt) return;
-  const int n = P.n, ts = tile_cells(n), tps = n / ts;
+  const int n = P.n, ts = TS ? TS : tile_cells(n), tps = n / ts, tpsh = ilog2(tps);
   const int tid = threadIdx.x;
   const int bw = ts + 3, nwin = bw * bw;
   const int sexp = FixedPoint<T>::B - (int)P.aux[SC_RV_SCALE];
@@ -408,7 +411,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
       continue;
     }
     if (tid == 0 && it.w <= 1) P.bin_cnt[t] = 0;
-    const int X0 = (t % tps) * ts - 1, Y0 = (t / tps) * ts - 1;   // window origin
+    const int X0 = (t & (tps - 1)) * ts - 1, Y0 = (t >> tpsh) * ts - 1;   // window origin
     // the item's records (at most kTileChunk), loaded before the window is
     // cleared; clamped duplicates past the end add zero
     constexpr int kPer = kTileChunk / kTileBlock;
@@ -465,6 +468,18 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
     }
     if (i + fb.nblk < cnt) lds_barrier();   // the window is cleared for the next item
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__restrict__ d, FlatMap fm) {
+  __shared__ long long win[kMaxWin];
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  if (tile_cells(P.n) == 32)
+    tile_scatter_body<T, 32>(P, fb, win);
+  else
+    tile_scatter_body<T, 0>(P, fb, win);
 }
 
 // 5.: kFixupTiles tiles per workgroup, a few border nodes per thread; every
@@ -662,16 +677,11 @@ __device__ __forceinline__ void stencil_velocity(const T *s, int pitch, double f
 // the item forms its velocity from LDS and writes it at its own index.
 constexpr int kVelWin = kMaxTileCells + 6;
 
-template <class T>
-__global__ __launch_bounds__(kTileBlock) void k_tile_velocity(const ProbDesc *__restrict__ d, FlatMap fm) {
-  __shared__ T win[kVelWin * kVelWin];
-  FlatBlock fb;
-  if (!flat_block(fm, &fb)) return;
-  const ProbDesc &P = d[fb.prob];
-  if (P.u == nullptr || !P.vel_tiles) return;
+template <class T, int TS>
+__device__ __forceinline__ void tile_velocity_body(const ProbDesc &P, const FlatBlock &fb, T *win) {
   const int cnt = P.items[0];
   if (fb.blk >= cnt) return;
-  const int n = P.n, ts = tile_cells(n), tps = n / ts;
+  const int n = P.n, ts = TS ? TS : tile_cells(n), tps = n / ts, tpsh = ilog2(tps);
   const int tid = threadIdx.x;
   const int bw = ts + 6, nwin = bw * bw;
   const T *s = static_cast<const T *>(P.psi);
@@ -682,7 +692,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_velocity(const ProbDesc *__
     const int4 it = *reinterpret_cast<const int4 *>(P.items + 4 * (1 + i));
     const int t = it.x, b0 = it.y, b1 = it.z;
     if (b0 == b1) continue;   // an empty tile's item
-    const int X0 = (t % tps) * ts - 2, Y0 = (t / tps) * ts - 2;   // window origin
+    const int X0 = (t & (tps - 1)) * ts - 2, Y0 = (t >> tpsh) * ts - 2;   // window origin
     double4 rec[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j)
@@ -706,6 +716,19 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_velocity(const ProbDesc *__
     }
     if (i + fb.nblk < cnt) lds_barrier();   // the window is reloaded for the next item
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(kTileBlock) void k_tile_velocity(const ProbDesc *__restrict__ d, FlatMap fm) {
+  __shared__ T win[kVelWin * kVelWin];
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  if (P.u == nullptr || !P.vel_tiles) return;
+  if (tile_cells(P.n) == 32)
+    tile_velocity_body<T, 32>(P, fb, win);
+  else
+    tile_velocity_body<T, 0>(P, fb, win);
 }
 
 // Velocities vortex by vortex, reading s from global memory.  After R_v of
