@@ -152,15 +152,30 @@ gpf_status DescRing::push(const void *src, size_t nbytes, hipStream_t s, void **
   char *h = host + (size_t)slot * slot_bytes;
   char *d = dev.as<char>() + (size_t)slot * slot_bytes;
   std::memcpy(h, src, nbytes);
-  GPF_HIP(hipMemcpyAsync(d, h, nbytes, hipMemcpyHostToDevice, s));
+  if (capturing && defer_captured)
+    deferred.emplace_back(slot, nbytes);   // copied once the capture has ended
+  else
+    GPF_HIP(hipMemcpyAsync(d, h, nbytes, hipMemcpyHostToDevice, s));
   if (capturing) {
-    pinned[slot] = 1;  // the graph replays this copy: keep the slot forever
+    pinned[slot] = 1;  // the graph reads this slot: keep it until the graph is gone
   } else {
     GPF_HIP(hipEventRecord(ev[slot], s));
     busy[slot] = 1;
   }
   *dptr = d;
   return GPF_OK;
+}
+
+gpf_status DescRing::flush_deferred() {
+  gpf_status st = GPF_OK;
+  for (const auto &p : deferred) {
+    const hipError_t e = hipMemcpy(dev.as<char>() + (size_t)p.first * slot_bytes,
+                                   host + (size_t)p.first * slot_bytes, p.second,
+                                   hipMemcpyHostToDevice);
+    if (e != hipSuccess && st == GPF_OK) st = fail(GPF_E_DEVICE, "descriptor copy after capture failed");
+  }
+  deferred.clear();
+  return st;
 }
 
 namespace {
@@ -1851,12 +1866,16 @@ gpf_status gpf_rk2_create(gpf_plan *plan, const gpf_body *body, const gpf_inputs
     gpf_status st;
     {
       TimerScope none(nullptr);
+      plan->ring.defer_captured = true;   // the slots get one copy, below
       st = rk2_enqueue(rk.get(), rk->cap);
+      plan->ring.defer_captured = false;
     }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(rk->cap, &g);
     for (int k = 0; k < plan->ring.slots; ++k)
       if (plan->ring.pinned[k] && !pinned_before[k]) rk->held.push_back(k);
+    const gpf_status fst = plan->ring.flush_deferred();
+    if (st == GPF_OK) st = fst;
     if (st != GPF_OK) {
       if (g) (void)hipGraphDestroy(g);
       return st;   // ~gpf_rk2 releases the slots: nothing was replayed

@@ -106,12 +106,18 @@ struct DescRing {
   std::vector<hipEvent_t> ev;
   std::vector<char> busy, pinned;
   int next = 0;
+  // set by the library around a capture of its own: a block pushed while
+  // capturing is copied once after the capture (flush_deferred) instead of
+  // by a copy node that every replay would repeat
+  bool defer_captured = false;
+  std::vector<std::pair<int, size_t>> deferred;   // (slot, bytes)
   DescRing() = default;
   DescRing(const DescRing &) = delete;
   DescRing &operator=(const DescRing &) = delete;
   ~DescRing();
   gpf_status init(int nslots, size_t bytes_per_slot);
   gpf_status push(const void *src, size_t bytes, hipStream_t s, void **dptr);
+  gpf_status flush_deferred();   // synchronous copies of the deferred blocks
   void unpin(int slot) {
     pinned[slot] = 0;
     busy[slot] = 0;
