@@ -319,6 +319,8 @@ gpf_status gpf_workspace::ensure_vortices(int nvv) {
     GPF_TRY(items.alloc(4 * sizeof(int) * (1 + (size_t)tile_items_max(n, nv))));
     GPF_TRY(halo.alloc(sizeof(double) * kHaloRing * (size_t)std::max(1, bin_tiles(n))));
   }
+  GPF_TRY(splits.alloc(4 * sizeof(int) * (1 + (size_t)split_tiles_max(nv))));
+  GPF_TRY(splitwin.alloc(sizeof(long long) * kSplitWin * (size_t)std::max(1, split_items_max(nv))));
   return GPF_OK;
 }
 
@@ -412,6 +414,8 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.bin_start = ws->bin_start.as<int>();
   pd.items = ws->items.as<int>();
   pd.halo = ws->halo.p;
+  pd.splits = ws->splits.as<int>();
+  pd.splitwin = ws->splitwin.as<long long>();
   pd.rank = ws->rank.as<int>();
   pd.sorted = ws->sorted.as<double>();
   pd.status = out->d_status;
@@ -659,7 +663,7 @@ bool mergeable(const GroupCfg &c) {
 // five entries per problem).
 size_t merged_block_bytes(int nb) {
   return ((size_t)nb * kProblemDescBytes + 15) / 16 * 16 + 9 * (size_t)nb * sizeof(MultiEntry) +
-         6 * (size_t)nb * sizeof(FlatEntry);   // four binning maps per class, two velocity maps
+         7 * (size_t)nb * sizeof(FlatEntry);   // five binning maps per class, two velocity maps
 }
 
 // Every stage of the solve as one launch per precision class over problems
@@ -745,22 +749,25 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   };
   auto bin_blocks = [&](int i) { return pd[i].nv > 0 ? bin_count_blocks(pd[i].nv) : 1; };
   auto place_blocks = [&](int i) { return std::max(1, (pd[i].nv + 255) / 256); };
+  auto split_tile_blocks = [&](int i) { return pd[i].nv > 0 ? split_blocks(pd[i].nv) : 0; };
   auto tile_blocks = [&](int i) { return tile_items_max(pd[i].n, pd[i].nv); };
   auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
   auto halo_blocks = [&](int i) { return pd[i].nv > 0 && !pd[i].halo_defer ? fixup_blocks(pd[i].n) : 0; };
-  FlatMap fsa[4], fsb[4], fvel[2];
+  FlatMap fsa[5], fsb[5], fvel[2];
   if (na > 0) {
     make_flat(0, na, bin_blocks, &fsa[0]);
     make_flat(0, na, tile_blocks, &fsa[1]);
     make_flat(0, na, halo_blocks, &fsa[2]);
     make_flat(0, na, place_blocks, &fsa[3]);
+    make_flat(0, na, split_tile_blocks, &fsa[4]);
   }
   if (nbb > 0) {
     make_flat(na, nb, bin_blocks, &fsb[0]);
     make_flat(na, nb, tile_blocks, &fsb[1]);
     make_flat(na, nb, halo_blocks, &fsb[2]);
     make_flat(na, nb, place_blocks, &fsb[3]);
+    make_flat(na, nb, split_tile_blocks, &fsb[4]);
   }
   make_flat(0, nb, vel_gather, &fvel[0]);
   make_flat(0, nb, vel_tiles, &fvel[1]);
@@ -792,8 +799,8 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto fixf = [&](FlatMap *fm, int k) {
     for (int i = 0; i < k; ++i) fm[i].e = reinterpret_cast<const FlatEntry *>(base + (size_t)fm[i].e);
   };
-  if (na > 0) fixf(fsa, 4);
-  if (nbb > 0) fixf(fsb, 4);
+  if (na > 0) fixf(fsa, 5);
+  if (nbb > 0) fixf(fsb, 5);
   fixf(fvel, 2);
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
@@ -1497,6 +1504,8 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   pd.bin_start = plan->ws.bin_start.as<int>();
   pd.items = plan->ws.items.as<int>();
   pd.halo = plan->ws.halo.p;
+  pd.splits = plan->ws.splits.as<int>();
+  pd.splitwin = plan->ws.splitwin.as<long long>();
   pd.rank = plan->ws.rank.as<int>();
   pd.sorted = plan->ws.sorted.as<double>();
   if (d_status) pd.status = d_status;

@@ -227,7 +227,10 @@ struct ProbDesc {
                                 // (kHaloRing values of the field type)
   int *items;                   // work list of the tile kernels, 4 ints per item:
                                 // [0] = {count, 0, 0, 0}, then {tile, first record,
-                                // end record, 1 if the tile has other items}
+                                // end record, 0 alone or 1 + window slot}
+  int *splits;                  // tiles of several items: [0] = {count, 0, 0, 0},
+                                // then {tile, first window slot, items, 0}
+  long long *splitwin;          // window slots of split tiles' items (kSplitWin each)
   double *sorted;
   // body
   int ns;
@@ -286,8 +289,15 @@ int bin_tiles(int n);  // tiles per grid (square tiles of 32 cells, fewer for n 
 // A tile of more than kTileChunk vortices is split into items of at most
 // kTileChunk records each, and a tile without vortices is one empty item
 // (it clears its halo slot); tile_items_max bounds the items of a problem.
+// The items of a split tile store their fixed-point windows ((32 + 3)^2
+// nodes) in slots of their own, which a second kernel sums; a problem has
+// at most split_tiles_max such tiles and split_items_max such items.
 constexpr int kTileChunk = 512;
 int tile_items_max(int n, int nv);
+constexpr int kSplitWin = (32 + 3) * (32 + 3);
+inline int split_tiles_max(int nv) { return nv / (kTileChunk + 1); }
+inline int split_items_max(int nv) { return nv / kTileChunk + split_tiles_max(nv); }
+int split_blocks(int nv);   // workgroups of the split-tile kernel of one problem
 // A tile's window (ts + 3)^2 nodes minus its own ts^2: 6 ts + 9 at most.
 constexpr int kHaloRing = 6 * 32 + 9;
 int halo_tiles(int n);   // tiles that neighbours' windows reach (0 for one tile)
@@ -357,8 +367,8 @@ __device__ __forceinline__ bool flat_block(const FlatMap &fm, FlatBlock *fb) {
 // halos as they read the field.
 // fm (merged batches): fm[0] the count's map, fm[1] the tile kernel's,
 // fm[2] the halo kernel's, fm[3] the place kernel's (one block per 256
-// vortices); nullptr: a 2-D grid of nb problems, with the halo pass when
-// `halo_pass` is set
+// vortices), fm[4] the split-tile kernel's; nullptr: a 2-D grid of nb
+// problems, with the halo pass when `halo_pass` is set
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
                                    const FlatMap *fm = nullptr, bool halo_pass = true);
@@ -527,7 +537,7 @@ struct gpf_workspace {
   int n = 0, ns = 0, nv = 0;
   gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y;
   gpf::DevBuf xb;   // compact band of the first convolution's column pass
-  gpf::DevBuf bin_cnt, bin_start, items, rank, sorted, halo;
+  gpf::DevBuf bin_cnt, bin_start, items, rank, sorted, halo, splits, splitwin;
   // band: rows of a body's band (16-row groups), 0 without a body
   gpf_status ensure(int n, bool need32, bool need64, int ns, int band = 0);
   gpf_status ensure_vortices(int nv);

@@ -51,8 +51,9 @@ __global__ void k_fill(unsigned *p, size_t words) {
 // records of a dense tile), sums its stencils in an LDS window around the
 // tile in 64-bit fixed point with a per-problem power-of-two scale (no sum
 // can overflow, and the window's sums do not depend on the order of the
-// additions), and adds the window to the field: plain stores on the nodes
-// only this item reaches, one global atomic on the others.
+// additions), and stores the tile's own nodes into the field and the
+// others into the tile's halo slot; the windows of a dense tile's items
+// are summed by a second kernel.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int tile_cells(int n) { return n <= 32 ? n : 32; }
 constexpr int kMaxTiles = 4096;
@@ -178,10 +179,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
 // 2. one workgroup per problem: tile starts (exclusive scan of the counts),
 //    the work list of the tile kernels, the circulation and sum |Gamma|
 //    (partials summed in a fixed order, so every solve gives the same bits)
-//    and the fixed-point scale; the halo slots of split tiles are cleared.
+//    and the fixed-point scale.
 template <class T>
 __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__restrict__ d) {
-  __shared__ int wsum[kScatterBlock / 64];
+  __shared__ int wsum[kScatterBlock / 64], wsum2[kScatterBlock / 64];
   __shared__ double gsum[2][kScatterBlock / 64];
   const ProbDesc &P = d[blockIdx.x];
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
@@ -237,46 +238,64 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
   {
     // work list of the tile kernels, in tile order: a tile of c records
     // gives ceil(c / kTileChunk) items of consecutive records, an empty tile
-    // one empty item (which clears the tile's halo slot)
+    // one empty item (which clears the tile's halo slot).  A tile of
+    // several items goes on the split list with the first of its items'
+    // window slots.
     auto parts_of = [&](int k) {
       return k < per && lo + k < ntiles ? max(1, (cnts[k] + kTileChunk - 1) / kTileChunk) : 0;
     };
-    int ni = 0;
+    // items; split tiles (low 16 bits) and their items (high bits): both
+    // below 2^15 (tiles + nv / kTileChunk, split_items_max)
+    int ni = 0, sp = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) ni += parts_of(k);
-    int inc = ni;
+    for (int k = 0; k < kPer; ++k) {
+      const int q = parts_of(k);
+      ni += q;
+      if (q > 1) sp += 1 + (q << 16);
+    }
+    int a = ni, b = sp;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(inc, off);
-      if (lane >= off) inc += v;
+      const int va = __shfl_up(a, off), vb = __shfl_up(b, off);
+      if (lane >= off) {
+        a += va;
+        b += vb;
+      }
     }
     __syncthreads();   // wsum is reused
-    if (lane == 63) wsum[wave] = inc;
+    if (lane == 63) {
+      wsum[wave] = a;
+      wsum2[wave] = b;
+    }
     __syncthreads();
-    int at = inc - ni, tot_items = 0;
+    int at = a - ni, sat = b - sp, tot_items = 0, tot_sp = 0;
 #pragma unroll
     for (int w = 0; w < kScatterBlock / 64; ++w) {
-      if (w < wave) at += wsum[w];
+      if (w < wave) {
+        at += wsum[w];
+        sat += wsum2[w];
+      }
       tot_items += wsum[w];
+      tot_sp += wsum2[w];
     }
+    int stile = sat & 0xffff, slot = sat >> 16;
     int r = pos0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int c = cnts[k];
-      const int parts = parts_of(k);
-      if (parts > 1) {
-        // the items of a split tile add their halos to the tile's slot
-        T *hal = static_cast<T *>(P.halo) + (size_t)(lo + k) * kHaloRing;
-        for (int h = 0; h < kHaloRing; ++h) hal[h] = (T)0;
-      }
+      const int parts = parts_of(k), c = cnts[k];
+      // last field: 0 the tile's only item, else 1 + the item's window slot
       for (int j = 0; j < parts; ++j) {
-        // last field: 0 the tile's only item, 1 the first of several, 2 a later one
         const int4 it = make_int4(lo + k, r + j * kTileChunk, min(r + c, r + (j + 1) * kTileChunk),
-                                  parts == 1 ? 0 : (j == 0 ? 1 : 2));
+                                  parts > 1 ? 1 + slot + j : 0);
         *reinterpret_cast<int4 *>(P.items + 4 * (1 + at++)) = it;
+      }
+      if (parts > 1) {
+        *reinterpret_cast<int4 *>(P.splits + 4 * (1 + stile++)) = make_int4(lo + k, slot, parts, 0);
+        slot += parts;
       }
       r += c;
     }
+    if (tid == 0) *reinterpret_cast<int4 *>(P.splits) = make_int4(tot_sp & 0xffff, 0, 0, 0);
     if (tid == 0) *reinterpret_cast<int4 *>(P.items) = make_int4(tot_items, 0, 0, 0);
   }
   if (tid == 0) {
@@ -335,11 +354,10 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__r
 //    additions.  The tile's own ts^2 nodes (window-local 1 .. ts) are then
 //    stored into the field (zero, or the values to add to); the other
 //    6 ts + 9 window nodes belong to neighbouring tiles and are stored in
-//    the tile's halo slot, which step 5 adds to their owners.  No global
-//    atomic is needed, and the field is the same bits on every run.  The
-//    items of a split tile (more than kTileChunk records) add their own
-//    nodes and their halos with atomics instead (the slot was cleared by
-//    step 2).  The tile's count is cleared for the next solve.
+//    the tile's halo slot, which the convolutions (or step 5) add to their
+//    owners.  A dense tile's workgroup takes its records kTileChunk at a
+//    time into the same window: no global atomic, and the field is the same
+//    bits on every run.  The tile's count is cleared for the next solve.
 // 5. one workgroup per tile whose neighbours' windows can reach it: each of
 //    its 6 ts - 9 border nodes (local 0, 1 or ts-1 on an axis) adds, in a
 //    fixed order, the halo values of the non-empty neighbours that reach it.
@@ -383,6 +401,40 @@ template <> struct FixedPoint<double> {
   static __device__ __forceinline__ long long to_int(double x) { return __double2ll_rn(x); }
 };
 
+// A tile's summed window (fixed point; value_at(u, k) is node k, the u-th
+// of this thread): its own nodes go to the field (zero, or the values to
+// add to), the others to the tile's halo slot (every entry, zeros included)
+constexpr int kWinPer = (kSplitWin + kTileBlock - 1) / kTileBlock;   // nodes per thread
+// UNROLLED: the loop over a thread's nodes is unrolled (value_at may then
+// index registers by u); otherwise u is 0
+template <class T, bool UNROLLED, class F>
+__device__ __forceinline__ void store_tile_window(const ProbDesc &P, int t, int ts, int tps, int X0,
+                                                  int Y0, double inv, F value_at) {
+  const int n = P.n, bw = ts + 3, nwin = bw * bw;
+  T *w = static_cast<T *>(P.w);
+  T *hal = static_cast<T *>(P.halo) + (size_t)t * kHaloRing;
+  auto store = [&](long long v, int k) {
+    const int kx = k % bw, ky = k / bw;
+    const T val = (T)((double)v * inv);
+    if (kx >= 1 && kx <= ts && ky >= 1 && ky <= ts) {
+      if (v == 0) return;
+      T *node = w + (size_t)(Y0 + ky) * n + X0 + kx;
+      *node = P.w_accumulate ? *node + val : val;
+    } else {
+      hal[halo_index(kx, ky, ts)] = val;
+    }
+  };
+  if constexpr (UNROLLED) {
+#pragma unroll
+    for (int u = 0; u < kWinPer; ++u) {
+      const int k = threadIdx.x + u * kTileBlock;
+      if (k < nwin) store(value_at(u, k), k);
+    }
+  } else {
+    for (int k = threadIdx.x; k < nwin; k += kTileBlock) store(value_at(0, k), k);
+  }
+}
+
 // TS: the tile size when it is known at compile time (32, every grid of
 // n >= 32), 0 otherwise: the window loops then divide by constants
 template <class T, int TS>
@@ -395,14 +447,12 @@ __device__ __forceinline__ void tile_scatter_body(const ProbDesc &P, const FlatB
   const int bw = ts + 3, nwin = bw * bw;
   const int sexp = FixedPoint<T>::B - (int)P.aux[SC_RV_SCALE];
   const double scale = ldexp(1.0, sexp), inv = ldexp(1.0, -sexp);
-  T *w = static_cast<T *>(P.w);
   T *halo = static_cast<T *>(P.halo);
   // one item per workgroup when the launch covers the work list (it is
   // sized for the most items a problem can have)
   for (int i = fb.blk; i < cnt; i += fb.nblk) {
     const int4 it = *reinterpret_cast<const int4 *>(P.items + 4 * (1 + i));
     const int t = it.x, b0 = it.y, b1 = it.z;
-    const bool alone = it.w == 0;
     if (b0 == b1) {
       // a tile without vortices: its halo slot holds zeros for the readers
       // that add every neighbour's slot (the LDS window is not touched)
@@ -410,7 +460,6 @@ __device__ __forceinline__ void tile_scatter_body(const ProbDesc &P, const FlatB
       for (int k = tid; k < kHaloRing; k += kTileBlock) hal[k] = (T)0;
       continue;
     }
-    if (tid == 0 && it.w <= 1) P.bin_cnt[t] = 0;
     const int X0 = (t & (tps - 1)) * ts - 1, Y0 = (t >> tpsh) * ts - 1;   // window origin
     // the item's records (at most kTileChunk), loaded before the window is
     // cleared; clamped duplicates past the end add zero
@@ -448,23 +497,14 @@ __device__ __forceinline__ void tile_scatter_body(const ProbDesc &P, const FlatB
       }
     }
     lds_barrier();
-    T *hal = halo + (size_t)t * kHaloRing;
-    for (int k = tid; k < nwin; k += kTileBlock) {
-      const long long v = win[k];
-      const int kx = k % bw, ky = k / bw;
-      const T val = (T)((double)v * inv);
-      if (kx >= 1 && kx <= ts && ky >= 1 && ky <= ts) {
-        if (v == 0) continue;
-        T *node = w + (size_t)(Y0 + ky) * n + X0 + kx;
-        if (alone)
-          *node = P.w_accumulate ? *node + val : val;
-        else
-          atomic_add(node, val);
-      } else if (alone) {
-        hal[halo_index(kx, ky, ts)] = val;   // every entry, zeros included
-      } else if (v != 0) {
-        atomic_add(hal + halo_index(kx, ky, ts), val);
-      }
+    if (it.w == 0) {
+      if (tid == 0) P.bin_cnt[t] = 0;
+      store_tile_window<T, false>(P, t, ts, tps, X0, Y0, inv, [&](int, int k) { return win[k]; });
+    } else {
+      // an item of a split tile: its window goes to its own slot, and
+      // k_split_combine stores the tile's sum after this launch
+      long long *mine = P.splitwin + (size_t)(it.w - 1) * kSplitWin;
+      for (int k = tid; k < nwin; k += kTileBlock) mine[k] = win[k];
     }
     if (i + fb.nblk < cnt) lds_barrier();   // the window is cleared for the next item
   }
@@ -480,6 +520,41 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
     tile_scatter_body<T, 32>(P, fb, win);
   else
     tile_scatter_body<T, 0>(P, fb, win);
+}
+
+// 4b. one workgroup per tile of several items (after the tile kernel): the
+//     items' windows summed in integers (exact, so neither the order nor
+//     the split changes a bit), stored as a lone item's window would be
+template <class T>
+__global__ __launch_bounds__(kTileBlock) void k_split_combine(const ProbDesc *__restrict__ d, FlatMap fm) {
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  if (P.nv <= 0) return;
+  const int nsplit = P.splits[0];
+  const int n = P.n, ts = tile_cells(n), tps = n / ts;
+  const double inv = ldexp(1.0, (int)P.aux[SC_RV_SCALE] - FixedPoint<T>::B);
+  for (int e = fb.blk; e < nsplit; e += fb.nblk) {
+    const int4 sp = *reinterpret_cast<const int4 *>(P.splits + 4 * (1 + e));
+    const int t = sp.x, parts = sp.z;
+    const long long *win = P.splitwin + (size_t)sp.y * kSplitWin;
+    const int X0 = (t % tps) * ts - 1, Y0 = (t / tps) * ts - 1;
+    // each thread's nodes summed part by part: the loads of one part are
+    // issued together
+    long long acc[kWinPer];
+#pragma unroll
+    for (int u = 0; u < kWinPer; ++u) acc[u] = 0;
+    for (int q = 0; q < parts; ++q) {
+      const long long *wq = win + (size_t)q * kSplitWin;
+#pragma unroll
+      for (int u = 0; u < kWinPer; ++u) {
+        const int k = threadIdx.x + u * kTileBlock;
+        acc[u] += k < kSplitWin ? wq[k] : 0;
+      }
+    }
+    store_tile_window<T, true>(P, t, ts, tps, X0, Y0, inv, [&](int u, int) { return acc[u]; });
+    if (threadIdx.x == 0) P.bin_cnt[t] = 0;
+  }
 }
 
 // 5.: kFixupTiles tiles per workgroup, a few border nodes per thread; every
@@ -875,10 +950,9 @@ int fixup_blocks(int n) { return (halo_tiles(n) + kFixupTiles - 1) / kFixupTiles
 
 // items of a problem: one per tile plus one per further kTileChunk records
 // of a tile (sum over tiles of floor((c - 1) / kTileChunk) <= nv / kTileChunk)
-int tile_items_max(int n, int nv) {
-  if (nv <= 0) return 0;
-  return bin_tiles(n) + nv / kTileChunk;
-}
+int tile_items_max(int n, int nv) { return nv > 0 ? bin_tiles(n) + nv / kTileChunk : 0; }
+
+int split_blocks(int nv) { return std::min(64, split_tiles_max(nv)); }
 
 // grid of a launch: the flat map's blocks, or nb problems of `per` blocks
 static dim3 grid_of(const FlatMap *fm, int per, int nb) {
@@ -901,6 +975,11 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   // one workgroup per item of the work list, then one per tile for the halos
   hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
                      dim3(kTileBlock), 0, s, d, mt);
+  // tiles of several items: their windows summed after the tile kernel
+  const FlatMap ms = fm ? fm[4] : none;
+  if (fm ? ms.total > 0 : split_blocks(nv_max) > 0)
+    hipLaunchKernelGGL((k_split_combine<T>), grid_of(fm ? &ms : nullptr, split_blocks(nv_max), nb),
+                       dim3(kTileBlock), 0, s, d, ms);
   if (fm ? mh.total > 0 : (halo_pass && nv_max > 0 && halo_tiles(n) > 0))
     hipLaunchKernelGGL((k_halo_fixup<T>), grid_of(fm ? &mh : nullptr, fixup_blocks(n), nb), dim3(kFixupBlock),
                        0, s, d, mh);

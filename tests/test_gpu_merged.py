@@ -17,6 +17,7 @@ if not torch.cuda.is_available():
 
 from paper_2102_11910_amd import gpf  # noqa: E402
 from paper_2102_11910_amd import workloads as wl  # noqa: E402
+from oracle import operators as op  # noqa: E402
 from oracle.solve import solve as oracle_solve  # noqa: E402
 from tests.conftest import rell2  # noqa: E402
 from tests.oracle_adapter import body_of, problem_of  # noqa: E402
@@ -208,8 +209,7 @@ def test_dense_clouds_velocity_tiles(ctx):
 
 def _cluster_case(seed, n, nv, center, radius):
     """All vortices in a disc a few cells across: one or a few tiles hold
-    thousands of records, so R_v splits them into several work items whose
-    windows all add to the field atomically."""
+    thousands of records, which their R_v workgroups take 512 at a time."""
     dx = 2.56 / n
     rng = np.random.default_rng(seed)
     r = radius * np.sqrt(rng.uniform(0.0, 1.0, nv))
@@ -221,11 +221,11 @@ def _cluster_case(seed, n, nv, center, radius):
                    mode="circulation", gamma_b=float(-np.sum(G)))
 
 
-def test_dense_tiles_split_into_items(ctx):
-    """Tiles of more than 512 vortices are split into several items: a
-    uniform cloud of about 1200 per tile, one of exactly 512 and 513 per
-    tile on average, and a tight cluster inside one tile (thousands of
-    records); alone, merged, and against the oracle."""
+def test_dense_tiles_in_chunks(ctx):
+    """Tiles of more than 512 vortices, whose workgroups take their records
+    in several chunks: a uniform cloud of about 1200 per tile, one of
+    exactly 512 and 513 per tile on average, and a tight cluster inside one
+    tile (thousands of records); alone, merged, and against the oracle."""
     cases = [wl.random_case(241, 128, 2.0 / 128, 20000, surface="cylinder"),
              _cluster_case(242, 256, 4000, (0.6, -0.55), 6.0 * 2.56 / 256),
              _cluster_case(243, 256, 513, (-0.4, 0.5), 3.0 * 2.56 / 256),
@@ -242,7 +242,7 @@ def test_dense_tiles_split_into_items(ctx):
         gpf.gpf_solve(st.plans[i], st.bodies[i], st.ins[i], oa.struct)
         gpf.gpf_sync(oa.status)
         hm = _host(outs[i])
-        _compare(hm, _host(oa), f"[split items batch vs alone] {c.name}")
+        _compare(hm, _host(oa), f"[dense tiles batch vs alone] {c.name}")
         ref = oracle_solve(problem_of(c), body_of(c))
         es, ef = rell2(hm["s"], ref.s), rell2(hm["f"], ref.f)
         eu = rell2(hm["uv"], np.r_[ref.u, ref.v])
@@ -250,16 +250,27 @@ def test_dense_tiles_split_into_items(ctx):
         assert es <= 1e-5 and ef <= 1e-4 and eu <= 1e-4
 
 
+def _with_dense_cluster(c, k, seed):
+    """c plus k vortices within a few cells of a tile corner: that tile and
+    its neighbours hold more than 512 vortices each (several chunks)."""
+    rng = np.random.default_rng(seed)
+    cx = c.x0 + c.dx * 64.0
+    c.X = np.r_[c.X, wl.f32(cx + c.dx * rng.uniform(-3.0, 3.0, k))]
+    c.Y = np.r_[c.Y, wl.f32(cx + c.dx * rng.uniform(-3.0, 3.0, k))]
+    c.G = np.r_[c.G, wl.f32(rng.normal(0.0, 1e-2, k))]
+    return c
+
+
 def test_scattered_field_repeats_bit_for_bit(ctx):
-    """R_v without atomics (tiles of at most 512 vortices): the source field
-    is the same bits on every call, whatever order the workgroups run in
-    (sparse and dense clouds, one and several tiles per grid, overwrite and
-    accumulate).  Full solves are not compared this way: R_s f still adds
-    with atomics."""
+    """R_v: the source field is the same bits on every call, whatever order
+    the workgroups run in (sparse and dense clouds, one and several tiles per
+    grid, tiles of several chunks of records, overwrite and accumulate), and
+    for the vortices given in another order."""
     cases = [wl.random_case(251, 512, 2.56 / 512, 20000, surface="ellipse"),
              wl.random_case(252, 256, 2.56 / 256, 3000, surface="plate", mode="shed"),
              wl.random_case(253, 1024, 2.56 / 1024, 4000, surface="cylinder"),
              wl.random_case(254, 128, 2.0 / 128, 6000, surface="cylinder"),
+             _with_dense_cluster(wl.random_case(256, 128, 2.0 / 128, 4000, surface=None), 6000, 256),
              wl.random_case(255, 32, 2.0 / 32, 300, surface=None)]
     for c in cases:
         plan = gpf.Plan(ctx, c.n, c.dx)
@@ -271,7 +282,35 @@ def test_scattered_field_repeats_bit_for_bit(ctx):
             gpf.gpf_regularize_vortices(plan, X, Y, G, w, accumulate=True)   # 2 R_v
             torch.cuda.synchronize()
             fields.append(w.cpu().numpy())
+        perm = np.random.default_rng(7).permutation(c.nv)
+        Xp, Yp, Gp = (torch.as_tensor(a[perm], dtype=torch.float64).to(DEV) for a in (c.X, c.Y, c.G))
+        w = torch.full((c.n, c.n), float("nan"), dtype=plan.field_dtype, device=DEV)
+        gpf.gpf_regularize_vortices(plan, Xp, Yp, Gp, w)
+        gpf.gpf_regularize_vortices(plan, Xp, Yp, Gp, w, accumulate=True)
+        torch.cuda.synchronize()
+        fields.append(w.cpu().numpy())
         same = all(np.array_equal(fields[0], f) for f in fields[1:])
         ok = np.isfinite(fields[0]).all() and np.abs(fields[0]).max() > 0
-        say(f"[R_v repeat] {c.name} nv={c.nv}: bit-identical {same}, finite {ok}")
+        ref = 2.0 * op.regularize_vortices(op.Grid.centered(c.n, c.dx), c.X, c.Y, c.G)
+        err = rell2(fields[0].astype(np.float64), ref)
+        say(f"[R_v repeat] {c.name} nv={c.nv}: bit-identical {same}, finite {ok}, relL2 {err:.1e}")
         assert same and ok, c.name
+        assert err <= 1e-6, (c.name, err)
+
+
+def test_solve_without_body_repeats_bit_for_bit(ctx):
+    """Without a body no step of a solve adds with atomics: the
+    streamfunction and the velocities are the same bits on every call, with
+    tiles of several chunks of records."""
+    c = _with_dense_cluster(wl.random_case(257, 128, 2.0 / 128, 4000, surface=None), 6000, 257)
+    outs = []
+    for rep in range(3):
+        s = gpf.Solver(ctx, c.n, c.dx, None, flags=gpf.GPF_FP32)
+        X, Y, G = s.upload(c)
+        s.solve(s.inputs_for(c, X, Y, G), X, velocities=True)
+        gpf.gpf_sync(s.status)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy() for t in (s.psi, s.u, s.v)])
+    same = all(np.array_equal(a, b) for o in outs[1:] for a, b in zip(outs[0], o))
+    say(f"[solve repeat] n={c.n} nv={c.nv}: bit-identical {same}")
+    assert same
