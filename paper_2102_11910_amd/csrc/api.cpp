@@ -294,6 +294,7 @@ gpf_status gpf_workspace::ensure(int nn, bool need32, bool need64, int nns, int 
     const size_t cols = 1 + GPF_MAX_EDGES;
     GPF_TRY(rhs.alloc(cols * nns * sizeof(double)));
     GPF_TRY(y.alloc(cols * nns * sizeof(double)));
+    GPF_TRY(fsurf.alloc(nns * sizeof(double)));
     ns = std::max(ns, nns);
   }
   n = std::max(n, nn);
@@ -523,6 +524,11 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.st_w = b->st_w.as<double>();
   pd.gamma0 = b->gamma0;
   pd.rhs = ws->rhs.as<double>();
+  pd.fs = ws->fsurf.as<double>();
+  pd.rs_node = b->rs_node.as<int>();
+  pd.rs_off = b->rs_off.as<int>();
+  pd.rs_code = b->rs_code.as<int>();
+  pd.rs_nodes = b->rs_nodes;
   pd.f_out = out->d_f;
   pd.ft_out = out->d_ftilde;
   pd.nx = b->nx.as<double>();
@@ -576,7 +582,7 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
                         const ConvDesc *c2, int nv_max, int ns_max, int m_max, bool impulse,
                         int band, int xcds, const ConvSched &sc1, const ConvSched &sc2,
                         bool shared, const double *shared_sinv, int vel_kinds, int fband2,
-                        bool halo_pass, hipStream_t s) {
+                        bool halo_pass, int rs_blocks, hipStream_t s) {
   GPF_HIP(launch_scatter_vortices<TW>(pd, nb, cfg.n, nv_max, s, nullptr, halo_pass));
   GPF_HIP((launch_convolve<TW, T1>(cfg.n, c1, nb, xcds, cfg.body ? band : 0, s, sc1)));
   if (cfg.body) {
@@ -587,6 +593,7 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
       if (shared) GPF_HIP(launch_schur_gemm(pd, nb, ns_max, m_max, shared_sinv, s));
       GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, m_max, s));
     }
+    GPF_HIP(launch_rs_apply<TW>(pd, nb, rs_blocks, s));
     GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2, fband2)));
   }
   GPF_HIP(launch_solve_velocity<T2>(pd, nb, cfg.n, nv_max, s, nullptr, vel_kinds));
@@ -608,8 +615,10 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   int vel_kinds = 0;   // velocity kernels the group needs: 1 vortex by vortex, 2 tile by tile
   int fband2 = 0;      // source rows the second forward row pass transforms (most of any problem)
   bool halo_pass = false;   // some problem's halos are added by the scatter's halo pass
+  int rs_blocks = 0;        // workgroups of the R_s gather per problem (most of any)
   for (int i = 0; i < nb; ++i) {
     describe(probs[i], cfg, pd[i], c1[i], c2[i]);
+    if (cfg.body) rs_blocks = std::max(rs_blocks, rs_apply_blocks(pd[i].rs_nodes, pd[i].sv.m));
     halo_pass = halo_pass || (pd[i].nv > 0 && !pd[i].halo_defer);
     fband2 = std::max(fband2, c2[i].fwd_hi - c2[i].fwd_lo + 1);
     if (pd[i].u && pd[i].nv > 0) vel_kinds |= pd[i].vel_tiles ? 2 : 1;
@@ -639,14 +648,14 @@ gpf_status run_group(const GroupCfg &cfg, const std::vector<ProblemRef> &probs, 
   if (cfg.fp64_plan)
     return launch_group<double, double, double>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, rs_blocks, s);
   if (cfg.conv1_fp64)
     return launch_group<double, double, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, rs_blocks, s);
   return launch_group<float, float, float>(cfg, nb, dpd, dc1, dc2, nv_max, ns_max, m_max, impulse,
                                                    band, xcds, sc1, sc2, shared,
-                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, s);
+                                                   shared ? probs[0].body->sinv.as<double>() : nullptr, vel_kinds, fband2, halo_pass, rs_blocks, s);
 }
 
 // A batch can run merged when its problems differ only in grid size and in
@@ -659,11 +668,11 @@ bool mergeable(const GroupCfg &c) {
 // Bytes of the descriptor block of a merged batch of nb problems: the
 // problem and convolution descriptors, the work tables of the multi-size
 // passes (three per convolution, two convolutions, two classes), then the
-// flat block maps (binning, tile scatter, halo fix-up, two velocity kernels:
-// five entries per problem).
+// flat block maps (per class: bin count, tile scatter, halo pass, bin
+// place, split tiles, R_s gather; over all problems: two velocity kernels).
 size_t merged_block_bytes(int nb) {
   return ((size_t)nb * kProblemDescBytes + 15) / 16 * 16 + 9 * (size_t)nb * sizeof(MultiEntry) +
-         7 * (size_t)nb * sizeof(FlatEntry);   // five binning maps per class, two velocity maps
+         8 * (size_t)nb * sizeof(FlatEntry);   // six maps per class, two velocity maps
 }
 
 // Every stage of the solve as one launch per precision class over problems
@@ -750,17 +759,19 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto bin_blocks = [&](int i) { return pd[i].nv > 0 ? bin_count_blocks(pd[i].nv) : 1; };
   auto place_blocks = [&](int i) { return std::max(1, (pd[i].nv + 255) / 256); };
   auto split_tile_blocks = [&](int i) { return pd[i].nv > 0 ? split_blocks(pd[i].nv) : 0; };
+  auto rs_blocks = [&](int i) { return rs_apply_blocks(pd[i].rs_nodes, pd[i].sv.m); };
   auto tile_blocks = [&](int i) { return tile_items_max(pd[i].n, pd[i].nv); };
   auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
   auto halo_blocks = [&](int i) { return pd[i].nv > 0 && !pd[i].halo_defer ? fixup_blocks(pd[i].n) : 0; };
-  FlatMap fsa[5], fsb[5], fvel[2];
+  FlatMap fsa[6], fsb[6], fvel[2];
   if (na > 0) {
     make_flat(0, na, bin_blocks, &fsa[0]);
     make_flat(0, na, tile_blocks, &fsa[1]);
     make_flat(0, na, halo_blocks, &fsa[2]);
     make_flat(0, na, place_blocks, &fsa[3]);
     make_flat(0, na, split_tile_blocks, &fsa[4]);
+    make_flat(0, na, rs_blocks, &fsa[5]);
   }
   if (nbb > 0) {
     make_flat(na, nb, bin_blocks, &fsb[0]);
@@ -768,6 +779,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     make_flat(na, nb, halo_blocks, &fsb[2]);
     make_flat(na, nb, place_blocks, &fsb[3]);
     make_flat(na, nb, split_tile_blocks, &fsb[4]);
+    make_flat(na, nb, rs_blocks, &fsb[5]);
   }
   make_flat(0, nb, vel_gather, &fvel[0]);
   make_flat(0, nb, vel_tiles, &fvel[1]);
@@ -799,8 +811,8 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto fixf = [&](FlatMap *fm, int k) {
     for (int i = 0; i < k; ++i) fm[i].e = reinterpret_cast<const FlatEntry *>(base + (size_t)fm[i].e);
   };
-  if (na > 0) fixf(fsa, 5);
-  if (nbb > 0) fixf(fsb, 5);
+  if (na > 0) fixf(fsa, 6);
+  if (nbb > 0) fixf(fsb, 6);
   fixf(fvel, 2);
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
@@ -827,6 +839,8 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   if (nbb > 0) GPF_HIP(launch_surface_rhs<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
   if (na > 0) GPF_HIP(launch_schur_apply<float>(dpd, na, ca.ns_max, ca.m_max, s));
   if (nbb > 0) GPF_HIP(launch_schur_apply<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
+  if (na > 0) GPF_HIP(launch_rs_apply<float>(dpd, na, 0, s, &fsa[5]));
+  if (nbb > 0) GPF_HIP(launch_rs_apply<double>(dpd + na, nbb, 0, s, &fsb[5]));
   // final convolution of all vorticity
   if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc2, mp2a, s)));
   if (nbb > 0) GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, s)));
@@ -1088,6 +1102,37 @@ gpf_status gpf_body_create(gpf_plan *plan, int ns, const double *h_xs, const dou
   GPF_HIP(hipMemcpy(&hstatus, status, sizeof(unsigned), hipMemcpyDeviceToHost));
   GPF_TRY(fill_now(status, 0, sizeof(unsigned)));
   if (hstatus & GPF_DEV_OUT_OF_GRID) return fail(GPF_E_OUT_OF_GRID, "gpf_body_create: stencil outside grid");
+  {
+    // R_s as a gather (Sec. 2.2, eq. basicblock: R_s spreads each point's
+    // value over its 4 x 4 stencil): the nodes the stencils reach, each with
+    // its (point, a, b) entries in point order, so that a solve adds R_s f
+    // node by node in a fixed order
+    std::vector<int> sti(2 * (size_t)ns);
+    GPF_HIP(hipMemcpy(sti.data(), b->st_i.p, sti.size() * sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<std::pair<int, int>> e;
+    e.reserve(16 * (size_t)ns);
+    for (int p = 0; p < ns; ++p)
+      for (int bb = 0; bb < 4; ++bb)
+        for (int a = 0; a < 4; ++a)
+          e.emplace_back((sti[2 * p + 1] + bb) * g.n + sti[2 * p] + a, 16 * p + 4 * bb + a);
+    std::sort(e.begin(), e.end());
+    std::vector<int> node, off, code(e.size());
+    for (size_t k = 0; k < e.size(); ++k) {
+      if (k == 0 || e[k].first != e[k - 1].first) {
+        node.push_back(e[k].first);
+        off.push_back((int)k);
+      }
+      code[k] = e[k].second;
+    }
+    off.push_back((int)e.size());
+    b->rs_nodes = (int)node.size();
+    GPF_TRY(b->rs_node.alloc(node.size() * sizeof(int)));
+    GPF_TRY(b->rs_off.alloc(off.size() * sizeof(int)));
+    GPF_TRY(b->rs_code.alloc(code.size() * sizeof(int)));
+    GPF_HIP(hipMemcpy(b->rs_node.p, node.data(), node.size() * sizeof(int), hipMemcpyHostToDevice));
+    GPF_HIP(hipMemcpy(b->rs_off.p, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+    GPF_HIP(hipMemcpy(b->rs_code.p, code.data(), code.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
   double g0 = 0.0, nr = 0.0, nf = 0.0, nrhs = 0.0, npert = 0.0;
   double mx = 0.0, my = 0.0, mr2 = 0.0;
   for (int p = 0; p < ns; ++p) {

@@ -241,6 +241,12 @@ struct ProbDesc {
   double gamma0;
   double mom_x, mom_y, mom_r2;  // sums of fhat0 x, fhat0 y, fhat0 (x^2 + y^2)
   double *rhs;                  // Schur right-hand sides: ns x (1+m)
+  double *fs;                   // f per surface point, written by the surface step
+  // R_s as a gather: the rs_nodes grid nodes (n j + i, ascending) the surface
+  // stencils reach, node k's entries rs_code[rs_off[k] .. rs_off[k+1]) =
+  // 16 p + 4 b + a (stencil weight a, b of point p), in point order
+  const int *rs_node, *rs_off, *rs_code;
+  int rs_nodes;
   double *y;                    // S^-1 rhs, formed for the whole launch (problems sharing
                                 // one body), or null: each workgroup forms its rows
   // outputs (nullable)
@@ -418,6 +424,13 @@ hipError_t launch_schur_gemm(const ProbDesc *d, int nb, int ns, int m_max, const
 // the same for bodies of several parts (mode GPF_PARTS)
 template <class T>
 hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
+// R_s f and the new vortices' stencils added to the source field after the
+// surface step, node by node in a fixed order; `blocks` per problem (the
+// most of rs_apply_blocks over the launch), or the flat map fm
+template <class T>
+hipError_t launch_rs_apply(const ProbDesc *d, int nb, int blocks, hipStream_t s,
+                           const FlatMap *fm = nullptr);
+inline int rs_apply_blocks(int rs_nodes, int m) { return (rs_nodes + 255) / 256 + (m > 0 ? 1 : 0); }
 template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);
 // velocities of a solve's vortices from their tile-sorted records (after
@@ -535,7 +548,7 @@ int sched_class(int nb);
 // convolution output, aux block and Schur vectors.
 struct gpf_workspace {
   int n = 0, ns = 0, nv = 0;
-  gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y;
+  gpf::DevBuf w32, w64, x32, x64, s64, aux, part, rhs, y, fsurf;
   gpf::DevBuf xb;   // compact band of the first convolution's column pass
   gpf::DevBuf bin_cnt, bin_start, items, rank, sorted, halo, splits, splitwin;
   // band: rows of a body's band (16-row groups), 0 without a body
@@ -584,6 +597,8 @@ struct gpf_body {
   int row_lo = 0, row_hi = 0; // grid rows read by the surface stencils
   gpf::DevBuf xs, ys, ds;     // surface geometry (double)
   gpf::DevBuf st_i, st_w;     // stencils: base (i0, j0) per point, 8 weights
+  gpf::DevBuf rs_node, rs_off, rs_code;   // R_s as a gather (ProbDesc)
+  int rs_nodes = 0;
   gpf::DevBuf sinv;           // ns x ns S^-1, row-major, FP64
   gpf::DevBuf f0;             // S^-1 1
   gpf::DevBuf ghat;           // S^-T dS

@@ -302,8 +302,6 @@ __global__ __launch_bounds__(kRB) void k_surface_rhs(const ProbDesc *__restrict_
   if (active && lane == 0) P.rhs[(size_t)(1 + j) * ns + p] = val;
 }
 
-__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 
 // Surface solve of one batch in one launch.  Every scalar the constraint
@@ -350,13 +348,11 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   const double gw_dev = P.aux[SC_GAMMA_W];
-  // the finishing step's loads (this thread's row and stencil node) do not
-  // depend on the solve: issued first
+  // the finishing step's load (this thread's row) does not depend on the
+  // solve: issued first
   const int lr = tid >> 4, node = tid & 15;
   const int pf = min(row0 + min(lr, CR - 1), ns - 1);
-  const double f0p = P.f0[pf], dsp = P.ds[pf];
-  const int sti = P.st_i[2 * pf], stj = P.st_i[2 * pf + 1];
-  const double swa = P.st_w[8 * pf + (node & 3)], swb = P.st_w[8 * pf + 4 + (node >> 2)];
+  const double f0p = P.f0[pf];
   size_t coff[MC];   // column offsets, clamped to the last column
 #pragma unroll
   for (int c = 0; c < MC; ++c) coff[c] = (size_t)min(c, ncol - 1) * ns;
@@ -594,14 +590,12 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
   }
   __syncthreads();
 
-  // f, f~ of the rows; 16 lanes per row add R_s f at its 16 stencil nodes
+  // f, f~ of the rows (R_s f and the new vortices go to the field in
+  // k_rs_apply, node by node)
   const double c1 = scal[0], s0 = scal[1];
-  const int n = P.n;
-  T *w = static_cast<T *>(P.w);
-  const double inv_dx2 = 1.0 / (P.dx * P.dx);
   {
     const int p = row0 + lr;
-    if (lr < CR && p < ns) {
+    if (lr < CR && p < ns && node == 0) {
       double ft, f;
       if (mode == GPF_CIRCULATION) {
         f = yr[lr][0] - s0 * f0p;
@@ -612,26 +606,9 @@ __global__ __launch_bounds__(kCB) void k_schur_apply(const ProbDesc *__restrict_
         ft = x - s0;
         f = f0p * ft;
       }
-      if (node == 0) {
-        if (P.f_out) P.f_out[p] = f;
-        if (P.ft_out) P.ft_out[p] = ft;
-      }
-      const int a = node & 3, b = node >> 2;
-      const double amp = dsp * f * inv_dx2;
-      atomic_add(w + (size_t)(stj + b) * n + sti + a, (T)(amp * swa * swb));
-    }
-  }
-  if (blockIdx.x == 0 && mode == GPF_KUTTA_SHED && tid < 16 * m) {
-    const int j = tid >> 4, node = tid & 15;
-    const double zx = sv.znew_from >= 0 ? P.xv[sv.znew_from + j] : sv.xnew[j];
-    const double zy = sv.znew_from >= 0 ? P.yv[sv.znew_from + j] : sv.ynew[j];
-    const double xi = (zx - P.x0) / P.dx, eta = (zy - P.y0) / P.dx;
-    if (xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0) {
-      const int i0 = (int)floor(xi) - 1, j0 = (int)floor(eta) - 1;
-      const double fx = xi - floor(xi), fy = eta - floor(eta);
-      const int a = node & 3, b = node >> 2;
-      atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
-                 (T)(scal[3 + j] * inv_dx2 * m4p(fy + 1.0 - b) * m4p(fx + 1.0 - a)));
+      P.fs[p] = f;
+      if (P.f_out) P.f_out[p] = f;
+      if (P.ft_out) P.ft_out[p] = ft;
     }
   }
   // workgroup 0 writes the scalars last, so that no barrier waits on them
@@ -968,40 +945,104 @@ __global__ __launch_bounds__(kCB) void k_schur_apply_parts(const ProbDesc *__res
   }
   __syncthreads();
 
-  // f, f~ of the rows; 16 lanes per row add R_s f at its 16 stencil nodes
-  const int n = P.n;
-  T *w = static_cast<T *>(P.w);
-  const double inv_dx2 = 1.0 / (P.dx * P.dx);
+  // f, f~ of the rows (R_s f and the new vortices go to the field in
+  // k_rs_apply, node by node)
   {
     const int lr = tid >> 4, node = tid & 15;
     const int p = row0 + lr;
-    if (p < ns) {
+    if (p < ns && node == 0) {
       double f = yr[lr][0];
       for (int i = 0; i < m; ++i) f += sol[np + i] * yr[lr][1 + i];
       for (int l = 0; l < np; ++l) f -= sol[l] * P.zpart[(size_t)l * ns + p];
-      if (node == 0) {
-        if (P.f_out) P.f_out[p] = f;
-        if (P.ft_out) P.ft_out[p] = f / P.f0[p];
-      }
-      const int a = node & 3, b = node >> 2;
-      const int i0 = P.st_i[2 * p], j0 = P.st_i[2 * p + 1];
-      const double amp = P.ds[p] * f * inv_dx2;
-      atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
-                 (T)(amp * P.st_w[8 * p + a] * P.st_w[8 * p + 4 + b]));
+      P.fs[p] = f;
+      if (P.f_out) P.f_out[p] = f;
+      if (P.ft_out) P.ft_out[p] = f / P.f0[p];
     }
   }
-  if (blockIdx.x == 0 && tid < 16 * m) {
-    const int j = tid >> 4, node = tid & 15;
-    const double zx = sv.znew_from >= 0 ? P.xv[sv.znew_from + j] : sv.xnew[j];
-    const double zy = sv.znew_from >= 0 ? P.yv[sv.znew_from + j] : sv.ynew[j];
-    const double xi = (zx - P.x0) / P.dx, eta = (zy - P.y0) / P.dx;
-    if (xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0) {
-      const int i0 = (int)floor(xi) - 1, j0 = (int)floor(eta) - 1;
-      const double fx = xi - floor(xi), fy = eta - floor(eta);
-      const int a = node & 3, b = node >> 2;
-      atomic_add(w + (size_t)(j0 + b) * n + i0 + a,
-                 (T)(sol[np + j] * inv_dx2 * m4p(fy + 1.0 - b) * m4p(fx + 1.0 - a)));
+}
+
+// R_s f and the new vortices' stencils added to the source field (Sec. 2.2,
+// eq. basicblock; new vortices Sec. 2.4.2), node by node: one thread per
+// node the surface stencils reach sums its entries in point order, then the
+// new vortices reaching the node in their order, and adds the sum once; the
+// last workgroup of a problem that adds new vortices takes their nodes
+// outside that list (the first of equal candidates).  No two threads write
+// one node, so the field is the same bits on every run.
+// new vortex j's base node (i0, j0) and fractions; false outside the window
+__device__ __forceinline__ bool new_vortex_cell(const ProbDesc &P, int j, int *i0, int *j0, double *fx,
+                                                double *fy) {
+  const SolveScalars &sv = P.sv;
+  const int n = P.n;
+  const double zx = sv.znew_from >= 0 ? P.xv[sv.znew_from + j] : sv.xnew[j];
+  const double zy = sv.znew_from >= 0 ? P.yv[sv.znew_from + j] : sv.ynew[j];
+  const double xi = (zx - P.x0) / P.dx, eta = (zy - P.y0) / P.dx;
+  if (!(xi >= 2.0 && xi < n - 3.0 && eta >= 2.0 && eta < n - 3.0)) return false;
+  *i0 = (int)floor(xi) - 1;
+  *j0 = (int)floor(eta) - 1;
+  *fx = xi - floor(xi);
+  *fy = eta - floor(eta);
+  return true;
+}
+
+// sum over new vortices 0 .. m-1 whose stencils reach node (ix, iy) of
+// Gamma_j times the stencil weight there
+__device__ __forceinline__ double new_vortex_weights(const ProbDesc &P, int m, int ix, int iy) {
+  double v = 0.0;
+  for (int j = 0; j < m; ++j) {
+    int i0, j0;
+    double fx, fy;
+    if (!new_vortex_cell(P, j, &i0, &j0, &fx, &fy)) continue;
+    const int a = ix - i0, b = iy - j0;
+    if (a < 0 || a > 3 || b < 0 || b > 3) continue;
+    v += P.aux[SC_GAMMA_NEW + j] * m4p(fy + 1.0 - b) * m4p(fx + 1.0 - a);
+  }
+  return v;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_rs_apply(const ProbDesc *__restrict__ d, FlatMap fm) {
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  const int K = P.rs_nodes, n = P.n, m = P.sv.m;
+  const int kb = (K + 255) / 256;
+  T *w = static_cast<T *>(P.w);
+  const double inv_dx2 = 1.0 / (P.dx * P.dx);
+  if (fb.blk < kb) {
+    const int k = fb.blk * 256 + threadIdx.x;
+    if (k >= K) return;
+    const int node = P.rs_node[k], e1 = P.rs_off[k + 1];
+    double v = 0.0;
+    for (int e = P.rs_off[k]; e < e1; ++e) {
+      const int c = P.rs_code[e], p = c >> 4, b = (c >> 2) & 3, a = c & 3;
+      v += P.ds[p] * P.fs[p] * inv_dx2 * P.st_w[8 * p + a] * P.st_w[8 * p + 4 + b];
     }
+    if (m > 0) v += new_vortex_weights(P, m, node % n, node / n) * inv_dx2;
+    w[node] = (T)((double)w[node] + v);
+  } else if (fb.blk == kb && m > 0) {
+    // candidates: node (a, b) of new vortex j, thread 16 j + 4 b + a
+    const int t = threadIdx.x, j = t >> 4, a = t & 3, b = (t >> 2) & 3;
+    if (j >= m) return;
+    int i0, j0;
+    double fx, fy;
+    if (!new_vortex_cell(P, j, &i0, &j0, &fx, &fy)) return;
+    const int ix = i0 + a, iy = j0 + b, node = iy * n + ix;
+    // a node on the list is its thread's; one an earlier new vortex
+    // reaches is that vortex's candidate
+    int lo = 0, hi = K;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (P.rs_node[mid] < node) lo = mid + 1; else hi = mid;
+    }
+    if (lo < K && P.rs_node[lo] == node) return;
+    for (int jj = 0; jj < j; ++jj) {
+      int ki, kj;
+      double gx, gy;
+      if (new_vortex_cell(P, jj, &ki, &kj, &gx, &gy) && ix - ki >= 0 && ix - ki <= 3 && iy - kj >= 0 &&
+          iy - kj <= 3)
+        return;
+    }
+    w[node] = (T)((double)w[node] + new_vortex_weights(P, m, ix, iy) * inv_dx2);
   }
 }
 
@@ -1404,5 +1445,15 @@ hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipSt
 }
 template hipError_t launch_schur_apply_parts<float>(const ProbDesc *, int, int, hipStream_t);
 template hipError_t launch_schur_apply_parts<double>(const ProbDesc *, int, int, hipStream_t);
+
+template <class T>
+hipError_t launch_rs_apply(const ProbDesc *d, int nb, int blocks, hipStream_t s, const FlatMap *fm) {
+  if (fm ? fm->total <= 0 : blocks <= 0) return hipSuccess;
+  const dim3 grid = fm ? dim3(fm->total) : dim3(blocks, nb);
+  hipLaunchKernelGGL((k_rs_apply<T>), grid, dim3(256), 0, s, d, fm ? *fm : FlatMap{nullptr, 0, 0});
+  return hipGetLastError();
+}
+template hipError_t launch_rs_apply<float>(const ProbDesc *, int, int, hipStream_t, const FlatMap *);
+template hipError_t launch_rs_apply<double>(const ProbDesc *, int, int, hipStream_t, const FlatMap *);
 
 }  // namespace gpf

@@ -31,8 +31,6 @@ __device__ __forceinline__ bool cell(double p, double o, double dx, int lo, int 
   return true;
 }
 
-__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 constexpr int kScatterBlock = 256;
 static_assert(kPartStride * kScatterBlock == kMaxVortices, "one partial per bin_count workgroup");

@@ -298,6 +298,50 @@ def test_scattered_field_repeats_bit_for_bit(ctx):
         assert err <= 1e-6, (c.name, err)
 
 
+def test_solves_repeat_bit_for_bit(ctx):
+    """No step of a solve adds with float atomics (R_v in integers, R_s f
+    and the new vortices node by node): streamfunction, f and velocities
+    are the same bits on every call, alone and in a merged batch, for a
+    cylinder with prescribed circulation, a plate shedding at both edges,
+    an FP64 first convolution, and tiles of several items."""
+    cases = [wl.random_case(261, 128, 2.0 / 128, 3000, surface="cylinder"),
+             wl.random_case(262, 256, 2.0 / 256, 2000, surface="plate", mode="shed"),
+             _with_dense_cluster(wl.random_case(263, 128, 2.0 / 128, 1000, surface="ellipse"), 3000, 263)]
+    flags = [gpf.GPF_FP32, gpf.GPF_FP32, gpf.GPF_CONV1_FP64]
+    for c, fl in zip(cases, flags):
+        outs = []
+        for rep in range(3):
+            r = run_solve_case(ctx, c, fl)
+            outs.append(r)
+        same = all(np.array_equal(outs[0][k], o[k]) for o in outs[1:] for k in outs[0])
+        say(f"[solve repeat] {c.name} flags={fl}: bit-identical {same}")
+        assert same, c.name
+    st = Setup(ctx, cases)
+    batch = gpf.Batch(ctx, len(cases))
+    runs = []
+    for rep in range(3):
+        outs = st.outputs()
+        batch.solve(st.plans, st.bodies, st.ins, [o.struct for o in outs])
+        for o in outs:
+            gpf.gpf_sync(o.status)
+        runs.append([_host(o) for o in outs])
+    same = all(np.array_equal(runs[0][i][k], r[i][k]) for r in runs[1:] for i in range(len(cases))
+               for k in runs[0][i])
+    say(f"[merged repeat] {len(cases)} problems: bit-identical {same}")
+    assert same
+
+
+def run_solve_case(ctx, c, flags):
+    edges = tuple(c.edges) if c.mode in ("kutta", "shed") else None
+    s = gpf.Solver(ctx, c.n, c.dx, c.surface, flags=flags, edges=edges)
+    X, Y, G = s.upload(c)
+    s.solve(s.inputs_for(c, X, Y, G), X, velocities=True)
+    gpf.gpf_sync(s.status)
+    torch.cuda.synchronize()
+    return {"s": s.psi.cpu().numpy(), "u": s.u.cpu().numpy(), "v": s.v.cpu().numpy(),
+            "f": s.f.cpu().numpy(), "sc": s.scalars.cpu().numpy()}
+
+
 def test_solve_without_body_repeats_bit_for_bit(ctx):
     """Without a body no step of a solve adds with atomics: the
     streamfunction and the velocities are the same bits on every call, with
