@@ -409,6 +409,7 @@ void describe(const ProblemRef &r, const GroupCfg &cfg, ProbDesc &pd, ConvDesc &
   pd.yv = in->d_yv;
   pd.gv = in->d_gv;
   pd.w = w64 ? ws->w64.p : ws->w32.p;
+  pd.w64 = w64 ? 1 : 0;
   pd.aux = ws->aux.as<double>();
   pd.partials = ws->part.as<double>();
   pd.bin_cnt = ws->bin_cnt.as<int>();
@@ -593,7 +594,7 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
       if (shared) GPF_HIP(launch_schur_gemm(pd, nb, ns_max, m_max, shared_sinv, s));
       GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, m_max, s));
     }
-    GPF_HIP(launch_rs_apply<TW>(pd, nb, rs_blocks, s));
+    GPF_HIP(launch_rs_apply(pd, nb, rs_blocks, s));
     GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2, fband2)));
   }
   GPF_HIP(launch_solve_velocity<T2>(pd, nb, cfg.n, nv_max, s, nullptr, vel_kinds));
@@ -764,23 +765,24 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
   auto halo_blocks = [&](int i) { return pd[i].nv > 0 && !pd[i].halo_defer ? fixup_blocks(pd[i].n) : 0; };
-  FlatMap fsa[6], fsb[6], fvel[2];
+  // per class: bin count, tile scatter, halo pass, bin place (the split
+  // tiles' kernel runs once for both classes: fs*[4] stays empty); over
+  // all problems: split tiles, R_s gather, two velocity kernels
+  FlatMap fsa[5] = {}, fsb[5] = {}, fcomb, frs, fvel[2];
   if (na > 0) {
     make_flat(0, na, bin_blocks, &fsa[0]);
     make_flat(0, na, tile_blocks, &fsa[1]);
     make_flat(0, na, halo_blocks, &fsa[2]);
     make_flat(0, na, place_blocks, &fsa[3]);
-    make_flat(0, na, split_tile_blocks, &fsa[4]);
-    make_flat(0, na, rs_blocks, &fsa[5]);
   }
   if (nbb > 0) {
     make_flat(na, nb, bin_blocks, &fsb[0]);
     make_flat(na, nb, tile_blocks, &fsb[1]);
     make_flat(na, nb, halo_blocks, &fsb[2]);
     make_flat(na, nb, place_blocks, &fsb[3]);
-    make_flat(na, nb, split_tile_blocks, &fsb[4]);
-    make_flat(na, nb, rs_blocks, &fsb[5]);
   }
+  make_flat(0, nb, split_tile_blocks, &fcomb);
+  make_flat(0, nb, rs_blocks, &frs);
   make_flat(0, nb, vel_gather, &fvel[0]);
   make_flat(0, nb, vel_tiles, &fvel[1]);
   MultiPass mp1a[3], mp2a[3], mp2b[3];
@@ -811,8 +813,10 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto fixf = [&](FlatMap *fm, int k) {
     for (int i = 0; i < k; ++i) fm[i].e = reinterpret_cast<const FlatEntry *>(base + (size_t)fm[i].e);
   };
-  if (na > 0) fixf(fsa, 6);
-  if (nbb > 0) fixf(fsb, 6);
+  if (na > 0) fixf(fsa, 4);
+  if (nbb > 0) fixf(fsb, 4);
+  fixf(&fcomb, 1);
+  fixf(&frs, 1);
   fixf(fvel, 2);
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
@@ -821,6 +825,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   // R_v
   if (na > 0) GPF_HIP(launch_scatter_vortices<float>(dpd, na, ca.n_max, ca.nv_max, s, fsa));
   if (nbb > 0) GPF_HIP(launch_scatter_vortices<double>(dpd + na, nbb, cbi.n_max, cbi.nv_max, s, fsb));
+  GPF_HIP(launch_split_combine(dpd, nb, 0, s, &fcomb));
   // first convolution (surface band only)
   if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc1, mp1a, s)));
   for (int i = na; i < nb;) {
@@ -839,8 +844,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   if (nbb > 0) GPF_HIP(launch_surface_rhs<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
   if (na > 0) GPF_HIP(launch_schur_apply<float>(dpd, na, ca.ns_max, ca.m_max, s));
   if (nbb > 0) GPF_HIP(launch_schur_apply<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
-  if (na > 0) GPF_HIP(launch_rs_apply<float>(dpd, na, 0, s, &fsa[5]));
-  if (nbb > 0) GPF_HIP(launch_rs_apply<double>(dpd + na, nbb, 0, s, &fsb[5]));
+  GPF_HIP(launch_rs_apply(dpd, nb, 0, s, &frs));
   // final convolution of all vorticity
   if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc2, mp2a, s)));
   if (nbb > 0) GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, s)));
@@ -1543,6 +1547,7 @@ gpf_status gpf_regularize_vortices(gpf_plan *plan, int nv, const double *d_xv, c
   pd.gv = d_gv;
   pd.w = d_w;
   pd.w_accumulate = accumulate ? 1 : 0;
+  pd.w64 = plan->fp64 ? 1 : 0;
   pd.aux = plan->ws.aux.as<double>();
   pd.partials = plan->ws.part.as<double>();
   pd.bin_cnt = plan->ws.bin_cnt.as<int>();

@@ -212,6 +212,7 @@ struct ProbDesc {
   // fields
   void *w;                      // source field (zero on entry, or the values R_v adds to)
   int w_accumulate;             // 1: w holds values R_v adds to; 0: w is zero on entry
+  int w64;                      // 1: the source field w is FP64, 0: FP32
   int halo_defer;               // 1: the solve's convolutions add the tiles' halos as
                                 // they read w (no halo pass); 0: the halo pass adds them
   int vel_tiles;                // 1: velocities tile by tile through LDS (dense clouds)
@@ -373,8 +374,9 @@ __device__ __forceinline__ bool flat_block(const FlatMap &fm, FlatBlock *fb) {
 // halos as they read the field.
 // fm (merged batches): fm[0] the count's map, fm[1] the tile kernel's,
 // fm[2] the halo kernel's, fm[3] the place kernel's (one block per 256
-// vortices), fm[4] the split-tile kernel's; nullptr: a 2-D grid of nb
-// problems, with the halo pass when `halo_pass` is set
+// vortices), fm[4] the split-tile kernel's (total 0: the caller launches it
+// with launch_split_combine); nullptr: a 2-D grid of nb problems, with the
+// halo pass when `halo_pass` is set
 template <class T>
 hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max, hipStream_t s,
                                    const FlatMap *fm = nullptr, bool halo_pass = true);
@@ -425,11 +427,16 @@ hipError_t launch_schur_gemm(const ProbDesc *d, int nb, int ns, int m_max, const
 template <class T>
 hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipStream_t s);
 // R_s f and the new vortices' stencils added to the source field after the
-// surface step, node by node in a fixed order; `blocks` per problem (the
-// most of rs_apply_blocks over the launch), or the flat map fm
-template <class T>
+// surface step, node by node in a fixed order (FP32 and FP64 fields in one
+// launch, by each problem's w64); `blocks` per problem (the most of
+// rs_apply_blocks over the launch), or the flat map fm
 hipError_t launch_rs_apply(const ProbDesc *d, int nb, int blocks, hipStream_t s,
                            const FlatMap *fm = nullptr);
+// the split tiles' windows summed into the field after R_v's tile kernel,
+// for FP32 and FP64 fields in one launch; `blocks` per problem
+// (split_blocks of the most vortices), or the flat map fm
+hipError_t launch_split_combine(const ProbDesc *d, int nb, int blocks, hipStream_t s,
+                                const FlatMap *fm = nullptr);
 inline int rs_apply_blocks(int rs_nodes, int m) { return (rs_nodes + 255) / 256 + (m > 0 ? 1 : 0); }
 template <class T>
 hipError_t launch_vortex_velocity(const ProbDesc *d, int nb, int nv_max, hipStream_t s);

@@ -1000,10 +1000,7 @@ __device__ __forceinline__ double new_vortex_weights(const ProbDesc &P, int m, i
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_rs_apply(const ProbDesc *__restrict__ d, FlatMap fm) {
-  FlatBlock fb;
-  if (!flat_block(fm, &fb)) return;
-  const ProbDesc &P = d[fb.prob];
+__device__ __forceinline__ void rs_apply_body(const ProbDesc &P, const FlatBlock &fb) {
   const int K = P.rs_nodes, n = P.n, m = P.sv.m;
   const int kb = (K + 255) / 256;
   T *w = static_cast<T *>(P.w);
@@ -1044,6 +1041,16 @@ __global__ __launch_bounds__(256) void k_rs_apply(const ProbDesc *__restrict__ d
     }
     w[node] = (T)((double)w[node] + new_vortex_weights(P, m, ix, iy) * inv_dx2);
   }
+}
+
+__global__ __launch_bounds__(256) void k_rs_apply(const ProbDesc *__restrict__ d, FlatMap fm) {
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  if (P.w64)
+    rs_apply_body<double>(P, fb);
+  else
+    rs_apply_body<float>(P, fb);
 }
 
 
@@ -1446,14 +1453,11 @@ hipError_t launch_schur_apply_parts(const ProbDesc *d, int nb, int ns_max, hipSt
 template hipError_t launch_schur_apply_parts<float>(const ProbDesc *, int, int, hipStream_t);
 template hipError_t launch_schur_apply_parts<double>(const ProbDesc *, int, int, hipStream_t);
 
-template <class T>
 hipError_t launch_rs_apply(const ProbDesc *d, int nb, int blocks, hipStream_t s, const FlatMap *fm) {
   if (fm ? fm->total <= 0 : blocks <= 0) return hipSuccess;
   const dim3 grid = fm ? dim3(fm->total) : dim3(blocks, nb);
-  hipLaunchKernelGGL((k_rs_apply<T>), grid, dim3(256), 0, s, d, fm ? *fm : FlatMap{nullptr, 0, 0});
+  hipLaunchKernelGGL(k_rs_apply, grid, dim3(256), 0, s, d, fm ? *fm : FlatMap{nullptr, 0, 0});
   return hipGetLastError();
 }
-template hipError_t launch_rs_apply<float>(const ProbDesc *, int, int, hipStream_t, const FlatMap *);
-template hipError_t launch_rs_apply<double>(const ProbDesc *, int, int, hipStream_t, const FlatMap *);
 
 }  // namespace gpf

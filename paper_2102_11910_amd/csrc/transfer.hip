@@ -524,11 +524,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
 //     items' windows summed in integers (exact, so neither the order nor
 //     the split changes a bit), stored as a lone item's window would be
 template <class T>
-__global__ __launch_bounds__(kTileBlock) void k_split_combine(const ProbDesc *__restrict__ d, FlatMap fm) {
-  FlatBlock fb;
-  if (!flat_block(fm, &fb)) return;
-  const ProbDesc &P = d[fb.prob];
-  if (P.nv <= 0) return;
+__device__ __forceinline__ void split_combine_body(const ProbDesc &P, const FlatBlock &fb) {
   const int nsplit = P.splits[0];
   const int n = P.n, ts = tile_cells(n), tps = n / ts;
   const double inv = ldexp(1.0, (int)P.aux[SC_RV_SCALE] - FixedPoint<T>::B);
@@ -553,6 +549,17 @@ __global__ __launch_bounds__(kTileBlock) void k_split_combine(const ProbDesc *__
     store_tile_window<T, true>(P, t, ts, tps, X0, Y0, inv, [&](int u, int) { return acc[u]; });
     if (threadIdx.x == 0) P.bin_cnt[t] = 0;
   }
+}
+
+__global__ __launch_bounds__(kTileBlock) void k_split_combine(const ProbDesc *__restrict__ d, FlatMap fm) {
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  if (P.nv <= 0) return;
+  if (P.w64)
+    split_combine_body<double>(P, fb);
+  else
+    split_combine_body<float>(P, fb);
 }
 
 // 5.: kFixupTiles tiles per workgroup, a few border nodes per thread; every
@@ -974,10 +981,10 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
                      dim3(kTileBlock), 0, s, d, mt);
   // tiles of several items: their windows summed after the tile kernel
-  const FlatMap ms = fm ? fm[4] : none;
-  if (fm ? ms.total > 0 : split_blocks(nv_max) > 0)
-    hipLaunchKernelGGL((k_split_combine<T>), grid_of(fm ? &ms : nullptr, split_blocks(nv_max), nb),
-                       dim3(kTileBlock), 0, s, d, ms);
+  if (fm ? fm[4].total > 0 : split_blocks(nv_max) > 0) {
+    const hipError_t e = launch_split_combine(d, nb, split_blocks(nv_max), s, fm ? &fm[4] : nullptr);
+    if (e != hipSuccess) return e;
+  }
   if (fm ? mh.total > 0 : (halo_pass && nv_max > 0 && halo_tiles(n) > 0))
     hipLaunchKernelGGL((k_halo_fixup<T>), grid_of(fm ? &mh : nullptr, fixup_blocks(n), nb), dim3(kFixupBlock),
                        0, s, d, mh);
@@ -988,6 +995,13 @@ template hipError_t launch_scatter_vortices<float>(const ProbDesc *, int, int, i
                                                    const FlatMap *, bool);
 template hipError_t launch_scatter_vortices<double>(const ProbDesc *, int, int, int, hipStream_t,
                                                     const FlatMap *, bool);
+
+hipError_t launch_split_combine(const ProbDesc *d, int nb, int blocks, hipStream_t s, const FlatMap *fm) {
+  if (fm ? fm->total <= 0 : blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_combine, grid_of(fm, blocks, nb), dim3(kTileBlock), 0, s, d,
+                     fm ? *fm : FlatMap{nullptr, 0, 0});
+  return hipGetLastError();
+}
 
 hipError_t launch_surface_stencils(int n, double dx, double x0, double y0, int ns,
                                    const double *xs, const double *ys, int *st_i, double *st_w,
