@@ -107,14 +107,15 @@ def kept_rows(case) -> float:
 
 # kernel class -> (source file, kernel-name prefixes in a profiler trace)
 KERNEL_SOURCES = {
-    "scatter": ("transfer.hip", ("k_bin_count", "k_bin_scan", "k_bin_place", "k_tile_scatter", "k_halo_fixup")),
+    "scatter": ("transfer.hip", ("k_bin_count", "k_bin_scan", "k_bin_place", "k_tile_scatter", "k_split_combine",
+                                 "k_halo_fixup")),
     "rows_fwd": ("fft_conv.hip", ("k_rows_fwd_multi",)),
     "cols": ("fft_conv.hip", ("k_cols_multi<float",)),
     "rows_inv": ("fft_conv.hip", ("k_rows_inv_multi<float",)),
     "rows_fwd64": ("fft_conv.hip", ("k_rows_fwd<double, double",)),
     "cols64": ("fft_conv.hip", ("k_cols_conv<double", "k_cols_conv_split<double")),
     "rows_inv64": ("fft_conv.hip", ("k_rows_inv<double",)),
-    "surface": ("schur.hip", ("k_surface_rhs", "k_schur_apply")),
+    "surface": ("schur.hip", ("k_surface_rhs", "k_schur_apply", "k_rs_apply")),
     "velocity": ("transfer.hip", ("k_vortex_velocity", "k_tile_velocity")),
 }
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "c4_batch64_hbm_traffic.md")

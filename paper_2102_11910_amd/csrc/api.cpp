@@ -594,7 +594,9 @@ gpf_status launch_group(const GroupCfg &cfg, int nb, const ProbDesc *pd, const C
       if (shared) GPF_HIP(launch_schur_gemm(pd, nb, ns_max, m_max, shared_sinv, s));
       GPF_HIP(launch_schur_apply<TW>(pd, nb, ns_max, m_max, s));
     }
+    timer_begin(GPF_TK_SURFACE, s);
     GPF_HIP(launch_rs_apply(pd, nb, rs_blocks, s));
+    timer_end(s);
     GPF_HIP((launch_convolve<TW, T2>(cfg.n, c2, nb, xcds, 0, s, sc2, fband2)));
   }
   GPF_HIP(launch_solve_velocity<T2>(pd, nb, cfg.n, nv_max, s, nullptr, vel_kinds));
@@ -825,7 +827,9 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   // R_v
   if (na > 0) GPF_HIP(launch_scatter_vortices<float>(dpd, na, ca.n_max, ca.nv_max, s, fsa));
   if (nbb > 0) GPF_HIP(launch_scatter_vortices<double>(dpd + na, nbb, cbi.n_max, cbi.nv_max, s, fsb));
+  timer_begin(GPF_TK_SCATTER, s);
   GPF_HIP(launch_split_combine(dpd, nb, 0, s, &fcomb));
+  timer_end(s);
   // first convolution (surface band only)
   if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc1, mp1a, s)));
   for (int i = na; i < nb;) {
@@ -844,7 +848,9 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   if (nbb > 0) GPF_HIP(launch_surface_rhs<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
   if (na > 0) GPF_HIP(launch_schur_apply<float>(dpd, na, ca.ns_max, ca.m_max, s));
   if (nbb > 0) GPF_HIP(launch_schur_apply<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
+  timer_begin(GPF_TK_SURFACE, s);
   GPF_HIP(launch_rs_apply(dpd, nb, 0, s, &frs));
+  timer_end(s);
   // final convolution of all vorticity
   if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc2, mp2a, s)));
   if (nbb > 0) GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, s)));
