@@ -30,11 +30,14 @@ size_t plan_bytes(int n) {
   return 20 * c + 44 * (size_t)n * n + (1u << 20);
 }
 
-// Device bytes of one problem workspace (source fields and half spectra of
-// both precisions, vortex binning, Schur right-hand sides), rounded up.
+// Device bytes of one problem workspace, rounded up: per cell the source
+// fields and half spectra of both precisions and the tiles' halo slots
+// (46 B); per vortex the rank and the 32-byte record (36 B) and the window
+// slots of split tiles (at most 2 / 512 of a 9800-byte window: 39 B); per
+// surface point the Schur right-hand sides, products and f (80 B).
 size_t slot_bytes(int n, int nv, int ns) {
   const size_t cap = nv > 1024 ? (size_t)nv : 1024;
-  return 44 * (size_t)(n + 1) * n + 28 * cap + 72 * (size_t)ns + (1u << 20);
+  return 46 * (size_t)(n + 1) * n + 75 * cap + 80 * (size_t)ns + (1u << 20);
 }
 
 constexpr int kServerSets = 3;
