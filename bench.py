@@ -107,7 +107,7 @@ def kept_rows(case) -> float:
 
 # kernel class -> (source file, kernel-name prefixes in a profiler trace)
 KERNEL_SOURCES = {
-    "scatter": ("transfer.hip", ("k_bin_count", "k_bin_scan", "k_bin_place", "k_tile_scatter", "k_split_combine",
+    "scatter": ("transfer.hip", ("k_bin_count", "k_bin_place", "k_tile_scatter", "k_split_combine",
                                  "k_halo_fixup")),
     "rows_fwd": ("fft_conv.hip", ("k_rows_fwd_multi",)),
     "cols": ("fft_conv.hip", ("k_cols_multi<float",)),

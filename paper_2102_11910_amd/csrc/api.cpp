@@ -760,7 +760,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     fused += hi - lo;
   };
   auto bin_blocks = [&](int i) { return pd[i].nv > 0 ? bin_count_blocks(pd[i].nv) : 1; };
-  auto place_blocks = [&](int i) { return std::max(1, (pd[i].nv + 255) / 256); };
+  auto place_map_blocks = [&](int i) { return place_blocks(pd[i].nv); };
   auto split_tile_blocks = [&](int i) { return pd[i].nv > 0 ? split_blocks(pd[i].nv) : 0; };
   auto rs_blocks = [&](int i) { return rs_apply_blocks(pd[i].rs_nodes, pd[i].sv.m); };
   auto tile_blocks = [&](int i) { return tile_items_max(pd[i].n, pd[i].nv); };
@@ -775,13 +775,13 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     make_flat(0, na, bin_blocks, &fsa[0]);
     make_flat(0, na, tile_blocks, &fsa[1]);
     make_flat(0, na, halo_blocks, &fsa[2]);
-    make_flat(0, na, place_blocks, &fsa[3]);
+    make_flat(0, na, place_map_blocks, &fsa[3]);
   }
   if (nbb > 0) {
     make_flat(na, nb, bin_blocks, &fsb[0]);
     make_flat(na, nb, tile_blocks, &fsb[1]);
     make_flat(na, nb, halo_blocks, &fsb[2]);
-    make_flat(na, nb, place_blocks, &fsb[3]);
+    make_flat(na, nb, place_map_blocks, &fsb[3]);
   }
   make_flat(0, nb, split_tile_blocks, &fcomb);
   make_flat(0, nb, rs_blocks, &frs);

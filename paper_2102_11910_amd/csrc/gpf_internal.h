@@ -269,6 +269,7 @@ struct ProbDesc {
 // kernel launchers (asynchronous on `s`; `nb` problems, same n)
 // ---------------------------------------------------------------------------
 int scatter_blocks(int nv_max);
+int place_blocks(int nv);   // workgroups of the binning place kernel of one problem
 // binning partials per workgroup of vortices, five planes of kPartStride:
 // sum Gamma, sum Gamma x, sum Gamma y, sum Gamma (x^2 + y^2), sum |Gamma|
 constexpr int kMaxVortices = 1 << 22;

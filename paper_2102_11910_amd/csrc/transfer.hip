@@ -174,15 +174,27 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
   }
 }
 
-// 2. one workgroup per problem: tile starts (exclusive scan of the counts),
-//    the work list of the tile kernels, the circulation and sum |Gamma|
-//    (partials summed in a fixed order, so every solve gives the same bits)
-//    and the fixed-point scale.
-template <class T>
-__global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__restrict__ d) {
+// 2. tile starts, work list, scalars and the records, in one kernel: every
+//    workgroup of a problem scans the tile counts (at most kMaxTiles) in
+//    LDS for the starts its vortices need; workgroup 0 also writes the
+//    starts, the work list of the tile kernels, the circulation and sum
+//    |Gamma| (partials summed in a fixed order, so every solve gives the
+//    same bits) and the fixed-point scale.  Each vortex goes to slot
+//    start + rank of the tile-sorted list as (xi, eta, Gamma / dx^2, q):
+//    32 bytes, the vortex's own index last (the tile velocity kernel writes
+//    its result there).  A vortex outside the window (already reported)
+//    gets no record and NaN velocities.
+constexpr int kPlacePer = 4;                               // vortices per thread
+constexpr int kPlaceBlock = kPlacePer * kScatterBlock;     // vortices per workgroup
+__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d, FlatMap fm) {
+  __shared__ int start_s[kMaxTiles];
   __shared__ int wsum[kScatterBlock / 64], wsum2[kScatterBlock / 64];
   __shared__ double gsum[2][kScatterBlock / 64];
-  const ProbDesc &P = d[blockIdx.x];
+  FlatBlock fb;
+  if (!flat_block(fm, &fb)) return;
+  const ProbDesc &P = d[fb.prob];
+  const bool lead = fb.blk == 0;
+  if (!lead && fb.blk * kPlaceBlock >= P.nv) return;   // no vortex of its own to place
   const int n = P.n, ts = tile_cells(n), tps = n / ts, ntiles = tps * tps;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int kPer = kMaxTiles / kScatterBlock;
@@ -204,7 +216,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
   // circulation and sum |Gamma| over the bin_count partials, strided per
   // thread, then waves, in a fixed order
   double g = 0.0, ga = 0.0;
-  const int nvb = P.nv > 0 ? bin_count_blocks(P.nv) : 0;   // workgroups of bin_count
+  const int nvb = lead && P.nv > 0 ? bin_count_blocks(P.nv) : 0;   // workgroups of bin_count
   for (int b = tid; b < nvb; b += kScatterBlock) {
     g += P.partials[b];
     ga += P.partials[4 * (size_t)kPartStride + b];
@@ -229,11 +241,12 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     if (k < per && lo + k < ntiles) {
-      P.bin_start[lo + k] = pos;
+      start_s[lo + k] = pos;
+      if (lead) P.bin_start[lo + k] = pos;
       pos += cnts[k];
     }
   }
-  {
+  if (lead) {
     // work list of the tile kernels, in tile order: a tile of c records
     // gives ceil(c / kTileChunk) items of consecutive records, an empty tile
     // one empty item (which clears the tile's halo slot).  A tile of
@@ -293,70 +306,81 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_scan(const ProbDesc *__re
       }
       r += c;
     }
-    if (tid == 0) *reinterpret_cast<int4 *>(P.splits) = make_int4(tot_sp & 0xffff, 0, 0, 0);
-    if (tid == 0) *reinterpret_cast<int4 *>(P.items) = make_int4(tot_items, 0, 0, 0);
-  }
-  if (tid == 0) {
-    P.bin_start[ntiles] = total;
-    double gw = 0.0, gabs = 0.0;
-    for (int w = 0; w < kScatterBlock / 64; ++w) {
-      gw += gsum[0][w];
-      gabs += gsum[1][w];
-    }
-    P.aux[SC_GAMMA_W] = gw;
-    if (P.sc_out) P.sc_out[SC_GAMMA_W] = gw;
-    // no node sum exceeds sum |Gamma| / dx^2 (each 1-D weight is at most 1
-    // in magnitude); the sums are scaled to below 2^B (FixedPoint<T>)
-    const double smax = gabs / (P.dx * P.dx);
-    int e = 0;
-    if (smax > 0.0) {
-      frexp(smax, &e);   // smax < 2^e
-    }
-    P.aux[SC_RV_SCALE] = (double)e;   // sum |Gamma| / dx^2 < 2^e
-  }
-}
-
-// 3. write each vortex to slot start + rank of the tile-sorted list as
-//    (xi, eta, Gamma / dx^2, q): 32 bytes, the vortex's own index last (the
-//    tile velocity kernel writes its result there).  A vortex outside the
-//    window (already reported) gets no record and NaN velocities.
-__global__ __launch_bounds__(kScatterBlock) void k_bin_place(const ProbDesc *__restrict__ d, FlatMap fm) {
-  FlatBlock fb;
-  if (!flat_block(fm, &fb)) return;
-  const ProbDesc &P = d[fb.prob];
-  const int n = P.n, ts = tile_cells(n), tps = n / ts;
-  for (int q = fb.blk * kScatterBlock + threadIdx.x; q < P.nv; q += fb.nblk * kScatterBlock) {
-    const int r = P.rank[q];
-    if (r < 0) {
-      if (P.u) {
-        P.u[q] = NAN;
-        P.v[q] = NAN;
+    if (tid == 0) {
+      *reinterpret_cast<int4 *>(P.splits) = make_int4(tot_sp & 0xffff, 0, 0, 0);
+      *reinterpret_cast<int4 *>(P.items) = make_int4(tot_items, 0, 0, 0);
+      P.bin_start[ntiles] = total;
+      double gw = 0.0, gabs = 0.0;
+      for (int w = 0; w < kScatterBlock / 64; ++w) {
+        gw += gsum[0][w];
+        gabs += gsum[1][w];
       }
-      continue;
+      P.aux[SC_GAMMA_W] = gw;
+      if (P.sc_out) P.sc_out[SC_GAMMA_W] = gw;
+      // no node sum exceeds sum |Gamma| / dx^2 (each 1-D weight is at most 1
+      // in magnitude); the sums are scaled to below 2^B (FixedPoint<T>)
+      const double smax = gabs / (P.dx * P.dx);
+      int e = 0;
+      if (smax > 0.0) {
+        frexp(smax, &e);   // smax < 2^e
+      }
+      P.aux[SC_RV_SCALE] = (double)e;   // sum |Gamma| / dx^2 < 2^e
     }
-    const double xi = (P.xv[q] - P.x0) / P.dx, eta = (P.yv[q] - P.y0) / P.dx;
-    const int t = vortex_tile((int)floor(xi) - 1, (int)floor(eta) - 1, ts, tps);
-    double4 o;
-    o.x = xi;
-    o.y = eta;
-    o.z = P.gv[q] / (P.dx * P.dx);
-    o.w = (double)q;
-    *reinterpret_cast<double4 *>(P.sorted + 4 * (size_t)(P.bin_start[t] + r)) = o;
+  }
+  __syncthreads();   // start_s is complete
+  // kPlacePer vortices per thread, all loads issued first
+  const int *__restrict__ rank = P.rank;
+  const double *__restrict__ xv = P.xv;
+  const double *__restrict__ yv = P.yv;
+  const double *__restrict__ gv = P.gv;
+  double *__restrict__ sorted = P.sorted;
+  const double inv_dx2 = 1.0 / (P.dx * P.dx);
+  for (int q0 = fb.blk * kPlaceBlock + tid; q0 < P.nv; q0 += fb.nblk * kPlaceBlock) {
+    int rk[kPlacePer];
+    double x[kPlacePer], y[kPlacePer], gq[kPlacePer];
+#pragma unroll
+    for (int u = 0; u < kPlacePer; ++u) {
+      const int q = min(q0 + u * kScatterBlock, P.nv - 1);
+      rk[u] = rank[q];
+      x[u] = xv[q];
+      y[u] = yv[q];
+      gq[u] = gv[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kPlacePer; ++u) {
+      const int q = q0 + u * kScatterBlock;
+      if (q >= P.nv) break;
+      if (rk[u] < 0) {
+        if (P.u) {
+          P.u[q] = NAN;
+          P.v[q] = NAN;
+        }
+        continue;
+      }
+      const double xi = (x[u] - P.x0) / P.dx, eta = (y[u] - P.y0) / P.dx;
+      const int t = vortex_tile((int)floor(xi) - 1, (int)floor(eta) - 1, ts, tps);
+      double4 o;
+      o.x = xi;
+      o.y = eta;
+      o.z = gq[u] * inv_dx2;
+      o.w = (double)q;
+      *reinterpret_cast<double4 *>(sorted + 4 * (size_t)(start_s[t] + rk[u])) = o;
+    }
   }
 }
 
-// 4. one workgroup per item of the work list (a tile, or a part of a dense
+// 3. one workgroup per item of the work list (a tile, or a part of a dense
 //    tile's records): the item's vortices add their 4 x 4 stencils to an
 //    LDS window of (ts+3)^2 nodes (nodes X0-1 .. X0+ts+1) in 64-bit fixed
 //    point, so the window's sums do not depend on the order of the
 //    additions.  The tile's own ts^2 nodes (window-local 1 .. ts) are then
 //    stored into the field (zero, or the values to add to); the other
 //    6 ts + 9 window nodes belong to neighbouring tiles and are stored in
-//    the tile's halo slot, which the convolutions (or step 5) add to their
+//    the tile's halo slot, which the convolutions (or step 4) add to their
 //    owners.  A dense tile's workgroup takes its records kTileChunk at a
 //    time into the same window: no global atomic, and the field is the same
 //    bits on every run.  The tile's count is cleared for the next solve.
-// 5. one workgroup per tile whose neighbours' windows can reach it: each of
+// 4. one workgroup per tile whose neighbours' windows can reach it: each of
 //    its 6 ts - 9 border nodes (local 0, 1 or ts-1 on an axis) adds, in a
 //    fixed order, the halo values of the non-empty neighbours that reach it.
 constexpr int kTileBlock = 128;
@@ -520,7 +544,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_scatter(const ProbDesc *__r
     tile_scatter_body<T, 0>(P, fb, win);
 }
 
-// 4b. one workgroup per tile of several items (after the tile kernel): the
+// 3b. one workgroup per tile of several items (after the tile kernel): the
 //     items' windows summed in integers (exact, so neither the order nor
 //     the split changes a bit), stored as a lone item's window would be
 template <class T>
@@ -562,7 +586,7 @@ __global__ __launch_bounds__(kTileBlock) void k_split_combine(const ProbDesc *__
     split_combine_body<float>(P, fb);
 }
 
-// 5.: kFixupTiles tiles per workgroup, a few border nodes per thread; every
+// 4.: kFixupTiles tiles per workgroup, a few border nodes per thread; every
 // load a node needs (the neighbours' tile counts, their halo entries, the
 // node) is issued before any is used, and a neighbour without vortices
 // (whose halo slot holds nothing of this solve) is dropped by a select.
@@ -936,6 +960,8 @@ hipError_t launch_axpy2(int nv, const double *x, const double *y, const double *
 
 int scatter_blocks(int nv_max) { return nv_max > 0 ? (nv_max + kScatterBlock - 1) / kScatterBlock : 1; }
 
+int place_blocks(int nv) { return nv > 0 ? (nv + kPlaceBlock - 1) / kPlaceBlock : 1; }
+
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
   int blocks = (int)std::min<size_t>((words + 255) / 256, 4096);
@@ -973,9 +999,8 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   const FlatMap mp = fm ? fm[3] : none;
   // the count's workgroups take up to 4096 vortices (bin_per_thread); the
   // place kernel one per thread
-  const int cb = nv_max > 0 ? bin_count_blocks(nv_max) : 1, vb = scatter_blocks(nv_max);
+  const int cb = nv_max > 0 ? bin_count_blocks(nv_max) : 1, vb = place_blocks(nv_max);
   hipLaunchKernelGGL(k_bin_count, grid_of(fm ? &mb : nullptr, cb, nb), dim3(kScatterBlock), 0, s, d, mb);
-  hipLaunchKernelGGL((k_bin_scan<T>), dim3(nb), dim3(kScatterBlock), 0, s, d);
   hipLaunchKernelGGL(k_bin_place, grid_of(fm ? &mp : nullptr, vb, nb), dim3(kScatterBlock), 0, s, d, mp);
   // one workgroup per item of the work list, then one per tile for the halos
   hipLaunchKernelGGL((k_tile_scatter<T>), grid_of(fm ? &mt : nullptr, tile_items_max(n, nv_max), nb),
