@@ -457,6 +457,40 @@ __device__ __forceinline__ void store_tile_window(const ProbDesc &P, int t, int 
   }
 }
 
+// store_tile_window for 32-cell tiles and a window in LDS: the own nodes by
+// rows of 32 (one line of the field each), then the halo ring decoded in
+// its own order (window row 0, rows 33 and 34, then columns 0, 33 and 34
+// of rows 1 .. 32), without a division by the window width per entry
+template <class T>
+__device__ __forceinline__ void store_window32(const ProbDesc &P, int t, int X0, int Y0, double inv,
+                                               const long long *win) {
+  constexpr int bw = 32 + 3;
+  const int n = P.n;
+  T *w = static_cast<T *>(P.w);
+  T *hal = static_cast<T *>(P.halo) + (size_t)t * kHaloRing;
+  for (int e = threadIdx.x; e < 32 * 32; e += kTileBlock) {
+    const int r = e >> 5, c = e & 31;
+    const long long v = win[(r + 1) * bw + c + 1];
+    if (v == 0) continue;
+    const T val = (T)((double)v * inv);
+    T *node = w + (size_t)(Y0 + 1 + r) * n + X0 + 1 + c;
+    *node = P.w_accumulate ? *node + val : val;
+  }
+  for (int h = threadIdx.x; h < kHaloRing; h += kTileBlock) {
+    int kx, ky;
+    if (h < 3 * bw) {
+      const int row = h / bw;   // 0, 1, 2: window rows 0, 33, 34
+      ky = row == 0 ? 0 : 32 + row;
+      kx = h - row * bw;
+    } else {
+      const int q = h - 3 * bw, c = q % 3;
+      ky = 1 + q / 3;
+      kx = c == 0 ? 0 : 32 + c;
+    }
+    hal[h] = (T)((double)win[ky * bw + kx] * inv);
+  }
+}
+
 // TS: the tile size when it is known at compile time (32, every grid of
 // n >= 32), 0 otherwise: the window loops then divide by constants
 template <class T, int TS>
@@ -521,7 +555,10 @@ __device__ __forceinline__ void tile_scatter_body(const ProbDesc &P, const FlatB
     lds_barrier();
     if (it.w == 0) {
       if (tid == 0) P.bin_cnt[t] = 0;
-      store_tile_window<T, false>(P, t, ts, tps, X0, Y0, inv, [&](int, int k) { return win[k]; });
+      if constexpr (TS == 32)
+        store_window32<T>(P, t, X0, Y0, inv, win);
+      else
+        store_tile_window<T, false>(P, t, ts, tps, X0, Y0, inv, [&](int, int k) { return win[k]; });
     } else {
       // an item of a split tile: its window goes to its own slot, and
       // k_split_combine stores the tile's sum after this launch
