@@ -24,12 +24,34 @@ def test_version_and_error_strings():
 
 
 def test_host_lgf_table_matches_oracle():
+    """The library's table comes from the heat-kernel (Bessel) integral, the
+    oracle's from the Fourier integral over one angle: two routes to the same
+    function, which must agree."""
     from oracle.lgf import lgf_table
-    n = 160                      # crosses the quadrature / far-field switch at r = 128
+    n = 160                      # crosses the near-field / far-field switch at r = 128
     T = gpf.lgf_table(n)
     To = lgf_table(n)
     assert np.max(np.abs(T - To)) <= 1e-13
     assert T[0, 0] == 0.0 and abs(T[1, 0] - 0.25) < 1e-15
+
+
+def test_host_lgf_table_closed_values_and_laplacian():
+    """The library's table pinned without the oracle: known closed values of
+    the square-lattice Green's function of the 5-point Laplacian (gauge
+    G(0,0) = 0), and Delta_h G = delta on the near-field region."""
+    T = gpf.lgf_table(160)
+    pi = np.pi
+    closed = {(1, 0): 0.25, (1, 1): 1 / pi, (2, 0): 1 - 2 / pi, (2, 1): 2 / pi - 0.25,
+              (2, 2): 4 / (3 * pi), (3, 0): 17 / 4 - 12 / pi, (3, 3): 23 / (15 * pi)}
+    for (a, b), v in closed.items():
+        assert abs(T[a, b] - v) < 5e-15, (a, b, T[a, b], v)
+        assert T[a, b] == T[b, a]
+    # 5-point Laplacian on the even extension: rows/columns -1 mirror 1
+    E = np.pad(T[:126, :126], ((1, 0), (1, 0)), mode="reflect")
+    lap = E[2:, 1:-1] + E[:-2, 1:-1] + E[1:-1, 2:] + E[1:-1, :-2] - 4 * E[1:-1, 1:-1]
+    delta = np.zeros_like(lap)
+    delta[0, 0] = 1.0
+    assert np.max(np.abs(lap - delta)) < 1e-13
 
 
 def test_null_arguments_rejected_without_device():
