@@ -638,6 +638,14 @@ struct gpf_batch {
   // batches of several grid sizes run merged (one launch per stage over all
   // sizes) unless this is cleared
   int merge = 1;
+  // sizes every workspace of a call is kept at: the largest grid, vortex
+  // count, surface and band the batch has held, and whether FP32 / FP64
+  // fields were needed.  A slot grown only to the problem in hand grows
+  // again, and hipFree then waits for the whole device, each time a larger
+  // problem than it has held lands on it.  The request server raises them
+  // to its own high-water marks before each batch.
+  int hw_n = 0, hw_nv = 0, hw_ns = 0, hw_band = 0;
+  bool hw_w32 = false, hw_w64 = false;
   hipStream_t lane_stream[kMaxLanes] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
   ~gpf_batch();

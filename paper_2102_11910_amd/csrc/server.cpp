@@ -118,6 +118,15 @@ void gpf_server::retire(int k) {
 // that one bad request fails alone.
 gpf_status gpf_server::dispatch(int k, std::vector<Req> &rs) {
   const int m = (int)rs.size();
+  {
+    // the set's workspaces go straight to the admitted high-water sizes
+    // (what admission budgets for every slot), so that they grow, and
+    // synchronise the device, rarely instead of with each new largest request
+    std::lock_guard<std::mutex> lk(plan_mu);
+    batch[k]->hw_n = std::max(batch[k]->hw_n, n_hw);
+    batch[k]->hw_nv = std::max(batch[k]->hw_nv, nv_hw);
+    batch[k]->hw_ns = std::max(batch[k]->hw_ns, ns_hw);
+  }
   std::vector<gpf_plan *> pl(m);
   std::vector<const gpf_body *> bo(m);
   std::vector<gpf_inputs> in(m);
