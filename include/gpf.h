@@ -331,8 +331,14 @@ gpf_status gpf_batch_set_lanes(gpf_batch *batch, int lanes);
 int gpf_batch_get_lanes(const gpf_batch *batch);
 
 /* merge = 1 (the default) lets gpf_solve_batched run a batch of several
- * grid sizes merged (see below); 0 makes it run such a batch group by group
- * on its lanes, the path the merged one is compared with. */
+ * grid sizes merged (see below), with the problems whose first convolution
+ * is FP64 solved up to their Schur step on a side stream of the batch
+ * (forked from and joined to the caller's stream with events), beside the
+ * FP32 ones; 2 runs merged batches on the caller's stream alone (the same
+ * kernels, none concurrent: what per-kernel timing measures); 0 makes it
+ * run such a batch group by group on its lanes, the path the merged one is
+ * compared with.  Results are the same bits for every value.  GPF_E_INVALID
+ * for a value outside 0..2. */
 gpf_status gpf_batch_set_merge(gpf_batch *batch, int merge);
 
 /* Solve nprob independent problems (each as in gpf_solve; bodies may be
@@ -350,8 +356,9 @@ gpf_status gpf_batch_set_merge(gpf_batch *batch, int merge);
  * Problem i uses workspace i of the batch; plans and bodies may repeat.
  * Every problem needs its own output buffers and status word (a status word
  * may be shared).  Asynchronous on hip_stream; the batch serves one stream
- * at a time.  Results equal those of solving each problem alone up to the
- * order of floating-point atomic additions. */
+ * at a time.  No step adds with floating-point atomics: every call gives
+ * the same bits, and results equal those of solving each problem alone up
+ * to rounding (merged launches shape the transforms differently). */
 gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans,
                              const gpf_body *const *bodies, const gpf_inputs *inputs,
                              const gpf_outputs *outputs, void *hip_stream);

@@ -331,6 +331,9 @@ gpf_batch::~gpf_batch() {
     if (join_ev[l]) (void)hipEventDestroy(join_ev[l]);
   }
   if (fork_ev) (void)hipEventDestroy(fork_ev);
+  if (side) (void)hipStreamDestroy(side);
+  if (side_fork) (void)hipEventDestroy(side_fork);
+  if (side_join) (void)hipEventDestroy(side_join);
   for (auto *w : ws) delete w;
 }
 
@@ -683,7 +686,10 @@ size_t merged_block_bytes(int nb) {
 // convolution).  The transforms of FP32 fields are the multi-size passes,
 // whose work lists take the largest grids first; FP64 first convolutions
 // run per grid size (in order of decreasing n).
-gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, hipStream_t s) {
+// side: the batch, whose side stream and events take class B's first half
+// when both classes are present (nullptr: one stream)
+gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, hipStream_t s,
+                      gpf_batch *side) {
   const int nb = (int)probs.size();
   // class A before class B, each by decreasing n (stable: input order kept)
   std::stable_sort(probs.begin(), probs.end(), [](const ProblemRef &a, const ProblemRef &b) {
@@ -767,23 +773,23 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto vel_gather = [&](int i) { return pd[i].u && !pd[i].vel_tiles ? (pd[i].nv + 255) / 256 : 0; };
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
   auto halo_blocks = [&](int i) { return pd[i].nv > 0 && !pd[i].halo_defer ? fixup_blocks(pd[i].n) : 0; };
-  // per class: bin count, tile scatter, halo pass, bin place (the split
-  // tiles' kernel runs once for both classes: fs*[4] stays empty); over
-  // all problems: split tiles, R_s gather, two velocity kernels
-  FlatMap fsa[5] = {}, fsb[5] = {}, fcomb, frs, fvel[2];
+  // per class: bin count, tile scatter, halo pass, bin place (fs*[4] stays
+  // empty), split tiles; over all problems: R_s gather, two velocity kernels
+  FlatMap fsa[5] = {}, fsb[5] = {}, fcomb[2] = {}, frs, fvel[2];
   if (na > 0) {
     make_flat(0, na, bin_blocks, &fsa[0]);
     make_flat(0, na, tile_blocks, &fsa[1]);
     make_flat(0, na, halo_blocks, &fsa[2]);
     make_flat(0, na, place_map_blocks, &fsa[3]);
+    make_flat(0, na, split_tile_blocks, &fcomb[0]);
   }
   if (nbb > 0) {
     make_flat(na, nb, bin_blocks, &fsb[0]);
     make_flat(na, nb, tile_blocks, &fsb[1]);
     make_flat(na, nb, halo_blocks, &fsb[2]);
     make_flat(na, nb, place_map_blocks, &fsb[3]);
+    make_flat(na, nb, split_tile_blocks, &fcomb[1]);
   }
-  make_flat(0, nb, split_tile_blocks, &fcomb);
   make_flat(0, nb, rs_blocks, &frs);
   make_flat(0, nb, vel_gather, &fvel[0]);
   make_flat(0, nb, vel_tiles, &fvel[1]);
@@ -815,39 +821,72 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto fixf = [&](FlatMap *fm, int k) {
     for (int i = 0; i < k; ++i) fm[i].e = reinterpret_cast<const FlatEntry *>(base + (size_t)fm[i].e);
   };
-  if (na > 0) fixf(fsa, 4);
-  if (nbb > 0) fixf(fsb, 4);
-  fixf(&fcomb, 1);
+  if (na > 0) {
+    fixf(fsa, 4);
+    fixf(&fcomb[0], 1);
+  }
+  if (nbb > 0) {
+    fixf(fsb, 4);
+    fixf(&fcomb[1], 1);
+  }
   fixf(&frs, 1);
   fixf(fvel, 2);
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
   const ConvDesc *dc2 = dc1 + nb;
   gpf_ctx *ctx = probs[0].plan->ctx;
-  // R_v
-  if (na > 0) GPF_HIP(launch_scatter_vortices<float>(dpd, na, ca.n_max, ca.nv_max, s, fsa));
-  if (nbb > 0) GPF_HIP(launch_scatter_vortices<double>(dpd + na, nbb, cbi.n_max, cbi.nv_max, s, fsb));
-  timer_begin(GPF_TK_SCATTER, s);
-  GPF_HIP(launch_split_combine(dpd, nb, 0, s, &fcomb));
-  timer_end(s);
-  // first convolution (surface band only)
-  if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc1, mp1a, s)));
-  for (int i = na; i < nb;) {
-    int j = i;
-    int band = 0;
-    while (j < nb && pd[j].n == pd[i].n) {
-      band = std::max(band, (c1[j].row_hi | 15) - (c1[j].row_lo & ~15) + 1);
-      ++j;
+  // each class up to its Schur solve: R_v (scatter, split tiles), the first
+  // convolution (surface band only), surface right-hand sides, Schur
+  // complement and constraints.  Class B's kernels are few and small (FP64
+  // transforms of a handful of problems): with both classes present they
+  // run on the side stream, issued first, beside class A's, and the main
+  // stream waits for them before the R_s gather.
+  const bool fork = side != nullptr && na > 0 && nbb > 0;
+  const hipStream_t sb = fork ? side->side : s;
+  auto class_a = [&]() -> gpf_status {
+    GPF_HIP(launch_scatter_vortices<float>(dpd, na, ca.n_max, ca.nv_max, s, fsa));
+    timer_begin(GPF_TK_SCATTER, s);
+    GPF_HIP(launch_split_combine(dpd, na, 0, s, &fcomb[0]));
+    timer_end(s);
+    GPF_HIP((launch_convolve_multi<float, float>(dc1, mp1a, s)));
+    GPF_HIP(launch_surface_rhs<float>(dpd, na, ca.ns_max, ca.m_max, s));
+    GPF_HIP(launch_schur_apply<float>(dpd, na, ca.ns_max, ca.m_max, s));
+    return GPF_OK;
+  };
+  auto class_b = [&]() -> gpf_status {
+    GPF_HIP(launch_scatter_vortices<double>(dpd + na, nbb, cbi.n_max, cbi.nv_max, sb, fsb));
+    timer_begin(GPF_TK_SCATTER, sb);
+    GPF_HIP(launch_split_combine(dpd + na, nbb, 0, sb, &fcomb[1]));
+    timer_end(sb);
+    for (int i = na; i < nb;) {
+      int j = i;
+      int band = 0;
+      while (j < nb && pd[j].n == pd[i].n) {
+        band = std::max(band, (c1[j].row_hi | 15) - (c1[j].row_lo & ~15) + 1);
+        ++j;
+      }
+      const ConvSched sc = ctx->sched_for(pd[i].n, true, j - i);
+      GPF_HIP((launch_convolve<double, double>(pd[i].n, dc1 + i, j - i, xcds, band, sb, sc)));
+      i = j;
     }
-    const ConvSched sc = ctx->sched_for(pd[i].n, true, j - i);
-    GPF_HIP((launch_convolve<double, double>(pd[i].n, dc1 + i, j - i, xcds, band, s, sc)));
-    i = j;
+    GPF_HIP(launch_surface_rhs<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, sb));
+    GPF_HIP(launch_schur_apply<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, sb));
+    return GPF_OK;
+  };
+  if (fork) {
+    // after the descriptor copy on s, and after every earlier use of these
+    // problems' buffers on s
+    GPF_HIP(hipEventRecord(side->side_fork, s));
+    GPF_HIP(hipStreamWaitEvent(sb, side->side_fork, 0));
+    GPF_TRY(class_b());
+    GPF_HIP(hipEventRecord(side->side_join, sb));
+    GPF_TRY(class_a());
+    GPF_HIP(hipStreamWaitEvent(s, side->side_join, 0));
+  } else {
+    if (na > 0) GPF_TRY(class_a());
+    if (nbb > 0) GPF_TRY(class_b());
   }
-  // surface right-hand sides, Schur complement and constraints, R_s f
-  if (na > 0) GPF_HIP(launch_surface_rhs<float>(dpd, na, ca.ns_max, ca.m_max, s));
-  if (nbb > 0) GPF_HIP(launch_surface_rhs<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
-  if (na > 0) GPF_HIP(launch_schur_apply<float>(dpd, na, ca.ns_max, ca.m_max, s));
-  if (nbb > 0) GPF_HIP(launch_schur_apply<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, s));
+  // R_s f of every problem
   timer_begin(GPF_TK_SURFACE, s);
   GPF_HIP(launch_rs_apply(dpd, nb, 0, s, &frs));
   timer_end(s);
@@ -1725,8 +1764,9 @@ gpf_status gpf_batch_set_lanes(gpf_batch *batch, int lanes) {
 int gpf_batch_get_lanes(const gpf_batch *batch) { return batch ? batch->lanes : 0; }
 
 gpf_status gpf_batch_set_merge(gpf_batch *batch, int merge) {
-  if (!batch) return fail(GPF_E_INVALID, "gpf_batch_set_merge: null batch");
-  batch->merge = merge ? 1 : 0;
+  if (!batch || merge < 0 || merge > 2)
+    return fail(GPF_E_INVALID, "gpf_batch_set_merge: null batch or merge not in [0, 2]");
+  batch->merge = merge;
   return GPF_OK;
 }
 
@@ -1794,7 +1834,12 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
   if (merge) {
     // one launch per stage and precision class over every grid size; the
     // lanes, if any, wait for nothing and join at once
-    GPF_TRY(run_merged(refs, batch->ring, batch->ctx->xcds, s));
+    if (batch->merge == 1 && !batch->side) {
+      GPF_HIP(hipStreamCreateWithFlags(&batch->side, hipStreamNonBlocking));
+      GPF_HIP(hipEventCreateWithFlags(&batch->side_fork, hipEventDisableTiming));
+      GPF_HIP(hipEventCreateWithFlags(&batch->side_join, hipEventDisableTiming));
+    }
+    GPF_TRY(run_merged(refs, batch->ring, batch->ctx->xcds, s, batch->merge == 1 ? batch : nullptr));
   } else if (lanes == 1) {
     for (int g = 0; g < ng; ++g) GPF_TRY(run_group(cfgs[g], groups[g], batch->ring, batch->ctx->xcds, s));
   } else if (ng >= 2) {

@@ -636,7 +636,8 @@ struct gpf_batch {
   // from and joined to the caller's stream with events
   int lanes = 1;
   // batches of several grid sizes run merged (one launch per stage over all
-  // sizes) unless this is cleared
+  // sizes): 1 with the side stream below, 2 on the caller's stream alone;
+  // 0 runs them group by group
   int merge = 1;
   // sizes every workspace of a call is kept at: the largest grid, vortex
   // count, surface and band the batch has held, and whether FP32 / FP64
@@ -648,6 +649,11 @@ struct gpf_batch {
   bool hw_w32 = false, hw_w64 = false;
   hipStream_t lane_stream[kMaxLanes] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
+  // side stream of merged batches (created at the first merged batch with
+  // both precision classes): the class with an FP64 first convolution runs
+  // up to its Schur solve there, beside the FP32 class
+  hipStream_t side = nullptr;
+  hipEvent_t side_fork = nullptr, side_join = nullptr;
   ~gpf_batch();
 };
 

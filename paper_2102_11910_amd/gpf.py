@@ -514,7 +514,7 @@ def gpf_vortex_velocity(plan: Plan, s, X, Y, u_inf, v_inf, u, v, status=None, st
 class Batch:
     """Workspaces for up to max_problems problems solved in shared launches."""
 
-    def __init__(self, ctx: Context, max_problems: int, lanes: int = 1, merge: bool = True):
+    def __init__(self, ctx: Context, max_problems: int, lanes: int = 1, merge: int = 1):
         h = C.c_void_p()
         check(lib.gpf_batch_create(ctx.h, max_problems, C.byref(h)), "gpf_batch_create")
         self.h = h
@@ -523,9 +523,15 @@ class Batch:
         if lanes != 1:
             check(lib.gpf_batch_set_lanes(h, int(lanes)), "gpf_batch_set_lanes")
         self.lanes = lanes
-        if not merge:
-            check(lib.gpf_batch_set_merge(h, 0), "gpf_batch_set_merge")
-        self.merge = bool(merge)
+        self.merge = 1
+        if int(merge) != 1:
+            self.set_merge(merge)
+
+    def set_merge(self, merge: int):
+        """0: group by group; 1: merged, FP64-first-convolution problems on a
+        side stream; 2: merged on the caller's stream alone (gpf_batch_set_merge)."""
+        check(lib.gpf_batch_set_merge(self.h, int(merge)), "gpf_batch_set_merge")
+        self.merge = int(merge)
 
     def solve(self, plans, bodies, inputs, outputs, stream=None):
         k = len(plans)

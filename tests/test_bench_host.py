@@ -80,6 +80,19 @@ def test_trace_and_counter_summaries(tmp_path, monkeypatch):
         w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"])
         w.writerow([names[0], 135, 135 * 97000, 97000, 60.0, 90000, 110000])
         w.writerow([names[1], 90, 90 * 20000, 20000, 40.0, 1000, 50000])
+    # the trace: 5 warmup steps, 20 event-timed steps, 20 headline steps; per
+    # step 3 column dispatches (100, 97, 110 us in the three phases) and 2
+    # bin counts of 20 us; the per-class rows use the event-timed steps only
+    with open(td / "c4_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        t = 1000
+        for step in range(45):
+            cols_ns = 100000 if step < 5 else (97000 if step < 25 else 110000)
+            for nm, dur, k in ((names[1], 20000, 2), (names[0], cols_ns, 3)):
+                for _ in range(k):
+                    w.writerow([nm, t, t + dur])
+                    t += dur + 500
     res = {"warmup": 5, "steps": 20, "ms_per_step": 1.2,
            "roofline": {"kernel": "cols", "avg_us": 97.5, "achieved": 2900.0, "frac": 0.36},
            "kernels": {"cols": {"us_per_step": 292.0, "avg_us": 97.5}}}
@@ -89,8 +102,10 @@ def test_trace_and_counter_summaries(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRACE_SUMMARY", str(out))
     bench.summarize_trace(str(tmp_path / "trace"), str(bj))
     text = out.read_text()
-    # 135 dispatches of 97 us over 45 steps: 3 per step, 291 us per step
+    # the 60 column dispatches of the event-timed steps, 97 us each: 3 per
+    # step, 291 us per step
     assert "| cols | 1 | 291.00 | 97.00 | 3.00 | 292.00 | 97.50 |" in text
+    assert "| scatter | 1 | 40.00 | 20.00 | 2.00 |" in text
     assert "| k_bin_count | 90 | 20.00 |" in text
 
     sq = []

@@ -181,6 +181,63 @@ def test_merged_batch_graph_replays(ctx):
             gpf.gpf_sync(o.status)
 
 
+def test_side_stream_same_bits_and_graph(ctx):
+    """A merged batch with both first-convolution precisions: the FP64 class
+    on the batch's side stream (merge 1, the default) gives the same bits as
+    every kernel on the caller's stream (merge 2), and the grouped path
+    (merge 0) agrees within tolerance; a graph captured with the side stream
+    forked and joined replays the eager bits, with eager work and
+    synchronizations between replays; merge values outside 0..2 are refused."""
+    cases = [wl.config2(seed=271, nv=2500),
+             wl.random_case(272, 256, 2.56 / 256, 900, surface="plate", mode="kutta"),
+             wl.random_case(273, 128, 2.0 / 128, 400, surface="cylinder"),
+             _with_dense_cluster(wl.random_case(274, 128, 2.0 / 128, 500, surface="ellipse"), 2000, 274)]
+    st = Setup(ctx, cases)
+    fp64 = [b.info()["conv1_fp64"] for b in st.bodies]
+    say(f"[side stream] FP64 first convolution: {fp64}")
+    assert any(fp64) and not all(fp64)
+    res = {}
+    for m in (1, 2, 0):
+        batch = gpf.Batch(ctx, len(cases), merge=m)
+        outs = st.outputs()
+        batch.solve(st.plans, st.bodies, st.ins, [o.struct for o in outs])
+        for o in outs:
+            gpf.gpf_sync(o.status)
+        res[m] = [_host(o) for o in outs]
+        batch.close()
+    for i, c in enumerate(cases):
+        same = all(np.array_equal(res[1][i][k], res[2][i][k]) for k in res[1][i])
+        say(f"[side stream vs one stream] {c.name}: bit-identical {same}")
+        assert same, c.name
+        _compare(res[1][i], res[0][i], f"[side stream vs grouped] {c.name}")
+    batch = gpf.Batch(ctx, len(cases))
+    outs = st.outputs()
+    structs = [o.struct for o in outs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch.solve(st.plans, st.bodies, st.ins, structs, stream=stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        batch.solve(st.plans, st.bodies, st.ins, structs, stream=stream)
+    for rep in range(3):
+        for o in outs:
+            o.psi.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            h = _host(o)
+            same = all(np.array_equal(h[k], res[1][i][k]) for k in h)
+            say(f"[side stream graph replay {rep}] {cases[i].name}: bit-identical {same}")
+            assert same, cases[i].name
+        batch.solve(st.plans, st.bodies, st.ins, structs)
+        for o in outs:
+            gpf.gpf_sync(o.status)
+    for bad in (-1, 3):
+        with pytest.raises(gpf.GpfError):
+            batch.set_merge(bad)
+
+
 def test_dense_clouds_velocity_tiles(ctx):
     """Clouds of at least one vortex per four nodes take the tile-by-tile
     velocity kernel (the field window of a tile through LDS): alone, in a
