@@ -774,8 +774,8 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto vel_tiles = [&](int i) { return pd[i].u && pd[i].vel_tiles ? tile_blocks(i) : 0; };
   auto halo_blocks = [&](int i) { return pd[i].nv > 0 && !pd[i].halo_defer ? fixup_blocks(pd[i].n) : 0; };
   // per class: bin count, tile scatter, halo pass, bin place (fs*[4] stays
-  // empty), split tiles; over all problems: R_s gather, two velocity kernels
-  FlatMap fsa[5] = {}, fsb[5] = {}, fcomb[2] = {}, frs, fvel[2];
+  // empty), split tiles, R_s gather; over all problems: two velocity kernels
+  FlatMap fsa[5] = {}, fsb[5] = {}, fcomb[2] = {}, frs[2] = {}, fvel[2];
   if (na > 0) {
     make_flat(0, na, bin_blocks, &fsa[0]);
     make_flat(0, na, tile_blocks, &fsa[1]);
@@ -790,7 +790,8 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     make_flat(na, nb, place_map_blocks, &fsb[3]);
     make_flat(na, nb, split_tile_blocks, &fcomb[1]);
   }
-  make_flat(0, nb, rs_blocks, &frs);
+  if (na > 0) make_flat(0, na, rs_blocks, &frs[0]);
+  if (nbb > 0) make_flat(na, nb, rs_blocks, &frs[1]);
   make_flat(0, nb, vel_gather, &fvel[0]);
   make_flat(0, nb, vel_tiles, &fvel[1]);
   MultiPass mp1a[3], mp2a[3], mp2b[3];
@@ -824,23 +825,25 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   if (na > 0) {
     fixf(fsa, 4);
     fixf(&fcomb[0], 1);
+    fixf(&frs[0], 1);
   }
   if (nbb > 0) {
     fixf(fsb, 4);
     fixf(&fcomb[1], 1);
+    fixf(&frs[1], 1);
   }
-  fixf(&frs, 1);
   fixf(fvel, 2);
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
   const ConvDesc *dc2 = dc1 + nb;
   gpf_ctx *ctx = probs[0].plan->ctx;
-  // each class up to its Schur solve: R_v (scatter, split tiles), the first
+  // each class up to its velocities: R_v (scatter, split tiles), the first
   // convolution (surface band only), surface right-hand sides, Schur
-  // complement and constraints.  Class B's kernels are few and small (FP64
-  // transforms of a handful of problems): with both classes present they
-  // run on the side stream, issued first, beside class A's, and the main
-  // stream waits for them before the R_s gather.
+  // complement and constraints, R_s f, the final convolution.  Class B's
+  // kernels are few and small (FP64 transforms of a handful of problems):
+  // with both classes present they run on the side stream, issued first,
+  // beside class A's, and the main stream waits for them before the
+  // velocities.
   const bool fork = side != nullptr && na > 0 && nbb > 0;
   const hipStream_t sb = fork ? side->side : s;
   auto class_a = [&]() -> gpf_status {
@@ -851,6 +854,10 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     GPF_HIP((launch_convolve_multi<float, float>(dc1, mp1a, s)));
     GPF_HIP(launch_surface_rhs<float>(dpd, na, ca.ns_max, ca.m_max, s));
     GPF_HIP(launch_schur_apply<float>(dpd, na, ca.ns_max, ca.m_max, s));
+    timer_begin(GPF_TK_SURFACE, s);
+    GPF_HIP(launch_rs_apply(dpd, na, 0, s, &frs[0]));
+    timer_end(s);
+    GPF_HIP((launch_convolve_multi<float, float>(dc2, mp2a, s)));
     return GPF_OK;
   };
   auto class_b = [&]() -> gpf_status {
@@ -871,6 +878,10 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     }
     GPF_HIP(launch_surface_rhs<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, sb));
     GPF_HIP(launch_schur_apply<double>(dpd + na, nbb, cbi.ns_max, cbi.m_max, sb));
+    timer_begin(GPF_TK_SURFACE, sb);
+    GPF_HIP(launch_rs_apply(dpd + na, nbb, 0, sb, &frs[1]));
+    timer_end(sb);
+    GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, sb)));
     return GPF_OK;
   };
   if (fork) {
@@ -886,13 +897,6 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     if (na > 0) GPF_TRY(class_a());
     if (nbb > 0) GPF_TRY(class_b());
   }
-  // R_s f of every problem
-  timer_begin(GPF_TK_SURFACE, s);
-  GPF_HIP(launch_rs_apply(dpd, nb, 0, s, &frs));
-  timer_end(s);
-  // final convolution of all vorticity
-  if (na > 0) GPF_HIP((launch_convolve_multi<float, float>(dc2, mp2a, s)));
-  if (nbb > 0) GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, s)));
   // velocities of every problem, then impulses where asked
   GPF_HIP(launch_solve_velocity<float>(dpd, nb, std::max(ca.n_max, cbi.n_max),
                                        std::max(ca.nv_max, cbi.nv_max), s, fvel));

@@ -651,7 +651,7 @@ struct gpf_batch {
   hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
   // side stream of merged batches (created at the first merged batch with
   // both precision classes): the class with an FP64 first convolution runs
-  // up to its Schur solve there, beside the FP32 class
+  // up to its velocities there, beside the FP32 class
   hipStream_t side = nullptr;
   hipEvent_t side_fork = nullptr, side_join = nullptr;
   ~gpf_batch();
