@@ -51,9 +51,19 @@ static thread_local KernelTimer *g_timer = nullptr;
 
 void timer_install(KernelTimer *t) { g_timer = t; }
 
+// more events for a timer whose pool runs short (host-side creation only)
+static bool timer_refill(KernelTimer *t) {
+  for (int i = 0; i < 1024; ++i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    t->pool.push_back(e);
+  }
+  return t->pool.size() >= 2;
+}
+
 void timer_begin(int kind, hipStream_t s) {
   KernelTimer *t = g_timer;
-  if (!t || t->pool.size() < 2) return;  // no timer, or out of events
+  if (!t || (t->pool.size() < 2 && !timer_refill(t))) return;  // no timer, or out of events
   hipEvent_t a = t->pool.back();
   t->pool.pop_back();
   if (hipEventRecord(a, s) != hipSuccess) {
@@ -67,6 +77,11 @@ void timer_begin(int kind, hipStream_t s) {
 void timer_end(hipStream_t s) {
   KernelTimer *t = g_timer;
   if (!t || !t->open_a) return;
+  if (t->pool.empty() && !timer_refill(t)) {
+    t->pool.push_back(t->open_a);
+    t->open_a = nullptr;
+    return;
+  }
   hipEvent_t b = t->pool.back();
   t->pool.pop_back();
   (void)hipEventRecord(b, s);
