@@ -1809,19 +1809,28 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
     ProblemRef r{plans[i], inputs[i].mode == GPF_NOBODY ? nullptr : b, &inputs[i], &outputs[i],
                  batch->ws[i]};
     const GroupCfg cfg = config_of(r);
-    batch->hw_n = std::max(batch->hw_n, cfg.n);
-    batch->hw_nv = std::max(batch->hw_nv, inputs[i].nv);
-    if (r.body) {
-      batch->hw_ns = std::max(batch->hw_ns, r.body->ns);
-      batch->hw_band = std::max(batch->hw_band, body_band(r.body));
+    if (batch->hw_all) {
+      batch->hw_n = std::max(batch->hw_n, cfg.n);
+      batch->hw_nv = std::max(batch->hw_nv, inputs[i].nv);
+      if (r.body) {
+        batch->hw_ns = std::max(batch->hw_ns, r.body->ns);
+        batch->hw_band = std::max(batch->hw_band, body_band(r.body));
+      }
+      batch->hw_w32 = batch->hw_w32 || !cfg.fp64_plan;
+      batch->hw_w64 = batch->hw_w64 || cfg.fp64_plan || cfg.conv1_fp64;
+    } else {
+      const bool w64 = cfg.fp64_plan || cfg.conv1_fp64;
+      GPF_TRY(r.ws->ensure(cfg.n, !cfg.fp64_plan, w64, r.body ? r.body->ns : 0,
+                           r.body ? body_band(r.body) : 0));
+      GPF_TRY(r.ws->ensure_vortices(inputs[i].nv));
     }
-    batch->hw_w32 = batch->hw_w32 || !cfg.fp64_plan;
-    batch->hw_w64 = batch->hw_w64 || cfg.fp64_plan || cfg.conv1_fp64;
     refs.push_back(r);
   }
-  for (ProblemRef &r : refs) {
-    GPF_TRY(r.ws->ensure(batch->hw_n, batch->hw_w32, batch->hw_w64, batch->hw_ns, batch->hw_band));
-    GPF_TRY(r.ws->ensure_vortices(batch->hw_nv));
+  if (batch->hw_all) {
+    for (ProblemRef &r : refs) {
+      GPF_TRY(r.ws->ensure(batch->hw_n, batch->hw_w32, batch->hw_w64, batch->hw_ns, batch->hw_band));
+      GPF_TRY(r.ws->ensure_vortices(batch->hw_nv));
+    }
   }
   if (nprob == 0) return GPF_OK;
   hipStream_t s = as_stream(hip_stream);

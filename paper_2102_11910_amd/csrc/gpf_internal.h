@@ -639,12 +639,16 @@ struct gpf_batch {
   // sizes): 1 with the side stream below, 2 on the caller's stream alone;
   // 0 runs them group by group
   int merge = 1;
-  // sizes every workspace of a call is kept at: the largest grid, vortex
-  // count, surface and band the batch has held, and whether FP32 / FP64
-  // fields were needed.  A slot grown only to the problem in hand grows
-  // again, and hipFree then waits for the whole device, each time a larger
-  // problem than it has held lands on it.  The request server raises them
-  // to its own high-water marks before each batch.
+  // with hw_all set (the request server's batches), every workspace of a
+  // call is kept at the high-water sizes: the largest grid, vortex count,
+  // surface and band the batch has held, and whether FP32 / FP64 fields were
+  // needed, which the server raises to its own admission marks before each
+  // batch.  A slot grown only to the problem in hand grows again, and
+  // hipFree then waits for the whole device, each time a larger problem
+  // than it has held lands on it.  Other batches size each slot to its
+  // problem (a mix of very different sizes would otherwise multiply the
+  // largest problem's footprint by the slot count).
+  bool hw_all = false;
   int hw_n = 0, hw_nv = 0, hw_ns = 0, hw_band = 0;
   bool hw_w32 = false, hw_w64 = false;
   hipStream_t lane_stream[kMaxLanes] = {};

@@ -223,6 +223,7 @@ gpf_status gpf_server_create(gpf_ctx *ctx, size_t hbm_budget_bytes, int max_slot
   s->flags = plan_flags;
   for (int k = 0; k < kServerSets; ++k) {
     GPF_TRY(gpf_batch_create(ctx, max_slots, &s->batch[k]));
+    s->batch[k]->hw_all = true;   // slots at the admitted high-water sizes
     GPF_HIP(hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming));
     GPF_HIP(hipStreamCreateWithFlags(&s->stream[k], hipStreamNonBlocking));
   }
