@@ -172,9 +172,10 @@ def test_graph_capture_replays_solve(ctx):
 
 def test_uneven_batch_of_64_matches_alone(ctx):
     """The 64-problem batch of uneven sizes (n from 128 to 1024, 1e3-1e5
-    vortices, ellipses of random aspect and rotation): one launch sequence
-    per configuration, every problem equal to its own plain solve, and the
-    two smallest problems against the oracle."""
+    vortices, ellipses of random aspect and rotation) as the benchmark runs
+    it: merged launches, the FP64-first-convolution problems on the batch's
+    side stream; every problem equal to its own plain solve, and the two
+    smallest problems against the oracle."""
     cases = wl.config4()
     dev = torch.device("cuda", 0)
     plans = {}
