@@ -275,7 +275,8 @@ int place_blocks(int nv);   // workgroups of the binning place kernel of one pro
 constexpr int kMaxVortices = 1 << 22;
 constexpr int kPartStride = kMaxVortices / 256;
 // Vortices per thread of the binning count (256 threads per workgroup), a
-// power of two from 1 to 16.  A workgroup adds one device atomic per
+// power of two from 1 to 8 (16 made the kernel, which holds every case,
+// keep 144 VGPRs instead of 81).  A workgroup adds one device atomic per
 // non-empty tile to the tile counts, and the atomics on one counter are
 // carried out one after another; a thread's vortices, on the other hand,
 // are a serial chain of FP64 cell arithmetic and LDS atomics.  About 64
@@ -285,7 +286,7 @@ constexpr int kPartStride = kMaxVortices / 256;
 __host__ __device__ inline int bin_per_thread(int nv) {
   const int want = (nv + 256 * 64 - 1) / (256 * 64);
   int p = 1;
-  while (p < want && p < 16) p *= 2;
+  while (p < want && p < 8) p *= 2;
   return p;
 }
 // workgroups of the binning count of a problem (one partial each)

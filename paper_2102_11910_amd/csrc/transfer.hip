@@ -169,8 +169,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_bin_count(const ProbDesc *__r
     case 1: bin_count_body<1>(P, fb.blk, hist, red); break;
     case 2: bin_count_body<2>(P, fb.blk, hist, red); break;
     case 4: bin_count_body<4>(P, fb.blk, hist, red); break;
-    case 8: bin_count_body<8>(P, fb.blk, hist, red); break;
-    default: bin_count_body<16>(P, fb.blk, hist, red); break;
+    default: bin_count_body<8>(P, fb.blk, hist, red); break;
   }
 }
 
@@ -1034,7 +1033,7 @@ hipError_t launch_scatter_vortices(const ProbDesc *d, int nb, int n, int nv_max,
   const FlatMap none{nullptr, 0, 0};
   const FlatMap mb = fm ? fm[0] : none, mt = fm ? fm[1] : none, mh = fm ? fm[2] : none;
   const FlatMap mp = fm ? fm[3] : none;
-  // the count's workgroups take up to 4096 vortices (bin_per_thread); the
+  // the count's workgroups take up to 2048 vortices (bin_per_thread); the
   // place kernel one per thread
   const int cb = nv_max > 0 ? bin_count_blocks(nv_max) : 1, vb = place_blocks(nv_max);
   hipLaunchKernelGGL(k_bin_count, grid_of(fm ? &mb : nullptr, cb, nb), dim3(kScatterBlock), 0, s, d, mb);
