@@ -349,6 +349,8 @@ gpf_batch::~gpf_batch() {
   if (side) (void)hipStreamDestroy(side);
   if (side_fork) (void)hipEventDestroy(side_fork);
   if (side_join) (void)hipEventDestroy(side_join);
+  if (side2) (void)hipStreamDestroy(side2);
+  if (side2_join) (void)hipEventDestroy(side2_join);
   for (auto *w : ws) delete w;
 }
 
@@ -723,16 +725,22 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   MultiEntry *tab = reinterpret_cast<MultiEntry *>(blk.data() + tab_off);
   struct ClassInfo {
     int nv_max = 0, ns_max = 0, m_max = 0, n_max = 0;
-  } ca, cbi;
+  } ca, cbi, ca1, ca2;
+  // with the side streams, class A runs as two parts on two streams: A1 the
+  // problems of its largest grid size, A2 the rest
+  int na1 = 0;
+  while (na1 < na && config_of(probs[na1]).n == config_of(probs[0]).n) ++na1;
   bool impulse = false;
   for (int i = 0; i < nb; ++i) {
     const GroupCfg cfg = config_of(probs[i]);
     describe(probs[i], cfg, pd[i], c1[i], c2[i]);
-    ClassInfo &ci = i < na ? ca : cbi;
-    ci.nv_max = std::max(ci.nv_max, pd[i].nv);
-    ci.ns_max = std::max(ci.ns_max, pd[i].ns);
-    ci.m_max = std::max(ci.m_max, pd[i].sv.m);
-    ci.n_max = std::max(ci.n_max, cfg.n);
+    for (ClassInfo *cp : {i < na ? &ca : &cbi, i < na1 ? &ca1 : (i < na ? &ca2 : &cbi)}) {
+      ClassInfo &ci = *cp;
+      ci.nv_max = std::max(ci.nv_max, pd[i].nv);
+      ci.ns_max = std::max(ci.ns_max, pd[i].ns);
+      ci.m_max = std::max(ci.m_max, pd[i].sv.m);
+      ci.n_max = std::max(ci.n_max, cfg.n);
+    }
     impulse = impulse || pd[i].imp_out != nullptr;
   }
   // work tables: pass kind per table (0 rows forward, 1 columns, 2 band rows
@@ -790,13 +798,30 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto halo_blocks = [&](int i) { return pd[i].nv > 0 && !pd[i].halo_defer ? fixup_blocks(pd[i].n) : 0; };
   // per class: bin count, tile scatter, halo pass, bin place (fs*[4] stays
   // empty), split tiles, R_s gather; over all problems: two velocity kernels
-  FlatMap fsa[5] = {}, fsb[5] = {}, fcomb[2] = {}, frs[2] = {}, fvel[2];
-  if (na > 0) {
-    make_flat(0, na, bin_blocks, &fsa[0]);
-    make_flat(0, na, tile_blocks, &fsa[1]);
-    make_flat(0, na, halo_blocks, &fsa[2]);
-    make_flat(0, na, place_map_blocks, &fsa[3]);
-    make_flat(0, na, split_tile_blocks, &fcomb[0]);
+  FlatMap fsb[5] = {}, fcomb[2] = {}, frs[2] = {}, fvel[2];
+  struct Sub {
+    int lo = 0, hi = 0;
+    ClassInfo ci;
+    FlatMap fs[5] = {}, fcomb = {}, frs = {};
+    MultiPass mp1[3], mp2[3];
+    hipStream_t st = nullptr;
+  } subs[2];
+  const bool split = side != nullptr && na1 > 0 && na1 < na;
+  const int nsub = na > 0 ? (split ? 2 : 1) : 0;
+  if (split) {
+    subs[0].lo = 0, subs[0].hi = na1, subs[0].ci = ca1, subs[0].st = s;
+    subs[1].lo = na1, subs[1].hi = na, subs[1].ci = ca2, subs[1].st = side->side2;
+  } else {
+    subs[0].lo = 0, subs[0].hi = na, subs[0].ci = ca, subs[0].st = s;
+  }
+  for (int k = 0; k < nsub; ++k) {
+    Sub &u = subs[k];
+    make_flat(u.lo, u.hi, bin_blocks, &u.fs[0]);
+    make_flat(u.lo, u.hi, tile_blocks, &u.fs[1]);
+    make_flat(u.lo, u.hi, halo_blocks, &u.fs[2]);
+    make_flat(u.lo, u.hi, place_map_blocks, &u.fs[3]);
+    make_flat(u.lo, u.hi, split_tile_blocks, &u.fcomb);
+    make_flat(u.lo, u.hi, rs_blocks, &u.frs);
   }
   if (nbb > 0) {
     make_flat(na, nb, bin_blocks, &fsb[0]);
@@ -805,18 +830,18 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     make_flat(na, nb, place_map_blocks, &fsb[3]);
     make_flat(na, nb, split_tile_blocks, &fcomb[1]);
   }
-  if (na > 0) make_flat(0, na, rs_blocks, &frs[0]);
   if (nbb > 0) make_flat(na, nb, rs_blocks, &frs[1]);
   make_flat(0, nb, vel_gather, &fvel[0]);
   make_flat(0, nb, vel_tiles, &fvel[1]);
-  MultiPass mp1a[3], mp2a[3], mp2b[3];
-  if (na > 0) {
-    make_table(0, c1, 0, na, &mp1a[0]);
-    make_table(1, c1, 0, na, &mp1a[1]);
-    make_table(2, c1, 0, na, &mp1a[2]);
-    make_table(0, c2, 0, na, &mp2a[0]);
-    make_table(1, c2, 0, na, &mp2a[1]);
-    make_table(3, c2, 0, na, &mp2a[2]);
+  MultiPass mp2b[3];
+  for (int k = 0; k < nsub; ++k) {
+    Sub &u = subs[k];
+    make_table(0, c1, u.lo, u.hi, &u.mp1[0]);
+    make_table(1, c1, u.lo, u.hi, &u.mp1[1]);
+    make_table(2, c1, u.lo, u.hi, &u.mp1[2]);
+    make_table(0, c2, u.lo, u.hi, &u.mp2[0]);
+    make_table(1, c2, u.lo, u.hi, &u.mp2[1]);
+    make_table(3, c2, u.lo, u.hi, &u.mp2[2]);
   }
   if (nbb > 0) {
     make_table(0, c2, na, nb, &mp2b[0]);
@@ -829,18 +854,18 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   auto fix = [&](MultiPass *mp) {   // table offsets -> device addresses
     for (int k = 0; k < 3; ++k) mp[k].e = reinterpret_cast<const MultiEntry *>(base + (size_t)mp[k].e);
   };
-  if (na > 0) {
-    fix(mp1a);
-    fix(mp2a);
+  for (int k = 0; k < nsub; ++k) {
+    fix(subs[k].mp1);
+    fix(subs[k].mp2);
   }
   if (nbb > 0) fix(mp2b);
   auto fixf = [&](FlatMap *fm, int k) {
     for (int i = 0; i < k; ++i) fm[i].e = reinterpret_cast<const FlatEntry *>(base + (size_t)fm[i].e);
   };
-  if (na > 0) {
-    fixf(fsa, 4);
-    fixf(&fcomb[0], 1);
-    fixf(&frs[0], 1);
+  for (int k = 0; k < nsub; ++k) {
+    fixf(subs[k].fs, 4);
+    fixf(&subs[k].fcomb, 1);
+    fixf(&subs[k].frs, 1);
   }
   if (nbb > 0) {
     fixf(fsb, 4);
@@ -857,22 +882,26 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   // complement and constraints, R_s f, the final convolution.  Class B's
   // kernels are few and small (FP64 transforms of a handful of problems):
   // with both classes present they run on the side stream, issued first,
-  // beside class A's, and the main stream waits for them before the
-  // velocities.
+  // beside class A's.  Class A's two parts run on the caller's stream (A1)
+  // and the second side stream (A2), so that one part's latency-bound
+  // stages overlap the other's transforms.  The main stream waits for the
+  // side streams before the velocities.
   const bool fork = side != nullptr && na > 0 && nbb > 0;
   const hipStream_t sb = fork ? side->side : s;
-  auto class_a = [&]() -> gpf_status {
-    GPF_HIP(launch_scatter_vortices<float>(dpd, na, ca.n_max, ca.nv_max, s, fsa));
-    timer_begin(GPF_TK_SCATTER, s);
-    GPF_HIP(launch_split_combine(dpd, na, 0, s, &fcomb[0]));
-    timer_end(s);
-    GPF_HIP((launch_convolve_multi<float, float>(dc1, mp1a, s)));
-    GPF_HIP(launch_surface_rhs<float>(dpd, na, ca.ns_max, ca.m_max, s));
-    GPF_HIP(launch_schur_apply<float>(dpd, na, ca.ns_max, ca.m_max, s));
-    timer_begin(GPF_TK_SURFACE, s);
-    GPF_HIP(launch_rs_apply(dpd, na, 0, s, &frs[0]));
-    timer_end(s);
-    GPF_HIP((launch_convolve_multi<float, float>(dc2, mp2a, s)));
+  auto class_a = [&](Sub &u) -> gpf_status {
+    const int lo = u.lo, m = u.hi - u.lo;
+    const hipStream_t st = u.st;
+    GPF_HIP(launch_scatter_vortices<float>(dpd + lo, m, u.ci.n_max, u.ci.nv_max, st, u.fs));
+    timer_begin(GPF_TK_SCATTER, st);
+    GPF_HIP(launch_split_combine(dpd + lo, m, 0, st, &u.fcomb));
+    timer_end(st);
+    GPF_HIP((launch_convolve_multi<float, float>(dc1 + lo, u.mp1, st)));
+    GPF_HIP(launch_surface_rhs<float>(dpd + lo, m, u.ci.ns_max, u.ci.m_max, st));
+    GPF_HIP(launch_schur_apply<float>(dpd + lo, m, u.ci.ns_max, u.ci.m_max, st));
+    timer_begin(GPF_TK_SURFACE, st);
+    GPF_HIP(launch_rs_apply(dpd + lo, m, 0, st, &u.frs));
+    timer_end(st);
+    GPF_HIP((launch_convolve_multi<float, float>(dc2 + lo, u.mp2, st)));
     return GPF_OK;
   };
   auto class_b = [&]() -> gpf_status {
@@ -899,17 +928,25 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, sb)));
     return GPF_OK;
   };
-  if (fork) {
+  if (fork || split) {
     // after the descriptor copy on s, and after every earlier use of these
     // problems' buffers on s
     GPF_HIP(hipEventRecord(side->side_fork, s));
-    GPF_HIP(hipStreamWaitEvent(sb, side->side_fork, 0));
-    GPF_TRY(class_b());
-    GPF_HIP(hipEventRecord(side->side_join, sb));
-    GPF_TRY(class_a());
-    GPF_HIP(hipStreamWaitEvent(s, side->side_join, 0));
+    if (fork) GPF_HIP(hipStreamWaitEvent(sb, side->side_fork, 0));
+    if (split) GPF_HIP(hipStreamWaitEvent(side->side2, side->side_fork, 0));
+    if (fork) {
+      GPF_TRY(class_b());
+      GPF_HIP(hipEventRecord(side->side_join, sb));
+    }
+    if (split) {
+      GPF_TRY(class_a(subs[1]));
+      GPF_HIP(hipEventRecord(side->side2_join, side->side2));
+    }
+    GPF_TRY(class_a(subs[0]));
+    if (fork) GPF_HIP(hipStreamWaitEvent(s, side->side_join, 0));
+    if (split) GPF_HIP(hipStreamWaitEvent(s, side->side2_join, 0));
   } else {
-    if (na > 0) GPF_TRY(class_a());
+    for (int k = 0; k < nsub; ++k) GPF_TRY(class_a(subs[k]));
     if (nbb > 0) GPF_TRY(class_b());
   }
   // velocities of every problem, then impulses where asked
@@ -1866,6 +1903,8 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
       GPF_HIP(hipStreamCreateWithFlags(&batch->side, hipStreamNonBlocking));
       GPF_HIP(hipEventCreateWithFlags(&batch->side_fork, hipEventDisableTiming));
       GPF_HIP(hipEventCreateWithFlags(&batch->side_join, hipEventDisableTiming));
+      GPF_HIP(hipStreamCreateWithFlags(&batch->side2, hipStreamNonBlocking));
+      GPF_HIP(hipEventCreateWithFlags(&batch->side2_join, hipEventDisableTiming));
     }
     GPF_TRY(run_merged(refs, batch->ring, batch->ctx->xcds, s, batch->merge == 1 ? batch : nullptr));
   } else if (lanes == 1) {

@@ -659,6 +659,10 @@ struct gpf_batch {
   // up to its velocities there, beside the FP32 class
   hipStream_t side = nullptr;
   hipEvent_t side_fork = nullptr, side_join = nullptr;
+  // second side stream: the FP32 class's problems below its largest grid
+  // size, beside those of the largest
+  hipStream_t side2 = nullptr;
+  hipEvent_t side2_join = nullptr;
   ~gpf_batch();
 };
 
