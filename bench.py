@@ -123,7 +123,8 @@ TRACE_SUMMARY = os.path.join(ROOT, "profiles", "c4_batch64_kernel_trace.md")
 SQ_SUMMARY = os.path.join(ROOT, "profiles", "c4_batch64_sq_counters.md")
 # profiled commands, run from /tmp with the repository at <repo>
 TRACE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d {out} -o c4 -- python3 "
-                 "<repo>/bench.py --steps 20 --warmup 400 --no-cpu-baseline --legs none --batched-only")
+                 "<repo>/bench.py --steps 20 --warmup 5 --no-cpu-baseline --legs none --batched-only "
+                 "--one-stream")
 PMC_COMMAND = "rocprofv3 --pmc {counters} --output-format csv -d {out} -o pmc -- python3 <repo>/bench.py --pmc-workload"
 COPY_BYTES = 1 << 28   # calibration copy: 256 MiB read + 256 MiB written
 SIDE_SETTLE = 400      # side-stream steps of the merged batch before the headline is timed
@@ -178,7 +179,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, command: str) -> None:
     copy_k = max(copy, key=lambda k: fetch_max[k])
     ff, fw = fetch_max[copy_k] / COPY_BYTES, write_max.get(copy_k, COPY_BYTES) / COPY_BYTES
     lines = ["# HBM traffic per launch, 64 uneven problems (n 128..1024) as one merged batch", "",
-             "Two rocprofv3 counter runs of the batched step (FETCH_SIZE, then WRITE_SIZE),",
+             "Two rocprofv3 counter runs of the batched step, its merged kernels on one stream "
+             "(FETCH_SIZE, then WRITE_SIZE),",
              "each scaled by the reading of the same counter for a 256 MiB device copy.", "",
              f"command_fetch: {command.format(counter='FETCH_SIZE', out=fetch_dir)}",
              f"command_write: {command.format(counter='WRITE_SIZE', out=write_dir)}",
@@ -240,10 +242,11 @@ def summarize_trace(trace_dir: str, bench_json: str) -> None:
     lines = ["# Kernel trace, 64 uneven problems (n 128..1024) as one merged batch", "",
              "Command (on one MI355X; only merged batched steps run):", "",
              "```", "cd /tmp && " + TRACE_COMMAND.format(out=trace_dir), "```", "",
-             f"Batched steps in the run: {nsteps} ({W} warmup, {K} with per-class events and "
-             f"the merged kernels on one stream, {K} without events and with the FP64-first-"
-             f"convolution class's first half on the batch's side stream).  Under the profiler the "
-             f"headline step took {res['ms_per_step']:.3f} ms.", "",
+             f"Batched steps in the run: {nsteps} ({W} warmup, {K} with per-class events, {K} "
+             f"without), every one with the merged kernels on one stream (merge mode 2, "
+             f"`--one-stream`: every step launches the same kernels, each alone on the device; the "
+             f"headline rate is timed with the side streams in the plain run).  Under the profiler "
+             f"the one-stream step took {res['ms_per_step']:.3f} ms.", "",
              "## Per kernel class: profiler time per step vs the run's own event timing", "",
              f"Both over the {K} event-timed steps (each kernel alone on the device).", "",
              "| class | kernels | profiler us/step | profiler avg us/dispatch | dispatches/step "
@@ -293,7 +296,8 @@ def summarize_sq(dirs) -> None:
                 if k != "name":
                     a[k].append(v)
     lines = ["# SQ counters, 64 uneven problems (n 128..1024) as one merged batch", "",
-             "Commands (on one MI355X; three batched steps and a copy):", ""]
+             "Commands (on one MI355X; three batched steps, the merged kernels on one stream, "
+             "and a copy):", ""]
     for d, cs in zip(dirs, sets):
         lines.append("    cd /tmp && " + PMC_COMMAND.format(counters=cs, out=d))
     lines += ["", "Means per dispatch; per-wave figures divide by SQ_WAVES.", "",
@@ -912,6 +916,9 @@ def main() -> int:
                     help="write the HBM-traffic summary from two counter runs")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the merged batched step (no one-by-one leg), for kernel traces")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="every merged step on the caller's stream alone (merge mode 2, warm-up and "
+                         "headline too), for kernel traces whose steps must all launch the same kernels")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
                     help="write the kernel-trace summary from a profiled --batched-only run")
     ap.add_argument("--summarize-sq", nargs="+", metavar="PMC_DIR",
@@ -971,6 +978,9 @@ def main() -> int:
             gpf.gpf_solve(p, b, i, o)
 
     if args.pmc_workload:
+        # the merged kernels on one stream, as the per-class event timing
+        # runs them (launches per step and bytes per launch alike)
+        batch.set_merge(2)
         for _ in range(3):
             step_batched()
         torch.cuda.synchronize()
@@ -982,6 +992,8 @@ def main() -> int:
         log("[bench] pmc workload done")
         return 0
 
+    if args.one_stream:
+        batch.set_merge(2)
     for _ in range(args.warmup):
         step_batched()
     for _ in range(0 if args.batched_only else 3):
@@ -997,11 +1009,11 @@ def main() -> int:
     # first half on the batch's side stream (the headline rate)
     batch.set_merge(2)
     wall_ev, lat_b, kt = timed(step_batched, K, P[0], gpf, torch, np)
-    batch.set_merge(1)
+    batch.set_merge(2 if args.one_stream else 1)
     # the side stream settles after its first few hundred steps in a
     # process: with a short warm-up, untimed side-stream steps make up
     # SIDE_SETTLE before the timed ones
-    settle = max(0, SIDE_SETTLE - args.warmup)
+    settle = 0 if args.one_stream else max(0, SIDE_SETTLE - args.warmup)
     for _ in range(settle):
         step_batched()
     wall_b, lat_b2, _ = timed(step_batched, K, P[0], gpf, torch, np, with_events=False)
@@ -1052,6 +1064,7 @@ def main() -> int:
         "steps": K,
         "warmup": args.warmup,
         "side_settle_steps": settle,
+        "one_stream": bool(args.one_stream),
         "ms_per_step": 1e3 * wall_b / K,
         "higher_is_better": True,
         "scaling": "weak",
