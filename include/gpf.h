@@ -616,8 +616,9 @@ gpf_status gpf_autotune(gpf_plan *plan, int fp64, int nb, const char *cache_path
  * precision policy uses the FP64 entry, its second the field precision),
  * the rules and every explicit shape in turn, each choice timing the whole
  * batched solve (gpf_solve_batched with these arguments, which it runs
- * about seven times per trial on hip_stream, overwriting the outputs) and
- * keeping the fastest (the lane count in the batch, the schedules in the
+ * about seven times per trial on hip_stream, overwriting the outputs; a
+ * lane count above one first runs it 400 times, since new streams run a
+ * workload's first few hundred solves slower) and keeping the fastest (the lane count in the batch, the schedules in the
  * context).  Entries are tuned one after another, the others staying at
  * their current values.  Blocks until done; the outputs then hold the
  * result of the last solve. */
