@@ -32,12 +32,14 @@ size_t plan_bytes(int n) {
 
 // Device bytes of one problem workspace, rounded up: per cell the source
 // fields and half spectra of both precisions and the tiles' halo slots
-// (46 B); per vortex the rank and the 32-byte record (36 B) and the window
-// slots of split tiles (at most 2 / 512 of a 9800-byte window: 39 B); per
-// surface point the Schur right-hand sides, products and f (80 B).
+// (46 B) and the first convolution's band buffer (at most n rows of FP64
+// complex: 16 B); per vortex the rank and the 32-byte record (36 B) and the
+// window slots of split tiles (at most 2 / 512 of a 9800-byte window:
+// 39 B); per surface point the Schur right-hand sides, products and f
+// (80 B).
 size_t slot_bytes(int n, int nv, int ns) {
   const size_t cap = nv > 1024 ? (size_t)nv : 1024;
-  return 46 * (size_t)(n + 1) * n + 75 * cap + 80 * (size_t)ns + (1u << 20);
+  return 62 * (size_t)(n + 1) * n + 75 * cap + 80 * (size_t)ns + (1u << 20);
 }
 
 constexpr int kServerSets = 3;
