@@ -332,7 +332,7 @@ int gpf_batch_get_lanes(const gpf_batch *batch);
 
 /* merge = 1 (the default) lets gpf_solve_batched run a batch of several
  * grid sizes merged (see below), with the problems whose first convolution
- * is FP64 solved up to their velocities on a side stream of the batch, and
+ * is FP64 solved (velocities included) on a side stream of the batch, and
  * the FP32 ones of the largest grid size and of the other sizes on the
  * caller's stream and a second side stream (forked from and joined to the
  * caller's stream with events); 2 runs merged batches on the caller's

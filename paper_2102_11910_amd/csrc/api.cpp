@@ -802,7 +802,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   struct Sub {
     int lo = 0, hi = 0;
     ClassInfo ci;
-    FlatMap fs[5] = {}, fcomb = {}, frs = {};
+    FlatMap fs[5] = {}, fcomb = {}, frs = {}, fvel[2] = {};
     MultiPass mp1[3], mp2[3];
     hipStream_t st = nullptr;
   } subs[2];
@@ -831,8 +831,22 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     make_flat(na, nb, split_tile_blocks, &fcomb[1]);
   }
   if (nbb > 0) make_flat(na, nb, rs_blocks, &frs[1]);
-  make_flat(0, nb, vel_gather, &fvel[0]);
-  make_flat(0, nb, vel_tiles, &fvel[1]);
+  // velocity maps: per part with the side streams, else over every problem
+  const bool vsplit = side != nullptr && ((na > 0 && nbb > 0) || split);
+  FlatMap fvelb[2] = {};
+  if (vsplit) {
+    for (int k = 0; k < nsub; ++k) {
+      make_flat(subs[k].lo, subs[k].hi, vel_gather, &subs[k].fvel[0]);
+      make_flat(subs[k].lo, subs[k].hi, vel_tiles, &subs[k].fvel[1]);
+    }
+    if (nbb > 0) {
+      make_flat(na, nb, vel_gather, &fvelb[0]);
+      make_flat(na, nb, vel_tiles, &fvelb[1]);
+    }
+  } else {
+    make_flat(0, nb, vel_gather, &fvel[0]);
+    make_flat(0, nb, vel_tiles, &fvel[1]);
+  }
   MultiPass mp2b[3];
   for (int k = 0; k < nsub; ++k) {
     Sub &u = subs[k];
@@ -872,7 +886,12 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     fixf(&fcomb[1], 1);
     fixf(&frs[1], 1);
   }
-  fixf(fvel, 2);
+  if (vsplit) {
+    for (int k = 0; k < nsub; ++k) fixf(subs[k].fvel, 2);
+    if (nbb > 0) fixf(fvelb, 2);
+  } else {
+    fixf(fvel, 2);
+  }
   const ProbDesc *dpd = reinterpret_cast<const ProbDesc *>(base);
   const ConvDesc *dc1 = reinterpret_cast<const ConvDesc *>(base + nb * sizeof(ProbDesc));
   const ConvDesc *dc2 = dc1 + nb;
@@ -884,8 +903,10 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
   // with both classes present they run on the side stream, issued first,
   // beside class A's.  Class A's two parts run on the caller's stream (A1)
   // and the second side stream (A2), so that one part's latency-bound
-  // stages overlap the other's transforms.  The main stream waits for the
-  // side streams before the velocities.
+  // stages overlap the other's transforms.  With the side streams each part
+  // also takes its velocities on its own stream, after its final
+  // convolution; the main stream waits for the side streams before the
+  // impulses.
   const bool fork = side != nullptr && na > 0 && nbb > 0;
   const hipStream_t sb = fork ? side->side : s;
   auto class_a = [&](Sub &u) -> gpf_status {
@@ -902,6 +923,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     GPF_HIP(launch_rs_apply(dpd + lo, m, 0, st, &u.frs));
     timer_end(st);
     GPF_HIP((launch_convolve_multi<float, float>(dc2 + lo, u.mp2, st)));
+    if (vsplit) GPF_HIP(launch_solve_velocity<float>(dpd + lo, m, u.ci.n_max, u.ci.nv_max, st, u.fvel));
     return GPF_OK;
   };
   auto class_b = [&]() -> gpf_status {
@@ -926,6 +948,7 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     GPF_HIP(launch_rs_apply(dpd + na, nbb, 0, sb, &frs[1]));
     timer_end(sb);
     GPF_HIP((launch_convolve_multi<double, float>(dc2 + na, mp2b, sb)));
+    if (vsplit) GPF_HIP(launch_solve_velocity<float>(dpd + na, nbb, cbi.n_max, cbi.nv_max, sb, fvelb));
     return GPF_OK;
   };
   if (fork || split) {
@@ -949,9 +972,11 @@ gpf_status run_merged(std::vector<ProblemRef> probs, DescRing &ring, int xcds, h
     for (int k = 0; k < nsub; ++k) GPF_TRY(class_a(subs[k]));
     if (nbb > 0) GPF_TRY(class_b());
   }
-  // velocities of every problem, then impulses where asked
-  GPF_HIP(launch_solve_velocity<float>(dpd, nb, std::max(ca.n_max, cbi.n_max),
-                                       std::max(ca.nv_max, cbi.nv_max), s, fvel));
+  // velocities of every problem (per part above with the side streams),
+  // then impulses where asked
+  if (!vsplit)
+    GPF_HIP(launch_solve_velocity<float>(dpd, nb, std::max(ca.n_max, cbi.n_max),
+                                         std::max(ca.nv_max, cbi.nv_max), s, fvel));
   if (impulse) GPF_HIP(launch_impulse(dpd, nb, s));
   return GPF_OK;
 }

@@ -656,7 +656,7 @@ struct gpf_batch {
   hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
   // side stream of merged batches (created at the first merged batch with
   // both precision classes): the class with an FP64 first convolution runs
-  // up to its velocities there, beside the FP32 class
+  // there, velocities included, beside the FP32 class
   hipStream_t side = nullptr;
   hipEvent_t side_fork = nullptr, side_join = nullptr;
   // second side stream: the FP32 class's problems below its largest grid
