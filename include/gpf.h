@@ -372,7 +372,8 @@ gpf_status gpf_solve_batched(gpf_batch *batch, int nprob, gpf_plan *const *plans
  * of max_slots problem workspaces, each with its own non-blocking HIP
  * stream, and a worker thread.  The worker takes queued requests in arrival
  * order, up to max_slots at a time, and solves them as one batch
- * (gpf_solve_batched) on a free set's stream, so up to three batches run on
+ * (gpf_solve_batched, merged on that stream alone: merge mode 2) on a free
+ * set's stream, so up to three batches run on
  * the device at once; completion is observed with an event per batch.
  * Admission: a request is refused with GPF_E_NOMEM when the server's
  * resident plans plus the three workspace sets at the largest grid seen
